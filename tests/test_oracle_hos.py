@@ -1,0 +1,304 @@
+"""Pins of the oracle's HOS step (Sec. 3.1, 3.1.2) against closed forms:
+exact harmonic Dirichlet-to-Neumann data, the linear (Airy) problem and
+the exact RK4 propagator, second-order Stokes harmonics, the deep-water
+nonlinear frequency, energy and mass invariants, and the free-surface
+conditions."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import Grid, hos, sea
+from oracle import reconstruct as rc
+
+LAM = 2 * math.pi
+
+
+# ---------------------------------------------------------------- P2: series
+def _dtn_case(eps, M, depth, nx=64, ny=1, k0=(3, 0), k1=(2, 0)):
+    lx, ly = LAM, LAM * (1 if ny > 1 else 1)
+    g = Grid(nx=nx, ny=ny, lx=lx, ly=ly, depth=depth, order_m=M)
+    x, y = g.node_coords((nx, ny))
+    X, Y = np.meshgrid(x, y)
+    kx0, ky0 = 2 * math.pi * k0[0] / lx, 2 * math.pi * k0[1] / ly
+    kx1, ky1 = 2 * math.pi * k1[0] / lx, 2 * math.pi * k1[1] / ly
+    kk = math.hypot(kx0, ky0)
+    eta = eps * np.cos(kx1 * X + ky1 * Y)
+    ph = np.cos(kx0 * X + ky0 * Y)
+    if depth > 0:
+        phis = np.cosh(kk * (eta + depth)) / math.cosh(kk * depth) * ph
+        wex = kk * np.sinh(kk * (eta + depth)) / math.cosh(kk * depth) * ph
+    else:
+        phis = np.exp(kk * eta) * ph
+        wex = kk * np.exp(kk * eta) * ph
+    eh = g.to_spec(eta)
+    psh = g.to_spec(phis)
+    etap = g.to_phys(eh)
+    modes, gg = hos.series(g, etap, psh)
+    W = hos.w_orders(g, etap, gg)
+    A = sum(modes)
+    target = np.zeros_like(A)
+    target[k0[1] % ny, k0[0]] = 0.5
+    err_a = np.abs(A - target).max()
+    Wn = g.to_spec(sum(W))
+    err_w = np.abs(Wn - g.to_spec(g.to_phys(g.to_spec(wex)))).max()
+    return err_a, err_w
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 4])
+@pytest.mark.parametrize("depth", [1.0, -1.0])
+def test_series_exact_harmonic_convergence_order(M, depth):
+    """Sum of phihat^(m) -> a single mode, W -> the exact surface vertical
+    velocity.  With a unit-amplitude potential the m-th term is
+    O((k eps)^(m-1)), so the truncation error after M terms is O((k eps)^M)
+    (O(eps^(M+1)) when the potential itself is counted as first order):
+    fitted log-log slope M +- 0.25."""
+    eps = np.array([0.02, 0.01, 0.005])
+    ea, ew = zip(*[_dtn_case(e, M, depth) for e in eps])
+    sa = np.polyfit(np.log(eps), np.log(ea), 1)[0]
+    sw = np.polyfit(np.log(eps), np.log(ew), 1)[0]
+    assert abs(sa - M) < 0.25, (sa, ea)
+    assert abs(sw - M) < 0.25, (sw, ew)
+
+
+def test_series_exact_harmonic_3d_oblique():
+    ea3, ew3 = _dtn_case(0.01, 3, 1.0, nx=32, ny=16, k0=(3, 2), k1=(1, 1))
+    ea5, ew5 = _dtn_case(0.01, 5, 1.0, nx=32, ny=16, k0=(3, 2), k1=(1, 1))
+    assert ea3 < 1e-5 and ew3 < 1e-5
+    assert ea5 < ea3 / 20 and ew5 < ew3 / 20
+
+
+# ------------------------------------------------------- P3: linear / RK4
+def _rk4_matrix(T, g, dt):
+    A = np.array([[0.0, T], [-g, 0.0]]) * dt
+    R = np.eye(2)
+    term = np.eye(2)
+    for n in range(1, 5):
+        term = term @ A / n
+        R = R + term
+    return R
+
+
+@pytest.mark.parametrize("depth,ny", [(2.0, 1), (-1.0, 1), (1.5, 8)])
+def test_linear_m1_equals_exact_rk4_propagator(depth, ny):
+    nx = 32
+    g = Grid(nx=nx, ny=ny, lx=4 * LAM, ly=2 * LAM, depth=depth, order_m=1)
+    rng = np.random.default_rng(7)
+    eh = (rng.standard_normal((ny, g.nxh)) + 1j * rng.standard_normal((ny, g.nxh))) * 1e-2
+    ph = (rng.standard_normal((ny, g.nxh)) + 1j * rng.standard_normal((ny, g.nxh))) * 1e-2
+    eh *= g.nyquist_mask(); ph *= g.nyquist_mask()
+    eh[0, 0] = 0.0
+    if ny > 1:
+        for q in range(1, ny // 2):
+            eh[ny - q, 0] = np.conj(eh[q, 0]); ph[ny - q, 0] = np.conj(ph[q, 0])
+    eh[0, 0] = 0; ph[0, 0] = ph[0, 0].real
+    dt, n = 0.1, 40
+    e, p = hos.run(g, eh, ph, dt, n)
+    T = g.dz_symbol(1)
+    for q in range(ny):
+        for pp in range(g.nxh):
+            R = np.linalg.matrix_power(_rk4_matrix(T[q, pp], g.g, dt), n)
+            ref = R @ np.array([eh[q, pp], ph[q, pp]])
+            assert abs(e[q, pp] - ref[0]) < 1e-12 and abs(p[q, pp] - ref[1]) < 1e-12
+
+
+def test_linear_m1_matches_airy_within_rk4_error():
+    g = Grid(nx=64, ny=1, lx=4 * LAM, ly=1.0, depth=2.0, order_m=1)
+    eh, ph, info = sea.stokes2(g, 4, 0.1)
+    eh[0, 8] = 0; ph[0, 8] = 0  # pure linear wave
+    w = info["omega"]
+    T = 2 * math.pi / w
+    dt = T / 64
+    e, p = hos.run(g, eh, ph, dt, 128)
+    # Airy: eta = a cos(kx - w t); after two periods the phase returns
+    ref = 0.5 * info["a"]
+    assert abs(abs(e[0, 4]) - ref) < 1e-5 * ref
+    dphase = np.angle(e[0, 4] / eh[0, 4])
+    # RK4 phase error per step ~ (w dt)^5 / 120
+    assert abs(dphase) < 2 * 128 * (w * dt) ** 5 / 120 + 1e-12
+
+
+def test_m1_evaluated_fields_match_airy_formulas():
+    """At M = 1 every evaluated field is the Airy field of the state's current
+    mode amplitude and phase (pressure incl. the quadratic term)."""
+    h = 2.0
+    g = Grid(nx=32, ny=1, lx=4 * LAM, ly=1.0, depth=h, order_m=1, g=9.81, rho=1000.0)
+    eh, ph, info = sea.stokes2(g, 4, 0.1)
+    eh[0, 8] = 0; ph[0, 8] = 0
+    e, p = hos.run(g, eh, ph, 0.05, 7)
+    A = hos.mean_level_modes(g, e, p)
+    At, eth = hos.mean_level_modes_t(g, e, p)
+    k = info["k"]
+    # current amplitude/phase: phis = Re(2 b e^{ikx})
+    b = 2 * p[0, 4]
+    c = 2 * e[0, 4]
+    xs, _ = g.node_coords((32, 1))
+    zl = np.array([-h, -1.0, -0.3, 0.0, 0.15])
+    out = rc.eval_grid(g, A, At, e, eth, 32, 1, zl, [rc.PHI, rc.U, rc.W, rc.PHI_T, rc.P, rc.ETA_T])
+    for li, z in enumerate(zl):
+        ch = math.cosh(k * (z + h)) / math.cosh(k * h)
+        sh = math.sinh(k * (z + h)) / math.cosh(k * h)
+        E = np.exp(1j * k * xs)
+        phi = np.real(b * E) * ch
+        u = np.real(1j * k * b * E) * ch
+        w = np.real(k * b * E) * sh
+        phit = np.real(-g.g * c * E) * ch
+        pr = -g.rho * (phit + 0.5 * (u * u + w * w) + g.g * z)
+        for f, ref in [(rc.PHI, phi), (rc.U, u), (rc.W, w), (rc.PHI_T, phit), (rc.P, pr)]:
+            assert np.abs(out[f][li, 0] - ref).max() < 1e-12 * max(1.0, np.abs(ref).max()), f
+    etat = np.real(k * math.tanh(k * h) * b * np.exp(1j * k * xs))
+    assert np.abs(out[rc.ETA_T][0] - etat).max() < 1e-13
+
+
+# ------------------------------------------------------- P4: Stokes waves
+def _harmonics_after(ka, depth, periods=2, M=3):
+    g = Grid(nx=64, ny=1, lx=4 * LAM, ly=1.0, depth=depth, order_m=M)
+    eh, ph, info = sea.stokes2(g, 4, ka)
+    T = 2 * math.pi / info["omega"]
+    dt = T / 64
+    amps = []
+
+    def cb(n, e, p):
+        if n % 8 == 0:
+            amps.append((2 * abs(e[0, 4]), 2 * abs(e[0, 8])))
+    hos.run(g, eh, ph, dt, 64 * periods, cb)
+    a1 = np.array([a for a, _ in amps]); a2 = np.array([b for _, b in amps])
+    return a1, a2, info
+
+
+def test_stokes_second_harmonic_ratio():
+    """a2/a = (ka/4) cosh kh (2 + cosh 2kh)/sinh^3 kh (0.05778 at ka=0.1,
+    kh=2) is held over two periods to within the third-order correction
+    (peak deviation ~6.4 (ka)^2 here, since the initial state is only
+    second order); the deviation drops 4x when ka halves."""
+    a1, a2, info = _harmonics_after(0.1, 2.0)
+    assert abs(info["a2"] / info["a"] - 0.05778) < 5e-5
+    dev1 = np.max(np.abs(a2 / a1 / (info["a2"] / info["a"]) - 1))
+    assert dev1 < 0.08
+    b1, b2, info2 = _harmonics_after(0.05, 2.0)
+    dev2 = np.max(np.abs(b2 / b1 / (info2["a2"] / info2["a"]) - 1))
+    assert 3.6 < dev1 / dev2 < 4.4, (dev1, dev2)
+
+
+def test_deep_water_nonlinear_frequency():
+    """Deep water: w = sqrt(g k) (1 + (ka)^2/2) to O((ka)^4); the phase of the
+    first harmonic is tracked over two periods."""
+    for ka in (0.1, 0.14):
+        g = Grid(nx=64, ny=1, lx=4 * LAM, ly=1.0, depth=-1.0, order_m=3)
+        eh, ph, info = sea.stokes2(g, 4, ka)
+        w0 = info["omega"]
+        dt = 2 * math.pi / w0 / 128
+        phases, times = [], []
+
+        def cb(n, e, p):
+            phases.append(np.angle(e[0, 4])); times.append(n * dt)
+        hos.run(g, eh, ph, dt, 256, cb)
+        ph_un = np.unwrap(np.array(phases))
+        w = -np.polyfit(np.array(times), ph_un, 1)[0]
+        theory = math.sqrt(g.g * info["k"]) * (1 + 0.5 * ka * ka)
+        linear = math.sqrt(g.g * info["k"])
+        assert abs(w - theory) / theory < 0.15 * (ka ** 2 / 2), (w, theory, linear)
+
+
+# ----------------------------------------------------------- P5: invariants
+def _jonswap_small(M, nx=32, ny=16):
+    g = Grid(nx=nx, ny=ny, lx=nx * LAM / 6.4, ly=ny * LAM / 6.4, depth=-1.0, order_m=M)
+    phases = synth.mode_phases(11, ny, g.nxh)
+    eh, ph = sea.jonswap(g, 0.04 * LAM, 1.0, 3.3, phases)
+    return g, eh, ph
+
+
+def test_energy_drift_converges_with_dt_and_order():
+    """With the sea resolved well inside the band (|k| <= N/6, so the
+    order-M products do not push energy past the kept modes), the truncated
+    equations conserve E for M = 2, 3, 5 and the drift over one period falls
+    like the RK4 error (>= 16x per halving of dt).  A 10% error in any
+    nonlinear term leaves an O(1e-5..1e-3) floor instead."""
+    for M in (2, 3, 5):
+        g = Grid(nx=64, ny=32, lx=32 * LAM / 6.4, ly=16 * LAM / 6.4, depth=-1.0, order_m=M)
+        eh, ph = sea.jonswap(g, 0.04 * LAM, 1.0, 3.3, synth.mode_phases(11, 32, g.nxh))
+        _, _, K = g.kvec()
+        eh[K > 1.6] = 0
+        ph[K > 1.6] = 0
+        E0 = hos.energy(g, eh, ph)
+        d = []
+        for nper in (32, 64):
+            e, p = hos.run(g, eh, ph, 2 * math.pi / nper, nper)
+            d.append(abs(hos.energy(g, e, p) - E0) / E0)
+        assert d[0] / d[1] > 16 and d[1] < 5e-6, (M, d)
+
+
+def test_mass_and_hermitian_symmetry_preserved():
+    g, eh, ph = _jonswap_small(3)
+    e, p = hos.run(g, eh, ph, 2 * math.pi / 32, 8)
+    assert abs(e[0, 0]) < 1e-15
+    for q in range(1, g.ny // 2):
+        assert abs(e[g.ny - q, 0] - np.conj(e[q, 0])) < 1e-14
+        assert abs(p[g.ny - q, 0] - np.conj(p[q, 0])) < 1e-14
+
+
+def test_jonswap_hs_and_dispersion_relation():
+    g, eh, ph = _jonswap_small(3, nx=64, ny=32)
+    eta = g.to_phys(eh, (g.nx, g.ny))
+    hs = 4 * math.sqrt(np.mean(eta * eta))
+    assert abs(hs - 0.04 * LAM) < 1e-12
+    _, _, K = g.kvec()
+    nz = np.abs(eh) > 0
+    assert np.allclose(np.abs(ph[nz]), np.abs(eh[nz]) / np.sqrt(K[nz]))
+
+
+# -------------------------------------------------------- P6: surface BCs
+def _bc_residuals(M, ka=0.1, nx=64):
+    h = 2.0
+    g = Grid(nx=nx, ny=1, lx=4 * LAM, ly=1.0, depth=h, order_m=M)
+    eh, ph, info = sea.stokes2(g, 4, ka)
+    e, p = hos.run(g, eh, ph, 2 * math.pi / info["omega"] / 64, 16)
+    A = hos.mean_level_modes(g, e, p)
+    At, eth = hos.mean_level_modes_t(g, e, p)
+    xs, _ = g.node_coords((nx, 1))
+    eta = g.to_phys(e, (nx, 1))[0]
+    pts = np.stack([xs, np.zeros_like(xs), eta])
+    v = rc.analytic_at_points(g, A, At, e, eth, pts, [rc.P, rc.U, rc.W])
+    etat = g.to_phys(eth, (nx, 1))[0]
+    KX, _, _ = g.kvec()
+    etax = g.to_phys(1j * KX * e, (nx, 1))[0]
+    kin = etat + v[rc.U] * etax - v[rc.W]
+    scale_p = g.rho * g.g * info["a"]
+    return np.abs(v[rc.P]).max() / scale_p, np.abs(kin).max() / (info["omega"] * info["a"])
+
+
+def test_free_surface_conditions_residuals_fall_with_order():
+    """p(x, eta) = 0 and the kinematic condition at z = eta, evaluated by the
+    brute-force modal sums, have residuals that fall by about ka per order."""
+    r = {M: _bc_residuals(M) for M in (1, 2, 3, 4, 5)}
+    for M in (2, 3, 4, 5):
+        assert r[M][0] < r[M - 1][0] / 4 and r[M][1] < r[M - 1][1] / 4, r
+    assert r[5][0] < 2e-5 and r[5][1] < 2e-4
+
+
+# ---------------------------------------------------- P11: phi_t path
+def test_phi_t_modes_match_centred_time_difference():
+    """A_t from the Dirichlet series on phis_t - W eta_t against a centred
+    time difference of A(t): at M = 1 they agree to O(dt^2) (ratio 4 per
+    halving); at M >= 2 the difference is the order-M truncation of the
+    series, which falls with M."""
+    floors = []
+    for M in (1, 2, 3, 4):
+        g = Grid(nx=64, ny=32, lx=32 * LAM / 6.4, ly=16 * LAM / 6.4, depth=-1.0, order_m=M)
+        eh, ph = sea.jonswap(g, 0.04 * LAM, 1.0, 3.3, synth.mode_phases(11, 32, g.nxh))
+        _, _, K = g.kvec()
+        eh[K > 1.6] = 0
+        ph[K > 1.6] = 0
+        At, _ = hos.mean_level_modes_t(g, eh, ph)
+        errs = []
+        for h in (2 * math.pi / 256, 2 * math.pi / 512):
+            ep, pp = hos.rk4_step(g, eh, ph, h)
+            em, pm = hos.rk4_step(g, eh, ph, -h)
+            Ad = (hos.mean_level_modes(g, ep, pp) - hos.mean_level_modes(g, em, pm)) / (2 * h)
+            errs.append(np.abs(Ad - At).max() / np.abs(At).max())
+        if M == 1:
+            assert 3.8 < errs[0] / errs[1] < 4.2 and errs[0] < 2e-4, errs
+        else:
+            floors.append(errs[1])
+    assert floors[0] < 2e-2 and floors[1] < floors[0] / 3 and floors[2] < floors[1] / 3, floors
