@@ -1,0 +1,202 @@
+/*
+ * swense.h - C ABI of the MI355X (gfx950) incident-wave library.
+ *
+ * The library implements the incident-wave side of the two-phase SWENSE
+ * method (Li et al., "Spectral Wave Explicit Navier-Stokes Equations for
+ * wave-structure interactions using two-phase CFD solvers", arXiv 2005.12716):
+ *   - the High-Order Spectral (HOS) free-surface step (Sec. 3.1.2),
+ *   - the modal evaluation of potential, velocity, pressure and their time
+ *     derivatives on an intermediate grid with zero-padding refinement and
+ *     extension into the air (Sec. 3.2.2, 3.2.4, 3.3),
+ *   - the interpolation of those fields to CFD cell centres (Sec. 3.2.2) and
+ *     the divergence diagnostic of Sec. 3.2.3.
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: 0 (SWENSE_OK) or a negative SWENSE_E* code.  No entry point
+ *     throws, aborts or frees caller memory.  The text of the last error of a
+ *     handle is returned by swense_last_error.
+ *   - Spectral layout: half spectrum [ny][nx/2+1] of interleaved FP64
+ *     (re, im) pairs, x fastest; f(x,y) = sum_k fhat(k) exp(i k.x) with
+ *     k = (2 pi p/lx, 2 pi q/ly), q >= ny/2 meaning q - ny (fhat = DFT / (nx ny)).
+ *     Physical layout: [ny][nx] FP64, node (i, j) at (i lx/nx, j ly/ny).
+ *     Nyquist modes (p = nx/2, q = ny/2) are held at zero.
+ *   - Memory: pointers documented "host" are ordinary host memory read or
+ *     written synchronously; "device" pointers are HIP device memory owned by
+ *     the caller.  Each handle owns the device memory it allocates internally
+ *     (state, workspaces, bound point data) and releases it in its destroy call.
+ *   - Streams: all GPU work of a handle is ordered on the HIP stream given at
+ *     creation (NULL = the null stream) and is asynchronous unless a call is
+ *     documented to synchronise.  A handle is not thread-safe.
+ *   - Units: any consistent set (g and rho are parameters).  z points up,
+ *     z = 0 is the still-water level.
+ */
+#ifndef SWENSE_H
+#define SWENSE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SWENSE_OK = 0,
+  SWENSE_EINVAL = -1,    /* bad argument or descriptor                        */
+  SWENSE_ENOMEM = -2,    /* device allocation failed                          */
+  SWENSE_EHIP = -3,      /* HIP runtime error (message kept)                  */
+  SWENSE_EUNSTABLE = -4, /* non-finite state                                  */
+  SWENSE_ERANGE = -5,    /* some points outside the grid or layers (non-fatal) */
+  SWENSE_ENOTSUP = -6    /* unsupported combination                           */
+};
+
+/* Field bits for evaluation and interpolation masks; the output order is the
+ * bit order of the fields present in the mask. */
+enum {
+  SWENSE_PHI = 1u << 0,   /* velocity potential                         */
+  SWENSE_U = 1u << 1,     /* velocity components                        */
+  SWENSE_V = 1u << 2,
+  SWENSE_W = 1u << 3,
+  SWENSE_P = 1u << 4,     /* pressure -rho (phi_t + |grad phi|^2/2 + g z) */
+  SWENSE_PHI_T = 1u << 5, /* time derivatives of phi, u, v, w           */
+  SWENSE_U_T = 1u << 6,
+  SWENSE_V_T = 1u << 7,
+  SWENSE_W_T = 1u << 8,
+  SWENSE_ETA = 1u << 9,   /* free-surface elevation (z-independent)     */
+  SWENSE_ETA_T = 1u << 10,
+  SWENSE_ALL_FIELDS = (1u << 11) - 1u
+};
+
+enum { SWENSE_PHYSICAL = 0, SWENSE_SPECTRAL = 1 };
+
+typedef struct swense_hos swense_hos;     /* one HOS realisation (opaque)       */
+typedef struct swense_cells swense_cells; /* a bound, static point cloud (opaque) */
+
+/* One HOS realisation (Sec. 3.1.2).
+ *   dim: 2 (x, z; ny must be 1) or 3.  nx, ny: modes per direction, even and
+ *   2/3/5-smooth (ny = 1 for dim 2).  depth <= 0 selects infinite depth.
+ *   order_m >= 1: order of the vertical-velocity series.  dealias: 1 forms
+ *   products on the (M+1)/2 zero-padded grid, 0 on the mode grid.
+ *   precision: 0 = FP32 transforms with FP64 state, symbols and time
+ *   integration; 1 = FP64 throughout.  dt: RK4 time step; t0: initial time. */
+typedef struct {
+  int dim;
+  int nx, ny;
+  double lx, ly;
+  double depth;
+  double g, rho;
+  int order_m;
+  int dealias;
+  int precision;
+  double dt, t0;
+} swense_hos_desc;
+
+/* Intermediate grid (Sec. 3.2.2, 3.2.4).  gx, gy nodes per period: gx > nx
+ * zero-pads the spectrum (refinement n = gx/nx), gx < nx folds it; both give
+ * the exact modal sum at the nodes.  Window: nodes ix0..ix0+wx-1 (mod gx),
+ * iy0..iy0+wy-1 (mod gy).  nl layer heights z (ascending, host memory), any
+ * z (above z = 0 the modal formula extends the fields into the air, Sec. 3.3).
+ * In 2D gy = wy = 1, iy0 = 0. */
+typedef struct {
+  int gx, gy;
+  int ix0, iy0, wx, wy;
+  int nl;
+  const double* z;
+} swense_grid_desc;
+
+/* Sea-state description for the initial spectra (set-up, Sec. 3.1.2 and the
+ * JONSWAP example of Sec. 3.2.2).  kind 0: JONSWAP with peak wavenumber kp,
+ * significant height hs, peakedness gamma, spreading 0 = cos^2, 1 = all energy
+ * along +x; amplitudes scaled so that 4 sqrt(m0) = hs on the discrete modes.
+ * kind 1: second-order Stokes wave on mode `mode` along x with steepness ka. */
+typedef struct {
+  int kind;
+  double hs, kp, gamma;
+  int spreading;
+  int mode;
+  double ka;
+} swense_sea_desc;
+
+/* ---- set-up ----------------------------------------------------------- */
+
+/* Initial half spectra of a linear sea (kind 0) or a second-order Stokes wave
+ * (kind 1).  phases: host [ny][nx/2+1] FP64 phases of the modes (kind 0 only;
+ * may be NULL for kind 1).  eta_hat, phis_hat: host outputs, spectral layout.
+ * Deterministic amplitudes; the random phases are an input. */
+int swense_sea_spectrum(const swense_hos_desc* d, const swense_sea_desc* sea,
+                        const double* phases, double* eta_hat, double* phis_hat);
+
+/* Create a realisation and load its initial state (eta, surface potential
+ * phis = phi at z = eta).  eta0, phis0: host arrays in `layout` (SWENSE_PHYSICAL
+ * or SWENSE_SPECTRAL).  stream: a hipStream_t or NULL.  Allocates the state and
+ * workspaces on the current device.  EINVAL on a bad descriptor. */
+int swense_hos_init(const swense_hos_desc* d, const double* eta0, const double* phis0, int layout,
+                    void* stream, swense_hos** out);
+
+/* Replace the state (host arrays in `layout`) and set the time to t. */
+int swense_hos_set_state(swense_hos* h, const double* eta, const double* phis, int layout, double t);
+
+/* ---- HOS step (Sec. 3.1.2) -------------------------------------------- */
+
+/* Advance nsteps classical RK4 steps of size dt.  Asynchronous. */
+int swense_hos_step(swense_hos* h, int nsteps);
+
+/* Copy the state to host arrays in `layout` (eta, phis may be NULL) and the
+ * time to *t (may be NULL).  Synchronises the handle's stream.  Returns
+ * EUNSTABLE if the state holds a non-finite value. */
+int swense_hos_get_state(swense_hos* h, double* eta, double* phis, double* t, int layout);
+
+/* Right-hand side of the evolution equations at the current state, as half
+ * spectra (host outputs).  Synchronises. */
+int swense_hos_rhs(swense_hos* h, double* eta_t_hat, double* phis_t_hat);
+
+/* Mean-level modal amplitudes of the potential A (Sec. 3.1, 3.2) and of its
+ * time derivative A_t, plus eta_t, as half spectra (host outputs; any may be
+ * NULL).  Synchronises. */
+int swense_hos_modes(swense_hos* h, double* a_hat, double* a_t_hat, double* eta_t_hat);
+
+/* Energy 1/2 int phis eta_t dA + 1/2 g int eta^2 dA.  Synchronises. */
+int swense_hos_energy(swense_hos* h, double* energy);
+
+/* ---- evaluation on the intermediate grid (Sec. 3.2.2, 3.2.4, 3.3) ------ */
+
+/* Fields of `mask` at the window nodes of every layer.  out: device FP32,
+ * volume fields as [F][nl][wy][wx], then surface fields (ETA, ETA_T) as
+ * [wy][wx] each, in field-bit order.  Asynchronous. */
+int swense_eval_grid(swense_hos* h, const swense_grid_desc* gd, unsigned mask, float* out);
+
+/* Number of floats swense_eval_grid writes for (gd, mask). */
+size_t swense_eval_grid_size(const swense_hos* h, const swense_grid_desc* gd, unsigned mask);
+
+/* ---- interpolation to cell centres (Sec. 3.2.2) ------------------------ */
+
+/* Bind a static point cloud to a grid: xyz is device FP64 [3][n] (x row, y
+ * row, z row).  Each point's stencil (periodic cubic spline horizontally on
+ * the grid nodes, 4-point Lagrange vertically on the layers) is located once
+ * here.  Points whose stencil leaves the window or whose z lies outside
+ * [z_0, z_nl-1] are flagged out of range.  The grid descriptor (and its z
+ * array) is copied.  Synchronises. */
+int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, const double* xyz,
+                      swense_cells** out);
+
+/* Interpolate the fields of `mask` at the bound points of the current state.
+ * out: device FP32 [F][n] in the caller's point order (field-bit order).
+ * Out-of-range points get NaN; their count goes to *n_out_of_range if that
+ * pointer is non-NULL (which synchronises) and the call then returns ERANGE
+ * when the count is non-zero. */
+int swense_interp_cells(swense_hos* h, swense_cells* c, unsigned mask, float* out,
+                        long long* n_out_of_range);
+
+/* Divergence diagnostic (Sec. 3.2.3) at the bound points: du/dx + dv/dy +
+ * dw/dz of the interpolant (device FP32 [n], caller order).  Asynchronous. */
+int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div);
+
+/* ---- lifetime ---------------------------------------------------------- */
+void swense_hos_destroy(swense_hos* h);
+void swense_cells_destroy(swense_cells* c);
+const char* swense_last_error(const swense_hos* h);
+const char* swense_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWENSE_H */

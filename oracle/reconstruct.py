@@ -77,6 +77,24 @@ def node_values(grid: Grid, fh: np.ndarray, gx: int, gy: int, prefilter: bool = 
     inverse complex FFT.  With prefilter, returns the periodic cubic B-spline
     coefficients that interpolate those node values."""
     ny, nx = grid.ny, grid.nx
+    if gx >= nx and (gy >= ny or ny == 1):
+        # zero-padding only: place the half spectrum and inverse real FFT
+        hx = nx // 2
+        big = np.zeros((gy, gx // 2 + 1), dtype=np.complex128)
+        sub = fh[:, :hx].copy()
+        if prefilter:
+            bx = _beta(2 * math.pi * np.arange(hx) / gx)
+            qs = np.arange(ny)
+            qs = np.where(qs < ny // 2, qs, qs - ny) if ny > 1 else qs
+            by = _beta(2 * math.pi * qs / gy) if ny > 1 else np.ones(1)
+            sub = sub / (by[:, None] * bx[None, :])
+        if ny == 1:
+            big[0, :hx] = sub[0]
+        else:
+            hy = ny // 2
+            big[:hy, :hx] = sub[:hy]
+            big[gy - (ny - hy - 1):, :hx] = sub[hy + 1:]
+        return np.fft.irfft2(big, s=(gy, gx)) * (gx * gy)
     full = np.zeros((ny, nx), dtype=np.complex128)
     nxh = grid.nxh
     full[:, :nxh] = fh

@@ -1,0 +1,829 @@
+// High-Order Spectral free-surface step on gfx950 (Sec. 3.1.2).
+//
+// State: FP64 half spectra (eta_hat, phis_hat) [ny][nx/2+1].  One right-hand
+// side is a chain of three kinds of launches:
+//   y-inverse : per column tile of kx, multiply the FP64 spectrum by a FP64
+//               symbol (1, i ky, Dz^j = k^j (tanh kh)^{j odd}, ...), zero-pad
+//               ny -> Py, inverse transform along y in LDS, store rows
+//               [Py][nx/2+1] (x still spectral) in the transform precision;
+//   x pass    : one block per physical row; builds every needed physical field
+//               by an inverse x transform (two real fields packed in one
+//               complex transform), forms the order-M products in LDS and
+//               transforms the result(s) forward again, keeping the nx/2 kept
+//               modes - the padded physical grid never touches HBM;
+//   y-forward : forward y transform, truncation to the ny kept modes, and an
+//               epilogue that stores a series mode or adds the exact linear
+//               part of the right-hand side in FP64 and performs the RK4 stage
+//               update in place.
+// Series (West et al. expansion of the vertical velocity, order M):
+//   phi^(1) = phis, phi^(m+1) = -sum_{j=1..m} eta^j/j! g(m+1-j, j),
+//   W^(m) = sum_{j=0..m-1} eta^j/j! g(m-j, j+1),  g(m,j) = F^-1(Dz^j phi^(m)).
+// Only the nonlinear remainders eta_t - W^(1) and phis_t + g eta pass through
+// the reduced-precision transforms; Dz phis and -g eta are added exactly.
+#include "internal.h"
+#include "yinv.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace {
+
+// ------------------------------------------------------------------ device
+template <typename R>
+__global__ void __launch_bounds__(256) k_yinv(YInvArgs args, Geom G, FftPlan plan, int TW, int nrows, int row0) {
+  extern __shared__ unsigned char smem[];
+  yinv_body<R>(args.job[blockIdx.y], G, plan, TW, nrows, row0, smem);
+}
+
+template <typename R>
+__device__ __forceinline__ cpx<R> load_row(const XIn& f, int y, int p, const Geom& G) {
+  cpx<R> v = reinterpret_cast<const cpx<R>*>(f.src)[(size_t)y * G.nxh + p];
+  if (f.dx) {
+    const R kx = (R)(2.0 * M_PI * (double)p / G.lx);
+    v = mk(-kx * v.y, kx * v.x);
+  }
+  return v;
+}
+
+template <typename R>
+__device__ __forceinline__ void apply_role(const XIn& f, R v, R other, int x, int Px, R* acc, const XArgs& A) {
+  switch (f.role) {
+    case XR_ETA: acc[A.s_eta * Px + x] = v; break;
+    case XR_GRADPAIR:
+      acc[A.s_ge2 * Px + x] += v * v;
+      acc[A.s_dot * Px + x] += v * other;
+      acc[A.s_gp2 * Px + x] += other * other;
+      break;
+    case XR_G: {
+      const R e = acc[A.s_eta * Px + x];
+      R c = (R)1;
+      for (int k = 1; k <= f.pw; ++k) c *= e / (R)k;
+      acc[f.slot * Px + x] += c * v;
+    } break;
+    case XR_ETAT: acc[A.s_etat * Px + x] = v; break;
+    case XR_PHIT: acc[A.s_phit * Px + x] = v; break;
+    default: break;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R w2sum(const R* W, int K) {
+  R s = (R)0;
+  for (int m = 2; m <= K; ++m)
+    for (int l = 1; l < m; ++l) s += W[l - 1] * W[m - l - 1];
+  return s;
+}
+
+// Fused x pass: one block per physical row y of the product grid.
+template <typename R>
+__global__ void __launch_bounds__(256) k_xpass(XArgs A, Geom G, FftPlan plan) {
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  const int Px = plan.n;
+  const int y = blockIdx.x;
+  const int hx = G.nx / 2;
+  C* za = reinterpret_cast<C*>(smem);
+  C* zb = za + Px;
+  R* acc = reinterpret_cast<R*>(zb + Px);
+  for (int e = threadIdx.x; e < A.nslots * Px; e += blockDim.x) acc[e] = (R)0;
+  for (int i = 0; i < A.nin; i += 2) {
+    const XIn& fa = A.in[i];
+    const bool hasb = (i + 1) < A.nin;
+    const XIn& fb = A.in[hasb ? i + 1 : i];
+    for (int s = threadIdx.x; s < Px; s += blockDim.x) {
+      C z = mk((R)0, (R)0);
+      if (s < hx) {
+        C va = load_row<R>(fa, y, s, G);
+        C vb = hasb ? load_row<R>(fb, y, s, G) : mk((R)0, (R)0);
+        z = mk(va.x - vb.y, va.y + vb.x);  // va + i vb
+      } else if (s > Px - hx) {
+        const int p = Px - s;
+        C va = conjg(load_row<R>(fa, y, p, G));
+        C vb = hasb ? conjg(load_row<R>(fb, y, p, G)) : mk((R)0, (R)0);
+        z = mk(va.x - vb.y, va.y + vb.x);
+      }
+      za[s] = z;
+    }
+    __syncthreads();
+    C* res = block_fft<R>(za, zb, plan, 1, +1);
+    for (int x = threadIdx.x; x < Px; x += blockDim.x) {
+      const R va = res[x].x, vb = res[x].y;
+      apply_role<R>(fa, va, vb, x, Px, acc, A);
+      if (hasb && fa.role != XR_GRADPAIR) apply_role<R>(fb, vb, (R)0, x, Px, acc, A);
+    }
+    __syncthreads();
+  }
+  const int M = A.M;
+  for (int x = threadIdx.x; x < Px; x += blockDim.x) {
+    R o0 = (R)0, o1 = (R)0;
+    if (A.stage == XS_SERIES) {
+      o0 = -acc[A.s_w[0] * Px + x];
+    } else if (A.stage == XS_FTILDE) {
+      o0 = acc[A.s_phit * Px + x];
+      if (M >= 2) o0 -= acc[A.s_w[0] * Px + x] * acc[A.s_etat * Px + x];
+    } else {
+      R W[kMaxM];
+      R wm = (R)0, wm2 = (R)0;
+      for (int m = 0; m < M; ++m) {
+        W[m] = acc[A.s_w[m] * Px + x];
+        wm += W[m];
+        if (m < M - 2) wm2 += W[m];
+      }
+      const R ge2 = acc[A.s_ge2 * Px + x];
+      const R dot = acc[A.s_dot * Px + x];
+      const R gp2 = acc[A.s_gp2 * Px + x];
+      o0 = wm - W[0];
+      if (M >= 3) o0 += ge2 * wm2;
+      if (M >= 2) o0 -= dot;
+      o1 = (R)0.5 * w2sum(W, M);
+      if (M >= 2) o1 -= (R)0.5 * gp2;
+      if (M >= 4) o1 += (R)0.5 * ge2 * w2sum(W, M - 2);
+    }
+    za[x] = mk(o0, o1);
+  }
+  __syncthreads();
+  C* res = block_fft<R>(za, zb, plan, 1, -1);
+  const R sc = (R)(0.5 / (double)Px);
+  C* d0 = reinterpret_cast<C*>(A.out0);
+  C* d1 = reinterpret_cast<C*>(A.out1);
+  for (int p = threadIdx.x; p < G.nxh; p += blockDim.x) {
+    C o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
+    if (p < hx) {
+      C zp = res[p];
+      C zm = conjg(res[(Px - p) % Px]);
+      C s = zp + zm, t = zp - zm;
+      o0 = cscale(s, sc);
+      o1 = mk(t.y * sc, -t.x * sc);
+    }
+    d0[(size_t)y * G.nxh + p] = o0;
+    if (d1) d1[(size_t)y * G.nxh + p] = o1;
+  }
+}
+
+// y-forward: grid (ceil(nxh / TW), njobs).  Keeps modes |q| < ny/2, zeroes the
+// Nyquist row and column, scales by 1/Ly, then applies the epilogue.
+template <typename R>
+__global__ void __launch_bounds__(256) k_yfwd(YFwdArgs A, Geom G, FftPlan plan, int TW) {
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  const int Ly = plan.n;
+  C* a = reinterpret_cast<C*>(smem);
+  C* b = a + (size_t)TW * Ly;
+  const YFwdJob& jb = A.job[blockIdx.y];
+  const int p0 = blockIdx.x * TW;
+  const C* src = reinterpret_cast<const C*>(jb.src);
+  for (int e = threadIdx.x; e < Ly * TW; e += blockDim.x) {
+    const int s = e / TW, c = e - s * TW, p = p0 + c;
+    a[(size_t)c * Ly + s] = p < G.nxh ? src[(size_t)s * G.nxh + p] : mk((R)0, (R)0);
+  }
+  __syncthreads();
+  C* res = block_fft<R>(a, b, plan, TW, -1);
+  const double inv = 1.0 / (double)Ly;
+  const RkArgs& rk = A.rk;
+  for (int e = threadIdx.x; e < G.ny * TW; e += blockDim.x) {
+    const int q = e / TW, c = e - q * TW, p = p0 + c;
+    if (p >= G.nxh) continue;
+    const int qs = signed_q(q, G.ny);
+    cd v = mk(0.0, 0.0);
+    if (2 * p != G.nx && !(G.ny > 1 && 2 * q == G.ny)) {
+      const int slot = ((qs % Ly) + Ly) % Ly;
+      C r = res[(size_t)c * Ly + slot];
+      v = mk((double)r.x * inv, (double)r.y * inv);
+    }
+    const size_t idx = (size_t)q * G.nxh + p;
+    if (jb.epi == YE_STORE) {
+      jb.dst[idx] = v;
+      if (jb.acc_mode == 1) jb.acc[idx] = jb.acc[idx] + v;
+      else if (jb.acc_mode == 2) jb.acc[idx] = v;
+      continue;
+    }
+    const int w = jb.epi == YE_RHS_ETA ? 0 : 1;
+    cd k = v;
+    if (w == 0) {
+      const double kx = 2.0 * M_PI * (double)p / G.lx;
+      const double ky = G.ny > 1 ? 2.0 * M_PI * (double)qs / G.ly : 0.0;
+      const double kk = sqrt(kx * kx + ky * ky);
+      const double dz1 = G.depth > 0.0 ? kk * tanh(kk * G.depth) : kk;
+      k = k + cscale(rk.sin[1][idx], dz1);
+      if (p == 0 && q == 0) k = mk(0.0, 0.0);
+    } else {
+      k = k + cscale(rk.sin[0][idx], -G.g);
+    }
+    switch (rk.stage) {
+      case 0: rk.kout[w][idx] = k; break;
+      case 1:
+        rk.acc[w][idx] = k;
+        rk.sout[w][idx] = rk.xn[w][idx] + cscale(k, 0.5 * rk.dt);
+        break;
+      case 2:
+        rk.acc[w][idx] = rk.acc[w][idx] + cscale(k, 2.0);
+        rk.sout[w][idx] = rk.xn[w][idx] + cscale(k, 0.5 * rk.dt);
+        break;
+      case 3:
+        rk.acc[w][idx] = rk.acc[w][idx] + cscale(k, 2.0);
+        rk.sout[w][idx] = rk.xn[w][idx] + cscale(k, rk.dt);
+        break;
+      default:
+        rk.xn[w][idx] = rk.xn[w][idx] + cscale(rk.acc[w][idx] + k, rk.dt / 6.0);
+        break;
+    }
+  }
+}
+
+// Physical rows <-> spectra on the mode grid (FP64, state in/out only).
+__global__ void __launch_bounds__(256) k_phys_out(const cd* e_rows, const cd* p_rows, double* out_e, double* out_p,
+                                                  Geom G, FftPlan plan) {
+  extern __shared__ unsigned char smem[];
+  const int Px = plan.n, y = blockIdx.x, hx = G.nx / 2;
+  cd* za = reinterpret_cast<cd*>(smem);
+  cd* zb = za + Px;
+  for (int s = threadIdx.x; s < Px; s += blockDim.x) {
+    cd z = mk(0.0, 0.0);
+    int p = -1;
+    bool cj = false;
+    if (s < hx) p = s;
+    else if (s > Px - hx) { p = Px - s; cj = true; }
+    if (p >= 0) {
+      cd va = e_rows[(size_t)y * G.nxh + p], vb = p_rows[(size_t)y * G.nxh + p];
+      if (cj) { va = conjg(va); vb = conjg(vb); }
+      z = mk(va.x - vb.y, va.y + vb.x);
+    }
+    za[s] = z;
+  }
+  __syncthreads();
+  cd* res = block_fft<double>(za, zb, plan, 1, +1);
+  for (int x = threadIdx.x; x < Px; x += blockDim.x) {
+    out_e[(size_t)y * Px + x] = res[x].x;
+    out_p[(size_t)y * Px + x] = res[x].y;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_phys_in(const double* in_e, const double* in_p, cd* e_rows, cd* p_rows,
+                                                 Geom G, FftPlan plan) {
+  extern __shared__ unsigned char smem[];
+  const int Px = plan.n, y = blockIdx.x, hx = G.nx / 2;
+  cd* za = reinterpret_cast<cd*>(smem);
+  cd* zb = za + Px;
+  for (int x = threadIdx.x; x < Px; x += blockDim.x)
+    za[x] = mk(in_e[(size_t)y * Px + x], in_p[(size_t)y * Px + x]);
+  __syncthreads();
+  cd* res = block_fft<double>(za, zb, plan, 1, -1);
+  const double sc = 0.5 / (double)Px;
+  for (int p = threadIdx.x; p < G.nxh; p += blockDim.x) {
+    cd o0 = mk(0.0, 0.0), o1 = mk(0.0, 0.0);
+    if (p < hx) {
+      cd zp = res[p], zm = conjg(res[(Px - p) % Px]);
+      cd s = zp + zm, t = zp - zm;
+      o0 = cscale(s, sc);
+      o1 = mk(t.y * sc, -t.x * sc);
+    }
+    e_rows[(size_t)y * G.nxh + p] = o0;
+    p_rows[(size_t)y * G.nxh + p] = o1;
+  }
+}
+
+__global__ void k_copy_cd(const cd* __restrict__ src, cd* __restrict__ dst, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_finite(const cd* a, const cd* b, size_t n, int* bad) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    if (!isfinite(a[i].x) || !isfinite(a[i].y) || !isfinite(b[i].x) || !isfinite(b[i].y)) atomicOr(bad, 1);
+  }
+}
+
+// ------------------------------------------------------------------ host
+int choose_tw(int Ly, size_t csize) {
+  long cap = 65536 / (2L * Ly * (long)csize);
+  int tw = 1;
+  while (tw * 2 <= cap && tw * 2 <= 256) tw *= 2;
+  return tw;
+}
+
+template <typename R>
+void set_lds_limit(const void* fn, size_t bytes) {
+  if (bytes > 65536) SW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+template <typename R>
+void yinv_t(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, int row0, hipStream_t st) {
+  if (a.njobs == 0) return;
+  const int TW = choose_tw(plan.n, sizeof(cpx<R>));
+  const size_t lds = 2ull * TW * plan.n * sizeof(cpx<R>);
+  dim3 grid((h->G.nxh + TW - 1) / TW, a.njobs);
+  hipLaunchKernelGGL(k_yinv<R>, grid, dim3(256), lds, st, a, h->G, plan, TW, nrows, row0);
+  SW_HIP(hipGetLastError());
+}
+
+template <typename R>
+void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t st) {
+  const int TW = choose_tw(plan.n, sizeof(cpx<R>));
+  const size_t lds = 2ull * TW * plan.n * sizeof(cpx<R>);
+  dim3 grid((h->G.nxh + TW - 1) / TW, a.njobs);
+  hipLaunchKernelGGL(k_yfwd<R>, grid, dim3(256), lds, st, a, h->G, plan, TW);
+  SW_HIP(hipGetLastError());
+}
+
+template <typename R>
+void xpass_t(swense_hos* h, const XArgs& a) {
+  const int Px = h->plan_px.n;
+  const size_t lds = 2ull * Px * sizeof(cpx<R>) + (size_t)a.nslots * Px * sizeof(R);
+  SW_REQUIRE(lds <= 160 * 1024, "x pass needs more LDS than a workgroup has (reduce nx or order)");
+  set_lds_limit<R>(reinterpret_cast<const void*>(&k_xpass<R>), lds);
+  hipLaunchKernelGGL(k_xpass<R>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, h->plan_px);
+  SW_HIP(hipGetLastError());
+}
+
+void add_job(YInvArgs& a, const cd* src, void* dst, int sym, int jpow = 0) {
+  SW_REQUIRE(a.njobs < kMaxYJobs, "too many y jobs");
+  YInvJob& j = a.job[a.njobs++];
+  std::memset(&j, 0, sizeof(j));
+  j.src = src;
+  j.dst = dst;
+  j.sym = sym;
+  j.jpow = jpow;
+}
+
+void add_in(XArgs& a, const void* src, int dx, int role, int slot = 0, int pw = 0) {
+  SW_REQUIRE(a.nin < kMaxXIn, "too many x inputs");
+  XIn& f = a.in[a.nin++];
+  f.src = src;
+  f.dx = dx;
+  f.role = role;
+  f.slot = slot;
+  f.pw = pw;
+}
+
+// Order-M Dirichlet series: given g(1, j) = F^-1(Dz^j base) already in the
+// g buffers for j <= jmax(1), produce modes m = 2..M into `modes` and the
+// g(m, j) they need; jmax(m) = M - m + extra (extra = 1 when W is needed).
+template <typename R>
+void series_t(swense_hos* h, cd** modes, cd* accum, int extra) {
+  const int M = h->d.order_m;
+  for (int m = 1; m < M; ++m) {
+    XArgs xa;
+    std::memset(&xa, 0, sizeof(xa));
+    xa.stage = XS_SERIES;
+    xa.M = M;
+    xa.nslots = 2;
+    xa.s_eta = 0;
+    xa.s_w[0] = 1;
+    add_in(xa, h->e_, 0, XR_ETA);
+    for (int j = 1; j <= m; ++j) add_in(xa, h->gbuf[m + 1 - j][j], 0, XR_G, 1, j);
+    xa.out0 = h->q_;
+    xa.out1 = nullptr;
+    xpass_t<R>(h, xa);
+    YFwdArgs fa;
+    std::memset(&fa, 0, sizeof(fa));
+    fa.njobs = 1;
+    fa.job[0].src = h->q_;
+    fa.job[0].dst = modes[m + 1];
+    fa.job[0].acc = accum;
+    fa.job[0].acc_mode = accum ? 1 : 0;
+    fa.job[0].epi = YE_STORE;
+    yfwd_t<R>(h, fa, h->plan_py, h->st);
+    YInvArgs ya;
+    std::memset(&ya, 0, sizeof(ya));
+    for (int j = 1; j <= M - (m + 1) + extra; ++j) add_job(ya, modes[m + 1], h->gbuf[m + 1][j], SYM_DZ, j);
+    yinv_t<R>(h, ya, h->plan_py, h->Py, 0, h->st);
+  }
+}
+
+template <typename R>
+void rhs_t(swense_hos* h, const cd* se, const cd* sp, const RkArgs& rk, bool want_modes) {
+  const int M = h->d.order_m;
+  const bool three = h->G.ny > 1;
+  YInvArgs ya;
+  std::memset(&ya, 0, sizeof(ya));
+  add_job(ya, se, h->e_, SYM_ONE);
+  if (three) add_job(ya, se, h->ey_, SYM_IKY);
+  add_job(ya, sp, h->ph_, SYM_ONE);
+  if (three) add_job(ya, sp, h->py_, SYM_IKY);
+  for (int j = 1; j <= M; ++j) add_job(ya, sp, h->gbuf[1][j], SYM_DZ, j);
+  yinv_t<R>(h, ya, h->plan_py, h->Py, 0, h->st);
+  if (want_modes) {
+    hipLaunchKernelGGL(k_copy_cd, dim3((h->nc + 255) / 256), dim3(256), 0, h->st, sp, h->amod, h->nc);
+    SW_HIP(hipGetLastError());
+  }
+  series_t<R>(h, h->phim, want_modes ? h->amod : nullptr, 1);
+  // final products
+  XArgs xa;
+  std::memset(&xa, 0, sizeof(xa));
+  xa.stage = XS_FINAL;
+  xa.M = M;
+  xa.s_eta = 0;
+  xa.s_ge2 = 1;
+  xa.s_dot = 2;
+  xa.s_gp2 = 3;
+  for (int m = 0; m < M; ++m) xa.s_w[m] = 4 + m;
+  xa.nslots = 4 + M;
+  add_in(xa, h->e_, 0, XR_ETA);
+  add_in(xa, h->gbuf[1][1], 0, XR_G, xa.s_w[0], 0);
+  add_in(xa, h->e_, 1, XR_GRADPAIR);
+  add_in(xa, h->ph_, 1, XR_NONE);
+  if (three) {
+    add_in(xa, h->ey_, 0, XR_GRADPAIR);
+    add_in(xa, h->py_, 0, XR_NONE);
+  }
+  for (int m = 1; m <= M; ++m)
+    for (int j = 1; m + j <= M + 1; ++j) {
+      if (m == 1 && j == 1) continue;
+      add_in(xa, h->gbuf[m][j], 0, XR_G, xa.s_w[m + j - 2], j - 1);
+    }
+  xa.out0 = h->r0_;
+  xa.out1 = h->r1_;
+  xpass_t<R>(h, xa);
+  YFwdArgs fa;
+  std::memset(&fa, 0, sizeof(fa));
+  fa.njobs = 2;
+  fa.job[0].src = h->r0_;
+  fa.job[0].epi = YE_RHS_ETA;
+  fa.job[1].src = h->r1_;
+  fa.job[1].epi = YE_RHS_PHI;
+  fa.rk = rk;
+  yfwd_t<R>(h, fa, h->plan_py, h->st);
+}
+
+template <typename R>
+void step_t(swense_hos* h, int nsteps) {
+  for (int n = 0; n < nsteps; ++n) {
+    const cd* sin_e[4] = {h->xn[0], h->sa[0], h->sb[0], h->sa[0]};
+    const cd* sin_p[4] = {h->xn[1], h->sa[1], h->sb[1], h->sa[1]};
+    cd* sout_e[4] = {h->sa[0], h->sb[0], h->sa[0], nullptr};
+    cd* sout_p[4] = {h->sa[1], h->sb[1], h->sa[1], nullptr};
+    for (int s = 0; s < 4; ++s) {
+      RkArgs rk;
+      std::memset(&rk, 0, sizeof(rk));
+      rk.stage = s + 1;
+      rk.dt = h->d.dt;
+      rk.xn[0] = h->xn[0];
+      rk.xn[1] = h->xn[1];
+      rk.sin[0] = sin_e[s];
+      rk.sin[1] = sin_p[s];
+      rk.sout[0] = sout_e[s];
+      rk.sout[1] = sout_p[s];
+      rk.acc[0] = h->acc[0];
+      rk.acc[1] = h->acc[1];
+      rhs_t<R>(h, sin_e[s], sin_p[s], rk, false);
+    }
+    h->t += h->d.dt;
+  }
+  h->version++;
+}
+
+template <typename R>
+void rhs_only_t(swense_hos* h, bool want_modes) {
+  RkArgs rk;
+  std::memset(&rk, 0, sizeof(rk));
+  rk.stage = 0;
+  rk.sin[0] = h->xn[0];
+  rk.sin[1] = h->xn[1];
+  rk.kout[0] = h->kk[0];
+  rk.kout[1] = h->kk[1];
+  rhs_t<R>(h, h->xn[0], h->xn[1], rk, want_modes);
+}
+
+// a6: A = sum phi^(m) (from the series), eta_t (the right-hand side) and A_t
+// from the series on f = phis_t - [M>=2] W_M eta_t.
+template <typename R>
+void modes_t(swense_hos* h) {
+  const int M = h->d.order_m;
+  rhs_only_t<R>(h, true);
+  YInvArgs ya;
+  std::memset(&ya, 0, sizeof(ya));
+  add_job(ya, h->kk[0], h->et_, SYM_ONE);
+  add_job(ya, h->kk[1], h->pt_, SYM_ONE);
+  yinv_t<R>(h, ya, h->plan_py, h->Py, 0, h->st);
+  XArgs xa;
+  std::memset(&xa, 0, sizeof(xa));
+  xa.stage = XS_FTILDE;
+  xa.M = M;
+  xa.s_eta = 0;
+  xa.s_w[0] = 1;
+  xa.s_etat = 2;
+  xa.s_phit = 3;
+  xa.nslots = 4;
+  add_in(xa, h->e_, 0, XR_ETA);
+  if (M >= 2)
+    for (int m = 1; m <= M; ++m)
+      for (int j = 1; m + j <= M + 1; ++j) add_in(xa, h->gbuf[m][j], 0, XR_G, 1, j - 1);
+  add_in(xa, h->et_, 0, XR_ETAT);
+  add_in(xa, h->pt_, 0, XR_PHIT);
+  xa.out0 = h->q_;
+  xpass_t<R>(h, xa);
+  YFwdArgs fa;
+  std::memset(&fa, 0, sizeof(fa));
+  fa.njobs = 1;
+  fa.job[0].src = h->q_;
+  fa.job[0].dst = h->bm[1];
+  fa.job[0].acc = h->atmod;
+  fa.job[0].acc_mode = 2;
+  fa.job[0].epi = YE_STORE;
+  yfwd_t<R>(h, fa, h->plan_py, h->st);
+  std::memset(&ya, 0, sizeof(ya));
+  for (int j = 1; j <= M - 1; ++j) add_job(ya, h->bm[1], h->gbuf[1][j], SYM_DZ, j);
+  yinv_t<R>(h, ya, h->plan_py, h->Py, 0, h->st);
+  series_t<R>(h, h->bm, h->atmod, 0);
+  h->modes_version = h->version;
+}
+
+void set_state_phys(swense_hos* h, const double* eta, const double* phis) {
+  const int nx = h->G.nx, ny = h->G.ny;
+  const size_t np = (size_t)nx * ny;
+  SW_HIP(hipMemcpyAsync(h->phys, eta, np * sizeof(double), hipMemcpyHostToDevice, h->st));
+  SW_HIP(hipMemcpyAsync(h->phys + np, phis, np * sizeof(double), hipMemcpyHostToDevice, h->st));
+  cd* rows_e = reinterpret_cast<cd*>(h->phys + 2 * np);
+  cd* rows_p = rows_e + (size_t)ny * h->G.nxh;
+  const size_t lds = 2ull * nx * sizeof(cd);
+  hipLaunchKernelGGL(k_phys_in, dim3(ny), dim3(256), lds, h->st, h->phys, h->phys + np, rows_e, rows_p, h->G,
+                     h->plan_nx);
+  SW_HIP(hipGetLastError());
+  YFwdArgs fa;
+  std::memset(&fa, 0, sizeof(fa));
+  fa.njobs = 2;
+  fa.job[0] = YFwdJob{rows_e, h->xn[0], nullptr, 0, YE_STORE};
+  fa.job[1] = YFwdJob{rows_p, h->xn[1], nullptr, 0, YE_STORE};
+  yfwd_t<double>(h, fa, h->plan_ny, h->st);
+}
+
+void get_state_phys(swense_hos* h, double* eta, double* phis) {
+  const int nx = h->G.nx, ny = h->G.ny;
+  const size_t np = (size_t)nx * ny;
+  cd* rows_e = reinterpret_cast<cd*>(h->phys + 2 * np);
+  cd* rows_p = rows_e + (size_t)ny * h->G.nxh;
+  YInvArgs ya;
+  std::memset(&ya, 0, sizeof(ya));
+  add_job(ya, h->xn[0], rows_e, SYM_ONE);
+  add_job(ya, h->xn[1], rows_p, SYM_ONE);
+  yinv_t<double>(h, ya, h->plan_ny, ny, 0, h->st);
+  const size_t lds = 2ull * nx * sizeof(cd);
+  hipLaunchKernelGGL(k_phys_out, dim3(ny), dim3(256), lds, h->st, rows_e, rows_p, h->phys, h->phys + np, h->G,
+                     h->plan_nx);
+  SW_HIP(hipGetLastError());
+  if (eta) SW_HIP(hipMemcpyAsync(eta, h->phys, np * sizeof(double), hipMemcpyDeviceToHost, h->st));
+  if (phis) SW_HIP(hipMemcpyAsync(phis, h->phys + np, np * sizeof(double), hipMemcpyDeviceToHost, h->st));
+  SW_HIP(hipStreamSynchronize(h->st));
+}
+
+void check_desc(const swense_hos_desc* d) {
+  SW_REQUIRE(d != nullptr, "null descriptor");
+  SW_REQUIRE(d->dim == 2 || d->dim == 3, "dim must be 2 or 3");
+  SW_REQUIRE(d->nx >= 4 && d->nx % 2 == 0 && is_235_smooth(d->nx), "nx must be even, >= 4 and 2/3/5-smooth");
+  if (d->dim == 2) SW_REQUIRE(d->ny == 1, "ny must be 1 in 2D");
+  else SW_REQUIRE(d->ny >= 4 && d->ny % 2 == 0 && is_235_smooth(d->ny), "ny must be even, >= 4 and 2/3/5-smooth");
+  SW_REQUIRE(d->order_m >= 1 && d->order_m <= kMaxM, "order_m must be in [1, 8]");
+  SW_REQUIRE(d->lx > 0 && d->ly > 0 && d->g > 0 && d->rho > 0, "lengths, g and rho must be positive");
+  SW_REQUIRE(d->precision == 0 || d->precision == 1, "precision must be 0 or 1");
+  SW_REQUIRE(d->dealias == 0 || d->dealias == 1, "dealias must be 0 or 1");
+}
+
+int padded_len(int n, int M, int dealias) {
+  if (n == 1) return 1;
+  if (!dealias) return n;
+  int v = ((M + 1) * n + 1) / 2;
+  v += v & 1;
+  while (!is_235_smooth(v)) v += 2;
+  return v;
+}
+
+void allocate(swense_hos* h) {
+  const int M = h->d.order_m;
+  h->nc = (size_t)h->G.ny * h->G.nxh;
+  h->ni = (size_t)h->Py * h->G.nxh;
+  const size_t ncd = 2 * 5 + (size_t)(M + 1) * 2 + 2;  // xn sa sb acc kk, phim bm, amod atmod
+  int ngb = 0;
+  for (int m = 1; m <= M; ++m) ngb += M + 2 - m;
+  const size_t nint = 4 + (size_t)ngb + 5;
+  const size_t nphys = (size_t)h->G.nx * h->G.ny;
+  size_t bytes = ncd * h->nc * sizeof(cd) + nint * h->ni * h->isz() + 2 * nphys * sizeof(double) +
+                 2 * h->nc * sizeof(cd) + 1024;
+  SW_HIP(hipMalloc(&h->pool, bytes));
+  SW_HIP(hipMemsetAsync(h->pool, 0, bytes, h->st));
+  char* p = reinterpret_cast<char*>(h->pool);
+  auto take_cd = [&]() {
+    cd* r = reinterpret_cast<cd*>(p);
+    p += h->nc * sizeof(cd);
+    return r;
+  };
+  auto take_i = [&]() {
+    void* r = p;
+    p += h->ni * h->isz();
+    return r;
+  };
+  for (int w = 0; w < 2; ++w) {
+    h->xn[w] = take_cd();
+    h->sa[w] = take_cd();
+    h->sb[w] = take_cd();
+    h->acc[w] = take_cd();
+    h->kk[w] = take_cd();
+  }
+  for (int m = 0; m <= M; ++m) {
+    h->phim[m] = take_cd();
+    h->bm[m] = take_cd();
+  }
+  h->amod = take_cd();
+  h->atmod = take_cd();
+  h->e_ = take_i();
+  h->ey_ = take_i();
+  h->ph_ = take_i();
+  h->py_ = take_i();
+  for (int m = 1; m <= M; ++m)
+    for (int j = 1; j <= M + 1 - m; ++j) h->gbuf[m][j] = take_i();
+  h->q_ = take_i();
+  h->r0_ = take_i();
+  h->r1_ = take_i();
+  h->et_ = take_i();
+  h->pt_ = take_i();
+  p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255));
+  h->phys = reinterpret_cast<double*>(p);
+}
+
+void load_state(swense_hos* h, const double* eta, const double* phis, int layout) {
+  SW_REQUIRE(eta && phis, "null state arrays");
+  if (layout == SWENSE_SPECTRAL) {
+    // enforce the kept-mode convention: zero Nyquist row/column
+    std::vector<cd> e(h->nc), ph(h->nc);
+    std::memcpy(e.data(), eta, h->nc * sizeof(cd));
+    std::memcpy(ph.data(), phis, h->nc * sizeof(cd));
+    for (int q = 0; q < h->G.ny; ++q)
+      for (int pp = 0; pp < h->G.nxh; ++pp) {
+        bool nyq = (2 * pp == h->G.nx) || (h->G.ny > 1 && 2 * q == h->G.ny);
+        if (nyq) {
+          e[(size_t)q * h->G.nxh + pp] = mk(0.0, 0.0);
+          ph[(size_t)q * h->G.nxh + pp] = mk(0.0, 0.0);
+        }
+      }
+    SW_HIP(hipMemcpyAsync(h->xn[0], e.data(), h->nc * sizeof(cd), hipMemcpyHostToDevice, h->st));
+    SW_HIP(hipMemcpyAsync(h->xn[1], ph.data(), h->nc * sizeof(cd), hipMemcpyHostToDevice, h->st));
+    SW_HIP(hipStreamSynchronize(h->st));
+  } else {
+    SW_REQUIRE(layout == SWENSE_PHYSICAL, "layout must be SWENSE_PHYSICAL or SWENSE_SPECTRAL");
+    set_state_phys(h, eta, phis);
+    SW_HIP(hipStreamSynchronize(h->st));
+  }
+  h->version++;
+}
+
+}  // namespace
+
+void set_error(swense_hos* h, const SwenseError& e) { h->err = e.msg; }
+
+void launch_yinv(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, int row0, hipStream_t st) {
+  if (h->fp64) yinv_t<double>(h, a, plan, nrows, row0, st);
+  else yinv_t<float>(h, a, plan, nrows, row0, st);
+}
+
+void launch_modes(swense_hos* h) {
+  if (h->modes_version == h->version) return;
+  if (h->fp64) modes_t<double>(h);
+  else modes_t<float>(h);
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* swense_version(void) { return "swense-gfx950 0.1"; }
+
+const char* swense_last_error(const swense_hos* h) {
+  if (!h) return "no handle";
+  return h->err.c_str();
+}
+
+int swense_hos_init(const swense_hos_desc* d, const double* eta0, const double* phis0, int layout, void* stream,
+                    swense_hos** out) {
+  if (!out) return SWENSE_EINVAL;
+  *out = nullptr;
+  swense_hos* h = nullptr;
+  try {
+    check_desc(d);
+    h = new swense_hos();
+    h->d = *d;
+    h->st = reinterpret_cast<hipStream_t>(stream);
+    h->fp64 = d->precision == 1;
+    h->G = Geom{d->nx, d->ny, d->nx / 2 + 1, d->lx, d->dim == 2 ? 1.0 : d->ly, d->depth, d->g, d->rho};
+    h->Px = padded_len(d->nx, d->order_m, d->dealias);
+    h->Py = padded_len(d->ny, d->order_m, d->dealias);
+    h->t = d->t0;
+    SW_HIP(hipGetDevice(&h->device));
+    h->plan_px = h->tw.get(h->Px, h->fp64);
+    h->plan_py = h->tw.get(h->Py, h->fp64);
+    h->plan_nx = h->tw.get(d->nx, true);
+    h->plan_ny = h->tw.get(d->ny, true);
+    allocate(h);
+    load_state(h, eta0, phis0, layout);
+    *out = h;
+    return SWENSE_OK;
+  } catch (const SwenseError& e) {
+    if (h) {
+      swense_hos_destroy(h);
+    }
+    return e.code;
+  } catch (...) {
+    if (h) swense_hos_destroy(h);
+    return SWENSE_EHIP;
+  }
+}
+
+int swense_hos_set_state(swense_hos* h, const double* eta, const double* phis, int layout, double t) {
+  if (!h) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    load_state(h, eta, phis, layout);
+    h->t = t;
+    return SWENSE_OK;
+  });
+}
+
+int swense_hos_step(swense_hos* h, int nsteps) {
+  if (!h) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    SW_REQUIRE(nsteps >= 0, "nsteps must be >= 0");
+    if (h->fp64) step_t<double>(h, nsteps);
+    else step_t<float>(h, nsteps);
+    return SWENSE_OK;
+  });
+}
+
+int swense_hos_get_state(swense_hos* h, double* eta, double* phis, double* t, int layout) {
+  if (!h) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    int* bad = nullptr;
+    SW_HIP(hipMalloc(&bad, sizeof(int)));
+    SW_HIP(hipMemsetAsync(bad, 0, sizeof(int), h->st));
+    hipLaunchKernelGGL(k_finite, dim3((h->nc + 255) / 256), dim3(256), 0, h->st, h->xn[0], h->xn[1], h->nc, bad);
+    int hb = 0;
+    SW_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->st));
+    SW_HIP(hipStreamSynchronize(h->st));
+    SW_HIP(hipFree(bad));
+    if (layout == SWENSE_SPECTRAL) {
+      if (eta) SW_HIP(hipMemcpyAsync(eta, h->xn[0], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+      if (phis) SW_HIP(hipMemcpyAsync(phis, h->xn[1], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+      SW_HIP(hipStreamSynchronize(h->st));
+    } else {
+      SW_REQUIRE(layout == SWENSE_PHYSICAL, "layout must be SWENSE_PHYSICAL or SWENSE_SPECTRAL");
+      get_state_phys(h, eta, phis);
+    }
+    if (t) *t = h->t;
+    if (hb) throw SwenseError{SWENSE_EUNSTABLE, "state holds non-finite values"};
+    return SWENSE_OK;
+  });
+}
+
+int swense_hos_rhs(swense_hos* h, double* eta_t, double* phis_t) {
+  if (!h) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    if (h->fp64) rhs_only_t<double>(h, false);
+    else rhs_only_t<float>(h, false);
+    if (eta_t) SW_HIP(hipMemcpyAsync(eta_t, h->kk[0], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+    if (phis_t) SW_HIP(hipMemcpyAsync(phis_t, h->kk[1], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+    SW_HIP(hipStreamSynchronize(h->st));
+    return SWENSE_OK;
+  });
+}
+
+int swense_hos_modes(swense_hos* h, double* a_hat, double* a_t_hat, double* eta_t_hat) {
+  if (!h) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    launch_modes(h);
+    if (a_hat) SW_HIP(hipMemcpyAsync(a_hat, h->amod, h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+    if (a_t_hat) SW_HIP(hipMemcpyAsync(a_t_hat, h->atmod, h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+    if (eta_t_hat) SW_HIP(hipMemcpyAsync(eta_t_hat, h->kk[0], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+    SW_HIP(hipStreamSynchronize(h->st));
+    return SWENSE_OK;
+  });
+}
+
+int swense_hos_energy(swense_hos* h, double* energy) {
+  if (!h || !energy) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    launch_modes(h);
+    std::vector<cd> e(h->nc), ph(h->nc), et(h->nc);
+    SW_HIP(hipMemcpyAsync(e.data(), h->xn[0], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+    SW_HIP(hipMemcpyAsync(ph.data(), h->xn[1], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+    SW_HIP(hipMemcpyAsync(et.data(), h->kk[0], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+    SW_HIP(hipStreamSynchronize(h->st));
+    // Parseval on the half spectrum: p = 0 column once, p > 0 twice.
+    double s1 = 0.0, s2 = 0.0;
+    for (int q = 0; q < h->G.ny; ++q)
+      for (int p = 0; p < h->G.nxh; ++p) {
+        const size_t i = (size_t)q * h->G.nxh + p;
+        const double w = p == 0 ? 1.0 : 2.0;
+        s1 += w * (ph[i].x * et[i].x + ph[i].y * et[i].y);
+        s2 += w * (e[i].x * e[i].x + e[i].y * e[i].y);
+      }
+    const double area = h->G.lx * h->G.ly;
+    *energy = 0.5 * area * s1 + 0.5 * h->G.g * area * s2;
+    return SWENSE_OK;
+  });
+}
+
+void swense_hos_destroy(swense_hos* h) {
+  if (!h) return;
+  eval_release(h);
+  if (h->pool) (void)hipFree(h->pool);
+  h->tw.release();
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// Internal state of a realisation handle and the launch helpers shared by
+// the HOS and reconstruction translation units.
+#pragma once
+
+#include "common.h"
+
+// Symbol kinds multiplied into a half spectrum before the y transform.
+enum SymKind { SYM_ONE = 0, SYM_IKX = 1, SYM_IKY = 2, SYM_DZ = 3, SYM_EVAL = 4 };
+
+// Field-in-layer description of an evaluation symbol: vertical factor
+// (0: C = cosh k(z+h)/cosh kh, 1: S = sinh k(z+h)/cosh kh, 2: none) times
+// multiplier (0: 1, 1: i kx, 2: i ky, 3: |k|), optional B-spline prefilter.
+struct EvalSym {
+  int vf;
+  int mult;
+  int pre;
+  int gx, gy;
+};
+
+struct YInvJob {
+  const cd* src;  // [ny][nxh] FP64 half spectrum
+  void* dst;      // [nrows][nxh] complex, transform precision
+  int sym;
+  int jpow;
+  double z;
+  EvalSym ev;
+};
+
+constexpr int kMaxYJobs = 16;
+struct YInvArgs {
+  int njobs;
+  YInvJob job[kMaxYJobs];
+};
+
+// Roles of an input field of the fused x pass (see the HOS x-pass kernel).
+enum XRole { XR_NONE = 0, XR_ETA = 1, XR_GRADPAIR = 2, XR_G = 3, XR_ETAT = 4, XR_PHIT = 5 };
+enum XStage { XS_SERIES = 0, XS_FINAL = 1, XS_FTILDE = 2 };
+
+struct XIn {
+  const void* src;  // [Py][nxh] complex rows (x still spectral)
+  int dx;           // multiply by i kx before the x transform
+  int role;
+  int slot;         // accumulator slot written by XR_G
+  int pw;           // power of eta for XR_G
+};
+
+constexpr int kMaxXIn = 24;
+constexpr int kMaxM = 8;
+struct XArgs {
+  int nin;
+  XIn in[kMaxXIn];
+  int stage;
+  int M;
+  int nslots;
+  int s_eta, s_ge2, s_dot, s_gp2, s_etat, s_phit;
+  int s_w[kMaxM];
+  void* out0;
+  void* out1;
+};
+
+// Epilogue of the forward y transform.
+enum YEpi { YE_STORE = 0, YE_RHS_ETA = 1, YE_RHS_PHI = 2 };
+
+struct YFwdJob {
+  const void* src;  // [Py][nxh] complex rows
+  cd* dst;          // [ny][nxh] FP64 (YE_STORE)
+  cd* acc;          // accumulate target (YE_STORE) or null
+  int acc_mode;     // 0 none, 1 add, 2 assign
+  int epi;
+};
+
+// RK4 bookkeeping for the right-hand-side epilogue (classical RK4 on the
+// spectral state; stage 0 only stores the right-hand side).
+struct RkArgs {
+  int stage;
+  double dt;
+  cd* xn[2];         // base state (eta, phis), updated in place at stage 4
+  const cd* sin[2];  // stage input state (used by the exact linear part)
+  cd* sout[2];       // next stage input
+  cd* acc[2];        // k1 + 2 k2 + 2 k3
+  cd* kout[2];       // right-hand side output (stage 0)
+};
+
+constexpr int kMaxYFwd = 4;
+struct YFwdArgs {
+  int njobs;
+  YFwdJob job[kMaxYFwd];
+  RkArgs rk;
+};
+
+struct EvalWork;  // reconstruction workspace (evalgrid.hip)
+
+struct swense_hos {
+  swense_hos_desc d{};
+  Geom G{};
+  hipStream_t st = nullptr;
+  bool fp64 = false;
+  int Px = 0, Py = 0;
+  TwiddleCache tw;
+  FftPlan plan_px{}, plan_py{}, plan_nx{}, plan_ny{};
+  double t = 0.0;
+  long version = 0;        // bumped whenever the state changes
+  long modes_version = -1;  // state version the mean-level modes belong to
+  std::string err;
+  int device = 0;
+
+  // FP64 spectral buffers, each [ny][nxh]
+  size_t nc = 0;
+  void* pool = nullptr;  // one allocation carved below
+  cd* xn[2]{};
+  cd* sa[2]{};
+  cd* sb[2]{};
+  cd* acc[2]{};
+  cd* kk[2]{};            // right-hand side at the current state
+  cd* phim[kMaxM + 1]{};  // series modes phi^(m), m >= 2 (index m)
+  cd* amod = nullptr;     // A   = sum_m phi^(m)
+  cd* atmod = nullptr;    // A_t = sum_m B^(m)
+  cd* bm[kMaxM + 1]{};    // series modes of phi_t
+  // transform-precision intermediates, each [Py][nxh] complex
+  size_t ni = 0;           // elements per intermediate
+  void* e_ = nullptr;      // eta
+  void* ey_ = nullptr;     // i ky eta
+  void* ph_ = nullptr;     // phis
+  void* py_ = nullptr;     // i ky phis
+  void* gbuf[kMaxM + 1][kMaxM + 2]{};  // g(m, j) = F^-1(Dz^j phi^(m))
+  void* q_ = nullptr;      // series product
+  void* r0_ = nullptr;     // nonlinear eta_t
+  void* r1_ = nullptr;     // nonlinear phis_t
+  void* et_ = nullptr;     // eta_t rows
+  void* pt_ = nullptr;     // phis_t rows
+  // physical staging for state in/out, FP64 [ny][nx] x 2
+  double* phys = nullptr;
+  EvalWork* ev = nullptr;
+
+  size_t isz() const { return fp64 ? sizeof(cd) : sizeof(cf); }
+};
+
+// ---- launch helpers implemented in hos.hip (templated on precision there)
+void launch_yinv(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, int row0, hipStream_t st);
+void launch_modes(swense_hos* h);  // A, A_t, eta_t at the current state (if stale)
+void set_error(swense_hos* h, const SwenseError& e);
+
+// ---- reconstruction cleanup (evalgrid.hip)
+void eval_release(swense_hos* h);
+
+// run a body and convert exceptions to error codes
+template <typename F>
+int guarded(swense_hos* h, F&& f) {
+  try {
+    return f();
+  } catch (const SwenseError& e) {
+    if (h) set_error(h, e);
+    return e.code;
+  } catch (const std::exception& e) {
+    if (h) set_error(h, SwenseError{SWENSE_EHIP, e.what()});
+    return SWENSE_EHIP;
+  }
+}

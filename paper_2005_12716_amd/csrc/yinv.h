@@ -1,0 +1,87 @@
+// Inverse transform along y of symbol-weighted half spectra (shared by the
+// HOS step and the grid evaluation).
+#pragma once
+
+#include "internal.h"
+
+__device__ __forceinline__ cd symbol_of(const Geom& G, const YInvJob& jb, int p, int qs) {
+  const double kx = 2.0 * M_PI * (double)p / G.lx;
+  const double ky = G.ny > 1 ? 2.0 * M_PI * (double)qs / G.ly : 0.0;
+  const double k = sqrt(kx * kx + ky * ky);
+  switch (jb.sym) {
+    case SYM_ONE: return mk(1.0, 0.0);
+    case SYM_IKX: return mk(0.0, kx);
+    case SYM_IKY: return mk(0.0, ky);
+    case SYM_DZ: {
+      double s = 1.0;
+      for (int i = 0; i < jb.jpow; ++i) s *= k;
+      if ((jb.jpow & 1) && G.depth > 0.0) s *= tanh(k * G.depth);
+      return mk(s, 0.0);
+    }
+    default: {
+      double C = 1.0, S = 1.0;
+      if (jb.ev.vf != 2) vfactors(k, jb.z, G.depth, C, S);
+      const double f = jb.ev.vf == 0 ? C : (jb.ev.vf == 1 ? S : 1.0);
+      cd m;
+      switch (jb.ev.mult) {
+        case 0: m = mk(f, 0.0); break;
+        case 1: m = mk(0.0, kx * f); break;
+        case 2: m = mk(0.0, ky * f); break;
+        default: m = mk(k * f, 0.0); break;
+      }
+      if (jb.ev.pre) {
+        double bx = (4.0 + 2.0 * cos(2.0 * M_PI * (double)p / (double)jb.ev.gx)) / 6.0;
+        double by = G.ny > 1 ? (4.0 + 2.0 * cos(2.0 * M_PI * (double)qs / (double)jb.ev.gy)) / 6.0 : 1.0;
+        m = cscale(m, 1.0 / (bx * by));
+      }
+      return m;
+    }
+  }
+}
+
+// y-inverse: grid (ceil(nxh / TW), njobs).  Slot s of the length-Ly
+// sequence gathers every kept mode q whose signed index is = s (mod Ly):
+// zero-padding when Ly >= ny, alias-folding when Ly < ny.  Rows
+// (row0 + r) mod Ly, r < nrows, are stored.
+template <typename R>
+__device__ __forceinline__ void yinv_body(const YInvJob& jb, const Geom& G, const FftPlan& plan, int TW, int nrows,
+                                          int row0, unsigned char* smem) {
+  using C = cpx<R>;
+  const int Ly = plan.n;
+  C* a = reinterpret_cast<C*>(smem);
+  C* b = a + (size_t)TW * Ly;
+  const int p0 = blockIdx.x * TW;
+  const int half = G.ny / 2;
+  for (int e = threadIdx.x; e < Ly * TW; e += blockDim.x) {
+    const int s = e / TW, c = e - s * TW, p = p0 + c;
+    double ax = 0.0, ay = 0.0;
+    if (p < G.nxh && 2 * p != G.nx) {
+      if (G.ny == 1) {
+        if (s == 0) {
+          cd v = cmul(jb.src[p], symbol_of(G, jb, p, 0));
+          ax = v.x;
+          ay = v.y;
+        }
+      } else {
+        for (int qs = s - ((s + half - 1) / Ly) * Ly; qs <= half - 1; qs += Ly) {
+          const int q = qs >= 0 ? qs : qs + G.ny;
+          cd v = cmul(jb.src[(size_t)q * G.nxh + p], symbol_of(G, jb, p, qs));
+          ax += v.x;
+          ay += v.y;
+        }
+      }
+    }
+    a[(size_t)c * Ly + s] = mk((R)ax, (R)ay);
+  }
+  __syncthreads();
+  C* res = block_fft<R>(a, b, plan, TW, +1);
+  C* dst = reinterpret_cast<C*>(jb.dst);
+  for (int e = threadIdx.x; e < nrows * TW; e += blockDim.x) {
+    const int r = e / TW, c = e - r * TW, p = p0 + c;
+    if (p < G.nxh) {
+      const int y = (row0 + r) % Ly;
+      dst[(size_t)r * G.nxh + p] = res[(size_t)c * Ly + y];
+    }
+  }
+}
+

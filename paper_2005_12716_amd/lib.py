@@ -1,0 +1,255 @@
+"""ctypes binding of libswense.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts numpy host
+arrays and torch device tensors to the plain pointers of the C ABI declared
+in include/swense.h.  torch is imported first so that the library shares
+torch's HIP runtime, device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libswense.so")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ERANGE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+PHI, U, V, W, P, PHI_T, U_T, V_T, W_T, ETA, ETA_T = (1 << i for i in range(11))
+ALL_FIELDS = (1 << 11) - 1
+FIELD_BITS = [PHI, U, V, W, P, PHI_T, U_T, V_T, W_T, ETA, ETA_T]
+PHYSICAL, SPECTRAL = 0, 1
+
+
+class HosDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("lx", C.c_double), ("ly", C.c_double),
+                ("depth", C.c_double), ("g", C.c_double), ("rho", C.c_double), ("order_m", C.c_int),
+                ("dealias", C.c_int), ("precision", C.c_int), ("dt", C.c_double), ("t0", C.c_double)]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("gx", C.c_int), ("gy", C.c_int), ("ix0", C.c_int), ("iy0", C.c_int), ("wx", C.c_int),
+                ("wy", C.c_int), ("nl", C.c_int), ("z", C.POINTER(C.c_double))]
+
+
+class SeaDesc(C.Structure):
+    _fields_ = [("kind", C.c_int), ("hs", C.c_double), ("kp", C.c_double), ("gamma", C.c_double),
+                ("spreading", C.c_int), ("mode", C.c_int), ("ka", C.c_double)]
+
+
+class SwenseError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"swense error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load the built library; raises if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2005_12716_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, fp = C.c_void_p, C.POINTER(C.c_double), C.c_void_p
+    sig = {
+        "swense_version": (C.c_char_p, []),
+        "swense_last_error": (C.c_char_p, [vp]),
+        "swense_sea_spectrum": (C.c_int, [C.POINTER(HosDesc), C.POINTER(SeaDesc), vp, vp, vp]),
+        "swense_hos_init": (C.c_int, [C.POINTER(HosDesc), vp, vp, C.c_int, vp, C.POINTER(vp)]),
+        "swense_hos_set_state": (C.c_int, [vp, vp, vp, C.c_int, C.c_double]),
+        "swense_hos_step": (C.c_int, [vp, C.c_int]),
+        "swense_hos_get_state": (C.c_int, [vp, vp, vp, dp, C.c_int]),
+        "swense_hos_rhs": (C.c_int, [vp, vp, vp]),
+        "swense_hos_modes": (C.c_int, [vp, vp, vp, vp]),
+        "swense_hos_energy": (C.c_int, [vp, dp]),
+        "swense_eval_grid": (C.c_int, [vp, C.POINTER(GridDesc), C.c_uint, fp]),
+        "swense_eval_grid_size": (C.c_size_t, [vp, C.POINTER(GridDesc), C.c_uint]),
+        "swense_cells_bind": (C.c_int, [vp, C.POINTER(GridDesc), C.c_longlong, vp, C.POINTER(vp)]),
+        "swense_interp_cells": (C.c_int, [vp, vp, C.c_uint, fp, C.POINTER(C.c_longlong)]),
+        "swense_interp_divergence": (C.c_int, [vp, vp, fp]),
+        "swense_hos_destroy": (None, [vp]),
+        "swense_cells_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swense_hos_init",
+            "swense_hos_set_state", "swense_hos_step", "swense_hos_get_state", "swense_hos_rhs",
+            "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
+            "swense_cells_bind", "swense_interp_cells", "swense_interp_divergence", "swense_hos_destroy",
+            "swense_cells_destroy"]
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def hos_desc(dim, nx, ny, lx, ly, depth, order_m=3, dt=0.1, g=1.0, rho=1.0, dealias=1, precision=0, t0=0.0):
+    return HosDesc(dim, nx, ny, lx, ly, depth, g, rho, order_m, dealias, precision, dt, t0)
+
+
+def grid_desc(gx, gy, z, window=None):
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    ix0, iy0, wx, wy = window if window is not None else (0, 0, gx, gy)
+    gd = GridDesc(gx, gy, ix0, iy0, wx, wy, z.size, z.ctypes.data_as(C.POINTER(C.c_double)))
+    gd._z = z  # keep alive
+    return gd
+
+
+def sea_spectrum(desc: HosDesc, kind=0, hs=0.0, kp=1.0, gamma=3.3, spreading=0, mode=0, ka=0.0, phases=None):
+    """Initial half spectra (eta_hat, phis_hat) as complex128 [ny][nx/2+1]."""
+    L = load()
+    ny = 1 if desc.dim == 2 else desc.ny
+    nxh = desc.nx // 2 + 1
+    e = np.zeros((ny, nxh), dtype=np.complex128)
+    p = np.zeros((ny, nxh), dtype=np.complex128)
+    ph = None if phases is None else np.ascontiguousarray(phases, dtype=np.float64)
+    sd = SeaDesc(kind, hs, kp, gamma, spreading, mode, ka)
+    rc = L.swense_sea_spectrum(C.byref(desc), C.byref(sd), _ptr(ph), _ptr(e), _ptr(p))
+    if rc != OK:
+        raise SwenseError(rc, "sea_spectrum")
+    return e, p
+
+
+class Hos:
+    """One HOS realisation on the current torch device and stream."""
+
+    def __init__(self, desc: HosDesc, eta, phis, layout=SPECTRAL, stream=None):
+        self.L = load()
+        self.desc = desc
+        self.ny = 1 if desc.dim == 2 else desc.ny
+        self.nxh = desc.nx // 2 + 1
+        eta = np.ascontiguousarray(eta, dtype=np.complex128 if layout == SPECTRAL else np.float64)
+        phis = np.ascontiguousarray(phis, dtype=np.complex128 if layout == SPECTRAL else np.float64)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = st
+        h = C.c_void_p()
+        rc = self.L.swense_hos_init(C.byref(desc), _ptr(eta), _ptr(phis), layout, C.c_void_p(st.cuda_stream),
+                                    C.byref(h))
+        if rc != OK:
+            raise SwenseError(rc, "hos_init")
+        self.h = h
+
+    def _check(self, rc, what):
+        if rc not in (OK,):
+            msg = self.L.swense_last_error(self.h)
+            raise SwenseError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def step(self, n=1):
+        self._check(self.L.swense_hos_step(self.h, n), "step")
+
+    def set_state(self, eta, phis, layout=SPECTRAL, t=0.0):
+        eta = np.ascontiguousarray(eta, dtype=np.complex128 if layout == SPECTRAL else np.float64)
+        phis = np.ascontiguousarray(phis, dtype=np.complex128 if layout == SPECTRAL else np.float64)
+        self._check(self.L.swense_hos_set_state(self.h, _ptr(eta), _ptr(phis), layout, t), "set_state")
+
+    def state(self, layout=SPECTRAL):
+        if layout == SPECTRAL:
+            e = np.zeros((self.ny, self.nxh), dtype=np.complex128)
+            p = np.zeros_like(e)
+        else:
+            e = np.zeros((self.ny, self.desc.nx))
+            p = np.zeros_like(e)
+        t = C.c_double()
+        self._check(self.L.swense_hos_get_state(self.h, _ptr(e), _ptr(p), C.byref(t), layout), "get_state")
+        return e, p, t.value
+
+    def rhs(self):
+        e = np.zeros((self.ny, self.nxh), dtype=np.complex128)
+        p = np.zeros_like(e)
+        self._check(self.L.swense_hos_rhs(self.h, _ptr(e), _ptr(p)), "rhs")
+        return e, p
+
+    def modes(self):
+        a = np.zeros((self.ny, self.nxh), dtype=np.complex128)
+        at = np.zeros_like(a)
+        et = np.zeros_like(a)
+        self._check(self.L.swense_hos_modes(self.h, _ptr(a), _ptr(at), _ptr(et)), "modes")
+        return a, at, et
+
+    def energy(self):
+        e = C.c_double()
+        self._check(self.L.swense_hos_energy(self.h, C.byref(e)), "energy")
+        return e.value
+
+    def grid_size(self, gd, mask):
+        return int(self.L.swense_eval_grid_size(self.h, C.byref(gd), mask))
+
+    def eval_grid(self, gd, mask, out=None):
+        n = self.grid_size(gd, mask)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device="cuda")
+        assert out.is_cuda and out.dtype == torch.float32 and out.numel() >= n
+        self._check(self.L.swense_eval_grid(self.h, C.byref(gd), mask, _ptr(out)), "eval_grid")
+        return out
+
+    def bind(self, gd, xyz: torch.Tensor):
+        return Cells(self, gd, xyz)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.swense_hos_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Cells:
+    """A bound static point cloud (device FP64 coordinates [3][n])."""
+
+    def __init__(self, hos: Hos, gd, xyz: torch.Tensor):
+        assert xyz.is_cuda and xyz.dtype == torch.float64 and xyz.dim() == 2 and xyz.shape[0] == 3
+        xyz = xyz.contiguous()
+        self.hos = hos
+        self.n = xyz.shape[1]
+        c = C.c_void_p()
+        rc = hos.L.swense_cells_bind(hos.h, C.byref(gd), self.n, _ptr(xyz), C.byref(c))
+        hos._check(rc, "cells_bind")
+        self.c = c
+        self.gd = gd
+
+    def interp(self, mask, out=None, count=True):
+        nf = bin(mask).count("1")
+        if out is None:
+            out = torch.empty((nf, self.n), dtype=torch.float32, device="cuda")
+        nbad = C.c_longlong(-1)
+        rc = self.hos.L.swense_interp_cells(self.hos.h, self.c, mask, _ptr(out), C.byref(nbad) if count else None)
+        if rc not in (OK, ERANGE):
+            self.hos._check(rc, "interp_cells")
+        return out, (nbad.value if count else None)
+
+    def divergence(self, out=None):
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        self.hos._check(self.hos.L.swense_interp_divergence(self.hos.h, self.c, _ptr(out)), "divergence")
+        return out
+
+    def close(self):
+        if getattr(self, "c", None):
+            self.hos.L.swense_cells_destroy(self.c)
+            self.c = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

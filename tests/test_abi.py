@@ -1,0 +1,67 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/swense.h declares, and its host set-up routine (initial sea
+spectra, no GPU involved) matches the oracle."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import Grid, sea
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "swense.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(swense_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for n in ["swense_hos_init", "swense_hos_step", "swense_eval_grid", "swense_cells_bind", "swense_interp_cells"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2005_12716_amd import lib
+    L = lib.load()
+    for n in _declared():
+        assert hasattr(L, n), n
+    assert set(_declared()) <= set(lib.EXPORTED) | {"swense_version"}
+    assert L.swense_version().startswith(b"swense")
+
+
+@pytest.mark.parametrize("dim,nx,ny,spread", [(3, 32, 16, 0), (3, 24, 20, 1), (2, 64, 1, 0)])
+def test_sea_spectrum_matches_oracle_jonswap(dim, nx, ny, spread):
+    from paper_2005_12716_amd import lib
+    lam = 2 * math.pi
+    lx, ly = nx * lam / 6.4, (ny * lam / 6.4 if ny > 1 else 1.0)
+    d = lib.hos_desc(dim, nx, ny, lx, ly, -1.0)
+    phases = synth.mode_phases(3, ny, nx // 2 + 1)
+    e, p = lib.sea_spectrum(d, kind=0, hs=0.02 * lam, kp=1.0, gamma=3.3, spreading=spread, phases=phases)
+    g = Grid(nx=nx, ny=ny, lx=lx, ly=ly, depth=-1.0)
+    er, pr = sea.jonswap(g, 0.02 * lam, 1.0, 3.3, phases, "cos2" if spread == 0 else "uni")
+    assert np.abs(e - er).max() <= 1e-13 * np.abs(er).max()
+    assert np.abs(p - pr).max() <= 1e-13 * np.abs(pr).max()
+
+
+@pytest.mark.parametrize("depth", [2.0, -1.0])
+def test_sea_spectrum_matches_oracle_stokes(depth):
+    from paper_2005_12716_amd import lib
+    lam = 2 * math.pi
+    d = lib.hos_desc(2, 256, 1, 4 * lam, 1.0, depth)
+    e, p = lib.sea_spectrum(d, kind=1, mode=4, ka=0.1)
+    g = Grid(nx=256, ny=1, lx=4 * lam, ly=1.0, depth=depth)
+    er, pr, _ = sea.stokes2(g, 4, 0.1)
+    assert np.abs(e - er).max() < 1e-16 and np.abs(p - pr).max() < 1e-15
+
+
+def test_bad_descriptors_are_rejected_without_gpu_work():
+    from paper_2005_12716_amd import lib
+    d = lib.hos_desc(2, 63, 1, 1.0, 1.0, -1.0)
+    with pytest.raises(lib.SwenseError):
+        lib.sea_spectrum(d, kind=1, mode=4, ka=0.1)
