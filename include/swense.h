@@ -190,6 +190,32 @@ int swense_interp_cells(swense_hos* h, swense_cells* c, unsigned mask, float* ou
  * dw/dz of the interpolant (device FP32 [n], caller order).  Asynchronous. */
 int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div);
 
+/* ---- per-kernel timing -------------------------------------------------- */
+
+/* Kernel classes timed by the profiler. */
+enum {
+  SWENSE_K_YINV = 0,      /* HOS inverse y transforms                   */
+  SWENSE_K_XPASS = 1,     /* HOS fused x pass (products)                */
+  SWENSE_K_YFWD = 2,      /* HOS forward y transforms + RK4 epilogue    */
+  SWENSE_K_YINV_EVAL = 3, /* grid evaluation, y transforms              */
+  SWENSE_K_XEVAL = 4,     /* grid evaluation, x transforms (volume)     */
+  SWENSE_K_XEVAL_SURF = 5,/* grid evaluation, x transforms (surface)    */
+  SWENSE_K_INTERP = 6,    /* interpolation gather                       */
+  SWENSE_K_INTERP_DIV = 7,/* divergence of the interpolant              */
+  SWENSE_K_BIND = 8,      /* point binding                              */
+  SWENSE_K_AUX = 9,       /* copies, fills, state conversion            */
+  SWENSE_K_COUNT = 10
+};
+
+/* Enable (1) or disable (0) per-kernel timing on the handle's stream: while
+ * enabled, every launch is bracketed by a pair of HIP events.  Enabling
+ * clears the accumulated records. */
+int swense_profile_enable(swense_hos* h, int enable);
+
+/* Synchronise and return the summed duration (ms) and the launch count of
+ * kernel class `kernel` recorded since profiling was enabled. */
+int swense_profile_read(swense_hos* h, int kernel, double* total_ms, long long* count);
+
 /* ---- lifetime ---------------------------------------------------------- */
 void swense_hos_destroy(swense_hos* h);
 void swense_cells_destroy(swense_cells* c);

@@ -528,7 +528,7 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
       for (int g = 0; g < f; ++g)
         if ((mask & (1u << g)) && g != F_ETA && g != F_ETAT && !(pre && g == F_P)) ++slot;
       const size_t n = (size_t)A.nl * plane;
-      hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, h->st, out + (size_t)slot * n, n, 0.0f);
+      SW_LAUNCH(h, SWENSE_K_AUX, k_fill, dim3((n + 255) / 256), dim3(256), 0, h->st, out + (size_t)slot * n, n, 0.0f);
       SW_HIP(hipGetLastError());
     }
   }
@@ -549,7 +549,7 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     const size_t lds = 2ull * TW * py.n * csz;
     dim3 grid((h->G.nxh + TW - 1) / TW, njobs);
     SW_REQUIRE(njobs <= 65535, "too many (field, layer) pairs");
-    hipLaunchKernelGGL(k_yinv_eval<R>, grid, dim3(256), lds, h->st, A, h->G, py, TW);
+    SW_LAUNCH(h, SWENSE_K_YINV_EVAL, k_yinv_eval<R>, grid, dim3(256), lds, h->st, A, h->G, py, TW);
     SW_HIP(hipGetLastError());
   }
   if (A.nvol > 0) {
@@ -558,7 +558,7 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     if (lds > 65536)
       SW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xeval_vol<R>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_xeval_vol<R>, dim3(A.wy, A.nl), dim3(256), lds, h->st, A, h->G, px);
+    SW_LAUNCH(h, SWENSE_K_XEVAL, k_xeval_vol<R>, dim3(A.wy, A.nl), dim3(256), lds, h->st, A, h->G, px);
     SW_HIP(hipGetLastError());
   }
   if (A.nsurf > 0) {
@@ -566,7 +566,7 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     if (lds > 65536)
       SW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xeval_surf<R>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_xeval_surf<R>, dim3(A.wy), dim3(256), lds, h->st, A, h->G, px);
+    SW_LAUNCH(h, SWENSE_K_XEVAL_SURF, k_xeval_surf<R>, dim3(A.wy), dim3(256), lds, h->st, A, h->G, px);
     SW_HIP(hipGetLastError());
   }
 }
@@ -727,7 +727,7 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
     if (n > 0) {
       const double dx = h->G.lx / gd->gx;
       const double dy = h->G.ny > 1 ? h->G.ly / gd->gy : 1.0;
-      hipLaunchKernelGGL(k_bind, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->st, xyz, n, c->dev, c->zdev,
+      SW_LAUNCH(h, SWENSE_K_BIND, k_bind, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->st, xyz, n, c->dev, c->zdev,
                          gd->nl, dx, dy, gd->gx, h->G.ny > 1 ? gd->gy : 1, gd->ix0, gd->iy0, gd->wx, gd->wy,
                          h->G.ny > 1 ? 1 : 0, h->G.rho * h->G.g, dbad);
       SW_HIP(hipGetLastError());
@@ -751,7 +751,7 @@ int swense_interp_cells(swense_hos* h, swense_cells* c, unsigned mask, float* ou
       refresh_coef(h, c, cm);
       InterpArgs A;
       interp_args(h, c, mask, out, A);
-      hipLaunchKernelGGL(k_interp, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, h->st, A, c->dev);
+      SW_LAUNCH(h, SWENSE_K_INTERP, k_interp, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, h->st, A, c->dev);
       SW_HIP(hipGetLastError());
     }
     if (n_out_of_range) {
@@ -774,7 +774,7 @@ int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div) {
     interp_args(h, c, m, nullptr, A);
     const double dx = h->G.lx / c->gd.gx;
     const double dy = three ? h->G.ly / c->gd.gy : 1.0;
-    hipLaunchKernelGGL(k_interp_div, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, h->st, A, c->dev, dx, dy,
+    SW_LAUNCH(h, SWENSE_K_INTERP_DIV, k_interp_div, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, h->st, A, c->dev, dx, dy,
                        div);
     SW_HIP(hipGetLastError());
     return (int)SWENSE_OK;

@@ -313,7 +313,7 @@ void yinv_t(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, in
   const int TW = choose_tw(plan.n, sizeof(cpx<R>));
   const size_t lds = 2ull * TW * plan.n * sizeof(cpx<R>);
   dim3 grid((h->G.nxh + TW - 1) / TW, a.njobs);
-  hipLaunchKernelGGL(k_yinv<R>, grid, dim3(256), lds, st, a, h->G, plan, TW, nrows, row0);
+  SW_LAUNCH(h, SWENSE_K_YINV, k_yinv<R>, grid, dim3(256), lds, st, a, h->G, plan, TW, nrows, row0);
   SW_HIP(hipGetLastError());
 }
 
@@ -322,7 +322,7 @@ void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t s
   const int TW = choose_tw(plan.n, sizeof(cpx<R>));
   const size_t lds = 2ull * TW * plan.n * sizeof(cpx<R>);
   dim3 grid((h->G.nxh + TW - 1) / TW, a.njobs);
-  hipLaunchKernelGGL(k_yfwd<R>, grid, dim3(256), lds, st, a, h->G, plan, TW);
+  SW_LAUNCH(h, SWENSE_K_YFWD, k_yfwd<R>, grid, dim3(256), lds, st, a, h->G, plan, TW);
   SW_HIP(hipGetLastError());
 }
 
@@ -332,7 +332,7 @@ void xpass_t(swense_hos* h, const XArgs& a) {
   const size_t lds = 2ull * Px * sizeof(cpx<R>) + (size_t)a.nslots * Px * sizeof(R);
   SW_REQUIRE(lds <= 160 * 1024, "x pass needs more LDS than a workgroup has (reduce nx or order)");
   set_lds_limit<R>(reinterpret_cast<const void*>(&k_xpass<R>), lds);
-  hipLaunchKernelGGL(k_xpass<R>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, h->plan_px);
+  SW_LAUNCH(h, SWENSE_K_XPASS, k_xpass<R>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, h->plan_px);
   SW_HIP(hipGetLastError());
 }
 
@@ -404,7 +404,7 @@ void rhs_t(swense_hos* h, const cd* se, const cd* sp, const RkArgs& rk, bool wan
   for (int j = 1; j <= M; ++j) add_job(ya, sp, h->gbuf[1][j], SYM_DZ, j);
   yinv_t<R>(h, ya, h->plan_py, h->Py, 0, h->st);
   if (want_modes) {
-    hipLaunchKernelGGL(k_copy_cd, dim3((h->nc + 255) / 256), dim3(256), 0, h->st, sp, h->amod, h->nc);
+    SW_LAUNCH(h, SWENSE_K_AUX, k_copy_cd, dim3((h->nc + 255) / 256), dim3(256), 0, h->st, sp, h->amod, h->nc);
     SW_HIP(hipGetLastError());
   }
   series_t<R>(h, h->phim, want_modes ? h->amod : nullptr, 1);
@@ -537,7 +537,7 @@ void set_state_phys(swense_hos* h, const double* eta, const double* phis) {
   cd* rows_e = reinterpret_cast<cd*>(h->phys + 2 * np);
   cd* rows_p = rows_e + (size_t)ny * h->G.nxh;
   const size_t lds = 2ull * nx * sizeof(cd);
-  hipLaunchKernelGGL(k_phys_in, dim3(ny), dim3(256), lds, h->st, h->phys, h->phys + np, rows_e, rows_p, h->G,
+  SW_LAUNCH(h, SWENSE_K_AUX, k_phys_in, dim3(ny), dim3(256), lds, h->st, h->phys, h->phys + np, rows_e, rows_p, h->G,
                      h->plan_nx);
   SW_HIP(hipGetLastError());
   YFwdArgs fa;
@@ -559,7 +559,7 @@ void get_state_phys(swense_hos* h, double* eta, double* phis) {
   add_job(ya, h->xn[1], rows_p, SYM_ONE);
   yinv_t<double>(h, ya, h->plan_ny, ny, 0, h->st);
   const size_t lds = 2ull * nx * sizeof(cd);
-  hipLaunchKernelGGL(k_phys_out, dim3(ny), dim3(256), lds, h->st, rows_e, rows_p, h->phys, h->phys + np, h->G,
+  SW_LAUNCH(h, SWENSE_K_AUX, k_phys_out, dim3(ny), dim3(256), lds, h->st, rows_e, rows_p, h->phys, h->phys + np, h->G,
                      h->plan_nx);
   SW_HIP(hipGetLastError());
   if (eta) SW_HIP(hipMemcpyAsync(eta, h->phys, np * sizeof(double), hipMemcpyDeviceToHost, h->st));
@@ -751,7 +751,7 @@ int swense_hos_get_state(swense_hos* h, double* eta, double* phis, double* t, in
     int* bad = nullptr;
     SW_HIP(hipMalloc(&bad, sizeof(int)));
     SW_HIP(hipMemsetAsync(bad, 0, sizeof(int), h->st));
-    hipLaunchKernelGGL(k_finite, dim3((h->nc + 255) / 256), dim3(256), 0, h->st, h->xn[0], h->xn[1], h->nc, bad);
+    SW_LAUNCH(h, SWENSE_K_AUX, k_finite, dim3((h->nc + 255) / 256), dim3(256), 0, h->st, h->xn[0], h->xn[1], h->nc, bad);
     int hb = 0;
     SW_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->st));
     SW_HIP(hipStreamSynchronize(h->st));
@@ -818,8 +818,43 @@ int swense_hos_energy(swense_hos* h, double* energy) {
   });
 }
 
+int swense_profile_enable(swense_hos* h, int enable) {
+  if (!h) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    SW_HIP(hipStreamSynchronize(h->st));
+    h->prof.recs.clear();
+    h->prof.used = 0;
+    for (int k = 0; k < SWENSE_K_COUNT; ++k) {
+      h->prof.total_ms[k] = 0.0;
+      h->prof.count[k] = 0;
+    }
+    h->prof.on = enable != 0;
+    return SWENSE_OK;
+  });
+}
+
+int swense_profile_read(swense_hos* h, int kernel, double* total_ms, long long* count) {
+  if (!h || kernel < 0 || kernel >= SWENSE_K_COUNT) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    SW_HIP(hipStreamSynchronize(h->st));
+    // fold the pending records into the totals and recycle their events
+    for (const ProfRec& r : h->prof.recs) {
+      float ms = 0.f;
+      SW_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      h->prof.total_ms[r.kid] += ms;
+      h->prof.count[r.kid] += 1;
+    }
+    h->prof.recs.clear();
+    h->prof.used = 0;
+    if (total_ms) *total_ms = h->prof.total_ms[kernel];
+    if (count) *count = h->prof.count[kernel];
+    return SWENSE_OK;
+  });
+}
+
 void swense_hos_destroy(swense_hos* h) {
   if (!h) return;
+  h->prof.release();
   eval_release(h);
   if (h->pool) (void)hipFree(h->pool);
   h->tw.release();

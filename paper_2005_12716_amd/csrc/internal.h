@@ -90,6 +90,34 @@ struct YFwdArgs {
 
 struct EvalWork;  // reconstruction workspace (evalgrid.hip)
 
+// Per-kernel event timing (enabled on demand).
+struct ProfRec {
+  int kid;
+  hipEvent_t a, b;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<ProfRec> recs;
+  double total_ms[SWENSE_K_COUNT] = {};
+  long long count[SWENSE_K_COUNT] = {};
+  hipEvent_t take() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      SW_HIP(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void release() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+    recs.clear();
+    used = 0;
+  }
+};
+
 struct swense_hos {
   swense_hos_desc d{};
   Geom G{};
@@ -131,9 +159,35 @@ struct swense_hos {
   // physical staging for state in/out, FP64 [ny][nx] x 2
   double* phys = nullptr;
   EvalWork* ev = nullptr;
+  Profiler prof;
 
   size_t isz() const { return fp64 ? sizeof(cd) : sizeof(cf); }
 };
+
+// Brackets one launch with events when the handle's profiler is on.
+struct ProfScope {
+  swense_hos* h;
+  int kid;
+  hipEvent_t b = nullptr;
+  ProfScope(swense_hos* hh, int k) : h(hh), kid(k) {
+    if (h->prof.on) {
+      hipEvent_t a = h->prof.take();
+      b = h->prof.take();
+      SW_HIP(hipEventRecord(a, h->st));
+      h->prof.recs.push_back(ProfRec{kid, a, b});
+    }
+  }
+  ~ProfScope() {
+    if (b) (void)hipEventRecord(b, h->st);
+  }
+};
+
+#define SW_LAUNCH(h, kid, ...)          \
+  do {                                  \
+    ProfScope ps_((h), (kid));          \
+    hipLaunchKernelGGL(__VA_ARGS__);    \
+    SW_HIP(hipGetLastError());          \
+  } while (0)
 
 // ---- launch helpers implemented in hos.hip (templated on precision there)
 void launch_yinv(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, int row0, hipStream_t st);

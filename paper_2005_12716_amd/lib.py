@@ -21,6 +21,7 @@ PHI, U, V, W, P, PHI_T, U_T, V_T, W_T, ETA, ETA_T = (1 << i for i in range(11))
 ALL_FIELDS = (1 << 11) - 1
 FIELD_BITS = [PHI, U, V, W, P, PHI_T, U_T, V_T, W_T, ETA, ETA_T]
 PHYSICAL, SPECTRAL = 0, 1
+KERNELS = ["yinv", "xpass", "yfwd", "yinv_eval", "xeval", "xeval_surf", "interp", "interp_div", "bind", "aux"]
 
 
 class HosDesc(C.Structure):
@@ -73,6 +74,8 @@ def load():
         "swense_cells_bind": (C.c_int, [vp, C.POINTER(GridDesc), C.c_longlong, vp, C.POINTER(vp)]),
         "swense_interp_cells": (C.c_int, [vp, vp, C.c_uint, fp, C.POINTER(C.c_longlong)]),
         "swense_interp_divergence": (C.c_int, [vp, vp, fp]),
+        "swense_profile_enable": (C.c_int, [vp, C.c_int]),
+        "swense_profile_read": (C.c_int, [vp, C.c_int, dp, C.POINTER(C.c_longlong)]),
         "swense_hos_destroy": (None, [vp]),
         "swense_cells_destroy": (None, [vp]),
     }
@@ -87,7 +90,8 @@ def load():
 EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swense_hos_init",
             "swense_hos_set_state", "swense_hos_step", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
-            "swense_cells_bind", "swense_interp_cells", "swense_interp_divergence", "swense_hos_destroy",
+            "swense_cells_bind", "swense_interp_cells", "swense_interp_divergence", "swense_profile_enable",
+            "swense_profile_read", "swense_hos_destroy",
             "swense_cells_destroy"]
 
 
@@ -186,6 +190,19 @@ class Hos:
         e = C.c_double()
         self._check(self.L.swense_hos_energy(self.h, C.byref(e)), "energy")
         return e.value
+
+    def profile(self, enable=True):
+        self._check(self.L.swense_profile_enable(self.h, 1 if enable else 0), "profile_enable")
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches)} since profiling was enabled."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms = C.c_double()
+            cnt = C.c_longlong()
+            self._check(self.L.swense_profile_read(self.h, k, C.byref(ms), C.byref(cnt)), "profile_read")
+            out[name] = (ms.value, cnt.value)
+        return out
 
     def grid_size(self, gd, mask):
         return int(self.L.swense_eval_grid_size(self.h, C.byref(gd), mask))
