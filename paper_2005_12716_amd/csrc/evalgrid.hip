@@ -166,229 +166,58 @@ __global__ void __launch_bounds__(256) k_xeval_surf(EvArgs A, Geom G, FftPlan pl
   }
 }
 
+// x pass for interpolation coefficient grids, node-major layout: every
+// node's (layer, field) values are contiguous, coef[(r wx + xw) K + l Fv + f],
+// surface fields at l = L (offset L Fv + s).  Block (window row r, layer
+// group g); the last group index holds the surface fields.
+template <typename R>
+__global__ void __launch_bounds__(256) k_xcoef(EvArgs A, Geom G, FftPlan plan, int LG, int K, float* coef) {
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  const int gx = plan.n, r = blockIdx.x, g = blockIdx.y, hx = G.nx / 2;
+  C* za = reinterpret_cast<C*>(smem);
+  C* zb = za + gx;
+  float* stage = reinterpret_cast<float*>(zb + gx);
+  const int Fv = A.nvol;
+  const int ngroups = Fv > 0 ? (A.nl + LG - 1) / LG : 0;
+  const bool surf = g == ngroups;
+  int nitems, base_off, l0 = 0;
+  if (surf) {
+    nitems = A.nsurf;
+    base_off = A.nl * Fv;
+  } else {
+    l0 = g * LG;
+    nitems = min(LG, A.nl - l0) * Fv;
+    base_off = l0 * Fv;
+  }
+  const C* inter = reinterpret_cast<const C*>(A.inter);
+  auto row = [&](int j) -> const C* {
+    const int job = surf ? A.nvol * A.nl + j : (j % Fv) * A.nl + l0 + j / Fv;
+    return inter + ((size_t)job * A.wy + r) * G.nxh;
+  };
+  for (int i = 0; i < nitems; i += 2) {
+    const bool hasb = i + 1 < nitems;
+    const C* ra = row(i);
+    const C* rb = hasb ? row(i + 1) : nullptr;
+    for (int s = threadIdx.x; s < gx; s += blockDim.x) za[s] = gather_x<R>(ra, rb, s, gx, hx);
+    __syncthreads();
+    C* res = block_fft<R>(za, zb, plan, 1, +1);
+    for (int xw = threadIdx.x; xw < A.wx; xw += blockDim.x) {
+      const int x = (A.ix0 + xw) % gx;
+      stage[xw * nitems + i] = (float)res[x].x;
+      if (hasb) stage[xw * nitems + i + 1] = (float)res[x].y;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < A.wx * nitems; e += blockDim.x) {
+    const int xw = e / nitems, j = e - xw * nitems;
+    coef[((size_t)r * A.wx + xw) * K + base_off + j] = stage[e];
+  }
+}
+
 __global__ void k_fill(float* p, size_t n, float v) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
-}
-
-// ---------------------------------------------------------------- binding
-struct CellsDev {
-  int* ix;    // first stencil node, window-local (x)
-  int* iy;    // (y)
-  float* tx;  // fractional position in [0,1)
-  float* ty;
-  int* l0;    // first stencil layer, -1: out of range
-  float* wz;  // [4][n] Lagrange weights
-  float* dwz; // [4][n] their z-derivatives
-  float* pz;  // rho g z
-};
-
-__global__ void k_bind(const double* xyz, long long n, CellsDev c, const double* zl, int nl, double dx, double dy,
-                       int gx, int gy, int ix0, int iy0, int wx, int wy, int three, double rho_g,
-                       unsigned long long* nbad) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
-  bool ok = isfinite(x) && isfinite(y) && isfinite(z);
-  const double sx = x / dx;
-  const double fx = floor(sx);
-  long long st = (long long)fx - 1 - ix0;
-  if (wx == gx) st = ((st % gx) + gx) % gx;
-  else ok = ok && st >= 0 && st + 3 < wx;
-  long long sty = 0;
-  double ty = 0.0;
-  if (three) {
-    const double sy = y / dy;
-    const double fy = floor(sy);
-    sty = (long long)fy - 1 - iy0;
-    if (wy == gy) sty = ((sty % gy) + gy) % gy;
-    else ok = ok && sty >= 0 && sty + 3 < wy;
-    ty = sy - fy;
-  }
-  ok = ok && z >= zl[0] && z <= zl[nl - 1];
-  int l0 = -1;
-  double w[4] = {0, 0, 0, 0}, dw[4] = {0, 0, 0, 0};
-  if (ok) {
-    int lo = 0, hi = nl - 1;  // last layer index with zl <= z, clamped to nl-2
-    while (hi - lo > 1) {
-      int mid = (lo + hi) >> 1;
-      if (zl[mid] <= z) lo = mid;
-      else hi = mid;
-    }
-    int l = lo;
-    l0 = l - 1;
-    if (l0 < 0) l0 = 0;
-    if (l0 > nl - 4) l0 = nl - 4;
-    double zn[4];
-    for (int a = 0; a < 4; ++a) zn[a] = zl[l0 + a];
-    for (int a = 0; a < 4; ++a) {
-      double wa = 1.0, dwa = 0.0;
-      for (int b = 0; b < 4; ++b) {
-        if (b == a) continue;
-        wa *= (z - zn[b]) / (zn[a] - zn[b]);
-      }
-      for (int cc = 0; cc < 4; ++cc) {
-        if (cc == a) continue;
-        double term = 1.0 / (zn[a] - zn[cc]);
-        for (int b = 0; b < 4; ++b) {
-          if (b == a || b == cc) continue;
-          term *= (z - zn[b]) / (zn[a] - zn[b]);
-        }
-        dwa += term;
-      }
-      w[a] = wa;
-      dw[a] = dwa;
-    }
-  } else {
-    atomicAdd(nbad, 1ull);
-  }
-  c.ix[i] = (int)st;
-  c.iy[i] = (int)sty;
-  c.tx[i] = (float)(sx - fx);
-  c.ty[i] = (float)ty;
-  c.l0[i] = l0;
-  for (int a = 0; a < 4; ++a) {
-    c.wz[(size_t)a * n + i] = (float)w[a];
-    c.dwz[(size_t)a * n + i] = (float)dw[a];
-  }
-  c.pz[i] = (float)(rho_g * z);
-}
-
-__device__ __forceinline__ void bsw(float t, float* w) {
-  const float t2 = t * t, t3 = t2 * t, u = 1.0f - t;
-  w[0] = u * u * u * (1.0f / 6.0f);
-  w[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
-  w[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * (1.0f / 6.0f);
-  w[3] = t3 * (1.0f / 6.0f);
-}
-__device__ __forceinline__ void dbsw(float t, float* w) {
-  const float t2 = t * t, u = 1.0f - t;
-  w[0] = -0.5f * u * u;
-  w[1] = 1.5f * t2 - 2.0f * t;
-  w[2] = -1.5f * t2 + t + 0.5f;
-  w[3] = 0.5f * t2;
-}
-
-struct InterpArgs {
-  const float* coef;  // volume coefficient grids [nvc][nl][wy][wx], then surface [nsc][wy][wx]
-  int nvc, nsc, nl, wx, wy, gx, gy, three;
-  int vol_src[kNumFields];  // output slot -> coefficient field (volume), -1 none
-  int srf_src[kNumFields];  // output slot -> coefficient field (surface), -1 none
-  int p_slot;
-  int c_phit, c_u, c_v, c_w;  // coefficient fields used by the pressure (-1 none)
-  int nout;
-  float rho;
-  float* out;
-  long long n;
-};
-
-__device__ __forceinline__ int wrapi(int i, int w, int g) {
-  if (w == g) {
-    if (i >= g) i -= g;
-  }
-  return i;
-}
-
-__global__ void __launch_bounds__(256) k_interp(InterpArgs A, CellsDev c) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.n) return;
-  const int l0 = c.l0[i];
-  const size_t n = (size_t)A.n;
-  if (l0 < 0) {
-    for (int o = 0; o < A.nout; ++o) A.out[(size_t)o * n + i] = __builtin_nanf("");
-    return;
-  }
-  float wx[4], wy[4] = {1.f, 0.f, 0.f, 0.f}, wz[4];
-  bsw(c.tx[i], wx);
-  if (A.three) bsw(c.ty[i], wy);
-  for (int a = 0; a < 4; ++a) wz[a] = c.wz[(size_t)a * n + i];
-  int xs[4], ys[4];
-  const int ix = c.ix[i], iy = c.iy[i];
-  for (int a = 0; a < 4; ++a) {
-    xs[a] = wrapi(ix + a, A.wx, A.gx);
-    ys[a] = A.three ? wrapi(iy + a, A.wy, A.gy) : 0;
-  }
-  const int nyt = A.three ? 4 : 1;
-  const size_t plane = (size_t)A.wy * A.wx;
-  auto vol = [&](int f) {
-    const float* base = A.coef + (size_t)f * A.nl * plane;
-    float acc = 0.f;
-    for (int cc = 0; cc < 4; ++cc) {
-      const float* lay = base + (size_t)(l0 + cc) * plane;
-      float h = 0.f;
-      for (int b = 0; b < nyt; ++b) {
-        const float* row = lay + (size_t)ys[b] * A.wx;
-        h += wy[b] * (wx[0] * row[xs[0]] + wx[1] * row[xs[1]] + wx[2] * row[xs[2]] + wx[3] * row[xs[3]]);
-      }
-      acc += wz[cc] * h;
-    }
-    return acc;
-  };
-  auto srf = [&](int f) {
-    const float* base = A.coef + (size_t)A.nvc * A.nl * plane + (size_t)f * plane;
-    float h = 0.f;
-    for (int b = 0; b < nyt; ++b) {
-      const float* row = base + (size_t)ys[b] * A.wx;
-      h += wy[b] * (wx[0] * row[xs[0]] + wx[1] * row[xs[1]] + wx[2] * row[xs[2]] + wx[3] * row[xs[3]]);
-    }
-    return h;
-  };
-  for (int o = 0; o < A.nout; ++o) {
-    float v = 0.f;
-    if (o == A.p_slot) {
-      const float pt = vol(A.c_phit), u = vol(A.c_u), w = vol(A.c_w);
-      const float vv = A.c_v >= 0 ? vol(A.c_v) : 0.f;
-      v = -A.rho * (pt + 0.5f * (u * u + vv * vv + w * w)) - c.pz[i];
-    } else if (A.vol_src[o] >= 0) {
-      v = vol(A.vol_src[o]);
-    } else if (A.srf_src[o] >= 0) {
-      v = srf(A.srf_src[o]);
-    }
-    A.out[(size_t)o * n + i] = v;
-  }
-}
-
-__global__ void __launch_bounds__(256) k_interp_div(InterpArgs A, CellsDev c, double dx, double dy, float* div) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.n) return;
-  const int l0 = c.l0[i];
-  const size_t n = (size_t)A.n;
-  if (l0 < 0) {
-    div[i] = __builtin_nanf("");
-    return;
-  }
-  float wx[4], dwx[4], wy[4] = {1.f, 0.f, 0.f, 0.f}, dwy[4] = {0.f, 0.f, 0.f, 0.f}, wz[4], dwz[4];
-  bsw(c.tx[i], wx);
-  dbsw(c.tx[i], dwx);
-  if (A.three) {
-    bsw(c.ty[i], wy);
-    dbsw(c.ty[i], dwy);
-  }
-  for (int a = 0; a < 4; ++a) {
-    wz[a] = c.wz[(size_t)a * n + i];
-    dwz[a] = c.dwz[(size_t)a * n + i];
-    dwx[a] *= (float)(1.0 / dx);
-    dwy[a] *= (float)(1.0 / dy);
-  }
-  int xs[4], ys[4];
-  for (int a = 0; a < 4; ++a) {
-    xs[a] = wrapi(c.ix[i] + a, A.wx, A.gx);
-    ys[a] = A.three ? wrapi(c.iy[i] + a, A.wy, A.gy) : 0;
-  }
-  const int nyt = A.three ? 4 : 1;
-  const size_t plane = (size_t)A.wy * A.wx;
-  float d = 0.f;
-  for (int cc = 0; cc < 4; ++cc) {
-    for (int b = 0; b < nyt; ++b) {
-      for (int a = 0; a < 4; ++a) {
-        const size_t off = (size_t)(l0 + cc) * plane + (size_t)ys[b] * A.wx + xs[a];
-        d += wz[cc] * wy[b] * dwx[a] * A.coef[(size_t)A.c_u * A.nl * plane + off];
-        if (A.c_v >= 0) d += wz[cc] * dwy[b] * wx[a] * A.coef[(size_t)A.c_v * A.nl * plane + off];
-        d += dwz[cc] * wy[b] * wx[a] * A.coef[(size_t)A.c_w * A.nl * plane + off];
-      }
-    }
-  }
-  div[i] = d;
 }
 
 }  // namespace
@@ -399,19 +228,6 @@ struct EvalWork {
   size_t inter_bytes = 0;
   double* zdev = nullptr;
   size_t zcap = 0;
-};
-
-struct swense_cells {
-  swense_hos* h = nullptr;
-  swense_grid_desc gd{};
-  std::vector<double> z;
-  long long n = 0;
-  unsigned long long nbad = 0;
-  void* mem = nullptr;
-  CellsDev dev{};
-  double* zdev = nullptr;
-  float* coef = nullptr;
-  size_t coef_bytes = 0;
 };
 
 namespace {
@@ -521,7 +337,7 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
   A.nvol_out = nvo;
   const size_t plane = (size_t)A.wy * A.wx;
   // zero-fill outputs that no transform writes (v, v_t in 2D)
-  if (h->G.ny == 1) {
+  if (h->G.ny == 1 && !pre) {
     for (int f : {F_V, F_VT}) {
       if (!(mask & (1u << f))) continue;
       int slot = 0;
@@ -551,6 +367,21 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     SW_REQUIRE(njobs <= 65535, "too many (field, layer) pairs");
     SW_LAUNCH(h, SWENSE_K_YINV_EVAL, k_yinv_eval<R>, grid, dim3(256), lds, h->st, A, h->G, py, TW);
     SW_HIP(hipGetLastError());
+  }
+  if (pre) {
+    const int Fv = A.nvol;
+    const int LG = Fv > 0 ? std::max(1, 32 / Fv) : 1;
+    const int ngroups = Fv > 0 ? (A.nl + LG - 1) / LG : 0;
+    const int K = A.nl * Fv + A.nsurf;
+    const int maxitems = std::max(LG * Fv, A.nsurf);
+    const size_t lds = 2ull * px.n * csz + (size_t)A.wx * maxitems * sizeof(float);
+    SW_REQUIRE(lds <= 160 * 1024, "grid row too long for one workgroup");
+    if (lds > 65536)
+      SW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xcoef<R>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    SW_LAUNCH(h, SWENSE_K_XEVAL, k_xcoef<R>, dim3(A.wy, ngroups + (A.nsurf > 0 ? 1 : 0)), dim3(256), lds, h->st, A,
+              h->G, px, LG, K, out);
+    return;
   }
   if (A.nvol > 0) {
     const size_t lds = 2ull * px.n * csz + 4ull * A.wx * sizeof(R);
@@ -582,70 +413,38 @@ size_t grid_floats(const swense_hos* h, const swense_grid_desc* gd, unsigned mas
   for (int f = 0; f < kNumFields; ++f) {
     if (!(mask & (1u << f))) continue;
     if (f == F_ETA || f == F_ETAT) ++ns;
-    else if (!(pre && f == F_P)) ++nv;
+    else if (pre && (f == F_P || (h->G.ny == 1 && (f == F_V || f == F_VT)))) continue;
+    else ++nv;
   }
   const size_t plane = (size_t)gd->wx * gd->wy;
   return nv * gd->nl * plane + ns * plane;
 }
 
-// coefficient fields an interpolation of `mask` needs (volume fields incl.
-// the inputs of the pressure; surface fields)
-unsigned coef_mask(unsigned mask, bool three) {
-  unsigned m = mask & ~(unsigned)SWENSE_P;
-  if (mask & SWENSE_P) m |= SWENSE_PHI_T | SWENSE_U | SWENSE_W | (three ? SWENSE_V : 0u);
-  return m;
-}
-
-void interp_args(swense_hos* h, swense_cells* c, unsigned mask, float* out, InterpArgs& A) {
-  std::memset(&A, 0, sizeof(A));
-  const bool three = h->G.ny > 1;
-  const unsigned cm = coef_mask(mask, three);
-  // coefficient field index of each bit in the coefficient grid layout
-  int cidx[kNumFields];
-  int nv = 0, ns = 0;
-  for (int f = 0; f < kNumFields; ++f) {
-    cidx[f] = -1;
-    if (!(cm & (1u << f))) continue;
-    if (f == F_ETA || f == F_ETAT) cidx[f] = ns++;
-    else cidx[f] = nv++;
-  }
-  A.coef = c->coef;
-  A.nvc = nv;
-  A.nsc = ns;
-  A.nl = c->gd.nl;
-  A.wx = c->gd.wx;
-  A.wy = c->gd.wy;
-  A.gx = c->gd.gx;
-  A.gy = three ? c->gd.gy : 1;
-  A.three = three ? 1 : 0;
-  A.p_slot = -1;
-  A.c_phit = cidx[F_PHIT];
-  A.c_u = cidx[F_U];
-  A.c_v = three ? cidx[F_V] : -1;
-  A.c_w = cidx[F_W];
-  int o = 0;
-  for (int f = 0; f < kNumFields; ++f) {
-    if (!(mask & (1u << f))) continue;
-    A.vol_src[o] = -1;
-    A.srf_src[o] = -1;
-    if (f == F_P) A.p_slot = o;
-    else if (f == F_ETA || f == F_ETAT) A.srf_src[o] = cidx[f];
-    else A.vol_src[o] = cidx[f];
-    ++o;
-  }
-  A.nout = o;
-  A.rho = (float)h->G.rho;
-  A.out = out;
-  A.n = c->n;
-}
-
-void refresh_coef(swense_hos* h, swense_cells* c, unsigned cm) {
-  const size_t nfl = grid_floats(h, &c->gd, cm, true);
-  ensure(reinterpret_cast<void**>(&c->coef), &c->coef_bytes, std::max<size_t>(nfl, 1) * sizeof(float));
-  eval_dispatch(h, &c->gd, c->zdev, cm, true, c->coef);
-}
-
 }  // namespace
+
+void check_grid_desc(const swense_hos* h, const swense_grid_desc* gd) { check_grid(h, gd); }
+void ensure_device(void** p, size_t* cap, size_t bytes) { ensure(p, cap, bytes); }
+
+CoefLayout coef_layout(swense_hos* h, unsigned cm, int nl) {
+  EvArgs A;
+  int idx[kNumFields];
+  for (int f = 0; f < kNumFields; ++f) idx[f] = -1;
+  int nvo = 0, nso = 0;
+  plan_fields(h, cm, true, A, idx, &nvo, &nso);
+  CoefLayout L{};
+  L.fv = A.nvol;
+  L.fs = A.nsurf;
+  L.nl = nl;
+  L.k = nl * A.nvol + A.nsurf;
+  for (int f = 0; f < kNumFields; ++f) L.idx[f] = (cm & (1u << f)) ? idx[f] : -1;
+  return L;
+}
+
+void eval_coef(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned cm, float* coef) {
+  eval_dispatch(h, gd, zdev, cm, true, coef);
+}
+
+size_t coef_floats(swense_hos* h, const swense_grid_desc* gd, unsigned cm) { return grid_floats(h, gd, cm, true); }
 
 void eval_release(swense_hos* h) {
   if (!h->ev) return;
@@ -676,116 +475,6 @@ int swense_eval_grid(swense_hos* h, const swense_grid_desc* gd, unsigned mask, f
     eval_dispatch(h, gd, w->zdev, mask, false, out);
     return SWENSE_OK;
   });
-}
-
-int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, const double* xyz,
-                      swense_cells** out) {
-  if (!h || !out) return SWENSE_EINVAL;
-  *out = nullptr;
-  swense_cells* c = nullptr;
-  int rc = guarded(h, [&] {
-    check_grid(h, gd);
-    SW_REQUIRE(n >= 0, "negative point count");
-    SW_REQUIRE(n == 0 || xyz != nullptr, "null coordinates");
-    SW_REQUIRE(gd->nl >= 4, "interpolation needs at least 4 layers");
-    c = new swense_cells();
-    c->h = h;
-    c->gd = *gd;
-    c->z.assign(gd->z, gd->z + gd->nl);
-    c->gd.z = c->z.data();
-    c->n = n;
-    const size_t nn = (size_t)std::max<long long>(n, 1);
-    // carve: counter, layer heights, then the per-point arrays (each 256-B aligned)
-    const size_t sizes[] = {sizeof(unsigned long long), gd->nl * sizeof(double), nn * 4, nn * 4, nn * 4, nn * 4,
-                            nn * 4, nn * 16, nn * 16, nn * 4};
-    size_t bytes = 0;
-    for (size_t b : sizes) bytes += (b + 255) & ~size_t(255);
-    SW_HIP(hipMalloc(&c->mem, bytes));
-    char* p = reinterpret_cast<char*>(c->mem);
-    int k = 0;
-    auto take = [&](size_t b) {
-      SW_REQUIRE(b == sizes[k], "internal carve mismatch");
-      ++k;
-      void* r = p;
-      p += (b + 255) & ~size_t(255);
-      return r;
-    };
-    unsigned long long* dbad = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long)));
-    c->zdev = reinterpret_cast<double*>(take(gd->nl * sizeof(double)));
-    c->dev.ix = reinterpret_cast<int*>(take(nn * 4));
-    c->dev.iy = reinterpret_cast<int*>(take(nn * 4));
-    c->dev.tx = reinterpret_cast<float*>(take(nn * 4));
-    c->dev.ty = reinterpret_cast<float*>(take(nn * 4));
-    c->dev.l0 = reinterpret_cast<int*>(take(nn * 4));
-    c->dev.wz = reinterpret_cast<float*>(take(nn * 16));
-    c->dev.dwz = reinterpret_cast<float*>(take(nn * 16));
-    c->dev.pz = reinterpret_cast<float*>(take(nn * 4));
-    SW_REQUIRE(k == (int)(sizeof(sizes) / sizeof(sizes[0])) && p <= reinterpret_cast<char*>(c->mem) + bytes,
-               "internal carve overflow");
-    SW_HIP(hipMemcpyAsync(c->zdev, gd->z, gd->nl * sizeof(double), hipMemcpyHostToDevice, h->st));
-    SW_HIP(hipMemsetAsync(dbad, 0, sizeof(unsigned long long), h->st));
-    if (n > 0) {
-      const double dx = h->G.lx / gd->gx;
-      const double dy = h->G.ny > 1 ? h->G.ly / gd->gy : 1.0;
-      SW_LAUNCH(h, SWENSE_K_BIND, k_bind, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->st, xyz, n, c->dev, c->zdev,
-                         gd->nl, dx, dy, gd->gx, h->G.ny > 1 ? gd->gy : 1, gd->ix0, gd->iy0, gd->wx, gd->wy,
-                         h->G.ny > 1 ? 1 : 0, h->G.rho * h->G.g, dbad);
-      SW_HIP(hipGetLastError());
-    }
-    SW_HIP(hipMemcpyAsync(&c->nbad, dbad, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->st));
-    SW_HIP(hipStreamSynchronize(h->st));
-    *out = c;
-    return SWENSE_OK;
-  });
-  if (rc != SWENSE_OK && c) swense_cells_destroy(c);
-  return rc;
-}
-
-int swense_interp_cells(swense_hos* h, swense_cells* c, unsigned mask, float* out, long long* n_out_of_range) {
-  if (!h || !c || c->h != h) return SWENSE_EINVAL;
-  return guarded(h, [&] {
-    SW_REQUIRE(out != nullptr || c->n == 0, "null output");
-    SW_REQUIRE((mask & ~(unsigned)SWENSE_ALL_FIELDS) == 0 && mask != 0, "bad field mask");
-    if (c->n > 0) {
-      const unsigned cm = coef_mask(mask, h->G.ny > 1);
-      refresh_coef(h, c, cm);
-      InterpArgs A;
-      interp_args(h, c, mask, out, A);
-      SW_LAUNCH(h, SWENSE_K_INTERP, k_interp, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, h->st, A, c->dev);
-      SW_HIP(hipGetLastError());
-    }
-    if (n_out_of_range) {
-      *n_out_of_range = (long long)c->nbad;
-      if (c->nbad) return (int)SWENSE_ERANGE;
-    }
-    return (int)SWENSE_OK;
-  });
-}
-
-int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div) {
-  if (!h || !c || c->h != h) return SWENSE_EINVAL;
-  return guarded(h, [&] {
-    SW_REQUIRE(div != nullptr || c->n == 0, "null output");
-    if (c->n == 0) return (int)SWENSE_OK;
-    const bool three = h->G.ny > 1;
-    const unsigned m = SWENSE_U | SWENSE_W | (three ? SWENSE_V : 0u);
-    refresh_coef(h, c, m);
-    InterpArgs A;
-    interp_args(h, c, m, nullptr, A);
-    const double dx = h->G.lx / c->gd.gx;
-    const double dy = three ? h->G.ly / c->gd.gy : 1.0;
-    SW_LAUNCH(h, SWENSE_K_INTERP_DIV, k_interp_div, dim3((unsigned)((c->n + 255) / 256)), dim3(256), 0, h->st, A, c->dev, dx, dy,
-                       div);
-    SW_HIP(hipGetLastError());
-    return (int)SWENSE_OK;
-  });
-}
-
-void swense_cells_destroy(swense_cells* c) {
-  if (!c) return;
-  if (c->mem) (void)hipFree(c->mem);
-  if (c->coef) (void)hipFree(c->coef);
-  delete c;
 }
 
 }  // extern "C"

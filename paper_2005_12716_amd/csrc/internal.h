@@ -194,8 +194,20 @@ void launch_yinv(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrow
 void launch_modes(swense_hos* h);  // A, A_t, eta_t at the current state (if stale)
 void set_error(swense_hos* h, const SwenseError& e);
 
-// ---- reconstruction cleanup (evalgrid.hip)
+// ---- reconstruction (evalgrid.hip)
 void eval_release(swense_hos* h);
+void check_grid_desc(const swense_hos* h, const swense_grid_desc* gd);
+void ensure_device(void** p, size_t* cap, size_t bytes);
+// Node-major coefficient grid: per window node K = nl fv + fs floats; idx[bit]
+// = field index (volume: 0..fv-1 at offset l fv + idx; surface: offset nl fv
+// + idx), -1 when the field is absent (also v, v_t in 2D, which are zero).
+struct CoefLayout {
+  int fv, fs, nl, k;
+  int idx[11];
+};
+CoefLayout coef_layout(swense_hos* h, unsigned cm, int nl);
+void eval_coef(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned cm, float* coef);
+size_t coef_floats(swense_hos* h, const swense_grid_desc* gd, unsigned cm);
 
 // run a body and convert exceptions to error codes
 template <typename F>

@@ -1,0 +1,530 @@
+// Interpolation of the incident fields to CFD cell centres (Sec. 3.2.2) and
+// the divergence of the interpolant (Sec. 3.2.3), gfx950.
+//
+// Scheme: periodic cubic spline horizontally (uniform cubic B-spline on a
+// coefficient grid whose modes were divided by the B-spline symbol
+// (4 + 2 cos(k dx))/6 per axis, so that the spline interpolates the node
+// values), 4-point Lagrange vertically on the arbitrary layer heights.
+//
+// Binding (once per static mesh, host FP64): every point gets its horizontal
+// stencil (first node, fractional offset) and its vertical stencil (first
+// layer, 4 weights and their z-derivatives).  Points sharing one exact (x, y)
+// - the columns of structured and extruded CFD meshes - are grouped, and the
+// columns are ordered by stencil node so neighbouring columns share cache
+// lines.
+//
+// Gather (every call): one 64-lane wavefront per column contracts the 16
+// horizontal taps once for every (layer, field) the column's points need -
+// the coefficient grid is node-major, so each tap is one contiguous vector
+// load across the wavefront - keeps the column profile in LDS, then each
+// point takes 4 vertical taps per field.  Pressure is formed at the point
+// from phi_t, u, v, w: p = -rho (phi_t + |u|^2/2) - rho g z.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+struct Col {
+  int start, count;  // range in the sorted point arrays
+  int ix, iy;        // first stencil node, window-local
+  float tx, ty;      // fractional offsets
+  int lmin, nlc;     // first layer and number of layers the column needs (0: all out of range)
+};
+
+struct PtDev {
+  int* perm;   // caller index of sorted point i
+  int* l0;     // first stencil layer (-1: out of range)
+  float* wz;   // [4][n] Lagrange weights
+  float* dwz;  // [4][n] d/dz of the weights
+  float* pz;   // rho g z
+};
+
+constexpr int kColsPerBlock = 4;
+
+struct GatherArgs {
+  const float* coef;
+  int K, fv, fs, nl;
+  int wx, wy, gx, gy, three;
+  int nout;
+  int vol[11];  // output slot -> volume field index (-1: none)
+  int srf[11];  // output slot -> surface field index (-1: none)
+  int zero[11]; // output slot is identically zero (v, v_t in 2D)
+  int p_slot;
+  int c_phit, c_u, c_v, c_w;
+  float rho;
+  float* out;
+  long long n;
+  int kmax;  // LDS floats per column
+};
+
+__device__ __forceinline__ void bsw(float t, float* w) {
+  const float t2 = t * t, t3 = t2 * t, u = 1.0f - t;
+  w[0] = u * u * u * (1.0f / 6.0f);
+  w[1] = (3.0f * t3 - 6.0f * t2 + 4.0f) * (1.0f / 6.0f);
+  w[2] = (-3.0f * t3 + 3.0f * t2 + 3.0f * t + 1.0f) * (1.0f / 6.0f);
+  w[3] = t3 * (1.0f / 6.0f);
+}
+__device__ __forceinline__ void dbsw(float t, float* w) {
+  const float t2 = t * t, u = 1.0f - t;
+  w[0] = -0.5f * u * u;
+  w[1] = 1.5f * t2 - 2.0f * t;
+  w[2] = -1.5f * t2 + t + 0.5f;
+  w[3] = 0.5f * t2;
+}
+__device__ __forceinline__ int wrapn(int i, int w, int g) { return (w == g && i >= g) ? i - g : i; }
+
+// Node offsets (in floats) of the 4 x 4 (or 4 x 1) horizontal stencil.
+__device__ __forceinline__ void stencil(const Col& c, const GatherArgs& A, long long* off) {
+  for (int b = 0; b < 4; ++b)
+    for (int a = 0; a < 4; ++a) {
+      const int yy = A.three ? wrapn(c.iy + b, A.wy, A.gy) : 0;
+      const int xx = wrapn(c.ix + a, A.wx, A.gx);
+      off[b * 4 + a] = ((long long)yy * A.wx + xx) * A.K;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_gather_col(GatherArgs A, const Col* __restrict__ cols, int ncols, PtDev pd) {
+  extern __shared__ float hbuf[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ci = blockIdx.x * kColsPerBlock + wave;
+  float* h = hbuf + wave * A.kmax;
+  Col c{};
+  const bool valid = ci < ncols;
+  if (valid) c = cols[ci];
+  const int nv = c.nlc * A.fv;
+  if (valid && c.nlc > 0) {
+    float wx[4], wy[4] = {1.f, 0.f, 0.f, 0.f};
+    bsw(c.tx, wx);
+    if (A.three) bsw(c.ty, wy);
+    long long off[16];
+    stencil(c, A, off);
+    const int nb = A.three ? 4 : 1;
+    const int j0 = c.lmin * A.fv;
+    for (int j = lane; j < nv + A.fs; j += 64) {
+      const int jj = j < nv ? j0 + j : A.nl * A.fv + (j - nv);
+      float acc = 0.f;
+      for (int b = 0; b < nb; ++b) {
+        float r = 0.f;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) r += wx[a] * A.coef[off[b * 4 + a] + jj];
+        acc += wy[b] * r;
+      }
+      h[j] = acc;
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+  const size_t n = (size_t)A.n;
+  for (int i = lane; i < c.count; i += 64) {
+    const int sp = c.start + i;
+    const int orig = pd.perm[sp];
+    const int l0 = c.nlc > 0 ? pd.l0[sp] : -1;
+    if (l0 < 0) {
+      for (int o = 0; o < A.nout; ++o) A.out[(size_t)o * n + orig] = __builtin_nanf("");
+      continue;
+    }
+    float wz[4];
+    for (int a = 0; a < 4; ++a) wz[a] = pd.wz[(size_t)a * n + sp];
+    const int base = (l0 - c.lmin) * A.fv;
+    auto vol = [&](int f) {
+      return wz[0] * h[base + f] + wz[1] * h[base + A.fv + f] + wz[2] * h[base + 2 * A.fv + f] +
+             wz[3] * h[base + 3 * A.fv + f];
+    };
+    for (int o = 0; o < A.nout; ++o) {
+      float v = 0.f;
+      if (o == A.p_slot) {
+        const float pt = vol(A.c_phit), u = vol(A.c_u), w = vol(A.c_w);
+        const float vv = A.c_v >= 0 ? vol(A.c_v) : 0.f;
+        v = -A.rho * (pt + 0.5f * (u * u + vv * vv + w * w)) - pd.pz[sp];
+      } else if (A.vol[o] >= 0) {
+        v = vol(A.vol[o]);
+      } else if (A.srf[o] >= 0) {
+        v = h[nv + A.srf[o]];
+      }
+      A.out[(size_t)o * n + orig] = v;
+    }
+  }
+}
+
+// du/dx + dv/dy + dw/dz of the interpolant: per column the horizontal
+// derivative contractions of u (x) and v (y) and the plain contraction of w
+// per layer, then the vertical weights (and their derivatives) per point.
+__global__ void __launch_bounds__(256) k_div_col(GatherArgs A, const Col* __restrict__ cols, int ncols, PtDev pd,
+                                                 float inv_dx, float inv_dy, float* div) {
+  extern __shared__ float hbuf[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ci = blockIdx.x * kColsPerBlock + wave;
+  float* h = hbuf + wave * A.kmax;  // [3][nlc]: d/dx u + d/dy v, w
+  Col c{};
+  const bool valid = ci < ncols;
+  if (valid) c = cols[ci];
+  if (valid && c.nlc > 0) {
+    float wx[4], dwx[4], wy[4] = {1.f, 0.f, 0.f, 0.f}, dwy[4] = {0.f, 0.f, 0.f, 0.f};
+    bsw(c.tx, wx);
+    dbsw(c.tx, dwx);
+    if (A.three) {
+      bsw(c.ty, wy);
+      dbsw(c.ty, dwy);
+    }
+    long long off[16];
+    stencil(c, A, off);
+    const int nb = A.three ? 4 : 1;
+    for (int l = lane; l < c.nlc; l += 64) {
+      const int lay = (c.lmin + l) * A.fv;
+      float hdx = 0.f, hw = 0.f;
+      for (int b = 0; b < nb; ++b)
+        for (int a = 0; a < 4; ++a) {
+          const long long o = off[b * 4 + a] + lay;
+          hdx += wy[b] * dwx[a] * inv_dx * A.coef[o + A.c_u];
+          if (A.c_v >= 0) hdx += dwy[b] * wx[a] * inv_dy * A.coef[o + A.c_v];
+          hw += wy[b] * wx[a] * A.coef[o + A.c_w];
+        }
+      h[l] = hdx;
+      h[c.nlc + l] = hw;
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+  const size_t n = (size_t)A.n;
+  for (int i = lane; i < c.count; i += 64) {
+    const int sp = c.start + i;
+    const int orig = pd.perm[sp];
+    const int l0 = c.nlc > 0 ? pd.l0[sp] : -1;
+    if (l0 < 0) {
+      div[orig] = __builtin_nanf("");
+      continue;
+    }
+    const int b = l0 - c.lmin;
+    float d = 0.f;
+    for (int a = 0; a < 4; ++a)
+      d += pd.wz[(size_t)a * n + sp] * h[b + a] + pd.dwz[(size_t)a * n + sp] * h[c.nlc + b + a];
+    div[orig] = d;
+  }
+}
+
+}  // namespace
+
+struct swense_cells {
+  swense_hos* h = nullptr;
+  swense_grid_desc gd{};
+  std::vector<double> z;
+  long long n = 0;
+  unsigned long long nbad = 0;
+  int ncols = 0;
+  int max_nlc = 0;
+  void* mem = nullptr;
+  Col* cols = nullptr;
+  PtDev pd{};
+  double* zdev = nullptr;
+  void* coef = nullptr;
+  size_t coef_bytes = 0;
+};
+
+namespace {
+
+// Host binding in FP64: stencils, column grouping, ordering.
+void bind_host(swense_cells* c, const std::vector<double>& xyz, double lx, double ly, bool three,
+               std::vector<Col>& cols, std::vector<int>& perm, std::vector<int>& l0v, std::vector<float>& wzv,
+               std::vector<float>& dwzv, std::vector<float>& pzv, double rho_g) {
+  const long long n = c->n;
+  const swense_grid_desc& gd = c->gd;
+  const int gx = gd.gx, gy = three ? gd.gy : 1;
+  const double dx = lx / gx, dy = three ? ly / gy : 1.0;
+  const double* X = xyz.data();
+  const double* Y = X + n;
+  const double* Z = Y + n;
+  const int nl = gd.nl;
+  const double* zl = c->z.data();
+  std::vector<int> ixs(n), iys(n);
+  std::vector<float> txs(n), tys(n);
+  std::vector<char> okh(n);
+  l0v.assign(n, -1);
+  wzv.assign(4 * n, 0.f);
+  dwzv.assign(4 * n, 0.f);
+  pzv.assign(n, 0.f);
+  std::vector<int> l0_orig(n, -1);
+  std::vector<float> w_orig(4 * n, 0.f), dw_orig(4 * n, 0.f);
+  for (long long i = 0; i < n; ++i) {
+    const double x = X[i], y = Y[i], z = Z[i];
+    bool ok = std::isfinite(x) && std::isfinite(y) && std::isfinite(z);
+    long long st = 0, sty = 0;
+    double fx = 0, fy = 0, sx = 0, sy = 0;
+    if (ok) {
+      sx = x / dx;
+      fx = std::floor(sx);
+      st = (long long)fx - 1 - gd.ix0;
+      if (gd.wx == gx) st = ((st % gx) + gx) % gx;
+      else ok = st >= 0 && st + 3 < gd.wx;
+      if (three) {
+        sy = y / dy;
+        fy = std::floor(sy);
+        sty = (long long)fy - 1 - gd.iy0;
+        if (gd.wy == gy) sty = ((sty % gy) + gy) % gy;
+        else ok = ok && sty >= 0 && sty + 3 < gd.wy;
+      }
+    }
+    okh[i] = ok;
+    ixs[i] = ok ? (int)st : 0;
+    iys[i] = ok ? (int)sty : 0;
+    txs[i] = ok ? (float)(sx - fx) : 0.f;
+    tys[i] = (ok && three) ? (float)(sy - fy) : 0.f;
+    if (ok && z >= zl[0] && z <= zl[nl - 1]) {
+      int l = int(std::upper_bound(zl, zl + nl, z) - zl) - 1;
+      l = std::min(std::max(l, 0), nl - 2);
+      int b0 = std::min(std::max(l - 1, 0), nl - 4);
+      double zn[4];
+      for (int a = 0; a < 4; ++a) zn[a] = zl[b0 + a];
+      for (int a = 0; a < 4; ++a) {
+        double wa = 1.0, dwa = 0.0;
+        for (int b = 0; b < 4; ++b)
+          if (b != a) wa *= (z - zn[b]) / (zn[a] - zn[b]);
+        for (int cc = 0; cc < 4; ++cc) {
+          if (cc == a) continue;
+          double term = 1.0 / (zn[a] - zn[cc]);
+          for (int b = 0; b < 4; ++b)
+            if (b != a && b != cc) term *= (z - zn[b]) / (zn[a] - zn[b]);
+          dwa += term;
+        }
+        w_orig[4 * i + a] = (float)wa;
+        dw_orig[4 * i + a] = (float)dwa;
+      }
+      l0_orig[i] = b0;
+    }
+  }
+  // order: by stencil node (iy, ix), then exact (x, y), then z; columns are
+  // runs of identical (x, y)
+  perm.resize(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+    if (okh[a] != okh[b]) return okh[a] > okh[b];
+    if (!okh[a]) return false;  // out-of-range points keep their order (coordinates may be NaN)
+    if (iys[a] != iys[b]) return iys[a] < iys[b];
+    if (ixs[a] != ixs[b]) return ixs[a] < ixs[b];
+    if (X[a] != X[b]) return X[a] < X[b];
+    if (Y[a] != Y[b]) return Y[a] < Y[b];
+    return Z[a] < Z[b];
+  });
+  cols.clear();
+  unsigned long long bad = 0;
+  long long i = 0;
+  while (i < n) {
+    const int p0 = perm[i];
+    long long j = i + 1;
+    while (okh[p0] && j < n && okh[perm[j]] && X[perm[j]] == X[p0] && Y[perm[j]] == Y[p0]) ++j;
+    Col col{};
+    col.start = (int)i;
+    col.count = (int)(j - i);
+    col.ix = ixs[p0];
+    col.iy = iys[p0];
+    col.tx = txs[p0];
+    col.ty = tys[p0];
+    int lmin = nl, lmax = -1;
+    for (long long k = i; k < j; ++k) {
+      const int q = perm[k];
+      const int l0 = okh[q] ? l0_orig[q] : -1;
+      l0v[k] = l0;
+      for (int a = 0; a < 4; ++a) {
+        wzv[(size_t)a * n + k] = w_orig[4 * q + a];
+        dwzv[(size_t)a * n + k] = dw_orig[4 * q + a];
+      }
+      pzv[k] = (float)(rho_g * Z[q]);
+      if (l0 < 0) {
+        ++bad;
+        continue;
+      }
+      lmin = std::min(lmin, l0);
+      lmax = std::max(lmax, l0);
+    }
+    if (lmax >= 0) {
+      col.lmin = lmin;
+      col.nlc = lmax - lmin + 4;
+    } else {
+      col.lmin = 0;
+      col.nlc = 0;
+    }
+    cols.push_back(col);
+    i = j;
+  }
+  c->nbad = bad;
+}
+
+void gather_args(swense_hos* h, swense_cells* c, unsigned mask, const CoefLayout& L, float* out, GatherArgs& A) {
+  std::memset(&A, 0, sizeof(A));
+  const bool three = h->G.ny > 1;
+  A.coef = reinterpret_cast<const float*>(c->coef);
+  A.K = L.k;
+  A.fv = L.fv;
+  A.fs = L.fs;
+  A.nl = L.nl;
+  A.wx = c->gd.wx;
+  A.wy = three ? c->gd.wy : 1;
+  A.gx = c->gd.gx;
+  A.gy = three ? c->gd.gy : 1;
+  A.three = three ? 1 : 0;
+  A.p_slot = -1;
+  A.c_phit = L.idx[5];
+  A.c_u = L.idx[1];
+  A.c_v = three ? L.idx[2] : -1;
+  A.c_w = L.idx[3];
+  int o = 0;
+  for (int f = 0; f < 11; ++f) {
+    if (!(mask & (1u << f))) continue;
+    A.vol[o] = -1;
+    A.srf[o] = -1;
+    if (f == 4) A.p_slot = o;
+    else if (f == 9 || f == 10) A.srf[o] = L.idx[f];
+    else A.vol[o] = L.idx[f];
+    ++o;
+  }
+  A.nout = o;
+  A.rho = (float)h->G.rho;
+  A.out = out;
+  A.n = c->n;
+  A.kmax = std::max(c->max_nlc * L.fv + L.fs, 3 * c->max_nlc);
+}
+
+void refresh(swense_hos* h, swense_cells* c, unsigned cm, CoefLayout* L) {
+  *L = coef_layout(h, cm, c->gd.nl);
+  const size_t nfl = std::max<size_t>(coef_floats(h, &c->gd, cm), 1);
+  ensure_device(&c->coef, &c->coef_bytes, nfl * sizeof(float));
+  eval_coef(h, &c->gd, c->zdev, cm, reinterpret_cast<float*>(c->coef));
+}
+
+unsigned coef_mask(unsigned mask, bool three) {
+  unsigned m = mask & ~(unsigned)SWENSE_P;
+  if (mask & SWENSE_P) m |= SWENSE_PHI_T | SWENSE_U | SWENSE_W | (three ? SWENSE_V : 0u);
+  return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, const double* xyz,
+                      swense_cells** out) {
+  if (!h || !out) return SWENSE_EINVAL;
+  *out = nullptr;
+  swense_cells* c = nullptr;
+  int rc = guarded(h, [&] {
+    check_grid_desc(h, gd);
+    SW_REQUIRE(n >= 0 && n < (1ll << 31), "point count must be in [0, 2^31)");
+    SW_REQUIRE(n == 0 || xyz != nullptr, "null coordinates");
+    SW_REQUIRE(gd->nl >= 4, "interpolation needs at least 4 layers");
+    c = new swense_cells();
+    c->h = h;
+    c->gd = *gd;
+    c->z.assign(gd->z, gd->z + gd->nl);
+    c->gd.z = c->z.data();
+    c->n = n;
+    std::vector<double> hx((size_t)3 * n);
+    if (n > 0) {
+      SW_HIP(hipMemcpyAsync(hx.data(), xyz, hx.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+      SW_HIP(hipStreamSynchronize(h->st));
+    }
+    std::vector<Col> cols;
+    std::vector<int> perm, l0v;
+    std::vector<float> wz, dwz, pz;
+    const bool three = h->G.ny > 1;
+    bind_host(c, hx, h->G.lx, h->G.ly, three, cols, perm, l0v, wz, dwz, pz, h->G.rho * h->G.g);
+    c->ncols = (int)cols.size();
+    for (const Col& col : cols) c->max_nlc = std::max(c->max_nlc, col.nlc);
+    const size_t nn = (size_t)std::max<long long>(n, 1);
+    const size_t nc = std::max<size_t>(cols.size(), 1);
+    const size_t sizes[] = {gd->nl * sizeof(double), nc * sizeof(Col), nn * 4, nn * 4, nn * 16, nn * 16, nn * 4};
+    size_t bytes = 0;
+    for (size_t b : sizes) bytes += (b + 255) & ~size_t(255);
+    SW_HIP(hipMalloc(&c->mem, bytes));
+    char* p = reinterpret_cast<char*>(c->mem);
+    auto take = [&](size_t b) {
+      void* r = p;
+      p += (b + 255) & ~size_t(255);
+      return r;
+    };
+    c->zdev = reinterpret_cast<double*>(take(sizes[0]));
+    c->cols = reinterpret_cast<Col*>(take(sizes[1]));
+    c->pd.perm = reinterpret_cast<int*>(take(sizes[2]));
+    c->pd.l0 = reinterpret_cast<int*>(take(sizes[3]));
+    c->pd.wz = reinterpret_cast<float*>(take(sizes[4]));
+    c->pd.dwz = reinterpret_cast<float*>(take(sizes[5]));
+    c->pd.pz = reinterpret_cast<float*>(take(sizes[6]));
+    SW_REQUIRE(p <= reinterpret_cast<char*>(c->mem) + bytes, "internal carve overflow");
+    SW_HIP(hipMemcpy(c->zdev, gd->z, gd->nl * sizeof(double), hipMemcpyHostToDevice));
+    if (n > 0) {
+      SW_HIP(hipMemcpy(c->cols, cols.data(), cols.size() * sizeof(Col), hipMemcpyHostToDevice));
+      SW_HIP(hipMemcpy(c->pd.perm, perm.data(), n * 4, hipMemcpyHostToDevice));
+      SW_HIP(hipMemcpy(c->pd.l0, l0v.data(), n * 4, hipMemcpyHostToDevice));
+      SW_HIP(hipMemcpy(c->pd.wz, wz.data(), n * 16, hipMemcpyHostToDevice));
+      SW_HIP(hipMemcpy(c->pd.dwz, dwz.data(), n * 16, hipMemcpyHostToDevice));
+      SW_HIP(hipMemcpy(c->pd.pz, pz.data(), n * 4, hipMemcpyHostToDevice));
+    }
+    *out = c;
+    return SWENSE_OK;
+  });
+  if (rc != SWENSE_OK && c) swense_cells_destroy(c);
+  return rc;
+}
+
+int swense_interp_cells(swense_hos* h, swense_cells* c, unsigned mask, float* out, long long* n_out_of_range) {
+  if (!h || !c || c->h != h) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    SW_REQUIRE(out != nullptr || c->n == 0, "null output");
+    SW_REQUIRE((mask & ~(unsigned)SWENSE_ALL_FIELDS) == 0 && mask != 0, "bad field mask");
+    if (c->n > 0) {
+      CoefLayout L;
+      refresh(h, c, coef_mask(mask, h->G.ny > 1), &L);
+      GatherArgs A;
+      gather_args(h, c, mask, L, out, A);
+      const size_t lds = (size_t)kColsPerBlock * A.kmax * sizeof(float);
+      SW_REQUIRE(lds <= 160 * 1024, "column profile too long for LDS");
+      if (lds > 65536)
+        SW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather_col),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      const unsigned nblk = (unsigned)((c->ncols + kColsPerBlock - 1) / kColsPerBlock);
+      SW_LAUNCH(h, SWENSE_K_INTERP, k_gather_col, dim3(nblk), dim3(64 * kColsPerBlock), lds, h->st, A, c->cols,
+                c->ncols, c->pd);
+    }
+    if (n_out_of_range) {
+      *n_out_of_range = (long long)c->nbad;
+      if (c->nbad) return (int)SWENSE_ERANGE;
+    }
+    return (int)SWENSE_OK;
+  });
+}
+
+int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div) {
+  if (!h || !c || c->h != h) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    SW_REQUIRE(div != nullptr || c->n == 0, "null output");
+    if (c->n == 0) return (int)SWENSE_OK;
+    const bool three = h->G.ny > 1;
+    const unsigned m = SWENSE_U | SWENSE_W | (three ? SWENSE_V : 0u);
+    CoefLayout L;
+    refresh(h, c, m, &L);
+    GatherArgs A;
+    gather_args(h, c, m, L, nullptr, A);
+    const float inv_dx = (float)(c->gd.gx / h->G.lx);
+    const float inv_dy = three ? (float)(c->gd.gy / h->G.ly) : 0.f;
+    const size_t lds = (size_t)kColsPerBlock * A.kmax * sizeof(float);
+    SW_REQUIRE(lds <= 160 * 1024, "column profile too long for LDS");
+    if (lds > 65536)
+      SW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_div_col),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const unsigned nblk = (unsigned)((c->ncols + kColsPerBlock - 1) / kColsPerBlock);
+    SW_LAUNCH(h, SWENSE_K_INTERP_DIV, k_div_col, dim3(nblk), dim3(64 * kColsPerBlock), lds, h->st, A, c->cols,
+              c->ncols, c->pd, inv_dx, inv_dy, div);
+    return (int)SWENSE_OK;
+  });
+}
+
+void swense_cells_destroy(swense_cells* c) {
+  if (!c) return;
+  if (c->mem) (void)hipFree(c->mem);
+  if (c->coef) (void)hipFree(c->coef);
+  delete c;
+}
+
+}  // extern "C"
