@@ -50,10 +50,7 @@ struct EvArgs {
 
 // y-inverse for evaluation: job = (field, layer) for volume fields, then
 // one job per surface field.
-template <typename R>
-__global__ void __launch_bounds__(256) k_yinv_eval(EvArgs A, Geom G, FftPlan plan, int TW) {
-  extern __shared__ unsigned char smem[];
-  const int job = blockIdx.y;
+__device__ __forceinline__ YInvJob eval_job(const EvArgs& A, const Geom& G, int job, size_t csz) {
   YInvJob jb = {};
   int fi;
   if (job < A.nvol * A.nl) {
@@ -64,14 +61,33 @@ __global__ void __launch_bounds__(256) k_yinv_eval(EvArgs A, Geom G, FftPlan pla
     jb.z = 0.0;
   }
   jb.src = A.f[fi].src;
-  jb.dst = reinterpret_cast<cpx<R>*>(A.inter) + (size_t)job * A.wy * G.nxh;
+  jb.dst = reinterpret_cast<char*>(A.inter) + (size_t)job * A.wy * G.nxh * csz;
   jb.sym = SYM_EVAL;
   jb.ev.vf = A.f[fi].vf;
   jb.ev.mult = A.f[fi].mult;
   jb.ev.pre = A.pre;
   jb.ev.gx = A.gx;
   jb.ev.gy = A.gy;
+  return jb;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_yinv_eval(EvArgs A, Geom G, FftPlan plan, int TW) {
+  extern __shared__ unsigned char smem[];
+  const YInvJob jb = eval_job(A, G, blockIdx.y, sizeof(cpx<R>));
   yinv_body<R>(jb, G, plan, TW, A.wy, A.iy0, smem);
+}
+
+// wavefront version: one wavefront per kx column, four per block
+template <typename R, int MAXE>
+__global__ void __launch_bounds__(256) k_yinv_eval_w(EvArgs A, Geom G, WPlan plan) {
+  extern __shared__ unsigned char smem[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
+  if (p >= G.nxh) return;
+  const YInvJob jb = eval_job(A, G, blockIdx.y, sizeof(cpx<R>));
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem) + (size_t)wave * wbuf_len(plan.n);
+  yinv_wave<R, MAXE>(jb, G, plan, A.wy, A.iy0, p, buf, lane);
 }
 
 // Complex length-gx sequence whose inverse transform is a + i b at the nodes,
@@ -209,6 +225,60 @@ __global__ void __launch_bounds__(256) k_xcoef(EvArgs A, Geom G, FftPlan plan, i
     }
     __syncthreads();
   }
+  for (int e = threadIdx.x; e < A.wx * nitems; e += blockDim.x) {
+    const int xw = e / nitems, j = e - xw * nitems;
+    coef[((size_t)r * A.wx + xw) * K + base_off + j] = stage[e];
+  }
+}
+
+// Wavefront version of the coefficient x pass: the (layer, field) pairs of
+// the block are spread over its four wavefronts, each with its own FFT
+// buffer; window values are staged in LDS and stored node-major after one
+// block barrier.
+template <typename R, int MAXE>
+__global__ void __launch_bounds__(256) k_xcoef_w(EvArgs A, Geom G, WPlan plan, int LG, int K, float* coef) {
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  const int gx = plan.n, r = blockIdx.x, g = blockIdx.y, hx = G.nx / 2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  C* zbuf = reinterpret_cast<C*>(smem) + (size_t)wave * wbuf_len(gx);
+  float* stage = reinterpret_cast<float*>(reinterpret_cast<C*>(smem) + 4 * (size_t)wbuf_len(gx));
+  const int Fv = A.nvol;
+  const int ngroups = Fv > 0 ? (A.nl + LG - 1) / LG : 0;
+  const bool surf = g == ngroups;
+  int nitems, base_off, l0 = 0;
+  if (surf) {
+    nitems = A.nsurf;
+    base_off = A.nl * Fv;
+  } else {
+    l0 = g * LG;
+    nitems = min(LG, A.nl - l0) * Fv;
+    base_off = l0 * Fv;
+  }
+  const C* inter = reinterpret_cast<const C*>(A.inter);
+  auto row = [&](int j) -> const C* {
+    const int job = surf ? A.nvol * A.nl + j : (j % Fv) * A.nl + l0 + j / Fv;
+    return inter + ((size_t)job * A.wy + r) * G.nxh;
+  };
+  const int npairs = (nitems + 1) / 2;
+  for (int pi = wave; pi < npairs; pi += 4) {
+    const int i = 2 * pi;
+    const bool hasb = i + 1 < nitems;
+    const C* ra = row(i);
+    const C* rb = hasb ? row(i + 1) : nullptr;
+    for (int s = lane; s < gx; s += 64) zbuf[sk(s)] = gather_x<R>(ra, rb, s, gx, hx);
+    wave_sync();
+    wave_fft<R, MAXE>(zbuf, plan, +1, lane);
+    for (int xw = lane; xw < A.wx; xw += 64) {
+      int x = A.ix0 + xw;
+      if (x >= gx) x -= gx;
+      const C zx = zbuf[sk(x)];
+      stage[xw * nitems + i] = (float)zx.x;
+      if (hasb) stage[xw * nitems + i + 1] = (float)zx.y;
+    }
+    wave_sync();
+  }
+  __syncthreads();
   for (int e = threadIdx.x; e < A.wx * nitems; e += blockDim.x) {
     const int xw = e / nitems, j = e - xw * nitems;
     coef[((size_t)r * A.wx + xw) * K + base_off + j] = stage[e];
@@ -357,30 +427,53 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
   TwiddleCache& tc = h->tw;
   FftPlan py = tc.get(A.gy, sizeof(R) == 8);
   FftPlan px = tc.get(A.gx, sizeof(R) == 8);
-  // y pass; jobs may exceed the grid's y limit -> chunk
-  {
+  // y pass
+  SW_REQUIRE(njobs <= 65535, "too many (field, layer) pairs");
+  if (py.n <= (sizeof(R) == 4 ? 4096 : 2048)) {
+    const WPlan wp = make_wplan(py);
+    const size_t lds = 4ull * wbuf_len(py.n) * csz;
+    dim3 grid((h->G.nxh + 3) / 4, njobs);
+#define L_YEV(E) sw_launch(h, SWENSE_K_YINV_EVAL, &k_yinv_eval_w<R, E>, grid, dim3(256), lds, h->st, A, h->G, wp)
+    switch (wave_maxe(py.n)) {
+      case 8: L_YEV(8); break;
+      case 16: L_YEV(16); break;
+      case 32: L_YEV(32); break;
+      case 48: L_YEV(48); break;
+      default: L_YEV(64); break;
+    }
+#undef L_YEV
+  } else {
     int TW = 1;
     long cap = 65536 / (2L * py.n * (long)csz);
     while (TW * 2 <= cap && TW * 2 <= 256) TW *= 2;
     const size_t lds = 2ull * TW * py.n * csz;
     dim3 grid((h->G.nxh + TW - 1) / TW, njobs);
-    SW_REQUIRE(njobs <= 65535, "too many (field, layer) pairs");
-    SW_LAUNCH(h, SWENSE_K_YINV_EVAL, k_yinv_eval<R>, grid, dim3(256), lds, h->st, A, h->G, py, TW);
-    SW_HIP(hipGetLastError());
+    sw_launch(h, SWENSE_K_YINV_EVAL, &k_yinv_eval<R>, grid, dim3(256), lds, h->st, A, h->G, py, TW);
   }
   if (pre) {
     const int Fv = A.nvol;
-    const int LG = Fv > 0 ? std::max(1, 32 / Fv) : 1;
+    const int LG = Fv > 0 ? std::max(1, 16 / Fv) : 1;
     const int ngroups = Fv > 0 ? (A.nl + LG - 1) / LG : 0;
     const int K = A.nl * Fv + A.nsurf;
     const int maxitems = std::max(LG * Fv, A.nsurf);
+    dim3 grid(A.wy, ngroups + (A.nsurf > 0 ? 1 : 0));
+    const size_t ldsw = 4ull * wbuf_len(px.n) * csz + (size_t)A.wx * maxitems * sizeof(float);
+    if (px.n <= (sizeof(R) == 4 ? 4096 : 2048) && ldsw <= 160 * 1024) {
+      const WPlan wp = make_wplan(px);
+#define L_XC(E) sw_launch(h, SWENSE_K_XEVAL, &k_xcoef_w<R, E>, grid, dim3(256), ldsw, h->st, A, h->G, wp, LG, K, out)
+      switch (wave_maxe(px.n)) {
+        case 8: L_XC(8); break;
+        case 16: L_XC(16); break;
+        case 32: L_XC(32); break;
+        case 48: L_XC(48); break;
+        default: L_XC(64); break;
+      }
+#undef L_XC
+      return;
+    }
     const size_t lds = 2ull * px.n * csz + (size_t)A.wx * maxitems * sizeof(float);
     SW_REQUIRE(lds <= 160 * 1024, "grid row too long for one workgroup");
-    if (lds > 65536)
-      SW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xcoef<R>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    SW_LAUNCH(h, SWENSE_K_XEVAL, k_xcoef<R>, dim3(A.wy, ngroups + (A.nsurf > 0 ? 1 : 0)), dim3(256), lds, h->st, A,
-              h->G, px, LG, K, out);
+    sw_launch(h, SWENSE_K_XEVAL, &k_xcoef<R>, grid, dim3(256), lds, h->st, A, h->G, px, LG, K, out);
     return;
   }
   if (A.nvol > 0) {

@@ -68,9 +68,13 @@ __device__ __forceinline__ void apply_role(const XIn& f, R v, R other, int x, in
 
 template <typename R>
 __device__ __forceinline__ R w2sum(const R* W, int K) {
+  // [W^2]_K = sum_{m=2..K} sum_{l=1..m-1} W^(l) W^(m-l); unrolled to constant indices
   R s = (R)0;
-  for (int m = 2; m <= K; ++m)
-    for (int l = 1; l < m; ++l) s += W[l - 1] * W[m - l - 1];
+#pragma unroll
+  for (int m = 2; m <= kMaxM; ++m)
+#pragma unroll
+    for (int l = 1; l < m; ++l)
+      if (m <= K) s += W[l - 1] * W[m - l - 1];
   return s;
 }
 
@@ -160,6 +164,48 @@ __global__ void __launch_bounds__(256) k_xpass(XArgs A, Geom G, FftPlan plan) {
   }
 }
 
+// Epilogue of the forward y transform for mode (p, q) with value v.
+__device__ __forceinline__ void yfwd_epilogue(const YFwdJob& jb, const RkArgs& rk, const Geom& G, int p, int q, int qs,
+                                              cd v) {
+  const size_t idx = (size_t)q * G.nxh + p;
+  if (jb.epi == YE_STORE) {
+    jb.dst[idx] = v;
+    if (jb.acc_mode == 1) jb.acc[idx] = jb.acc[idx] + v;
+    else if (jb.acc_mode == 2) jb.acc[idx] = v;
+    return;
+  }
+  const int w = jb.epi == YE_RHS_ETA ? 0 : 1;
+  cd k = v;
+  if (w == 0) {
+    const double kx = 2.0 * M_PI * (double)p / G.lx;
+    const double ky = G.ny > 1 ? 2.0 * M_PI * (double)qs / G.ly : 0.0;
+    const double kk = sqrt(kx * kx + ky * ky);
+    const double dz1 = G.depth > 0.0 ? kk * tanh(kk * G.depth) : kk;
+    k = k + cscale(rk.sin[1][idx], dz1);
+    if (p == 0 && q == 0) k = mk(0.0, 0.0);
+  } else {
+    k = k + cscale(rk.sin[0][idx], -G.g);
+  }
+  switch (rk.stage) {
+    case 0: rk.kout[w][idx] = k; break;
+    case 1:
+      rk.acc[w][idx] = k;
+      rk.sout[w][idx] = rk.xn[w][idx] + cscale(k, 0.5 * rk.dt);
+      break;
+    case 2:
+      rk.acc[w][idx] = rk.acc[w][idx] + cscale(k, 2.0);
+      rk.sout[w][idx] = rk.xn[w][idx] + cscale(k, 0.5 * rk.dt);
+      break;
+    case 3:
+      rk.acc[w][idx] = rk.acc[w][idx] + cscale(k, 2.0);
+      rk.sout[w][idx] = rk.xn[w][idx] + cscale(k, rk.dt);
+      break;
+    default:
+      rk.xn[w][idx] = rk.xn[w][idx] + cscale(rk.acc[w][idx] + k, rk.dt / 6.0);
+      break;
+  }
+}
+
 // y-forward: grid (ceil(nxh / TW), njobs).  Keeps modes |q| < ny/2, zeroes the
 // Nyquist row and column, scales by 1/Ly, then applies the epilogue.
 template <typename R>
@@ -190,43 +236,163 @@ __global__ void __launch_bounds__(256) k_yfwd(YFwdArgs A, Geom G, FftPlan plan, 
       C r = res[(size_t)c * Ly + slot];
       v = mk((double)r.x * inv, (double)r.y * inv);
     }
-    const size_t idx = (size_t)q * G.nxh + p;
-    if (jb.epi == YE_STORE) {
-      jb.dst[idx] = v;
-      if (jb.acc_mode == 1) jb.acc[idx] = jb.acc[idx] + v;
-      else if (jb.acc_mode == 2) jb.acc[idx] = v;
-      continue;
+    yfwd_epilogue(jb, A.rk, G, p, q, qs, v);
+  }
+}
+
+// Wavefront versions of the y transforms: one wavefront per kx column, four
+// columns per block, tiles ordered XCD by XCD.
+template <typename R, int MAXE>
+__global__ void __launch_bounds__(256) k_yinv_w(YInvArgs args, Geom G, WPlan plan, int nrows, int row0) {
+  extern __shared__ unsigned char smem[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
+  if (p >= G.nxh) return;
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem) + (size_t)wave * wbuf_len(plan.n);
+  yinv_wave<R, MAXE>(args.job[blockIdx.y], G, plan, nrows, row0, p, buf, lane);
+}
+
+template <typename R, int MAXE>
+__global__ void __launch_bounds__(256) k_yfwd_w(YFwdArgs A, Geom G, WPlan plan) {
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
+  if (p >= G.nxh) return;
+  const int Ly = plan.n;
+  C* buf = reinterpret_cast<C*>(smem) + (size_t)wave * wbuf_len(Ly);
+  const YFwdJob& jb = A.job[blockIdx.y];
+  const C* src = reinterpret_cast<const C*>(jb.src);
+  for (int s = lane; s < Ly; s += 64) buf[sk(s)] = src[(size_t)s * G.nxh + p];
+  wave_sync();
+  wave_fft<R, MAXE>(buf, plan, -1, lane);
+  const double inv = 1.0 / (double)Ly;
+  for (int q = lane; q < G.ny; q += 64) {
+    const int qs = signed_q(q, G.ny);
+    cd v = mk(0.0, 0.0);
+    if (2 * p != G.nx && !(G.ny > 1 && 2 * q == G.ny)) {
+      const int slot = ((qs % Ly) + Ly) % Ly;
+      C r = buf[sk(slot)];
+      v = mk((double)r.x * inv, (double)r.y * inv);
     }
-    const int w = jb.epi == YE_RHS_ETA ? 0 : 1;
-    cd k = v;
-    if (w == 0) {
-      const double kx = 2.0 * M_PI * (double)p / G.lx;
-      const double ky = G.ny > 1 ? 2.0 * M_PI * (double)qs / G.ly : 0.0;
-      const double kk = sqrt(kx * kx + ky * ky);
-      const double dz1 = G.depth > 0.0 ? kk * tanh(kk * G.depth) : kk;
-      k = k + cscale(rk.sin[1][idx], dz1);
-      if (p == 0 && q == 0) k = mk(0.0, 0.0);
+    yfwd_epilogue(jb, A.rk, G, p, q, qs, v);
+  }
+}
+
+// Fused x pass, wavefront version: block = physical row y, four wavefronts.
+// Field pairs are spread over the wavefronts (each transforms its pair in
+// its own LDS buffer and leaves the two real rows in LDS); after one block
+// barrier every thread forms the order-M products of its points in
+// registers; wavefront 0 transforms the result forward.
+template <typename R, int MAXE>
+__global__ void __launch_bounds__(256) k_xpass_w(XArgs A, Geom G, WPlan plan) {
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  const int Px = plan.n;
+  const int y = blockIdx.x;
+  const int hx = G.nx / 2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wl = wbuf_len(Px);
+  C* zbuf = reinterpret_cast<C*>(smem) + (size_t)wave * wl;
+  R* phys = reinterpret_cast<R*>(reinterpret_cast<C*>(smem) + 4 * (size_t)wl);  // [nin][Px]
+  const int npairs = (A.nin + 1) / 2;
+  for (int pi = wave; pi < npairs; pi += 4) {
+    const XIn& fa = A.in[2 * pi];
+    const bool hasb = 2 * pi + 1 < A.nin;
+    const XIn& fb = A.in[hasb ? 2 * pi + 1 : 2 * pi];
+    for (int s = lane; s < Px; s += 64) {
+      C z = mk((R)0, (R)0);
+      int p = -1;
+      bool cj = false;
+      if (s < hx) p = s;
+      else if (s > Px - hx) { p = Px - s; cj = true; }
+      if (p >= 0) {
+        C va = load_row<R>(fa, y, p, G);
+        C vb = hasb ? load_row<R>(fb, y, p, G) : mk((R)0, (R)0);
+        if (cj) { va = conjg(va); vb = conjg(vb); }
+        z = mk(va.x - vb.y, va.y + vb.x);
+      }
+      zbuf[sk(s)] = z;
+    }
+    wave_sync();
+    wave_fft<R, MAXE>(zbuf, plan, +1, lane);
+    for (int x = lane; x < Px; x += 64) {
+      const C zx = zbuf[sk(x)];
+      phys[(size_t)(2 * pi) * Px + x] = zx.x;
+      if (hasb) phys[(size_t)(2 * pi + 1) * Px + x] = zx.y;
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  const int M = A.M;
+  C* zout = reinterpret_cast<C*>(smem);  // wavefront 0's buffer
+  for (int x = threadIdx.x; x < Px; x += blockDim.x) {
+    R eta = (R)0, ge2 = (R)0, dot = (R)0, gp2 = (R)0, etat = (R)0, phit = (R)0;
+    R W[kMaxM];
+#pragma unroll
+    for (int m = 0; m < kMaxM; ++m) W[m] = (R)0;
+    for (int i = 0; i < A.nin; ++i) {
+      const XIn& f = A.in[i];
+      const R v = phys[(size_t)i * Px + x];
+      switch (f.role) {
+        case XR_ETA: eta = v; break;
+        case XR_GRADPAIR: {
+          const R b = phys[(size_t)(i + 1) * Px + x];
+          ge2 += v * v;
+          dot += v * b;
+          gp2 += b * b;
+        } break;
+        case XR_G: {
+          R c = (R)1;
+          for (int k = 1; k <= f.pw; ++k) c *= eta / (R)k;
+#pragma unroll
+          for (int m = 0; m < kMaxM; ++m)
+            if (m == f.wi) W[m] += c * v;
+        } break;
+        case XR_ETAT: etat = v; break;
+        case XR_PHIT: phit = v; break;
+        default: break;
+      }
+    }
+    R o0 = (R)0, o1 = (R)0;
+    if (A.stage == XS_SERIES) {
+      o0 = -W[0];
+    } else if (A.stage == XS_FTILDE) {
+      o0 = phit;
+      if (M >= 2) o0 -= W[0] * etat;
     } else {
-      k = k + cscale(rk.sin[0][idx], -G.g);
+      R wm = (R)0, wm2 = (R)0;
+#pragma unroll
+      for (int m = 0; m < kMaxM; ++m) {
+        if (m < M) wm += W[m];
+        if (m < M - 2) wm2 += W[m];
+      }
+      o0 = wm - W[0];
+      if (M >= 3) o0 += ge2 * wm2;
+      if (M >= 2) o0 -= dot;
+      o1 = (R)0.5 * w2sum(W, M);
+      if (M >= 2) o1 -= (R)0.5 * gp2;
+      if (M >= 4) o1 += (R)0.5 * ge2 * w2sum(W, M - 2);
     }
-    switch (rk.stage) {
-      case 0: rk.kout[w][idx] = k; break;
-      case 1:
-        rk.acc[w][idx] = k;
-        rk.sout[w][idx] = rk.xn[w][idx] + cscale(k, 0.5 * rk.dt);
-        break;
-      case 2:
-        rk.acc[w][idx] = rk.acc[w][idx] + cscale(k, 2.0);
-        rk.sout[w][idx] = rk.xn[w][idx] + cscale(k, 0.5 * rk.dt);
-        break;
-      case 3:
-        rk.acc[w][idx] = rk.acc[w][idx] + cscale(k, 2.0);
-        rk.sout[w][idx] = rk.xn[w][idx] + cscale(k, rk.dt);
-        break;
-      default:
-        rk.xn[w][idx] = rk.xn[w][idx] + cscale(rk.acc[w][idx] + k, rk.dt / 6.0);
-        break;
+    zout[sk(x)] = mk(o0, o1);
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  wave_fft<R, MAXE>(zout, plan, -1, lane);
+  const R sc = (R)(0.5 / (double)Px);
+  C* d0 = reinterpret_cast<C*>(A.out0);
+  C* d1 = reinterpret_cast<C*>(A.out1);
+  for (int p = lane; p < G.nxh; p += 64) {
+    C o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
+    if (p < hx) {
+      C zp = zout[sk(p)];
+      C zm = conjg(zout[sk((Px - p) % Px)]);
+      C sum = zp + zm, t = zp - zm;
+      o0 = cscale(sum, sc);
+      o1 = mk(t.y * sc, -t.x * sc);
     }
+    d0[(size_t)y * G.nxh + p] = o0;
+    if (d1) d1[(size_t)y * G.nxh + p] = o1;
   }
 }
 
@@ -308,8 +474,31 @@ void set_lds_limit(const void* fn, size_t bytes) {
 }
 
 template <typename R>
+bool wave_ok(int n) {
+  return n <= (sizeof(R) == 4 ? 4096 : 2048);
+}
+
+#define SW_MAXE_DISPATCH(n, LAUNCH) \
+  switch (wave_maxe(n)) {           \
+    case 8: LAUNCH(8); break;       \
+    case 16: LAUNCH(16); break;     \
+    case 32: LAUNCH(32); break;     \
+    case 48: LAUNCH(48); break;     \
+    default: LAUNCH(64); break;     \
+  }
+
+template <typename R>
 void yinv_t(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, int row0, hipStream_t st) {
   if (a.njobs == 0) return;
+  if (wave_ok<R>(plan.n)) {
+    const WPlan wp = make_wplan(plan);
+    const size_t lds = 4ull * wbuf_len(plan.n) * sizeof(cpx<R>);
+    dim3 grid((h->G.nxh + 3) / 4, a.njobs);
+#define L_YINV(E) sw_launch(h, SWENSE_K_YINV, &k_yinv_w<R, E>, grid, dim3(256), lds, st, a, h->G, wp, nrows, row0)
+    SW_MAXE_DISPATCH(plan.n, L_YINV);
+#undef L_YINV
+    return;
+  }
   const int TW = choose_tw(plan.n, sizeof(cpx<R>));
   const size_t lds = 2ull * TW * plan.n * sizeof(cpx<R>);
   dim3 grid((h->G.nxh + TW - 1) / TW, a.njobs);
@@ -319,6 +508,15 @@ void yinv_t(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, in
 
 template <typename R>
 void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t st) {
+  if (wave_ok<R>(plan.n)) {
+    const WPlan wp = make_wplan(plan);
+    const size_t lds = 4ull * wbuf_len(plan.n) * sizeof(cpx<R>);
+    dim3 grid((h->G.nxh + 3) / 4, a.njobs);
+#define L_YFWD(E) sw_launch(h, SWENSE_K_YFWD, &k_yfwd_w<R, E>, grid, dim3(256), lds, st, a, h->G, wp)
+    SW_MAXE_DISPATCH(plan.n, L_YFWD);
+#undef L_YFWD
+    return;
+  }
   const int TW = choose_tw(plan.n, sizeof(cpx<R>));
   const size_t lds = 2ull * TW * plan.n * sizeof(cpx<R>);
   dim3 grid((h->G.nxh + TW - 1) / TW, a.njobs);
@@ -329,6 +527,16 @@ void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t s
 template <typename R>
 void xpass_t(swense_hos* h, const XArgs& a) {
   const int Px = h->plan_px.n;
+  {
+    const size_t lds = 4ull * wbuf_len(Px) * sizeof(cpx<R>) + (size_t)a.nin * Px * sizeof(R);
+    if (wave_ok<R>(Px) && lds <= 160 * 1024) {
+      const WPlan wp = make_wplan(h->plan_px);
+#define L_XP(E) sw_launch(h, SWENSE_K_XPASS, &k_xpass_w<R, E>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, wp)
+      SW_MAXE_DISPATCH(Px, L_XP);
+#undef L_XP
+      return;
+    }
+  }
   const size_t lds = 2ull * Px * sizeof(cpx<R>) + (size_t)a.nslots * Px * sizeof(R);
   SW_REQUIRE(lds <= 160 * 1024, "x pass needs more LDS than a workgroup has (reduce nx or order)");
   set_lds_limit<R>(reinterpret_cast<const void*>(&k_xpass<R>), lds);
@@ -346,7 +554,7 @@ void add_job(YInvArgs& a, const cd* src, void* dst, int sym, int jpow = 0) {
   j.jpow = jpow;
 }
 
-void add_in(XArgs& a, const void* src, int dx, int role, int slot = 0, int pw = 0) {
+void add_in(XArgs& a, const void* src, int dx, int role, int slot = 0, int pw = 0, int wi = 0) {
   SW_REQUIRE(a.nin < kMaxXIn, "too many x inputs");
   XIn& f = a.in[a.nin++];
   f.src = src;
@@ -354,6 +562,7 @@ void add_in(XArgs& a, const void* src, int dx, int role, int slot = 0, int pw = 
   f.role = role;
   f.slot = slot;
   f.pw = pw;
+  f.wi = wi;
 }
 
 // Order-M Dirichlet series: given g(1, j) = F^-1(Dz^j base) already in the
@@ -420,7 +629,7 @@ void rhs_t(swense_hos* h, const cd* se, const cd* sp, const RkArgs& rk, bool wan
   for (int m = 0; m < M; ++m) xa.s_w[m] = 4 + m;
   xa.nslots = 4 + M;
   add_in(xa, h->e_, 0, XR_ETA);
-  add_in(xa, h->gbuf[1][1], 0, XR_G, xa.s_w[0], 0);
+  add_in(xa, h->gbuf[1][1], 0, XR_G, xa.s_w[0], 0, 0);
   add_in(xa, h->e_, 1, XR_GRADPAIR);
   add_in(xa, h->ph_, 1, XR_NONE);
   if (three) {
@@ -430,7 +639,7 @@ void rhs_t(swense_hos* h, const cd* se, const cd* sp, const RkArgs& rk, bool wan
   for (int m = 1; m <= M; ++m)
     for (int j = 1; m + j <= M + 1; ++j) {
       if (m == 1 && j == 1) continue;
-      add_in(xa, h->gbuf[m][j], 0, XR_G, xa.s_w[m + j - 2], j - 1);
+      add_in(xa, h->gbuf[m][j], 0, XR_G, xa.s_w[m + j - 2], j - 1, m + j - 2);
     }
   xa.out0 = h->r0_;
   xa.out1 = h->r1_;

@@ -42,6 +42,7 @@ struct XIn {
   int role;
   int slot;         // accumulator slot written by XR_G
   int pw;           // power of eta for XR_G
+  int wi;           // index of the W order (or series sum) XR_G adds to
 };
 
 constexpr int kMaxXIn = 24;
@@ -188,6 +189,18 @@ struct ProfScope {
     hipLaunchKernelGGL(__VA_ARGS__);    \
     SW_HIP(hipGetLastError());          \
   } while (0)
+
+// Launch with optional >64 KB dynamic LDS and per-kernel timing.
+template <typename... KArgs, typename... Args>
+void sw_launch(swense_hos* h, int kid, void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds, hipStream_t st,
+               Args... args) {
+  if (lds > 65536)
+    SW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+  ProfScope ps(h, kid);
+  hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+  SW_HIP(hipGetLastError());
+}
 
 // ---- launch helpers implemented in hos.hip (templated on precision there)
 void launch_yinv(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, int row0, hipStream_t st);

@@ -1,0 +1,169 @@
+// Wavefront-level FFT: one 64-lane wavefront transforms one sequence held in
+// its own LDS buffer, in place, with mixed-radix self-sorting (Stockham)
+// passes of radix 16, 8, 4, 2, 3 or 5.  In every pass each lane first loads
+// all of its butterflies into registers, the wavefront synchronises, then each
+// lane twiddles, transforms and stores; no workgroup barrier is involved, so
+// the waves of a workgroup run independent transforms.
+//
+// MAXE is the largest number of elements per lane (n <= 64 MAXE); register
+// arrays are sized by it.  Twiddles come from a table exp(-2 pi i m / n)
+// computed in FP64 and rounded to the transform precision.
+#pragma once
+
+#include "common.h"
+
+// LDS index of element i of a wavefront FFT buffer: one pad slot every 16
+// elements, so the strided stores of the early Stockham passes spread over
+// the banks.  Buffers hold wbuf_len(n) elements.
+__host__ __device__ __forceinline__ int sk(int i) { return i + (i >> 4); }
+__host__ __device__ __forceinline__ int wbuf_len(int n) { return n + (n >> 4) + 1; }
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// exp(sign i pi m / 8) for the inner twiddles of the radix-16 butterfly
+template <typename R>
+__device__ __forceinline__ cpx<R> w16(int m, int sign) {
+  const R c1 = (R)0.92387953251128675613, s1 = (R)0.38268343236508977173, h = (R)0.70710678118654752440;
+  switch (m) {
+    case 1: return mk(c1, sign * s1);
+    case 2: return mk(h, sign * h);
+    case 3: return mk(s1, sign * c1);
+    case 4: return mk((R)0, (R)sign);
+    case 6: return mk(-h, sign * h);
+    case 9: return mk(-c1, -sign * s1);
+    default: return mk((R)1, (R)0);
+  }
+}
+
+// 16-point DFT as 4 x 4 with inner twiddles exp(sign 2 pi i n2 k1 / 16).
+template <typename R>
+__device__ __forceinline__ void dft16(cpx<R>* v, int sign) {
+  cpx<R> a[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    cpx<R> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+    dft4(t, sign);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = (n2 * k1 == 0) ? t[k1] : cmul(t[k1], w16<R>(n2 * k1, sign));
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cpx<R> t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+    dft4(t, sign);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+  }
+}
+
+template <typename R, int RAD>
+__device__ __forceinline__ void dft_any(cpx<R>* v, int sign) {
+  if (RAD == 2) dft2(v);
+  else if (RAD == 3) dft3(v, sign);
+  else if (RAD == 4) dft4(v, sign);
+  else if (RAD == 5) dft5(v, sign);
+  else if (RAD == 8) dft8(v, sign);
+  else dft16(v, sign);
+}
+
+template <typename R, int RAD, int MAXE>
+__device__ __forceinline__ void wave_pass(cpx<R>* buf, int n, int Ns, const cpx<R>* __restrict__ tw, int sign,
+                                          int lane) {
+  constexpr int MAXB = (MAXE + RAD - 1) / RAD;
+  const int nb = n / RAD;
+  const int twstep = n / (Ns * RAD);
+  const bool pow2 = (Ns & (Ns - 1)) == 0;
+  cpx<R> v[MAXB][RAD];
+#pragma unroll
+  for (int m = 0; m < MAXB; ++m) {
+    const int j = lane + 64 * m;
+    if (j < nb) {
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[m][r] = buf[sk(j + r * nb)];
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int m = 0; m < MAXB; ++m) {
+    const int j = lane + 64 * m;
+    if (j < nb) {
+      const int k = pow2 ? (j & (Ns - 1)) : (j % Ns);
+      if (k > 0) {
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          cpx<R> w = tw[k * r * twstep];
+          if (sign > 0) w.y = -w.y;
+          v[m][r] = cmul(v[m][r], w);
+        }
+      }
+      dft_any<R, RAD>(v[m], sign);
+      const int o = (j - k) * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) buf[sk(o + r * Ns)] = v[m][r];
+    }
+  }
+  wave_sync();
+}
+
+// Plan for the wavefront FFT: radices 16 first, then one of 8/4/2, then 3s
+// and 5s.
+struct WPlan {
+  int n;
+  int nrad;
+  int rad[kMaxRad];
+  const void* tw;
+};
+
+inline WPlan make_wplan(const FftPlan& p) {
+  WPlan w{};
+  w.n = p.n;
+  w.tw = p.tw;
+  int n = p.n;
+  int np = 0;
+  while (n % 16 == 0) { w.rad[np++] = 16; n /= 16; }
+  if (n % 8 == 0) { w.rad[np++] = 8; n /= 8; }
+  if (n % 4 == 0) { w.rad[np++] = 4; n /= 4; }
+  if (n % 2 == 0) { w.rad[np++] = 2; n /= 2; }
+  while (n % 3 == 0) { w.rad[np++] = 3; n /= 3; }
+  while (n % 5 == 0) { w.rad[np++] = 5; n /= 5; }
+  w.nrad = np;
+  return w;
+}
+
+// Elements per lane a kernel instantiation must hold for length n.
+inline int wave_maxe(int n) {
+  const int e = (n + 63) / 64;
+  if (e <= 8) return 8;
+  if (e <= 16) return 16;
+  if (e <= 32) return 32;
+  if (e <= 48) return 48;
+  return 64;
+}
+
+template <typename R, int MAXE>
+__device__ void wave_fft(cpx<R>* buf, const WPlan& plan, int sign, int lane) {
+  const cpx<R>* tw = reinterpret_cast<const cpx<R>*>(plan.tw);
+  int Ns = 1;
+  for (int p = 0; p < plan.nrad; ++p) {
+    switch (plan.rad[p]) {
+      case 16: wave_pass<R, 16, MAXE>(buf, plan.n, Ns, tw, sign, lane); break;
+      case 8: wave_pass<R, 8, MAXE>(buf, plan.n, Ns, tw, sign, lane); break;
+      case 4: wave_pass<R, 4, MAXE>(buf, plan.n, Ns, tw, sign, lane); break;
+      case 2: wave_pass<R, 2, MAXE>(buf, plan.n, Ns, tw, sign, lane); break;
+      case 3: wave_pass<R, 3, MAXE>(buf, plan.n, Ns, tw, sign, lane); break;
+      default: wave_pass<R, 5, MAXE>(buf, plan.n, Ns, tw, sign, lane); break;
+    }
+    Ns *= plan.rad[p];
+  }
+}
+
+// Block index remapped so that the blocks resident on one XCD (blocks are
+// dealt round-robin over the 8 XCDs) process a contiguous range of tiles.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int q = nblocks >> 3, r = nblocks & 7;
+  const int xcd = b & 7, k = b >> 3;
+  return xcd * q + min(xcd, r) + k;
+}

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "internal.h"
+#include "wfft.h"
 
 __device__ __forceinline__ cd symbol_of(const Geom& G, const YInvJob& jb, int p, int qs) {
   const double kx = 2.0 * M_PI * (double)p / G.lx;
@@ -43,6 +44,51 @@ __device__ __forceinline__ cd symbol_of(const Geom& G, const YInvJob& jb, int p,
 // sequence gathers every kept mode q whose signed index is = s (mod Ly):
 // zero-padding when Ly >= ny, alias-folding when Ly < ny.  Rows
 // (row0 + r) mod Ly, r < nrows, are stored.
+// Value of slot s of column p: the sum over kept modes q with signed index
+// = s (mod Ly) of spectrum x symbol (zero-padding or alias-folding in y).
+__device__ __forceinline__ cd yinv_slot(const YInvJob& jb, const Geom& G, int Ly, int p, int s) {
+  double ax = 0.0, ay = 0.0;
+  if (p < G.nxh && 2 * p != G.nx) {
+    if (G.ny == 1) {
+      if (s == 0) {
+        cd v = cmul(jb.src[p], symbol_of(G, jb, p, 0));
+        ax = v.x;
+        ay = v.y;
+      }
+    } else {
+      const int half = G.ny / 2;
+      for (int qs = s - ((s + half - 1) / Ly) * Ly; qs <= half - 1; qs += Ly) {
+        const int q = qs >= 0 ? qs : qs + G.ny;
+        cd v = cmul(jb.src[(size_t)q * G.nxh + p], symbol_of(G, jb, p, qs));
+        ax += v.x;
+        ay += v.y;
+      }
+    }
+  }
+  return mk(ax, ay);
+}
+
+// Wavefront version: the calling wavefront transforms column p in its LDS
+// buffer (wbuf_len(Ly) complex, skewed index) and stores rows
+// (row0 + r) mod Ly, r < nrows.
+template <typename R, int MAXE>
+__device__ __forceinline__ void yinv_wave(const YInvJob& jb, const Geom& G, const WPlan& plan, int nrows, int row0,
+                                          int p, cpx<R>* buf, int lane) {
+  const int Ly = plan.n;
+  for (int s = lane; s < Ly; s += 64) {
+    cd v = yinv_slot(jb, G, Ly, p, s);
+    buf[sk(s)] = mk((R)v.x, (R)v.y);
+  }
+  wave_sync();
+  wave_fft<R, MAXE>(buf, plan, +1, lane);
+  cpx<R>* dst = reinterpret_cast<cpx<R>*>(jb.dst);
+  for (int r = lane; r < nrows; r += 64) {
+    int y = row0 + r;
+    if (y >= Ly) y -= Ly * (y / Ly);
+    dst[(size_t)r * G.nxh + p] = buf[sk(y)];
+  }
+}
+
 template <typename R>
 __device__ __forceinline__ void yinv_body(const YInvJob& jb, const Geom& G, const FftPlan& plan, int TW, int nrows,
                                           int row0, unsigned char* smem) {
