@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) k_yinv_eval(EvArgs A, Geom G, FftPlan pla
 }
 
 // wavefront version: one wavefront per kx column, four per block
-template <typename R, int MAXE>
+template <typename R, int MAXE, int NS0>
 __global__ void __launch_bounds__(256) k_yinv_eval_w(EvArgs A, Geom G, WPlan plan) {
   extern __shared__ unsigned char smem[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256) k_yinv_eval_w(EvArgs A, Geom G, WPlan pla
   if (p >= G.nxh) return;
   const YInvJob jb = eval_job(A, G, blockIdx.y, sizeof(cpx<R>));
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem) + (size_t)wave * wbuf_len(plan.n);
-  yinv_wave<R, MAXE>(jb, G, plan, A.wy, A.iy0, p, buf, lane);
+  yinv_wave<R, MAXE, NS0>(jb, G, plan, A.wy, A.iy0, p, buf, lane);
 }
 
 // Complex length-gx sequence whose inverse transform is a + i b at the nodes,
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(256) k_xcoef(EvArgs A, Geom G, FftPlan plan, i
 // the block are spread over its four wavefronts, each with its own FFT
 // buffer; window values are staged in LDS and stored node-major after one
 // block barrier.
-template <typename R, int MAXE>
+template <typename R, int MAXE, int NS0>
 __global__ void __launch_bounds__(256) k_xcoef_w(EvArgs A, Geom G, WPlan plan, int LG, int K, float* coef) {
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(256) k_xcoef_w(EvArgs A, Geom G, WPlan plan, i
     const C* rb = hasb ? row(i + 1) : nullptr;
     for (int s = lane; s < gx; s += 64) zbuf[sk(s)] = gather_x<R>(ra, rb, s, gx, hx);
     wave_sync();
-    wave_fft<R, MAXE>(zbuf, plan, +1, lane);
+    wave_fft_any<R, MAXE, NS0>(zbuf, plan, +1, lane);
     for (int xw = lane; xw < A.wx; xw += 64) {
       int x = A.ix0 + xw;
       if (x >= gx) x -= gx;
@@ -282,6 +282,62 @@ __global__ void __launch_bounds__(256) k_xcoef_w(EvArgs A, Geom G, WPlan plan, i
   for (int e = threadIdx.x; e < A.wx * nitems; e += blockDim.x) {
     const int xw = e / nitems, j = e - xw * nitems;
     coef[((size_t)r * A.wx + xw) * K + base_off + j] = stage[e];
+  }
+}
+
+// Coefficient x pass on skeleton heights: block (window row, field f); the
+// R skeleton transforms of f are spread over the block's wavefronts, staged
+// in LDS, and every layer is formed as sum_r T[l][r] s_r at each window node
+// before the node-major store.  Blocks with f = Fv handle the surface fields.
+template <typename R, int MAXE, int NS0>
+__global__ void __launch_bounds__(256) k_xcoef_skel(EvArgs A, Geom G, WPlan plan, Skel skl, int L, int K, float* coef) {
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  constexpr int WPB = 4;
+  const int gx = plan.n, r = blockIdx.x, f = blockIdx.y, hx = G.nx / 2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  C* zbuf = reinterpret_cast<C*>(smem) + (size_t)wave * wbuf_len(gx);
+  float* stage = reinterpret_cast<float*>(reinterpret_cast<C*>(smem) + WPB * (size_t)wbuf_len(gx));
+  const int Fv = A.nvol;
+  const bool surf = f == Fv;
+  const int nitems = surf ? A.nsurf : skl.R;
+  const C* inter = reinterpret_cast<const C*>(A.inter);
+  auto row = [&](int j) -> const C* {
+    const int job = surf ? Fv * skl.R + j : f * skl.R + j;
+    return inter + ((size_t)job * A.wy + r) * G.nxh;
+  };
+  const int npairs = (nitems + 1) / 2;
+  for (int pi = wave; pi < npairs; pi += WPB) {
+    const int i = 2 * pi;
+    const bool hasb = i + 1 < nitems;
+    const C* ra = row(i);
+    const C* rb = hasb ? row(i + 1) : nullptr;
+    for (int s = lane; s < gx; s += 64) zbuf[sk(s)] = gather_x<R>(ra, rb, s, gx, hx);
+    wave_sync();
+    wave_fft_any<R, MAXE, NS0>(zbuf, plan, +1, lane);
+    for (int xw = lane; xw < A.wx; xw += 64) {
+      int x = A.ix0 + xw;
+      if (x >= gx) x -= gx;
+      const C zx = zbuf[sk(x)];
+      stage[i * A.wx + xw] = (float)zx.x;
+      if (hasb) stage[(i + 1) * A.wx + xw] = (float)zx.y;
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  if (surf) {
+    for (int e = threadIdx.x; e < A.wx * nitems; e += blockDim.x) {
+      const int xw = e / nitems, j = e - xw * nitems;
+      coef[((size_t)r * A.wx + xw) * K + (size_t)L * Fv + j] = stage[j * A.wx + xw];
+    }
+    return;
+  }
+  const float* T = A.f[f].vf == 1 ? skl.ts : skl.tc;
+  for (int e = threadIdx.x; e < A.wx * L; e += blockDim.x) {
+    const int xw = e / L, l = e - xw * L;
+    float acc = 0.f;
+    for (int j = 0; j < skl.R; ++j) acc += T[l * skl.R + j] * stage[j * A.wx + xw];
+    coef[((size_t)r * A.wx + xw) * K + (size_t)l * Fv + f] = acc;
   }
 }
 
@@ -389,13 +445,15 @@ void plan_fields(swense_hos* h, unsigned mask, bool pre, EvArgs& A, int* out_of_
 }
 
 template <typename R>
-void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned mask, bool pre, float* out) {
+void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned mask, bool pre, float* out,
+            const Skel* skel) {
   launch_modes(h);
   EvArgs A;
   int nvo = 0, nso = 0;
   plan_fields(h, mask, pre, A, nullptr, &nvo, &nso);
-  A.z = zdev;
-  A.nl = gd->nl;
+  const bool use_skel = pre && skel && skel->R > 0;
+  A.z = use_skel ? skel->zeta : zdev;
+  A.nl = use_skel ? skel->R : gd->nl;
   A.gx = gd->gx;
   A.gy = h->G.ny > 1 ? gd->gy : 1;
   A.ix0 = gd->ix0;
@@ -433,14 +491,8 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     const WPlan wp = make_wplan(py);
     const size_t lds = 4ull * wbuf_len(py.n) * csz;
     dim3 grid((h->G.nxh + 3) / 4, njobs);
-#define L_YEV(E) sw_launch(h, SWENSE_K_YINV_EVAL, &k_yinv_eval_w<R, E>, grid, dim3(256), lds, h->st, A, h->G, wp)
-    switch (wave_maxe(py.n)) {
-      case 8: L_YEV(8); break;
-      case 16: L_YEV(16); break;
-      case 32: L_YEV(32); break;
-      case 48: L_YEV(48); break;
-      default: L_YEV(64); break;
-    }
+#define L_YEV(E, N) sw_launch(h, SWENSE_K_YINV_EVAL, &k_yinv_eval_w<R, E, N>, grid, dim3(256), lds, h->st, A, h->G, wp)
+    SW_FFT_DISPATCH(py.n, L_YEV);
 #undef L_YEV
   } else {
     int TW = 1;
@@ -449,6 +501,20 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     const size_t lds = 2ull * TW * py.n * csz;
     dim3 grid((h->G.nxh + TW - 1) / TW, njobs);
     sw_launch(h, SWENSE_K_YINV_EVAL, &k_yinv_eval<R>, grid, dim3(256), lds, h->st, A, h->G, py, TW);
+  }
+  if (use_skel) {
+    const int Fv = A.nvol;
+    const int L = gd->nl;
+    const int K = L * Fv + A.nsurf;
+    const int maxitems = std::max(skel->R, A.nsurf);
+    const size_t lds = 4ull * wbuf_len(px.n) * csz + (size_t)A.wx * maxitems * sizeof(float);
+    SW_REQUIRE(px.n <= (sizeof(R) == 4 ? 4096 : 2048) && lds <= 160 * 1024, "grid row too long for one workgroup");
+    const WPlan wp = make_wplan(px);
+    dim3 grid(A.wy, Fv + (A.nsurf > 0 ? 1 : 0));
+#define L_XS(E, N) sw_launch(h, SWENSE_K_XEVAL, &k_xcoef_skel<R, E, N>, grid, dim3(256), lds, h->st, A, h->G, wp, *skel, L, K, out)
+    SW_FFT_DISPATCH(px.n, L_XS);
+#undef L_XS
+    return;
   }
   if (pre) {
     const int Fv = A.nvol;
@@ -460,14 +526,8 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     const size_t ldsw = 4ull * wbuf_len(px.n) * csz + (size_t)A.wx * maxitems * sizeof(float);
     if (px.n <= (sizeof(R) == 4 ? 4096 : 2048) && ldsw <= 160 * 1024) {
       const WPlan wp = make_wplan(px);
-#define L_XC(E) sw_launch(h, SWENSE_K_XEVAL, &k_xcoef_w<R, E>, grid, dim3(256), ldsw, h->st, A, h->G, wp, LG, K, out)
-      switch (wave_maxe(px.n)) {
-        case 8: L_XC(8); break;
-        case 16: L_XC(16); break;
-        case 32: L_XC(32); break;
-        case 48: L_XC(48); break;
-        default: L_XC(64); break;
-      }
+#define L_XC(E, N) sw_launch(h, SWENSE_K_XEVAL, &k_xcoef_w<R, E, N>, grid, dim3(256), ldsw, h->st, A, h->G, wp, LG, K, out)
+      SW_FFT_DISPATCH(px.n, L_XC);
 #undef L_XC
       return;
     }
@@ -496,9 +556,9 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
 }
 
 void eval_dispatch(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned mask, bool pre,
-                   float* out) {
-  if (h->fp64) eval_t<double>(h, gd, zdev, mask, pre, out);
-  else eval_t<float>(h, gd, zdev, mask, pre, out);
+                   float* out, const Skel* skel = nullptr) {
+  if (h->fp64) eval_t<double>(h, gd, zdev, mask, pre, out, skel);
+  else eval_t<float>(h, gd, zdev, mask, pre, out, skel);
 }
 
 size_t grid_floats(const swense_hos* h, const swense_grid_desc* gd, unsigned mask, bool pre) {
@@ -533,8 +593,9 @@ CoefLayout coef_layout(swense_hos* h, unsigned cm, int nl) {
   return L;
 }
 
-void eval_coef(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned cm, float* coef) {
-  eval_dispatch(h, gd, zdev, cm, true, coef);
+void eval_coef(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned cm, float* coef,
+               const Skel* sk) {
+  eval_dispatch(h, gd, zdev, cm, true, coef, sk);
 }
 
 size_t coef_floats(swense_hos* h, const swense_grid_desc* gd, unsigned cm) { return grid_floats(h, gd, cm, true); }

@@ -242,17 +242,17 @@ __global__ void __launch_bounds__(256) k_yfwd(YFwdArgs A, Geom G, FftPlan plan, 
 
 // Wavefront versions of the y transforms: one wavefront per kx column, four
 // columns per block, tiles ordered XCD by XCD.
-template <typename R, int MAXE>
+template <typename R, int MAXE, int NS0>
 __global__ void __launch_bounds__(256) k_yinv_w(YInvArgs args, Geom G, WPlan plan, int nrows, int row0) {
   extern __shared__ unsigned char smem[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int p = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
   if (p >= G.nxh) return;
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem) + (size_t)wave * wbuf_len(plan.n);
-  yinv_wave<R, MAXE>(args.job[blockIdx.y], G, plan, nrows, row0, p, buf, lane);
+  yinv_wave<R, MAXE, NS0>(args.job[blockIdx.y], G, plan, nrows, row0, p, buf, lane);
 }
 
-template <typename R, int MAXE>
+template <typename R, int MAXE, int NS0>
 __global__ void __launch_bounds__(256) k_yfwd_w(YFwdArgs A, Geom G, WPlan plan) {
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(256) k_yfwd_w(YFwdArgs A, Geom G, WPlan plan) 
   const C* src = reinterpret_cast<const C*>(jb.src);
   for (int s = lane; s < Ly; s += 64) buf[sk(s)] = src[(size_t)s * G.nxh + p];
   wave_sync();
-  wave_fft<R, MAXE>(buf, plan, -1, lane);
+  wave_fft_any<R, MAXE, NS0>(buf, plan, -1, lane);
   const double inv = 1.0 / (double)Ly;
   for (int q = lane; q < G.ny; q += 64) {
     const int qs = signed_q(q, G.ny);
@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(256) k_yfwd_w(YFwdArgs A, Geom G, WPlan plan) 
 // its own LDS buffer and leaves the two real rows in LDS); after one block
 // barrier every thread forms the order-M products of its points in
 // registers; wavefront 0 transforms the result forward.
-template <typename R, int MAXE>
+template <typename R, int MAXE, int NS0>
 __global__ void __launch_bounds__(256) k_xpass_w(XArgs A, Geom G, WPlan plan) {
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(256) k_xpass_w(XArgs A, Geom G, WPlan plan) {
       zbuf[sk(s)] = z;
     }
     wave_sync();
-    wave_fft<R, MAXE>(zbuf, plan, +1, lane);
+    wave_fft_any<R, MAXE, NS0>(zbuf, plan, +1, lane);
     for (int x = lane; x < Px; x += 64) {
       const C zx = zbuf[sk(x)];
       phys[(size_t)(2 * pi) * Px + x] = zx.x;
@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(256) k_xpass_w(XArgs A, Geom G, WPlan plan) {
   }
   __syncthreads();
   if (wave != 0) return;
-  wave_fft<R, MAXE>(zout, plan, -1, lane);
+  wave_fft_any<R, MAXE, NS0>(zout, plan, -1, lane);
   const R sc = (R)(0.5 / (double)Px);
   C* d0 = reinterpret_cast<C*>(A.out0);
   C* d1 = reinterpret_cast<C*>(A.out1);
@@ -494,8 +494,8 @@ void yinv_t(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, in
     const WPlan wp = make_wplan(plan);
     const size_t lds = 4ull * wbuf_len(plan.n) * sizeof(cpx<R>);
     dim3 grid((h->G.nxh + 3) / 4, a.njobs);
-#define L_YINV(E) sw_launch(h, SWENSE_K_YINV, &k_yinv_w<R, E>, grid, dim3(256), lds, st, a, h->G, wp, nrows, row0)
-    SW_MAXE_DISPATCH(plan.n, L_YINV);
+#define L_YINV(E, N) sw_launch(h, SWENSE_K_YINV, &k_yinv_w<R, E, N>, grid, dim3(256), lds, st, a, h->G, wp, nrows, row0)
+    SW_FFT_DISPATCH(plan.n, L_YINV);
 #undef L_YINV
     return;
   }
@@ -512,8 +512,8 @@ void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t s
     const WPlan wp = make_wplan(plan);
     const size_t lds = 4ull * wbuf_len(plan.n) * sizeof(cpx<R>);
     dim3 grid((h->G.nxh + 3) / 4, a.njobs);
-#define L_YFWD(E) sw_launch(h, SWENSE_K_YFWD, &k_yfwd_w<R, E>, grid, dim3(256), lds, st, a, h->G, wp)
-    SW_MAXE_DISPATCH(plan.n, L_YFWD);
+#define L_YFWD(E, N) sw_launch(h, SWENSE_K_YFWD, &k_yfwd_w<R, E, N>, grid, dim3(256), lds, st, a, h->G, wp)
+    SW_FFT_DISPATCH(plan.n, L_YFWD);
 #undef L_YFWD
     return;
   }
@@ -531,8 +531,8 @@ void xpass_t(swense_hos* h, const XArgs& a) {
     const size_t lds = 4ull * wbuf_len(Px) * sizeof(cpx<R>) + (size_t)a.nin * Px * sizeof(R);
     if (wave_ok<R>(Px) && lds <= 160 * 1024) {
       const WPlan wp = make_wplan(h->plan_px);
-#define L_XP(E) sw_launch(h, SWENSE_K_XPASS, &k_xpass_w<R, E>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, wp)
-      SW_MAXE_DISPATCH(Px, L_XP);
+#define L_XP(E, N) sw_launch(h, SWENSE_K_XPASS, &k_xpass_w<R, E, N>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, wp)
+      SW_FFT_DISPATCH(Px, L_XP);
 #undef L_XP
       return;
     }

@@ -219,7 +219,18 @@ struct CoefLayout {
   int idx[11];
 };
 CoefLayout coef_layout(swense_hos* h, unsigned cm, int nl);
-void eval_coef(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned cm, float* coef);
+// Skeleton heights for the vertical factors: the factors C(k, z_l) (and
+// S(k, z_l)) of every layer are reproduced, for all |k| of the mode grid, by
+// combinations  sum_r T[l][r] C(k, zeta_r)  of r < R skeleton heights chosen
+// among the layers, so only R transforms per field are needed.
+struct Skel {
+  int R;              // 0: not used
+  const double* zeta; // device [R]
+  const float* tc;    // device [nl][R] for C-type fields (phi, u, v and their time derivatives)
+  const float* ts;    // device [nl][R] for S-type fields (w, w_t)
+};
+void eval_coef(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned cm, float* coef,
+               const Skel* sk);
 size_t coef_floats(swense_hos* h, const swense_grid_desc* gd, unsigned cm);
 
 // run a body and convert exceptions to error codes

@@ -20,6 +20,7 @@
 // point takes 4 vertical taps per field.  Pressure is formed at the point
 // from phi_t, u, v, w: p = -rho (phi_t + |u|^2/2) - rho g z.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -222,9 +223,130 @@ struct swense_cells {
   double* zdev = nullptr;
   void* coef = nullptr;
   size_t coef_bytes = 0;
+  Skel skel{};            // skeleton heights of the layers (R = 0: none)
+  void* skel_mem = nullptr;
 };
 
 namespace {
+
+// Skeleton heights (host, FP64).  Rows: |k| sampled on [0, kmax] for both
+// factor families C = cosh k(z+h)/cosh kh and S = sinh k(z+h)/cosh kh (deep
+// water: e^{kz} for both), each row scaled by max(1, max_l |factor|);
+// columns: the layers.  Greedy column-pivoted Gram-Schmidt picks layers until
+// every remaining column is reproduced to `tol` (per row, relative to the
+// row scale); T = least-squares coefficients of every layer on the picks,
+// separately for C and S.  Returns false if no worthwhile reduction exists.
+bool build_skeleton(const std::vector<double>& z, double kmax, double depth, double tol, std::vector<int>& sel,
+                    std::vector<float>& tc, std::vector<float>& ts) {
+  const int L = (int)z.size();
+  const int nk = 1024;
+  const bool deep = !(depth > 0);
+  std::vector<double> BC((size_t)nk * L), BS((size_t)nk * L);
+  for (int i = 0; i < nk; ++i) {
+    const double k = kmax * i / (nk - 1);
+    double sc = 1.0, ss = 1.0;
+    for (int l = 0; l < L; ++l) {
+      double c, sv;
+      if (deep) {
+        c = sv = std::exp(k * z[l]);
+      } else {
+        const double a = std::exp(k * z[l]), b = std::exp(-k * (z[l] + 2 * depth)), d = 1.0 + std::exp(-2 * k * depth);
+        c = (a + b) / d;
+        sv = (a - b) / d;
+      }
+      BC[(size_t)l * nk + i] = c;
+      BS[(size_t)l * nk + i] = sv;
+      sc = std::max(sc, std::fabs(c));
+      ss = std::max(ss, std::fabs(sv));
+    }
+    for (int l = 0; l < L; ++l) {
+      BC[(size_t)l * nk + i] /= sc;
+      BS[(size_t)l * nk + i] /= ss;
+    }
+  }
+  // joint residual matrix [BC; BS], column-major, 2 nk rows
+  const int m = 2 * nk;
+  std::vector<double> Rm((size_t)m * L);
+  for (int l = 0; l < L; ++l)
+    for (int i = 0; i < nk; ++i) {
+      Rm[(size_t)l * m + i] = BC[(size_t)l * nk + i];
+      Rm[(size_t)l * m + nk + i] = BS[(size_t)l * nk + i];
+    }
+  sel.clear();
+  std::vector<char> used(L, 0);
+  for (int it = 0; it < L; ++it) {
+    int jb = -1;
+    double best = 0.0, bmax = 0.0;
+    for (int l = 0; l < L; ++l) {
+      if (used[l]) continue;
+      double nn = 0.0, mx = 0.0;
+      for (int i = 0; i < m; ++i) {
+        nn += Rm[(size_t)l * m + i] * Rm[(size_t)l * m + i];
+        mx = std::max(mx, std::fabs(Rm[(size_t)l * m + i]));
+      }
+      if (nn > best) { best = nn; jb = l; }
+      bmax = std::max(bmax, mx);
+    }
+    if (jb < 0 || bmax <= tol) break;
+    used[jb] = 1;
+    sel.push_back(jb);
+    const double inv = 1.0 / std::sqrt(best);
+    std::vector<double> q(m);
+    for (int i = 0; i < m; ++i) q[i] = Rm[(size_t)jb * m + i] * inv;
+    for (int l = 0; l < L; ++l) {
+      double dp = 0.0;
+      for (int i = 0; i < m; ++i) dp += q[i] * Rm[(size_t)l * m + i];
+      for (int i = 0; i < m; ++i) Rm[(size_t)l * m + i] -= dp * q[i];
+    }
+  }
+  const int R = (int)sel.size();
+  if (R == 0 || 4 * R > 3 * L) return false;
+  std::sort(sel.begin(), sel.end());
+  // least squares per family via modified Gram-Schmidt on the picked columns
+  auto solve = [&](const std::vector<double>& B, std::vector<float>& T) -> double {
+    std::vector<double> Q((size_t)nk * R), Rr((size_t)R * R, 0.0);
+    for (int j = 0; j < R; ++j) {
+      for (int i = 0; i < nk; ++i) Q[(size_t)j * nk + i] = B[(size_t)sel[j] * nk + i];
+      for (int p = 0; p < j; ++p) {
+        double dp = 0.0;
+        for (int i = 0; i < nk; ++i) dp += Q[(size_t)p * nk + i] * Q[(size_t)j * nk + i];
+        Rr[(size_t)p * R + j] = dp;
+        for (int i = 0; i < nk; ++i) Q[(size_t)j * nk + i] -= dp * Q[(size_t)p * nk + i];
+      }
+      double nn = 0.0;
+      for (int i = 0; i < nk; ++i) nn += Q[(size_t)j * nk + i] * Q[(size_t)j * nk + i];
+      nn = std::sqrt(nn);
+      Rr[(size_t)j * R + j] = nn;
+      if (nn > 0)
+        for (int i = 0; i < nk; ++i) Q[(size_t)j * nk + i] /= nn;
+    }
+    T.assign((size_t)L * R, 0.f);
+    double err = 0.0;
+    std::vector<double> c(R);
+    for (int l = 0; l < L; ++l) {
+      for (int j = 0; j < R; ++j) {
+        double dp = 0.0;
+        for (int i = 0; i < nk; ++i) dp += Q[(size_t)j * nk + i] * B[(size_t)l * nk + i];
+        c[j] = dp;
+      }
+      for (int j = R - 1; j >= 0; --j) {  // back substitution R t = Q^T b
+        double v = c[j];
+        for (int p = j + 1; p < R; ++p) v -= Rr[(size_t)j * R + p] * c[p];
+        c[j] = Rr[(size_t)j * R + j] != 0 ? v / Rr[(size_t)j * R + j] : 0.0;
+      }
+      for (int j = 0; j < R; ++j) T[(size_t)l * R + j] = (float)c[j];
+      for (int i = 0; i < nk; ++i) {
+        double v = 0.0;
+        for (int j = 0; j < R; ++j) v += c[j] * B[(size_t)sel[j] * nk + i];
+        err = std::max(err, std::fabs(v - B[(size_t)l * nk + i]));
+      }
+    }
+    return err;
+  };
+  const double ec = solve(BC, tc);
+  const double es = solve(BS, ts);
+  return ec <= 10 * tol && es <= 10 * tol;
+}
 
 // Host binding in FP64: stencils, column grouping, ordering.
 void bind_host(swense_cells* c, const std::vector<double>& xyz, double lx, double ly, bool three,
@@ -391,7 +513,7 @@ void refresh(swense_hos* h, swense_cells* c, unsigned cm, CoefLayout* L) {
   *L = coef_layout(h, cm, c->gd.nl);
   const size_t nfl = std::max<size_t>(coef_floats(h, &c->gd, cm), 1);
   ensure_device(&c->coef, &c->coef_bytes, nfl * sizeof(float));
-  eval_coef(h, &c->gd, c->zdev, cm, reinterpret_cast<float*>(c->coef));
+  eval_coef(h, &c->gd, c->zdev, cm, reinterpret_cast<float*>(c->coef), c->skel.R > 0 ? &c->skel : nullptr);
 }
 
 unsigned coef_mask(unsigned mask, bool three) {
@@ -461,6 +583,26 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
       SW_HIP(hipMemcpy(c->pd.dwz, dwz.data(), n * 16, hipMemcpyHostToDevice));
       SW_HIP(hipMemcpy(c->pd.pz, pz.data(), n * 4, hipMemcpyHostToDevice));
     }
+    // skeleton heights for the coefficient grids
+    {
+      const double kx = M_PI * h->G.nx / h->G.lx, ky = three ? M_PI * h->G.ny / h->G.ly : 0.0;
+      std::vector<int> sel;
+      std::vector<float> tc, ts;
+      if (gd->nl >= 8 && build_skeleton(c->z, std::sqrt(kx * kx + ky * ky), h->G.depth, 1e-9, sel, tc, ts)) {
+        const int R = (int)sel.size(), L = gd->nl;
+        std::vector<double> zeta(R);
+        for (int j = 0; j < R; ++j) zeta[j] = c->z[sel[j]];
+        const size_t b0 = ((R * sizeof(double)) + 255) & ~size_t(255);
+        const size_t b1 = ((size_t)L * R * sizeof(float) + 255) & ~size_t(255);
+        SW_HIP(hipMalloc(&c->skel_mem, b0 + 2 * b1));
+        char* q = reinterpret_cast<char*>(c->skel_mem);
+        SW_HIP(hipMemcpy(q, zeta.data(), R * sizeof(double), hipMemcpyHostToDevice));
+        SW_HIP(hipMemcpy(q + b0, tc.data(), (size_t)L * R * sizeof(float), hipMemcpyHostToDevice));
+        SW_HIP(hipMemcpy(q + b0 + b1, ts.data(), (size_t)L * R * sizeof(float), hipMemcpyHostToDevice));
+        c->skel = Skel{R, reinterpret_cast<const double*>(q), reinterpret_cast<const float*>(q + b0),
+                       reinterpret_cast<const float*>(q + b0 + b1)};
+      }
+    }
     *out = c;
     return SWENSE_OK;
   });
@@ -524,6 +666,7 @@ void swense_cells_destroy(swense_cells* c) {
   if (!c) return;
   if (c->mem) (void)hipFree(c->mem);
   if (c->coef) (void)hipFree(c->coef);
+  if (c->skel_mem) (void)hipFree(c->skel_mem);
   delete c;
 }
 

@@ -160,6 +160,107 @@ __device__ void wave_fft(cpx<R>* buf, const WPlan& plan, int sign, int lane) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Compile-time-length version for powers of two (64 ... 4096): radix-16
+// passes with Ns = 1, 16, 256, then one radix 2/4/8/16 pass.  Every stride is
+// a constant, so the skewed LDS addresses reduce to one base register plus
+// immediate offsets.
+template <typename R, int N, int RAD, int NS>
+__device__ __forceinline__ void spass(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int lane) {
+  constexpr int NB = N / RAD;
+  constexpr int MB = (NB + 63) / 64;
+  constexpr int TWS = N / (NS * RAD);
+  static_assert(16 % RAD == 0 || RAD == 16, "radix must divide 16");
+  static_assert(NS == 1 || NS % 16 == 0, "pass stride must be 1 or a multiple of 16");
+  cpx<R> v[MB][RAD];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int j = lane + 64 * m;
+    if (NB % 64 == 0 || j < NB) {
+      if constexpr (NB % 16 == 0) {
+        constexpr int SB = NB + NB / 16;
+        const int b = sk(j);
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) v[m][r] = buf[b + r * SB];
+      } else {
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) v[m][r] = buf[sk(j + r * NB)];
+      }
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int j = lane + 64 * m;
+    if (NB % 64 == 0 || j < NB) {
+      const int k = j & (NS - 1);
+      if (NS > 1 && k > 0) {
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          cpx<R> w = tw[k * r * TWS];
+          if (sign > 0) w.y = -w.y;
+          v[m][r] = cmul(v[m][r], w);
+        }
+      }
+      dft_any<R, RAD>(v[m], sign);
+      const int o = (j - k) * RAD + k;
+      if constexpr (NS == 1) {
+        const int b = o + (o >> 4);
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) buf[b + r] = v[m][r];
+      } else {
+        constexpr int SS = NS + NS / 16;
+        const int b = sk(o);
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) buf[b + r * SS] = v[m][r];
+      }
+    }
+  }
+  wave_sync();
+}
+
+template <typename R, int N>
+__device__ __forceinline__ void wave_fft_static(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int lane) {
+  static_assert(N >= 64 && N <= 4096 && (N & (N - 1)) == 0, "power of two in [64, 4096]");
+  spass<R, N, 16, 1>(buf, tw, sign, lane);
+  if constexpr (N == 64) spass<R, N, 4, 16>(buf, tw, sign, lane);
+  else if constexpr (N == 128) spass<R, N, 8, 16>(buf, tw, sign, lane);
+  else {
+    spass<R, N, 16, 16>(buf, tw, sign, lane);
+    if constexpr (N == 512) spass<R, N, 2, 256>(buf, tw, sign, lane);
+    else if constexpr (N == 1024) spass<R, N, 4, 256>(buf, tw, sign, lane);
+    else if constexpr (N == 2048) spass<R, N, 8, 256>(buf, tw, sign, lane);
+    else if constexpr (N == 4096) spass<R, N, 16, 256>(buf, tw, sign, lane);
+  }
+}
+
+// Transform with compile-time length NS0 when NS0 > 0, else the runtime plan.
+template <typename R, int MAXE, int NS0>
+__device__ __forceinline__ void wave_fft_any(cpx<R>* buf, const WPlan& plan, int sign, int lane) {
+  if constexpr (NS0 > 0) wave_fft_static<R, NS0>(buf, reinterpret_cast<const cpx<R>*>(plan.tw), sign, lane);
+  else wave_fft<R, MAXE>(buf, plan, sign, lane);
+}
+
+// Host: choose (MAXE, N) template arguments for a length n.
+#define SW_FFT_DISPATCH(n, LAUNCH)          \
+  switch (n) {                              \
+    case 64: LAUNCH(8, 64); break;          \
+    case 128: LAUNCH(8, 128); break;        \
+    case 256: LAUNCH(8, 256); break;        \
+    case 512: LAUNCH(8, 512); break;        \
+    case 1024: LAUNCH(16, 1024); break;     \
+    case 2048: LAUNCH(32, 2048); break;     \
+    case 4096: LAUNCH(64, 4096); break;     \
+    default:                                \
+      switch (wave_maxe(n)) {               \
+        case 8: LAUNCH(8, 0); break;        \
+        case 16: LAUNCH(16, 0); break;      \
+        case 32: LAUNCH(32, 0); break;      \
+        case 48: LAUNCH(48, 0); break;      \
+        default: LAUNCH(64, 0); break;      \
+      }                                     \
+  }
+
 // Block index remapped so that the blocks resident on one XCD (blocks are
 // dealt round-robin over the 8 XCDs) process a contiguous range of tiles.
 __device__ __forceinline__ int xcd_tile(int b, int nblocks) {

@@ -71,7 +71,7 @@ __device__ __forceinline__ cd yinv_slot(const YInvJob& jb, const Geom& G, int Ly
 // Wavefront version: the calling wavefront transforms column p in its LDS
 // buffer (wbuf_len(Ly) complex, skewed index) and stores rows
 // (row0 + r) mod Ly, r < nrows.
-template <typename R, int MAXE>
+template <typename R, int MAXE, int NS0>
 __device__ __forceinline__ void yinv_wave(const YInvJob& jb, const Geom& G, const WPlan& plan, int nrows, int row0,
                                           int p, cpx<R>* buf, int lane) {
   const int Ly = plan.n;
@@ -80,7 +80,7 @@ __device__ __forceinline__ void yinv_wave(const YInvJob& jb, const Geom& G, cons
     buf[sk(s)] = mk((R)v.x, (R)v.y);
   }
   wave_sync();
-  wave_fft<R, MAXE>(buf, plan, +1, lane);
+  wave_fft_any<R, MAXE, NS0>(buf, plan, +1, lane);
   cpx<R>* dst = reinterpret_cast<cpx<R>*>(jb.dst);
   for (int r = lane; r < nrows; r += 64) {
     int y = row0 + r;
