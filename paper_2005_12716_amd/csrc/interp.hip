@@ -293,11 +293,12 @@ bool build_skeleton(const std::vector<double>& z, double kmax, double depth, dou
     const double inv = 1.0 / std::sqrt(best);
     std::vector<double> q(m);
     for (int i = 0; i < m; ++i) q[i] = Rm[(size_t)jb * m + i] * inv;
-    for (int l = 0; l < L; ++l) {
-      double dp = 0.0;
-      for (int i = 0; i < m; ++i) dp += q[i] * Rm[(size_t)l * m + i];
-      for (int i = 0; i < m; ++i) Rm[(size_t)l * m + i] -= dp * q[i];
-    }
+    for (int pass = 0; pass < 2; ++pass)  // deflate twice (orthogonality at this conditioning)
+      for (int l = 0; l < L; ++l) {
+        double dp = 0.0;
+        for (int i = 0; i < m; ++i) dp += q[i] * Rm[(size_t)l * m + i];
+        for (int i = 0; i < m; ++i) Rm[(size_t)l * m + i] -= dp * q[i];
+      }
   }
   const int R = (int)sel.size();
   if (R == 0 || 4 * R > 3 * L) return false;
@@ -307,12 +308,13 @@ bool build_skeleton(const std::vector<double>& z, double kmax, double depth, dou
     std::vector<double> Q((size_t)nk * R), Rr((size_t)R * R, 0.0);
     for (int j = 0; j < R; ++j) {
       for (int i = 0; i < nk; ++i) Q[(size_t)j * nk + i] = B[(size_t)sel[j] * nk + i];
-      for (int p = 0; p < j; ++p) {
-        double dp = 0.0;
-        for (int i = 0; i < nk; ++i) dp += Q[(size_t)p * nk + i] * Q[(size_t)j * nk + i];
-        Rr[(size_t)p * R + j] = dp;
-        for (int i = 0; i < nk; ++i) Q[(size_t)j * nk + i] -= dp * Q[(size_t)p * nk + i];
-      }
+      for (int pass = 0; pass < 2; ++pass)  // modified Gram-Schmidt, reorthogonalised
+        for (int p = 0; p < j; ++p) {
+          double dp = 0.0;
+          for (int i = 0; i < nk; ++i) dp += Q[(size_t)p * nk + i] * Q[(size_t)j * nk + i];
+          Rr[(size_t)p * R + j] += dp;
+          for (int i = 0; i < nk; ++i) Q[(size_t)j * nk + i] -= dp * Q[(size_t)p * nk + i];
+        }
       double nn = 0.0;
       for (int i = 0; i < nk; ++i) nn += Q[(size_t)j * nk + i] * Q[(size_t)j * nk + i];
       nn = std::sqrt(nn);
