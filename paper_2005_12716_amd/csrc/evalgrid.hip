@@ -183,8 +183,8 @@ __global__ void __launch_bounds__(256) k_xeval_surf(EvArgs A, Geom G, FftPlan pl
 }
 
 // x pass for interpolation coefficient grids, node-major layout: every
-// node's (layer, field) values are contiguous, coef[(r wx + xw) K + l Fv + f],
-// surface fields at l = L (offset L Fv + s).  Block (window row r, layer
+// node's (field, layer) values are contiguous, coef[(r wx + xw) K + f L + l],
+// surface fields at offset L Fv + s.  Block (window row r, layer
 // group g); the last group index holds the surface fields.
 template <typename R>
 __global__ void __launch_bounds__(256) k_xcoef(EvArgs A, Geom G, FftPlan plan, int LG, int K, float* coef) {
@@ -227,7 +227,8 @@ __global__ void __launch_bounds__(256) k_xcoef(EvArgs A, Geom G, FftPlan plan, i
   }
   for (int e = threadIdx.x; e < A.wx * nitems; e += blockDim.x) {
     const int xw = e / nitems, j = e - xw * nitems;
-    coef[((size_t)r * A.wx + xw) * K + base_off + j] = stage[e];
+    const int off = surf ? base_off + j : (j % Fv) * A.nl + l0 + j / Fv;
+    coef[((size_t)r * A.wx + xw) * K + off] = stage[e];
   }
 }
 
@@ -281,7 +282,8 @@ __global__ void __launch_bounds__(256) k_xcoef_w(EvArgs A, Geom G, WPlan plan, i
   __syncthreads();
   for (int e = threadIdx.x; e < A.wx * nitems; e += blockDim.x) {
     const int xw = e / nitems, j = e - xw * nitems;
-    coef[((size_t)r * A.wx + xw) * K + base_off + j] = stage[e];
+    const int off = surf ? base_off + j : (j % Fv) * A.nl + l0 + j / Fv;
+    coef[((size_t)r * A.wx + xw) * K + off] = stage[e];
   }
 }
 
@@ -337,7 +339,7 @@ __global__ void __launch_bounds__(256) k_xcoef_skel(EvArgs A, Geom G, WPlan plan
     const int xw = e / L, l = e - xw * L;
     float acc = 0.f;
     for (int j = 0; j < skl.R; ++j) acc += T[l * skl.R + j] * stage[j * A.wx + xw];
-    coef[((size_t)r * A.wx + xw) * K + (size_t)l * Fv + f] = acc;
+    coef[((size_t)r * A.wx + xw) * K + (size_t)f * L + l] = acc;
   }
 }
 

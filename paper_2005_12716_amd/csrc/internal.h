@@ -211,9 +211,10 @@ void set_error(swense_hos* h, const SwenseError& e);
 void eval_release(swense_hos* h);
 void check_grid_desc(const swense_hos* h, const swense_grid_desc* gd);
 void ensure_device(void** p, size_t* cap, size_t bytes);
-// Node-major coefficient grid: per window node K = nl fv + fs floats; idx[bit]
-// = field index (volume: 0..fv-1 at offset l fv + idx; surface: offset nl fv
-// + idx), -1 when the field is absent (also v, v_t in 2D, which are zero).
+// Node-major coefficient grid: per window node K = fv nl + fs floats, volume
+// field f at offsets f nl + l (its layers contiguous), surface field s at
+// fv nl + s; idx[bit] = field index, -1 when the field is absent (also v, v_t
+// in 2D, which are zero).
 struct CoefLayout {
   int fv, fs, nl, k;
   int idx[11];

@@ -104,9 +104,15 @@ __global__ void __launch_bounds__(256) k_gather_col(GatherArgs A, const Col* __r
     long long off[16];
     stencil(c, A, off);
     const int nb = A.three ? 4 : 1;
-    const int j0 = c.lmin * A.fv;
     for (int j = lane; j < nv + A.fs; j += 64) {
-      const int jj = j < nv ? j0 + j : A.nl * A.fv + (j - nv);
+      // column profile h[f nlc + (l - lmin)], then the surface fields
+      int jj;
+      if (j < nv) {
+        const int f = j / c.nlc;
+        jj = f * A.nl + c.lmin + (j - f * c.nlc);
+      } else {
+        jj = A.nl * A.fv + (j - nv);
+      }
       float acc = 0.f;
       for (int b = 0; b < nb; ++b) {
         float r = 0.f;
@@ -130,10 +136,10 @@ __global__ void __launch_bounds__(256) k_gather_col(GatherArgs A, const Col* __r
     }
     float wz[4];
     for (int a = 0; a < 4; ++a) wz[a] = pd.wz[(size_t)a * n + sp];
-    const int base = (l0 - c.lmin) * A.fv;
+    const int base = l0 - c.lmin;
     auto vol = [&](int f) {
-      return wz[0] * h[base + f] + wz[1] * h[base + A.fv + f] + wz[2] * h[base + 2 * A.fv + f] +
-             wz[3] * h[base + 3 * A.fv + f];
+      const float* hf = h + f * c.nlc + base;
+      return wz[0] * hf[0] + wz[1] * hf[1] + wz[2] * hf[2] + wz[3] * hf[3];
     };
     for (int o = 0; o < A.nout; ++o) {
       float v = 0.f;
@@ -175,14 +181,14 @@ __global__ void __launch_bounds__(256) k_div_col(GatherArgs A, const Col* __rest
     stencil(c, A, off);
     const int nb = A.three ? 4 : 1;
     for (int l = lane; l < c.nlc; l += 64) {
-      const int lay = (c.lmin + l) * A.fv;
+      const int lay = c.lmin + l;
       float hdx = 0.f, hw = 0.f;
       for (int b = 0; b < nb; ++b)
         for (int a = 0; a < 4; ++a) {
           const long long o = off[b * 4 + a] + lay;
-          hdx += wy[b] * dwx[a] * inv_dx * A.coef[o + A.c_u];
-          if (A.c_v >= 0) hdx += dwy[b] * wx[a] * inv_dy * A.coef[o + A.c_v];
-          hw += wy[b] * wx[a] * A.coef[o + A.c_w];
+          hdx += wy[b] * dwx[a] * inv_dx * A.coef[o + (long long)A.c_u * A.nl];
+          if (A.c_v >= 0) hdx += dwy[b] * wx[a] * inv_dy * A.coef[o + (long long)A.c_v * A.nl];
+          hw += wy[b] * wx[a] * A.coef[o + (long long)A.c_w * A.nl];
         }
       h[l] = hdx;
       h[c.nlc + l] = hw;
