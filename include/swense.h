@@ -190,6 +190,37 @@ int swense_interp_cells(swense_hos* h, swense_cells* c, unsigned mask, float* ou
  * dw/dz of the interpolant (device FP32 [n], caller order).  Asynchronous. */
 int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div);
 
+/* ---- batched realisations ---------------------------------------------- */
+
+typedef struct swense_batch swense_batch; /* many realisations, one captured graph (opaque) */
+
+/* Batch n independent realisations of any sizes: one swense_batch_run advances
+ * every hos[i] by nsteps RK4 steps and, where cells[i] is non-NULL,
+ * interpolates masks[i] (NULL: all fields) into the device buffer outs[i]
+ * ([F][n_i] FP32).  The whole batch is captured once as a HIP graph whose
+ * branches (realisations spread over K worker streams) run concurrently;
+ * replays record nothing new.  Creation runs the work once eagerly to size
+ * every workspace and then restores the states, so the realisations are
+ * unchanged when it returns.  stream: the stream graph launches go to.
+ * The handles must stay alive and must not be used concurrently with the
+ * batch.  (Batched execution of uneven realisations; no passage of the paper
+ * - the paper runs one wave model.) */
+int swense_batch_create(swense_hos* const* hos, swense_cells* const* cells, const unsigned* masks,
+                        float* const* outs, int n, int nsteps, void* stream, swense_batch** out);
+
+/* One graph launch (asynchronous on the batch stream). */
+int swense_batch_run(swense_batch* b);
+
+/* Choose K (concurrent branches) by timing candidate graphs with HIP events,
+ * or take it from the JSON cache file `cache_path` (may be NULL) keyed by the
+ * GPU architecture and the batch's shapes; stores new choices there.  States
+ * are restored after timing.  *chosen: K; *best_ms: measured ms per launch
+ * (-1 when taken from the cache). */
+int swense_batch_autotune(swense_batch* b, const char* cache_path, int* chosen, double* best_ms);
+
+const char* swense_batch_last_error(const swense_batch* b);
+void swense_batch_destroy(swense_batch* b);
+
 /* ---- per-kernel timing -------------------------------------------------- */
 
 /* Kernel classes timed by the profiler. */

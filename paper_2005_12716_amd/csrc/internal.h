@@ -194,9 +194,16 @@ struct ProfScope {
 template <typename... KArgs, typename... Args>
 void sw_launch(swense_hos* h, int kid, void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds, hipStream_t st,
                Args... args) {
-  if (lds > 65536)
-    SW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
+  if (lds > 65536) {
+    // once per kernel and size, so that graph capture records launches only
+    static thread_local std::map<const void*, size_t> done;
+    const void* key = reinterpret_cast<const void*>(kernel);
+    auto it = done.find(key);
+    if (it == done.end() || it->second < lds) {
+      SW_HIP(hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      done[key] = lds;
+    }
+  }
   ProfScope ps(h, kid);
   hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
   SW_HIP(hipGetLastError());

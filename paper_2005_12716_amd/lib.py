@@ -76,6 +76,12 @@ def load():
         "swense_interp_divergence": (C.c_int, [vp, vp, fp]),
         "swense_profile_enable": (C.c_int, [vp, C.c_int]),
         "swense_profile_read": (C.c_int, [vp, C.c_int, dp, C.POINTER(C.c_longlong)]),
+        "swense_batch_create": (C.c_int, [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_uint), C.POINTER(vp),
+                                          C.c_int, C.c_int, vp, C.POINTER(vp)]),
+        "swense_batch_run": (C.c_int, [vp]),
+        "swense_batch_autotune": (C.c_int, [vp, C.c_char_p, C.POINTER(C.c_int), dp]),
+        "swense_batch_last_error": (C.c_char_p, [vp]),
+        "swense_batch_destroy": (None, [vp]),
         "swense_hos_destroy": (None, [vp]),
         "swense_cells_destroy": (None, [vp]),
     }
@@ -91,7 +97,8 @@ EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swens
             "swense_hos_set_state", "swense_hos_step", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
             "swense_cells_bind", "swense_interp_cells", "swense_interp_divergence", "swense_profile_enable",
-            "swense_profile_read", "swense_hos_destroy",
+            "swense_profile_read", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
+            "swense_batch_last_error", "swense_batch_destroy", "swense_hos_destroy",
             "swense_cells_destroy"]
 
 
@@ -264,6 +271,51 @@ class Cells:
         if getattr(self, "c", None):
             self.hos.L.swense_cells_destroy(self.c)
             self.c = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many realisations advanced (and interpolated) by one graph launch."""
+
+    def __init__(self, hoses, cells=None, masks=None, outs=None, nsteps=1, stream=None):
+        self.L = load()
+        n = len(hoses)
+        self.hoses, self.cells_list, self.outs = list(hoses), cells, outs
+        H = (C.c_void_p * n)(*[h.h for h in hoses])
+        Cc = (C.c_void_p * n)(*[(c.c if c is not None else None) for c in cells]) if cells else None
+        Mm = (C.c_uint * n)(*masks) if masks else None
+        Oo = (C.c_void_p * n)(*[(o.data_ptr() if o is not None else None) for o in outs]) if outs else None
+        st = stream if stream is not None else torch.cuda.current_stream()
+        b = C.c_void_p()
+        rc = self.L.swense_batch_create(H, Cc, Mm, Oo, n, nsteps, C.c_void_p(st.cuda_stream), C.byref(b))
+        if rc != OK:
+            raise SwenseError(rc, "batch_create")
+        self.b = b
+
+    def _check(self, rc, what):
+        if rc != OK:
+            msg = self.L.swense_batch_last_error(self.b)
+            raise SwenseError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def run(self):
+        self._check(self.L.swense_batch_run(self.b), "batch_run")
+
+    def autotune(self, cache_path=None):
+        k = C.c_int()
+        ms = C.c_double()
+        self._check(self.L.swense_batch_autotune(self.b, cache_path.encode() if cache_path else None,
+                                                 C.byref(k), C.byref(ms)), "batch_autotune")
+        return k.value, ms.value
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.L.swense_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:
