@@ -51,6 +51,68 @@ def workload():
     return pts, (gx, gy, ix0, iy0, wx, wy), np.asarray(zl), phases
 
 
+def batched_setup(lib, torch, pts_scale=1.0, fields=None):
+    """The batched configuration: 64 seeded JONSWAP realisations with mode
+    grids uniform over the even 5-smooth sizes in [128, 512] per axis,
+    Hs/lambda_p ~ U[0.01, 0.03], M = 3, each interpolated (n = 4 window, 32
+    layers) to 100k..1M box-cloud points clustered toward z = 0."""
+    import numpy as np
+    import synth
+    reals = synth.batch_realisations(3)
+    hoses, cells, outs, npts = [], [], [], 0
+    mask = lib.ALL_FIELDS if fields is None else fields
+    nf = bin(mask).count("1")
+    for r in reals:
+        nx, ny = r["nx"], r["ny"]
+        lx, ly = nx * LAM / 12.8, ny * LAM / 12.8
+        hs = r["hs_over_lambda"] * LAM
+        d = lib.hos_desc(3, nx, ny, lx, ly, -1.0, order_m=M, dt=LAM / 64)
+        eh, ph = lib.sea_spectrum(d, kind=0, hs=hs, kp=1.0, gamma=3.3,
+                                  phases=synth.mode_phases(r["phase_seed"], ny, nx // 2 + 1))
+        h = lib.Hos(d, eh, ph)
+        n = max(1000, int(r["npts"] * pts_scale))
+        x0, y0 = lx / 2 - 2 * LAM, ly / 2 - 2 * LAM
+        p = synth.box_cloud(r["phase_seed"], n, x0, y0, 4 * LAM, 4 * LAM, -0.5 * LAM, 0.1 * LAM)
+        gx, gy = 4 * nx, 4 * ny
+        dx, dy = lx / gx, ly / gy
+        ix0, iy0 = int(math.floor(x0 / dx)) - 2, int(math.floor(y0 / dy)) - 2
+        wx, wy = int(math.ceil(4 * LAM / dx)) + 6, int(math.ceil(4 * LAM / dy)) + 6
+        zl = synth.clustered_layers(-0.5 * LAM - 1e-9, 0.1 * LAM + 1e-9, 32, 0.01 * LAM)
+        gd = lib.grid_desc(gx, gy, zl, (ix0, iy0, wx, wy))
+        c = h.bind(gd, torch.tensor(p, device="cuda"))
+        hoses.append(h)
+        cells.append(c)
+        outs.append(torch.empty((nf, n), dtype=torch.float32, device="cuda"))
+        npts += n
+    return hoses, cells, outs, npts, mask, nf
+
+
+def run_batched(lib, torch, steps):
+    import tempfile
+    hoses, cells, outs, npts, mask, nf = batched_setup(lib, torch)
+    b = lib.Batch(hoses, cells, [mask] * len(hoses), outs, nsteps=1)
+    with tempfile.TemporaryDirectory() as td:
+        k, tune_ms = b.autotune(os.path.join(td, "tune.json"))
+    b.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        b.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res = {"realisations": len(hoses), "points": npts, "branches": k, "ms_per_launch": ms,
+           "realisation_steps_per_s": len(hoses) * 1e3 / ms,
+           "cell_field_pts_per_s": npts * nf * 1e3 / ms}
+    b.close()
+    for c in cells:
+        c.close()
+    for h in hoses:
+        h.close()
+    return res
+
+
 def algorithmic_bytes(kind, ctx):
     """Compulsory HBM bytes per launch of a kernel class (inputs read once,
     outputs written once), as listed in the design notes."""
@@ -124,6 +186,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the workload is a single "
@@ -228,13 +291,17 @@ def main():
         "roofline": roof,
         "kernels": breakdown,
     }
+    cells.close()
+    h.close()
+    if not args.no_batched:
+        print("# batched configuration", file=sys.stderr, flush=True)
+        res["batched"] = run_batched(lib, torch, max(2, args.steps // 4))
+        print(f"# batched {res['batched']['ms_per_launch']:.2f} ms per launch", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(pts, win, zl, phases)
         res["cpu_baseline"] = cb
         res["speedup_vs_cpu_baseline"] = res["value"] / cb["value"]
         res["hos_speedup_vs_cpu_baseline"] = res["hos_steps_per_s"] / cb["hos_steps_per_s"]
-    cells.close()
-    h.close()
     print(json.dumps(res))
 
 

@@ -250,6 +250,11 @@ class Cells:
         hos._check(rc, "cells_bind")
         self.c = c
         self.gd = gd
+        self._xyz = xyz
+
+    @property
+    def xyz_host(self):
+        return self._xyz.cpu().numpy()
 
     def interp(self, mask, out=None, count=True):
         nf = bin(mask).count("1")

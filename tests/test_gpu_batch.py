@@ -94,3 +94,52 @@ def test_batch_autotune_and_cache(gpu_lib, tmp_path):
     b.close()
     for it in items:
         it[3].close()
+
+
+def test_batched_configuration_recipe_sampled(gpu_lib):
+    """The 64-realisation batched recipe (mode grids over the even 5-smooth
+    sizes in [128, 512], Hs/lambda_p in [0.01, 0.03], n = 4 windows, 32
+    layers) with the point counts scaled down: one graph launch of one step
+    each, sampled against the oracle (states of 6 realisations, fields of the
+    2 smallest at 300 points each)."""
+    import bench
+    from oracle import reconstruct as rc
+    from paper_2005_12716_amd import lib
+    hoses, cells, outs, npts, mask, nf = bench.batched_setup(lib, torch, pts_scale=0.01)
+    assert len(hoses) == 64
+    inits = [h.state() for h in hoses]
+    b = lib.Batch(hoses, cells, [mask] * 64, outs, nsteps=1)
+    b.run()
+    torch.cuda.synchronize()
+    sizes = [(h.desc.nx * h.desc.ny, i) for i, h in enumerate(hoses)]
+    check = [i for _, i in sorted(sizes)[:4]] + [i for _, i in sorted(sizes)[-2:]]
+    for i in check:
+        h = hoses[i]
+        d = h.desc
+        g = Grid(nx=d.nx, ny=d.ny, lx=d.lx, ly=d.ly, depth=-1.0, order_m=3)
+        er, pr = hos.run(g, inits[i][0], inits[i][1], d.dt, 1)
+        e, p, _ = h.state()
+        assert np.linalg.norm(e - er) / np.linalg.norm(er) < 1e-6
+    for i in check[:2]:
+        h, c, out = hoses[i], cells[i], outs[i].cpu().numpy()
+        d = h.desc
+        g = Grid(nx=d.nx, ny=d.ny, lx=d.lx, ly=d.ly, depth=-1.0, order_m=3)
+        e, p, _ = h.state()
+        A = hos.mean_level_modes(g, e, p)
+        At, eth = hos.mean_level_modes_t(g, e, p)
+        gd = c.gd
+        zl = np.ctypeslib.as_array(gd.z, shape=(gd.nl,)).copy()
+        win = (gd.ix0, gd.iy0, gd.wx, gd.wy)
+        coef = rc.eval_grid(g, A, At, e, eth, gd.gx, gd.gy, zl, [f for f in range(11) if f != rc.P],
+                            prefilter=True, window=win)
+        pts = c.xyz_host
+        sel = np.arange(0, pts.shape[1], max(1, pts.shape[1] // 300))
+        ref, nb = rc.interp_points(g, coef, zl, gd.gx, gd.gy, win, pts[:, sel], list(range(11)))
+        assert nb == 0
+        for f in range(11):
+            assert np.linalg.norm(out[f, sel] - ref[f]) <= 1e-5 * np.linalg.norm(ref[f]), f
+    b.close()
+    for c in cells:
+        c.close()
+    for h in hoses:
+        h.close()
