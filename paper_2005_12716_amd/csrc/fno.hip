@@ -1,0 +1,1028 @@
+// Spectral neural operator surrogate on gfx950: BF16 MFMA GEMMs with FP32
+// accumulation for every channel contraction (lift, 1x1 convolutions,
+// per-mode complex mixing, projection, and their transposes in the backward
+// pass), FP32 wavefront FFTs for the truncated spectral transforms, FP32
+// element-wise kernels, and an Adam optimiser on FP32 master weights that
+// re-quantises the BF16 copy used by the GEMMs after every step.
+//
+// Network (per sample, grid n x n, C channels):
+//   v0 = W0 x + b0;  for l = 1..L: z = W_l v + b_l + K_l(v), v = gelu(z);
+//   y = Q2 gelu(Q1 v + c1) + c2.
+//   K_l(v): rfft2(v)/n^2 on the retained modes S = {p < P, |q| <= Q}, per-mode
+//   complex mixing by R_l (C x C), Hermitian projection of the p = 0 column,
+//   inverse real transform sum_S c_p Re(y e^{ik.x}).
+// BF16 rounding (round to nearest even) happens at every GEMM input.
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+#include "swense_surrogate.h"
+#include "wfft.h"
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  unsigned int b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (unsigned short)(b >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+// ------------------------------------------------------------------ GEMM
+// C[b](m, n) = alpha sum_k A[b](m, k) B[b](k, n) + beta C[b](m, n) + bias[m]
+// Operands FP32 or BF16 with arbitrary strides; batch index b = b1 nb2 + b2
+// with separate strides for the two levels (split-K and per-sample batches).
+// Complex mode: A holds interleaved complex rows (real K' = 2K), B holds a
+// complex K x N matrix expanded on load to the real 2K x 2N block form
+// [[Re, Im], [-Im, Re]], C receives interleaved complex; conjugation flags
+// apply before the expansion.
+struct GemmArgs {
+  int M, N, K;        // real sizes (complex mode: K, N are the real 2K, 2N)
+  int nb1, nb2;
+  const void* A;
+  long long sAb1, sAb2, sAm, sAk;
+  int a_bf16, a_conj;  // a_conj: complex A (interleaved): negate odd k
+  const void* B;
+  long long sBb1, sBb2, sBk, sBn;  // complex mode: strides of the complex matrix
+  int b_bf16, b_cplx, b_conj;
+  float* C;
+  long long sCb1, sCb2, sCm, sCn;
+  float alpha, beta;
+  const float* bias;
+};
+
+constexpr int TM = 64, TN = 64, TK = 32;
+
+__device__ __forceinline__ float ld(const void* p, long long i, int bf) {
+  return bf ? bf2f(reinterpret_cast<const unsigned short*>(p)[i]) : reinterpret_cast<const float*>(p)[i];
+}
+
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+  __shared__ unsigned short As[TM][TK + 4];  // [m][k]
+  __shared__ unsigned short Bs[TN][TK + 4];  // [n][k]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tiles_n = (g.N + TN - 1) / TN;
+  const int m0 = (blockIdx.x / tiles_n) * TM, n0 = (blockIdx.x % tiles_n) * TN;
+  const int b = blockIdx.y;
+  const int b1 = b / g.nb2, b2 = b - b1 * g.nb2;
+  const long long aoff = b1 * g.sAb1 + b2 * g.sAb2;
+  const long long boff = b1 * g.sBb1 + b2 * g.sBb2;
+  const long long coff = b1 * g.sCb1 + b2 * g.sCb2;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  const bool a_kfast = g.sAk == 1;
+  const bool b_nfast = !g.b_cplx && g.sBn == 1;
+  for (int k0 = 0; k0 < g.K; k0 += TK) {
+    // A tile
+    for (int e = tid; e < TM * TK; e += 256) {
+      int m, k;
+      if (a_kfast) { m = e / TK; k = e - m * TK; }
+      else { k = e / TM; m = e - k * TM; }
+      const int gm = m0 + m, gk = k0 + k;
+      float v = 0.f;
+      if (gm < g.M && gk < g.K) {
+        v = ld(g.A, aoff + gm * g.sAm + gk * g.sAk, g.a_bf16);
+        if (g.a_conj && (gk & 1)) v = -v;
+      }
+      As[m][k] = f2bf(v);
+    }
+    // B tile (stored [n][k])
+    for (int e = tid; e < TN * TK; e += 256) {
+      int n, k;
+      if (b_nfast) { k = e / TN; n = e - k * TN; }
+      else { n = e / TK; k = e - n * TK; }
+      const int gn = n0 + n, gk = k0 + k;
+      float v = 0.f;
+      if (gn < g.N && gk < g.K) {
+        if (g.b_cplx) {
+          // real block form of a complex matrix: (gk, gn) -> complex (gk/2, gn/2)
+          const long long base = boff + (long long)(gk >> 1) * g.sBk + (long long)(gn >> 1) * g.sBn;
+          const float re = ld(g.B, 2 * base, g.b_bf16);
+          float im = ld(g.B, 2 * base + 1, g.b_bf16);
+          if (g.b_conj) im = -im;
+          const int rk = gk & 1, rn = gn & 1;
+          v = (rk == rn) ? re : (rk == 0 ? im : -im);
+        } else {
+          v = ld(g.B, boff + gk * g.sBk + gn * g.sBn, g.b_bf16);
+        }
+      }
+      Bs[n][k] = f2bf(v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 16) {
+      const int kq = kk + 4 * (lane >> 4);
+      v4s af[2], bfr[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = wm + 16 * i + (lane & 15);
+        af[i] = v4s{(short)As[r][kq], (short)As[r][kq + 1], (short)As[r][kq + 2], (short)As[r][kq + 3]};
+        const int c = wn + 16 * i + (lane & 15);
+        bfr[i] = v4s{(short)Bs[c][kq], (short)Bs[c][kq + 1], (short)Bs[c][kq + 2], (short)Bs[c][kq + 3]};
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        const int gn = n0 + wn + 16 * j + (lane & 15);
+        if (gm < g.M && gn < g.N) {
+          float* cp = g.C + coff + gm * g.sCm + gn * g.sCn;
+          float v = g.alpha * acc[i][j][r];
+          if (g.beta != 0.f) v += g.beta * *cp;
+          if (g.bias) v += g.bias[gm];
+          *cp = v;
+        }
+      }
+}
+
+// sum over split-K partials: out[i] = beta out[i] + sum_c part[c][i]
+__global__ void k_reduce_parts(const float* __restrict__ part, int nparts, long long n, float* out, float beta) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int c = 0; c < nparts; ++c) s += part[(long long)c * n + i];
+  out[i] = (beta != 0.f ? beta * out[i] : 0.f) + s;
+}
+
+// ------------------------------------------------------------------ spectral transforms
+// Forward: v [B][C][n][n] -> U [B][S][C] complex, S = (qi, p) retained modes
+// in q-major order (q = 0..Q, -Q..-1), p < P.  x pass: one wavefront per
+// (b, channel pair, row): real transform of two channels packed as one
+// complex sequence, keep p < P; y pass: one wavefront per (b, c, p).
+struct FnoDims {
+  int n, C, P, Q, B;
+};
+
+__device__ __forceinline__ int nq_of(const FnoDims& d) { return 2 * d.Q + 1; }
+
+template <int N>
+__global__ void __launch_bounds__(256) k_fno_fx(const float* __restrict__ v, cf* __restrict__ xi, FnoDims d,
+                                                WPlan plan) {
+  extern __shared__ unsigned char smem[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rows_per_block = 4;
+  const int ncp = d.C / 2;
+  const int job = blockIdx.x * rows_per_block + wave;  // (b, cpair, row)
+  const int row = job % N;
+  const int cp = (job / N) % ncp;
+  const int b = job / (N * ncp);
+  if (b >= d.B) return;
+  cf* buf = reinterpret_cast<cf*>(smem) + (size_t)wave * wbuf_len(N);
+  const float* a = v + (((size_t)b * d.C + 2 * cp) * N + row) * N;
+  const float* c = a + (size_t)N * N;
+  for (int x = lane; x < N; x += 64) buf[sk(x)] = mk(a[x], c[x]);
+  wave_sync();
+  wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N>(buf, plan, -1, lane);
+  const float sc = 0.5f;
+  for (int p = lane; p < d.P; p += 64) {
+    const cf zp = buf[sk(p)], zm = conjg(buf[sk((N - p) % N)]);
+    const cf s = zp + zm, t = zp - zm;
+    const cf o0 = cscale(s, sc), o1 = mk(t.y * sc, -t.x * sc);
+    xi[(((size_t)b * d.C + 2 * cp) * N + row) * d.P + p] = o0;
+    xi[(((size_t)b * d.C + 2 * cp + 1) * N + row) * d.P + p] = o1;
+  }
+}
+
+// y pass forward: U[b][s][c] = scale * (cp_flag ? c_p : 1) * F_y(xi[b][c][:, p])[q]
+template <int N>
+__global__ void __launch_bounds__(256) k_fno_fy(const cf* __restrict__ xi, cf* __restrict__ U, FnoDims d, WPlan plan,
+                                                float scale, int cp_flag) {
+  extern __shared__ unsigned char smem[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int job = blockIdx.x * 4 + wave;  // (b, c, p)
+  const int p = job % d.P, c = (job / d.P) % d.C, b = job / (d.P * d.C);
+  if (b >= d.B) return;
+  cf* buf = reinterpret_cast<cf*>(smem) + (size_t)wave * wbuf_len(N);
+  const cf* src = xi + ((size_t)b * d.C + c) * N * d.P + p;
+  for (int y = lane; y < N; y += 64) buf[sk(y)] = src[(size_t)y * d.P];
+  wave_sync();
+  wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N>(buf, plan, -1, lane);
+  const float s = scale * ((cp_flag && p > 0) ? 2.f : 1.f);
+  const int nq = nq_of(d);
+  for (int a = lane; a < nq; a += 64) {
+    const int q = a <= d.Q ? a : a - nq;  // retained order 0..Q, -Q..-1
+    const int slot = (q + N) % N;
+    U[((size_t)b * nq * d.P + (size_t)a * d.P + p) * d.C + c] = cscale(buf[sk(slot)], s);
+  }
+}
+
+// Hermitian projection of the p = 0 column of Y [B][S][C] (in place) with an
+// optional division by c_p of the p > 0 modes first.
+__global__ void k_fno_herm(cf* Y, FnoDims d, int div_cp) {
+  const int nq = nq_of(d);
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)d.B * d.C * nq * d.P) return;
+  // element (b, a, p, c)
+  const int c = (int)(i % d.C);
+  const int p = (int)((i / d.C) % d.P);
+  const int a = (int)((i / ((long long)d.C * d.P)) % nq);
+  const int b = (int)(i / ((long long)d.C * d.P * nq));
+  cf* e = Y + (((size_t)b * nq + a) * d.P + p) * d.C + c;
+  if (p > 0) {
+    if (div_cp) *e = cscale(*e, 0.5f);
+    return;
+  }
+  if (a == 0) {
+    e->y = 0.f;
+    return;
+  }
+  if (a > d.Q) return;  // the -q partner is written by the +q thread
+  const int am = nq - a;  // position of -q
+  cf* f = Y + (((size_t)b * nq + am) * d.P + 0) * d.C + c;
+  const cf x = *e, y = *f;
+  const cf avg = mk(0.5f * (x.x + y.x), 0.5f * (x.y - y.y));
+  *e = avg;
+  *f = conjg(avg);
+}
+
+// y pass inverse: xi[b][c][row][p] = F_y^-1 of the retained q values of Y[b][:, p][c]
+template <int N>
+__global__ void __launch_bounds__(256) k_fno_iy(const cf* __restrict__ Y, cf* __restrict__ xi, FnoDims d,
+                                                WPlan plan) {
+  extern __shared__ unsigned char smem[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int job = blockIdx.x * 4 + wave;
+  const int p = job % d.P, c = (job / d.P) % d.C, b = job / (d.P * d.C);
+  if (b >= d.B) return;
+  cf* buf = reinterpret_cast<cf*>(smem) + (size_t)wave * wbuf_len(N);
+  const int nq = nq_of(d);
+  for (int y = lane; y < N; y += 64) buf[sk(y)] = mk(0.f, 0.f);
+  wave_sync();
+  for (int a = lane; a < nq; a += 64) {
+    const int q = a <= d.Q ? a : a - nq;
+    buf[sk((q + N) % N)] = Y[((size_t)b * nq * d.P + (size_t)a * d.P + p) * d.C + c];
+  }
+  wave_sync();
+  wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N>(buf, plan, +1, lane);
+  cf* dst = xi + ((size_t)b * d.C + c) * N * d.P + p;
+  for (int y = lane; y < N; y += 64) dst[(size_t)y * d.P] = buf[sk(y)];
+}
+
+// x pass inverse: out[b][c][row][x] = scale * sum_p c_p Re(xi[..][p] e^{i p x})
+// (two channels per complex transform); beta: out = beta out + that.
+template <int N>
+__global__ void __launch_bounds__(256) k_fno_ix(const cf* __restrict__ xi, float* __restrict__ out, FnoDims d,
+                                                WPlan plan, float scale, float beta) {
+  extern __shared__ unsigned char smem[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ncp = d.C / 2;
+  const int job = blockIdx.x * 4 + wave;
+  const int row = job % N, cp = (job / N) % ncp, b = job / (N * ncp);
+  if (b >= d.B) return;
+  cf* buf = reinterpret_cast<cf*>(smem) + (size_t)wave * wbuf_len(N);
+  const cf* ra = xi + (((size_t)b * d.C + 2 * cp) * N + row) * d.P;
+  const cf* rb = xi + (((size_t)b * d.C + 2 * cp + 1) * N + row) * d.P;
+  for (int s = lane; s < N; s += 64) {
+    cf z = mk(0.f, 0.f);
+    int p = -1;
+    bool cj = false;
+    if (s < d.P) p = s;
+    else if (s > N - d.P) { p = N - s; cj = true; }
+    if (p >= 0) {
+      cf va = ra[p], vb = rb[p];
+      if (cj) { va = conjg(va); vb = conjg(vb); }
+      if (p == 0) { va.y = 0.f; vb.y = 0.f; }  // the p = 0 column transforms to real values
+      z = mk(va.x - vb.y, va.y + vb.x);
+    }
+    buf[sk(s)] = z;
+  }
+  wave_sync();
+  wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N>(buf, plan, +1, lane);
+  float* oa = out + (((size_t)b * d.C + 2 * cp) * N + row) * N;
+  float* ob = oa + (size_t)N * N;
+  for (int x = lane; x < N; x += 64) {
+    const cf z = buf[sk(x)];
+    oa[x] = (beta != 0.f ? beta * oa[x] : 0.f) + scale * z.x;
+    ob[x] = (beta != 0.f ? beta * ob[x] : 0.f) + scale * z.y;
+  }
+}
+
+// ------------------------------------------------------------------ element-wise
+__device__ __forceinline__ float gelu_f(float z) {
+  const float k = 0.7978845608028654f;
+  return 0.5f * z * (1.f + tanhf(k * (z + 0.044715f * z * z * z)));
+}
+__device__ __forceinline__ float gelu_g(float z) {
+  const float k = 0.7978845608028654f;
+  const float t = tanhf(k * (z + 0.044715f * z * z * z));
+  return 0.5f * (1.f + t) + 0.5f * z * (1.f - t * t) * k * (1.f + 3.f * 0.044715f * z * z);
+}
+
+// z = a + bias[c] + s (s may be null), v = gelu(z) (act) or z
+__global__ void k_fno_act(const float* a, const float* bias, const float* s, float* z, float* v, long long n,
+                          int chans, long long plane, int act) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = (int)((i / plane) % chans);
+  float t = a[i] + (bias ? bias[c] : 0.f) + (s ? s[i] : 0.f);
+  if (z) z[i] = t;
+  v[i] = act ? gelu_f(t) : t;
+}
+
+__global__ void k_fno_gelu_back(const float* gv, const float* z, float* gz, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) gz[i] = gv[i] * gelu_g(z[i]);
+}
+
+// per-channel sums over (b, points): gb[c] = sum g[b][c][pts]
+__global__ void __launch_bounds__(256) k_fno_bias_grad(const float* g, float* gb, int B, int chans, long long plane) {
+  const int c = blockIdx.x;
+  float s = 0.f;
+  for (int b = 0; b < B; ++b) {
+    const float* p = g + ((size_t)b * chans + c) * plane;
+    for (long long i = threadIdx.x; i < plane; i += blockDim.x) s += p[i];
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gb[c] = red[0];
+}
+
+// relative L2 per (b, channel): sums of d^2 and t^2 per plane
+__global__ void __launch_bounds__(256) k_fno_loss_sums(const float* y, const float* t, float* sums, long long plane) {
+  const int bc = blockIdx.x;
+  const float* py = y + (size_t)bc * plane;
+  const float* pt = t + (size_t)bc * plane;
+  float dd = 0.f, tt = 0.f;
+  for (long long i = threadIdx.x; i < plane; i += blockDim.x) {
+    const float d = py[i] - pt[i];
+    dd += d * d;
+    tt += pt[i] * pt[i];
+  }
+  __shared__ float r1[256], r2[256];
+  r1[threadIdx.x] = dd;
+  r2[threadIdx.x] = tt;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      r1[threadIdx.x] += r1[threadIdx.x + w];
+      r2[threadIdx.x] += r2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sums[2 * bc] = r1[0];
+    sums[2 * bc + 1] = r2[0];
+  }
+}
+
+__global__ void k_fno_loss_grad(const float* y, const float* t, const float* sums, float* gy, long long plane,
+                                long long n, float inv_count) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int bc = (int)(i / plane);
+  gy[i] = 2.f * (y[i] - t[i]) / sums[2 * bc + 1] * inv_count;
+}
+
+// Adam on FP32 masters; the BF16 copy read by the GEMMs is refreshed.
+__global__ void k_adam(float* w, unsigned short* wb, const float* g, float* m, float* v, long long n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  wb[i] = f2bf(wi);
+}
+
+__global__ void k_to_bf16(const float* w, unsigned short* wb, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) wb[i] = f2bf(w[i]);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host
+struct swense_fno {
+  swense_fno_desc d{};
+  hipStream_t st = nullptr;
+  std::string err;
+  TwiddleCache tw;
+  WPlan plan{};
+  size_t nparam = 0;
+  // parameter offsets (floats) in the packed vector
+  size_t oW0, ob0, oQ1, oc1, oQ2, oc2;
+  std::vector<size_t> oW, ob, oR;
+  float* w = nullptr;            // FP32 master
+  unsigned short* wb = nullptr;  // BF16 copy
+  float* g = nullptr;            // gradients
+  float* am = nullptr;           // Adam moments
+  float* av = nullptr;
+  long long adam_t = 0;
+  // activations for up to max_batch samples
+  int maxb = 0;
+  float* act = nullptr;  // v_0 .. v_L, z_1 .. z_L, zq, h  (each [B][C or H][n][n])
+  float* tmp = nullptr;  // scratch [B][H][n][n] x 2
+  cf* xi = nullptr;      // [B][C][n][P]
+  cf* U = nullptr;       // per layer [B][S][C]
+  cf* Y = nullptr;       // [B][S][C]
+  float* part = nullptr; // split-K partials
+  float* sums = nullptr;
+  int last_batch = 0;
+  void* mem = nullptr;
+};
+
+namespace {
+
+size_t count_params(const swense_fno_desc& d) {
+  const size_t C = d.channels, H = d.hidden, S = (size_t)(2 * d.q_modes + 1) * d.p_modes;
+  return C * 2 + C + (size_t)d.layers * (C * C + C + S * C * C * 2) + H * C + H + 2 * H + 2;
+}
+
+void layout(swense_fno* f) {
+  const auto& d = f->d;
+  const size_t C = d.channels, H = d.hidden, S = (size_t)(2 * d.q_modes + 1) * d.p_modes;
+  size_t o = 0;
+  f->oW0 = o; o += C * 2;
+  f->ob0 = o; o += C;
+  for (int l = 0; l < d.layers; ++l) {
+    f->oW.push_back(o); o += C * C;
+    f->ob.push_back(o); o += C;
+    f->oR.push_back(o); o += S * C * C * 2;
+  }
+  f->oQ1 = o; o += H * C;
+  f->oc1 = o; o += H;
+  f->oQ2 = o; o += 2 * H;
+  f->oc2 = o; o += 2;
+  f->nparam = o;
+}
+
+void launch_gemm(hipStream_t st, const GemmArgs& g) {
+  const int tiles = ((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN);
+  hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles, g.nb1 * g.nb2), dim3(256), 0, st, g);
+  SW_HIP(hipGetLastError());
+}
+
+GemmArgs gemm0() {
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.nb1 = g.nb2 = 1;
+  g.alpha = 1.f;
+  return g;
+}
+
+// out[b][o][pt] = sum_i W[o][i] in[b][i][pt] (+ bias), W BF16 [o][i]
+void conv1x1(swense_fno* f, const unsigned short* W, int cout, int cin, const float* in, float* out, int B,
+             const float* bias) {
+  const long long plane = (long long)f->d.n * f->d.n;
+  GemmArgs g = gemm0();
+  g.M = cout;
+  g.N = (int)plane;
+  g.K = cin;
+  g.nb1 = B;
+  g.A = W;
+  g.sAm = cin;
+  g.sAk = 1;
+  g.a_bf16 = 1;
+  g.B = in;
+  g.sBb1 = (long long)cin * plane;
+  g.sBk = plane;
+  g.sBn = 1;
+  g.C = out;
+  g.sCb1 = (long long)cout * plane;
+  g.sCm = plane;
+  g.sCn = 1;
+  g.bias = bias;
+  launch_gemm(f->st, g);
+}
+
+// in-grad of a 1x1 convolution: gin[b][i][pt] = sum_o W[o][i] gout[b][o][pt]
+void conv1x1_dx(swense_fno* f, const unsigned short* W, int cout, int cin, const float* gout, float* gin, int B,
+                float beta) {
+  const long long plane = (long long)f->d.n * f->d.n;
+  GemmArgs g = gemm0();
+  g.M = cin;
+  g.N = (int)plane;
+  g.K = cout;
+  g.nb1 = B;
+  g.A = W;
+  g.sAm = 1;
+  g.sAk = cin;
+  g.a_bf16 = 1;
+  g.B = gout;
+  g.sBb1 = (long long)cout * plane;
+  g.sBk = plane;
+  g.sBn = 1;
+  g.C = gin;
+  g.sCb1 = (long long)cin * plane;
+  g.sCm = plane;
+  g.sCn = 1;
+  g.beta = beta;
+  launch_gemm(f->st, g);
+}
+
+// weight grad: gW[o][i] = sum_{b,pt} gout[b][o][pt] in[b][i][pt], split over
+// (sample, point chunk) and reduced
+void conv1x1_dw(swense_fno* f, const float* gout, const float* in, int cout, int cin, int B, float* gW) {
+  const long long plane = (long long)f->d.n * f->d.n;
+  const int chunk = 4096;
+  const int nch = (int)((plane + chunk - 1) / chunk);
+  GemmArgs g = gemm0();
+  g.M = cout;
+  g.N = cin;
+  g.K = chunk;
+  g.nb1 = B;
+  g.nb2 = nch;
+  g.A = gout;
+  g.sAb1 = (long long)cout * plane;
+  g.sAb2 = chunk;
+  g.sAm = plane;
+  g.sAk = 1;
+  g.B = in;
+  g.sBb1 = (long long)cin * plane;
+  g.sBb2 = chunk;
+  g.sBk = 1;
+  g.sBn = plane;
+  g.C = f->part;
+  g.sCb1 = (long long)nch * cout * cin;
+  g.sCb2 = (long long)cout * cin;
+  g.sCm = cin;
+  g.sCn = 1;
+  SW_REQUIRE(plane % chunk == 0, "grid size must be a multiple of 4096 points");
+  launch_gemm(f->st, g);
+  const long long n = (long long)cout * cin;
+  hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, f->st, f->part, B * nch, n, gW,
+                     0.f);
+  SW_HIP(hipGetLastError());
+}
+
+template <int N>
+void spec_fwd_n(swense_fno* f, const float* v, cf* U, int B, float scale, int cp_flag) {
+  const FnoDims dd{N, f->d.channels, f->d.p_modes, f->d.q_modes, B};
+  const size_t lds = 4ull * wbuf_len(N) * sizeof(cf);
+  const int jx = B * (f->d.channels / 2) * N;
+  hipLaunchKernelGGL(k_fno_fx<N>, dim3((jx + 3) / 4), dim3(256), lds, f->st, v, f->xi, dd, f->plan);
+  SW_HIP(hipGetLastError());
+  const int jy = B * f->d.channels * f->d.p_modes;
+  hipLaunchKernelGGL(k_fno_fy<N>, dim3((jy + 3) / 4), dim3(256), lds, f->st, f->xi, U, dd, f->plan, scale, cp_flag);
+  SW_HIP(hipGetLastError());
+}
+
+template <int N>
+void spec_inv_n(swense_fno* f, const cf* Y, float* out, int B, float scale, float beta) {
+  const FnoDims dd{N, f->d.channels, f->d.p_modes, f->d.q_modes, B};
+  const size_t lds = 4ull * wbuf_len(N) * sizeof(cf);
+  const int jy = B * f->d.channels * f->d.p_modes;
+  hipLaunchKernelGGL(k_fno_iy<N>, dim3((jy + 3) / 4), dim3(256), lds, f->st, Y, f->xi, dd, f->plan);
+  SW_HIP(hipGetLastError());
+  const int jx = B * (f->d.channels / 2) * N;
+  hipLaunchKernelGGL(k_fno_ix<N>, dim3((jx + 3) / 4), dim3(256), lds, f->st, f->xi, out, dd, f->plan, scale, beta);
+  SW_HIP(hipGetLastError());
+}
+
+void spec_fwd(swense_fno* f, const float* v, cf* U, int B, float scale, int cp_flag) {
+  switch (f->d.n) {
+    case 64: spec_fwd_n<64>(f, v, U, B, scale, cp_flag); break;
+    case 128: spec_fwd_n<128>(f, v, U, B, scale, cp_flag); break;
+    case 256: spec_fwd_n<256>(f, v, U, B, scale, cp_flag); break;
+    default: spec_fwd_n<512>(f, v, U, B, scale, cp_flag); break;
+  }
+}
+
+void spec_inv(swense_fno* f, const cf* Y, float* out, int B, float scale, float beta) {
+  switch (f->d.n) {
+    case 64: spec_inv_n<64>(f, Y, out, B, scale, beta); break;
+    case 128: spec_inv_n<128>(f, Y, out, B, scale, beta); break;
+    case 256: spec_inv_n<256>(f, Y, out, B, scale, beta); break;
+    default: spec_inv_n<512>(f, Y, out, B, scale, beta); break;
+  }
+}
+
+void herm(swense_fno* f, cf* Y, int B, int div_cp) {
+  const FnoDims dd{f->d.n, f->d.channels, f->d.p_modes, f->d.q_modes, B};
+  const long long n = (long long)B * f->d.channels * (2 * f->d.q_modes + 1) * f->d.p_modes;
+  hipLaunchKernelGGL(k_fno_herm, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, f->st, Y, dd, div_cp);
+  SW_HIP(hipGetLastError());
+}
+
+// Y[b][s][o] = sum_i U[b][s][i] R[s][i][o] (complex), per mode s
+void mix(swense_fno* f, const cf* U, const unsigned short* R, cf* Y, int B) {
+  const int C = f->d.channels, S = (2 * f->d.q_modes + 1) * f->d.p_modes;
+  GemmArgs g = gemm0();
+  g.M = B;
+  g.N = 2 * C;
+  g.K = 2 * C;
+  g.nb1 = S;
+  g.A = U;
+  g.sAb1 = 2LL * C;     // floats
+  g.sAm = 2LL * S * C;  // next sample
+  g.sAk = 1;
+  g.B = R;
+  g.b_bf16 = 1;
+  g.b_cplx = 1;
+  g.sBb1 = (long long)C * C;  // complex elements
+  g.sBk = C;
+  g.sBn = 1;
+  g.C = reinterpret_cast<float*>(Y);
+  g.sCb1 = 2LL * C;
+  g.sCm = 2LL * S * C;
+  g.sCn = 1;
+  launch_gemm(f->st, g);
+}
+
+// gU[b][s][i] = sum_o gY[b][s][o] conj(R[s][i][o])
+void mix_dx(swense_fno* f, const cf* gY, const unsigned short* R, cf* gU, int B) {
+  const int C = f->d.channels, S = (2 * f->d.q_modes + 1) * f->d.p_modes;
+  GemmArgs g = gemm0();
+  g.M = B;
+  g.N = 2 * C;
+  g.K = 2 * C;
+  g.nb1 = S;
+  g.A = gY;
+  g.sAb1 = 2LL * C;
+  g.sAm = 2LL * S * C;
+  g.sAk = 1;
+  g.B = R;
+  g.b_bf16 = 1;
+  g.b_cplx = 1;
+  g.b_conj = 1;
+  g.sBb1 = (long long)C * C;
+  g.sBk = 1;  // element (k = o, n = i) -> R[i][o]
+  g.sBn = C;
+  g.C = reinterpret_cast<float*>(gU);
+  g.sCb1 = 2LL * C;
+  g.sCm = 2LL * S * C;
+  g.sCn = 1;
+  launch_gemm(f->st, g);
+}
+
+// gR[s][i][o] = sum_b conj(U[b][s][i]) gY[b][s][o]
+void mix_dw(swense_fno* f, const cf* U, const cf* gY, float* gR, int B) {
+  const int C = f->d.channels, S = (2 * f->d.q_modes + 1) * f->d.p_modes;
+  // Four real GEMMs per mode, summed over the samples b (k index):
+  //   Re gR[s][i][o] = sum_b (Ur gYr + Ui gYi),  Im gR[s][i][o] = sum_b (Ur gYi - Ui gYr)
+  // with output element (m = o, n = i).
+  const long long sb = 2LL * S * C;  // floats between samples
+  for (int part = 0; part < 4; ++part) {
+    // part 0: gYr Ur, 1: gYi Ui, 2: gYi Ur, 3: gYr Ui  (o x i, summed over b)
+    const int ay = (part == 1 || part == 2) ? 1 : 0;  // imag of gY
+    const int bu = (part == 1 || part == 3) ? 1 : 0;  // imag of U
+    GemmArgs h = gemm0();
+    h.M = C;
+    h.N = C;
+    h.K = B;
+    h.nb1 = S;
+    h.A = reinterpret_cast<const float*>(gY) + ay;
+    h.sAb1 = 2LL * C;
+    h.sAm = 2;
+    h.sAk = sb;
+    h.B = reinterpret_cast<const float*>(U) + bu;
+    h.sBb1 = 2LL * C;
+    h.sBk = sb;
+    h.sBn = 2;
+    // gR[s][i][o] complex: Re = sum(Ur gYr + Ui gYi), Im = sum(Ur gYi - Ui gYr)
+    // output element (m = o, n = i) -> gR[s][i][o].(re|im)
+    const int im_out = (part >= 2) ? 1 : 0;
+    h.C = gR + im_out;
+    h.sCb1 = 2LL * C * C;
+    h.sCm = 2;
+    h.sCn = 2LL * C;
+    h.alpha = (part == 3) ? -1.f : 1.f;
+    h.beta = (part == 1 || part == 3) ? 1.f : 0.f;
+    launch_gemm(f->st, h);
+  }
+}
+
+void check_fno_desc(const swense_fno_desc* d) {
+  SW_REQUIRE(d != nullptr, "null descriptor");
+  SW_REQUIRE(d->n == 64 || d->n == 128 || d->n == 256 || d->n == 512, "n must be 64, 128, 256 or 512");
+  SW_REQUIRE(d->channels >= 2 && d->channels % 2 == 0 && d->channels <= 256, "channels must be even, <= 256");
+  SW_REQUIRE(d->layers >= 1 && d->layers <= 32, "layers in [1, 32]");
+  SW_REQUIRE(d->p_modes >= 1 && d->p_modes < d->n / 2, "p_modes in [1, n/2)");
+  SW_REQUIRE(d->q_modes >= 0 && 2 * d->q_modes + 1 <= d->n / 2, "2 q_modes + 1 <= n/2");
+  SW_REQUIRE(d->hidden >= 1 && d->max_batch >= 1, "hidden and max_batch must be positive");
+}
+
+void allocate_fno(swense_fno* f) {
+  const auto& d = f->d;
+  const size_t plane = (size_t)d.n * d.n, B = d.max_batch, C = d.channels, H = d.hidden;
+  const size_t S = (size_t)(2 * d.q_modes + 1) * d.p_modes;
+  const size_t nact = (size_t)(2 * d.layers + 1) * B * C * plane + 2 * B * H * plane + 4 * B * plane;
+  const size_t ntmp = 2 * B * std::max(H, C) * plane;
+  const size_t nxi = B * C * d.n * d.p_modes;
+  const size_t nU = (size_t)d.layers * B * S * C;
+  const size_t nY = 2 * B * S * C;
+  const size_t npart = std::max<size_t>(B * (plane / 4096 + 1) * std::max(C, H) * C, 16);
+  size_t bytes = f->nparam * (4 + 2 + 4 + 4 + 4) + nact * 4 + ntmp * 4 + nxi * 8 + nU * 8 + nY * 8 + npart * 4 +
+                 2 * B * 2 * 4 + 16 * 256;
+  SW_HIP(hipMalloc(&f->mem, bytes));
+  SW_HIP(hipMemset(f->mem, 0, bytes));
+  char* p = reinterpret_cast<char*>(f->mem);
+  auto take = [&](size_t b) {
+    void* r = p;
+    p += (b + 255) & ~size_t(255);
+    return r;
+  };
+  f->w = reinterpret_cast<float*>(take(f->nparam * 4));
+  f->wb = reinterpret_cast<unsigned short*>(take(f->nparam * 2));
+  f->g = reinterpret_cast<float*>(take(f->nparam * 4));
+  f->am = reinterpret_cast<float*>(take(f->nparam * 4));
+  f->av = reinterpret_cast<float*>(take(f->nparam * 4));
+  f->act = reinterpret_cast<float*>(take(nact * 4));
+  f->tmp = reinterpret_cast<float*>(take(ntmp * 4));
+  f->xi = reinterpret_cast<cf*>(take(nxi * 8));
+  f->U = reinterpret_cast<cf*>(take(nU * 8));
+  f->Y = reinterpret_cast<cf*>(take(nY * 8));
+  f->part = reinterpret_cast<float*>(take(npart * 4));
+  f->sums = reinterpret_cast<float*>(take(2 * B * 2 * 4));
+  SW_REQUIRE(p <= reinterpret_cast<char*>(f->mem) + bytes, "internal carve overflow");
+}
+
+// activation slots: v_l (l = 0..L) then z_l (l = 1..L), then zq, h
+float* v_of(swense_fno* f, int l) {
+  return f->act + (size_t)l * (size_t)f->d.max_batch * f->d.channels * f->d.n * f->d.n;
+}
+float* z_of(swense_fno* f, int l) {
+  return f->act + (size_t)(f->d.layers + l) * (size_t)f->d.max_batch * f->d.channels * f->d.n * f->d.n;
+}
+float* zq_of(swense_fno* f) {
+  return f->act + (size_t)(2 * f->d.layers + 1) * (size_t)f->d.max_batch * f->d.channels * f->d.n * f->d.n;
+}
+float* h_of(swense_fno* f) { return zq_of(f) + (size_t)f->d.max_batch * f->d.hidden * f->d.n * f->d.n; }
+
+void elementwise(swense_fno* f, const float* a, const float* bias, const float* s, float* z, float* v, int B,
+                 int chans, int act) {
+  const long long plane = (long long)f->d.n * f->d.n;
+  const long long n = (long long)B * chans * plane;
+  hipLaunchKernelGGL(k_fno_act, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, f->st, a, bias, s, z, v, n, chans,
+                     plane, act);
+  SW_HIP(hipGetLastError());
+}
+
+void forward_impl(swense_fno* f, const float* x, float* y, int B) {
+  const auto& d = f->d;
+  const int C = d.channels, H = d.hidden;
+  float* tA = f->tmp;
+  float* tS = f->tmp + (size_t)d.max_batch * std::max(H, C) * d.n * d.n;
+  conv1x1(f, f->wb + f->oW0, C, 2, x, v_of(f, 0), B, f->w + f->ob0);
+  for (int l = 1; l <= d.layers; ++l) {
+    const float* v = v_of(f, l - 1);
+    cf* U = f->U + (size_t)(l - 1) * d.max_batch * (2 * d.q_modes + 1) * d.p_modes * C;
+    spec_fwd(f, v, U, B, 1.f / ((float)d.n * d.n), 0);
+    mix(f, U, f->wb + f->oR[l - 1], f->Y, B);
+    herm(f, f->Y, B, 0);
+    spec_inv(f, f->Y, tS, B, 1.f, 0.f);
+    conv1x1(f, f->wb + f->oW[l - 1], C, C, v, tA, B, nullptr);
+    elementwise(f, tA, f->w + f->ob[l - 1], tS, z_of(f, l), v_of(f, l), B, C, 1);
+  }
+  conv1x1(f, f->wb + f->oQ1, H, C, v_of(f, d.layers), tA, B, nullptr);
+  elementwise(f, tA, f->w + f->oc1, nullptr, zq_of(f), h_of(f), B, H, 1);
+  conv1x1(f, f->wb + f->oQ2, 2, H, h_of(f), y, B, f->w + f->oc2);
+  f->last_batch = B;
+}
+
+void bias_grad(swense_fno* f, const float* g, float* gb, int B, int chans) {
+  hipLaunchKernelGGL(k_fno_bias_grad, dim3(chans), dim3(256), 0, f->st, g, gb, B, chans, (long long)f->d.n * f->d.n);
+  SW_HIP(hipGetLastError());
+}
+
+void gelu_back(swense_fno* f, const float* gv, const float* z, float* gz, long long n) {
+  hipLaunchKernelGGL(k_fno_gelu_back, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, f->st, gv, z, gz, n);
+  SW_HIP(hipGetLastError());
+}
+
+// gradients of the loss w.r.t. every parameter (into f->g) given gy; the
+// input gradient goes to gx when non-null
+void backward_impl(swense_fno* f, const float* x, const float* gy, float* gx, int B) {
+  const auto& d = f->d;
+  const int C = d.channels, H = d.hidden;
+  const long long plane = (long long)d.n * d.n;
+  float* gh = f->tmp;  // [B][H] then reused
+  float* gv = f->tmp + (size_t)d.max_batch * std::max(H, C) * plane;
+  const int S = (2 * d.q_modes + 1) * d.p_modes;
+  // projection
+  conv1x1_dw(f, gy, h_of(f), 2, H, B, f->g + f->oQ2);
+  bias_grad(f, gy, f->g + f->oc2, B, 2);
+  conv1x1_dx(f, f->wb + f->oQ2, 2, H, gy, gh, B, 0.f);
+  gelu_back(f, gh, zq_of(f), gh, (long long)B * H * plane);
+  conv1x1_dw(f, gh, v_of(f, d.layers), H, C, B, f->g + f->oQ1);
+  bias_grad(f, gh, f->g + f->oc1, B, H);
+  conv1x1_dx(f, f->wb + f->oQ1, H, C, gh, gv, B, 0.f);
+  float* gz = gh;  // reuse
+  cf* gY = f->Y;
+  cf* gU = f->Y + (size_t)d.max_batch * S * C;
+  for (int l = d.layers; l >= 1; --l) {
+    gelu_back(f, gv, z_of(f, l), gz, (long long)B * C * plane);
+    const float* u = v_of(f, l - 1);
+    conv1x1_dw(f, gz, u, C, C, B, f->g + f->oW[l - 1]);
+    bias_grad(f, gz, f->g + f->ob[l - 1], B, C);
+    // spectral branch
+    spec_fwd(f, gz, gY, B, 1.f, 1);  // c_p n^2 rfft2(gz)/n^2
+    herm(f, gY, B, 0);
+    const cf* U = f->U + (size_t)(l - 1) * d.max_batch * S * C;
+    mix_dw(f, U, gY, f->g + f->oR[l - 1], B);
+    mix_dx(f, gY, f->wb + f->oR[l - 1], gU, B);
+    herm(f, gU, B, 1);  // P(gU / c_p)
+    // gv = W^T gz + (1/n^2) Re sum gU e^{ik.x}
+    conv1x1_dx(f, f->wb + f->oW[l - 1], C, C, gz, gv, B, 0.f);
+    spec_inv(f, gU, gv, B, 1.f / ((float)plane), 1.f);
+  }
+  conv1x1_dw(f, gv, x, C, 2, B, f->g + f->oW0);
+  bias_grad(f, gv, f->g + f->ob0, B, C);
+  if (gx) conv1x1_dx(f, f->wb + f->oW0, C, 2, gv, gx, B, 0.f);
+}
+
+float loss_impl(swense_fno* f, const float* y, const float* t, float* gy, int B) {
+  const long long plane = (long long)f->d.n * f->d.n;
+  hipLaunchKernelGGL(k_fno_loss_sums, dim3(B * 2), dim3(256), 0, f->st, y, t, f->sums, plane);
+  SW_HIP(hipGetLastError());
+  const long long n = (long long)B * 2 * plane;
+  hipLaunchKernelGGL(k_fno_loss_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, f->st, y, t, f->sums, gy,
+                     plane, n, 1.f / (2.f * B));
+  SW_HIP(hipGetLastError());
+  std::vector<float> s(4 * B);
+  SW_HIP(hipMemcpyAsync(s.data(), f->sums, 4 * B * sizeof(float), hipMemcpyDeviceToHost, f->st));
+  SW_HIP(hipStreamSynchronize(f->st));
+  double L = 0.0;
+  for (int i = 0; i < 2 * B; ++i) L += s[2 * i] / s[2 * i + 1];
+  return (float)(L / (2.0 * B));
+}
+
+template <typename F>
+int guarded_f(swense_fno* f, F&& fn) {
+  try {
+    return fn();
+  } catch (const SwenseError& e) {
+    if (f) f->err = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    if (f) f->err = e.what();
+    return SWENSE_EHIP;
+  }
+}
+
+}  // namespace
+
+hipStream_t fno_stream(const swense_fno* f) { return f->st; }
+swense_fno_desc fno_desc_of(const swense_fno* f) { return f->d; }
+
+extern "C" {
+
+size_t swense_fno_param_count(const swense_fno_desc* d) { return d ? count_params(*d) : 0; }
+
+int swense_fno_create(const swense_fno_desc* d, const float* params, void* stream, swense_fno** out) {
+  if (!out) return SWENSE_EINVAL;
+  *out = nullptr;
+  swense_fno* f = new swense_fno();
+  int rc = guarded_f(f, [&] {
+    check_fno_desc(d);
+    SW_REQUIRE(params != nullptr, "null parameters");
+    f->d = *d;
+    f->st = reinterpret_cast<hipStream_t>(stream);
+    layout(f);
+    SW_REQUIRE(f->nparam == count_params(*d), "internal layout mismatch");
+    f->plan = make_wplan(f->tw.get(d->n, false));
+    allocate_fno(f);
+    SW_HIP(hipMemcpy(f->w, params, f->nparam * 4, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((f->nparam + 255) / 256)), dim3(256), 0, f->st, f->w, f->wb,
+                       (long long)f->nparam);
+    SW_HIP(hipGetLastError());
+    SW_HIP(hipStreamSynchronize(f->st));
+    return (int)SWENSE_OK;
+  });
+  if (rc != SWENSE_OK) {
+    swense_fno_destroy(f);
+    return rc;
+  }
+  *out = f;
+  return SWENSE_OK;
+}
+
+int swense_fno_forward(swense_fno* f, const float* x, float* y, int batch) {
+  if (!f || !x || !y) return SWENSE_EINVAL;
+  return guarded_f(f, [&] {
+    SW_REQUIRE(batch >= 1 && batch <= f->d.max_batch, "batch outside [1, max_batch]");
+    forward_impl(f, x, y, batch);
+    return (int)SWENSE_OK;
+  });
+}
+
+int swense_fno_backward(swense_fno* f, const float* x, const float* gy, float* gx, int batch) {
+  if (!f || !x || !gy) return SWENSE_EINVAL;
+  return guarded_f(f, [&] {
+    SW_REQUIRE(batch == f->last_batch, "backward must follow a forward of the same batch");
+    backward_impl(f, x, gy, gx, batch);
+    return (int)SWENSE_OK;
+  });
+}
+
+int swense_fno_loss(swense_fno* f, const float* y, const float* t, float* gy, int batch, float* loss) {
+  if (!f || !y || !t || !gy) return SWENSE_EINVAL;
+  return guarded_f(f, [&] {
+    SW_REQUIRE(batch >= 1 && batch <= f->d.max_batch, "batch outside [1, max_batch]");
+    const float L = loss_impl(f, y, t, gy, batch);
+    if (loss) *loss = L;
+    return (int)SWENSE_OK;
+  });
+}
+
+int swense_fno_train_step(swense_fno* f, const float* x, const float* t, int batch, float lr, float* loss) {
+  if (!f || !x || !t) return SWENSE_EINVAL;
+  return guarded_f(f, [&] {
+    SW_REQUIRE(batch >= 1 && batch <= f->d.max_batch, "batch outside [1, max_batch]");
+    const long long plane = (long long)f->d.n * f->d.n;
+    float* y = h_of(f) + (size_t)f->d.max_batch * f->d.hidden * plane;
+    float* gy = y + (size_t)f->d.max_batch * 2 * plane;
+    forward_impl(f, x, y, batch);
+    const float L = loss_impl(f, y, t, gy, batch);
+    backward_impl(f, x, gy, nullptr, batch);
+    f->adam_t++;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)f->adam_t), c2 = 1.f - std::pow(b2, (float)f->adam_t);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((f->nparam + 255) / 256)), dim3(256), 0, f->st, f->w, f->wb, f->g,
+                       f->am, f->av, (long long)f->nparam, lr, b1, b2, 1e-8f, c1, c2);
+    SW_HIP(hipGetLastError());
+    if (loss) *loss = L;
+    return (int)SWENSE_OK;
+  });
+}
+
+int swense_fno_get(swense_fno* f, int what, float* host) {
+  if (!f || !host) return SWENSE_EINVAL;
+  return guarded_f(f, [&] {
+    SW_REQUIRE(what >= 0 && what <= 3, "what must be 0..3");
+    const float* src = what == 0 ? f->w : what == 1 ? f->g : what == 2 ? f->am : f->av;
+    SW_HIP(hipStreamSynchronize(f->st));
+    SW_HIP(hipMemcpy(host, src, f->nparam * 4, hipMemcpyDeviceToHost));
+    return (int)SWENSE_OK;
+  });
+}
+
+int swense_fno_set(swense_fno* f, int what, const float* host) {
+  if (!f || !host) return SWENSE_EINVAL;
+  return guarded_f(f, [&] {
+    SW_REQUIRE(what == 0 || what == 2 || what == 3, "what must be 0, 2 or 3");
+    SW_HIP(hipStreamSynchronize(f->st));
+    float* dst = what == 0 ? f->w : (what == 2 ? f->am : f->av);
+    SW_HIP(hipMemcpy(dst, host, f->nparam * 4, hipMemcpyHostToDevice));
+    if (what == 0) {
+      hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((f->nparam + 255) / 256)), dim3(256), 0, f->st, f->w, f->wb,
+                         (long long)f->nparam);
+      SW_HIP(hipGetLastError());
+      SW_HIP(hipStreamSynchronize(f->st));
+    }
+    return (int)SWENSE_OK;
+  });
+}
+
+int swense_gemm_bf16(int M, int N, int K, const float* A, const float* B, float* C, void* stream) {
+  if (!A || !B || !C || M < 1 || N < 1 || K < 1) return SWENSE_EINVAL;
+  try {
+    GemmArgs g = gemm0();
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.A = A;
+    g.sAm = K;
+    g.sAk = 1;
+    g.B = B;
+    g.sBk = N;
+    g.sBn = 1;
+    g.C = C;
+    g.sCm = N;
+    g.sCn = 1;
+    launch_gemm(reinterpret_cast<hipStream_t>(stream), g);
+  } catch (const SwenseError& e) {
+    return e.code;
+  }
+  return SWENSE_OK;
+}
+
+const char* swense_fno_last_error(const swense_fno* f) { return f ? f->err.c_str() : "no handle"; }
+
+void swense_fno_destroy(swense_fno* f) {
+  if (!f) return;
+  if (f->mem) (void)hipFree(f->mem);
+  f->tw.release();
+  delete f;
+}
+
+}  // extern "C"

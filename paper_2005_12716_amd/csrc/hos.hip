@@ -739,38 +739,15 @@ void modes_t(swense_hos* h) {
 }
 
 void set_state_phys(swense_hos* h, const double* eta, const double* phis) {
-  const int nx = h->G.nx, ny = h->G.ny;
-  const size_t np = (size_t)nx * ny;
+  const size_t np = (size_t)h->G.nx * h->G.ny;
   SW_HIP(hipMemcpyAsync(h->phys, eta, np * sizeof(double), hipMemcpyHostToDevice, h->st));
   SW_HIP(hipMemcpyAsync(h->phys + np, phis, np * sizeof(double), hipMemcpyHostToDevice, h->st));
-  cd* rows_e = reinterpret_cast<cd*>(h->phys + 2 * np);
-  cd* rows_p = rows_e + (size_t)ny * h->G.nxh;
-  const size_t lds = 2ull * nx * sizeof(cd);
-  SW_LAUNCH(h, SWENSE_K_AUX, k_phys_in, dim3(ny), dim3(256), lds, h->st, h->phys, h->phys + np, rows_e, rows_p, h->G,
-                     h->plan_nx);
-  SW_HIP(hipGetLastError());
-  YFwdArgs fa;
-  std::memset(&fa, 0, sizeof(fa));
-  fa.njobs = 2;
-  fa.job[0] = YFwdJob{rows_e, h->xn[0], nullptr, 0, YE_STORE};
-  fa.job[1] = YFwdJob{rows_p, h->xn[1], nullptr, 0, YE_STORE};
-  yfwd_t<double>(h, fa, h->plan_ny, h->st);
+  hos_phys_to_spec(h, h->xn[0], h->xn[1], false);
 }
 
 void get_state_phys(swense_hos* h, double* eta, double* phis) {
-  const int nx = h->G.nx, ny = h->G.ny;
-  const size_t np = (size_t)nx * ny;
-  cd* rows_e = reinterpret_cast<cd*>(h->phys + 2 * np);
-  cd* rows_p = rows_e + (size_t)ny * h->G.nxh;
-  YInvArgs ya;
-  std::memset(&ya, 0, sizeof(ya));
-  add_job(ya, h->xn[0], rows_e, SYM_ONE);
-  add_job(ya, h->xn[1], rows_p, SYM_ONE);
-  yinv_t<double>(h, ya, h->plan_ny, ny, 0, h->st);
-  const size_t lds = 2ull * nx * sizeof(cd);
-  SW_LAUNCH(h, SWENSE_K_AUX, k_phys_out, dim3(ny), dim3(256), lds, h->st, rows_e, rows_p, h->phys, h->phys + np, h->G,
-                     h->plan_nx);
-  SW_HIP(hipGetLastError());
+  const size_t np = (size_t)h->G.nx * h->G.ny;
+  hos_spec_to_phys(h, h->xn[0], h->xn[1]);
   if (eta) SW_HIP(hipMemcpyAsync(eta, h->phys, np * sizeof(double), hipMemcpyDeviceToHost, h->st));
   if (phis) SW_HIP(hipMemcpyAsync(phis, h->phys + np, np * sizeof(double), hipMemcpyDeviceToHost, h->st));
   SW_HIP(hipStreamSynchronize(h->st));
@@ -879,6 +856,74 @@ void load_state(swense_hos* h, const double* eta, const double* phis, int layout
 
 void set_error(swense_hos* h, const SwenseError& e) { h->err = e.msg; }
 
+void hos_phys_to_spec(swense_hos* h, cd* e, cd* p, bool add) {
+  const int nx = h->G.nx, ny = h->G.ny;
+  const size_t np = (size_t)nx * ny;
+  cd* rows_e = reinterpret_cast<cd*>(h->phys + 2 * np);
+  cd* rows_p = rows_e + (size_t)ny * h->G.nxh;
+  const size_t lds = 2ull * nx * sizeof(cd);
+  SW_LAUNCH(h, SWENSE_K_AUX, k_phys_in, dim3(ny), dim3(256), lds, h->st, h->phys, h->phys + np, rows_e, rows_p, h->G,
+            h->plan_nx);
+  SW_HIP(hipGetLastError());
+  YFwdArgs fa;
+  std::memset(&fa, 0, sizeof(fa));
+  fa.njobs = 2;
+  if (add) {
+    // the transformed fields are added into (e, p); the RK stage buffers (free
+    // between steps) take the plain result
+    cd* tmp_e = reinterpret_cast<cd*>(h->sa[0]);
+    cd* tmp_p = reinterpret_cast<cd*>(h->sa[1]);
+    fa.job[0] = YFwdJob{rows_e, tmp_e, e, 1, YE_STORE};
+    fa.job[1] = YFwdJob{rows_p, tmp_p, p, 1, YE_STORE};
+  } else {
+    fa.job[0] = YFwdJob{rows_e, e, nullptr, 0, YE_STORE};
+    fa.job[1] = YFwdJob{rows_p, p, nullptr, 0, YE_STORE};
+  }
+  yfwd_t<double>(h, fa, h->plan_ny, h->st);
+  h->version++;
+}
+
+void hos_spec_to_phys(swense_hos* h, const cd* e, const cd* p) {
+  const int nx = h->G.nx, ny = h->G.ny;
+  const size_t np = (size_t)nx * ny;
+  cd* rows_e = reinterpret_cast<cd*>(h->phys + 2 * np);
+  cd* rows_p = rows_e + (size_t)ny * h->G.nxh;
+  YInvArgs ya;
+  std::memset(&ya, 0, sizeof(ya));
+  add_job(ya, const_cast<cd*>(e), rows_e, SYM_ONE);
+  add_job(ya, const_cast<cd*>(p), rows_p, SYM_ONE);
+  yinv_t<double>(h, ya, h->plan_ny, ny, 0, h->st);
+  const size_t lds = 2ull * nx * sizeof(cd);
+  SW_LAUNCH(h, SWENSE_K_AUX, k_phys_out, dim3(ny), dim3(256), lds, h->st, rows_e, rows_p, h->phys, h->phys + np, h->G,
+            h->plan_nx);
+  SW_HIP(hipGetLastError());
+}
+
+void hos_step(swense_hos* h, int nsteps) {
+  if (h->fp64) step_t<double>(h, nsteps);
+  else step_t<float>(h, nsteps);
+}
+
+double hos_energy(swense_hos* h) {
+  launch_modes(h);
+  std::vector<cd> e(h->nc), ph(h->nc), et(h->nc);
+  SW_HIP(hipMemcpyAsync(e.data(), h->xn[0], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+  SW_HIP(hipMemcpyAsync(ph.data(), h->xn[1], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+  SW_HIP(hipMemcpyAsync(et.data(), h->kk[0], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
+  SW_HIP(hipStreamSynchronize(h->st));
+  // Parseval on the half spectrum: p = 0 column once, p > 0 twice.
+  double s1 = 0.0, s2 = 0.0;
+  for (int q = 0; q < h->G.ny; ++q)
+    for (int p = 0; p < h->G.nxh; ++p) {
+      const size_t i = (size_t)q * h->G.nxh + p;
+      const double w = p == 0 ? 1.0 : 2.0;
+      s1 += w * (ph[i].x * et[i].x + ph[i].y * et[i].y);
+      s2 += w * (e[i].x * e[i].x + e[i].y * e[i].y);
+    }
+  const double area = h->G.lx * h->G.ly;
+  return 0.5 * area * s1 + 0.5 * h->G.g * area * s2;
+}
+
 void launch_yinv(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, int row0, hipStream_t st) {
   if (h->fp64) yinv_t<double>(h, a, plan, nrows, row0, st);
   else yinv_t<float>(h, a, plan, nrows, row0, st);
@@ -948,8 +993,7 @@ int swense_hos_step(swense_hos* h, int nsteps) {
   if (!h) return SWENSE_EINVAL;
   return guarded(h, [&] {
     SW_REQUIRE(nsteps >= 0, "nsteps must be >= 0");
-    if (h->fp64) step_t<double>(h, nsteps);
-    else step_t<float>(h, nsteps);
+    hos_step(h, nsteps);
     return SWENSE_OK;
   });
 }
@@ -1006,23 +1050,7 @@ int swense_hos_modes(swense_hos* h, double* a_hat, double* a_t_hat, double* eta_
 int swense_hos_energy(swense_hos* h, double* energy) {
   if (!h || !energy) return SWENSE_EINVAL;
   return guarded(h, [&] {
-    launch_modes(h);
-    std::vector<cd> e(h->nc), ph(h->nc), et(h->nc);
-    SW_HIP(hipMemcpyAsync(e.data(), h->xn[0], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
-    SW_HIP(hipMemcpyAsync(ph.data(), h->xn[1], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
-    SW_HIP(hipMemcpyAsync(et.data(), h->kk[0], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
-    SW_HIP(hipStreamSynchronize(h->st));
-    // Parseval on the half spectrum: p = 0 column once, p > 0 twice.
-    double s1 = 0.0, s2 = 0.0;
-    for (int q = 0; q < h->G.ny; ++q)
-      for (int p = 0; p < h->G.nxh; ++p) {
-        const size_t i = (size_t)q * h->G.nxh + p;
-        const double w = p == 0 ? 1.0 : 2.0;
-        s1 += w * (ph[i].x * et[i].x + ph[i].y * et[i].y);
-        s2 += w * (e[i].x * e[i].x + e[i].y * e[i].y);
-      }
-    const double area = h->G.lx * h->G.ly;
-    *energy = 0.5 * area * s1 + 0.5 * h->G.g * area * s2;
+    *energy = hos_energy(h);
     return SWENSE_OK;
   });
 }

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "common.h"
+#include "swense_surrogate.h"
 
 // Symbol kinds multiplied into a half spectrum before the y transform.
 enum SymKind { SYM_ONE = 0, SYM_IKX = 1, SYM_IKY = 2, SYM_DZ = 3, SYM_EVAL = 4 };
@@ -213,6 +214,16 @@ void sw_launch(swense_hos* h, int kid, void (*kernel)(KArgs...), dim3 grid, dim3
 void launch_yinv(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, int row0, hipStream_t st);
 void launch_modes(swense_hos* h);  // A, A_t, eta_t at the current state (if stale)
 void set_error(swense_hos* h, const SwenseError& e);
+// Physical fields at h->phys ([ny][nx] FP64, eta then phis) -> half spectra
+// (e, p); add = true adds them into (e, p) instead of overwriting.
+void hos_phys_to_spec(swense_hos* h, cd* e, cd* p, bool add);
+// Half spectra (e, p) -> physical fields at h->phys.
+void hos_spec_to_phys(swense_hos* h, const cd* e, const cd* p);
+void hos_step(swense_hos* h, int nsteps);
+double hos_energy(swense_hos* h);  // synchronises
+// Network handle accessors (the surrogate runs the network on the HOS stream).
+hipStream_t fno_stream(const swense_fno* f);
+swense_fno_desc fno_desc_of(const swense_fno* f);
 
 // ---- reconstruction (evalgrid.hip)
 void eval_release(swense_hos* h);

@@ -40,6 +40,25 @@ class SeaDesc(C.Structure):
                 ("spreading", C.c_int), ("mode", C.c_int), ("ka", C.c_double)]
 
 
+class FnoDesc(C.Structure):
+    _fields_ = [("n", C.c_int), ("channels", C.c_int), ("layers", C.c_int), ("p_modes", C.c_int),
+                ("q_modes", C.c_int), ("hidden", C.c_int), ("max_batch", C.c_int)]
+
+
+class SurrogateDesc(C.Structure):
+    _fields_ = [("stride_s", C.c_int), ("sigma_eta", C.c_double), ("sigma_phi", C.c_double), ("rho", C.c_double),
+                ("tol", C.c_double), ("audit_every", C.c_int), ("cooldown", C.c_int), ("energy_tol", C.c_double)]
+
+
+class SurrogateStats(C.Structure):
+    _fields_ = [("calls", C.c_longlong), ("surrogate_calls", C.c_longlong), ("hos_calls", C.c_longlong),
+                ("audits", C.c_longlong), ("fallbacks", C.c_longlong), ("guard_trips", C.c_longlong),
+                ("max_audit_err", C.c_double), ("last_audit_err", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class SwenseError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"swense error {code}: {msg}")
@@ -84,6 +103,23 @@ def load():
         "swense_batch_destroy": (None, [vp]),
         "swense_hos_destroy": (None, [vp]),
         "swense_cells_destroy": (None, [vp]),
+        "swense_fno_param_count": (C.c_size_t, [C.POINTER(FnoDesc)]),
+        "swense_fno_create": (C.c_int, [C.POINTER(FnoDesc), vp, vp, C.POINTER(vp)]),
+        "swense_fno_forward": (C.c_int, [vp, vp, vp, C.c_int]),
+        "swense_fno_loss": (C.c_int, [vp, vp, vp, vp, C.c_int, C.POINTER(C.c_float)]),
+        "swense_fno_backward": (C.c_int, [vp, vp, vp, vp, C.c_int]),
+        "swense_fno_train_step": (C.c_int, [vp, vp, vp, C.c_int, C.c_float, C.POINTER(C.c_float)]),
+        "swense_fno_get": (C.c_int, [vp, C.c_int, vp]),
+        "swense_fno_set": (C.c_int, [vp, C.c_int, vp]),
+        "swense_fno_last_error": (C.c_char_p, [vp]),
+        "swense_fno_destroy": (None, [vp]),
+        "swense_gemm_bf16": (C.c_int, [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp]),
+        "swense_surrogate_create": (C.c_int, [vp, vp, C.POINTER(SurrogateDesc), C.POINTER(vp)]),
+        "swense_surrogate_features": (C.c_int, [vp, vp, vp]),
+        "swense_surrogate_target": (C.c_int, [vp, vp, vp, vp]),
+        "swense_surrogate_advance": (C.c_int, [vp, C.c_int, C.POINTER(SurrogateStats)]),
+        "swense_surrogate_last_error": (C.c_char_p, [vp]),
+        "swense_surrogate_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -99,7 +135,11 @@ EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swens
             "swense_cells_bind", "swense_interp_cells", "swense_interp_divergence", "swense_profile_enable",
             "swense_profile_read", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
             "swense_batch_last_error", "swense_batch_destroy", "swense_hos_destroy",
-            "swense_cells_destroy"]
+            "swense_cells_destroy", "swense_fno_param_count", "swense_fno_create", "swense_fno_forward",
+            "swense_fno_loss", "swense_fno_backward", "swense_fno_train_step", "swense_fno_get", "swense_fno_set",
+            "swense_fno_last_error", "swense_fno_destroy", "swense_gemm_bf16", "swense_surrogate_create",
+            "swense_surrogate_features", "swense_surrogate_target", "swense_surrogate_advance",
+            "swense_surrogate_last_error", "swense_surrogate_destroy"]
 
 
 def _ptr(a):
@@ -321,6 +361,202 @@ class Batch:
         if getattr(self, "b", None):
             self.L.swense_batch_destroy(self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- surrogate network
+
+def fno_desc(n=256, channels=64, layers=8, p_modes=32, q_modes=31, hidden=128, max_batch=8):
+    return FnoDesc(n, channels, layers, p_modes, q_modes, hidden, max_batch)
+
+
+def fno_names(desc: FnoDesc):
+    """Names and shapes of the packed parameter vector, in order."""
+    C_, H = desc.channels, desc.hidden
+    nq = 2 * desc.q_modes + 1
+    out = [("W0", (C_, 2)), ("b0", (C_,))]
+    for l in range(1, desc.layers + 1):
+        out += [(f"W{l}", (C_, C_)), (f"b{l}", (C_,)), (f"R{l}", (nq, desc.p_modes, C_, C_))]
+    out += [("Q1", (H, C_)), ("c1", (H,)), ("Q2", (2, H)), ("c2", (2,))]
+    return out
+
+
+def fno_pack(desc: FnoDesc, params: dict) -> np.ndarray:
+    """Dict of arrays (R complex) -> packed FP32 vector of the C ABI."""
+    parts = []
+    for name, shape in fno_names(desc):
+        a = np.asarray(params[name])
+        assert a.shape == shape, (name, a.shape, shape)
+        if np.iscomplexobj(a):
+            a = np.stack([a.real, a.imag], axis=-1)
+        parts.append(a.astype(np.float32).ravel())
+    v = np.concatenate(parts)
+    assert v.size == load().swense_fno_param_count(C.byref(desc))
+    return v
+
+
+def fno_unpack(desc: FnoDesc, vec: np.ndarray) -> dict:
+    out, o = {}, 0
+    for name, shape in fno_names(desc):
+        if name.startswith("R"):
+            m = int(np.prod(shape)) * 2
+            a = vec[o:o + m].reshape(shape + (2,)).astype(np.float64)
+            out[name] = a[..., 0] + 1j * a[..., 1]
+        else:
+            m = int(np.prod(shape))
+            out[name] = vec[o:o + m].reshape(shape).astype(np.float64)
+        o += m
+    return out
+
+
+def fno_init(desc: FnoDesc, seed: int) -> np.ndarray:
+    """Seeded initial weights (packed FP32): pointwise weights ~ N(0, 1/fan_in),
+    spectral weights uniform in [-1, 1] (re, im) / C^2, biases zero, the last
+    projection scaled by 0.1."""
+    rng = np.random.default_rng(seed)
+    C_, H = desc.channels, desc.hidden
+    nq = 2 * desc.q_modes + 1
+    P = {"W0": rng.standard_normal((C_, 2)) / np.sqrt(2), "b0": np.zeros(C_),
+         "Q1": rng.standard_normal((H, C_)) / np.sqrt(C_), "c1": np.zeros(H),
+         "Q2": rng.standard_normal((2, H)) / np.sqrt(H) * 0.1, "c2": np.zeros(2)}
+    for l in range(1, desc.layers + 1):
+        P[f"W{l}"] = rng.standard_normal((C_, C_)) / np.sqrt(C_)
+        P[f"b{l}"] = np.zeros(C_)
+        sh = (nq, desc.p_modes, C_, C_)
+        P[f"R{l}"] = (rng.uniform(-1, 1, sh) + 1j * rng.uniform(-1, 1, sh)) / (C_ * C_)
+    return fno_pack(desc, P)
+
+
+class Fno:
+    """Handle of the spectral neural operator (weights, Adam state, workspaces)."""
+
+    def __init__(self, desc: FnoDesc, params: np.ndarray, stream=None):
+        L = load()
+        self.desc = desc
+        st = stream if stream is not None else torch.cuda.current_stream()
+        self.n_params = int(L.swense_fno_param_count(C.byref(desc)))
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        assert params.size == self.n_params
+        h = C.c_void_p()
+        rc = L.swense_fno_create(C.byref(desc), params.ctypes.data_as(C.c_void_p), C.c_void_p(st.cuda_stream),
+                                 C.byref(h))
+        if rc != OK:
+            raise SwenseError(rc, "swense_fno_create failed")
+        self.h = h
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise SwenseError(rc, f"{what}: {load().swense_fno_last_error(self.h).decode()}")
+
+    def forward(self, x: torch.Tensor, y: torch.Tensor = None) -> torch.Tensor:
+        b = x.shape[0]
+        if y is None:
+            y = torch.empty((b, 2, self.desc.n, self.desc.n), dtype=torch.float32, device=x.device)
+        self._check(load().swense_fno_forward(self.h, _ptr(x), _ptr(y), b), "forward")
+        return y
+
+    def loss(self, y, t, gy=None):
+        if gy is None:
+            gy = torch.empty_like(y)
+        v = C.c_float()
+        self._check(load().swense_fno_loss(self.h, _ptr(y), _ptr(t), _ptr(gy), y.shape[0], C.byref(v)), "loss")
+        return v.value, gy
+
+    def backward(self, x, gy, want_gx=False):
+        gx = torch.empty_like(x) if want_gx else None
+        self._check(load().swense_fno_backward(self.h, _ptr(x), _ptr(gy), _ptr(gx), x.shape[0]), "backward")
+        return gx
+
+    def train_step(self, x, t, lr):
+        v = C.c_float()
+        self._check(load().swense_fno_train_step(self.h, _ptr(x), _ptr(t), x.shape[0], lr, C.byref(v)), "train")
+        return v.value
+
+    def get(self, what=0) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._check(load().swense_fno_get(self.h, what, out.ctypes.data_as(C.c_void_p)), "get")
+        return out
+
+    def set(self, vec: np.ndarray, what=0):
+        vec = np.ascontiguousarray(vec, dtype=np.float32)
+        assert vec.size == self.n_params
+        self._check(load().swense_fno_set(self.h, what, vec.ctypes.data_as(C.c_void_p)), "set")
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().swense_fno_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gemm_bf16(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    """C = bf16(A) bf16(B) with FP32 accumulation (device FP32 row-major)."""
+    M, K = a.shape
+    K2, N = b.shape
+    assert K == K2 and a.is_contiguous() and b.is_contiguous()
+    c = torch.empty((M, N), dtype=torch.float32, device=a.device)
+    rc = load().swense_gemm_bf16(M, N, K, _ptr(a), _ptr(b), _ptr(c), None)
+    if rc != OK:
+        raise SwenseError(rc, "swense_gemm_bf16 failed")
+    return c
+
+
+def surrogate_desc(stride_s=10, sigma_eta=1.0, sigma_phi=1.0, rho=1.0, tol=1e-3, audit_every=4, cooldown=4,
+                   energy_tol=0.0):
+    return SurrogateDesc(stride_s, sigma_eta, sigma_phi, rho, tol, audit_every, cooldown, energy_tol)
+
+
+class Surrogate:
+    """A network tied to one square realisation (same stream), advancing it
+    with HOS as fallback and judge."""
+
+    def __init__(self, hos: Hos, net: Fno, desc: SurrogateDesc):
+        self.hos, self.net, self.desc = hos, net, desc
+        self.n = net.desc.n
+        h = C.c_void_p()
+        rc = load().swense_surrogate_create(hos.h, net.h, C.byref(desc), C.byref(h))
+        if rc != OK:
+            raise SwenseError(rc, "swense_surrogate_create failed")
+        self.h = h
+        self.stats = SurrogateStats()
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise SwenseError(rc, f"{what}: {load().swense_surrogate_last_error(self.h).decode()}")
+
+    def features(self, x=None, lin=None, want_lin=True):
+        dev = torch.device("cuda")
+        if x is None:
+            x = torch.empty((2, self.n, self.n), dtype=torch.float32, device=dev)
+        if want_lin and lin is None:
+            lin = torch.empty((2, self.n, self.n), dtype=torch.float32, device=dev)
+        self._check(load().swense_surrogate_features(self.h, _ptr(x), _ptr(lin) if want_lin else None), "features")
+        return x, lin
+
+    def target(self, x_next, lin, t=None):
+        if t is None:
+            t = torch.empty_like(lin)
+        self._check(load().swense_surrogate_target(self.h, _ptr(x_next), _ptr(lin), _ptr(t)), "target")
+        return t
+
+    def advance(self, ncalls):
+        self._check(load().swense_surrogate_advance(self.h, ncalls, C.byref(self.stats)), "advance")
+        return self.stats.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().swense_surrogate_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

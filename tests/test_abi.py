@@ -1,5 +1,5 @@
 """Host-side checks of the C ABI: the library loads, exports every function
-include/swense.h declares, and its host set-up routine (initial sea
+include/*.h declare, and its host set-up routine (initial sea
 spectra, no GPU involved) matches the oracle."""
 import math
 import os
@@ -15,7 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    txt = open(os.path.join(ROOT, "include", "swense.h")).read()
+    import glob
+    txt = "".join(open(p).read() for p in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(swense_[a-z_0-9]+)\s*\(", txt)))
 

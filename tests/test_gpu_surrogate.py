@@ -1,0 +1,164 @@
+"""GPU checks of the surrogate rollout: network input features and the exact
+linear propagation against the oracle, the training target, and the
+advance loop's decisions (judged calls keep the HOS state bit for bit, guards
+catch non-finite and energy-violating states, cool-down after a fallback,
+the residual enters with its stated scaling)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import Grid, fno as F
+
+pytestmark = pytest.mark.gpu
+LAM = 2 * math.pi
+N = 64
+S = 5
+
+
+def _realisation(lib, depth=-1.0, seed=7):
+    lx = N * LAM / 6.4
+    d = lib.hos_desc(3, N, N, lx, lx, depth, order_m=3, dt=LAM / 64)
+    eh, ph = lib.sea_spectrum(d, kind=0, hs=0.02 * LAM, kp=1.0, gamma=3.3,
+                              phases=synth.mode_phases(seed, N, N // 2 + 1))
+    return d, eh, ph
+
+
+def _net(lib, seed=1):
+    desc = lib.fno_desc(N, 8, 2, 8, 7, 16, max_batch=1)
+    return desc, lib.fno_init(desc, seed)
+
+
+def _sur(lib, depth=-1.0, **kw):
+    d, eh, ph = _realisation(lib, depth)
+    h = lib.Hos(d, eh, ph)
+    desc, vec = _net(lib)
+    net = lib.Fno(desc, vec)
+    sig = 0.02 * LAM / 4
+    sd = lib.surrogate_desc(stride_s=S, sigma_eta=sig, sigma_phi=sig, rho=0.05, **kw)
+    return d, eh, ph, h, desc, vec, net, lib.Surrogate(h, net, sd), sd
+
+
+def _close(*objs):
+    for o in objs:
+        o.close()
+
+
+def _grid(d):
+    return Grid(nx=d.nx, ny=d.ny, lx=d.lx, ly=d.ly, depth=d.depth, order_m=3)
+
+
+def _lin(d, eh, ph, tau):
+    g = _grid(d)
+    _, _, K = g.kvec()
+    kt = K * np.tanh(K * d.depth) if d.depth > 0 else K
+    return F.linear_propagator(eh, ph, kt, d.g, tau)
+
+
+@pytest.mark.parametrize("depth", [-1.0, 1.5])
+def test_features_and_linear_propagation(gpu_lib, depth):
+    from paper_2005_12716_amd import lib
+    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, depth)
+    x, lin = sur.features()
+    x, lin = x.cpu().numpy(), lin.cpu().numpy()
+    g = _grid(d)
+    e_phys, p_phys, _ = h.state(lib.PHYSICAL)
+    sig = sd.sigma_eta
+    assert np.abs(x[0] - e_phys / sig).max() <= 1e-6 * np.abs(e_phys / sig).max()
+    assert np.abs(x[1] - p_phys / sig).max() <= 1e-6 * np.abs(p_phys / sig).max()
+    le, lp = _lin(d, eh, ph, S * d.dt)
+    for got, ref in ((lin[0], g.to_phys(le, (N, N)) / sig), (lin[1], g.to_phys(lp, (N, N)) / sig)):
+        assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
+    # the target of a pair is (x_next - lin) / rho, elementwise
+    h.step(S)
+    xn, _ = sur.features(want_lin=False)
+    t = sur.target(xn, torch.tensor(lin, device="cuda")).cpu().numpy()
+    ref = (xn.cpu().numpy() - lin) * np.float32(1.0 / sd.rho)
+    assert np.allclose(t, ref, rtol=1e-6, atol=1e-6 * np.abs(ref).max())
+    _close(sur, net, h)
+
+
+def _hos_ref(lib, d, eh, ph, nsteps):
+    ref = lib.Hos(d, eh, ph)
+    ref.step(nsteps)
+    out = ref.state()
+    ref.close()
+    return out
+
+
+def test_judged_calls_keep_the_hos_state(gpu_lib):
+    """tol = 0 and A = 1: every call is judged and falls back, so the rollout
+    is the plain HOS run bit for bit."""
+    from paper_2005_12716_amd import lib
+    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, tol=0.0, audit_every=1, cooldown=0)
+    st = sur.advance(3)
+    assert st["audits"] == 3 and st["fallbacks"] == 3 and st["surrogate_calls"] == 3 and st["hos_calls"] == 0
+    assert st["max_audit_err"] > 0
+    e, p, t = h.state()
+    er, pr, tr = _hos_ref(lib, d, eh, ph, 3 * S)
+    assert np.array_equal(e, er) and np.array_equal(p, pr) and t == tr
+    _close(sur, net, h)
+
+
+def test_cooldown_after_fallback(gpu_lib):
+    from paper_2005_12716_amd import lib
+    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, tol=0.0, audit_every=1, cooldown=2)
+    st = sur.advance(5)
+    assert st["surrogate_calls"] == 2 and st["hos_calls"] == 3 and st["fallbacks"] == 2
+    e, p, t = h.state()
+    er, pr, tr = _hos_ref(lib, d, eh, ph, 5 * S)
+    assert np.array_equal(e, er) and np.array_equal(p, pr)
+    _close(sur, net, h)
+
+
+def test_nan_weights_trip_the_guard(gpu_lib):
+    from paper_2005_12716_amd import lib
+    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, tol=1.0, audit_every=1000, cooldown=0)
+    bad = vec.copy()
+    bad[0] = np.nan
+    net.set(bad)
+    st = sur.advance(2)
+    assert st["guard_trips"] == 2 and st["fallbacks"] == 2 and st["audits"] == 2
+    e, p, t = h.state()
+    er, pr, tr = _hos_ref(lib, d, eh, ph, 2 * S)
+    assert np.array_equal(e, er) and np.array_equal(p, pr)
+    _close(sur, net, h)
+
+
+def test_energy_guard(gpu_lib):
+    from paper_2005_12716_amd import lib
+    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, tol=1.0, audit_every=1000, cooldown=0, energy_tol=1e-14)
+    st = sur.advance(1)
+    assert st["guard_trips"] == 1 and st["fallbacks"] == 1
+    _close(sur, net, h)
+
+
+def _with_output(lib, vec, desc, c2):
+    P = lib.fno_unpack(desc, vec)
+    P["Q2"] = np.zeros_like(P["Q2"])
+    P["c2"] = np.array(c2, dtype=np.float64)
+    return lib.fno_pack(desc, P)
+
+
+@pytest.mark.parametrize("depth", [-1.0, 1.5])
+def test_network_call_is_linear_plus_scaled_residual(gpu_lib, depth):
+    """Zero projection weights make the network output the constant c2: the
+    state becomes Lin(X) plus rho sigma c2 in the k = 0 modes, with the mean
+    of eta kept (mass)."""
+    from paper_2005_12716_amd import lib
+    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, depth, tol=1.0, audit_every=1000, cooldown=0)
+    net.set(_with_output(lib, vec, desc, [0.75, -0.5]))
+    st = sur.advance(2)
+    assert st["surrogate_calls"] == 2 and st["audits"] == 0
+    e, p, t = h.state()
+    er, pr = eh, ph
+    for _ in range(2):
+        er, pr = _lin(d, er, pr, S * d.dt)
+        pr = pr.copy()
+        pr[0, 0] += sd.rho * sd.sigma_phi * (-0.5)
+    assert np.abs(e - er).max() <= 1e-13 * np.abs(er).max()
+    assert np.abs(p - pr).max() <= 1e-13 * np.abs(pr).max()
+    assert abs(t - 2 * S * d.dt) < 1e-12
+    _close(sur, net, h)

@@ -106,9 +106,13 @@ def test_bf16_rounding_definition():
     assert abs(got[4] - 3.0e-3) / 3.0e-3 < 2 ** -8 and got[5] == 65536.0
 
 
-def test_linear_propagator_equals_m1_hos():
+@pytest.mark.parametrize("depth", [-1.0, 2.0])
+def test_linear_propagator_equals_m1_hos(depth):
+    """At order M = 1 the HOS step is the linear problem, so a finely stepped
+    M = 1 run pins the closed-form propagator (finite depth: k tanh(kh) in
+    place of k)."""
     LAM = 2 * math.pi
-    g = Grid(nx=32, ny=16, lx=32 * LAM / 6.4, ly=16 * LAM / 6.4, depth=-1.0, order_m=1)
+    g = Grid(nx=32, ny=16, lx=32 * LAM / 6.4, ly=16 * LAM / 6.4, depth=depth, order_m=1)
     rng = np.random.default_rng(3)
     eh = (rng.standard_normal((16, 17)) + 1j * rng.standard_normal((16, 17))) * g.nyquist_mask() * 1e-2
     ph = (rng.standard_normal((16, 17)) + 1j * rng.standard_normal((16, 17))) * g.nyquist_mask() * 1e-2
@@ -120,5 +124,6 @@ def test_linear_propagator_equals_m1_hos():
     tau = 10 * LAM / 64
     e1, p1 = hos.run(g, eh, ph, tau / 400, 400)
     _, _, K = g.kvec()
-    e2, p2 = fno.linear_propagator(eh, ph, K, 1.0, tau)
+    kt = K * np.tanh(K * depth) if depth > 0 else K
+    e2, p2 = fno.linear_propagator(eh, ph, kt, 1.0, tau)
     assert np.abs(e1 - e2).max() < 1e-9 and np.abs(p1 - p2).max() < 1e-9
