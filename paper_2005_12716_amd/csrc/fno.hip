@@ -55,6 +55,10 @@ struct GemmArgs {
   long long sCb1, sCb2, sCm, sCn;
   float alpha, beta;
   const float* bias;
+  // load modes chosen on the host from strides and alignment:
+  // a_mode 0 scalar, 1 FP32 x4 along k, 2 BF16 x4 along k, 3 BF16 x4 along m;
+  // b_mode 0 scalar, 1 FP32 x4 along k, 2 FP32 x4 along n, 3 complex BF16 pairs
+  int a_mode, b_mode;
 };
 
 constexpr int TM = 64, TN = 64, TK = 32;
@@ -63,44 +67,100 @@ __device__ __forceinline__ float ld(const void* p, long long i, int bf) {
   return bf ? bf2f(reinterpret_cast<const unsigned short*>(p)[i]) : reinterpret_cast<const float*>(p)[i];
 }
 
-__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
-  __shared__ unsigned short As[TM][TK + 4];  // [m][k]
-  __shared__ unsigned short Bs[TN][TK + 4];  // [n][k]
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int tiles_n = (g.N + TN - 1) / TN;
-  const int m0 = (blockIdx.x / tiles_n) * TM, n0 = (blockIdx.x % tiles_n) * TN;
-  const int b = blockIdx.y;
-  const int b1 = b / g.nb2, b2 = b - b1 * g.nb2;
-  const long long aoff = b1 * g.sAb1 + b2 * g.sAb2;
-  const long long boff = b1 * g.sBb1 + b2 * g.sBb2;
-  const long long coff = b1 * g.sCb1 + b2 * g.sCb2;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  v4f acc[2][2];
+__device__ __forceinline__ float4 ld4(const void* p, long long i) {
+  return *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(p) + i);
+}
+
+__device__ __forceinline__ uint2 pack4(float a, float b, float c, float d) {
+  return uint2{(unsigned)f2bf(a) | ((unsigned)f2bf(b) << 16), (unsigned)f2bf(c) | ((unsigned)f2bf(d) << 16)};
+}
+
+// Scalar-mode element e of a tile: (row, k) of A or (col, k) of B.
+__device__ __forceinline__ void a_elem(const GemmArgs& g, int e, int& m, int& k) {
+  if (g.sAk == 1) { m = e / TK; k = e - m * TK; }
+  else { k = e / TM; m = e - k * TM; }
+}
+__device__ __forceinline__ void b_elem(const GemmArgs& g, int e, int& n, int& k) {
+  if (!g.b_cplx && g.sBn == 1) { k = e / TN; n = e - k * TN; }
+  else { n = e / TK; k = e - n * TK; }
+}
+
+// Global -> registers for the tile at k0 (8 values of A and of B per thread).
+template <int AM, int BM>
+__device__ __forceinline__ void gemm_load(const GemmArgs& g, long long aoff, long long boff, int m0, int n0, int k0,
+                                          int tid, float ra[8], float rb[8]) {
+  if constexpr (AM == 1) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const int gm = m0 + (tid >> 3) + 32 * j, gk = k0 + (tid & 7) * 4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gm < g.M && gk < g.K) v = ld4(g.A, aoff + gm * g.sAm + gk);
+      ra[4 * j] = v.x; ra[4 * j + 1] = v.y; ra[4 * j + 2] = v.z; ra[4 * j + 3] = v.w;
+    }
+  } else if constexpr (AM == 2 || AM == 3) {
+    // raw BF16 bits, four consecutive along k (AM 2) or m (AM 3)
+    const unsigned short* A = reinterpret_cast<const unsigned short*>(g.A);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  const bool a_kfast = g.sAk == 1;
-  const bool b_nfast = !g.b_cplx && g.sBn == 1;
-  for (int k0 = 0; k0 < g.K; k0 += TK) {
-    // A tile
-    for (int e = tid; e < TM * TK; e += 256) {
+    for (int j = 0; j < 2; ++j) {
+      const int e = tid + 256 * j;
+      int gm, gk;
+      if constexpr (AM == 2) { gm = m0 + (e >> 3); gk = k0 + (e & 7) * 4; }
+      else { gk = k0 + (e >> 4); gm = m0 + (e & 15) * 4; }
+      uint2 v = uint2{0u, 0u};
+      if (gm < g.M && gk < g.K) v = *reinterpret_cast<const uint2*>(A + aoff + gm * g.sAm + gk * g.sAk);
+      ra[2 * j] = __uint_as_float(v.x);
+      ra[2 * j + 1] = __uint_as_float(v.y);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
       int m, k;
-      if (a_kfast) { m = e / TK; k = e - m * TK; }
-      else { k = e / TM; m = e - k * TM; }
+      a_elem(g, tid + 256 * j, m, k);
       const int gm = m0 + m, gk = k0 + k;
       float v = 0.f;
       if (gm < g.M && gk < g.K) {
         v = ld(g.A, aoff + gm * g.sAm + gk * g.sAk, g.a_bf16);
         if (g.a_conj && (gk & 1)) v = -v;
       }
-      As[m][k] = f2bf(v);
+      ra[j] = v;
     }
-    // B tile (stored [n][k])
-    for (int e = tid; e < TN * TK; e += 256) {
+  }
+  if constexpr (BM == 1) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gn = n0 + (tid >> 3) + 32 * j, gk = k0 + (tid & 7) * 4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gn < g.N && gk < g.K) v = ld4(g.B, boff + gn * g.sBn + gk);
+      rb[4 * j] = v.x; rb[4 * j + 1] = v.y; rb[4 * j + 2] = v.z; rb[4 * j + 3] = v.w;
+    }
+  } else if constexpr (BM == 2) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gk = k0 + (tid >> 4) + 16 * j, gn = n0 + (tid & 15) * 4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gn < g.N && gk < g.K) v = ld4(g.B, boff + gk * g.sBk + gn);
+      rb[4 * j] = v.x; rb[4 * j + 1] = v.y; rb[4 * j + 2] = v.z; rb[4 * j + 3] = v.w;
+    }
+  } else if constexpr (BM == 3) {
+    // one complex BF16 element (re, im) per load, expanded to its 2 x 2 real block on store
+    const unsigned* Bc = reinterpret_cast<const unsigned*>(g.B);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int e = tid + 256 * j;
+      int kc, nc;
+      if (g.sBn == 1) { nc = e & 31; kc = e >> 5; }
+      else { kc = e & 15; nc = e >> 4; }
+      const int gk = k0 + 2 * kc, gn = n0 + 2 * nc;
+      unsigned v = 0u;
+      if (gk < g.K && gn < g.N) v = Bc[boff + (long long)(gk >> 1) * g.sBk + (long long)(gn >> 1) * g.sBn];
+      if (g.b_conj) v ^= 0x80000000u;
+      rb[j] = __uint_as_float(v);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
       int n, k;
-      if (b_nfast) { k = e / TN; n = e - k * TN; }
-      else { n = e / TK; k = e - n * TK; }
+      b_elem(g, tid + 256 * j, n, k);
       const int gn = n0 + n, gk = k0 + k;
       float v = 0.f;
       if (gn < g.N && gk < g.K) {
@@ -116,19 +176,117 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
           v = ld(g.B, boff + gk * g.sBk + gn * g.sBn, g.b_bf16);
         }
       }
-      Bs[n][k] = f2bf(v);
+      rb[j] = v;
     }
+  }
+}
+
+// Registers -> LDS tiles, rounded to BF16.
+template <int AM, int BM>
+__device__ __forceinline__ void gemm_store(const GemmArgs& g, int tid, const float ra[8], const float rb[8],
+                                           unsigned short (*As)[TK + 4], unsigned short (*Bs)[TK + 4]) {
+  if constexpr (AM == 1) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int m = (tid >> 3) + 32 * j, k = (tid & 7) * 4;
+      *reinterpret_cast<uint2*>(&As[m][k]) = pack4(ra[4 * j], ra[4 * j + 1], ra[4 * j + 2], ra[4 * j + 3]);
+    }
+  } else if constexpr (AM == 2) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int e = tid + 256 * j;
+      *reinterpret_cast<uint2*>(&As[e >> 3][(e & 7) * 4]) = uint2{__float_as_uint(ra[2 * j]), __float_as_uint(ra[2 * j + 1])};
+    }
+  } else if constexpr (AM == 3) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int e = tid + 256 * j;
+      const int k = e >> 4, m = (e & 15) * 4;
+      const unsigned lo = __float_as_uint(ra[2 * j]), hi = __float_as_uint(ra[2 * j + 1]);
+      As[m][k] = (unsigned short)(lo & 0xFFFFu);
+      As[m + 1][k] = (unsigned short)(lo >> 16);
+      As[m + 2][k] = (unsigned short)(hi & 0xFFFFu);
+      As[m + 3][k] = (unsigned short)(hi >> 16);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      int m, k;
+      a_elem(g, tid + 256 * j, m, k);
+      As[m][k] = f2bf(ra[j]);
+    }
+  }
+  if constexpr (BM == 1) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = (tid >> 3) + 32 * j, k = (tid & 7) * 4;
+      *reinterpret_cast<uint2*>(&Bs[n][k]) = pack4(rb[4 * j], rb[4 * j + 1], rb[4 * j + 2], rb[4 * j + 3]);
+    }
+  } else if constexpr (BM == 2) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int k = (tid >> 4) + 16 * j, n = (tid & 15) * 4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Bs[n + i][k] = f2bf(rb[4 * j + i]);
+    }
+  } else if constexpr (BM == 3) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int e = tid + 256 * j;
+      int kc, nc;
+      if (g.sBn == 1) { nc = e & 31; kc = e >> 5; }
+      else { kc = e & 15; nc = e >> 4; }
+      // [[re, im], [-im, re]] in (k, n): row n = 2nc holds (re, -im), row 2nc + 1 holds (im, re)
+      const unsigned v = __float_as_uint(rb[j]);
+      const unsigned re = v & 0xFFFFu, im = v >> 16, nim = im ^ 0x8000u;
+      *reinterpret_cast<unsigned*>(&Bs[2 * nc][2 * kc]) = re | (nim << 16);
+      *reinterpret_cast<unsigned*>(&Bs[2 * nc + 1][2 * kc]) = im | (re << 16);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      int n, k;
+      b_elem(g, tid + 256 * j, n, k);
+      Bs[n][k] = f2bf(rb[j]);
+    }
+  }
+}
+
+// One 64 x 64 output tile per block (4 waves, 32 x 32 each as 2 x 2 MFMA
+// 16x16x16 tiles); the next K tile is fetched into registers while the
+// current one is multiplied.  AM, BM: load modes (see GemmArgs).
+template <int AM, int BM>
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+  __shared__ __align__(16) unsigned short As[TM][TK + 4];  // [m][k]
+  __shared__ __align__(16) unsigned short Bs[TN][TK + 4];  // [n][k]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tiles_n = (g.N + TN - 1) / TN;
+  const int m0 = (blockIdx.x / tiles_n) * TM, n0 = (blockIdx.x % tiles_n) * TN;
+  const int b = blockIdx.y;
+  const int b1 = b / g.nb2, b2 = b - b1 * g.nb2;
+  const long long aoff = b1 * g.sAb1 + b2 * g.sAb2;
+  const long long boff = b1 * g.sBb1 + b2 * g.sBb2;
+  const long long coff = b1 * g.sCb1 + b2 * g.sCb2;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  float ra[8], rb[8];
+  gemm_load<AM, BM>(g, aoff, boff, m0, n0, 0, tid, ra, rb);
+  for (int k0 = 0; k0 < g.K; k0 += TK) {
+    gemm_store<AM, BM>(g, tid, ra, rb, As, Bs);
     __syncthreads();
+    if (k0 + TK < g.K) gemm_load<AM, BM>(g, aoff, boff, m0, n0, k0 + TK, tid, ra, rb);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 16) {
       const int kq = kk + 4 * (lane >> 4);
       v4s af[2], bfr[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const int r = wm + 16 * i + (lane & 15);
-        af[i] = v4s{(short)As[r][kq], (short)As[r][kq + 1], (short)As[r][kq + 2], (short)As[r][kq + 3]};
-        const int c = wn + 16 * i + (lane & 15);
-        bfr[i] = v4s{(short)Bs[c][kq], (short)Bs[c][kq + 1], (short)Bs[c][kq + 2], (short)Bs[c][kq + 3]};
+        af[i] = *reinterpret_cast<const v4s*>(&As[wm + 16 * i + (lane & 15)][kq]);
+        bfr[i] = *reinterpret_cast<const v4s*>(&Bs[wn + 16 * i + (lane & 15)][kq]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -153,6 +311,40 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
           *cp = v;
         }
       }
+}
+
+// first level of a split-K sum: out2[grp][i] = sum of part[c][i] over the
+// parts c of group grp (blockIdx.y), groups of ceil(nparts / gridDim.y)
+__global__ void k_reduce_stage(const float* __restrict__ part, int nparts, long long n, float* __restrict__ out2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int per = (nparts + gridDim.y - 1) / gridDim.y;
+  const int c0 = blockIdx.y * per, c1 = min(nparts, c0 + per);
+  float s = 0.f;
+  for (int c = c0; c < c1; ++c) s += part[(long long)c * n + i];
+  out2[(long long)blockIdx.y * n + i] = s;
+}
+
+// per-channel sums, first level: part[split][c] = sum of channel c of g
+// [B][chans][plane] over the split-th slice of the (sample, point) range
+__global__ void __launch_bounds__(256) k_rowsum_stage(const float* __restrict__ g, float* __restrict__ part, int B,
+                                                      int chans, long long plane) {
+  const int c = blockIdx.x, split = blockIdx.y, nsplit = gridDim.y;
+  const long long total = (long long)B * plane, len = (total + nsplit - 1) / nsplit;
+  const long long u0 = split * len, u1 = min(total, u0 + len);
+  float s = 0.f;
+  for (long long u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
+    const long long b = u / plane, pt = u - b * plane;
+    s += g[(b * chans + c) * plane + pt];
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long long)split * chans + c] = red[0];
 }
 
 // sum over split-K partials: out[i] = beta out[i] + sum_c part[c][i]
@@ -344,24 +536,6 @@ __global__ void k_fno_gelu_back(const float* gv, const float* z, float* gz, long
   if (i < n) gz[i] = gv[i] * gelu_g(z[i]);
 }
 
-// per-channel sums over (b, points): gb[c] = sum g[b][c][pts]
-__global__ void __launch_bounds__(256) k_fno_bias_grad(const float* g, float* gb, int B, int chans, long long plane) {
-  const int c = blockIdx.x;
-  float s = 0.f;
-  for (int b = 0; b < B; ++b) {
-    const float* p = g + ((size_t)b * chans + c) * plane;
-    for (long long i = threadIdx.x; i < plane; i += blockDim.x) s += p[i];
-  }
-  __shared__ float red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) gb[c] = red[0];
-}
-
 // relative L2 per (b, channel): sums of d^2 and t^2 per plane
 __global__ void __launch_bounds__(256) k_fno_loss_sums(const float* y, const float* t, float* sums, long long plane) {
   const int bc = blockIdx.x;
@@ -444,7 +618,10 @@ struct swense_fno {
   cf* xi = nullptr;      // [B][C][n][P]
   cf* U = nullptr;       // per layer [B][S][C]
   cf* Y = nullptr;       // [B][S][C]
-  float* part = nullptr; // split-K partials
+  float* part = nullptr;     // split-K partials
+  float* part2 = nullptr;    // first-level sums of the partials
+  float* rowpart = nullptr;  // per-channel partial sums
+  size_t npart = 0;
   float* sums = nullptr;
   int last_batch = 0;
   void* mem = nullptr;
@@ -475,9 +652,61 @@ void layout(swense_fno* f) {
   f->nparam = o;
 }
 
-void launch_gemm(hipStream_t st, const GemmArgs& g) {
+bool aligned(const void* p, int bytes) { return (reinterpret_cast<uintptr_t>(p) & (bytes - 1)) == 0; }
+
+void launch_gemm(hipStream_t st, GemmArgs g) {
+  // vector load modes where the contiguous dimension and every offset allow
+  // 16-byte (FP32) or 8-byte (BF16) loads
+  const bool a_off4 = g.sAb1 % 4 == 0 && g.sAb2 % 4 == 0;
+  g.a_mode = 0;
+  if (!g.a_conj && a_off4) {
+    if (!g.a_bf16 && aligned(g.A, 16) && g.sAk == 1 && g.K % 4 == 0 && g.sAm % 4 == 0) g.a_mode = 1;
+    else if (g.a_bf16 && aligned(g.A, 8) && g.sAk == 1 && g.K % 4 == 0 && g.sAm % 4 == 0) g.a_mode = 2;
+    else if (g.a_bf16 && aligned(g.A, 8) && g.sAm == 1 && g.M % 4 == 0 && g.sAk % 4 == 0) g.a_mode = 3;
+  }
+  const bool b_off4 = g.sBb1 % 4 == 0 && g.sBb2 % 4 == 0;
+  g.b_mode = 0;
+  if (g.b_cplx) {
+    if (g.b_bf16 && aligned(g.B, 4) && (g.sBk == 1 || g.sBn == 1)) g.b_mode = 3;
+  } else if (!g.b_bf16 && b_off4 && aligned(g.B, 16)) {
+    if (g.sBk == 1 && g.K % 4 == 0 && g.sBn % 4 == 0) g.b_mode = 1;
+    else if (g.sBn == 1 && g.N % 4 == 0 && g.sBk % 4 == 0) g.b_mode = 2;
+  }
   const int tiles = ((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN);
-  hipLaunchKernelGGL(k_gemm_bf16, dim3(tiles, g.nb1 * g.nb2), dim3(256), 0, st, g);
+  SW_REQUIRE(g.nb1 * g.nb2 <= 65535, "GEMM batch count above the grid limit");
+  const dim3 grid(tiles, g.nb1 * g.nb2);
+#define SW_GEMM_CASE(a, b) \
+  case 4 * a + b: hipLaunchKernelGGL((k_gemm_bf16<a, b>), grid, dim3(256), 0, st, g); break;
+  switch (4 * g.a_mode + g.b_mode) {
+    SW_GEMM_CASE(0, 0) SW_GEMM_CASE(0, 1) SW_GEMM_CASE(0, 2) SW_GEMM_CASE(0, 3)
+    SW_GEMM_CASE(1, 0) SW_GEMM_CASE(1, 1) SW_GEMM_CASE(1, 2) SW_GEMM_CASE(1, 3)
+    SW_GEMM_CASE(2, 0) SW_GEMM_CASE(2, 1) SW_GEMM_CASE(2, 2) SW_GEMM_CASE(2, 3)
+    SW_GEMM_CASE(3, 0) SW_GEMM_CASE(3, 1) SW_GEMM_CASE(3, 2) SW_GEMM_CASE(3, 3)
+    default: throw SwenseError{SWENSE_EINVAL, "GEMM load mode"};
+  }
+#undef SW_GEMM_CASE
+  SW_HIP(hipGetLastError());
+}
+
+// Split of the point range of a weight-gradient reduction: about 1024 parts
+// (several blocks per CU in flight), each a power-of-two chunk of >= 256
+// points within one sample.
+int wgrad_chunk(long long plane, int B) {
+  long long c = 256;
+  while (c < plane && (long long)B * plane / c > 1024) c *= 2;
+  return (int)c;
+}
+
+constexpr int kReduceGroups = 64;
+
+// gW = sum over the nparts partial products in f->part (deterministic two-level sum)
+void reduce_parts(swense_fno* f, int nparts, long long n, float* gW) {
+  const int groups = std::min(kReduceGroups, nparts);
+  hipLaunchKernelGGL(k_reduce_stage, dim3((unsigned)((n + 255) / 256), groups), dim3(256), 0, f->st, f->part, nparts,
+                     n, f->part2);
+  SW_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, f->st, f->part2, groups, n, gW,
+                     0.f);
   SW_HIP(hipGetLastError());
 }
 
@@ -543,8 +772,8 @@ void conv1x1_dx(swense_fno* f, const unsigned short* W, int cout, int cin, const
 // (sample, point chunk) and reduced
 void conv1x1_dw(swense_fno* f, const float* gout, const float* in, int cout, int cin, int B, float* gW) {
   const long long plane = (long long)f->d.n * f->d.n;
-  const int chunk = 4096;
-  const int nch = (int)((plane + chunk - 1) / chunk);
+  const int chunk = wgrad_chunk(plane, B);
+  const int nch = (int)(plane / chunk);
   GemmArgs g = gemm0();
   g.M = cout;
   g.N = cin;
@@ -566,12 +795,9 @@ void conv1x1_dw(swense_fno* f, const float* gout, const float* in, int cout, int
   g.sCb2 = (long long)cout * cin;
   g.sCm = cin;
   g.sCn = 1;
-  SW_REQUIRE(plane % chunk == 0, "grid size must be a multiple of 4096 points");
+  SW_REQUIRE(plane % chunk == 0 && (long long)B * nch * cout * cin <= (long long)f->npart, "split-K sizes");
   launch_gemm(f->st, g);
-  const long long n = (long long)cout * cin;
-  hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, f->st, f->part, B * nch, n, gW,
-                     0.f);
-  SW_HIP(hipGetLastError());
+  reduce_parts(f, B * nch, (long long)cout * cin, gW);
 }
 
 template <int N>
@@ -677,34 +903,30 @@ void mix_dx(swense_fno* f, const cf* gY, const unsigned short* R, cf* gU, int B)
 // gR[s][i][o] = sum_b conj(U[b][s][i]) gY[b][s][o]
 void mix_dw(swense_fno* f, const cf* U, const cf* gY, float* gR, int B) {
   const int C = f->d.channels, S = (2 * f->d.q_modes + 1) * f->d.p_modes;
-  // Four real GEMMs per mode, summed over the samples b (k index):
+  // Four real GEMMs per mode, summed over the samples b (the k index), with
+  // output element (m = i, n = o) so that lanes write consecutive o:
   //   Re gR[s][i][o] = sum_b (Ur gYr + Ui gYi),  Im gR[s][i][o] = sum_b (Ur gYi - Ui gYr)
-  // with output element (m = o, n = i).
   const long long sb = 2LL * S * C;  // floats between samples
   for (int part = 0; part < 4; ++part) {
-    // part 0: gYr Ur, 1: gYi Ui, 2: gYi Ur, 3: gYr Ui  (o x i, summed over b)
-    const int ay = (part == 1 || part == 2) ? 1 : 0;  // imag of gY
-    const int bu = (part == 1 || part == 3) ? 1 : 0;  // imag of U
+    const int au = (part == 1 || part == 3) ? 1 : 0;  // imaginary part of U
+    const int by = (part == 1 || part == 2) ? 1 : 0;  // imaginary part of gY
     GemmArgs h = gemm0();
     h.M = C;
     h.N = C;
     h.K = B;
     h.nb1 = S;
-    h.A = reinterpret_cast<const float*>(gY) + ay;
+    h.A = reinterpret_cast<const float*>(U) + au;
     h.sAb1 = 2LL * C;
     h.sAm = 2;
     h.sAk = sb;
-    h.B = reinterpret_cast<const float*>(U) + bu;
+    h.B = reinterpret_cast<const float*>(gY) + by;
     h.sBb1 = 2LL * C;
     h.sBk = sb;
     h.sBn = 2;
-    // gR[s][i][o] complex: Re = sum(Ur gYr + Ui gYi), Im = sum(Ur gYi - Ui gYr)
-    // output element (m = o, n = i) -> gR[s][i][o].(re|im)
-    const int im_out = (part >= 2) ? 1 : 0;
-    h.C = gR + im_out;
+    h.C = gR + ((part >= 2) ? 1 : 0);
     h.sCb1 = 2LL * C * C;
-    h.sCm = 2;
-    h.sCn = 2LL * C;
+    h.sCm = 2LL * C;
+    h.sCn = 2;
     h.alpha = (part == 3) ? -1.f : 1.f;
     h.beta = (part == 1 || part == 3) ? 1.f : 0.f;
     launch_gemm(f->st, h);
@@ -730,8 +952,16 @@ void allocate_fno(swense_fno* f) {
   const size_t nxi = B * C * d.n * d.p_modes;
   const size_t nU = (size_t)d.layers * B * S * C;
   const size_t nY = 2 * B * S * C;
-  const size_t npart = std::max<size_t>(B * (plane / 4096 + 1) * std::max(C, H) * C, 16);
+  // split-K partials: at most max(1024, B plane / 256) parts of the largest
+  // weight matrix (H x C, C x C, 2 x H or C x 2)
+  const size_t maxmn = std::max({C * C, H * C, 2 * H, 2 * C});
+  const size_t nparts = std::max<size_t>(1024, B * plane / 256);
+  const size_t npart = nparts * maxmn;
+  const size_t npart2 = (size_t)kReduceGroups * maxmn;
+  const size_t nrow = 64 * std::max(C, H);
+  f->npart = npart;
   size_t bytes = f->nparam * (4 + 2 + 4 + 4 + 4) + nact * 4 + ntmp * 4 + nxi * 8 + nU * 8 + nY * 8 + npart * 4 +
+                 npart2 * 4 + nrow * 4 + 3 * 256 +
                  2 * B * 2 * 4 + 16 * 256;
   SW_HIP(hipMalloc(&f->mem, bytes));
   SW_HIP(hipMemset(f->mem, 0, bytes));
@@ -752,6 +982,8 @@ void allocate_fno(swense_fno* f) {
   f->U = reinterpret_cast<cf*>(take(nU * 8));
   f->Y = reinterpret_cast<cf*>(take(nY * 8));
   f->part = reinterpret_cast<float*>(take(npart * 4));
+  f->part2 = reinterpret_cast<float*>(take(npart2 * 4));
+  f->rowpart = reinterpret_cast<float*>(take(nrow * 4));
   f->sums = reinterpret_cast<float*>(take(2 * B * 2 * 4));
   SW_REQUIRE(p <= reinterpret_cast<char*>(f->mem) + bytes, "internal carve overflow");
 }
@@ -800,7 +1032,12 @@ void forward_impl(swense_fno* f, const float* x, float* y, int B) {
 }
 
 void bias_grad(swense_fno* f, const float* g, float* gb, int B, int chans) {
-  hipLaunchKernelGGL(k_fno_bias_grad, dim3(chans), dim3(256), 0, f->st, g, gb, B, chans, (long long)f->d.n * f->d.n);
+  constexpr int nsplit = 64;
+  hipLaunchKernelGGL(k_rowsum_stage, dim3(chans, nsplit), dim3(256), 0, f->st, g, f->rowpart, B, chans,
+                     (long long)f->d.n * f->d.n);
+  SW_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((chans + 255) / 256)), dim3(256), 0, f->st, f->rowpart, nsplit,
+                     (long long)chans, gb, 0.f);
   SW_HIP(hipGetLastError());
 }
 

@@ -226,3 +226,10 @@ def batch_realisations(seed: int, count: int = 64, lo: int = 128, hi: int = 512,
             "phase_seed": 1000 * (seed + 1) + r,
         })
     return out
+
+
+def surrogate_sea(seed: int) -> dict:
+    """Training/test sea of the surrogate: Hs/lambda_p ~ U[0.01, 0.03] drawn
+    from the seed, JONSWAP gamma 3.3, phases from the same seed."""
+    u = _uniform_stream(seed, 20, 1)
+    return {"hs_over_lambda": 0.01 + 0.02 * float(u[0]), "gamma": 3.3, "phase_seed": seed}

@@ -17,7 +17,7 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
 
 
-@pytest.mark.parametrize("M,N,K", [(64, 64, 32), (70, 130, 45), (1, 257, 3), (200, 33, 300)])
+@pytest.mark.parametrize("M,N,K", [(64, 64, 32), (70, 130, 45), (1, 257, 3), (200, 33, 300), (96, 132, 100)])
 def test_gemm_bf16_matches_rounded_fp64(gpu_lib, M, N, K):
     from paper_2005_12716_amd import lib
     rng = np.random.default_rng(M * 1000 + N + K)
