@@ -12,7 +12,7 @@
  * Conventions are those of swense.h (return codes, streams, ownership).
  *
  * Network, per sample on an n x n grid (x fastest), C channels:
- *   v_0 = W_0 x + b_0                               (lift, 2 -> C, pointwise)
+ *   v_0 = W_0 x + b_0                               (lift, in -> C, pointwise)
  *   v_l = gelu(W_l v_{l-1} + b_l + K_l(v_{l-1}))     (l = 1..L)
  *   y   = Q_2 gelu(Q_1 v_L + c_1) + c_2              (projection C -> H -> 2)
  * K_l(v) is the truncated spectral convolution: vhat = rfft2(v) / n^2 on the
@@ -26,7 +26,7 @@
  * weights are FP32.
  *
  * Parameter vector (FP32, packed in this order, row-major):
- *   W_0 [C][2], b_0 [C],
+ *   W_0 [C][in_channels], b_0 [C],
  *   for l = 1..L: W_l [C][C], b_l [C], R_l [nq][P][C][C] complex (re, im)
  *                 interleaved, mode index s = a P + p with a the position of q
  *                 in the order 0, 1, .., Q, -Q, .., -1 (nq = 2Q + 1),
@@ -51,6 +51,8 @@ typedef struct swense_fno_desc {
   int p_modes;   /* P: retained p in [0, P), 1 <= P < n/2                     */
   int q_modes;   /* Q: retained q in [-Q, Q], 2Q + 1 <= n/2                   */
   int hidden;    /* H: projection width                                       */
+  int in_channels; /* input fields: 2 (eta, phis) or 4 (with their linear    */
+                   /* propagation over the surrogate stride), 1..16          */
   int max_batch; /* largest batch passed to any call (sizes the workspaces)   */
 } swense_fno_desc;
 
@@ -65,7 +67,7 @@ size_t swense_fno_param_count(const swense_fno_desc* d);
  * stream: HIP stream of all later work (NULL = null stream).  Synchronises. */
 int swense_fno_create(const swense_fno_desc* d, const float* params, void* stream, swense_fno** out);
 
-/* Forward pass: x device [batch][2][n][n] -> y device [batch][2][n][n].
+/* Forward pass: x device [batch][in_channels][n][n] -> y device [batch][2][n][n].
  * Keeps the activations for a following swense_fno_backward.  Asynchronous. */
 int swense_fno_forward(swense_fno* f, const float* x, float* y, int batch);
 
@@ -76,7 +78,7 @@ int swense_fno_loss(swense_fno* f, const float* y, const float* t, float* gy, in
 
 /* Backward pass of the last forward (same batch and x): parameter gradients
  * into the handle's gradient vector (overwritten), input gradient into gx
- * (device [batch][2][n][n], may be NULL).  Asynchronous. */
+ * (device [batch][in_channels][n][n], may be NULL).  Asynchronous. */
 int swense_fno_backward(swense_fno* f, const float* x, const float* gy, float* gx, int batch);
 
 /* One optimiser step on (x, t): forward, loss, backward, Adam (beta1 0.9,
@@ -107,7 +109,8 @@ int swense_gemm_bf16(int M, int N, int K, const float* A, const float* B, float*
 
 /* Surrogate call: with X = (eta, phis) the physical surface state of a square
  * realisation (nx = ny = n of the network), the network input is
- * x = (eta / sigma_eta, phis / sigma_phi) and its output y gives
+ * x = (eta / sigma_eta, phis / sigma_phi), followed for a 4-channel network
+ * by the same scaling of Lin_{s dt} X, and its output y gives
  *   X(t + s dt) = Lin_{s dt} X(t) + rho (sigma_eta y_0, sigma_phi y_1),
  * Lin_tau the exact linear propagator, mode by mode with omega^2 = g k tanh(kh)
  * (deep water: g k): eta <- cos(w tau) eta + (k tanh(kh)/w) sin(w tau) phis,

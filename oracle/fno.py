@@ -55,6 +55,7 @@ class FnoConfig:
     p_modes: int = 32     # p in [0, p_modes)
     q_modes: int = 31     # q in [-q_modes, q_modes]
     hidden: int = 128     # projection width (2 C)
+    in_channels: int = 2  # network input: (eta, phis), or with the linearly propagated pair (4)
 
 
 def retained(cfg: FnoConfig):
@@ -67,7 +68,7 @@ def retained(cfg: FnoConfig):
 def init_params(cfg: FnoConfig, rng: np.random.Generator) -> dict:
     C, H = cfg.channels, cfg.hidden
     nq = 2 * cfg.q_modes + 1
-    P = {"W0": rng.standard_normal((C, 2)) / math.sqrt(2), "b0": np.zeros(C),
+    P = {"W0": rng.standard_normal((C, cfg.in_channels)) / math.sqrt(cfg.in_channels), "b0": np.zeros(C),
          "Q1": rng.standard_normal((H, C)) / math.sqrt(C), "c1": np.zeros(H),
          "Q2": rng.standard_normal((2, H)) / math.sqrt(H) * 0.1, "c2": np.zeros(2)}
     for l in range(cfg.layers):
@@ -121,7 +122,7 @@ def _cp(cfg):
 
 
 def forward(P: dict, x: np.ndarray, cfg: FnoConfig, bf16: bool = False):
-    """x [B, 2, n, n] -> y [B, 2, n, n]; returns (y, cache)."""
+    """x [B, in_channels, n, n] -> y [B, 2, n, n]; returns (y, cache)."""
     q = to_bf16 if bf16 else (lambda a: a)
     qc = cbf16 if bf16 else (lambda a: a)
     cache = {"x": x}

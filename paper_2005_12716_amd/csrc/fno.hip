@@ -6,7 +6,7 @@
 // re-quantises the BF16 copy used by the GEMMs after every step.
 //
 // Network (per sample, grid n x n, C channels):
-//   v0 = W0 x + b0;  for l = 1..L: z = W_l v + b_l + K_l(v), v = gelu(z);
+//   v0 = W0 x + b0 (x: in_channels input fields);  for l = 1..L: z = W_l v + b_l + K_l(v), v = gelu(z);
 //   y = Q2 gelu(Q1 v + c1) + c2.
 //   K_l(v): rfft2(v)/n^2 on the retained modes S = {p < P, |q| <= Q}, per-mode
 //   complex mixing by R_l (C x C), Hermitian projection of the p = 0 column,
@@ -509,6 +509,36 @@ __global__ void __launch_bounds__(256) k_fno_ix(const cf* __restrict__ xi, float
   }
 }
 
+// Spectral weight gradient: gR[s][i][o] = sum_b conj(U[b][s][i]) gY[b][s][o]
+// with both factors rounded to BF16.  A handful of samples per mode makes
+// this an outer-product sum bound by the store of gR, so it runs on plain
+// FP32 FMAs, one block per mode, the factors staged in LDS.
+__global__ void __launch_bounds__(256) k_mix_dw(const cf* __restrict__ U, const cf* __restrict__ gY,
+                                                float* __restrict__ gR, int B, int S, int C) {
+  extern __shared__ unsigned char smem[];
+  cf* su = reinterpret_cast<cf*>(smem);
+  cf* sy = su + (size_t)B * C;
+  const int s = blockIdx.x;
+  for (int e = threadIdx.x; e < B * C; e += blockDim.x) {
+    const int b = e / C, c = e - b * C;
+    const cf u = U[((size_t)b * S + s) * C + c], y = gY[((size_t)b * S + s) * C + c];
+    su[e] = mk(bf2f(f2bf(u.x)), bf2f(f2bf(u.y)));
+    sy[e] = mk(bf2f(f2bf(y.x)), bf2f(f2bf(y.y)));
+  }
+  __syncthreads();
+  float2* out = reinterpret_cast<float2*>(gR) + (size_t)s * C * C;
+  for (int e = threadIdx.x; e < C * C; e += blockDim.x) {
+    const int i = e / C, o = e - i * C;
+    float re = 0.f, im = 0.f;
+    for (int b = 0; b < B; ++b) {
+      const cf u = su[b * C + i], y = sy[b * C + o];
+      re += u.x * y.x + u.y * y.y;
+      im += u.x * y.y - u.y * y.x;
+    }
+    out[e] = make_float2(re, im);
+  }
+}
+
 // ------------------------------------------------------------------ element-wise
 __device__ __forceinline__ float gelu_f(float z) {
   const float k = 0.7978845608028654f;
@@ -631,14 +661,14 @@ namespace {
 
 size_t count_params(const swense_fno_desc& d) {
   const size_t C = d.channels, H = d.hidden, S = (size_t)(2 * d.q_modes + 1) * d.p_modes;
-  return C * 2 + C + (size_t)d.layers * (C * C + C + S * C * C * 2) + H * C + H + 2 * H + 2;
+  return C * d.in_channels + C + (size_t)d.layers * (C * C + C + S * C * C * 2) + H * C + H + 2 * H + 2;
 }
 
 void layout(swense_fno* f) {
   const auto& d = f->d;
   const size_t C = d.channels, H = d.hidden, S = (size_t)(2 * d.q_modes + 1) * d.p_modes;
   size_t o = 0;
-  f->oW0 = o; o += C * 2;
+  f->oW0 = o; o += C * d.in_channels;
   f->ob0 = o; o += C;
   for (int l = 0; l < d.layers; ++l) {
     f->oW.push_back(o); o += C * C;
@@ -903,34 +933,9 @@ void mix_dx(swense_fno* f, const cf* gY, const unsigned short* R, cf* gU, int B)
 // gR[s][i][o] = sum_b conj(U[b][s][i]) gY[b][s][o]
 void mix_dw(swense_fno* f, const cf* U, const cf* gY, float* gR, int B) {
   const int C = f->d.channels, S = (2 * f->d.q_modes + 1) * f->d.p_modes;
-  // Four real GEMMs per mode, summed over the samples b (the k index), with
-  // output element (m = i, n = o) so that lanes write consecutive o:
-  //   Re gR[s][i][o] = sum_b (Ur gYr + Ui gYi),  Im gR[s][i][o] = sum_b (Ur gYi - Ui gYr)
-  const long long sb = 2LL * S * C;  // floats between samples
-  for (int part = 0; part < 4; ++part) {
-    const int au = (part == 1 || part == 3) ? 1 : 0;  // imaginary part of U
-    const int by = (part == 1 || part == 2) ? 1 : 0;  // imaginary part of gY
-    GemmArgs h = gemm0();
-    h.M = C;
-    h.N = C;
-    h.K = B;
-    h.nb1 = S;
-    h.A = reinterpret_cast<const float*>(U) + au;
-    h.sAb1 = 2LL * C;
-    h.sAm = 2;
-    h.sAk = sb;
-    h.B = reinterpret_cast<const float*>(gY) + by;
-    h.sBb1 = 2LL * C;
-    h.sBk = sb;
-    h.sBn = 2;
-    h.C = gR + ((part >= 2) ? 1 : 0);
-    h.sCb1 = 2LL * C * C;
-    h.sCm = 2LL * C;
-    h.sCn = 2;
-    h.alpha = (part == 3) ? -1.f : 1.f;
-    h.beta = (part == 1 || part == 3) ? 1.f : 0.f;
-    launch_gemm(f->st, h);
-  }
+  const size_t lds = 2ull * B * C * sizeof(cf);
+  hipLaunchKernelGGL(k_mix_dw, dim3(S), dim3(256), lds, f->st, U, gY, gR, B, S, C);
+  SW_HIP(hipGetLastError());
 }
 
 void check_fno_desc(const swense_fno_desc* d) {
@@ -941,6 +946,8 @@ void check_fno_desc(const swense_fno_desc* d) {
   SW_REQUIRE(d->p_modes >= 1 && d->p_modes < d->n / 2, "p_modes in [1, n/2)");
   SW_REQUIRE(d->q_modes >= 0 && 2 * d->q_modes + 1 <= d->n / 2, "2 q_modes + 1 <= n/2");
   SW_REQUIRE(d->hidden >= 1 && d->max_batch >= 1, "hidden and max_batch must be positive");
+  SW_REQUIRE(d->in_channels >= 1 && d->in_channels <= 16, "in_channels in [1, 16]");
+  SW_REQUIRE(2ull * d->max_batch * d->channels * sizeof(cf) <= 64 * 1024, "max_batch x channels too large");
 }
 
 void allocate_fno(swense_fno* f) {
@@ -953,8 +960,8 @@ void allocate_fno(swense_fno* f) {
   const size_t nU = (size_t)d.layers * B * S * C;
   const size_t nY = 2 * B * S * C;
   // split-K partials: at most max(1024, B plane / 256) parts of the largest
-  // weight matrix (H x C, C x C, 2 x H or C x 2)
-  const size_t maxmn = std::max({C * C, H * C, 2 * H, 2 * C});
+  // weight matrix (H x C, C x C, 2 x H or C x in_channels)
+  const size_t maxmn = std::max({C * C, H * C, 2 * H, C * (size_t)d.in_channels});
   const size_t nparts = std::max<size_t>(1024, B * plane / 256);
   const size_t npart = nparts * maxmn;
   const size_t npart2 = (size_t)kReduceGroups * maxmn;
@@ -1014,7 +1021,7 @@ void forward_impl(swense_fno* f, const float* x, float* y, int B) {
   const int C = d.channels, H = d.hidden;
   float* tA = f->tmp;
   float* tS = f->tmp + (size_t)d.max_batch * std::max(H, C) * d.n * d.n;
-  conv1x1(f, f->wb + f->oW0, C, 2, x, v_of(f, 0), B, f->w + f->ob0);
+  conv1x1(f, f->wb + f->oW0, C, d.in_channels, x, v_of(f, 0), B, f->w + f->ob0);
   for (int l = 1; l <= d.layers; ++l) {
     const float* v = v_of(f, l - 1);
     cf* U = f->U + (size_t)(l - 1) * d.max_batch * (2 * d.q_modes + 1) * d.p_modes * C;
@@ -1082,9 +1089,9 @@ void backward_impl(swense_fno* f, const float* x, const float* gy, float* gx, in
     conv1x1_dx(f, f->wb + f->oW[l - 1], C, C, gz, gv, B, 0.f);
     spec_inv(f, gU, gv, B, 1.f / ((float)plane), 1.f);
   }
-  conv1x1_dw(f, gv, x, C, 2, B, f->g + f->oW0);
+  conv1x1_dw(f, gv, x, C, d.in_channels, B, f->g + f->oW0);
   bias_grad(f, gv, f->g + f->ob0, B, C);
-  if (gx) conv1x1_dx(f, f->wb + f->oW0, C, 2, gv, gx, B, 0.f);
+  if (gx) conv1x1_dx(f, f->wb + f->oW0, C, d.in_channels, gv, gx, B, 0.f);
 }
 
 float loss_impl(swense_fno* f, const float* y, const float* t, float* gy, int B) {

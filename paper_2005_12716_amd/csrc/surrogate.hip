@@ -21,6 +21,7 @@ struct swense_surrogate {
   double* sums = nullptr;  // 4 reduction slots
   int* bad = nullptr;
   void* mem = nullptr;
+  int in_channels = 2;     // network input: 2 (state) or 4 (state, linear propagation)
   int cool = 0;            // cool-down calls left
   long long nsur = 0;      // network calls so far (audit counter)
 };
@@ -184,11 +185,12 @@ void network_call(swense_surrogate* s, swense_surrogate_stats* st) {
   copy_state(s, h->xn[0], h->xn[1], s->backup[0], s->backup[1]);
   const bool eguard = s->d.energy_tol > 0.0;
   const double E0 = eguard ? hos_energy(h) : 0.0;
+  const long long np = (long long)h->G.nx * h->G.ny;
   features_of(s, s->backup[0], s->backup[1], s->x);
+  linear_into(s, s->backup[0], s->backup[1], h->xn[0], h->xn[1]);
+  if (s->in_channels == 4) features_of(s, h->xn[0], h->xn[1], s->x + 2 * np);
   const int rc = swense_fno_forward(s->f, s->x, s->y, 1);
   if (rc != SWENSE_OK) throw SwenseError{rc, "network forward failed"};
-  linear_into(s, s->backup[0], s->backup[1], h->xn[0], h->xn[1]);
-  const long long np = (long long)h->G.nx * h->G.ny;
   hipLaunchKernelGGL(k_residual_in, dim3(nblk(np)), dim3(256), 0, h->st, s->y, h->phys, h->phys + np, np,
                      s->d.rho * s->d.sigma_eta, s->d.rho * s->d.sigma_phi);
   SW_HIP(hipGetLastError());
@@ -250,13 +252,15 @@ int swense_surrogate_create(swense_hos* h, swense_fno* f, const swense_surrogate
     const swense_fno_desc fd = fno_desc_of(f);
     SW_REQUIRE(h->d.dim == 3 && h->G.nx == fd.n && h->G.ny == fd.n, "realisation must be n x n with the network's n");
     SW_REQUIRE(fno_stream(f) == h->st, "network and realisation must share one stream");
+    SW_REQUIRE(fd.in_channels == 2 || fd.in_channels == 4, "network input must have 2 or 4 channels");
+    s->in_channels = fd.in_channels;
     SW_REQUIRE(d->stride_s >= 1 && d->audit_every >= 1 && d->cooldown >= 0, "stride, audit period or cool-down");
     SW_REQUIRE(d->sigma_eta > 0.0 && d->sigma_phi > 0.0 && d->rho > 0.0 && d->tol >= 0.0, "scales and tol");
     s->h = h;
     s->f = f;
     s->d = *d;
     const size_t nc = h->nc, np = (size_t)fd.n * fd.n;
-    const size_t bytes = 4 * nc * sizeof(cd) + 4 * np * sizeof(float) + 8 * sizeof(double) + 256 * 8;
+    const size_t bytes = 4 * nc * sizeof(cd) + 6 * np * sizeof(float) + 8 * sizeof(double) + 256 * 8;
     SW_HIP(hipMalloc(&s->mem, bytes));
     char* p = reinterpret_cast<char*>(s->mem);
     auto take = [&](size_t b) {
@@ -266,7 +270,7 @@ int swense_surrogate_create(swense_hos* h, swense_fno* f, const swense_surrogate
     };
     for (int k = 0; k < 2; ++k) s->backup[k] = reinterpret_cast<cd*>(take(nc * sizeof(cd)));
     for (int k = 0; k < 2; ++k) s->sur[k] = reinterpret_cast<cd*>(take(nc * sizeof(cd)));
-    s->x = reinterpret_cast<float*>(take(2 * np * sizeof(float)));
+    s->x = reinterpret_cast<float*>(take(4 * np * sizeof(float)));
     s->y = reinterpret_cast<float*>(take(2 * np * sizeof(float)));
     s->sums = reinterpret_cast<double*>(take(4 * sizeof(double)));
     s->bad = reinterpret_cast<int*>(take(sizeof(int)));

@@ -42,7 +42,7 @@ class SeaDesc(C.Structure):
 
 class FnoDesc(C.Structure):
     _fields_ = [("n", C.c_int), ("channels", C.c_int), ("layers", C.c_int), ("p_modes", C.c_int),
-                ("q_modes", C.c_int), ("hidden", C.c_int), ("max_batch", C.c_int)]
+                ("q_modes", C.c_int), ("hidden", C.c_int), ("in_channels", C.c_int), ("max_batch", C.c_int)]
 
 
 class SurrogateDesc(C.Structure):
@@ -371,15 +371,15 @@ class Batch:
 
 # ---------------------------------------------------------------- surrogate network
 
-def fno_desc(n=256, channels=64, layers=8, p_modes=32, q_modes=31, hidden=128, max_batch=8):
-    return FnoDesc(n, channels, layers, p_modes, q_modes, hidden, max_batch)
+def fno_desc(n=256, channels=64, layers=8, p_modes=32, q_modes=31, hidden=128, max_batch=8, in_channels=2):
+    return FnoDesc(n, channels, layers, p_modes, q_modes, hidden, in_channels, max_batch)
 
 
 def fno_names(desc: FnoDesc):
     """Names and shapes of the packed parameter vector, in order."""
     C_, H = desc.channels, desc.hidden
     nq = 2 * desc.q_modes + 1
-    out = [("W0", (C_, 2)), ("b0", (C_,))]
+    out = [("W0", (C_, desc.in_channels)), ("b0", (C_,))]
     for l in range(1, desc.layers + 1):
         out += [(f"W{l}", (C_, C_)), (f"b{l}", (C_,)), (f"R{l}", (nq, desc.p_modes, C_, C_))]
     out += [("Q1", (H, C_)), ("c1", (H,)), ("Q2", (2, H)), ("c2", (2,))]
@@ -421,7 +421,8 @@ def fno_init(desc: FnoDesc, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     C_, H = desc.channels, desc.hidden
     nq = 2 * desc.q_modes + 1
-    P = {"W0": rng.standard_normal((C_, 2)) / np.sqrt(2), "b0": np.zeros(C_),
+    ci = desc.in_channels
+    P = {"W0": rng.standard_normal((C_, ci)) / np.sqrt(ci), "b0": np.zeros(C_),
          "Q1": rng.standard_normal((H, C_)) / np.sqrt(C_), "c1": np.zeros(H),
          "Q2": rng.standard_normal((2, H)) / np.sqrt(H) * 0.1, "c2": np.zeros(2)}
     for l in range(1, desc.layers + 1):

@@ -46,11 +46,14 @@ def default_scales(stride: int) -> dict:
 
 
 class Pairs:
-    """Device store of (input, target) pairs, [count][2][n][n] FP32 each."""
+    """Device store of (input, target) pairs: inputs [count][in_channels][n][n]
+    (the state, then for 4 channels its linear propagation), targets
+    [count][2][n][n], FP32."""
 
-    def __init__(self, count: int, n: int):
-        self.x = torch.empty((count, 2, n, n), dtype=torch.float32, device="cuda")
-        self.t = torch.empty_like(self.x)
+    def __init__(self, count: int, n: int, in_channels: int = 2):
+        self.x = torch.empty((count, in_channels, n, n), dtype=torch.float32, device="cuda")
+        self.t = torch.empty((count, 2, n, n), dtype=torch.float32, device="cuda")
+        self.in_channels = in_channels
         self.count = 0
 
 
@@ -65,10 +68,11 @@ def generate(net: lib.Fno, scales: dict, seeds, steps: int, periods: float, stor
         sur = lib.Surrogate(h, net, sd)
         for _ in range(steps // stride):
             i = store.count
-            sur.features(store.x[i], lin)
+            li = store.x[i, 2:4] if store.in_channels == 4 else lin
+            sur.features(store.x[i, 0:2], li)
             h.step(stride)
             sur.features(xn, want_lin=False)
-            sur.target(xn, lin, store.t[i])
+            sur.target(xn, li, store.t[i])
             store.count += 1
         sur.close()
         h.close()
@@ -84,8 +88,8 @@ def train(net: lib.Fno, store: Pairs, iters: int, batch: int, lr: float, seed: i
     without replacement per epoch (seeded)."""
     rng = np.random.default_rng(seed)
     n = net.desc.n
-    xb = torch.empty((batch, 2, n, n), dtype=torch.float32, device="cuda")
-    tb = torch.empty_like(xb)
+    xb = torch.empty((batch, store.in_channels, n, n), dtype=torch.float32, device="cuda")
+    tb = torch.empty((batch, 2, n, n), dtype=torch.float32, device="cuda")
     order = rng.permutation(store.count)
     pos = 0
     hist = []
@@ -176,6 +180,7 @@ def main(argv=None):
     ap.add_argument("--p-modes", type=int, default=32)
     ap.add_argument("--q-modes", type=int, default=31)
     ap.add_argument("--hidden", type=int, default=128)
+    ap.add_argument("--in-channels", type=int, default=4, choices=(2, 4))
     ap.add_argument("--trajectories", type=int, default=2000)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--stride", type=int, default=10)
@@ -192,11 +197,12 @@ def main(argv=None):
         print(msg, flush=True)
 
     lib.load()
-    desc = lib.fno_desc(a.n, a.channels, a.layers, a.p_modes, a.q_modes, a.hidden, max_batch=a.batch)
+    desc = lib.fno_desc(a.n, a.channels, a.layers, a.p_modes, a.q_modes, a.hidden, max_batch=a.batch,
+                        in_channels=a.in_channels)
     vec0 = lib.fno_init(desc, 0)
     net = lib.Fno(desc, vec0)
     scales = default_scales(a.stride)
-    store = Pairs(a.trajectories * (a.steps // a.stride), a.n)
+    store = Pairs(a.trajectories * (a.steps // a.stride), a.n, a.in_channels)
     t0 = time.time()
     generate(net, scales, range(1000, 1000 + a.trajectories), a.steps, a.periods, store, log)
     t_gen = time.time() - t0
@@ -227,7 +233,7 @@ def main(argv=None):
             json.dump(rep, f, indent=1)
     if a.out:
         np.savez(a.out, params=net.get(0), adam_m=net.get(2), adam_v=net.get(3),
-                 desc=np.array([a.n, a.channels, a.layers, a.p_modes, a.q_modes, a.hidden]),
+                 desc=np.array([a.n, a.channels, a.layers, a.p_modes, a.q_modes, a.hidden, a.in_channels]),
                  scales=json.dumps(scales))
     zero.close()
     net.close()

@@ -37,18 +37,20 @@ def _setup(lib, cfg, B, seed):
     for k in list(P):
         if k[0] in "bc":
             P[k] = 0.1 * rng.standard_normal(P[k].shape)
-    desc = lib.fno_desc(cfg.n, cfg.channels, cfg.layers, cfg.p_modes, cfg.q_modes, cfg.hidden, max_batch=B)
+    desc = lib.fno_desc(cfg.n, cfg.channels, cfg.layers, cfg.p_modes, cfg.q_modes, cfg.hidden, max_batch=B,
+                        in_channels=cfg.in_channels)
     vec = lib.fno_pack(desc, P)
     P32 = lib.fno_unpack(desc, vec)  # the FP32 values both sides use
-    x = rng.standard_normal((B, 2, cfg.n, cfg.n)).astype(np.float32)
+    x = rng.standard_normal((B, cfg.in_channels, cfg.n, cfg.n)).astype(np.float32)
     return desc, vec, P32, x
 
 
 SMALL = [F.FnoConfig(n=64, channels=8, layers=2, p_modes=8, q_modes=7, hidden=16),
-         F.FnoConfig(n=128, channels=6, layers=3, p_modes=5, q_modes=9, hidden=10)]
+         F.FnoConfig(n=128, channels=6, layers=3, p_modes=5, q_modes=9, hidden=10),
+         F.FnoConfig(n=64, channels=12, layers=2, p_modes=6, q_modes=10, hidden=20, in_channels=4)]
 
 
-@pytest.mark.parametrize("cfg", SMALL, ids=["n64c8", "n128c6"])
+@pytest.mark.parametrize("cfg", SMALL, ids=["n64c8", "n128c6", "n64c12in4"])
 def test_fno_forward_backward_parity(gpu_lib, cfg):
     from paper_2005_12716_amd import lib
     B = 2
@@ -58,6 +60,7 @@ def test_fno_forward_backward_parity(gpu_lib, cfg):
     y = net.forward(xd).cpu().numpy()
     yr, cache = F.forward(P, x.astype(np.float64), cfg, bf16=True)
     assert rel(y, yr) < TOL
+    assert y.shape == (B, 2, cfg.n, cfg.n)
     t = np.random.default_rng(5).standard_normal(y.shape).astype(np.float32)
     Lg, gy = net.loss(torch.tensor(y, device="cuda"), torch.tensor(t, device="cuda"))
     Lr, gyr = F.loss(y.astype(np.float64), t.astype(np.float64))

@@ -26,15 +26,15 @@ def _realisation(lib, depth=-1.0, seed=7):
     return d, eh, ph
 
 
-def _net(lib, seed=1):
-    desc = lib.fno_desc(N, 8, 2, 8, 7, 16, max_batch=1)
+def _net(lib, seed=1, in_channels=2):
+    desc = lib.fno_desc(N, 8, 2, 8, 7, 16, max_batch=1, in_channels=in_channels)
     return desc, lib.fno_init(desc, seed)
 
 
-def _sur(lib, depth=-1.0, **kw):
+def _sur(lib, depth=-1.0, in_channels=2, **kw):
     d, eh, ph = _realisation(lib, depth)
     h = lib.Hos(d, eh, ph)
-    desc, vec = _net(lib)
+    desc, vec = _net(lib, in_channels=in_channels)
     net = lib.Fno(desc, vec)
     sig = 0.02 * LAM / 4
     sd = lib.surrogate_desc(stride_s=S, sigma_eta=sig, sigma_phi=sig, rho=0.05, **kw)
@@ -88,11 +88,12 @@ def _hos_ref(lib, d, eh, ph, nsteps):
     return out
 
 
-def test_judged_calls_keep_the_hos_state(gpu_lib):
+@pytest.mark.parametrize("in_channels", [2, 4])
+def test_judged_calls_keep_the_hos_state(gpu_lib, in_channels):
     """tol = 0 and A = 1: every call is judged and falls back, so the rollout
     is the plain HOS run bit for bit."""
     from paper_2005_12716_amd import lib
-    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, tol=0.0, audit_every=1, cooldown=0)
+    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, tol=0.0, audit_every=1, cooldown=0, in_channels=in_channels)
     st = sur.advance(3)
     assert st["audits"] == 3 and st["fallbacks"] == 3 and st["surrogate_calls"] == 3 and st["hos_calls"] == 0
     assert st["max_audit_err"] > 0
@@ -142,13 +143,13 @@ def _with_output(lib, vec, desc, c2):
     return lib.fno_pack(desc, P)
 
 
-@pytest.mark.parametrize("depth", [-1.0, 1.5])
-def test_network_call_is_linear_plus_scaled_residual(gpu_lib, depth):
+@pytest.mark.parametrize("depth,in_channels", [(-1.0, 2), (1.5, 2), (-1.0, 4)])
+def test_network_call_is_linear_plus_scaled_residual(gpu_lib, depth, in_channels):
     """Zero projection weights make the network output the constant c2: the
     state becomes Lin(X) plus rho sigma c2 in the k = 0 modes, with the mean
     of eta kept (mass)."""
     from paper_2005_12716_amd import lib
-    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, depth, tol=1.0, audit_every=1000, cooldown=0)
+    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, depth, in_channels, tol=1.0, audit_every=1000, cooldown=0)
     net.set(_with_output(lib, vec, desc, [0.75, -0.5]))
     st = sur.advance(2)
     assert st["surrogate_calls"] == 2 and st["audits"] == 0

@@ -12,15 +12,15 @@ from oracle import Grid, hos
 from oracle import fno
 
 
-def _tiny():
-    cfg = fno.FnoConfig(n=16, channels=6, layers=2, p_modes=4, q_modes=3, hidden=8)
+def _tiny(in_channels=2):
+    cfg = fno.FnoConfig(n=16, channels=6, layers=2, p_modes=4, q_modes=3, hidden=8, in_channels=in_channels)
     rng = np.random.default_rng(0)
     P = fno.init_params(cfg, rng)
     for k in P:  # non-trivial biases and a non-negligible output layer
         if k.startswith(("b", "c")):
             P[k] = 0.1 * rng.standard_normal(P[k].shape)
     P["Q2"] *= 10
-    x = rng.standard_normal((2, 2, 16, 16))
+    x = rng.standard_normal((2, in_channels, 16, 16))
     t = rng.standard_normal((2, 2, 16, 16))
     return cfg, P, x, t
 
@@ -52,12 +52,15 @@ def test_gradients_match_finite_differences(name):
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (name, idx, part, fd, an)
 
 
-def test_input_gradient_matches_finite_differences():
-    cfg, P, x, t = _tiny()
+@pytest.mark.parametrize("in_channels", [2, 4])
+def test_input_gradient_matches_finite_differences(in_channels):
+    cfg, P, x, t = _tiny(in_channels)
     y, cache = fno.forward(P, x, cfg)
     _, gy = fno.loss(y, t)
     G = fno.backward(P, cache, gy, cfg)
     rng = np.random.default_rng(5)
+    G0 = G["W0"]
+    assert G0.shape == (6, in_channels) and G["x"].shape == x.shape
     for _ in range(6):
         idx = tuple(rng.integers(0, s) for s in x.shape)
         h = 1e-6
