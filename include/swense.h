@@ -247,6 +247,12 @@ int swense_profile_enable(swense_hos* h, int enable);
  * kernel class `kernel` recorded since profiling was enabled. */
 int swense_profile_read(swense_hos* h, int kernel, double* total_ms, long long* count);
 
+/* Compulsory HBM bytes (every distinct input read once, every output written
+ * once, by each launch's own arguments) of the launches of kernel class
+ * `kernel` issued while profiling was enabled.  Counted for the HOS classes
+ * (YINV, XPASS, YFWD); 0 for the others. */
+int swense_profile_bytes(swense_hos* h, int kernel, double* bytes);
+
 /* ---- lifetime ---------------------------------------------------------- */
 void swense_hos_destroy(swense_hos* h);
 void swense_cells_destroy(swense_cells* c);

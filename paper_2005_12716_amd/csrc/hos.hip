@@ -490,6 +490,17 @@ bool wave_ok(int n) {
 template <typename R>
 void yinv_t(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, int row0, hipStream_t st) {
   if (a.njobs == 0) return;
+  if (h->prof.on) {
+    // each distinct FP64 source spectrum read once, each job's rows written once
+    const double spec = (double)h->G.ny * h->G.nxh * sizeof(cd);
+    double b = (double)a.njobs * nrows * h->G.nxh * sizeof(cpx<R>);
+    for (int j = 0; j < a.njobs; ++j) {
+      bool seen = false;
+      for (int i = 0; i < j; ++i) seen = seen || a.job[i].src == a.job[j].src;
+      if (!seen) b += spec;
+    }
+    h->prof.bytes[SWENSE_K_YINV] += b;
+  }
   if (wave_ok<R>(plan.n)) {
     const WPlan wp = make_wplan(plan);
     const size_t lds = 4ull * wbuf_len(plan.n) * sizeof(cpx<R>);
@@ -508,6 +519,22 @@ void yinv_t(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, in
 
 template <typename R>
 void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t st) {
+  if (h->prof.on) {
+    // rows read once; per mode the FP64 epilogue traffic of each job
+    const double modes = (double)h->G.ny * h->G.nxh, c16 = sizeof(cd);
+    double b = (double)a.njobs * plan.n * h->G.nxh * sizeof(cpx<R>);
+    for (int j = 0; j < a.njobs; ++j) {
+      const YFwdJob& jb = a.job[j];
+      double per = 0.0;
+      if (jb.epi == YE_STORE) per = c16 + (jb.acc_mode == 1 ? 2 * c16 : jb.acc_mode == 2 ? c16 : 0.0);
+      else {
+        const int st4 = a.rk.stage;  // sin read; then stage-dependent state traffic
+        per = c16 + (st4 == 0 ? c16 : st4 == 1 ? 3 * c16 : st4 <= 3 ? 4 * c16 : 3 * c16);
+      }
+      b += per * modes;
+    }
+    h->prof.bytes[SWENSE_K_YFWD] += b;
+  }
   if (wave_ok<R>(plan.n)) {
     const WPlan wp = make_wplan(plan);
     const size_t lds = 4ull * wbuf_len(plan.n) * sizeof(cpx<R>);
@@ -527,6 +554,17 @@ void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t s
 template <typename R>
 void xpass_t(swense_hos* h, const XArgs& a) {
   const int Px = h->plan_px.n;
+  if (h->prof.on) {
+    // each distinct input row set read once, each output written once
+    const double rows = (double)h->Py * h->G.nxh * sizeof(cpx<R>);
+    double b = ((a.out0 ? 1 : 0) + (a.out1 ? 1 : 0)) * rows;
+    for (int j = 0; j < a.nin; ++j) {
+      bool seen = false;
+      for (int i = 0; i < j; ++i) seen = seen || a.in[i].src == a.in[j].src;
+      if (!seen) b += rows;
+    }
+    h->prof.bytes[SWENSE_K_XPASS] += b;
+  }
   {
     const size_t lds = 4ull * wbuf_len(Px) * sizeof(cpx<R>) + (size_t)a.nin * Px * sizeof(R);
     if (wave_ok<R>(Px) && lds <= 160 * 1024) {
@@ -1064,6 +1102,7 @@ int swense_profile_enable(swense_hos* h, int enable) {
     for (int k = 0; k < SWENSE_K_COUNT; ++k) {
       h->prof.total_ms[k] = 0.0;
       h->prof.count[k] = 0;
+      h->prof.bytes[k] = 0.0;
     }
     h->prof.on = enable != 0;
     return SWENSE_OK;
@@ -1087,6 +1126,12 @@ int swense_profile_read(swense_hos* h, int kernel, double* total_ms, long long* 
     if (count) *count = h->prof.count[kernel];
     return SWENSE_OK;
   });
+}
+
+int swense_profile_bytes(swense_hos* h, int kernel, double* bytes) {
+  if (!h || !bytes || kernel < 0 || kernel >= SWENSE_K_COUNT) return SWENSE_EINVAL;
+  *bytes = h->prof.bytes[kernel];
+  return SWENSE_OK;
 }
 
 void swense_hos_destroy(swense_hos* h) {

@@ -104,6 +104,7 @@ struct Profiler {
   std::vector<ProfRec> recs;
   double total_ms[SWENSE_K_COUNT] = {};
   long long count[SWENSE_K_COUNT] = {};
+  double bytes[SWENSE_K_COUNT] = {};  // compulsory HBM bytes of the recorded launches
   hipEvent_t take() {
     if (used == pool.size()) {
       hipEvent_t e;

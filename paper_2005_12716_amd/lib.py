@@ -95,6 +95,7 @@ def load():
         "swense_interp_divergence": (C.c_int, [vp, vp, fp]),
         "swense_profile_enable": (C.c_int, [vp, C.c_int]),
         "swense_profile_read": (C.c_int, [vp, C.c_int, dp, C.POINTER(C.c_longlong)]),
+        "swense_profile_bytes": (C.c_int, [vp, C.c_int, dp]),
         "swense_batch_create": (C.c_int, [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_uint), C.POINTER(vp),
                                           C.c_int, C.c_int, vp, C.POINTER(vp)]),
         "swense_batch_run": (C.c_int, [vp]),
@@ -133,7 +134,7 @@ EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swens
             "swense_hos_set_state", "swense_hos_step", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
             "swense_cells_bind", "swense_interp_cells", "swense_interp_divergence", "swense_profile_enable",
-            "swense_profile_read", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
+            "swense_profile_read", "swense_profile_bytes", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
             "swense_batch_last_error", "swense_batch_destroy", "swense_hos_destroy",
             "swense_cells_destroy", "swense_fno_param_count", "swense_fno_create", "swense_fno_forward",
             "swense_fno_loss", "swense_fno_backward", "swense_fno_train_step", "swense_fno_get", "swense_fno_set",
@@ -240,6 +241,15 @@ class Hos:
 
     def profile(self, enable=True):
         self._check(self.L.swense_profile_enable(self.h, 1 if enable else 0), "profile_enable")
+
+    def profile_bytes(self):
+        """{kernel class: compulsory HBM bytes of the recorded launches}."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            b = C.c_double()
+            self._check(self.L.swense_profile_bytes(self.h, k, C.byref(b)), "profile_bytes")
+            out[name] = b.value
+        return out
 
     def profile_read(self):
         """{kernel class: (total ms, launches)} since profiling was enabled."""
