@@ -399,7 +399,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "3D JONSWAP 512x256 modes M=3 (40x20 lambda_p, Hs/lambda_p=0.02, gamma=3.3, seed 1) "
                                "-> 1,996,800-point cylinder O-mesh, 11 fields, n=4 window, 48 layers",
-                   "points": cells.n, "modes": [NX, NY], "order_m": M, "padded": [2 * NX, py],
+                   "points": cells.n, "modes": [NX, NY], "order_m": M, "padded": [2 * NX, 2 * NY],
                    "grid": [gx, gy], "window": [ix0, iy0, wx, wy], "layers": int(zl.size)},
         "hos_steps_per_s": 1e3 / ms_hos,
         "hos_mode_steps_per_s": NX * NY * 1e3 / ms_hos,

@@ -343,6 +343,151 @@ __global__ void __launch_bounds__(256) k_xcoef_skel(EvArgs A, Geom G, WPlan plan
   }
 }
 
+// Coefficient x pass on skeleton heights as a dense contraction on the
+// matrix cores.  For window row r and a tile of DX_T window nodes, every item
+// (a skeleton height of a volume field, or a surface field) is evaluated at
+// the nodes X as  out[item][x] = sum_{p < nx/2} c_p Re(a_p e^{2 pi i p X / gx}),
+// c_0 = 1, c_p = 2: a real GEMM of the interleaved (Re, Im) mode rows against
+// the matrix [c_p cos; -c_p sin], formed from the FP32 twiddle table in LDS
+// (index p X mod gx, which also folds modes above gx/2 when gx < nx), on FP32
+// MFMA with FP32 accumulation.  Each layer is then sum_j T[l][j] out[f R + j]
+// and every node's run of K coefficients is stored contiguously.
+constexpr int DX_T = 64, DX_KC = 64, DX_MAXMT = 8;
+// LDS row strides chosen so that the MFMA operand reads (16 rows x 4
+// consecutive k, or 4 k-rows x 16 columns) and the accumulator stores hit 64
+// distinct banks.
+constexpr int DX_SA = DX_KC + 4, DX_SB = DX_T + 16, DX_SS = DX_T + 4;
+static_assert(DX_SS == DX_SA, "the results reuse the operand rows");
+
+__global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const cf* __restrict__ tw, int gx, Skel skl,
+                                                   int L, int K, int nitems, float* __restrict__ coef) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const int x0 = blockIdx.x * DX_T, r = blockIdx.y;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int hx = G.nx / 2, Kr = 2 * hx;
+  const int mt_n = (nitems + 15) / 16, rows = mt_n * 16;
+  const int Fv = A.nvol, R = skl.R;
+  cf* tws = reinterpret_cast<cf*>(smem);
+  float* Ts = reinterpret_cast<float*>(tws + gx);  // [2][L][R]: C-type then S-type factors
+  float* As = Ts + ((2 * L * R + 3) & ~3);         // [rows][DX_SA]
+  float* Bs = As + rows * DX_SA;                   // [DX_KC][DX_SB]
+  float* S = As;                                   // after the contraction: [rows][DX_SS]
+  for (int i = tid; i < gx; i += 256) tws[i] = tw[i];
+  for (int i = tid; i < L * R; i += 256) {
+    Ts[i] = skl.tc[i];
+    Ts[L * R + i] = skl.ts[i];
+  }
+  const cf* inter = reinterpret_cast<const cf*>(A.inter);
+  static_assert(DX_T == 64 && DX_KC == 64, "fills assume 64 nodes and 32 modes per chunk");
+  const int Xn = (A.ix0 + x0 + (tid & (DX_T - 1))) % gx;  // this thread's node in the B fill
+  const int dX2 = (2 * Xn) % gx;
+  // A fill: thread -> mode pp = tid & 31 of items it = tid >> 5, it + 8, ...
+  const int pp = tid & 31, it0 = tid >> 5;
+  const int nA = (rows + 7) / 8;  // items per thread (<= 32)
+  cf pre[DX_MAXMT * 2];
+  auto fetchA = [&](int p0) {
+#pragma unroll
+    for (int q = 0; q < DX_MAXMT * 2; ++q) {
+      const int item = it0 + 8 * q, p = p0 + pp;
+      cf v = mk(0.f, 0.f);
+      if (q < nA && item < nitems && p < hx) v = inter[((size_t)item * A.wy + r) * G.nxh + p];
+      pre[q] = v;
+    }
+  };
+  constexpr int MTW = DX_MAXMT / 4;  // M tiles per wavefront
+  v4f acc[MTW][4];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  fetchA(0);
+  for (int k0 = 0; k0 < Kr; k0 += DX_KC) {
+    __syncthreads();
+    const int p0 = k0 >> 1;
+#pragma unroll
+    for (int q = 0; q < DX_MAXMT * 2; ++q) {
+      const int item = it0 + 8 * q;
+      if (q < nA && item < rows) *reinterpret_cast<float2*>(&As[item * DX_SA + 2 * pp]) = make_float2(pre[q].x, pre[q].y);
+    }
+    {
+      // thread -> fixed node n and rows kk = tid/64 + 4 i (modes p advancing by 2):
+      // the twiddle index p X mod gx advances by 2 X mod gx
+      const int n = tid & (DX_T - 1), kk0 = tid >> 6;
+      int p = p0 + (kk0 >> 1);
+      int t = (int)(((long long)p * Xn) % gx);
+      for (int kk = kk0; kk < DX_KC; kk += 4, p += 2) {
+        float v = 0.f;
+        if (p < hx) {
+          const cf w = tws[t];  // e^{-i theta}, theta = 2 pi p X / gx
+          const float cp = p == 0 ? 1.f : 2.f;
+          v = (kk & 1) ? cp * w.y : cp * w.x;  // -c_p sin(theta) or c_p cos(theta)
+        }
+        Bs[kk * DX_SB + n] = v;
+        t += dX2;
+        if (t >= gx) t -= gx;
+      }
+    }
+    __syncthreads();
+    if (k0 + DX_KC < Kr) fetchA(p0 + DX_KC / 2);  // next chunk in flight during the products
+#pragma unroll
+    for (int kk = 0; kk < DX_KC; kk += 4) {
+      const int krow = kk + (lane >> 4);
+      float b[4];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) b[nt] = Bs[krow * DX_SB + nt * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) {
+        const int mt = wave + 4 * i;
+        if (mt < mt_n) {
+          const float a = As[(mt * 16 + (lane & 15)) * DX_SA + krow];
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nt], acc[i][nt], 0, 0, 0);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const int mt = wave + 4 * i;
+    if (mt < mt_n) {
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          S[(mt * 16 + 4 * (lane >> 4) + q) * DX_SS + nt * 16 + (lane & 15)] = acc[i][nt][q];
+    }
+  }
+  __syncthreads();
+  // layers: thread -> one coefficient index kidx of every node of the tile
+  const int nvk = L * Fv;
+  const int nodes = min(DX_T, A.wx - x0);
+  for (int kb = 0; kb < K; kb += 256) {
+    const int kidx = kb + tid;
+    if (kidx >= K) break;
+    float* dst = coef + ((size_t)r * A.wx + x0) * K + kidx;
+    if (kidx < nvk) {
+      const int f = kidx / L, l = kidx - f * L;
+      const float* T = Ts + (A.f[f].vf == 1 ? L * R : 0) + l * R;
+      const float* srow = S + (f * R) * DX_SS;
+      for (int n4 = 0; n4 < nodes; n4 += 4) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int j = 0; j < R; ++j) {
+          const float tj = T[j];
+          const float4 sv = *reinterpret_cast<const float4*>(srow + j * DX_SS + n4);
+          v.x += tj * sv.x; v.y += tj * sv.y; v.z += tj * sv.z; v.w += tj * sv.w;
+        }
+        const float vv[4] = {v.x, v.y, v.z, v.w};
+        for (int q = 0; q < 4 && n4 + q < nodes; ++q) dst[(size_t)(n4 + q) * K] = vv[q];
+      }
+    } else {
+      const float* srow = S + (Fv * R + (kidx - nvk)) * DX_SS;
+      for (int n = 0; n < nodes; ++n) dst[(size_t)n * K] = srow[n];
+    }
+  }
+}
+
 __global__ void k_fill(float* p, size_t n, float v) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -508,6 +653,19 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     const int Fv = A.nvol;
     const int L = gd->nl;
     const int K = L * Fv + A.nsurf;
+    const int nitems = Fv * skel->R + A.nsurf;
+    if constexpr (sizeof(R) == 4) {
+      const int rows = (nitems + 15) / 16 * 16;
+      const size_t lds_dft = (size_t)px.n * sizeof(cf) +
+                             ((2ull * L * skel->R + 3) / 4 * 4 + (size_t)rows * DX_SA + (size_t)DX_KC * DX_SB) *
+                                 sizeof(float);
+      if (nitems <= DX_MAXMT * 16 && lds_dft <= 160 * 1024) {
+        dim3 grid((A.wx + DX_T - 1) / DX_T, A.wy);
+        sw_launch(h, SWENSE_K_XEVAL, &k_xcoef_dft, grid, dim3(256), lds_dft, h->st, A, h->G,
+                  reinterpret_cast<const cf*>(px.tw), px.n, *skel, L, K, nitems, out);
+        return;
+      }
+    }
     const int maxitems = std::max(skel->R, A.nsurf);
     const size_t lds = 4ull * wbuf_len(px.n) * csz + (size_t)A.wx * maxitems * sizeof(float);
     SW_REQUIRE(px.n <= (sizeof(R) == 4 ? 4096 : 2048) && lds <= 160 * 1024, "grid row too long for one workgroup");
