@@ -448,6 +448,20 @@ __global__ void __launch_bounds__(256) k_phys_in(const double* in_e, const doubl
   }
 }
 
+// First RK4 stage from a right-hand side already evaluated at the state
+// (the same k the stage would compute): acc = k, sout = xn + dt/2 k.
+__global__ void k_rk_first(const cd* __restrict__ k0, const cd* __restrict__ k1, const cd* __restrict__ x0,
+                           const cd* __restrict__ x1, cd* __restrict__ a0, cd* __restrict__ a1, cd* __restrict__ s0,
+                           cd* __restrict__ s1, double dt, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const cd ka = k0[i], kb = k1[i];
+  a0[i] = ka;
+  a1[i] = kb;
+  s0[i] = x0[i] + cscale(ka, 0.5 * dt);
+  s1[i] = x1[i] + cscale(kb, 0.5 * dt);
+}
+
 __global__ void k_copy_cd(const cd* __restrict__ src, cd* __restrict__ dst, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
@@ -695,6 +709,14 @@ void rhs_t(swense_hos* h, const cd* se, const cd* sp, const RkArgs& rk, bool wan
 
 template <typename R>
 void step_t(swense_hos* h, int nsteps) {
+  if (nsteps <= 0) return;
+  // The first stage reuses the right-hand side of the current state when the
+  // mean-level modes have just evaluated it (the usual CFD coupling: step,
+  // then interpolate); not while a graph is being captured, whose replays
+  // must not depend on what ran before them.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  SW_HIP(hipStreamIsCapturing(h->st, &cap));
+  const bool reuse_k = h->kk_version == h->version && cap == hipStreamCaptureStatusNone;
   for (int n = 0; n < nsteps; ++n) {
     const cd* sin_e[4] = {h->xn[0], h->sa[0], h->sb[0], h->sa[0]};
     const cd* sin_p[4] = {h->xn[1], h->sa[1], h->sb[1], h->sa[1]};
@@ -713,6 +735,12 @@ void step_t(swense_hos* h, int nsteps) {
       rk.sout[1] = sout_p[s];
       rk.acc[0] = h->acc[0];
       rk.acc[1] = h->acc[1];
+      if (s == 0 && n == 0 && reuse_k) {
+        SW_LAUNCH(h, SWENSE_K_AUX, k_rk_first, dim3((h->nc + 255) / 256), dim3(256), 0, h->st, h->kk[0], h->kk[1],
+                  h->xn[0], h->xn[1], h->acc[0], h->acc[1], sout_e[0], sout_p[0], h->d.dt, h->nc);
+        SW_HIP(hipGetLastError());
+        continue;
+      }
       rhs_t<R>(h, sin_e[s], sin_p[s], rk, false);
     }
     h->t += h->d.dt;
@@ -730,6 +758,7 @@ void rhs_only_t(swense_hos* h, bool want_modes) {
   rk.kout[0] = h->kk[0];
   rk.kout[1] = h->kk[1];
   rhs_t<R>(h, h->xn[0], h->xn[1], rk, want_modes);
+  h->kk_version = h->version;
 }
 
 // a6: A = sum phi^(m) (from the series), eta_t (the right-hand side) and A_t

@@ -132,6 +132,7 @@ struct swense_hos {
   double t = 0.0;
   long version = 0;        // bumped whenever the state changes
   long modes_version = -1;  // state version the mean-level modes belong to
+  long kk_version = -1;     // state version whose right-hand side kk holds
   std::string err;
   int device = 0;
 

@@ -150,3 +150,21 @@ def test_nonfinite_state_is_reported(gpu_lib):
         h.state()
     assert ei.value.code == lib.EUNSTABLE
     h.close()
+
+
+def test_first_stage_reuses_the_evaluated_rhs_bitwise(gpu_lib):
+    """Evaluating the mean-level modes between steps leaves the right-hand
+    side of the current state in place; the next step's first RK stage takes
+    it instead of recomputing it, with bit-identical results."""
+    from paper_2005_12716_amd import lib
+    d, g, eh, ph = _case(lib, 3, 32, 16, -1.0, 3)
+    a, b = lib.Hos(d, eh, ph), lib.Hos(d, eh, ph)
+    for _ in range(3):
+        a.step(1)
+        a.modes()
+    b.step(3)
+    ea, pa, ta = a.state()
+    eb, pb, tb = b.state()
+    assert np.array_equal(ea, eb) and np.array_equal(pa, pb) and ta == tb
+    a.close()
+    b.close()
