@@ -141,7 +141,7 @@ def run_surrogate(lib, torch, steps, train_trajectories=100, train_iters=1000):
     zero.close()
     # network-only calls (no audits) and plain HOS on the same sea
     h = T.sea_hos(256, 20.0, 3000)
-    sd = lib.surrogate_desc(tol=1e30, audit_every=1 << 30, cooldown=0, **scales)
+    sd = lib.surrogate_desc(tol=1e30, audit_every=1 << 30, cooldown=0, probation=0, **scales)
     sur = lib.Surrogate(h, net, sd)
     sur.advance(2)
     torch.cuda.synchronize()

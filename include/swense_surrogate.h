@@ -126,6 +126,8 @@ typedef struct swense_surrogate_desc {
   int audit_every;    /* A: every A-th surrogate call is re-run by HOS and judged */
   int cooldown;       /* calls advanced by HOS alone after a fallback             */
   double energy_tol;  /* guard on |E1 - E0| / |E0| per call (<= 0: off)           */
+  int probation;      /* passed audits in a row required before network calls */
+                      /* go unaudited between the A-th ones (0: none)          */
 } swense_surrogate_desc;
 
 /* Counters accumulated by swense_surrogate_advance (zero them before use). */
@@ -160,11 +162,13 @@ int swense_surrogate_target(swense_surrogate* s, const float* x_next, const floa
 
 /* Advance the realisation by ncalls x s HOS steps of time, each call by the
  * network (guards on every call: non-finite values, energy change) or by HOS
- * (cool-down after a fallback).  Every A-th network call, and any call whose
- * guard trips, is judged: HOS re-runs the s steps from the saved state, the
- * relative L2 error of the network's state against it is recorded, and the
- * HOS state is kept; an error above tol (tol = 0: always) or a tripped guard
- * counts as a fallback and starts the cool-down.  Synchronises per call. */
+ * (cool-down after a fallback).  A network call is judged when its guard
+ * trips, when it is the A-th since the last judged one, or while fewer than
+ * `probation` judged calls have passed in a row (from creation and after
+ * every fallback): HOS re-runs the s steps from the saved state, the relative
+ * L2 error of the network's state against it is recorded, and the HOS state
+ * is kept; an error above tol (tol = 0: always) or a tripped guard counts as
+ * a fallback and starts the cool-down.  Synchronises per call. */
 int swense_surrogate_advance(swense_surrogate* s, int ncalls, swense_surrogate_stats* stats);
 
 const char* swense_surrogate_last_error(const swense_surrogate* s);

@@ -23,6 +23,7 @@ struct swense_surrogate {
   void* mem = nullptr;
   int in_channels = 2;     // network input: 2 (state) or 4 (state, linear propagation)
   int cool = 0;            // cool-down calls left
+  int trust = 0;           // judged calls passed in a row
   long long nsur = 0;      // network calls so far (audit counter)
 };
 
@@ -208,7 +209,7 @@ void network_call(swense_surrogate* s, swense_surrogate_stats* st) {
   }
   st->surrogate_calls++;
   s->nsur++;
-  const bool audit = guard || (s->nsur % s->d.audit_every == 0);
+  const bool audit = guard || s->trust < s->d.probation || (s->nsur % s->d.audit_every == 0);
   if (!audit) return;
   // judge: HOS from the saved state; its result is kept
   copy_state(s, h->xn[0], h->xn[1], s->sur[0], s->sur[1]);
@@ -224,6 +225,9 @@ void network_call(swense_surrogate* s, swense_surrogate_stats* st) {
   if (guard || !(err <= s->d.tol)) {
     st->fallbacks++;
     s->cool = s->d.cooldown;
+    s->trust = 0;
+  } else {
+    s->trust++;
   }
 }
 
@@ -254,7 +258,8 @@ int swense_surrogate_create(swense_hos* h, swense_fno* f, const swense_surrogate
     SW_REQUIRE(fno_stream(f) == h->st, "network and realisation must share one stream");
     SW_REQUIRE(fd.in_channels == 2 || fd.in_channels == 4, "network input must have 2 or 4 channels");
     s->in_channels = fd.in_channels;
-    SW_REQUIRE(d->stride_s >= 1 && d->audit_every >= 1 && d->cooldown >= 0, "stride, audit period or cool-down");
+    SW_REQUIRE(d->stride_s >= 1 && d->audit_every >= 1 && d->cooldown >= 0 && d->probation >= 0,
+               "stride, audit period, cool-down or probation");
     SW_REQUIRE(d->sigma_eta > 0.0 && d->sigma_phi > 0.0 && d->rho > 0.0 && d->tol >= 0.0, "scales and tol");
     s->h = h;
     s->f = f;

@@ -47,7 +47,8 @@ class FnoDesc(C.Structure):
 
 class SurrogateDesc(C.Structure):
     _fields_ = [("stride_s", C.c_int), ("sigma_eta", C.c_double), ("sigma_phi", C.c_double), ("rho", C.c_double),
-                ("tol", C.c_double), ("audit_every", C.c_int), ("cooldown", C.c_int), ("energy_tol", C.c_double)]
+                ("tol", C.c_double), ("audit_every", C.c_int), ("cooldown", C.c_int), ("energy_tol", C.c_double),
+                ("probation", C.c_int)]
 
 
 class SurrogateStats(C.Structure):
@@ -523,8 +524,8 @@ def gemm_bf16(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
 
 
 def surrogate_desc(stride_s=10, sigma_eta=1.0, sigma_phi=1.0, rho=1.0, tol=1e-3, audit_every=4, cooldown=4,
-                   energy_tol=0.0):
-    return SurrogateDesc(stride_s, sigma_eta, sigma_phi, rho, tol, audit_every, cooldown, energy_tol)
+                   energy_tol=0.0, probation=2):
+    return SurrogateDesc(stride_s, sigma_eta, sigma_phi, rho, tol, audit_every, cooldown, energy_tol, probation)
 
 
 class Surrogate:

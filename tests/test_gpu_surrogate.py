@@ -128,6 +128,26 @@ def test_nan_weights_trip_the_guard(gpu_lib):
     _close(sur, net, h)
 
 
+def test_probation_judges_calls_until_they_pass(gpu_lib):
+    """A network that never passes (tol = 0) is judged on every call under
+    probation even with a long audit period, so the rollout keeps the HOS state
+    throughout; with tol = inf the first `probation` calls are judged and the
+    rest run unaudited between the A-th ones."""
+    from paper_2005_12716_amd import lib
+    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, tol=0.0, audit_every=1000, cooldown=0, probation=2)
+    st = sur.advance(4)
+    assert st["audits"] == 4 and st["fallbacks"] == 4
+    e, p, t = h.state()
+    er, pr, tr = _hos_ref(lib, d, eh, ph, 4 * S)
+    assert np.array_equal(e, er) and np.array_equal(p, pr)
+    _close(sur, net, h)
+    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, tol=1e30, audit_every=3, cooldown=0, probation=2)
+    st = sur.advance(7)
+    # judged: calls 1, 2 (probation), then every 3rd network call: 3, 6
+    assert st["audits"] == 4 and st["fallbacks"] == 0
+    _close(sur, net, h)
+
+
 def test_energy_guard(gpu_lib):
     from paper_2005_12716_amd import lib
     d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, tol=1.0, audit_every=1000, cooldown=0, energy_tol=1e-14)
@@ -149,7 +169,8 @@ def test_network_call_is_linear_plus_scaled_residual(gpu_lib, depth, in_channels
     state becomes Lin(X) plus rho sigma c2 in the k = 0 modes, with the mean
     of eta kept (mass)."""
     from paper_2005_12716_amd import lib
-    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, depth, in_channels, tol=1.0, audit_every=1000, cooldown=0)
+    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, depth, in_channels, tol=1.0, audit_every=1000, cooldown=0,
+                                                 probation=0)
     net.set(_with_output(lib, vec, desc, [0.75, -0.5]))
     st = sur.advance(2)
     assert st["surrogate_calls"] == 2 and st["audits"] == 0
