@@ -396,6 +396,159 @@ __global__ void __launch_bounds__(256) k_xpass_w(XArgs A, Geom G, WPlan plan) {
   }
 }
 
+// Fused x pass in rounds (power-of-two rows up to 1024 points): each round,
+// the four wavefronts transform one input pair each in their own LDS buffer,
+// and after a block barrier every thread folds the round's rows into the
+// order-M products of its points, held in registers; the inputs are taken in
+// index order as in the single-pass version, so the arithmetic (and the
+// result) is the same, while LDS holds only the four transform buffers and
+// several rows' blocks fit on a CU.  Requires every gradient-pair input at
+// an even index (its partner in the same pair).
+template <int MW, typename R>
+__device__ __forceinline__ R w2sum_n(const R* W, int K) {
+  R s = (R)0;
+#pragma unroll
+  for (int m = 2; m <= MW; ++m)
+#pragma unroll
+    for (int l = 1; l < m; ++l)
+      if (m <= K) s += W[l - 1] * W[m - l - 1];
+  return s;
+}
+
+template <typename R, int MAXE, int NS0, int MW>
+__global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
+  static_assert(NS0 >= 64 && NS0 <= 1024, "rounds version for compile-time rows up to 1024 points");
+  constexpr int PPT = (NS0 + 255) / 256;  // points per thread
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  constexpr int Px = NS0;
+  const int y = blockIdx.x;
+  const int hx = G.nx / 2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wl = wbuf_len(Px);
+  C* bufs = reinterpret_cast<C*>(smem);
+  C* zbuf = bufs + (size_t)wave * wl;
+  R eta[PPT], ge2[PPT], dot[PPT], gp2[PPT], etat[PPT], phit[PPT], W[PPT][MW];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    eta[j] = ge2[j] = dot[j] = gp2[j] = etat[j] = phit[j] = (R)0;
+#pragma unroll
+    for (int m = 0; m < MW; ++m) W[j][m] = (R)0;
+  }
+  const int npairs = (A.nin + 1) / 2;
+  const int nrounds = (npairs + 3) / 4;
+  for (int rd = 0; rd < nrounds; ++rd) {
+    const int pi = 4 * rd + wave;
+    if (pi < npairs) {
+      const XIn& fa = A.in[2 * pi];
+      const bool hasb = 2 * pi + 1 < A.nin;
+      const XIn& fb = A.in[hasb ? 2 * pi + 1 : 2 * pi];
+      for (int s = lane; s < Px; s += 64) {
+        C z = mk((R)0, (R)0);
+        int p = -1;
+        bool cj = false;
+        if (s < hx) p = s;
+        else if (s > Px - hx) { p = Px - s; cj = true; }
+        if (p >= 0) {
+          C va = load_row<R>(fa, y, p, G);
+          C vb = hasb ? load_row<R>(fb, y, p, G) : mk((R)0, (R)0);
+          if (cj) { va = conjg(va); vb = conjg(vb); }
+          z = mk(va.x - vb.y, va.y + vb.x);
+        }
+        zbuf[sk(s)] = z;
+      }
+      wave_sync();
+      wave_fft_any<R, MAXE, NS0>(zbuf, plan, +1, lane);
+    }
+    __syncthreads();
+    const int i1 = min(A.nin, 8 * (rd + 1));
+    for (int i = 8 * rd; i < i1; ++i) {
+      const XIn& f = A.in[i];
+      const C* zb = bufs + (size_t)((i >> 1) - 4 * rd) * wl;
+      const bool hi = i & 1;
+      R c[PPT];
+      if (f.role == XR_G) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+          c[j] = (R)1;
+          for (int k = 1; k <= f.pw; ++k) c[j] *= eta[j] / (R)k;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const int x = threadIdx.x + 256 * j;
+        if (x >= Px) break;
+        const C zx = zb[sk(x)];
+        const R v = hi ? zx.y : zx.x;
+        switch (f.role) {
+          case XR_ETA: eta[j] = v; break;
+          case XR_GRADPAIR: {
+            const R b = zx.y;
+            ge2[j] += v * v;
+            dot[j] += v * b;
+            gp2[j] += b * b;
+          } break;
+          case XR_G:
+#pragma unroll
+            for (int m = 0; m < MW; ++m)
+              if (m == f.wi) W[j][m] += c[j] * v;
+            break;
+          case XR_ETAT: etat[j] = v; break;
+          case XR_PHIT: phit[j] = v; break;
+          default: break;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int M = A.M;
+  C* zout = bufs;  // wavefront 0's buffer
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int x = threadIdx.x + 256 * j;
+    if (x >= Px) break;
+    R o0 = (R)0, o1 = (R)0;
+    if (A.stage == XS_SERIES) {
+      o0 = -W[j][0];
+    } else if (A.stage == XS_FTILDE) {
+      o0 = phit[j];
+      if (M >= 2) o0 -= W[j][0] * etat[j];
+    } else {
+      R wm = (R)0, wm2 = (R)0;
+#pragma unroll
+      for (int m = 0; m < MW; ++m) {
+        if (m < M) wm += W[j][m];
+        if (m < M - 2) wm2 += W[j][m];
+      }
+      o0 = wm - W[j][0];
+      if (M >= 3) o0 += ge2[j] * wm2;
+      if (M >= 2) o0 -= dot[j];
+      o1 = (R)0.5 * w2sum_n<MW>(W[j], M);
+      if (M >= 2) o1 -= (R)0.5 * gp2[j];
+      if (M >= 4) o1 += (R)0.5 * ge2[j] * w2sum_n<MW>(W[j], M - 2);
+    }
+    zout[sk(x)] = mk(o0, o1);
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  wave_fft_any<R, MAXE, NS0>(zout, plan, -1, lane);
+  const R sc = (R)(0.5 / (double)Px);
+  C* d0 = reinterpret_cast<C*>(A.out0);
+  C* d1 = reinterpret_cast<C*>(A.out1);
+  for (int p = lane; p < G.nxh; p += 64) {
+    C o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
+    if (p < hx) {
+      C zp = zout[sk(p)];
+      C zm = conjg(zout[sk((Px - p) % Px)]);
+      C sum = zp + zm, t = zp - zm;
+      o0 = cscale(sum, sc);
+      o1 = mk(t.y * sc, -t.x * sc);
+    }
+    d0[(size_t)y * G.nxh + p] = o0;
+    if (d1) d1[(size_t)y * G.nxh + p] = o1;
+  }
+}
+
 // Physical rows <-> spectra on the mode grid (FP64, state in/out only).
 __global__ void __launch_bounds__(256) k_phys_out(const cd* e_rows, const cd* p_rows, double* out_e, double* out_p,
                                                   Geom G, FftPlan plan) {
@@ -578,6 +731,21 @@ void xpass_t(swense_hos* h, const XArgs& a) {
       if (!seen) b += rows;
     }
     h->prof.bytes[SWENSE_K_XPASS] += b;
+  }
+  // rounds version: power-of-two rows up to 1024 points, order <= 4, every
+  // gradient pair at an even input index
+  bool pairs_ok = true;
+  for (int i = 0; i < a.nin; ++i)
+    if (a.in[i].role == XR_GRADPAIR) pairs_ok = pairs_ok && (i % 2 == 0) && i + 1 < a.nin;
+  if (wave_ok<R>(Px) && pairs_ok && a.M <= 4 && (Px == 256 || Px == 512 || Px == 1024)) {
+    const size_t lds = 4ull * wbuf_len(Px) * sizeof(cpx<R>);
+    const WPlan wp = make_wplan(h->plan_px);
+    switch (Px) {
+      case 256: sw_launch(h, SWENSE_K_XPASS, &k_xpass_r<R, 8, 256, 4>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, wp); break;
+      case 512: sw_launch(h, SWENSE_K_XPASS, &k_xpass_r<R, 8, 512, 4>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, wp); break;
+      default: sw_launch(h, SWENSE_K_XPASS, &k_xpass_r<R, 16, 1024, 4>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, wp); break;
+    }
+    return;
   }
   {
     const size_t lds = 4ull * wbuf_len(Px) * sizeof(cpx<R>) + (size_t)a.nin * Px * sizeof(R);
