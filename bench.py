@@ -338,6 +338,19 @@ def main():
     ms_step = e0.elapsed_time(e1) / args.steps
     print(f"# end-to-end {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # the same step as one captured graph launch (batch of one realisation)
+    gb = lib.Batch([h], [cells], [lib.ALL_FIELDS], [out], nsteps=1)
+    gb.run()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        gb.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / args.steps
+    gb.close()
+    print(f"# graph launch {ms_graph:.3f} ms/step", file=sys.stderr, flush=True)
+
     # HOS step alone
     nh = 4 * args.steps
     e0.record()
@@ -401,6 +414,9 @@ def main():
                                "-> 1,996,800-point cylinder O-mesh, 11 fields, n=4 window, 48 layers",
                    "points": cells.n, "modes": [NX, NY], "order_m": M, "padded": [2 * NX, 2 * NY],
                    "grid": [gx, gy], "window": [ix0, iy0, wx, wy], "layers": int(zl.size)},
+        "eager_ms_per_step": ms_step,
+        "graph_ms_per_step": ms_graph,
+        "graph_cell_field_pts_per_s": cells.n * NFIELDS / (ms_graph / 1e3),
         "hos_steps_per_s": 1e3 / ms_hos,
         "hos_mode_steps_per_s": NX * NY * 1e3 / ms_hos,
         "interp_eval_pts_per_s": cells.n * NFIELDS / (ms_interp / 1e3),

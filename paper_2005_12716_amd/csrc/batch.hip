@@ -90,13 +90,18 @@ void capture(swense_batch* b, int k) {
     for (int j = 0; j < k; ++j) SW_HIP(hipStreamWaitEvent(b->workers[j], b->evs[0], 0));
     for (size_t i = 0; i < b->hos.size(); ++i) {
       b->hos[i]->st = b->workers[i % k];
+      // with cells, each replay ends with the modes (and right-hand side) of
+      // the new state, so the next replay's first RK stage may take it
+      b->hos[i]->graph_reuse_k = b->cells[i] != nullptr;
       enqueue_one(b, (int)i);
+      b->hos[i]->graph_reuse_k = false;
     }
     for (int j = 0; j < k; ++j) {
       SW_HIP(hipEventRecord(b->evs[1 + j], b->workers[j]));
       SW_HIP(hipStreamWaitEvent(b->cap, b->evs[1 + j], 0));
     }
   } catch (...) {
+    for (swense_hos* h : b->hos) h->graph_reuse_k = false;
     hipGraph_t g = nullptr;
     (void)hipStreamEndCapture(b->cap, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -115,8 +120,28 @@ void advance_host(swense_batch* b) {
     swense_hos* h = b->hos[i];
     h->t += b->nsteps * h->d.dt;
     h->version++;
-    if (b->cells[i]) h->modes_version = h->version;  // the graph recomputed the modes last
+    if (b->cells[i]) {
+      // the graph recomputed the modes and the right-hand side last
+      h->modes_version = h->version;
+      h->kk_version = h->version;
+    }
   }
+}
+
+// Before a launch: the first RK stage of realisations with cells takes the
+// right-hand side of the current state, so evaluate it where it is stale.
+void prime(swense_batch* b) {
+  bool any = false;
+  for (size_t i = 0; i < b->hos.size(); ++i) {
+    swense_hos* h = b->hos[i];
+    if (b->cells[i] && h->kk_version != h->version) {
+      hos_prime_rhs(h);
+      any = true;
+    }
+  }
+  if (!any) return;
+  for (size_t i = 0; i < b->hos.size(); ++i)
+    if (b->cells[i]) SW_HIP(hipStreamSynchronize(b->hos[i]->st));
 }
 
 struct Saved {
@@ -151,6 +176,7 @@ double time_graph(swense_batch* b, int reps) {
   hipEvent_t e0, e1;
   SW_HIP(hipEventCreate(&e0));
   SW_HIP(hipEventCreate(&e1));
+  prime(b);
   SW_HIP(hipGraphLaunch(b->exec, b->st));  // warm
   SW_HIP(hipEventRecord(e0, b->st));
   for (int r = 0; r < reps; ++r) SW_HIP(hipGraphLaunch(b->exec, b->st));
@@ -279,6 +305,7 @@ int swense_batch_create(swense_hos* const* hos, swense_cells* const* cells, cons
 int swense_batch_run(swense_batch* b) {
   if (!b || !b->exec) return SWENSE_EINVAL;
   return guarded_b(b, [&] {
+    prime(b);
     SW_HIP(hipGraphLaunch(b->exec, b->st));
     advance_host(b);
     return (int)SWENSE_OK;

@@ -880,11 +880,12 @@ void step_t(swense_hos* h, int nsteps) {
   if (nsteps <= 0) return;
   // The first stage reuses the right-hand side of the current state when the
   // mean-level modes have just evaluated it (the usual CFD coupling: step,
-  // then interpolate); not while a graph is being captured, whose replays
-  // must not depend on what ran before them.
+  // then interpolate).  Under graph capture the owner of the graph decides
+  // (graph_reuse_k): it holds only when every replay ends with the modes of
+  // its new state and the first replay is primed (hos_prime_rhs).
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   SW_HIP(hipStreamIsCapturing(h->st, &cap));
-  const bool reuse_k = h->kk_version == h->version && cap == hipStreamCaptureStatusNone;
+  const bool reuse_k = cap == hipStreamCaptureStatusNone ? h->kk_version == h->version : h->graph_reuse_k;
   for (int n = 0; n < nsteps; ++n) {
     const cd* sin_e[4] = {h->xn[0], h->sa[0], h->sb[0], h->sa[0]};
     const cd* sin_p[4] = {h->xn[1], h->sa[1], h->sb[1], h->sa[1]};
@@ -1137,6 +1138,12 @@ void hos_spec_to_phys(swense_hos* h, const cd* e, const cd* p) {
 void hos_step(swense_hos* h, int nsteps) {
   if (h->fp64) step_t<double>(h, nsteps);
   else step_t<float>(h, nsteps);
+}
+
+void hos_prime_rhs(swense_hos* h) {
+  if (h->kk_version == h->version) return;
+  h->modes_version = -1;
+  launch_modes(h);
 }
 
 double hos_energy(swense_hos* h) {

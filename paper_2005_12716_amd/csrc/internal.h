@@ -133,6 +133,7 @@ struct swense_hos {
   long version = 0;        // bumped whenever the state changes
   long modes_version = -1;  // state version the mean-level modes belong to
   long kk_version = -1;     // state version whose right-hand side kk holds
+  bool graph_reuse_k = false;  // under capture: first RK stage takes kk (the graph's modes refresh it)
   std::string err;
   int device = 0;
 
@@ -223,6 +224,9 @@ void hos_phys_to_spec(swense_hos* h, cd* e, cd* p, bool add);
 void hos_spec_to_phys(swense_hos* h, const cd* e, const cd* p);
 void hos_step(swense_hos* h, int nsteps);
 double hos_energy(swense_hos* h);  // synchronises
+// Make kk the right-hand side of the current state (evaluates the mean-level
+// modes when it is not); asynchronous on h->st.
+void hos_prime_rhs(swense_hos* h);
 // Network handle accessors (the surrogate runs the network on the HOS stream).
 hipStream_t fno_stream(const swense_fno* f);
 swense_fno_desc fno_desc_of(const swense_fno* f);
