@@ -10,8 +10,10 @@ O-mesh around a vertical cylinder of radius 0.1 lambda_p (grid refinement
 n = 4, a 4 x 4 lambda_p window, 48 layers).
 
 One step = one RK4 HOS step + mean-level modes A, A_t + coefficient-grid
-evaluation + interpolation to every cell centre (the whole CFD-side update).
-value = cell-centre field points per second = points x 11 fields / step time.
+evaluation + interpolation to every cell centre (the whole CFD-side update),
+timed both as two calls (step, then interpolate) and as one call that
+interpolates the current state while the step advances it; value = cell-centre
+field points per second = points x 11 fields / the faster step time.
 """
 from __future__ import annotations
 
@@ -338,6 +340,19 @@ def main():
     ms_step = e0.elapsed_time(e1) / args.steps
     print(f"# end-to-end {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # the same work as one call that interpolates the current state while the
+    # step advances it (evaluation + gather concurrent with the HOS step)
+    for _ in range(2):
+        cells.interp_step(lib.ALL_FIELDS, out, 1)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        cells.interp_step(lib.ALL_FIELDS, out, 1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_pipe = e0.elapsed_time(e1) / args.steps
+    print(f"# concurrent interp+step {ms_pipe:.3f} ms/step", file=sys.stderr, flush=True)
+
     # the same step as one captured graph launch (batch of one realisation)
     gb = lib.Batch([h], [cells], [lib.ALL_FIELDS], [out], nsteps=1)
     gb.run()
@@ -399,12 +414,12 @@ def main():
 
     res = {
         "metric": "cell-centre field pts/s (end-to-end CFD update: HOS step + modes + grid + interpolation)",
-        "value": cells.n * NFIELDS / (ms_step / 1e3),
+        "value": cells.n * NFIELDS / (min(ms_step, ms_pipe) / 1e3),
         "unit": "cell-centre field pts/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": min(ms_step, ms_pipe),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -412,9 +427,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "3D JONSWAP 512x256 modes M=3 (40x20 lambda_p, Hs/lambda_p=0.02, gamma=3.3, seed 1) "
                                "-> 1,996,800-point cylinder O-mesh, 11 fields, n=4 window, 48 layers",
+                   "execution": ("interpolation concurrent with the step (swense_interp_step)" if ms_pipe < ms_step
+                                 else "step, then interpolation (swense_hos_step + swense_interp_cells)"),
                    "points": cells.n, "modes": [NX, NY], "order_m": M, "padded": [2 * NX, 2 * NY],
                    "grid": [gx, gy], "window": [ix0, iy0, wx, wy], "layers": int(zl.size)},
         "eager_ms_per_step": ms_step,
+        "concurrent_ms_per_step": ms_pipe,
+        "concurrent_cell_field_pts_per_s": cells.n * NFIELDS / (ms_pipe / 1e3),
         "graph_ms_per_step": ms_graph,
         "graph_cell_field_pts_per_s": cells.n * NFIELDS / (ms_graph / 1e3),
         "hos_steps_per_s": 1e3 / ms_hos,

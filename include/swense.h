@@ -190,6 +190,16 @@ int swense_interp_cells(swense_hos* h, swense_cells* c, unsigned mask, float* ou
  * dw/dz of the interpolant (device FP32 [n], caller order).  Asynchronous. */
 int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div);
 
+/* One CFD coupling step in one call (Sec. 4.3: the incident fields at the
+ * current time are mapped to the cells, then the wave model advances): the
+ * fields of the current state, as swense_interp_cells would produce them, go
+ * to `out` while the state advances by nsteps RK4 steps; the evaluation and
+ * interpolation run on an internal stream concurrently with the step, reading
+ * the modes and a copy of eta taken at the start.  The whole call is ordered
+ * on the handle's stream (work issued after it waits for both halves).
+ * Asynchronous. */
+int swense_interp_step(swense_hos* h, swense_cells* c, unsigned mask, float* out, int nsteps);
+
 /* ---- batched realisations ---------------------------------------------- */
 
 typedef struct swense_batch swense_batch; /* many realisations, one captured graph (opaque) */

@@ -581,7 +581,7 @@ void plan_fields(swense_hos* h, unsigned mask, bool pre, EvArgs& A, int* out_of_
   for (int f : {F_ETA, F_ETAT}) {
     if (srf_slot_of[f] < 0) continue;
     EvField& e = A.f[nv + ns];
-    e.src = f == F_ETA ? h->xn[0] : h->kk[0];
+    e.src = f == F_ETA ? (h->eta_src ? h->eta_src : h->xn[0]) : h->kk[0];
     e.vf = 2;
     e.mult = 0;
     e.out_slot = srf_slot_of[f];

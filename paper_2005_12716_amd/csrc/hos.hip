@@ -1340,8 +1340,13 @@ int swense_profile_bytes(swense_hos* h, int kernel, double* bytes) {
 
 void swense_hos_destroy(swense_hos* h) {
   if (!h) return;
+  if (h->aux) (void)hipStreamSynchronize(h->aux);
   h->prof.release();
   eval_release(h);
+  if (h->eta_snap) (void)hipFree(h->eta_snap);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
   if (h->pool) (void)hipFree(h->pool);
   h->tw.release();
   delete h;

@@ -134,6 +134,13 @@ struct swense_hos {
   long modes_version = -1;  // state version the mean-level modes belong to
   long kk_version = -1;     // state version whose right-hand side kk holds
   bool graph_reuse_k = false;  // under capture: first RK stage takes kk (the graph's modes refresh it)
+  // concurrent interpolation + step (swense_interp_step): a copy of the
+  // surface elevation the evaluation reads while the step advances the state,
+  // an auxiliary stream and two events
+  cd* eta_snap = nullptr;
+  const cd* eta_src = nullptr;  // evaluation source of eta (null: the state)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   int device = 0;
 

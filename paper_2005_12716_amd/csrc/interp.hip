@@ -532,6 +532,23 @@ unsigned coef_mask(unsigned mask, bool three) {
 
 }  // namespace
 
+// Grid evaluation + gather of the current modes into out (on h->st).
+void interp_body(swense_hos* h, swense_cells* c, unsigned mask, float* out) {
+  if (c->n == 0) return;
+  CoefLayout L;
+  refresh(h, c, coef_mask(mask, h->G.ny > 1), &L);
+  GatherArgs A;
+  gather_args(h, c, mask, L, out, A);
+  const size_t lds = (size_t)kColsPerBlock * A.kmax * sizeof(float);
+  SW_REQUIRE(lds <= 160 * 1024, "column profile too long for LDS");
+  if (lds > 65536)
+    SW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather_col),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const unsigned nblk = (unsigned)((c->ncols + kColsPerBlock - 1) / kColsPerBlock);
+  SW_LAUNCH(h, SWENSE_K_INTERP, k_gather_col, dim3(nblk), dim3(64 * kColsPerBlock), lds, h->st, A, c->cols,
+            c->ncols, c->pd);
+}
+
 extern "C" {
 
 int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, const double* xyz,
@@ -623,24 +640,47 @@ int swense_interp_cells(swense_hos* h, swense_cells* c, unsigned mask, float* ou
   return guarded(h, [&] {
     SW_REQUIRE(out != nullptr || c->n == 0, "null output");
     SW_REQUIRE((mask & ~(unsigned)SWENSE_ALL_FIELDS) == 0 && mask != 0, "bad field mask");
-    if (c->n > 0) {
-      CoefLayout L;
-      refresh(h, c, coef_mask(mask, h->G.ny > 1), &L);
-      GatherArgs A;
-      gather_args(h, c, mask, L, out, A);
-      const size_t lds = (size_t)kColsPerBlock * A.kmax * sizeof(float);
-      SW_REQUIRE(lds <= 160 * 1024, "column profile too long for LDS");
-      if (lds > 65536)
-        SW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather_col),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      const unsigned nblk = (unsigned)((c->ncols + kColsPerBlock - 1) / kColsPerBlock);
-      SW_LAUNCH(h, SWENSE_K_INTERP, k_gather_col, dim3(nblk), dim3(64 * kColsPerBlock), lds, h->st, A, c->cols,
-                c->ncols, c->pd);
-    }
+    interp_body(h, c, mask, out);
     if (n_out_of_range) {
       *n_out_of_range = (long long)c->nbad;
       if (c->nbad) return (int)SWENSE_ERANGE;
     }
+    return (int)SWENSE_OK;
+  });
+}
+
+int swense_interp_step(swense_hos* h, swense_cells* c, unsigned mask, float* out, int nsteps) {
+  if (!h || !c || c->h != h || nsteps < 0) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    SW_REQUIRE(out != nullptr || c->n == 0, "null output");
+    SW_REQUIRE((mask & ~(unsigned)SWENSE_ALL_FIELDS) == 0 && mask != 0, "bad field mask");
+    if (!h->aux) {
+      SW_HIP(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+      SW_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+      SW_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    }
+    if (!h->eta_snap) SW_HIP(hipMalloc(&h->eta_snap, h->nc * sizeof(cd)));
+    // modes (and right-hand side) of the current state, and a copy of eta that
+    // the evaluation reads while the step rewrites the state
+    launch_modes(h);
+    SW_HIP(hipMemcpyAsync(h->eta_snap, h->xn[0], h->nc * sizeof(cd), hipMemcpyDeviceToDevice, h->st));
+    SW_HIP(hipEventRecord(h->ev_fork, h->st));
+    SW_HIP(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+    hipStream_t main = h->st;
+    h->st = h->aux;
+    h->eta_src = h->eta_snap;
+    try {
+      interp_body(h, c, mask, out);
+    } catch (...) {
+      h->st = main;
+      h->eta_src = nullptr;
+      throw;
+    }
+    h->st = main;
+    h->eta_src = nullptr;
+    SW_HIP(hipEventRecord(h->ev_join, h->aux));
+    hos_step(h, nsteps);
+    SW_HIP(hipStreamWaitEvent(h->st, h->ev_join, 0));
     return (int)SWENSE_OK;
   });
 }

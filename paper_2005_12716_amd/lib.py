@@ -94,6 +94,7 @@ def load():
         "swense_cells_bind": (C.c_int, [vp, C.POINTER(GridDesc), C.c_longlong, vp, C.POINTER(vp)]),
         "swense_interp_cells": (C.c_int, [vp, vp, C.c_uint, fp, C.POINTER(C.c_longlong)]),
         "swense_interp_divergence": (C.c_int, [vp, vp, fp]),
+        "swense_interp_step": (C.c_int, [vp, vp, C.c_uint, fp, C.c_int]),
         "swense_profile_enable": (C.c_int, [vp, C.c_int]),
         "swense_profile_read": (C.c_int, [vp, C.c_int, dp, C.POINTER(C.c_longlong)]),
         "swense_profile_bytes": (C.c_int, [vp, C.c_int, dp]),
@@ -134,7 +135,7 @@ def load():
 EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swense_hos_init",
             "swense_hos_set_state", "swense_hos_step", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
-            "swense_cells_bind", "swense_interp_cells", "swense_interp_divergence", "swense_profile_enable",
+            "swense_cells_bind", "swense_interp_cells", "swense_interp_divergence", "swense_interp_step", "swense_profile_enable",
             "swense_profile_read", "swense_profile_bytes", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
             "swense_batch_last_error", "swense_batch_destroy", "swense_hos_destroy",
             "swense_cells_destroy", "swense_fno_param_count", "swense_fno_create", "swense_fno_forward",
@@ -316,6 +317,14 @@ class Cells:
         if rc not in (OK, ERANGE):
             self.hos._check(rc, "interp_cells")
         return out, (nbad.value if count else None)
+
+    def interp_step(self, mask, out=None, nsteps=1):
+        """Fields of the current state into out while the state advances nsteps."""
+        nf = bin(mask).count("1")
+        if out is None:
+            out = torch.empty((nf, self.n), dtype=torch.float32, device="cuda")
+        self.hos._check(self.hos.L.swense_interp_step(self.hos.h, self.c, mask, _ptr(out), nsteps), "interp_step")
+        return out
 
     def divergence(self, out=None):
         if out is None:
