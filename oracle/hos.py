@@ -124,6 +124,55 @@ def rk4_step(grid: Grid, eta_hat, phis_hat, dt: float):
     return e, p
 
 
+def linear_propagate(grid: Grid, eta_hat, phis_hat, tau: float):
+    """Exact solution over tau of the linear part of the evolution (the
+    M = 1 equations eta_t = k tanh(kh) phis, phis_t = -g eta), mode by mode:
+    eta <- cos(w tau) eta + (kt/w) sin(w tau) phis, phis <- cos(w tau) phis -
+    (g/w) sin(w tau) eta with kt = k tanh(kh) (deep: k), w = sqrt(g kt);
+    k = 0: phis <- phis - g tau eta."""
+    _, _, K = grid.kvec()
+    kt = K * np.tanh(K * grid.depth) if grid.depth > 0 else K
+    w = np.sqrt(grid.g * kt)
+    c, s = np.cos(w * tau), np.sin(w * tau)
+    safe = np.where(w > 0, w, 1.0)
+    a = np.where(w > 0, kt * s / safe, 0.0)
+    b = np.where(w > 0, grid.g * s / safe, grid.g * tau)
+    return c * eta_hat + a * phis_hat, c * phis_hat - b * eta_hat
+
+
+def nonlinear_rhs(grid: Grid, eta_hat, phis_hat):
+    """The right-hand side minus its linear part (kt phis, -g eta)."""
+    _, _, K = grid.kvec()
+    kt = K * np.tanh(K * grid.depth) if grid.depth > 0 else K
+    et, pt = rhs(grid, eta_hat, phis_hat)
+    ne = et - kt * phis_hat * grid.nyquist_mask()
+    ne[0, 0] = 0.0
+    return ne, pt + grid.g * eta_hat * grid.nyquist_mask()
+
+
+def ifrk4_step(grid: Grid, eta_hat, phis_hat, h: float):
+    """One integrating-factor (Lawson) RK4 step of size h: classical RK4 on
+    v(t) = E(-t) X(t), E the exact linear propagator, so that only the
+    nonlinear part N is integrated numerically:
+      k1 = N(X), k2 = N(E_h/2 (X + h/2 k1)), k3 = N(E_h/2 X + h/2 k2),
+      k4 = N(E_h X + h E_h/2 k3),
+      X <- E_h X + h/6 (E_h k1 + 2 E_h/2 (k2 + k3) + k4).
+    (A time integrator for the surrogate's base step, not in the paper.)"""
+    def E(x, t):
+        return linear_propagate(grid, x[0], x[1], t)
+
+    def add(x, y, a=1.0):
+        return x[0] + a * y[0], x[1] + a * y[1]
+
+    X = (eta_hat, phis_hat)
+    k1 = nonlinear_rhs(grid, *X)
+    k2 = nonlinear_rhs(grid, *E(add(X, k1, 0.5 * h), 0.5 * h))
+    k3 = nonlinear_rhs(grid, *add(E(X, 0.5 * h), k2, 0.5 * h))
+    k4 = nonlinear_rhs(grid, *add(E(X, h), E(k3, 0.5 * h), h))
+    s = add(add(E(k1, h), E(add(k2, k3), 0.5 * h), 2.0), k4)
+    return add(E(X, h), s, h / 6.0)
+
+
 def run(grid: Grid, eta_hat, phis_hat, dt: float, nsteps: int, callback=None):
     for n in range(nsteps):
         eta_hat, phis_hat = rk4_step(grid, eta_hat, phis_hat, dt)
