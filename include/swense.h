@@ -140,6 +140,14 @@ int swense_hos_set_state(swense_hos* h, const double* eta, const double* phis, i
 /* Advance nsteps classical RK4 steps of size dt.  Asynchronous. */
 int swense_hos_step(swense_hos* h, int nsteps);
 
+/* Advance by a time tau with nsub integrating-factor (Lawson) RK4 substeps:
+ * classical RK4 on the state expressed in the frame of the exact linear
+ * evolution (per mode rotation with omega^2 = g k tanh(kh)), so that only the
+ * nonlinear part of the right-hand side of Sec. 3.1.2 is integrated
+ * numerically.  A coarse step for the surrogate's base prediction; the
+ * reference integrator stays swense_hos_step.  Asynchronous. */
+int swense_hos_step_exp(swense_hos* h, double tau, int nsub);
+
 /* Copy the state to host arrays in `layout` (eta, phis may be NULL) and the
  * time to *t (may be NULL).  Synchronises the handle's stream.  Returns
  * EUNSTABLE if the state holds a non-finite value. */

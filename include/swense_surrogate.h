@@ -110,9 +110,10 @@ int swense_gemm_bf16(int M, int N, int K, const float* A, const float* B, float*
 /* Surrogate call: with X = (eta, phis) the physical surface state of a square
  * realisation (nx = ny = n of the network), the network input is
  * x = (eta / sigma_eta, phis / sigma_phi), followed for a 4-channel network
- * by the same scaling of Lin_{s dt} X, and its output y gives
- *   X(t + s dt) = Lin_{s dt} X(t) + rho (sigma_eta y_0, sigma_phi y_1),
- * Lin_tau the exact linear propagator, mode by mode with omega^2 = g k tanh(kh)
+ * by the same scaling of the base prediction B(X), and its output y gives
+ *   X(t + s dt) = B(X(t)) + rho (sigma_eta y_0, sigma_phi y_1),
+ * B either Lin_{s dt} or a coarse integrating-factor RK4 step over s dt
+ * (base_substeps).  Lin_tau is the exact linear propagator, mode by mode with omega^2 = g k tanh(kh)
  * (deep water: g k): eta <- cos(w tau) eta + (k tanh(kh)/w) sin(w tau) phis,
  * phis <- cos(w tau) phis - (g/w) sin(w tau) eta; k = 0: phis <- phis - g tau
  * eta.  The mean of eta (k = 0) is kept from X(t): mass is conserved as in
@@ -128,6 +129,9 @@ typedef struct swense_surrogate_desc {
   double energy_tol;  /* guard on |E1 - E0| / |E0| per call (<= 0: off)           */
   int probation;      /* passed audits in a row required before network calls */
                       /* go unaudited between the A-th ones (0: none)          */
+  int base_substeps;  /* base prediction B: 0 = Lin_{s dt} (exact linear        */
+                      /* propagation); n > 0 = n integrating-factor RK4        */
+                      /* substeps over s dt (swense_hos_step_exp)              */
 } swense_surrogate_desc;
 
 /* Counters accumulated by swense_surrogate_advance (zero them before use). */
@@ -150,12 +154,13 @@ typedef struct swense_surrogate swense_surrogate; /* (opaque) */
 int swense_surrogate_create(swense_hos* h, swense_fno* f, const swense_surrogate_desc* d, swense_surrogate** out);
 
 /* Network input of the current state, x (device [2][n][n] FP32), and, when
- * lin is non-NULL, the scaled fields of Lin_{s dt} of the current state in
- * the same units (device [2][n][n]).  Training data come from these two and
- * swense_surrogate_target.  Asynchronous. */
+ * lin is non-NULL, the scaled fields of the base prediction B of the current
+ * state in the same units (device [2][n][n]); the state is left unchanged.
+ * Training data come from these two and swense_surrogate_target.
+ * Asynchronous. */
 int swense_surrogate_features(swense_surrogate* s, float* x, float* lin);
 
-/* Training target of a pair: t = (x_next - lin) / rho, elementwise over
+/* Training target of a pair: t = (x_next - base) / rho, elementwise over
  * [2][n][n] (x_next: features of the state s steps later; lin: from
  * swense_surrogate_features at the earlier state).  Asynchronous. */
 int swense_surrogate_target(swense_surrogate* s, const float* x_next, const float* lin, float* t);

@@ -174,6 +174,11 @@ __device__ __forceinline__ void yfwd_epilogue(const YFwdJob& jb, const RkArgs& r
     else if (jb.acc_mode == 2) jb.acc[idx] = v;
     return;
   }
+  if (jb.epi == YE_NL_ETA || jb.epi == YE_NL_PHI) {
+    const bool eta = jb.epi == YE_NL_ETA;
+    rk.kout[eta ? 0 : 1][idx] = (eta && p == 0 && q == 0) ? mk(0.0, 0.0) : v;
+    return;
+  }
   const int w = jb.epi == YE_RHS_ETA ? 0 : 1;
   cd k = v;
   if (w == 0) {
@@ -601,6 +606,72 @@ __global__ void __launch_bounds__(256) k_phys_in(const double* in_e, const doubl
   }
 }
 
+// Exact linear propagator over t of mode (a, b) = (eta, phis) with wavenumber k.
+__device__ __forceinline__ void lin_prop(const Geom& G, double k, double t, cd& a, cd& b) {
+  if (k == 0.0) {
+    b = b - cscale(a, G.g * t);
+    return;
+  }
+  const double kt = G.depth > 0.0 ? k * tanh(k * G.depth) : k;
+  const double w = sqrt(G.g * kt);
+  const double c = cos(w * t), s = sin(w * t);
+  const cd na = cscale(a, c) + cscale(b, kt * s / w);
+  const cd nb = cscale(b, c) - cscale(a, G.g * s / w);
+  a = na;
+  b = nb;
+}
+
+// Integrating-factor (Lawson) RK4 stage update per mode, E_t the exact
+// linear propagator, k the nonlinear part at the stage input:
+//   1: acc = E_h k1,        next = E_h/2 (x + h/2 k1)
+//   2: acc += 2 E_h/2 k2,   next = E_h/2 x + h/2 k2
+//   3: acc += 2 E_h/2 k3,   next = E_h x + h E_h/2 k3
+//   4: x = E_h x + h/6 (acc + k4)
+__global__ void k_ifrk4(int stage, cd* __restrict__ x0, cd* __restrict__ x1, const cd* __restrict__ k0,
+                        const cd* __restrict__ k1, cd* __restrict__ a0, cd* __restrict__ a1, cd* __restrict__ s0,
+                        cd* __restrict__ s1, Geom G, double hh) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)G.ny * G.nxh) return;
+  const int q = (int)(i / G.nxh), p = (int)(i % G.nxh);
+  const double kx = 2.0 * M_PI * (double)p / G.lx;
+  const double ky = G.ny > 1 ? 2.0 * M_PI * (double)signed_q(q, G.ny) / G.ly : 0.0;
+  const double k = sqrt(kx * kx + ky * ky);
+  const cd ke = k0[i], kp = k1[i];
+  const cd xe = x0[i], xp = x1[i];
+  if (stage == 1) {
+    cd ae = ke, ap = kp;
+    lin_prop(G, k, hh, ae, ap);
+    a0[i] = ae;
+    a1[i] = ap;
+    cd se = xe + cscale(ke, 0.5 * hh), sp = xp + cscale(kp, 0.5 * hh);
+    lin_prop(G, k, 0.5 * hh, se, sp);
+    s0[i] = se;
+    s1[i] = sp;
+  } else if (stage == 2 || stage == 3) {
+    cd he = ke, hp = kp;
+    lin_prop(G, k, 0.5 * hh, he, hp);
+    a0[i] = a0[i] + cscale(he, 2.0);
+    a1[i] = a1[i] + cscale(hp, 2.0);
+    cd se = xe, sp = xp;
+    if (stage == 2) {
+      lin_prop(G, k, 0.5 * hh, se, sp);
+      se = se + cscale(ke, 0.5 * hh);
+      sp = sp + cscale(kp, 0.5 * hh);
+    } else {
+      lin_prop(G, k, hh, se, sp);
+      se = se + cscale(he, hh);
+      sp = sp + cscale(hp, hh);
+    }
+    s0[i] = se;
+    s1[i] = sp;
+  } else {
+    cd ne = xe, np = xp;
+    lin_prop(G, k, hh, ne, np);
+    x0[i] = ne + cscale(a0[i] + ke, hh / 6.0);
+    x1[i] = np + cscale(a1[i] + kp, hh / 6.0);
+  }
+}
+
 // First RK4 stage from a right-hand side already evaluated at the state
 // (the same k the stage would compute): acc = k, sout = xn + dt/2 k.
 __global__ void k_rk_first(const cd* __restrict__ k0, const cd* __restrict__ k1, const cd* __restrict__ x0,
@@ -694,6 +765,7 @@ void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t s
       const YFwdJob& jb = a.job[j];
       double per = 0.0;
       if (jb.epi == YE_STORE) per = c16 + (jb.acc_mode == 1 ? 2 * c16 : jb.acc_mode == 2 ? c16 : 0.0);
+      else if (jb.epi == YE_NL_ETA || jb.epi == YE_NL_PHI) per = c16;
       else {
         const int st4 = a.rk.stage;  // sin read; then stage-dependent state traffic
         per = c16 + (st4 == 0 ? c16 : st4 == 1 ? 3 * c16 : st4 <= 3 ? 4 * c16 : 3 * c16);
@@ -821,7 +893,7 @@ void series_t(swense_hos* h, cd** modes, cd* accum, int extra) {
 }
 
 template <typename R>
-void rhs_t(swense_hos* h, const cd* se, const cd* sp, const RkArgs& rk, bool want_modes) {
+void rhs_t(swense_hos* h, const cd* se, const cd* sp, const RkArgs& rk, bool want_modes, bool nl_only = false) {
   const int M = h->d.order_m;
   const bool three = h->G.ny > 1;
   YInvArgs ya;
@@ -868,9 +940,9 @@ void rhs_t(swense_hos* h, const cd* se, const cd* sp, const RkArgs& rk, bool wan
   std::memset(&fa, 0, sizeof(fa));
   fa.njobs = 2;
   fa.job[0].src = h->r0_;
-  fa.job[0].epi = YE_RHS_ETA;
+  fa.job[0].epi = nl_only ? YE_NL_ETA : YE_RHS_ETA;
   fa.job[1].src = h->r1_;
-  fa.job[1].epi = YE_RHS_PHI;
+  fa.job[1].epi = nl_only ? YE_NL_PHI : YE_RHS_PHI;
   fa.rk = rk;
   yfwd_t<R>(h, fa, h->plan_py, h->st);
 }
@@ -913,6 +985,27 @@ void step_t(swense_hos* h, int nsteps) {
       rhs_t<R>(h, sin_e[s], sin_p[s], rk, false);
     }
     h->t += h->d.dt;
+  }
+  h->version++;
+}
+
+template <typename R>
+void step_exp_t(swense_hos* h, double tau, int nsub) {
+  const double hh = tau / nsub;
+  for (int n = 0; n < nsub; ++n) {
+    for (int s = 1; s <= 4; ++s) {
+      const cd* se = s == 1 ? h->xn[0] : h->sa[0];
+      const cd* sp = s == 1 ? h->xn[1] : h->sa[1];
+      RkArgs rk;
+      std::memset(&rk, 0, sizeof(rk));
+      rk.kout[0] = h->sb[0];
+      rk.kout[1] = h->sb[1];
+      rhs_t<R>(h, se, sp, rk, false, true);
+      SW_LAUNCH(h, SWENSE_K_AUX, k_ifrk4, dim3((h->nc + 255) / 256), dim3(256), 0, h->st, s, h->xn[0], h->xn[1],
+                h->sb[0], h->sb[1], h->acc[0], h->acc[1], h->sa[0], h->sa[1], h->G, hh);
+      SW_HIP(hipGetLastError());
+    }
+    h->t += hh;
   }
   h->version++;
 }
@@ -1140,6 +1233,12 @@ void hos_step(swense_hos* h, int nsteps) {
   else step_t<float>(h, nsteps);
 }
 
+void hos_step_exp(swense_hos* h, double tau, int nsub) {
+  SW_REQUIRE(nsub >= 1 && tau >= 0.0, "nsub >= 1 and tau >= 0");
+  if (h->fp64) step_exp_t<double>(h, tau, nsub);
+  else step_exp_t<float>(h, tau, nsub);
+}
+
 void hos_prime_rhs(swense_hos* h) {
   if (h->kk_version == h->version) return;
   h->modes_version = -1;
@@ -1236,6 +1335,14 @@ int swense_hos_step(swense_hos* h, int nsteps) {
   return guarded(h, [&] {
     SW_REQUIRE(nsteps >= 0, "nsteps must be >= 0");
     hos_step(h, nsteps);
+    return SWENSE_OK;
+  });
+}
+
+int swense_hos_step_exp(swense_hos* h, double tau, int nsub) {
+  if (!h) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    hos_step_exp(h, tau, nsub);
     return SWENSE_OK;
   });
 }

@@ -61,7 +61,8 @@ struct XArgs {
 };
 
 // Epilogue of the forward y transform.
-enum YEpi { YE_STORE = 0, YE_RHS_ETA = 1, YE_RHS_PHI = 2 };
+// YE_NL_*: store the nonlinear part of the right-hand side only (kout).
+enum YEpi { YE_STORE = 0, YE_RHS_ETA = 1, YE_RHS_PHI = 2, YE_NL_ETA = 3, YE_NL_PHI = 4 };
 
 struct YFwdJob {
   const void* src;  // [Py][nxh] complex rows
@@ -230,6 +231,9 @@ void hos_phys_to_spec(swense_hos* h, cd* e, cd* p, bool add);
 // Half spectra (e, p) -> physical fields at h->phys.
 void hos_spec_to_phys(swense_hos* h, const cd* e, const cd* p);
 void hos_step(swense_hos* h, int nsteps);
+// Advance by tau with nsub integrating-factor RK4 substeps (exact linear
+// propagation, RK4 on the nonlinear part).
+void hos_step_exp(swense_hos* h, double tau, int nsub);
 double hos_energy(swense_hos* h);  // synchronises
 // Make kk the right-hand side of the current state (evaluates the mean-level
 // modes when it is not); asynchronous on h->st.

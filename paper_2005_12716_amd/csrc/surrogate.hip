@@ -148,6 +148,19 @@ void linear_into(swense_surrogate* s, const cd* e, const cd* p, cd* oe, cd* op) 
   SW_HIP(hipGetLastError());
 }
 
+// State <- B(from): linear propagation, or integrating-factor RK4 substeps
+// run in place on the state (the caller restores the time).
+void base_into_state(swense_surrogate* s, const cd* e, const cd* p) {
+  swense_hos* h = s->h;
+  if (s->d.base_substeps <= 0) {
+    linear_into(s, e, p, h->xn[0], h->xn[1]);
+    return;
+  }
+  if (e != h->xn[0]) copy_state(s, e, p, h->xn[0], h->xn[1]);
+  h->version++;
+  hos_step_exp(h, tau_of(s), s->d.base_substeps);
+}
+
 bool state_finite(swense_surrogate* s) {
   swense_hos* h = s->h;
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, h->st, s->sums, 0, s->bad);
@@ -188,7 +201,7 @@ void network_call(swense_surrogate* s, swense_surrogate_stats* st) {
   const double E0 = eguard ? hos_energy(h) : 0.0;
   const long long np = (long long)h->G.nx * h->G.ny;
   features_of(s, s->backup[0], s->backup[1], s->x);
-  linear_into(s, s->backup[0], s->backup[1], h->xn[0], h->xn[1]);
+  base_into_state(s, s->backup[0], s->backup[1]);
   if (s->in_channels == 4) features_of(s, h->xn[0], h->xn[1], s->x + 2 * np);
   const int rc = swense_fno_forward(s->f, s->x, s->y, 1);
   if (rc != SWENSE_OK) throw SwenseError{rc, "network forward failed"};
@@ -258,8 +271,9 @@ int swense_surrogate_create(swense_hos* h, swense_fno* f, const swense_surrogate
     SW_REQUIRE(fno_stream(f) == h->st, "network and realisation must share one stream");
     SW_REQUIRE(fd.in_channels == 2 || fd.in_channels == 4, "network input must have 2 or 4 channels");
     s->in_channels = fd.in_channels;
-    SW_REQUIRE(d->stride_s >= 1 && d->audit_every >= 1 && d->cooldown >= 0 && d->probation >= 0,
-               "stride, audit period, cool-down or probation");
+    SW_REQUIRE(d->stride_s >= 1 && d->audit_every >= 1 && d->cooldown >= 0 && d->probation >= 0 &&
+                   d->base_substeps >= 0 && d->base_substeps <= 64,
+               "stride, audit period, cool-down, probation or base substeps");
     SW_REQUIRE(d->sigma_eta > 0.0 && d->sigma_phi > 0.0 && d->rho > 0.0 && d->tol >= 0.0, "scales and tol");
     s->h = h;
     s->f = f;
@@ -296,8 +310,19 @@ int swense_surrogate_features(swense_surrogate* s, float* x, float* lin) {
     swense_hos* h = s->h;
     features_of(s, h->xn[0], h->xn[1], x);
     if (lin) {
-      linear_into(s, h->xn[0], h->xn[1], s->sur[0], s->sur[1]);
-      features_of(s, s->sur[0], s->sur[1], lin);
+      if (s->d.base_substeps <= 0) {
+        linear_into(s, h->xn[0], h->xn[1], s->sur[0], s->sur[1]);
+        features_of(s, s->sur[0], s->sur[1], lin);
+      } else {
+        // base step on the state, then the state back (bit for bit)
+        const double t0 = h->t;
+        copy_state(s, h->xn[0], h->xn[1], s->sur[0], s->sur[1]);
+        base_into_state(s, h->xn[0], h->xn[1]);
+        features_of(s, h->xn[0], h->xn[1], lin);
+        copy_state(s, s->sur[0], s->sur[1], h->xn[0], h->xn[1]);
+        h->t = t0;
+        h->version++;
+      }
     }
     return (int)SWENSE_OK;
   });

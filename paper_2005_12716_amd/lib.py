@@ -48,7 +48,7 @@ class FnoDesc(C.Structure):
 class SurrogateDesc(C.Structure):
     _fields_ = [("stride_s", C.c_int), ("sigma_eta", C.c_double), ("sigma_phi", C.c_double), ("rho", C.c_double),
                 ("tol", C.c_double), ("audit_every", C.c_int), ("cooldown", C.c_int), ("energy_tol", C.c_double),
-                ("probation", C.c_int)]
+                ("probation", C.c_int), ("base_substeps", C.c_int)]
 
 
 class SurrogateStats(C.Structure):
@@ -85,6 +85,7 @@ def load():
         "swense_hos_init": (C.c_int, [C.POINTER(HosDesc), vp, vp, C.c_int, vp, C.POINTER(vp)]),
         "swense_hos_set_state": (C.c_int, [vp, vp, vp, C.c_int, C.c_double]),
         "swense_hos_step": (C.c_int, [vp, C.c_int]),
+        "swense_hos_step_exp": (C.c_int, [vp, C.c_double, C.c_int]),
         "swense_hos_get_state": (C.c_int, [vp, vp, vp, dp, C.c_int]),
         "swense_hos_rhs": (C.c_int, [vp, vp, vp]),
         "swense_hos_modes": (C.c_int, [vp, vp, vp, vp]),
@@ -133,7 +134,7 @@ def load():
 
 
 EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swense_hos_init",
-            "swense_hos_set_state", "swense_hos_step", "swense_hos_get_state", "swense_hos_rhs",
+            "swense_hos_set_state", "swense_hos_step", "swense_hos_step_exp", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
             "swense_cells_bind", "swense_interp_cells", "swense_interp_divergence", "swense_interp_step", "swense_profile_enable",
             "swense_profile_read", "swense_profile_bytes", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
@@ -206,6 +207,10 @@ class Hos:
 
     def step(self, n=1):
         self._check(self.L.swense_hos_step(self.h, n), "step")
+
+    def step_exp(self, tau, nsub=1):
+        """Advance by tau with nsub integrating-factor RK4 substeps."""
+        self._check(self.L.swense_hos_step_exp(self.h, tau, nsub), "step_exp")
 
     def set_state(self, eta, phis, layout=SPECTRAL, t=0.0):
         eta = np.ascontiguousarray(eta, dtype=np.complex128 if layout == SPECTRAL else np.float64)
@@ -533,8 +538,9 @@ def gemm_bf16(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
 
 
 def surrogate_desc(stride_s=10, sigma_eta=1.0, sigma_phi=1.0, rho=1.0, tol=1e-3, audit_every=4, cooldown=4,
-                   energy_tol=0.0, probation=2):
-    return SurrogateDesc(stride_s, sigma_eta, sigma_phi, rho, tol, audit_every, cooldown, energy_tol, probation)
+                   energy_tol=0.0, probation=2, base_substeps=0):
+    return SurrogateDesc(stride_s, sigma_eta, sigma_phi, rho, tol, audit_every, cooldown, energy_tol, probation,
+                         base_substeps)
 
 
 class Surrogate:

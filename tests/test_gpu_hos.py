@@ -168,3 +168,22 @@ def test_first_stage_reuses_the_evaluated_rhs_bitwise(gpu_lib):
     assert np.array_equal(ea, eb) and np.array_equal(pa, pb) and ta == tb
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision,nsub,depth", [(0, 1, -1.0), (0, 2, 1.5), (1, 2, -1.0)])
+def test_integrating_factor_step_matches_oracle(gpu_lib, precision, nsub, depth):
+    """The coarse integrating-factor RK4 step (the surrogate's base) against
+    the oracle's: FP32 transforms of the nonlinear part (1e-6), FP64 (1e-12)."""
+    from paper_2005_12716_amd import lib
+    d, g, eh, ph = _case(lib, 3, 32, 16, depth, 3, precision=precision)
+    h = lib.Hos(d, eh, ph)
+    tau = 10 * d.dt
+    h.step_exp(tau, nsub)
+    e, p, t = h.state()
+    er, pr = eh, ph
+    for _ in range(nsub):
+        er, pr = hos.ifrk4_step(g, er, pr, tau / nsub)
+    tol = 1e-6 if precision == 0 else 1e-12
+    assert rel(e, er) < tol and rel(p, pr) < tol
+    assert abs(t - tau) < 1e-12
+    h.close()

@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import synth
-from oracle import Grid, fno as F
+from oracle import Grid, hos, fno as F
 
 pytestmark = pytest.mark.gpu
 LAM = 2 * math.pi
@@ -183,4 +183,30 @@ def test_network_call_is_linear_plus_scaled_residual(gpu_lib, depth, in_channels
     assert np.abs(e - er).max() <= 1e-13 * np.abs(er).max()
     assert np.abs(p - pr).max() <= 1e-13 * np.abs(pr).max()
     assert abs(t - 2 * S * d.dt) < 1e-12
+    _close(sur, net, h)
+
+
+def test_network_call_over_the_integrating_factor_base(gpu_lib):
+    """With the coarse integrating-factor RK4 base and a constant network
+    output the state becomes the oracle's integrating-factor step plus the
+    scaled residual in the k = 0 mode of phis (eta's mean kept)."""
+    from paper_2005_12716_amd import lib
+    d, eh, ph, h, desc, vec, net, sur, sd = _sur(lib, -1.0, 4, tol=1.0, audit_every=1000, cooldown=0, probation=0,
+                                                 base_substeps=1)
+    net.set(_with_output(lib, vec, desc, [0.75, -0.5]))
+    x, base = sur.features()
+    e0, p0, t0 = h.state()
+    assert np.array_equal(e0, eh) and t0 == 0.0  # features leave the state unchanged
+    sur.advance(1)
+    e, p, t = h.state()
+    g = _grid(d)
+    er, pr = hos.ifrk4_step(g, eh, ph, S * d.dt)
+    pr = pr.copy()
+    pr[0, 0] += sd.rho * sd.sigma_phi * (-0.5)
+    er = er.copy()
+    er[0, 0] = eh[0, 0]
+    assert np.linalg.norm(e - er) <= 1e-6 * np.linalg.norm(er)
+    assert np.linalg.norm(p - pr) <= 1e-6 * np.linalg.norm(pr)
+    ref_base = g.to_phys(hos.ifrk4_step(g, eh, ph, S * d.dt)[0], (N, N)) / sd.sigma_eta
+    assert np.linalg.norm(base.cpu().numpy()[0] - ref_base) <= 1e-6 * np.linalg.norm(ref_base)
     _close(sur, net, h)

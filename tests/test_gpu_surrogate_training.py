@@ -25,7 +25,7 @@ def test_trained_network_beats_linear_propagation(gpu_lib, in_channels):
     assert np.mean(hist[-50:]) < 0.5 * np.mean(hist[:20])
     zero = lib.Fno(desc, T.zero_output(desc, vec0))
     errs = T.one_call_errors(net, scales, range(3000, 3004), 5, 5.0, zero)
-    e_net, e_lin = errs["network"].mean(), errs["linear_only"].mean()
+    e_net, e_lin = errs["network"].mean(), errs["base_only"].mean()
     print(f"in_channels {in_channels} one-call relative error: network {e_net:.3e}, linear only {e_lin:.3e}, "
           f"loss {np.mean(hist[:20]):.3e} -> {np.mean(hist[-50:]):.3e}")
     assert np.isfinite(e_net) and e_net < e_lin
