@@ -115,7 +115,7 @@ def run_batched(lib, torch, steps):
     return res
 
 
-def run_surrogate(lib, torch, steps, train_trajectories=100, train_iters=1000, base_substeps=1):
+def run_surrogate(lib, torch, steps, train_trajectories=100, train_iters=1000, base_substeps=2):
     """The learned configuration: the spectral neural operator (256^2 over 20
     lambda_p, 64 channels, 8 layers, p < 32, |q| <= 31, width 128, input the
     state and its linear propagation), trained here briefly on the GPU

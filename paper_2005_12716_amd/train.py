@@ -40,11 +40,12 @@ def sea_hos(n: int, periods: float, seed: int, order_m: int = 3) -> lib.Hos:
 def default_scales(stride: int, base_substeps: int = 0) -> dict:
     """Input scale sigma = Hs/4 at Hs/lambda_p = 0.02 for eta and, through the
     linear dispersion (phis ~ g/omega eta, omega_p = 1), for phis; residual
-    scale rho = 0.05 over the linear base, 0.005 over the integrating-factor
-    RK4 base (whose residual is about ten times smaller)."""
+    scale rho in proportion to the base's one-call error at s = 10 (about
+    4e-2 linear, 7e-3 with one integrating-factor RK4 substep, 2e-4 with
+    two): 0.05, 0.005, 0.0002."""
     sig = 0.02 * LAM / 4.0
-    return {"stride_s": stride, "sigma_eta": sig, "sigma_phi": sig, "rho": 0.05 if base_substeps == 0 else 0.005,
-            "base_substeps": base_substeps}
+    rho = {0: 0.05, 1: 0.005}.get(base_substeps, 0.0002)
+    return {"stride_s": stride, "sigma_eta": sig, "sigma_phi": sig, "rho": rho, "base_substeps": base_substeps}
 
 
 class Pairs:
