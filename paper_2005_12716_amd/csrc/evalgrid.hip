@@ -352,12 +352,11 @@ __global__ void __launch_bounds__(256) k_xcoef_skel(EvArgs A, Geom G, WPlan plan
 // (index p X mod gx, which also folds modes above gx/2 when gx < nx), on FP32
 // MFMA with FP32 accumulation.  Each layer is then sum_j T[l][j] out[f R + j]
 // and every node's run of K coefficients is stored contiguously.
-constexpr int DX_T = 64, DX_KC = 64, DX_MAXMT = 8;
+constexpr int DX_T = 64, DX_KC = 32, DX_MAXMT = 8;
 // LDS row strides chosen so that the MFMA operand reads (16 rows x 4
 // consecutive k, or 4 k-rows x 16 columns) and the accumulator stores hit 64
-// distinct banks.
+// distinct banks; the results overlay the operand tiles.
 constexpr int DX_SA = DX_KC + 4, DX_SB = DX_T + 16, DX_SS = DX_T + 4;
-static_assert(DX_SS == DX_SA, "the results reuse the operand rows");
 
 __global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const cf* __restrict__ tw, int gx, Skel skl,
                                                    int L, int K, int nitems, float* __restrict__ coef) {
@@ -368,28 +367,26 @@ __global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const cf* _
   const int hx = G.nx / 2, Kr = 2 * hx;
   const int mt_n = (nitems + 15) / 16, rows = mt_n * 16;
   const int Fv = A.nvol, R = skl.R;
-  cf* tws = reinterpret_cast<cf*>(smem);
-  float* Ts = reinterpret_cast<float*>(tws + gx);  // [2][L][R]: C-type then S-type factors
+  float* Ts = reinterpret_cast<float*>(smem);      // [2][L][R]: C-type then S-type factors
   float* As = Ts + ((2 * L * R + 3) & ~3);         // [rows][DX_SA]
   float* Bs = As + rows * DX_SA;                   // [DX_KC][DX_SB]
   float* S = As;                                   // after the contraction: [rows][DX_SS]
-  for (int i = tid; i < gx; i += 256) tws[i] = tw[i];
   for (int i = tid; i < L * R; i += 256) {
     Ts[i] = skl.tc[i];
     Ts[L * R + i] = skl.ts[i];
   }
   const cf* inter = reinterpret_cast<const cf*>(A.inter);
-  static_assert(DX_T == 64 && DX_KC == 64, "fills assume 64 nodes and 32 modes per chunk");
+  static_assert(DX_T == 64 && DX_KC == 32, "fills assume 64 nodes and 16 modes per chunk");
   const int Xn = (A.ix0 + x0 + (tid & (DX_T - 1))) % gx;  // this thread's node in the B fill
   const int dX2 = (2 * Xn) % gx;
-  // A fill: thread -> mode pp = tid & 31 of items it = tid >> 5, it + 8, ...
-  const int pp = tid & 31, it0 = tid >> 5;
-  const int nA = (rows + 7) / 8;  // items per thread (<= 32)
-  cf pre[DX_MAXMT * 2];
+  // A fill: thread -> mode pp = tid & 15 of items it = tid >> 4, it + 16, ...
+  const int pp = tid & 15, it0 = tid >> 4;
+  const int nA = (rows + 15) / 16;  // items per thread (<= 8)
+  cf pre[DX_MAXMT];
   auto fetchA = [&](int p0) {
 #pragma unroll
-    for (int q = 0; q < DX_MAXMT * 2; ++q) {
-      const int item = it0 + 8 * q, p = p0 + pp;
+    for (int q = 0; q < DX_MAXMT; ++q) {
+      const int item = it0 + 16 * q, p = p0 + pp;
       cf v = mk(0.f, 0.f);
       if (q < nA && item < nitems && p < hx) v = inter[((size_t)item * A.wy + r) * G.nxh + p];
       pre[q] = v;
@@ -406,8 +403,8 @@ __global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const cf* _
     __syncthreads();
     const int p0 = k0 >> 1;
 #pragma unroll
-    for (int q = 0; q < DX_MAXMT * 2; ++q) {
-      const int item = it0 + 8 * q;
+    for (int q = 0; q < DX_MAXMT; ++q) {
+      const int item = it0 + 16 * q;
       if (q < nA && item < rows) *reinterpret_cast<float2*>(&As[item * DX_SA + 2 * pp]) = make_float2(pre[q].x, pre[q].y);
     }
     {
@@ -419,7 +416,7 @@ __global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const cf* _
       for (int kk = kk0; kk < DX_KC; kk += 4, p += 2) {
         float v = 0.f;
         if (p < hx) {
-          const cf w = tws[t];  // e^{-i theta}, theta = 2 pi p X / gx
+          const cf w = tw[t];  // e^{-i theta}, theta = 2 pi p X / gx (table cached in L1/L2)
           const float cp = p == 0 ? 1.f : 2.f;
           v = (kk & 1) ? cp * w.y : cp * w.x;  // -c_p sin(theta) or c_p cos(theta)
         }
@@ -656,9 +653,9 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     const int nitems = Fv * skel->R + A.nsurf;
     if constexpr (sizeof(R) == 4) {
       const int rows = (nitems + 15) / 16 * 16;
-      const size_t lds_dft = (size_t)px.n * sizeof(cf) +
-                             ((2ull * L * skel->R + 3) / 4 * 4 + (size_t)rows * DX_SA + (size_t)DX_KC * DX_SB) *
-                                 sizeof(float);
+      const size_t lds_dft = ((2ull * L * skel->R + 3) / 4 * 4 +
+                              std::max((size_t)rows * DX_SA + (size_t)DX_KC * DX_SB, (size_t)rows * DX_SS)) *
+                             sizeof(float);
       if (nitems <= DX_MAXMT * 16 && lds_dft <= 160 * 1024) {
         dim3 grid((A.wx + DX_T - 1) / DX_T, A.wy);
         sw_launch(h, SWENSE_K_XEVAL, &k_xcoef_dft, grid, dim3(256), lds_dft, h->st, A, h->G,
