@@ -608,12 +608,13 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
       SW_HIP(hipMemcpy(c->pd.dwz, dwz.data(), n * 16, hipMemcpyHostToDevice));
       SW_HIP(hipMemcpy(c->pd.pz, pz.data(), n * 4, hipMemcpyHostToDevice));
     }
-    // skeleton heights for the coefficient grids
+    // skeleton heights for the coefficient grids: factors reproduced to 1e-7
+    // of each wavenumber's scale, below the FP32 rounding of the transforms
     {
       const double kx = M_PI * h->G.nx / h->G.lx, ky = three ? M_PI * h->G.ny / h->G.ly : 0.0;
       std::vector<int> sel;
       std::vector<float> tc, ts;
-      if (gd->nl >= 8 && build_skeleton(c->z, std::sqrt(kx * kx + ky * ky), h->G.depth, 1e-9, sel, tc, ts)) {
+      if (gd->nl >= 8 && build_skeleton(c->z, std::sqrt(kx * kx + ky * ky), h->G.depth, 1e-7, sel, tc, ts)) {
         const int R = (int)sel.size(), L = gd->nl;
         std::vector<double> zeta(R);
         for (int j = 0; j < R; ++j) zeta[j] = c->z[sel[j]];
