@@ -66,3 +66,21 @@ def test_bad_descriptors_are_rejected_without_gpu_work():
     d = lib.hos_desc(2, 63, 1, 1.0, 1.0, -1.0)
     with pytest.raises(lib.SwenseError):
         lib.sea_spectrum(d, kind=1, mode=4, ka=0.1)
+
+
+@pytest.mark.parametrize("in_channels", [2, 4])
+def test_network_parameter_packing_matches_the_library(in_channels):
+    """The packed parameter vector of the binding has the length the library
+    expects (host-only call), and unpacking inverts packing (FP32 values)."""
+    from oracle import fno as F
+    from paper_2005_12716_amd import lib
+    cfg = F.FnoConfig(n=64, channels=6, layers=3, p_modes=5, q_modes=4, hidden=10, in_channels=in_channels)
+    desc = lib.fno_desc(cfg.n, cfg.channels, cfg.layers, cfg.p_modes, cfg.q_modes, cfg.hidden, max_batch=2,
+                        in_channels=in_channels)
+    P = F.init_params(cfg, np.random.default_rng(0))
+    vec = lib.fno_pack(desc, P)
+    assert vec.size == lib.load().swense_fno_param_count(lib.C.byref(desc))
+    Q = lib.fno_unpack(desc, vec)
+    for k in P:
+        ref = P[k].astype(np.complex64) if np.iscomplexobj(P[k]) else P[k].astype(np.float32)
+        assert np.array_equal(Q[k], ref.astype(Q[k].dtype)), k
