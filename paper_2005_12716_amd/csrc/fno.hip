@@ -34,6 +34,16 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
+__device__ __forceinline__ float gelu_f(float z) {
+  const float k = 0.7978845608028654f;
+  return 0.5f * z * (1.f + tanhf(k * (z + 0.044715f * z * z * z)));
+}
+__device__ __forceinline__ float gelu_g(float z) {
+  const float k = 0.7978845608028654f;
+  const float t = tanhf(k * (z + 0.044715f * z * z * z));
+  return 0.5f * (1.f + t) + 0.5f * z * (1.f - t * t) * k * (1.f + 3.f * 0.044715f * z * z);
+}
+
 // ------------------------------------------------------------------ GEMM
 // C[b](m, n) = alpha sum_k A[b](m, k) B[b](k, n) + beta C[b](m, n) + bias[m]
 // Operands FP32 or BF16 with arbitrary strides; batch index b = b1 nb2 + b2
@@ -55,6 +65,10 @@ struct GemmArgs {
   long long sCb1, sCb2, sCm, sCn;
   float alpha, beta;
   const float* bias;
+  // optional epilogue: + add (same layout as C), pre-activation copy to zout, gelu
+  const float* add;
+  float* zout;
+  int act;
   // load modes chosen on the host from strides and alignment:
   // a_mode 0 scalar, 1 FP32 x4 along k, 2 BF16 x4 along k, 3 BF16 x4 along m;
   // b_mode 0 scalar, 1 FP32 x4 along k, 2 FP32 x4 along n, 3 complex BF16 pairs
@@ -308,6 +322,10 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
           float v = g.alpha * acc[i][j][r];
           if (g.beta != 0.f) v += g.beta * *cp;
           if (g.bias) v += g.bias[gm];
+          const long long ci = coff + gm * g.sCm + gn * g.sCn;
+          if (g.add) v += g.add[ci];
+          if (g.zout) g.zout[ci] = v;
+          if (g.act) v = gelu_f(v);
           *cp = v;
         }
       }
@@ -540,27 +558,6 @@ __global__ void __launch_bounds__(256) k_mix_dw(const cf* __restrict__ U, const 
 }
 
 // ------------------------------------------------------------------ element-wise
-__device__ __forceinline__ float gelu_f(float z) {
-  const float k = 0.7978845608028654f;
-  return 0.5f * z * (1.f + tanhf(k * (z + 0.044715f * z * z * z)));
-}
-__device__ __forceinline__ float gelu_g(float z) {
-  const float k = 0.7978845608028654f;
-  const float t = tanhf(k * (z + 0.044715f * z * z * z));
-  return 0.5f * (1.f + t) + 0.5f * z * (1.f - t * t) * k * (1.f + 3.f * 0.044715f * z * z);
-}
-
-// z = a + bias[c] + s (s may be null), v = gelu(z) (act) or z
-__global__ void k_fno_act(const float* a, const float* bias, const float* s, float* z, float* v, long long n,
-                          int chans, long long plane, int act) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = (int)((i / plane) % chans);
-  float t = a[i] + (bias ? bias[c] : 0.f) + (s ? s[i] : 0.f);
-  if (z) z[i] = t;
-  v[i] = act ? gelu_f(t) : t;
-}
-
 __global__ void k_fno_gelu_back(const float* gv, const float* z, float* gz, long long n) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) gz[i] = gv[i] * gelu_g(z[i]);
@@ -748,9 +745,11 @@ GemmArgs gemm0() {
   return g;
 }
 
-// out[b][o][pt] = sum_i W[o][i] in[b][i][pt] (+ bias), W BF16 [o][i]
+// out[b][o][pt] = sum_i W[o][i] in[b][i][pt] (+ bias), W BF16 [o][i]; with
+// add/zout/act the epilogue also adds `add`, keeps the pre-activation in zout
+// and applies gelu
 void conv1x1(swense_fno* f, const unsigned short* W, int cout, int cin, const float* in, float* out, int B,
-             const float* bias) {
+             const float* bias, const float* add = nullptr, float* zout = nullptr, int act = 0) {
   const long long plane = (long long)f->d.n * f->d.n;
   GemmArgs g = gemm0();
   g.M = cout;
@@ -770,6 +769,9 @@ void conv1x1(swense_fno* f, const unsigned short* W, int cout, int cin, const fl
   g.sCm = plane;
   g.sCn = 1;
   g.bias = bias;
+  g.add = add;
+  g.zout = zout;
+  g.act = act;
   launch_gemm(f->st, g);
 }
 
@@ -1007,19 +1009,9 @@ float* zq_of(swense_fno* f) {
 }
 float* h_of(swense_fno* f) { return zq_of(f) + (size_t)f->d.max_batch * f->d.hidden * f->d.n * f->d.n; }
 
-void elementwise(swense_fno* f, const float* a, const float* bias, const float* s, float* z, float* v, int B,
-                 int chans, int act) {
-  const long long plane = (long long)f->d.n * f->d.n;
-  const long long n = (long long)B * chans * plane;
-  hipLaunchKernelGGL(k_fno_act, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, f->st, a, bias, s, z, v, n, chans,
-                     plane, act);
-  SW_HIP(hipGetLastError());
-}
-
 void forward_impl(swense_fno* f, const float* x, float* y, int B) {
   const auto& d = f->d;
   const int C = d.channels, H = d.hidden;
-  float* tA = f->tmp;
   float* tS = f->tmp + (size_t)d.max_batch * std::max(H, C) * d.n * d.n;
   conv1x1(f, f->wb + f->oW0, C, d.in_channels, x, v_of(f, 0), B, f->w + f->ob0);
   for (int l = 1; l <= d.layers; ++l) {
@@ -1029,11 +1021,9 @@ void forward_impl(swense_fno* f, const float* x, float* y, int B) {
     mix(f, U, f->wb + f->oR[l - 1], f->Y, B);
     herm(f, f->Y, B, 0);
     spec_inv(f, f->Y, tS, B, 1.f, 0.f);
-    conv1x1(f, f->wb + f->oW[l - 1], C, C, v, tA, B, nullptr);
-    elementwise(f, tA, f->w + f->ob[l - 1], tS, z_of(f, l), v_of(f, l), B, C, 1);
+    conv1x1(f, f->wb + f->oW[l - 1], C, C, v, v_of(f, l), B, f->w + f->ob[l - 1], tS, z_of(f, l), 1);
   }
-  conv1x1(f, f->wb + f->oQ1, H, C, v_of(f, d.layers), tA, B, nullptr);
-  elementwise(f, tA, f->w + f->oc1, nullptr, zq_of(f), h_of(f), B, H, 1);
+  conv1x1(f, f->wb + f->oQ1, H, C, v_of(f, d.layers), h_of(f), B, f->w + f->oc1, nullptr, zq_of(f), 1);
   conv1x1(f, f->wb + f->oQ2, 2, H, h_of(f), y, B, f->w + f->oc2);
   f->last_batch = B;
 }
