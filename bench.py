@@ -53,7 +53,7 @@ def workload():
     return pts, (gx, gy, ix0, iy0, wx, wy), np.asarray(zl), phases
 
 
-def batched_setup(lib, torch, pts_scale=1.0, fields=None):
+def batched_setup(lib, torch, pts_scale=1.0, fields=None, streams=None):
     """The batched configuration: 64 seeded JONSWAP realisations with mode
     grids uniform over the even 5-smooth sizes in [128, 512] per axis,
     Hs/lambda_p ~ U[0.01, 0.03], M = 3, each interpolated (n = 4 window, 32
@@ -71,7 +71,7 @@ def batched_setup(lib, torch, pts_scale=1.0, fields=None):
         d = lib.hos_desc(3, nx, ny, lx, ly, -1.0, order_m=M, dt=LAM / 64)
         eh, ph = lib.sea_spectrum(d, kind=0, hs=hs, kp=1.0, gamma=3.3,
                                   phases=synth.mode_phases(r["phase_seed"], ny, nx // 2 + 1))
-        h = lib.Hos(d, eh, ph)
+        h = lib.Hos(d, eh, ph, stream=streams[len(hoses) % len(streams)] if streams else None)
         n = max(1000, int(r["npts"] * pts_scale))
         x0, y0 = lx / 2 - 2 * LAM, ly / 2 - 2 * LAM
         p = synth.box_cloud(r["phase_seed"], n, x0, y0, 4 * LAM, 4 * LAM, -0.5 * LAM, 0.1 * LAM)
