@@ -198,6 +198,19 @@ int swense_interp_cells(swense_hos* h, swense_cells* c, unsigned mask, float* ou
  * dw/dz of the interpolant (device FP32 [n], caller order).  Asynchronous. */
 int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div);
 
+/* Finite-volume divergence of the interpolated velocity (Sec. 3.2.3) on a
+ * structured box mesh with increasing cell edges xe[nx+1], ye[ny+1] (3D; in
+ * 2D ny = 1 and ye may be NULL) and ze[nz+1] (host FP64): the velocity of the
+ * interpolant on the grid gd (as swense_interp_cells) at every face centre,
+ * then per cell div = sum over its faces of u_f . A_f / V.  div: device FP32
+ * [nz][ny][nx], x fastest.  *rms and *maxabs (may be NULL) receive the RMS and
+ * the largest magnitude over the cells.  The face centres are bound and
+ * released inside the call (a diagnostic, not a per-step path); every face
+ * centre must lie inside the window and layers (else SWENSE_EINVAL).
+ * Synchronises. */
+int swense_fv_divergence(swense_hos* h, const swense_grid_desc* gd, const double* xe, int nx, const double* ye,
+                         int ny, const double* ze, int nz, float* div, double* rms, double* maxabs);
+
 /* One CFD coupling step in one call (Sec. 4.3: the incident fields at the
  * current time are mapped to the cells, then the wave model advances): the
  * fields of the current state, as swense_interp_cells would produce them, go

@@ -532,6 +532,60 @@ unsigned coef_mask(unsigned mask, bool three) {
 
 }  // namespace
 
+// Finite-volume divergence on a structured box mesh from the normal
+// velocity at the face centres (Sec. 3.2.3): per cell, the outflow through
+// its six (2D: four) faces over its volume, i.e. the differences of the face
+// velocities over the cell widths.  Face values f: rows of the interpolation
+// output (U, [V,] W) at the face-centre points ordered x faces
+// [nz][ny][nx+1], then y faces [nz][ny+1][nx] (3D), then z faces [nz+1][ny][nx].
+__global__ void k_fv_div(const float* __restrict__ f, long long nf, int three, int nx, int ny, int nz,
+                         const double* __restrict__ xe, const double* __restrict__ ye, const double* __restrict__ ze,
+                         float* __restrict__ div, double* __restrict__ sums) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ncell = (long long)nx * ny * nz;
+  double d2 = 0.0, dm = 0.0;
+  if (c < ncell) {
+    const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((long long)nx * ny));
+    const long long nxf = (long long)nz * ny * (nx + 1);
+    const long long nyf = three ? (long long)nz * (ny + 1) * nx : 0;
+    const float* fu = f;                        // U row
+    const float* fv = three ? f + nf : nullptr; // V row
+    const float* fw = f + (three ? 2 : 1) * nf; // W row
+    const long long ux = ((long long)k * ny + j) * (nx + 1) + i;
+    double v = ((double)fu[ux + 1] - (double)fu[ux]) / (xe[i + 1] - xe[i]);
+    if (three) {
+      const long long uy = nxf + ((long long)k * (ny + 1) + j) * nx + i;
+      v += ((double)fv[uy + nx] - (double)fv[uy]) / (ye[j + 1] - ye[j]);
+    }
+    const long long uz = nxf + nyf + ((long long)k * ny + j) * nx + i;
+    v += ((double)fw[uz + (long long)ny * nx] - (double)fw[uz]) / (ze[k + 1] - ze[k]);
+    div[c] = (float)v;
+    d2 = v * v;
+    dm = fabs(v);
+  }
+  __shared__ double r2[256], rm[256];
+  r2[threadIdx.x] = d2;
+  rm[threadIdx.x] = dm;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      r2[threadIdx.x] += r2[threadIdx.x + w];
+      rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&sums[0], r2[0]);
+    // non-negative doubles order like their bit patterns
+    atomicMax(reinterpret_cast<unsigned long long*>(&sums[1]), (unsigned long long)__double_as_longlong(rm[0]));
+  }
+}
+
+__global__ void k_zero2(double* s) {
+  s[0] = 0.0;
+  s[1] = 0.0;
+}
+
 // Grid evaluation + gather of the current modes into out (on h->st).
 void interp_body(swense_hos* h, swense_cells* c, unsigned mask, float* out) {
   if (c->n == 0) return;
@@ -684,6 +738,88 @@ int swense_interp_step(swense_hos* h, swense_cells* c, unsigned mask, float* out
     SW_HIP(hipStreamWaitEvent(h->st, h->ev_join, 0));
     return (int)SWENSE_OK;
   });
+}
+
+int swense_fv_divergence(swense_hos* h, const swense_grid_desc* gd, const double* xe, int nx, const double* ye,
+                         int ny, const double* ze, int nz, float* div, double* rms, double* maxabs) {
+  if (!h || !gd || !xe || !ze || !div) return SWENSE_EINVAL;
+  swense_cells* c = nullptr;
+  void* mem = nullptr;
+  const int rc = guarded(h, [&] {
+    const bool three = h->G.ny > 1;
+    SW_REQUIRE(nx >= 1 && nz >= 1 && (three ? (ny >= 1 && ye != nullptr) : ny == 1), "mesh sizes");
+    for (int i = 0; i < nx; ++i) SW_REQUIRE(xe[i + 1] > xe[i], "x edges must increase");
+    for (int k = 0; k < nz; ++k) SW_REQUIRE(ze[k + 1] > ze[k], "z edges must increase");
+    if (three)
+      for (int j = 0; j < ny; ++j) SW_REQUIRE(ye[j + 1] > ye[j], "y edges must increase");
+    const long long nxf = (long long)nz * ny * (nx + 1), nyf = three ? (long long)nz * (ny + 1) * nx : 0;
+    const long long nzf = (long long)(nz + 1) * ny * nx, nf = nxf + nyf + nzf;
+    SW_REQUIRE(nf < (1ll << 31), "too many faces");
+    // face centres [3][nf]
+    std::vector<double> xyz((size_t)3 * nf);
+    auto put = [&](long long idx, double x, double y, double z) {
+      xyz[idx] = x;
+      xyz[nf + idx] = y;
+      xyz[2 * nf + idx] = z;
+    };
+    std::vector<double> yedge(three ? ye : nullptr, three ? ye + ny + 1 : nullptr);
+    if (!three) yedge = {0.0, 0.0};
+    long long o = 0;
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i <= nx; ++i)
+          put(o++, xe[i], 0.5 * (yedge[j] + yedge[j + 1]), 0.5 * (ze[k] + ze[k + 1]));
+    if (three)
+      for (int k = 0; k < nz; ++k)
+        for (int j = 0; j <= ny; ++j)
+          for (int i = 0; i < nx; ++i)
+            put(o++, 0.5 * (xe[i] + xe[i + 1]), ye[j], 0.5 * (ze[k] + ze[k + 1]));
+    for (int k = 0; k <= nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+          put(o++, 0.5 * (xe[i] + xe[i + 1]), 0.5 * (yedge[j] + yedge[j + 1]), ze[k]);
+    const int nfields = three ? 3 : 2;
+    const size_t b_xyz = xyz.size() * sizeof(double), b_out = (size_t)nfields * nf * sizeof(float);
+    const size_t b_e = (size_t)(nx + 1 + (three ? ny + 1 : 0) + nz + 1) * sizeof(double);
+    SW_HIP(hipMalloc(&mem, b_xyz + b_out + b_e + 2 * sizeof(double) + 1024));
+    char* p = reinterpret_cast<char*>(mem);
+    auto take = [&](size_t b) {
+      void* r = p;
+      p += (b + 255) & ~size_t(255);
+      return r;
+    };
+    double* dxyz = reinterpret_cast<double*>(take(b_xyz));
+    float* fout = reinterpret_cast<float*>(take(b_out));
+    double* de = reinterpret_cast<double*>(take(b_e));
+    double* sums = reinterpret_cast<double*>(take(2 * sizeof(double)));
+    SW_HIP(hipMemcpyAsync(dxyz, xyz.data(), b_xyz, hipMemcpyHostToDevice, h->st));
+    std::vector<double> edges(xe, xe + nx + 1);
+    if (three) edges.insert(edges.end(), ye, ye + ny + 1);
+    edges.insert(edges.end(), ze, ze + nz + 1);
+    SW_HIP(hipMemcpyAsync(de, edges.data(), b_e, hipMemcpyHostToDevice, h->st));
+    int brc = swense_cells_bind(h, gd, nf, dxyz, &c);
+    if (brc != SWENSE_OK) throw SwenseError{brc, "binding the face centres: " + h->err};
+    const unsigned mask = SWENSE_U | SWENSE_W | (three ? SWENSE_V : 0u);
+    SW_REQUIRE(c->nbad == 0, "face centres outside the grid window or layers");
+    interp_body(h, c, mask, fout);
+    hipLaunchKernelGGL(k_zero2, dim3(1), dim3(1), 0, h->st, sums);
+    const long long ncell = (long long)nx * ny * nz;
+    hipLaunchKernelGGL(k_fv_div, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, h->st, fout, nf, three ? 1 : 0,
+                       nx, ny, nz, de, three ? de + nx + 1 : de, de + nx + 1 + (three ? ny + 1 : 0), div, sums);
+    SW_HIP(hipGetLastError());
+    double hs[2];
+    SW_HIP(hipMemcpyAsync(hs, sums, sizeof(hs), hipMemcpyDeviceToHost, h->st));
+    SW_HIP(hipStreamSynchronize(h->st));
+    if (rms) *rms = std::sqrt(hs[0] / (double)ncell);
+    if (maxabs) *maxabs = hs[1];
+    return (int)SWENSE_OK;
+  });
+  if (c) swense_cells_destroy(c);
+  if (mem) {
+    (void)hipStreamSynchronize(h->st);
+    (void)hipFree(mem);
+  }
+  return rc;
 }
 
 int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div) {

@@ -96,6 +96,8 @@ def load():
         "swense_interp_cells": (C.c_int, [vp, vp, C.c_uint, fp, C.POINTER(C.c_longlong)]),
         "swense_interp_divergence": (C.c_int, [vp, vp, fp]),
         "swense_interp_step": (C.c_int, [vp, vp, C.c_uint, fp, C.c_int]),
+        "swense_fv_divergence": (C.c_int, [vp, C.POINTER(GridDesc), vp, C.c_int, vp, C.c_int, vp, C.c_int, fp,
+                                           dp, dp]),
         "swense_profile_enable": (C.c_int, [vp, C.c_int]),
         "swense_profile_read": (C.c_int, [vp, C.c_int, dp, C.POINTER(C.c_longlong)]),
         "swense_profile_bytes": (C.c_int, [vp, C.c_int, dp]),
@@ -136,7 +138,7 @@ def load():
 EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swense_hos_init",
             "swense_hos_set_state", "swense_hos_step", "swense_hos_step_exp", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
-            "swense_cells_bind", "swense_interp_cells", "swense_interp_divergence", "swense_interp_step", "swense_profile_enable",
+            "swense_cells_bind", "swense_interp_cells", "swense_interp_divergence", "swense_interp_step", "swense_fv_divergence", "swense_profile_enable",
             "swense_profile_read", "swense_profile_bytes", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
             "swense_batch_last_error", "swense_batch_destroy", "swense_hos_destroy",
             "swense_cells_destroy", "swense_fno_param_count", "swense_fno_create", "swense_fno_forward",
@@ -281,6 +283,20 @@ class Hos:
 
     def bind(self, gd, xyz: torch.Tensor):
         return Cells(self, gd, xyz)
+
+    def fv_divergence(self, gd, xe, ye, ze):
+        """Finite-volume divergence on the structured mesh with edges xe, ye
+        (None in 2D), ze: (div [nz][ny][nx] device FP32, rms, max |div|)."""
+        xe = np.ascontiguousarray(xe, dtype=np.float64)
+        ze = np.ascontiguousarray(ze, dtype=np.float64)
+        ye = None if ye is None else np.ascontiguousarray(ye, dtype=np.float64)
+        nx, nz = xe.size - 1, ze.size - 1
+        ny = 1 if ye is None else ye.size - 1
+        div = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
+        rms, mx = C.c_double(), C.c_double()
+        self._check(self.L.swense_fv_divergence(self.h, C.byref(gd), _ptr(xe), nx, _ptr(ye), ny, _ptr(ze), nz,
+                                                _ptr(div), C.byref(rms), C.byref(mx)), "fv_divergence")
+        return div, rms.value, mx.value
 
     def close(self):
         if getattr(self, "h", None):
