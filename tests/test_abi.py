@@ -84,3 +84,31 @@ def test_network_parameter_packing_matches_the_library(in_channels):
     for k in P:
         ref = P[k].astype(np.complex64) if np.iscomplexobj(P[k]) else P[k].astype(np.float32)
         assert np.array_equal(Q[k], ref.astype(Q[k].dtype)), k
+
+
+def test_invalid_descriptors_are_rejected_before_any_device_work():
+    """Argument checks of the ABI run on the host first: bad descriptors give
+    SWENSE_EINVAL (no GPU needed to reach them)."""
+    import ctypes as C
+    from paper_2005_12716_amd import lib
+    L = lib.load()
+    eh = np.zeros((16, 17), dtype=np.complex128)
+    bad = [lib.hos_desc(3, 31, 16, 1.0, 1.0, -1.0),          # odd nx
+           lib.hos_desc(3, 32, 16, 1.0, 1.0, -1.0, order_m=0),  # order 0
+           lib.hos_desc(3, 32, 16, -1.0, 1.0, -1.0),         # negative length
+           lib.hos_desc(2, 32, 4, 1.0, 1.0, -1.0),           # 2D with ny > 1
+           lib.hos_desc(3, 32, 16, 1.0, 1.0, -1.0, precision=2)]
+    for d in bad:
+        h = C.c_void_p()
+        rc = L.swense_hos_init(C.byref(d), eh.ctypes.data_as(C.c_void_p), eh.ctypes.data_as(C.c_void_p), lib.SPECTRAL,
+                               None, C.byref(h))
+        assert rc == lib.EINVAL and not h.value
+    for fd in [lib.fno_desc(n=96), lib.fno_desc(channels=7), lib.fno_desc(p_modes=200), lib.fno_desc(q_modes=100),
+               lib.fno_desc(max_batch=0), lib.fno_desc(in_channels=0)]:
+        f = C.c_void_p()
+        params = np.zeros(8, dtype=np.float32)
+        assert L.swense_fno_create(C.byref(fd), params.ctypes.data_as(C.c_void_p), None, C.byref(f)) == lib.EINVAL
+        assert not f.value
+    assert L.swense_surrogate_create(None, None, None, C.byref(C.c_void_p())) == lib.EINVAL
+    assert L.swense_hos_step(None, 1) == lib.EINVAL
+    assert L.swense_gemm_bf16(0, 4, 4, None, None, None, None) == lib.EINVAL
