@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(256) k_yinv_eval(EvArgs A, Geom G, FftPlan pla
 template <typename R, int MAXE, int NS0>
 __global__ void __launch_bounds__(256) k_yinv_eval_w(EvArgs A, Geom G, WPlan plan) {
   extern __shared__ unsigned char smem[];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int p = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
   if (p >= G.nxh) return;
   const YInvJob jb = eval_job(A, G, blockIdx.y, sizeof(cpx<R>));
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(256) k_xcoef_w(EvArgs A, Geom G, WPlan plan, i
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
   const int gx = plan.n, r = blockIdx.x, g = blockIdx.y, hx = G.nx / 2;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   C* zbuf = reinterpret_cast<C*>(smem) + (size_t)wave * wbuf_len(gx);
   float* stage = reinterpret_cast<float*>(reinterpret_cast<C*>(smem) + 4 * (size_t)wbuf_len(gx));
   const int Fv = A.nvol;
@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(256) k_xcoef_skel(EvArgs A, Geom G, WPlan plan
   using C = cpx<R>;
   constexpr int WPB = 4;
   const int gx = plan.n, r = blockIdx.x, f = blockIdx.y, hx = G.nx / 2;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   C* zbuf = reinterpret_cast<C*>(smem) + (size_t)wave * wbuf_len(gx);
   float* stage = reinterpret_cast<float*>(reinterpret_cast<C*>(smem) + WPB * (size_t)wbuf_len(gx));
   const int Fv = A.nvol;

@@ -35,13 +35,17 @@ __global__ void __launch_bounds__(256) k_yinv(YInvArgs args, Geom G, FftPlan pla
   yinv_body<R>(args.job[blockIdx.y], G, plan, TW, nrows, row0, smem);
 }
 
+// v times i kx for mode p (kx rounded once from FP64 to the row precision)
+template <typename R>
+__device__ __forceinline__ cpx<R> times_ikx(cpx<R> v, int p, const Geom& G) {
+  const R kx = (R)(2.0 * M_PI * (double)p / G.lx);
+  return mk(-kx * v.y, kx * v.x);
+}
+
 template <typename R>
 __device__ __forceinline__ cpx<R> load_row(const XIn& f, int y, int p, const Geom& G) {
   cpx<R> v = reinterpret_cast<const cpx<R>*>(f.src)[(size_t)y * G.nxh + p];
-  if (f.dx) {
-    const R kx = (R)(2.0 * M_PI * (double)p / G.lx);
-    v = mk(-kx * v.y, kx * v.x);
-  }
+  if (f.dx) v = times_ikx<R>(v, p, G);
   return v;
 }
 
@@ -164,13 +168,37 @@ __global__ void __launch_bounds__(256) k_xpass(XArgs A, Geom G, FftPlan plan) {
   }
 }
 
-// Epilogue of the forward y transform for mode (p, q) with value v.
-__device__ __forceinline__ void yfwd_epilogue(const YFwdJob& jb, const RkArgs& rk, const Geom& G, int p, int q, int qs,
-                                              cd v) {
+// Epilogue of the forward y transform for mode (p, q) with value v, in two
+// halves: the state operands the mode needs are read first (so a caller can
+// issue the reads of several modes before it uses any), then the results
+// are formed and stored.  Each mode touches only its own index.
+struct EpiOps {
+  cd s;  // other field of the stage input (linear part)
+  cd x;  // base state
+  cd a;  // RK accumulator (or the YE_STORE accumulate target)
+};
+
+__device__ __forceinline__ EpiOps yfwd_epi_load(const YFwdJob& jb, const RkArgs& rk, size_t idx) {
+  EpiOps o;
+  o.s = o.x = o.a = mk(0.0, 0.0);
+  if (jb.epi == YE_STORE) {
+    if (jb.acc_mode == 1) o.a = jb.acc[idx];
+    return o;
+  }
+  if (jb.epi == YE_NL_ETA || jb.epi == YE_NL_PHI) return o;
+  const int w = jb.epi == YE_RHS_ETA ? 0 : 1;
+  o.s = rk.sin[1 - w][idx];
+  if (rk.stage != 0) o.x = rk.xn[w][idx];
+  if (rk.stage != 0 && rk.stage != 1) o.a = rk.acc[w][idx];
+  return o;
+}
+
+__device__ __forceinline__ void yfwd_epi_store(const YFwdJob& jb, const RkArgs& rk, const Geom& G, int p, int q,
+                                               int qs, cd v, const EpiOps& o) {
   const size_t idx = (size_t)q * G.nxh + p;
   if (jb.epi == YE_STORE) {
     jb.dst[idx] = v;
-    if (jb.acc_mode == 1) jb.acc[idx] = jb.acc[idx] + v;
+    if (jb.acc_mode == 1) jb.acc[idx] = o.a + v;
     else if (jb.acc_mode == 2) jb.acc[idx] = v;
     return;
   }
@@ -186,29 +214,34 @@ __device__ __forceinline__ void yfwd_epilogue(const YFwdJob& jb, const RkArgs& r
     const double ky = G.ny > 1 ? 2.0 * M_PI * (double)qs / G.ly : 0.0;
     const double kk = sqrt(kx * kx + ky * ky);
     const double dz1 = G.depth > 0.0 ? kk * tanh(kk * G.depth) : kk;
-    k = k + cscale(rk.sin[1][idx], dz1);
+    k = k + cscale(o.s, dz1);
     if (p == 0 && q == 0) k = mk(0.0, 0.0);
   } else {
-    k = k + cscale(rk.sin[0][idx], -G.g);
+    k = k + cscale(o.s, -G.g);
   }
   switch (rk.stage) {
     case 0: rk.kout[w][idx] = k; break;
     case 1:
       rk.acc[w][idx] = k;
-      rk.sout[w][idx] = rk.xn[w][idx] + cscale(k, 0.5 * rk.dt);
+      rk.sout[w][idx] = o.x + cscale(k, 0.5 * rk.dt);
       break;
     case 2:
-      rk.acc[w][idx] = rk.acc[w][idx] + cscale(k, 2.0);
-      rk.sout[w][idx] = rk.xn[w][idx] + cscale(k, 0.5 * rk.dt);
+      rk.acc[w][idx] = o.a + cscale(k, 2.0);
+      rk.sout[w][idx] = o.x + cscale(k, 0.5 * rk.dt);
       break;
     case 3:
-      rk.acc[w][idx] = rk.acc[w][idx] + cscale(k, 2.0);
-      rk.sout[w][idx] = rk.xn[w][idx] + cscale(k, rk.dt);
+      rk.acc[w][idx] = o.a + cscale(k, 2.0);
+      rk.sout[w][idx] = o.x + cscale(k, rk.dt);
       break;
     default:
-      rk.xn[w][idx] = rk.xn[w][idx] + cscale(rk.acc[w][idx] + k, rk.dt / 6.0);
+      rk.xn[w][idx] = o.x + cscale(o.a + k, rk.dt / 6.0);
       break;
   }
+}
+
+__device__ __forceinline__ void yfwd_epilogue(const YFwdJob& jb, const RkArgs& rk, const Geom& G, int p, int q, int qs,
+                                              cd v) {
+  yfwd_epi_store(jb, rk, G, p, q, qs, v, yfwd_epi_load(jb, rk, (size_t)q * G.nxh + p));
 }
 
 // y-forward: grid (ceil(nxh / TW), njobs).  Keeps modes |q| < ny/2, zeroes the
@@ -250,7 +283,7 @@ __global__ void __launch_bounds__(256) k_yfwd(YFwdArgs A, Geom G, FftPlan plan, 
 template <typename R, int MAXE, int NS0>
 __global__ void __launch_bounds__(256) k_yinv_w(YInvArgs args, Geom G, WPlan plan, int nrows, int row0) {
   extern __shared__ unsigned char smem[];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int p = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
   if (p >= G.nxh) return;
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem) + (size_t)wave * wbuf_len(plan.n);
@@ -261,26 +294,61 @@ template <typename R, int MAXE, int NS0>
 __global__ void __launch_bounds__(256) k_yfwd_w(YFwdArgs A, Geom G, WPlan plan) {
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int p = xcd_tile(blockIdx.x, gridDim.x) * 4 + wave;
   if (p >= G.nxh) return;
   const int Ly = plan.n;
   C* buf = reinterpret_cast<C*>(smem) + (size_t)wave * wbuf_len(Ly);
   const YFwdJob& jb = A.job[blockIdx.y];
   const C* src = reinterpret_cast<const C*>(jb.src);
-  for (int s = lane; s < Ly; s += 64) buf[sk(s)] = src[(size_t)s * G.nxh + p];
+  if constexpr (NS0 > 0) {
+    // column loads all issued before the LDS stores
+    C v[NS0 / 64];
+#pragma unroll
+    for (int j = 0; j < NS0 / 64; ++j) v[j] = src[(size_t)(lane + 64 * j) * G.nxh + p];
+#pragma unroll
+    for (int j = 0; j < NS0 / 64; ++j) buf[sk(lane + 64 * j)] = v[j];
+  } else {
+    for (int s = lane; s < Ly; s += 64) buf[sk(s)] = src[(size_t)s * G.nxh + p];
+  }
   wave_sync();
   wave_fft_any<R, MAXE, NS0>(buf, plan, -1, lane);
   const double inv = 1.0 / (double)Ly;
-  for (int q = lane; q < G.ny; q += 64) {
-    const int qs = signed_q(q, G.ny);
-    cd v = mk(0.0, 0.0);
-    if (2 * p != G.nx && !(G.ny > 1 && 2 * q == G.ny)) {
-      const int slot = ((qs % Ly) + Ly) % Ly;
-      C r = buf[sk(slot)];
-      v = mk((double)r.x * inv, (double)r.y * inv);
+  if constexpr (NS0 > 0) {
+    // state operands of a batch of modes first, then their results
+    constexpr int E = NS0 / 64, B = E < 4 ? E : 4;
+    for (int q0 = 0; q0 < G.ny; q0 += 64 * B) {
+      EpiOps o[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int q = q0 + lane + 64 * k;
+        if (q < G.ny) o[k] = yfwd_epi_load(jb, A.rk, (size_t)q * G.nxh + p);
+      }
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int q = q0 + lane + 64 * k;
+        if (q >= G.ny) continue;
+        const int qs = signed_q(q, G.ny);
+        cd v = mk(0.0, 0.0);
+        if (2 * p != G.nx && !(G.ny > 1 && 2 * q == G.ny)) {
+          const int slot = ((qs % Ly) + Ly) % Ly;
+          C r = buf[sk(slot)];
+          v = mk((double)r.x * inv, (double)r.y * inv);
+        }
+        yfwd_epi_store(jb, A.rk, G, p, q, qs, v, o[k]);
+      }
     }
-    yfwd_epilogue(jb, A.rk, G, p, q, qs, v);
+  } else {
+    for (int q = lane; q < G.ny; q += 64) {
+      const int qs = signed_q(q, G.ny);
+      cd v = mk(0.0, 0.0);
+      if (2 * p != G.nx && !(G.ny > 1 && 2 * q == G.ny)) {
+        const int slot = ((qs % Ly) + Ly) % Ly;
+        C r = buf[sk(slot)];
+        v = mk((double)r.x * inv, (double)r.y * inv);
+      }
+      yfwd_epilogue(jb, A.rk, G, p, q, qs, v);
+    }
   }
 }
 
@@ -296,7 +364,7 @@ __global__ void __launch_bounds__(256) k_xpass_w(XArgs A, Geom G, WPlan plan) {
   const int Px = plan.n;
   const int y = blockIdx.x;
   const int hx = G.nx / 2;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int wl = wbuf_len(Px);
   C* zbuf = reinterpret_cast<C*>(smem) + (size_t)wave * wl;
   R* phys = reinterpret_cast<R*>(reinterpret_cast<C*>(smem) + 4 * (size_t)wl);  // [nin][Px]
@@ -424,12 +492,15 @@ template <typename R, int MAXE, int NS0, int MW>
 __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
   static_assert(NS0 >= 64 && NS0 <= 1024, "rounds version for compile-time rows up to 1024 points");
   constexpr int PPT = (NS0 + 255) / 256;  // points per thread
+  constexpr int KP = NS0 / 128;            // kept modes per lane (p < Px / 2)
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
   constexpr int Px = NS0;
   const int y = blockIdx.x;
   const int hx = G.nx / 2;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // wave-uniform, so the input descriptors are read with scalar loads
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int wl = wbuf_len(Px);
   C* bufs = reinterpret_cast<C*>(smem);
   C* zbuf = bufs + (size_t)wave * wl;
@@ -445,22 +516,39 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
   for (int rd = 0; rd < nrounds; ++rd) {
     const int pi = 4 * rd + wave;
     if (pi < npairs) {
-      const XIn& fa = A.in[2 * pi];
+      // Every load of the pair's row is issued before the first is used.
+      // Mode p (0 <= p < hx) goes to slot p and its conjugate image to slot
+      // Px - p; the slots in between stay zero (padding).
+      const XIn fa = A.in[2 * pi];
       const bool hasb = 2 * pi + 1 < A.nin;
-      const XIn& fb = A.in[hasb ? 2 * pi + 1 : 2 * pi];
-      for (int s = lane; s < Px; s += 64) {
-        C z = mk((R)0, (R)0);
-        int p = -1;
-        bool cj = false;
-        if (s < hx) p = s;
-        else if (s > Px - hx) { p = Px - s; cj = true; }
-        if (p >= 0) {
-          C va = load_row<R>(fa, y, p, G);
-          C vb = hasb ? load_row<R>(fb, y, p, G) : mk((R)0, (R)0);
-          if (cj) { va = conjg(va); vb = conjg(vb); }
-          z = mk(va.x - vb.y, va.y + vb.x);
+      const XIn fb = A.in[hasb ? 2 * pi + 1 : 2 * pi];
+      const C* ra = reinterpret_cast<const C*>(fa.src) + (size_t)y * G.nxh;
+      const C* rb = reinterpret_cast<const C*>(fb.src) + (size_t)y * G.nxh;
+      C va[KP], vb[KP];
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        const int p = lane + 64 * k;
+        va[k] = vb[k] = mk((R)0, (R)0);
+        if (p < hx) {
+          va[k] = ra[p];
+          if (hasb) vb[k] = rb[p];
         }
-        zbuf[sk(s)] = z;
+      }
+#pragma unroll
+      for (int j = 0; j < Px / 64; ++j) {
+        const int s = lane + 64 * j;
+        if (s >= hx && s <= Px - hx) zbuf[sk(s)] = mk((R)0, (R)0);
+      }
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        const int p = lane + 64 * k;
+        if (p < hx) {
+          C a = va[k], b = vb[k];
+          if (fa.dx) a = times_ikx<R>(a, p, G);
+          if (hasb && fb.dx) b = times_ikx<R>(b, p, G);
+          zbuf[sk(p)] = mk(a.x - b.y, a.y + b.x);                 // a + i b
+          if (p > 0) zbuf[sk(Px - p)] = mk(a.x + b.y, b.x - a.y);  // conj(a) + i conj(b)
+        }
       }
       wave_sync();
       wave_fft_any<R, MAXE, NS0>(zbuf, plan, +1, lane);
@@ -809,7 +897,7 @@ void xpass_t(swense_hos* h, const XArgs& a) {
   bool pairs_ok = true;
   for (int i = 0; i < a.nin; ++i)
     if (a.in[i].role == XR_GRADPAIR) pairs_ok = pairs_ok && (i % 2 == 0) && i + 1 < a.nin;
-  if (wave_ok<R>(Px) && pairs_ok && a.M <= 4 && (Px == 256 || Px == 512 || Px == 1024)) {
+  if (wave_ok<R>(Px) && pairs_ok && a.M <= 4 && h->G.nx <= Px && (Px == 256 || Px == 512 || Px == 1024)) {
     const size_t lds = 4ull * wbuf_len(Px) * sizeof(cpx<R>);
     const WPlan wp = make_wplan(h->plan_px);
     switch (Px) {

@@ -80,7 +80,9 @@ __device__ __forceinline__ int wrapn(int i, int w, int g) { return (w == g && i 
 
 // Node offsets (in floats) of the 4 x 4 (or 4 x 1) horizontal stencil.
 __device__ __forceinline__ void stencil(const Col& c, const GatherArgs& A, long long* off) {
+#pragma unroll
   for (int b = 0; b < 4; ++b)
+#pragma unroll
     for (int a = 0; a < 4; ++a) {
       const int yy = A.three ? wrapn(c.iy + b, A.wy, A.gy) : 0;
       const int xx = wrapn(c.ix + a, A.wx, A.gx);
@@ -114,11 +116,14 @@ __global__ void __launch_bounds__(256) k_gather_col(GatherArgs A, const Col* __r
         jj = A.nl * A.fv + (j - nv);
       }
       float acc = 0.f;
-      for (int b = 0; b < nb; ++b) {
-        float r = 0.f;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) r += wx[a] * A.coef[off[b * 4 + a] + jj];
-        acc += wy[b] * r;
+      for (int b = 0; b < 4; ++b) {  // unrolled so the weights stay in registers
+        if (b < nb) {
+          float r = 0.f;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) r += wx[a] * A.coef[off[b * 4 + a] + jj];
+          acc += wy[b] * r;
+        }
       }
       h[j] = acc;
     }
@@ -183,13 +188,17 @@ __global__ void __launch_bounds__(256) k_div_col(GatherArgs A, const Col* __rest
     for (int l = lane; l < c.nlc; l += 64) {
       const int lay = c.lmin + l;
       float hdx = 0.f, hw = 0.f;
-      for (int b = 0; b < nb; ++b)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {  // unrolled so the weights stay in registers
+        if (b >= nb) continue;
+#pragma unroll
         for (int a = 0; a < 4; ++a) {
           const long long o = off[b * 4 + a] + lay;
           hdx += wy[b] * dwx[a] * inv_dx * A.coef[o + (long long)A.c_u * A.nl];
           if (A.c_v >= 0) hdx += dwy[b] * wx[a] * inv_dy * A.coef[o + (long long)A.c_v * A.nl];
           hw += wy[b] * wx[a] * A.coef[o + (long long)A.c_w * A.nl];
         }
+      }
       h[l] = hdx;
       h[c.nlc + l] = hw;
     }

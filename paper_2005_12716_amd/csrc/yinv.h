@@ -75,9 +75,53 @@ template <typename R, int MAXE, int NS0>
 __device__ __forceinline__ void yinv_wave(const YInvJob& jb, const Geom& G, const WPlan& plan, int nrows, int row0,
                                           int p, cpx<R>* buf, int lane) {
   const int Ly = plan.n;
-  for (int s = lane; s < Ly; s += 64) {
-    cd v = yinv_slot(jb, G, Ly, p, s);
-    buf[sk(s)] = mk((R)v.x, (R)v.y);
+  bool filled = false;
+  if constexpr (NS0 > 0) {
+    // Zero-padding in y (Ly >= ny): each kept mode q has a slot of its own,
+    // so the wavefront walks the modes instead of the slots, issuing a batch
+    // of column loads before the symbols are formed; slots no mode maps to
+    // are cleared.  Same values as the slot walk below.
+    if (G.ny > 1 && Ly >= G.ny) {
+      constexpr int E = NS0 / 64, B = E < 8 ? E : 8;
+      const int half = G.ny / 2;
+      const bool col = p < G.nxh && 2 * p != G.nx;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int s = lane + 64 * j;
+        if (!col || (s >= half && s <= Ly - half)) buf[sk(s)] = mk((R)0, (R)0);
+      }
+      if (col) {
+        for (int k0 = 0; k0 < E && 64 * k0 < G.ny; k0 += B) {
+          cd v[B];
+#pragma unroll
+          for (int k = 0; k < B; ++k) {
+            const int q = lane + 64 * (k0 + k);
+            const int qs = q >= half ? q - G.ny : q;  // kept: -ny/2 < qs < ny/2
+            v[k] = mk(0.0, 0.0);
+            if (q < G.ny && qs > -half) v[k] = jb.src[(size_t)q * G.nxh + p];
+          }
+#pragma unroll
+          for (int k = 0; k < B; ++k) {
+            const int q = lane + 64 * (k0 + k);
+            const int qs = q >= half ? q - G.ny : q;
+            if (q < G.ny && qs > -half) {
+              const cd w = cmul(v[k], symbol_of(G, jb, p, qs));
+              double ax = 0.0, ay = 0.0;
+              ax += w.x;
+              ay += w.y;
+              buf[sk(qs >= 0 ? qs : qs + Ly)] = mk((R)ax, (R)ay);
+            }
+          }
+        }
+      }
+      filled = true;
+    }
+  }
+  if (!filled) {
+    for (int s = lane; s < Ly; s += 64) {
+      cd v = yinv_slot(jb, G, Ly, p, s);
+      buf[sk(s)] = mk((R)v.x, (R)v.y);
+    }
   }
   wave_sync();
   wave_fft_any<R, MAXE, NS0>(buf, plan, +1, lane);
