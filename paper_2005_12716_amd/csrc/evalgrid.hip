@@ -362,7 +362,10 @@ __global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const cf* _
                                                    int L, int K, int nitems, float* __restrict__ coef) {
   extern __shared__ __align__(16) unsigned char smem[];
   typedef float v4f __attribute__((ext_vector_type(4)));
-  const int x0 = blockIdx.x * DX_T, r = blockIdx.y;
+  // the tiles of one window row read the same mode rows: consecutive tiles
+  // go to the workgroups of one XCD, so its L2 serves the shared rows
+  const int tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int r = tile / gridDim.x, x0 = (tile - r * gridDim.x) * DX_T;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int hx = G.nx / 2, Kr = 2 * hx;
   const int mt_n = (nitems + 15) / 16, rows = mt_n * 16;

@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "wfft.h"
 
 namespace {
 
@@ -93,7 +94,9 @@ __device__ __forceinline__ void stencil(const Col& c, const GatherArgs& A, long 
 __global__ void __launch_bounds__(256) k_gather_col(GatherArgs A, const Col* __restrict__ cols, int ncols, PtDev pd) {
   extern __shared__ float hbuf[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ci = blockIdx.x * kColsPerBlock + wave;
+  // neighbouring columns share coefficient nodes: consecutive column groups
+  // go to the workgroups of one XCD, so its L2 serves the shared nodes
+  const int ci = xcd_tile(blockIdx.x, gridDim.x) * kColsPerBlock + wave;
   float* h = hbuf + wave * A.kmax;
   Col c{};
   const bool valid = ci < ncols;
