@@ -82,7 +82,7 @@ __device__ __forceinline__ void yinv_wave(const YInvJob& jb, const Geom& G, cons
     // of column loads before the symbols are formed; slots no mode maps to
     // are cleared.  Same values as the slot walk below.
     if (G.ny > 1 && Ly >= G.ny) {
-      constexpr int E = NS0 / 64, B = E < 8 ? E : 8;
+      constexpr int E = NS0 / 64, B = E < 4 ? E : 4;
       const int half = G.ny / 2;
       const bool col = p < G.nxh && 2 * p != G.nx;
 #pragma unroll
