@@ -370,13 +370,16 @@ __global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const cf* _
   const int hx = G.nx / 2, Kr = 2 * hx;
   const int mt_n = (nitems + 15) / 16, rows = mt_n * 16;
   const int Fv = A.nvol, R = skl.R;
-  float* Ts = reinterpret_cast<float*>(smem);      // [2][L][R]: C-type then S-type factors
+  float* Ts = reinterpret_cast<float*>(smem);      // [2][R][L]: C-type then S-type factors
   float* As = Ts + ((2 * L * R + 3) & ~3);         // [rows][DX_SA]
   float* Bs = As + rows * DX_SA;                   // [DX_KC][DX_SB]
   float* S = As;                                   // after the contraction: [rows][DX_SS]
+  // factor j of layer l at j L + l, so that the threads of a wavefront (one
+  // layer each) read consecutive banks in the layer combine
   for (int i = tid; i < L * R; i += 256) {
-    Ts[i] = skl.tc[i];
-    Ts[L * R + i] = skl.ts[i];
+    const int l = i / R, j = i - l * R;
+    Ts[j * L + l] = skl.tc[i];
+    Ts[L * R + j * L + l] = skl.ts[i];
   }
   const cf* inter = reinterpret_cast<const cf*>(A.inter);
   static_assert(DX_T == 64 && DX_KC == 32, "fills assume 64 nodes and 16 modes per chunk");
@@ -469,12 +472,12 @@ __global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const cf* _
     float* dst = coef + ((size_t)r * A.wx + x0) * K + kidx;
     if (kidx < nvk) {
       const int f = kidx / L, l = kidx - f * L;
-      const float* T = Ts + (A.f[f].vf == 1 ? L * R : 0) + l * R;
+      const float* T = Ts + (A.f[f].vf == 1 ? L * R : 0) + l;
       const float* srow = S + (f * R) * DX_SS;
       for (int n4 = 0; n4 < nodes; n4 += 4) {
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         for (int j = 0; j < R; ++j) {
-          const float tj = T[j];
+          const float tj = T[j * L];
           const float4 sv = *reinterpret_cast<const float4*>(srow + j * DX_SS + n4);
           v.x += tj * sv.x; v.y += tj * sv.y; v.z += tj * sv.z; v.w += tj * sv.w;
         }
