@@ -301,29 +301,30 @@ __global__ void __launch_bounds__(256) k_yfwd_w(YFwdArgs A, Geom G, WPlan plan) 
   C* buf = reinterpret_cast<C*>(smem) + (size_t)wave * wbuf_len(Ly);
   const YFwdJob& jb = A.job[blockIdx.y];
   const C* src = reinterpret_cast<const C*>(jb.src);
-  if constexpr (NS0 > 0) {
-    // column loads all issued before the LDS stores
-    C v[NS0 / 64];
-#pragma unroll
-    for (int j = 0; j < NS0 / 64; ++j) v[j] = src[(size_t)(lane + 64 * j) * G.nxh + p];
-#pragma unroll
-    for (int j = 0; j < NS0 / 64; ++j) buf[sk(lane + 64 * j)] = v[j];
-  } else {
-    for (int s = lane; s < Ly; s += 64) buf[sk(s)] = src[(size_t)s * G.nxh + p];
-  }
-  wave_sync();
-  wave_fft_any<R, MAXE, NS0>(buf, plan, -1, lane);
   const double inv = 1.0 / (double)Ly;
   if constexpr (NS0 > 0) {
-    // state operands of a batch of modes first, then their results
+    // The column and the state operands of the first batch of modes (which
+    // do not depend on the transform) are all read before any is used;
+    // later batches read theirs before forming their results.
     constexpr int E = NS0 / 64, B = E < 4 ? E : 4;
-    for (int q0 = 0; q0 < G.ny; q0 += 64 * B) {
-      EpiOps o[B];
+    EpiOps o[B];
+    auto load_ops = [&](int q0) {
 #pragma unroll
       for (int k = 0; k < B; ++k) {
         const int q = q0 + lane + 64 * k;
         if (q < G.ny) o[k] = yfwd_epi_load(jb, A.rk, (size_t)q * G.nxh + p);
       }
+    };
+    C colv[NS0 / 64];
+#pragma unroll
+    for (int j = 0; j < NS0 / 64; ++j) colv[j] = src[(size_t)(lane + 64 * j) * G.nxh + p];
+    load_ops(0);
+#pragma unroll
+    for (int j = 0; j < NS0 / 64; ++j) buf[sk(lane + 64 * j)] = colv[j];
+    wave_sync();
+    wave_fft_any<R, MAXE, NS0>(buf, plan, -1, lane);
+    for (int q0 = 0; q0 < G.ny; q0 += 64 * B) {
+      if (q0 > 0) load_ops(q0);
 #pragma unroll
       for (int k = 0; k < B; ++k) {
         const int q = q0 + lane + 64 * k;
@@ -339,6 +340,9 @@ __global__ void __launch_bounds__(256) k_yfwd_w(YFwdArgs A, Geom G, WPlan plan) 
       }
     }
   } else {
+    for (int s = lane; s < Ly; s += 64) buf[sk(s)] = src[(size_t)s * G.nxh + p];
+    wave_sync();
+    wave_fft_any<R, MAXE, NS0>(buf, plan, -1, lane);
     for (int q = lane; q < G.ny; q += 64) {
       const int qs = signed_q(q, G.ny);
       cd v = mk(0.0, 0.0);
@@ -513,27 +517,32 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
   }
   const int npairs = (A.nin + 1) / 2;
   const int nrounds = (npairs + 3) / 4;
+  // Rows of this wavefront's input pair, read a round ahead: the loads of
+  // round rd + 1 are in flight during round rd's transform.  Mode p
+  // (0 <= p < hx) goes to slot p and its conjugate image to slot Px - p; the
+  // slots in between stay zero (padding).
+  C va[KP], vb[KP];
+  auto load_pair = [&](int pi) {
+    const bool hasb = 2 * pi + 1 < A.nin;
+    const C* ra = reinterpret_cast<const C*>(A.in[2 * pi].src) + (size_t)y * G.nxh;
+    const C* rb = reinterpret_cast<const C*>(A.in[hasb ? 2 * pi + 1 : 2 * pi].src) + (size_t)y * G.nxh;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int p = lane + 64 * k;
+      va[k] = vb[k] = mk((R)0, (R)0);
+      if (p < hx) {
+        va[k] = ra[p];
+        if (hasb) vb[k] = rb[p];
+      }
+    }
+  };
+  if (wave < npairs) load_pair(wave);
   for (int rd = 0; rd < nrounds; ++rd) {
     const int pi = 4 * rd + wave;
     if (pi < npairs) {
-      // Every load of the pair's row is issued before the first is used.
-      // Mode p (0 <= p < hx) goes to slot p and its conjugate image to slot
-      // Px - p; the slots in between stay zero (padding).
       const XIn fa = A.in[2 * pi];
       const bool hasb = 2 * pi + 1 < A.nin;
       const XIn fb = A.in[hasb ? 2 * pi + 1 : 2 * pi];
-      const C* ra = reinterpret_cast<const C*>(fa.src) + (size_t)y * G.nxh;
-      const C* rb = reinterpret_cast<const C*>(fb.src) + (size_t)y * G.nxh;
-      C va[KP], vb[KP];
-#pragma unroll
-      for (int k = 0; k < KP; ++k) {
-        const int p = lane + 64 * k;
-        va[k] = vb[k] = mk((R)0, (R)0);
-        if (p < hx) {
-          va[k] = ra[p];
-          if (hasb) vb[k] = rb[p];
-        }
-      }
 #pragma unroll
       for (int j = 0; j < Px / 64; ++j) {
         const int s = lane + 64 * j;
@@ -550,6 +559,7 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
           if (p > 0) zbuf[sk(Px - p)] = mk(a.x + b.y, b.x - a.y);  // conj(a) + i conj(b)
         }
       }
+      if (pi + 4 < npairs) load_pair(pi + 4);
       wave_sync();
       wave_fft_any<R, MAXE, NS0>(zbuf, plan, +1, lane);
     }
