@@ -356,6 +356,126 @@ __global__ void __launch_bounds__(256) k_yfwd_w(YFwdArgs A, Geom G, WPlan plan) 
   }
 }
 
+// Workgroup versions of the y transforms for power-of-two lengths N in
+// [256, 4096]: one kx column per 256-thread workgroup (columns ordered XCD by
+// XCD), the column's transform done by all four wavefronts (block4_fft), and
+// the loads and epilogue spread over the 256 threads.
+__host__ __device__ constexpr bool b4_len_ok(int n) { return n >= 256 && n <= 4096 && (n & (n - 1)) == 0; }
+
+template <typename R, int N>
+__global__ void __launch_bounds__(256) k_yinv_b4(YInvArgs args, Geom G, WPlan plan, int nrows, int row0) {
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  constexpr int Q = N / 4;
+  constexpr int T = N / 256;  // slots per thread
+  C* buf = reinterpret_cast<C*>(smem);
+  const int p = xcd_tile(blockIdx.x, gridDim.x);
+  const YInvJob& jb = args.job[blockIdx.y];
+  const int tid = threadIdx.x;
+  const int half = G.ny / 2;
+  const bool col = p < G.nxh && 2 * p != G.nx;
+  // zero-padding in y (N >= ny): kept mode q (-ny/2 < qs < ny/2) goes to
+  // slot qs mod N; every other slot is zero
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int s = tid + 256 * t;
+    if (!col || (s >= half && s <= N - half)) buf[b4_in<Q>(s)] = mk((R)0, (R)0);
+  }
+  if (col) {
+    cd v[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int q = tid + 256 * t;
+      const int qs = q >= half ? q - G.ny : q;
+      v[t] = mk(0.0, 0.0);
+      if (q < G.ny && qs > -half) v[t] = jb.src[(size_t)q * G.nxh + p];
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int q = tid + 256 * t;
+      const int qs = q >= half ? q - G.ny : q;
+      if (q < G.ny && qs > -half) {
+        const cd w = cmul(v[t], symbol_of(G, jb, p, qs));
+        double ax = 0.0, ay = 0.0;
+        ax += w.x;
+        ay += w.y;
+        buf[b4_in<Q>(qs >= 0 ? qs : qs + N)] = mk((R)ax, (R)ay);
+      }
+    }
+  }
+  block4_fft<R, N>(buf, reinterpret_cast<const C*>(plan.tw), +1);
+  if (p >= G.nxh) return;
+  C* dst = reinterpret_cast<C*>(jb.dst);
+  for (int r = tid; r < nrows; r += 256) {
+    int y = row0 + r;
+    if (y >= N) y -= N * (y / N);
+    dst[(size_t)r * G.nxh + p] = buf[b4_out<Q>(y)];
+  }
+}
+
+template <typename R, int N>
+__global__ void __launch_bounds__(256) k_yfwd_b4(YFwdArgs A, Geom G, WPlan plan) {
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  constexpr int Q = N / 4;
+  constexpr int T = N / 256;
+  constexpr int TQ = 4;  // modes per thread held at once (ny <= 1024 in one batch)
+  C* buf = reinterpret_cast<C*>(smem);
+  const int p = xcd_tile(blockIdx.x, gridDim.x);
+  const YFwdJob& jb = A.job[blockIdx.y];
+  const int tid = threadIdx.x;
+  const bool colp = p < G.nxh;
+  // the column and the state operands of the first modes, all read first
+  const C* src = reinterpret_cast<const C*>(jb.src);
+  C colv[T];
+  EpiOps o[TQ];
+  if (colp) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) colv[t] = src[(size_t)(tid + 256 * t) * G.nxh + p];
+#pragma unroll
+    for (int k = 0; k < TQ; ++k) {
+      const int q = tid + 256 * k;
+      if (q < G.ny) o[k] = yfwd_epi_load(jb, A.rk, (size_t)q * G.nxh + p);
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) buf[b4_in<Q>(tid + 256 * t)] = colv[t];
+  }
+  block4_fft<R, N>(buf, reinterpret_cast<const C*>(plan.tw), -1);
+  if (!colp) return;
+  const double inv = 1.0 / (double)N;
+  for (int q0 = 0; q0 < G.ny; q0 += 256 * TQ) {
+    if (q0 > 0) {
+#pragma unroll
+      for (int k = 0; k < TQ; ++k) {
+        const int q = q0 + tid + 256 * k;
+        if (q < G.ny) o[k] = yfwd_epi_load(jb, A.rk, (size_t)q * G.nxh + p);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < TQ; ++k) {
+      const int q = q0 + tid + 256 * k;
+      if (q >= G.ny) continue;
+      const int qs = signed_q(q, G.ny);
+      cd v = mk(0.0, 0.0);
+      if (2 * p != G.nx && !(G.ny > 1 && 2 * q == G.ny)) {
+        const int slot = ((qs % N) + N) % N;
+        const C r = buf[b4_out<Q>(slot)];
+        v = mk((double)r.x * inv, (double)r.y * inv);
+      }
+      yfwd_epi_store(jb, A.rk, G, p, q, qs, v, o[k]);
+    }
+  }
+}
+
+#define SW_B4_DISPATCH(n, LAUNCH) \
+  switch (n) {                    \
+    case 256: LAUNCH(256); break;   \
+    case 512: LAUNCH(512); break;   \
+    case 1024: LAUNCH(1024); break; \
+    case 2048: LAUNCH(2048); break; \
+    default: LAUNCH(4096); break;   \
+  }
+
 // Fused x pass, wavefront version: block = physical row y, four wavefronts.
 // Field pairs are spread over the wavefronts (each transforms its pair in
 // its own LDS buffer and leaves the two real rows in LDS); after one block
@@ -494,9 +614,10 @@ __device__ __forceinline__ R w2sum_n(const R* W, int K) {
 
 template <typename R, int MAXE, int NS0, int MW>
 __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
-  static_assert(NS0 >= 64 && NS0 <= 1024, "rounds version for compile-time rows up to 1024 points");
+  static_assert(NS0 >= 256 && NS0 <= 1024, "rounds version for compile-time rows of 256 to 1024 points");
   constexpr int PPT = (NS0 + 255) / 256;  // points per thread
   constexpr int KP = NS0 / 128;            // kept modes per lane (p < Px / 2)
+  constexpr int Q4 = NS0 / 4;              // sub-transform length of the output transform
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
   constexpr int Px = NS0;
@@ -571,10 +692,14 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
       const bool hi = i & 1;
       R c[PPT];
       if (f.role == XR_G) {
+        // eta^pw / pw! (pw <= M <= MW); unrolled, so the divisions by 1, 2
+        // and 4 become exact multiplications
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
           c[j] = (R)1;
-          for (int k = 1; k <= f.pw; ++k) c[j] *= eta[j] / (R)k;
+#pragma unroll
+          for (int k = 1; k <= MW; ++k)
+            if (k <= f.pw) c[j] *= eta[j] / (R)k;
         }
       }
 #pragma unroll
@@ -630,19 +755,18 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
       if (M >= 2) o1 -= (R)0.5 * gp2[j];
       if (M >= 4) o1 += (R)0.5 * ge2[j] * w2sum_n<MW>(W[j], M - 2);
     }
-    zout[sk(x)] = mk(o0, o1);
+    zout[b4_in<Q4>(x)] = mk(o0, o1);
   }
-  __syncthreads();
-  if (wave != 0) return;
-  wave_fft_any<R, MAXE, NS0>(zout, plan, -1, lane);
+  // forward transform of the products by all four wavefronts
+  block4_fft<R, NS0>(zout, reinterpret_cast<const C*>(plan.tw), -1);
   const R sc = (R)(0.5 / (double)Px);
   C* d0 = reinterpret_cast<C*>(A.out0);
   C* d1 = reinterpret_cast<C*>(A.out1);
-  for (int p = lane; p < G.nxh; p += 64) {
+  for (int p = threadIdx.x; p < G.nxh; p += 256) {
     C o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
     if (p < hx) {
-      C zp = zout[sk(p)];
-      C zm = conjg(zout[sk((Px - p) % Px)]);
+      C zp = zout[b4_out<Q4>(p)];
+      C zm = conjg(zout[b4_out<Q4>((Px - p) % Px)]);
       C sum = zp + zm, t = zp - zm;
       o0 = cscale(sum, sc);
       o1 = mk(t.y * sc, -t.x * sc);
@@ -837,6 +961,15 @@ void yinv_t(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, in
     }
     h->prof.bytes[SWENSE_K_YINV] += b;
   }
+  if (b4_len_ok(plan.n) && h->G.ny > 1 && plan.n >= h->G.ny) {
+    const WPlan wp = make_wplan(plan);
+    const size_t lds = 4ull * wbuf_len(plan.n / 4) * sizeof(cpx<R>);
+    dim3 grid(h->G.nxh, a.njobs);
+#define L_YB4(N) sw_launch(h, SWENSE_K_YINV, &k_yinv_b4<R, N>, grid, dim3(256), lds, st, a, h->G, wp, nrows, row0)
+    SW_B4_DISPATCH(plan.n, L_YB4);
+#undef L_YB4
+    return;
+  }
   if (wave_ok<R>(plan.n)) {
     const WPlan wp = make_wplan(plan);
     const size_t lds = 4ull * wbuf_len(plan.n) * sizeof(cpx<R>);
@@ -871,6 +1004,15 @@ void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t s
       b += per * modes;
     }
     h->prof.bytes[SWENSE_K_YFWD] += b;
+  }
+  if (b4_len_ok(plan.n) && h->G.ny <= 1024) {
+    const WPlan wp = make_wplan(plan);
+    const size_t lds = 4ull * wbuf_len(plan.n / 4) * sizeof(cpx<R>);
+    dim3 grid(h->G.nxh, a.njobs);
+#define L_YFB4(N) sw_launch(h, SWENSE_K_YFWD, &k_yfwd_b4<R, N>, grid, dim3(256), lds, st, a, h->G, wp)
+    SW_B4_DISPATCH(plan.n, L_YFB4);
+#undef L_YFB4
+    return;
   }
   if (wave_ok<R>(plan.n)) {
     const WPlan wp = make_wplan(plan);

@@ -241,6 +241,104 @@ __device__ __forceinline__ void wave_fft_any(cpx<R>* buf, const WPlan& plan, int
   else wave_fft<R, MAXE>(buf, plan, sign, lane);
 }
 
+// ---------------------------------------------------------------------------
+// Workgroup FFT of N = 4Q points (Q a power of two, 64 <= Q <= 1024) by the
+// four wavefronts of a 256-thread workgroup, decimating in time by 4:
+// wavefront w transforms the decimated sequence x[4m + w] (m < Q) in its own
+// sub-buffer with radix-4 (and one radix-2) Stockham passes, so that every
+// lane holds one butterfly per pass; then every thread combines the four
+// sub-spectra at frequencies k' < Q with the twiddles W_N^(w k') and a
+// 4-point DFT:  X[k' + Q j] = sum_w W_4^(w j) W_N^(w k') Y_w[k'].  Four
+// times the lanes of a single-wavefront transform work on one sequence.
+// Input element n sits at b4_in<Q>(n), output element k at b4_out<Q>(k);
+// sub-buffer w holds wbuf_len(Q) elements at w wbuf_len(Q).  The table `tw`
+// is the N-point one (the sub-transforms read every fourth entry).
+
+template <int Q>
+__device__ __forceinline__ int b4_in(int n) { return (n & 3) * (Q + Q / 16 + 1) + sk(n >> 2); }
+template <int Q>
+__device__ __forceinline__ int b4_out(int k) { return (k / Q) * (Q + Q / 16 + 1) + sk(k % Q); }
+
+// One Stockham pass of a length-Q wavefront transform, twiddles tw[TS m].
+template <typename R, int Q, int RAD, int NS, int TS>
+__device__ __forceinline__ void qpass(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int lane) {
+  constexpr int NB = Q / RAD;
+  constexpr int MB = (NB + 63) / 64;
+  constexpr int TWS = Q / (NS * RAD);
+  cpx<R> v[MB][RAD];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int j = lane + 64 * m;
+    if (NB % 64 == 0 || j < NB) {
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[m][r] = buf[sk(j + r * NB)];
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int j = lane + 64 * m;
+    if (NB % 64 == 0 || j < NB) {
+      const int k = j & (NS - 1);
+      if (NS > 1 && k > 0) {
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          cpx<R> w = tw[k * r * TWS * TS];
+          if (sign > 0) w.y = -w.y;
+          v[m][r] = cmul(v[m][r], w);
+        }
+      }
+      dft_any<R, RAD>(v[m], sign);
+      const int o = (j - k) * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) buf[sk(o + r * NS)] = v[m][r];
+    }
+  }
+  wave_sync();
+}
+
+template <typename R, int Q, int TS, int NS = 1>
+__device__ __forceinline__ void wave_fft_r4(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int lane) {
+  if constexpr (NS * 4 <= Q) {
+    qpass<R, Q, 4, NS, TS>(buf, tw, sign, lane);
+    wave_fft_r4<R, Q, TS, NS * 4>(buf, tw, sign, lane);
+  } else if constexpr (NS * 2 == Q) {
+    qpass<R, Q, 2, NS, TS>(buf, tw, sign, lane);
+  }
+}
+
+// All 256 threads of the workgroup must call this; it starts with a block
+// barrier (the inputs may have been written by any thread) and ends with one.
+template <typename R, int N>
+__device__ __forceinline__ void block4_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign) {
+  constexpr int Q = N / 4;
+  static_assert(Q >= 64 && Q <= 1024 && (Q & (Q - 1)) == 0, "N = 4Q with Q a power of two in [64, 1024]");
+  constexpr int WL = Q + Q / 16 + 1;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+  __syncthreads();
+  wave_fft_r4<R, Q, 4>(buf + wave * WL, tw, sign, lane);
+  __syncthreads();
+#pragma unroll
+  for (int k0 = 0; k0 < Q; k0 += 256) {
+    const int kq = k0 + (int)threadIdx.x;
+    if (Q % 256 == 0 || kq < Q) {
+      cpx<R> a[4];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) a[w] = buf[w * WL + sk(kq)];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        cpx<R> t = tw[w * kq];
+        if (sign > 0) t.y = -t.y;
+        a[w] = cmul(a[w], t);
+      }
+      dft4(a, sign);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) buf[j * WL + sk(kq)] = a[j];
+    }
+  }
+  __syncthreads();
+}
+
 // Host: choose (MAXE, N) template arguments for a length n.
 #define SW_FFT_DISPATCH(n, LAUNCH)          \
   switch (n) {                              \
