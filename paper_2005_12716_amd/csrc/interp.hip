@@ -118,13 +118,18 @@ __global__ void __launch_bounds__(256) k_gather_col(GatherArgs A, const Col* __r
       } else {
         jj = A.nl * A.fv + (j - nv);
       }
+      // all 16 taps read before any is used (in 2D the rows b >= 1 repeat
+      // row 0's nodes and are not summed)
+      float tap[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) tap[t] = A.coef[off[t] + jj];
       float acc = 0.f;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {  // unrolled so the weights stay in registers
         if (b < nb) {
           float r = 0.f;
 #pragma unroll
-          for (int a = 0; a < 4; ++a) r += wx[a] * A.coef[off[b * 4 + a] + jj];
+          for (int a = 0; a < 4; ++a) r += wx[a] * tap[b * 4 + a];
           acc += wy[b] * r;
         }
       }
