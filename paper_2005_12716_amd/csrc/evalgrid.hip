@@ -358,14 +358,43 @@ constexpr int DX_T = 64, DX_KC = 32, DX_MAXMT = 8;
 // distinct banks; the results overlay the operand tiles.
 constexpr int DX_SA = DX_KC + 4, DX_SB = DX_T + 16, DX_SS = DX_T + 4;
 
-__global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const cf* __restrict__ tw, int gx, Skel skl,
+// The B operand of the contraction for every node tile: row kk = 2p + c of
+// tile t holds c_p cos(theta) (c = 0) or -c_p sin(theta) (c = 1) at the 64
+// nodes X of the tile, theta = 2 pi p X / gx, from the FP32 table entry
+// p X mod gx; rows with p >= nx/2 (up to the chunk-padded row count) are
+// zero.  It does not depend on the window row, so it is formed once per
+// evaluation instead of once per workgroup.  basis: [ntx][dft_rows(hx)][DX_T].
+__host__ __device__ constexpr int dft_rows(int hx) { return (2 * hx + DX_KC - 1) / DX_KC * DX_KC; }
+
+__global__ void __launch_bounds__(256) k_dft_basis(const cf* __restrict__ tw, int gx, int ix0, int hx, int ntx,
+                                                   float* __restrict__ basis) {
+  const int Kp = dft_rows(hx);
+  const long long total = (long long)ntx * Kp * DX_T;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int n = (int)(e % DX_T);
+    const int kk = (int)((e / DX_T) % Kp);
+    const int t = (int)(e / ((long long)DX_T * Kp));
+    const int X = (ix0 + t * DX_T + n) % gx;
+    const int p = kk >> 1;
+    float v = 0.f;
+    if (p < hx) {
+      const cf w = tw[(int)(((long long)p * X) % gx)];
+      const float cp = p == 0 ? 1.f : 2.f;
+      v = (kk & 1) ? cp * w.y : cp * w.x;
+    }
+    basis[e] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const float* __restrict__ basis, Skel skl,
                                                    int L, int K, int nitems, float* __restrict__ coef) {
   extern __shared__ __align__(16) unsigned char smem[];
   typedef float v4f __attribute__((ext_vector_type(4)));
   // the tiles of one window row read the same mode rows: consecutive tiles
   // go to the workgroups of one XCD, so its L2 serves the shared rows
   const int tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int r = tile / gridDim.x, x0 = (tile - r * gridDim.x) * DX_T;
+  const int r = tile / gridDim.x, xt = tile - r * gridDim.x, x0 = xt * DX_T;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int hx = G.nx / 2, Kr = 2 * hx;
   const int mt_n = (nitems + 15) / 16, rows = mt_n * 16;
@@ -383,12 +412,14 @@ __global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const cf* _
   }
   const cf* inter = reinterpret_cast<const cf*>(A.inter);
   static_assert(DX_T == 64 && DX_KC == 32, "fills assume 64 nodes and 16 modes per chunk");
-  const int Xn = (A.ix0 + x0 + (tid & (DX_T - 1))) % gx;  // this thread's node in the B fill
-  const int dX2 = (2 * Xn) % gx;
   // A fill: thread -> mode pp = tid & 15 of items it = tid >> 4, it + 16, ...
   const int pp = tid & 15, it0 = tid >> 4;
   const int nA = (rows + 15) / 16;  // items per thread (<= 8)
+  // B fill: thread -> 8 consecutive floats (two float4) of the 32 x 64 chunk
+  const int brow = tid >> 3, bcol = (tid & 7) * 8;
+  const float* btile = basis + (size_t)xt * dft_rows(hx) * DX_T;  // rows >= Kr are zero
   cf pre[DX_MAXMT];
+  v4f preb0, preb1;
   auto fetchA = [&](int p0) {
 #pragma unroll
     for (int q = 0; q < DX_MAXMT; ++q) {
@@ -397,6 +428,9 @@ __global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const cf* _
       if (q < nA && item < nitems && p < hx) v = inter[((size_t)item * A.wy + r) * G.nxh + p];
       pre[q] = v;
     }
+    const v4f* bsrc = reinterpret_cast<const v4f*>(btile + (size_t)(2 * p0 + brow) * DX_T + bcol);
+    preb0 = bsrc[0];
+    preb1 = bsrc[1];
   };
   constexpr int MTW = DX_MAXMT / 4;  // M tiles per wavefront
   v4f acc[MTW][4];
@@ -413,24 +447,8 @@ __global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const cf* _
       const int item = it0 + 16 * q;
       if (q < nA && item < rows) *reinterpret_cast<float2*>(&As[item * DX_SA + 2 * pp]) = make_float2(pre[q].x, pre[q].y);
     }
-    {
-      // thread -> fixed node n and rows kk = tid/64 + 4 i (modes p advancing by 2):
-      // the twiddle index p X mod gx advances by 2 X mod gx
-      const int n = tid & (DX_T - 1), kk0 = tid >> 6;
-      int p = p0 + (kk0 >> 1);
-      int t = (int)(((long long)p * Xn) % gx);
-      for (int kk = kk0; kk < DX_KC; kk += 4, p += 2) {
-        float v = 0.f;
-        if (p < hx) {
-          const cf w = tw[t];  // e^{-i theta}, theta = 2 pi p X / gx (table cached in L1/L2)
-          const float cp = p == 0 ? 1.f : 2.f;
-          v = (kk & 1) ? cp * w.y : cp * w.x;  // -c_p sin(theta) or c_p cos(theta)
-        }
-        Bs[kk * DX_SB + n] = v;
-        t += dX2;
-        if (t >= gx) t -= gx;
-      }
-    }
+    *reinterpret_cast<v4f*>(&Bs[brow * DX_SB + bcol]) = preb0;
+    *reinterpret_cast<v4f*>(&Bs[brow * DX_SB + bcol + 4]) = preb1;
     __syncthreads();
     if (k0 + DX_KC < Kr) fetchA(p0 + DX_KC / 2);  // next chunk in flight during the products
 #pragma unroll
@@ -502,6 +520,8 @@ __global__ void k_fill(float* p, size_t n, float v) {
 struct EvalWork {
   void* inter = nullptr;
   size_t inter_bytes = 0;
+  void* basis = nullptr;  // B operand of the DFT coefficient pass
+  size_t basis_bytes = 0;
   double* zdev = nullptr;
   size_t zcap = 0;
 };
@@ -663,9 +683,17 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
                               std::max((size_t)rows * DX_SA + (size_t)DX_KC * DX_SB, (size_t)rows * DX_SS)) *
                              sizeof(float);
       if (nitems <= DX_MAXMT * 16 && lds_dft <= 160 * 1024) {
-        dim3 grid((A.wx + DX_T - 1) / DX_T, A.wy);
-        sw_launch(h, SWENSE_K_XEVAL, &k_xcoef_dft, grid, dim3(256), lds_dft, h->st, A, h->G,
-                  reinterpret_cast<const cf*>(px.tw), px.n, *skel, L, K, nitems, out);
+        const int ntx = (A.wx + DX_T - 1) / DX_T;
+        const int hx = h->G.nx / 2;
+        const size_t nb = (size_t)ntx * dft_rows(hx) * DX_T;
+        ensure(&w->basis, &w->basis_bytes, nb * sizeof(float));
+        float* basis = reinterpret_cast<float*>(w->basis);
+        const unsigned bblk = (unsigned)std::min<size_t>((nb + 255) / 256, 4096);
+        sw_launch(h, SWENSE_K_AUX, &k_dft_basis, dim3(bblk), dim3(256), 0, h->st, reinterpret_cast<const cf*>(px.tw),
+                  px.n, A.ix0, hx, ntx, basis);
+        dim3 grid(ntx, A.wy);
+        sw_launch(h, SWENSE_K_XEVAL, &k_xcoef_dft, grid, dim3(256), lds_dft, h->st, A, h->G, basis, *skel, L, K,
+                  nitems, out);
         return;
       }
     }
@@ -766,6 +794,7 @@ size_t coef_floats(swense_hos* h, const swense_grid_desc* gd, unsigned cm) { ret
 void eval_release(swense_hos* h) {
   if (!h->ev) return;
   if (h->ev->inter) (void)hipFree(h->ev->inter);
+  if (h->ev->basis) (void)hipFree(h->ev->basis);
   if (h->ev->zdev) (void)hipFree(h->ev->zdev);
   delete h->ev;
   h->ev = nullptr;
