@@ -414,7 +414,8 @@ def main():
     ms_interp = e0.elapsed_time(e1) / args.steps
     print(f"# hos {ms_hos:.3f} ms/step, interp+eval {ms_interp:.3f} ms", file=sys.stderr, flush=True)
 
-    # per-kernel pass: the same steps with every launch bracketed by HIP events
+    # per-kernel pass: the same steps, every launch carrying HIP start/stop
+    # events that the runtime stamps when the kernel itself starts and ends
     h.profile(True)
     for _ in range(args.steps):
         step()
@@ -423,9 +424,9 @@ def main():
     h.profile(False)
     launches_per_step = {k: c / args.steps for k, (_, c) in prof.items()}
     ctx = {"n": cells.n, "nl": zl.size, "wx": wx, "wy": wy}
-    # every launch of the profiled pass is bracketed by a pair of HIP events on
-    # the handle's stream; their sum per step exceeds the plain step time (the
-    # brackets separate launches that otherwise follow each other closely)
+    # the sum of the kernel times per step leaves out the gaps between
+    # launches (and counts the evaluation kernels that the concurrent form
+    # overlaps with the step)
     prof_step_ms = sum(ms for ms, _ in prof.values()) / args.steps
     kinds = sorted(prof, key=lambda k: -prof[k][0])
     dom = kinds[0]

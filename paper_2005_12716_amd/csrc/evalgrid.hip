@@ -369,17 +369,17 @@ __host__ __device__ constexpr int dft_rows(int hx) { return (2 * hx + DX_KC - 1)
 __global__ void __launch_bounds__(256) k_dft_basis(const cf* __restrict__ tw, int gx, int ix0, int hx, int ntx,
                                                    float* __restrict__ basis) {
   const int Kp = dft_rows(hx);
-  const long long total = (long long)ntx * Kp * DX_T;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int n = (int)(e % DX_T);
-    const int kk = (int)((e / DX_T) % Kp);
-    const int t = (int)(e / ((long long)DX_T * Kp));
+  const int total = ntx * Kp * DX_T;  // < 2^31: checked by the caller
+  const bool small = (long long)hx * gx < (1ll << 31);  // p X fits in 32 bits
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int n = e % DX_T;
+    const int kk = (e / DX_T) % Kp;
+    const int t = e / (DX_T * Kp);
     const int X = (ix0 + t * DX_T + n) % gx;
     const int p = kk >> 1;
     float v = 0.f;
     if (p < hx) {
-      const cf w = tw[(int)(((long long)p * X) % gx)];
+      const cf w = tw[small ? (p * X) % gx : (int)(((long long)p * X) % gx)];
       const float cp = p == 0 ? 1.f : 2.f;
       v = (kk & 1) ? cp * w.y : cp * w.x;
     }
@@ -686,6 +686,7 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
         const int ntx = (A.wx + DX_T - 1) / DX_T;
         const int hx = h->G.nx / 2;
         const size_t nb = (size_t)ntx * dft_rows(hx) * DX_T;
+        SW_REQUIRE(nb < (1ull << 31), "coefficient window too wide");
         ensure(&w->basis, &w->basis_bytes, nb * sizeof(float));
         float* basis = reinterpret_cast<float*>(w->basis);
         const unsigned bblk = (unsigned)std::min<size_t>((nb + 255) / 256, 4096);

@@ -2,6 +2,8 @@
 // the HOS and reconstruction translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "swense_surrogate.h"
 
@@ -177,32 +179,10 @@ struct swense_hos {
   size_t isz() const { return fp64 ? sizeof(cd) : sizeof(cf); }
 };
 
-// Brackets one launch with events when the handle's profiler is on.
-struct ProfScope {
-  swense_hos* h;
-  int kid;
-  hipEvent_t b = nullptr;
-  ProfScope(swense_hos* hh, int k) : h(hh), kid(k) {
-    if (h->prof.on) {
-      hipEvent_t a = h->prof.take();
-      b = h->prof.take();
-      SW_HIP(hipEventRecord(a, h->st));
-      h->prof.recs.push_back(ProfRec{kid, a, b});
-    }
-  }
-  ~ProfScope() {
-    if (b) (void)hipEventRecord(b, h->st);
-  }
-};
-
-#define SW_LAUNCH(h, kid, ...)          \
-  do {                                  \
-    ProfScope ps_((h), (kid));          \
-    hipLaunchKernelGGL(__VA_ARGS__);    \
-    SW_HIP(hipGetLastError());          \
-  } while (0)
-
-// Launch with optional >64 KB dynamic LDS and per-kernel timing.
+// Launch with optional >64 KB dynamic LDS and per-kernel timing: while the
+// handle's profiler is on, the launch carries a start and a stop event that
+// the runtime stamps when the kernel itself starts and ends (kernel time, as
+// a trace records it, without the launch's queueing).
 template <typename... KArgs, typename... Args>
 void sw_launch(swense_hos* h, int kid, void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds, hipStream_t st,
                Args... args) {
@@ -216,10 +196,17 @@ void sw_launch(swense_hos* h, int kid, void (*kernel)(KArgs...), dim3 grid, dim3
       done[key] = lds;
     }
   }
-  ProfScope ps(h, kid);
-  hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+  if (h->prof.on) {
+    hipEvent_t a = h->prof.take(), b = h->prof.take();
+    h->prof.recs.push_back(ProfRec{kid, a, b});
+    hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, st, a, b, 0u, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+  }
   SW_HIP(hipGetLastError());
 }
+
+#define SW_LAUNCH(h, kid, kernel, ...) sw_launch((h), (kid), &kernel, __VA_ARGS__)
 
 // ---- launch helpers implemented in hos.hip (templated on precision there)
 void launch_yinv(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, int row0, hipStream_t st);
