@@ -614,7 +614,7 @@ __device__ __forceinline__ R w2sum_n(const R* W, int K) {
 
 template <typename R, int MAXE, int NS0, int MW>
 __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
-  static_assert(NS0 >= 256 && NS0 <= 1024, "rounds version for compile-time rows of 256 to 1024 points");
+  static_assert(NS0 >= 256 && NS0 <= 1024 && NS0 % 256 == 0, "rounds version for compile-time rows of 256 to 1024 points");
   constexpr int PPT = (NS0 + 255) / 256;  // points per thread
   constexpr int KP = NS0 / 128;            // kept modes per lane (p < Px / 2)
   constexpr int Q4 = NS0 / 4;              // sub-transform length of the output transform
@@ -635,6 +635,14 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
     eta[j] = ge2[j] = dot[j] = gp2[j] = etat[j] = phit[j] = (R)0;
 #pragma unroll
     for (int m = 0; m < MW; ++m) W[j][m] = (R)0;
+  }
+  // role, power of eta and order of every input, read once from the
+  // arguments into LDS (visible after the first round's barrier): the fold
+  // then takes them from LDS instead of a chain of dependent argument loads
+  __shared__ int s_code[kMaxXIn];
+  if ((int)threadIdx.x < A.nin) {
+    const XIn& f = A.in[threadIdx.x];
+    s_code[threadIdx.x] = f.role | (f.pw << 8) | (f.wi << 16);
   }
   const int npairs = (A.nin + 1) / 2;
   const int nrounds = (npairs + 3) / 4;
@@ -687,11 +695,12 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
     __syncthreads();
     const int i1 = min(A.nin, 8 * (rd + 1));
     for (int i = 8 * rd; i < i1; ++i) {
-      const XIn& f = A.in[i];
+      const int code = __builtin_amdgcn_readfirstlane(s_code[i]);
+      const int role = code & 255, pw = (code >> 8) & 255, wi = code >> 16;
       const C* zb = bufs + (size_t)((i >> 1) - 4 * rd) * wl;
       const bool hi = i & 1;
       R c[PPT];
-      if (f.role == XR_G) {
+      if (role == XR_G) {
         // eta^pw / pw! (pw <= M <= MW); unrolled, so the divisions by 1, 2
         // and 4 become exact multiplications
 #pragma unroll
@@ -699,16 +708,18 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
           c[j] = (R)1;
 #pragma unroll
           for (int k = 1; k <= MW; ++k)
-            if (k <= f.pw) c[j] *= eta[j] / (R)k;
+            if (k <= pw) c[j] *= eta[j] / (R)k;
         }
       }
+      // the row values at this thread's points (Px = 256 PPT), all read first
+      C zv[PPT];
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) zv[j] = zb[sk(threadIdx.x + 256 * j)];
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        const int x = threadIdx.x + 256 * j;
-        if (x >= Px) break;
-        const C zx = zb[sk(x)];
+        const C zx = zv[j];
         const R v = hi ? zx.y : zx.x;
-        switch (f.role) {
+        switch (role) {
           case XR_ETA: eta[j] = v; break;
           case XR_GRADPAIR: {
             const R b = zx.y;
@@ -719,7 +730,7 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
           case XR_G:
 #pragma unroll
             for (int m = 0; m < MW; ++m)
-              if (m == f.wi) W[j][m] += c[j] * v;
+              if (m == wi) W[j][m] += c[j] * v;
             break;
           case XR_ETAT: etat[j] = v; break;
           case XR_PHIT: phit[j] = v; break;
