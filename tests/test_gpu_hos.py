@@ -52,6 +52,24 @@ def test_rhs_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision):
     h.close()
 
 
+# Padded y lengths 256, 512, 1024, 2048 and 4096 (powers of two): the y
+# transforms run one kx column per workgroup on the four-wavefront FFT.
+WG_CASES = [
+    # dim, nx, ny, depth, M, dealias   -> padded Py
+    (3, 64, 128, -1.0, 3, 1),  # 256
+    (3, 32, 256, 2.0, 3, 1),   # 512, finite depth
+    (3, 16, 512, -1.0, 3, 1),  # 1024
+    (3, 8, 1024, -1.0, 3, 1),  # 2048
+    (3, 8, 2048, 1.5, 3, 1),   # 4096
+]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("dim,nx,ny,depth,M,dealias", WG_CASES)
+def test_rhs_parity_workgroup_y_transforms(gpu_lib, dim, nx, ny, depth, M, dealias, precision):
+    test_rhs_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision)
+
+
 @pytest.mark.parametrize("precision", [1, 0])
 @pytest.mark.parametrize("dim,nx,ny,depth,M,dealias", CASES[:4])
 def test_steps_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision):
