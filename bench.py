@@ -335,7 +335,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the workload is a single "
-              "realisation and this build has no multi-GPU path", file=sys.stderr)
+              "realisation and the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
