@@ -141,25 +141,31 @@ __global__ void __launch_bounds__(256) k_gather_col(GatherArgs A, const Col* __r
   const size_t n = (size_t)A.n;
   for (int i = lane; i < c.count; i += 64) {
     const int sp = c.start + i;
+    // every per-point value is read before any is used
     const int orig = pd.perm[sp];
     const int l0 = c.nlc > 0 ? pd.l0[sp] : -1;
+    float wz[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) wz[a] = pd.wz[(size_t)a * n + sp];
+    const float pz = A.p_slot >= 0 ? pd.pz[sp] : 0.f;
     if (l0 < 0) {
       for (int o = 0; o < A.nout; ++o) A.out[(size_t)o * n + orig] = __builtin_nanf("");
       continue;
     }
-    float wz[4];
-    for (int a = 0; a < 4; ++a) wz[a] = pd.wz[(size_t)a * n + sp];
     const int base = l0 - c.lmin;
     auto vol = [&](int f) {
       const float* hf = h + f * c.nlc + base;
       return wz[0] * hf[0] + wz[1] * hf[1] + wz[2] * hf[2] + wz[3] * hf[3];
     };
-    for (int o = 0; o < A.nout; ++o) {
+    // unrolled over the output slots, so their field indices are read once
+#pragma unroll
+    for (int o = 0; o < 11; ++o) {
+      if (o >= A.nout) break;
       float v = 0.f;
       if (o == A.p_slot) {
         const float pt = vol(A.c_phit), u = vol(A.c_u), w = vol(A.c_w);
         const float vv = A.c_v >= 0 ? vol(A.c_v) : 0.f;
-        v = -A.rho * (pt + 0.5f * (u * u + vv * vv + w * w)) - pd.pz[sp];
+        v = -A.rho * (pt + 0.5f * (u * u + vv * vv + w * w)) - pz;
       } else if (A.vol[o] >= 0) {
         v = vol(A.vol[o]);
       } else if (A.srf[o] >= 0) {
