@@ -196,7 +196,9 @@ void sw_launch(swense_hos* h, int kid, void (*kernel)(KArgs...), dim3 grid, dim3
       done[key] = lds;
     }
   }
-  if (h->prof.on) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (h->prof.on) SW_HIP(hipStreamIsCapturing(st, &cs));
+  if (h->prof.on && cs == hipStreamCaptureStatusNone) {  // launches being captured are not timed
     hipEvent_t a = h->prof.take(), b = h->prof.take();
     h->prof.recs.push_back(ProfRec{kid, a, b});
     hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, st, a, b, 0u, args...);
