@@ -45,7 +45,7 @@ extern "C" {
 #endif
 
 typedef struct swense_fno_desc {
-  int n;         /* grid points per axis: 64, 128, 256 or 512                 */
+  int n;         /* grid points per axis: 64, 128, 256, 512 or 1024           */
   int channels;  /* C: even, 2..256                                           */
   int layers;    /* L: 1..32                                                  */
   int p_modes;   /* P: retained p in [0, P), 1 <= P < n/2                     */

@@ -861,7 +861,8 @@ void spec_fwd(swense_fno* f, const float* v, cf* U, int B, float scale, int cp_f
     case 64: spec_fwd_n<64>(f, v, U, B, scale, cp_flag); break;
     case 128: spec_fwd_n<128>(f, v, U, B, scale, cp_flag); break;
     case 256: spec_fwd_n<256>(f, v, U, B, scale, cp_flag); break;
-    default: spec_fwd_n<512>(f, v, U, B, scale, cp_flag); break;
+    case 512: spec_fwd_n<512>(f, v, U, B, scale, cp_flag); break;
+    default: spec_fwd_n<1024>(f, v, U, B, scale, cp_flag); break;
   }
 }
 
@@ -870,7 +871,8 @@ void spec_inv(swense_fno* f, const cf* Y, float* out, int B, float scale, float 
     case 64: spec_inv_n<64>(f, Y, out, B, scale, beta); break;
     case 128: spec_inv_n<128>(f, Y, out, B, scale, beta); break;
     case 256: spec_inv_n<256>(f, Y, out, B, scale, beta); break;
-    default: spec_inv_n<512>(f, Y, out, B, scale, beta); break;
+    case 512: spec_inv_n<512>(f, Y, out, B, scale, beta); break;
+    default: spec_inv_n<1024>(f, Y, out, B, scale, beta); break;
   }
 }
 
@@ -942,7 +944,8 @@ void mix_dw(swense_fno* f, const cf* U, const cf* gY, float* gR, int B) {
 
 void check_fno_desc(const swense_fno_desc* d) {
   SW_REQUIRE(d != nullptr, "null descriptor");
-  SW_REQUIRE(d->n == 64 || d->n == 128 || d->n == 256 || d->n == 512, "n must be 64, 128, 256 or 512");
+  SW_REQUIRE(d->n == 64 || d->n == 128 || d->n == 256 || d->n == 512 || d->n == 1024,
+             "n must be 64, 128, 256, 512 or 1024");
   SW_REQUIRE(d->channels >= 2 && d->channels % 2 == 0 && d->channels <= 256, "channels must be even, <= 256");
   SW_REQUIRE(d->layers >= 1 && d->layers <= 32, "layers in [1, 32]");
   SW_REQUIRE(d->p_modes >= 1 && d->p_modes < d->n / 2, "p_modes in [1, n/2)");

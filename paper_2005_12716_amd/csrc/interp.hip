@@ -260,20 +260,27 @@ namespace {
 
 // Skeleton heights (host, FP64).  Rows: |k| sampled on [0, kmax] for both
 // factor families C = cosh k(z+h)/cosh kh and S = sinh k(z+h)/cosh kh (deep
-// water: e^{kz} for both), each row scaled by max(1, max_l |factor|);
-// columns: the layers.  Greedy column-pivoted Gram-Schmidt picks layers until
-// every remaining column is reproduced to `tol` (per row, relative to the
-// row scale); T = least-squares coefficients of every layer on the picks,
-// separately for C and S.  Returns false if no worthwhile reduction exists.
+// water: e^{kz} for both); columns: the layers.  Picks: greedy
+// column-pivoted Gram-Schmidt on the rows scaled by max(1, max_l |factor|)
+// until every remaining column is reproduced to `tol`.  Coefficients: each
+// layer is a weighted least-squares combination of the picks with row i
+// weighted by 1 / max(1, |factor_i(z_l)|), so that the layer's own factors
+// are met to `tol` of their size (floored at the mean-level size 1) - above
+// the mean level the factors grow as e^{kz}, and a bound relative to the
+// largest layer would leave the deeper layers with errors of that size.
+// Accepted when, with the coefficients rounded to FP32, every layer's
+// weighted error is within 10 tol and the weighted sum of |coefficient| x
+// |pick factor| (the growth of the picks' own FP32 rounding) within 10;
+// failing layers join the picks, at most four more.  Returns false if no
+// worthwhile reduction exists.
 bool build_skeleton(const std::vector<double>& z, double kmax, double depth, double tol, std::vector<int>& sel,
                     std::vector<float>& tc, std::vector<float>& ts) {
   const int L = (int)z.size();
   const int nk = 1024;
   const bool deep = !(depth > 0);
-  std::vector<double> BC((size_t)nk * L), BS((size_t)nk * L);
+  std::vector<double> FC((size_t)nk * L), FS((size_t)nk * L);  // raw factors, [l][i]
   for (int i = 0; i < nk; ++i) {
     const double k = kmax * i / (nk - 1);
-    double sc = 1.0, ss = 1.0;
     for (int l = 0; l < L; ++l) {
       double c, sv;
       if (deep) {
@@ -283,24 +290,24 @@ bool build_skeleton(const std::vector<double>& z, double kmax, double depth, dou
         c = (a + b) / d;
         sv = (a - b) / d;
       }
-      BC[(size_t)l * nk + i] = c;
-      BS[(size_t)l * nk + i] = sv;
-      sc = std::max(sc, std::fabs(c));
-      ss = std::max(ss, std::fabs(sv));
-    }
-    for (int l = 0; l < L; ++l) {
-      BC[(size_t)l * nk + i] /= sc;
-      BS[(size_t)l * nk + i] /= ss;
+      FC[(size_t)l * nk + i] = c;
+      FS[(size_t)l * nk + i] = sv;
     }
   }
-  // joint residual matrix [BC; BS], column-major, 2 nk rows
+  // joint residual matrix [BC; BS] of row-scaled factors, column-major, 2 nk rows
   const int m = 2 * nk;
   std::vector<double> Rm((size_t)m * L);
-  for (int l = 0; l < L; ++l)
-    for (int i = 0; i < nk; ++i) {
-      Rm[(size_t)l * m + i] = BC[(size_t)l * nk + i];
-      Rm[(size_t)l * m + nk + i] = BS[(size_t)l * nk + i];
+  for (int i = 0; i < nk; ++i) {
+    double sc = 1.0, ss = 1.0;
+    for (int l = 0; l < L; ++l) {
+      sc = std::max(sc, std::fabs(FC[(size_t)l * nk + i]));
+      ss = std::max(ss, std::fabs(FS[(size_t)l * nk + i]));
     }
+    for (int l = 0; l < L; ++l) {
+      Rm[(size_t)l * m + i] = FC[(size_t)l * nk + i] / sc;
+      Rm[(size_t)l * m + nk + i] = FS[(size_t)l * nk + i] / ss;
+    }
+  }
   sel.clear();
   std::vector<char> used(L, 0);
   for (int it = 0; it < L; ++it) {
@@ -329,35 +336,47 @@ bool build_skeleton(const std::vector<double>& z, double kmax, double depth, dou
         for (int i = 0; i < m; ++i) Rm[(size_t)l * m + i] -= dp * q[i];
       }
   }
-  const int R = (int)sel.size();
-  if (R == 0 || 4 * R > 3 * L) return false;
+  if (sel.empty()) return false;
   std::sort(sel.begin(), sel.end());
-  // least squares per family via modified Gram-Schmidt on the picked columns
-  auto solve = [&](const std::vector<double>& B, std::vector<float>& T) -> double {
-    std::vector<double> Q((size_t)nk * R), Rr((size_t)R * R, 0.0);
-    for (int j = 0; j < R; ++j) {
-      for (int i = 0; i < nk; ++i) Q[(size_t)j * nk + i] = B[(size_t)sel[j] * nk + i];
-      for (int pass = 0; pass < 2; ++pass)  // modified Gram-Schmidt, reorthogonalised
-        for (int p = 0; p < j; ++p) {
-          double dp = 0.0;
-          for (int i = 0; i < nk; ++i) dp += Q[(size_t)p * nk + i] * Q[(size_t)j * nk + i];
-          Rr[(size_t)p * R + j] += dp;
-          for (int i = 0; i < nk; ++i) Q[(size_t)j * nk + i] -= dp * Q[(size_t)p * nk + i];
-        }
-      double nn = 0.0;
-      for (int i = 0; i < nk; ++i) nn += Q[(size_t)j * nk + i] * Q[(size_t)j * nk + i];
-      nn = std::sqrt(nn);
-      Rr[(size_t)j * R + j] = nn;
-      if (nn > 0)
-        for (int i = 0; i < nk; ++i) Q[(size_t)j * nk + i] /= nn;
-    }
+  // per-layer weighted least squares (modified Gram-Schmidt, reorthogonalised);
+  // returns the worst layer's badness (> 1: fails) and that layer
+  auto solve = [&](const std::vector<double>& F, std::vector<float>& T, int& worst) -> double {
+    const int R = (int)sel.size();
     T.assign((size_t)L * R, 0.f);
-    double err = 0.0;
-    std::vector<double> c(R);
+    std::vector<double> Q((size_t)nk * R), Rr((size_t)R * R), w(nk), c(R);
+    double bad = 0.0;
+    worst = -1;
     for (int l = 0; l < L; ++l) {
+      const double* f = &F[(size_t)l * nk];
+      const int self = int(std::find(sel.begin(), sel.end(), l) - sel.begin());
+      if (self < R) {
+        T[(size_t)l * R + self] = 1.f;
+        continue;
+      }
+      for (int i = 0; i < nk; ++i) w[i] = 1.0 / std::max(1.0, std::fabs(f[i]));
+      std::fill(Rr.begin(), Rr.end(), 0.0);
+      for (int j = 0; j < R; ++j) {
+        double* qj = &Q[(size_t)j * nk];
+        const double* pj = &F[(size_t)sel[j] * nk];
+        for (int i = 0; i < nk; ++i) qj[i] = pj[i] * w[i];
+        for (int pass = 0; pass < 2; ++pass)
+          for (int p = 0; p < j; ++p) {
+            const double* qp = &Q[(size_t)p * nk];
+            double dp = 0.0;
+            for (int i = 0; i < nk; ++i) dp += qp[i] * qj[i];
+            Rr[(size_t)p * R + j] += dp;
+            for (int i = 0; i < nk; ++i) qj[i] -= dp * qp[i];
+          }
+        double nn = 0.0;
+        for (int i = 0; i < nk; ++i) nn += qj[i] * qj[i];
+        nn = std::sqrt(nn);
+        Rr[(size_t)j * R + j] = nn;
+        if (nn > 0)
+          for (int i = 0; i < nk; ++i) qj[i] /= nn;
+      }
       for (int j = 0; j < R; ++j) {
         double dp = 0.0;
-        for (int i = 0; i < nk; ++i) dp += Q[(size_t)j * nk + i] * B[(size_t)l * nk + i];
+        for (int i = 0; i < nk; ++i) dp += Q[(size_t)j * nk + i] * f[i] * w[i];
         c[j] = dp;
       }
       for (int j = R - 1; j >= 0; --j) {  // back substitution R t = Q^T b
@@ -366,17 +385,33 @@ bool build_skeleton(const std::vector<double>& z, double kmax, double depth, dou
         c[j] = Rr[(size_t)j * R + j] != 0 ? v / Rr[(size_t)j * R + j] : 0.0;
       }
       for (int j = 0; j < R; ++j) T[(size_t)l * R + j] = (float)c[j];
+      double e = 0.0, g = 0.0;
       for (int i = 0; i < nk; ++i) {
-        double v = 0.0;
-        for (int j = 0; j < R; ++j) v += c[j] * B[(size_t)sel[j] * nk + i];
-        err = std::max(err, std::fabs(v - B[(size_t)l * nk + i]));
+        double v = 0.0, a = 0.0;
+        for (int j = 0; j < R; ++j) {
+          const double t = (double)T[(size_t)l * R + j], pf = F[(size_t)sel[j] * nk + i];
+          v += t * pf;
+          a += std::fabs(t * pf);
+        }
+        e = std::max(e, std::fabs(v - f[i]) * w[i]);
+        g = std::max(g, a * w[i]);
       }
+      const double b = std::max(e / (10 * tol), g / 10.0);
+      if (b > bad) { bad = b; worst = l; }
     }
-    return err;
+    return bad;
   };
-  const double ec = solve(BC, tc);
-  const double es = solve(BS, ts);
-  return ec <= 10 * tol && es <= 10 * tol;
+  const size_t r0 = sel.size();
+  for (;;) {
+    if (4 * sel.size() > 3 * (size_t)L || sel.size() > r0 + 4) return false;
+    int wc = -1, ws = -1;
+    const double bc = solve(FC, tc, wc);
+    const double bs = deep ? bc : solve(FS, ts, ws);
+    if (deep) ts = tc;
+    if (bc <= 1.0 && bs <= 1.0) return true;
+    sel.push_back(bc >= bs ? wc : ws);
+    std::sort(sel.begin(), sel.end());
+  }
 }
 
 // Host binding in FP64: stencils, column grouping, ordering.

@@ -54,10 +54,11 @@ def _setup(lib, cfg, B, seed):
 
 SMALL = [F.FnoConfig(n=64, channels=8, layers=2, p_modes=8, q_modes=7, hidden=16),
          F.FnoConfig(n=128, channels=6, layers=3, p_modes=5, q_modes=9, hidden=10),
-         F.FnoConfig(n=64, channels=12, layers=2, p_modes=6, q_modes=10, hidden=20, in_channels=4)]
+         F.FnoConfig(n=64, channels=12, layers=2, p_modes=6, q_modes=10, hidden=20, in_channels=4),
+         F.FnoConfig(n=1024, channels=4, layers=1, p_modes=8, q_modes=7, hidden=8)]
 
 
-@pytest.mark.parametrize("cfg", SMALL, ids=["n64c8", "n128c6", "n64c12in4"])
+@pytest.mark.parametrize("cfg", SMALL, ids=["n64c8", "n128c6", "n64c12in4", "n1024c4"])
 def test_fno_forward_backward_parity(gpu_lib, cfg):
     from paper_2005_12716_amd import lib
     B = 2

@@ -1,0 +1,250 @@
+"""Steep large sea at full size, through the C ABI: 1024 x 1024 modes over
+40 x 40 peak wavelengths, order M = 5, JONSWAP Hs/lambda_p = 0.04, gamma = 5,
+cos^2 spreading, deep water, phases seed 5, FP32 transforms with FP64 state;
+20M cell centres of a hex mesh (500 x 250 x 160 cells over 8 x 4 lambda_p at
+the domain centre, z in [-lambda_p/2, 0.2 lambda_p] clustered about the mean
+level with smallest cell Hs/16, +-10 % jitter with seed 6), coefficient grid
+refined four times (4096 x 4096 nodes, windowed with a halo), 64 layers.
+
+Inputs come from the oracle's JONSWAP generator with the shared seeded
+phases.  Checks against the FP64 oracle:
+* the right-hand side (relative L2 over all modes < 1e-5) and the state
+  after one RK4 step (< 1e-6);
+* all 11 fields at the 20M points: every point inside the grid and finite;
+  u, w and p at sampled points within 1e-5 of the oracle, per point and
+  relative to the larger of the value and the field's plane RMS at that
+  height; the oracle's spline coefficients at each point's 4 x 4 x 4
+  stencil nodes are direct modal sums (with the prefilter), combined with
+  the same B-spline and Lagrange weights;
+* the finite-volume divergence over the unjittered mesh (60M face centres):
+  its reported RMS and maximum agree with the returned field, and sampled
+  cells match the oracle's face sums of the same direct-sum interpolant.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import Grid, hos, sea
+from oracle import reconstruct as rc
+
+pytestmark = pytest.mark.gpu
+
+LAM = 2 * math.pi
+N, M = 1024, 5
+L = 40 * LAM
+HS = 0.04 * LAM
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _sea():
+    g = Grid(nx=N, ny=N, lx=L, ly=L, depth=-1.0, order_m=M)
+    e, p = sea.jonswap(g, HS, 1.0, 5.0, synth.mode_phases(5, N, N // 2 + 1), "cos2")
+    return g, e, p
+
+
+BOX = (L / 2 - 4 * LAM, L / 2 - 2 * LAM, 8 * LAM, 4 * LAM)   # x0, y0, wx, wy
+ZR = (-0.5 * LAM, 0.2 * LAM)
+GX = 4 * N
+
+
+def _mesh():
+    x0, y0, wx, wy = BOX
+    return synth.hex_cloud(6, x0, y0, wx, wy, ZR[0], ZR[1], 500, 250, 160, HS / 16)
+
+
+def _grid(lib, mesh):
+    """Coefficient grid: 4096^2 nodes windowed on the box with a halo, 64
+    layers spanning the mesh."""
+    x0, y0, wx, wy = BOX
+    dx = L / GX
+    win = (int(math.floor(x0 / dx)) - 2, int(math.floor(y0 / dx)) - 2, int(math.ceil(wx / dx)) + 6,
+           int(math.ceil(wy / dx)) + 6)
+    zl = synth.clustered_layers(mesh["ze"][0] - 1e-9, mesh["ze"][-1] + 1e-9, 64, HS / 16)
+    return lib.grid_desc(GX, GX, zl, win), zl
+
+
+def _plane_rms(g, fh):
+    """RMS over the horizontal plane of the real field with half spectrum fh
+    (kept modes: p < nx/2, -ny/2 < q < ny/2)."""
+    hx = g.nx // 2
+    q = np.arange(g.ny)
+    keep = q != g.ny // 2
+    w = np.where(np.arange(hx) == 0, 1.0, 2.0)
+    return math.sqrt(float(np.sum(w[None, :] * np.abs(fh[keep, :hx]) ** 2)))
+
+
+def _oracle_at(g, A, At, zl, f, P):
+    """Oracle interpolant of volume field f at points P [3][k]: each stencil
+    node's prefiltered spline coefficient by direct modal sum, weighted as in
+    the oracle's interpolation."""
+    ixs, wxs, _, okx = rc._hstencil(P[0], L / GX, 0, GX, GX)
+    iys, wys, _, oky = rc._hstencil(P[1], L / GX, 0, GX, GX)
+    l0, wz, _, okz = rc.lagrange_weights(np.asarray(zl), P[2])
+    assert okx.all() and oky.all() and okz.all()
+    vals = np.zeros(P.shape[1])
+    for k in range(P.shape[1]):
+        X = np.repeat(ixs[:, k], 4)      # node (y index b, x index a) pairs
+        Y = np.tile(iys[:, k], 4)
+        w_h = np.repeat(wxs[:, k], 4) * np.tile(wys[:, k], 4)
+        for c in range(4):
+            fh = rc.field_spectrum(g, f, A, At, float(zl[l0[k] + c]))
+            vals[k] += wz[c, k] * float(np.dot(w_h, _direct_nodes(g, fh, GX, GX, X, Y)))
+    return vals
+
+
+def test_steep_sea_rhs_and_step(gpu_lib):
+    from paper_2005_12716_amd import lib
+    g, e, p = _sea()
+    d = lib.hos_desc(3, N, N, L, L, -1.0, order_m=M, dt=LAM / 64)
+    h = lib.Hos(d, e, p)
+    et, pt = h.rhs()
+    er, pr = hos.rhs(g, e, p)
+    assert rel(et, er) < 1e-5 and rel(pt, pr) < 1e-5, (rel(et, er), rel(pt, pr))
+    h.step(1)
+    e1, p1, _ = h.state()
+    er1, pr1 = hos.run(g, e, p, d.dt, 1)
+    assert rel(e1, er1) < 1e-6 and rel(p1, pr1) < 1e-6, (rel(e1, er1), rel(p1, pr1))
+    h.close()
+
+
+def _direct_nodes(g, fh, gx, gy, X, Y):
+    """Prefiltered spline coefficients at global nodes (X[k], Y[k]) of the
+    gx x gy grid, by direct summation over the kept modes (the values the
+    oracle's node_values returns there)."""
+    hx = g.nx // 2
+    ps = np.arange(hx)
+    qs = np.arange(g.ny)
+    qs = np.where(qs < g.ny // 2, qs, qs - g.ny)
+    keep = qs > -(g.ny // 2)
+    bx = (4.0 + 2.0 * np.cos(2 * math.pi * ps / gx)) / 6.0
+    by = (4.0 + 2.0 * np.cos(2 * math.pi * qs / gy)) / 6.0
+    s = (fh[:, :hx] / (by[:, None] * bx[None, :]))[keep]
+    w = np.where(ps == 0, 1.0, 2.0)
+    ex = np.exp(2j * math.pi * np.outer(ps, X) / gx) * w[:, None]
+    ey = np.exp(2j * math.pi * np.outer(qs[keep], Y) / gy)
+    return np.real(np.sum((s @ ex) * ey, axis=0))
+
+
+def test_steep_sea_20M_points(gpu_lib):
+    import torch
+    from paper_2005_12716_amd import lib
+    g, e, p = _sea()
+    d = lib.hos_desc(3, N, N, L, L, -1.0, order_m=M, dt=LAM / 64)
+    h = lib.Hos(d, e, p)
+    pts, mesh = _mesh()
+    n = pts.shape[1]
+    assert n == 20_000_000
+    gd, zl = _grid(lib, mesh)
+    cells = h.bind(gd, torch.tensor(pts, device="cuda"))
+    out = torch.empty((11, n), dtype=torch.float32, device="cuda")
+    _, nbad = cells.interp(lib.ALL_FIELDS, out)
+    assert nbad == 0
+    assert bool(torch.isfinite(out).all())
+    # sampled points: spread over the mesh order, plus the point nearest the
+    # mean level and two further up the |z| ranking
+    order = np.argsort(np.abs(pts[2]))
+    idx = np.unique(np.concatenate([np.linspace(0, n - 1, 5).astype(np.int64), order[[0, n // 3, 2 * n // 3]]]))
+    sp = pts[:, idx]
+    got = out[:, torch.tensor(idx, device="cuda")].cpu().numpy().astype(np.float64)
+    A = hos.mean_level_modes(g, e, p)
+    At, _ = hos.mean_level_modes_t(g, e, p)
+    ref = {f: _oracle_at(g, A, At, zl, f, sp) for f in (rc.PHI_T, rc.U, rc.V, rc.W)}
+    ref[rc.P] = -g.rho * (ref[rc.PHI_T] + 0.5 * (ref[rc.U] ** 2 + ref[rc.V] ** 2 + ref[rc.W] ** 2) + g.g * sp[2])
+    # per point, relative to the larger of the value and the field's RMS over
+    # the horizontal plane at the point's height (Parseval over the kept
+    # modes): far above the crests the continued fields are sums of terms
+    # grown by e^{kz}, whose FP32 rounding sets the attainable accuracy
+    rms = {f: np.array([_plane_rms(g, rc.field_spectrum(g, f, A, At, float(z))) for z in sp[2]])
+           for f in (rc.PHI_T, rc.U, rc.V, rc.W)}
+    floor = {rc.U: rms[rc.U], rc.W: rms[rc.W],
+             rc.P: g.rho * (rms[rc.PHI_T] + rms[rc.U] ** 2 + rms[rc.V] ** 2 + rms[rc.W] ** 2)}
+    for f in (rc.U, rc.W, rc.P):
+        err = np.abs(got[f] - ref[f]) / np.maximum(np.abs(ref[f]), floor[f])
+        assert err.max() < 1e-5, (f, err)
+    cells.close()
+    h.close()
+
+
+def test_steep_sea_fv_divergence(gpu_lib):
+    from paper_2005_12716_amd import lib
+    g, e, p = _sea()
+    d = lib.hos_desc(3, N, N, L, L, -1.0, order_m=M, dt=LAM / 64)
+    h = lib.Hos(d, e, p)
+    _, mesh = _mesh()
+    xe, ye, ze = mesh["xe"], mesh["ye"], mesh["ze"]
+    gd, zl = _grid(lib, mesh)
+    div, rms, mx = h.fv_divergence(gd, xe, ye, ze)
+    got = div.cpu().numpy()
+    assert got.shape == (160, 250, 500)
+    g64 = got.astype(np.float64)
+    assert abs(rms - math.sqrt(float(np.mean(g64 ** 2)))) <= 1e-6 * rms
+    assert abs(mx - np.abs(g64).max()) <= 1e-6 * mx
+    # sampled cells (k, j, i): the oracle's face sums of the direct-sum interpolant
+    cells = [(0, 0, 0), (159, 249, 499), (80, 125, 250), (int(np.argmin(np.abs(ze))), 17, 311)]
+    A = hos.mean_level_modes(g, e, p)
+    At, _ = hos.mean_level_modes_t(g, e, p)
+    xc, yc, zc = (0.5 * (a[1:] + a[:-1]) for a in (xe, ye, ze))
+    for k, j, i in cells:
+        fu = np.array([[xe[i], xe[i + 1]], [yc[j]] * 2, [zc[k]] * 2])
+        fv = np.array([[xc[i]] * 2, [ye[j], ye[j + 1]], [zc[k]] * 2])
+        fw = np.array([[xc[i]] * 2, [yc[j]] * 2, [ze[k], ze[k + 1]]])
+        u = _oracle_at(g, A, At, zl, rc.U, fu)
+        v = _oracle_at(g, A, At, zl, rc.V, fv)
+        w = _oracle_at(g, A, At, zl, rc.W, fw)
+        dx, dy, dz = xe[i + 1] - xe[i], ye[j + 1] - ye[j], ze[k + 1] - ze[k]
+        ref = (u[1] - u[0]) / dx + (v[1] - v[0]) / dy + (w[1] - w[0]) / dz
+        scale = max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max()) / min(dx, dy, dz)
+        assert abs(got[k, j, i] - ref) <= 2e-5 * scale, ((k, j, i), got[k, j, i], ref, scale)
+    h.close()
+
+
+def test_steep_sea_plain_vs_surrogate(gpu_lib):
+    """Plain against surrogate-advanced rollout of the steep sea, with a
+    network of the surrogate architecture (64 channels, 8 layers, p < 32,
+    |q| <= 31, width 128) at 1024^2 that has not been trained for this sea:
+    the judge rejects its proposal on the first call (probation), the
+    cool-down hands the next calls to HOS, and the rollout is the plain HOS
+    run bit for bit."""
+    import time
+    import torch
+    from paper_2005_12716_amd import lib
+    g, e, p = _sea()
+    d = lib.hos_desc(3, N, N, L, L, -1.0, order_m=M, dt=LAM / 64)
+    S, calls = 10, 3
+    plain = lib.Hos(d, e, p)
+    plain.step(S * calls)
+    ep, pp, tp = plain.state()
+    # again from the same state, timed
+    plain.set_state(e, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain.step(S * calls)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    e2, p2, _ = plain.state()
+    assert np.array_equal(e2, ep) and np.array_equal(p2, pp)
+    plain.close()
+    h = lib.Hos(d, e, p)
+    desc = lib.fno_desc(N, 64, 8, 32, 31, 128, max_batch=1)
+    net = lib.Fno(desc, lib.fno_init(desc, 3))
+    sd = lib.surrogate_desc(stride_s=S, sigma_eta=HS / 4, sigma_phi=HS / 4, rho=1.0, tol=1e-3, audit_every=4,
+                            cooldown=4, probation=2)
+    sur = lib.Surrogate(h, net, sd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = sur.advance(calls)
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    print(f"plain {S * calls} steps {t_plain * 1e3:.1f} ms; surrogate-advanced {calls} calls {t_sur * 1e3:.1f} ms; {st}")
+    assert st["surrogate_calls"] == 1 and st["audits"] == 1 and st["fallbacks"] == 1 and st["hos_calls"] == 2
+    assert st["max_audit_err"] > 1e-3
+    es, ps, ts = h.state()
+    assert np.array_equal(es, ep) and np.array_equal(ps, pp) and ts == tp
+    sur.close()
+    net.close()
+    h.close()
