@@ -270,8 +270,10 @@ namespace {
 // largest layer would leave the deeper layers with errors of that size.
 // Accepted when, with the coefficients rounded to FP32, every layer's
 // weighted error is within 10 tol and the weighted sum of |coefficient| x
-// |pick factor| (the growth of the picks' own FP32 rounding) within 10;
-// failing layers join the picks, at most four more.  Returns false if no
+// |pick factor| within 30: a worst case over wavenumbers of the growth of
+// the picks' own FP32 rounding, whose errors are independent, so that the
+// typical growth is several times smaller.  Failing layers join the picks,
+// at most four more.  Returns false if no
 // worthwhile reduction exists.
 bool build_skeleton(const std::vector<double>& z, double kmax, double depth, double tol, std::vector<int>& sel,
                     std::vector<float>& tc, std::vector<float>& ts) {
@@ -396,7 +398,7 @@ bool build_skeleton(const std::vector<double>& z, double kmax, double depth, dou
         e = std::max(e, std::fabs(v - f[i]) * w[i]);
         g = std::max(g, a * w[i]);
       }
-      const double b = std::max(e / (10 * tol), g / 10.0);
+      const double b = std::max(e / (10 * tol), g / 30.0);
       if (b > bad) { bad = b; worst = l; }
     }
     return bad;
