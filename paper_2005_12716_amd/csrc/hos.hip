@@ -614,19 +614,35 @@ __device__ __forceinline__ R w2sum_n(const R* W, int K) {
 
 template <typename R, int MAXE, int NS0, int MW>
 __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
-  static_assert(NS0 >= 256 && NS0 <= 1024 && NS0 % 256 == 0, "rounds version for compile-time rows of 256 to 1024 points");
-  constexpr int PPT = (NS0 + 255) / 256;  // points per thread
+  // Rows of 256, 512 or 1024 points: wavefront transforms of the inputs and a
+  // four-wavefront transform of the products.  Rows of 3Q points (Q = 256,
+  // 512, 1024): every transform as three Q-point ones and a radix-3 combine
+  // (the inputs' by their wavefront, the products' by the workgroup).
+  constexpr bool B3 = NS0 % 3 == 0;
+  static_assert(B3 ? (NS0 / 3 >= 256 && NS0 / 3 <= 1024 && ((NS0 / 3) & (NS0 / 3 - 1)) == 0)
+                   : (NS0 >= 256 && NS0 <= 1024 && NS0 % 256 == 0),
+                "rows of 256, 512 or 1024 points, or three times that");
+  constexpr int PPT = NS0 / 256;           // points per thread
   constexpr int KP = NS0 / 128;            // kept modes per lane (p < Px / 2)
-  constexpr int Q4 = NS0 / 4;              // sub-transform length of the output transform
+  constexpr int Q4 = B3 ? 64 : NS0 / 4;    // sub-transform length of the four-wavefront transform
+  constexpr int Q3 = B3 ? NS0 / 3 : 64;    // sub-transform length of the three-way transforms
+  // rows read a round ahead where the registers allow (not at 3Q points:
+  // the per-point products already take most of them)
+  constexpr bool PREF = !B3;
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
   constexpr int Px = NS0;
+  const C* twc = reinterpret_cast<const C*>(plan.tw);
+  // LDS slot of input element s of an input transform, and of output element
+  // x of that transform
+  auto ipos = [](int s) { if constexpr (B3) return b3_in<Q3>(s); else return sk(s); };
+  auto fpos = [](int x) { if constexpr (B3) return b3_out<Q3>(x); else return sk(x); };
   const int y = blockIdx.x;
   const int hx = G.nx / 2;
   // wave-uniform, so the input descriptors are read with scalar loads
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int wl = wbuf_len(Px);
+  const int wl = B3 ? b3_len<Q3>() : wbuf_len(Px);
   C* bufs = reinterpret_cast<C*>(smem);
   C* zbuf = bufs + (size_t)wave * wl;
   R eta[PPT], ge2[PPT], dot[PPT], gp2[PPT], etat[PPT], phit[PPT], W[PPT][MW];
@@ -650,8 +666,9 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
   // round rd + 1 are in flight during round rd's transform.  Mode p
   // (0 <= p < hx) goes to slot p and its conjugate image to slot Px - p; the
   // slots in between stay zero (padding).
-  C va[KP], vb[KP];
+  C va[PREF ? KP : 1], vb[PREF ? KP : 1];
   auto load_pair = [&](int pi) {
+    if constexpr (!PREF) return;
     const bool hasb = 2 * pi + 1 < A.nin;
     const C* ra = reinterpret_cast<const C*>(A.in[2 * pi].src) + (size_t)y * G.nxh;
     const C* rb = reinterpret_cast<const C*>(A.in[hasb ? 2 * pi + 1 : 2 * pi].src) + (size_t)y * G.nxh;
@@ -665,7 +682,7 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
       }
     }
   };
-  if (wave < npairs) load_pair(wave);
+  if (PREF && wave < npairs) load_pair(wave);
   for (int rd = 0; rd < nrounds; ++rd) {
     const int pi = 4 * rd + wave;
     if (pi < npairs) {
@@ -675,22 +692,53 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
 #pragma unroll
       for (int j = 0; j < Px / 64; ++j) {
         const int s = lane + 64 * j;
-        if (s >= hx && s <= Px - hx) zbuf[sk(s)] = mk((R)0, (R)0);
+        if (s >= hx && s <= Px - hx) zbuf[ipos(s)] = mk((R)0, (R)0);
       }
+      if constexpr (PREF) {
 #pragma unroll
-      for (int k = 0; k < KP; ++k) {
-        const int p = lane + 64 * k;
-        if (p < hx) {
-          C a = va[k], b = vb[k];
-          if (fa.dx) a = times_ikx<R>(a, p, G);
-          if (hasb && fb.dx) b = times_ikx<R>(b, p, G);
-          zbuf[sk(p)] = mk(a.x - b.y, a.y + b.x);                 // a + i b
-          if (p > 0) zbuf[sk(Px - p)] = mk(a.x + b.y, b.x - a.y);  // conj(a) + i conj(b)
+        for (int k = 0; k < KP; ++k) {
+          const int p = lane + 64 * k;
+          if (p < hx) {
+            C a = va[k], b = vb[k];
+            if (fa.dx) a = times_ikx<R>(a, p, G);
+            if (hasb && fb.dx) b = times_ikx<R>(b, p, G);
+            zbuf[ipos(p)] = mk(a.x - b.y, a.y + b.x);                 // a + i b
+            if (p > 0) zbuf[ipos(Px - p)] = mk(a.x + b.y, b.x - a.y);  // conj(a) + i conj(b)
+          }
+        }
+        if (pi + 4 < npairs) load_pair(pi + 4);
+      } else {
+        // read straight into LDS, four modes per lane at a time
+        const C* ra = reinterpret_cast<const C*>(fa.src) + (size_t)y * G.nxh;
+        const C* rb = reinterpret_cast<const C*>(fb.src) + (size_t)y * G.nxh;
+#pragma unroll
+        for (int k0 = 0; k0 < KP; k0 += 4) {
+          C a4[4], b4[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int p = lane + 64 * (k0 + k);
+            a4[k] = b4[k] = mk((R)0, (R)0);
+            if (p < hx) {
+              a4[k] = ra[p];
+              if (hasb) b4[k] = rb[p];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int p = lane + 64 * (k0 + k);
+            if (p < hx) {
+              C a = a4[k], b = b4[k];
+              if (fa.dx) a = times_ikx<R>(a, p, G);
+              if (hasb && fb.dx) b = times_ikx<R>(b, p, G);
+              zbuf[ipos(p)] = mk(a.x - b.y, a.y + b.x);
+              if (p > 0) zbuf[ipos(Px - p)] = mk(a.x + b.y, b.x - a.y);
+            }
+          }
         }
       }
-      if (pi + 4 < npairs) load_pair(pi + 4);
       wave_sync();
-      wave_fft_any<R, MAXE, NS0>(zbuf, plan, +1, lane);
+      if constexpr (B3) wave_fft3<R, Q3>(zbuf, twc, +1, lane);
+      else wave_fft_any<R, MAXE, NS0>(zbuf, plan, +1, lane);
     }
     __syncthreads();
     const int i1 = min(A.nin, 8 * (rd + 1));
@@ -714,7 +762,7 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
       // the row values at this thread's points (Px = 256 PPT), all read first
       C zv[PPT];
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) zv[j] = zb[sk(threadIdx.x + 256 * j)];
+      for (int j = 0; j < PPT; ++j) zv[j] = zb[fpos(threadIdx.x + 256 * j)];
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         const C zx = zv[j];
@@ -766,18 +814,21 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
       if (M >= 2) o1 -= (R)0.5 * gp2[j];
       if (M >= 4) o1 += (R)0.5 * ge2[j] * w2sum_n<MW>(W[j], M - 2);
     }
-    zout[b4_in<Q4>(x)] = mk(o0, o1);
+    if constexpr (B3) zout[b3_in<Q3>(x)] = mk(o0, o1);
+    else zout[b4_in<Q4>(x)] = mk(o0, o1);
   }
-  // forward transform of the products by all four wavefronts
-  block4_fft<R, NS0>(zout, reinterpret_cast<const C*>(plan.tw), -1);
+  // forward transform of the products by the workgroup
+  if constexpr (B3) block3_fft<R, Q3>(zout, twc, -1);
+  else block4_fft<R, NS0>(zout, twc, -1);
+  auto opos = [](int k) { if constexpr (B3) return b3_out<Q3>(k); else return b4_out<Q4>(k); };
   const R sc = (R)(0.5 / (double)Px);
   C* d0 = reinterpret_cast<C*>(A.out0);
   C* d1 = reinterpret_cast<C*>(A.out1);
   for (int p = threadIdx.x; p < G.nxh; p += 256) {
     C o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
     if (p < hx) {
-      C zp = zout[b4_out<Q4>(p)];
-      C zm = conjg(zout[b4_out<Q4>((Px - p) % Px)]);
+      C zp = zout[opos(p)];
+      C zm = conjg(zout[opos((Px - p) % Px)]);
       C sum = zp + zm, t = zp - zm;
       o0 = cscale(sum, sc);
       o1 = mk(t.y * sc, -t.x * sc);
@@ -1069,6 +1120,21 @@ void xpass_t(swense_hos* h, const XArgs& a) {
       default: sw_launch(h, SWENSE_K_XPASS, &k_xpass_r<R, 16, 1024, 4>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, wp); break;
     }
     return;
+  }
+  // rounds version for FP32 rows of 768, 1536 and 3072 points (three-way
+  // transforms), order <= 5
+  if constexpr (sizeof(R) == 4) {
+    if (pairs_ok && a.M <= 5 && h->G.nx <= Px && (Px == 768 || Px == 1536 || Px == 3072)) {
+      const WPlan wp = make_wplan(h->plan_px);
+      const size_t wl = Px == 768 ? b3_len<256>() : (Px == 1536 ? b3_len<512>() : b3_len<1024>());
+      const size_t lds = 4ull * wl * sizeof(cpx<R>);
+      switch (Px) {
+        case 768: sw_launch(h, SWENSE_K_XPASS, &k_xpass_r<R, 16, 768, 5>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, wp); break;
+        case 1536: sw_launch(h, SWENSE_K_XPASS, &k_xpass_r<R, 32, 1536, 5>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, wp); break;
+        default: sw_launch(h, SWENSE_K_XPASS, &k_xpass_r<R, 48, 3072, 5>, dim3(h->Py), dim3(256), lds, h->st, a, h->G, wp); break;
+      }
+      return;
+    }
   }
   {
     const size_t lds = 4ull * wbuf_len(Px) * sizeof(cpx<R>) + (size_t)a.nin * Px * sizeof(R);

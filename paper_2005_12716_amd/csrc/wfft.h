@@ -165,7 +165,7 @@ __device__ void wave_fft(cpx<R>* buf, const WPlan& plan, int sign, int lane) {
 // passes with Ns = 1, 16, 256, then one radix 2/4/8/16 pass.  Every stride is
 // a constant, so the skewed LDS addresses reduce to one base register plus
 // immediate offsets.
-template <typename R, int N, int RAD, int NS>
+template <typename R, int N, int RAD, int NS, int TS = 1>
 __device__ __forceinline__ void spass(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int lane) {
   constexpr int NB = N / RAD;
   constexpr int MB = (NB + 63) / 64;
@@ -197,7 +197,7 @@ __device__ __forceinline__ void spass(cpx<R>* buf, const cpx<R>* __restrict__ tw
       if (NS > 1 && k > 0) {
 #pragma unroll
         for (int r = 1; r < RAD; ++r) {
-          cpx<R> w = tw[k * r * TWS];
+          cpx<R> w = tw[k * r * TWS * TS];
           if (sign > 0) w.y = -w.y;
           v[m][r] = cmul(v[m][r], w);
         }
@@ -219,18 +219,19 @@ __device__ __forceinline__ void spass(cpx<R>* buf, const cpx<R>* __restrict__ tw
   wave_sync();
 }
 
-template <typename R, int N>
+// TS: stride of the twiddle table (the N TS-point table of a larger transform).
+template <typename R, int N, int TS = 1>
 __device__ __forceinline__ void wave_fft_static(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int lane) {
   static_assert(N >= 64 && N <= 4096 && (N & (N - 1)) == 0, "power of two in [64, 4096]");
-  spass<R, N, 16, 1>(buf, tw, sign, lane);
-  if constexpr (N == 64) spass<R, N, 4, 16>(buf, tw, sign, lane);
-  else if constexpr (N == 128) spass<R, N, 8, 16>(buf, tw, sign, lane);
+  spass<R, N, 16, 1, TS>(buf, tw, sign, lane);
+  if constexpr (N == 64) spass<R, N, 4, 16, TS>(buf, tw, sign, lane);
+  else if constexpr (N == 128) spass<R, N, 8, 16, TS>(buf, tw, sign, lane);
   else {
-    spass<R, N, 16, 16>(buf, tw, sign, lane);
-    if constexpr (N == 512) spass<R, N, 2, 256>(buf, tw, sign, lane);
-    else if constexpr (N == 1024) spass<R, N, 4, 256>(buf, tw, sign, lane);
-    else if constexpr (N == 2048) spass<R, N, 8, 256>(buf, tw, sign, lane);
-    else if constexpr (N == 4096) spass<R, N, 16, 256>(buf, tw, sign, lane);
+    spass<R, N, 16, 16, TS>(buf, tw, sign, lane);
+    if constexpr (N == 512) spass<R, N, 2, 256, TS>(buf, tw, sign, lane);
+    else if constexpr (N == 1024) spass<R, N, 4, 256, TS>(buf, tw, sign, lane);
+    else if constexpr (N == 2048) spass<R, N, 8, 256, TS>(buf, tw, sign, lane);
+    else if constexpr (N == 4096) spass<R, N, 16, 256, TS>(buf, tw, sign, lane);
   }
 }
 
@@ -335,6 +336,69 @@ __device__ __forceinline__ void block4_fft(cpx<R>* buf, const cpx<R>* __restrict
 #pragma unroll
       for (int j = 0; j < 4; ++j) buf[j * WL + sk(kq)] = a[j];
     }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Transforms of N = 3Q points (Q a power of two, 64 <= Q <= 1024),
+// decimating in time by 3: the sequence x[3m + r] (m < Q) is transformed in
+// sub-buffer r with the compile-time radix-16 passes (every third entry of
+// the N-point table), then X[k' + Q j] = sum_r W_3^(r j) W_N^(r k') Y_r[k'] for k' < Q.
+// Input element n sits at b3_in<Q>(n), output element k at b3_out<Q>(k); the
+// three sub-buffers take b3_len<Q>() elements.  Each k' is combined in place
+// by one thread (it reads and writes the same three slots).
+template <int Q>
+__host__ __device__ constexpr int b3_len() { return 3 * (Q + Q / 16 + 1); }
+template <int Q>
+__device__ __forceinline__ int b3_in(int n) { return (n % 3) * (Q + Q / 16 + 1) + sk(n / 3); }
+template <int Q>
+__device__ __forceinline__ int b3_out(int k) { return (k / Q) * (Q + Q / 16 + 1) + sk(k % Q); }
+
+template <typename R, int Q>
+__device__ __forceinline__ void b3_combine(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int kq) {
+  constexpr int WL = Q + Q / 16 + 1;
+  cpx<R> a[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) a[r] = buf[r * WL + sk(kq)];
+#pragma unroll
+  for (int r = 1; r < 3; ++r) {
+    cpx<R> t = tw[r * kq];
+    if (sign > 0) t.y = -t.y;
+    a[r] = cmul(a[r], t);
+  }
+  dft3(a, sign);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) buf[j * WL + sk(kq)] = a[j];
+}
+
+// One wavefront: the three sub-transforms, then the combine.
+template <typename R, int Q>
+__device__ __forceinline__ void wave_fft3(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int lane) {
+  static_assert(Q >= 64 && Q <= 1024 && (Q & (Q - 1)) == 0, "N = 3Q with Q a power of two in [64, 1024]");
+  constexpr int WL = Q + Q / 16 + 1;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) wave_fft_static<R, Q, 3>(buf + r * WL, tw, sign, lane);
+#pragma unroll
+  for (int k0 = 0; k0 < Q; k0 += 64) b3_combine<R, Q>(buf, tw, sign, k0 + lane);
+  wave_sync();
+}
+
+// The workgroup (256 threads, all must call): wavefronts 0-2 take one
+// sub-transform each, every thread combines.  Starts and ends with a block
+// barrier.
+template <typename R, int Q>
+__device__ __forceinline__ void block3_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign) {
+  static_assert(Q >= 64 && Q <= 1024 && (Q & (Q - 1)) == 0, "N = 3Q with Q a power of two in [64, 1024]");
+  constexpr int WL = Q + Q / 16 + 1;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+  __syncthreads();
+  if (wave < 3) wave_fft_static<R, Q, 3>(buf + wave * WL, tw, sign, lane);
+  __syncthreads();
+#pragma unroll
+  for (int k0 = 0; k0 < Q; k0 += 256) {
+    const int kq = k0 + (int)threadIdx.x;
+    if (Q % 256 == 0 || kq < Q) b3_combine<R, Q>(buf, tw, sign, kq);
   }
   __syncthreads();
 }

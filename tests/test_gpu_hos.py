@@ -70,6 +70,24 @@ def test_rhs_parity_workgroup_y_transforms(gpu_lib, dim, nx, ny, depth, M, deali
     test_rhs_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision)
 
 
+# Padded x lengths 768, 1536 and 3072 (three times a power of two): in FP32
+# the x pass transforms each row as three sub-transforms and a radix-3
+# combine.  (At 3072 points the FP64 x pass does not fit a workgroup's LDS.)
+X3_CASES = [
+    # dim, nx, ny, depth, M, dealias, precisions   -> padded Px
+    (3, 384, 8, -1.0, 3, 1, (1, 0)),   # 768
+    (3, 768, 8, 1.5, 3, 1, (1, 0)),    # 1536
+    (3, 512, 8, -1.0, 5, 1, (1, 0)),   # 1536, order 5
+    (3, 1024, 8, 2.0, 5, 1, (0,)),     # 3072, order 5
+]
+
+
+@pytest.mark.parametrize("dim,nx,ny,depth,M,dealias,precisions", X3_CASES)
+def test_rhs_parity_three_way_x_transforms(gpu_lib, dim, nx, ny, depth, M, dealias, precisions):
+    for precision in precisions:
+        test_rhs_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision)
+
+
 @pytest.mark.parametrize("precision", [1, 0])
 @pytest.mark.parametrize("dim,nx,ny,depth,M,dealias", CASES[:4])
 def test_steps_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision):
