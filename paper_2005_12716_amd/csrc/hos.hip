@@ -360,13 +360,36 @@ __global__ void __launch_bounds__(256) k_yfwd_w(YFwdArgs A, Geom G, WPlan plan) 
 // [256, 4096]: one kx column per 256-thread workgroup (columns ordered XCD by
 // XCD), the column's transform done by all four wavefronts (block4_fft), and
 // the loads and epilogue spread over the 256 threads.
+// Lengths 768, 1536 and 3072 (three times a power of two) take the same
+// kernels with the three-way workgroup transform (block3_fft).
 __host__ __device__ constexpr bool b4_len_ok(int n) { return n >= 256 && n <= 4096 && (n & (n - 1)) == 0; }
+__host__ __device__ constexpr bool b3_len_ok(int n) { return n == 768 || n == 1536 || n == 3072; }
+__host__ __device__ constexpr bool grp_len_ok(int n) { return b4_len_ok(n) || b3_len_ok(n); }
+// LDS elements of a workgroup transform of length n
+inline size_t grp_lds_len(int n) {
+  if (b3_len_ok(n)) return n == 768 ? b3_len<256>() : (n == 1536 ? b3_len<512>() : b3_len<1024>());
+  return 4ull * wbuf_len(n / 4);
+}
+
+// Slot of element n of a workgroup transform's input, of element k of its
+// output, and the transform itself.
+template <int N>
+__device__ __forceinline__ int grp_in(int n) {
+  if constexpr (N % 3 == 0) return b3_in<N / 3>(n); else return b4_in<N / 4>(n);
+}
+template <int N>
+__device__ __forceinline__ int grp_out(int k) {
+  if constexpr (N % 3 == 0) return b3_out<N / 3>(k); else return b4_out<N / 4>(k);
+}
+template <typename R, int N>
+__device__ __forceinline__ void grp_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign) {
+  if constexpr (N % 3 == 0) block3_fft<R, N / 3>(buf, tw, sign); else block4_fft<R, N>(buf, tw, sign);
+}
 
 template <typename R, int N>
 __global__ void __launch_bounds__(256) k_yinv_b4(YInvArgs args, Geom G, WPlan plan, int nrows, int row0) {
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
-  constexpr int Q = N / 4;
   constexpr int T = N / 256;  // slots per thread
   C* buf = reinterpret_cast<C*>(smem);
   const int p = xcd_tile(blockIdx.x, gridDim.x);
@@ -379,7 +402,7 @@ __global__ void __launch_bounds__(256) k_yinv_b4(YInvArgs args, Geom G, WPlan pl
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int s = tid + 256 * t;
-    if (!col || (s >= half && s <= N - half)) buf[b4_in<Q>(s)] = mk((R)0, (R)0);
+    if (!col || (s >= half && s <= N - half)) buf[grp_in<N>(s)] = mk((R)0, (R)0);
   }
   if (col) {
     cd v[T];
@@ -399,17 +422,17 @@ __global__ void __launch_bounds__(256) k_yinv_b4(YInvArgs args, Geom G, WPlan pl
         double ax = 0.0, ay = 0.0;
         ax += w.x;
         ay += w.y;
-        buf[b4_in<Q>(qs >= 0 ? qs : qs + N)] = mk((R)ax, (R)ay);
+        buf[grp_in<N>(qs >= 0 ? qs : qs + N)] = mk((R)ax, (R)ay);
       }
     }
   }
-  block4_fft<R, N>(buf, reinterpret_cast<const C*>(plan.tw), +1);
+  grp_fft<R, N>(buf, reinterpret_cast<const C*>(plan.tw), +1);
   if (p >= G.nxh) return;
   C* dst = reinterpret_cast<C*>(jb.dst);
   for (int r = tid; r < nrows; r += 256) {
     int y = row0 + r;
     if (y >= N) y -= N * (y / N);
-    dst[(size_t)r * G.nxh + p] = buf[b4_out<Q>(y)];
+    dst[(size_t)r * G.nxh + p] = buf[grp_out<N>(y)];
   }
 }
 
@@ -417,7 +440,6 @@ template <typename R, int N>
 __global__ void __launch_bounds__(256) k_yfwd_b4(YFwdArgs A, Geom G, WPlan plan) {
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
-  constexpr int Q = N / 4;
   constexpr int T = N / 256;
   constexpr int TQ = 4;  // modes per thread held at once (ny <= 1024 in one batch)
   C* buf = reinterpret_cast<C*>(smem);
@@ -438,9 +460,9 @@ __global__ void __launch_bounds__(256) k_yfwd_b4(YFwdArgs A, Geom G, WPlan plan)
       if (q < G.ny) o[k] = yfwd_epi_load(jb, A.rk, (size_t)q * G.nxh + p);
     }
 #pragma unroll
-    for (int t = 0; t < T; ++t) buf[b4_in<Q>(tid + 256 * t)] = colv[t];
+    for (int t = 0; t < T; ++t) buf[grp_in<N>(tid + 256 * t)] = colv[t];
   }
-  block4_fft<R, N>(buf, reinterpret_cast<const C*>(plan.tw), -1);
+  grp_fft<R, N>(buf, reinterpret_cast<const C*>(plan.tw), -1);
   if (!colp) return;
   const double inv = 1.0 / (double)N;
   for (int q0 = 0; q0 < G.ny; q0 += 256 * TQ) {
@@ -459,7 +481,7 @@ __global__ void __launch_bounds__(256) k_yfwd_b4(YFwdArgs A, Geom G, WPlan plan)
       cd v = mk(0.0, 0.0);
       if (2 * p != G.nx && !(G.ny > 1 && 2 * q == G.ny)) {
         const int slot = ((qs % N) + N) % N;
-        const C r = buf[b4_out<Q>(slot)];
+        const C r = buf[grp_out<N>(slot)];
         v = mk((double)r.x * inv, (double)r.y * inv);
       }
       yfwd_epi_store(jb, A.rk, G, p, q, qs, v, o[k]);
@@ -473,6 +495,9 @@ __global__ void __launch_bounds__(256) k_yfwd_b4(YFwdArgs A, Geom G, WPlan plan)
     case 512: LAUNCH(512); break;   \
     case 1024: LAUNCH(1024); break; \
     case 2048: LAUNCH(2048); break; \
+    case 768: LAUNCH(768); break;   \
+    case 1536: LAUNCH(1536); break; \
+    case 3072: LAUNCH(3072); break; \
     default: LAUNCH(4096); break;   \
   }
 
@@ -1023,9 +1048,9 @@ void yinv_t(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, in
     }
     h->prof.bytes[SWENSE_K_YINV] += b;
   }
-  if (b4_len_ok(plan.n) && h->G.ny > 1 && plan.n >= h->G.ny) {
+  if (grp_len_ok(plan.n) && h->G.ny > 1 && plan.n >= h->G.ny) {
     const WPlan wp = make_wplan(plan);
-    const size_t lds = 4ull * wbuf_len(plan.n / 4) * sizeof(cpx<R>);
+    const size_t lds = grp_lds_len(plan.n) * sizeof(cpx<R>);
     dim3 grid(h->G.nxh, a.njobs);
 #define L_YB4(N) sw_launch(h, SWENSE_K_YINV, &k_yinv_b4<R, N>, grid, dim3(256), lds, st, a, h->G, wp, nrows, row0)
     SW_B4_DISPATCH(plan.n, L_YB4);
@@ -1067,9 +1092,9 @@ void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t s
     }
     h->prof.bytes[SWENSE_K_YFWD] += b;
   }
-  if (b4_len_ok(plan.n) && h->G.ny <= 1024) {
+  if (grp_len_ok(plan.n) && h->G.ny <= 1024) {
     const WPlan wp = make_wplan(plan);
-    const size_t lds = 4ull * wbuf_len(plan.n / 4) * sizeof(cpx<R>);
+    const size_t lds = grp_lds_len(plan.n) * sizeof(cpx<R>);
     dim3 grid(h->G.nxh, a.njobs);
 #define L_YFB4(N) sw_launch(h, SWENSE_K_YFWD, &k_yfwd_b4<R, N>, grid, dim3(256), lds, st, a, h->G, wp)
     SW_B4_DISPATCH(plan.n, L_YFB4);

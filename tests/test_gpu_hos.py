@@ -52,8 +52,9 @@ def test_rhs_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision):
     h.close()
 
 
-# Padded y lengths 256, 512, 1024, 2048 and 4096 (powers of two): the y
-# transforms run one kx column per workgroup on the four-wavefront FFT.
+# Padded y lengths 256 ... 4096 (powers of two) and 768, 1536, 3072: the y
+# transforms run one kx column per workgroup, on the four-wavefront FFT or
+# on three sub-transforms and a radix-3 combine.
 WG_CASES = [
     # dim, nx, ny, depth, M, dealias   -> padded Py
     (3, 64, 128, -1.0, 3, 1),  # 256
@@ -61,6 +62,11 @@ WG_CASES = [
     (3, 16, 512, -1.0, 3, 1),  # 1024
     (3, 8, 1024, -1.0, 3, 1),  # 2048
     (3, 8, 2048, 1.5, 3, 1),   # 4096
+    # three times a power of two: the three-way workgroup transform
+    (3, 8, 384, -1.0, 3, 1),   # 768
+    (3, 8, 768, 2.0, 3, 1),    # 1536
+    (3, 8, 512, -1.0, 5, 1),   # 1536, order 5
+    (3, 8, 1024, -1.0, 5, 1),  # 3072, order 5
 ]
 
 
