@@ -175,6 +175,17 @@ int swense_eval_grid(swense_hos* h, const swense_grid_desc* gd, unsigned mask, f
 /* Number of floats swense_eval_grid writes for (gd, mask). */
 size_t swense_eval_grid_size(const swense_hos* h, const swense_grid_desc* gd, unsigned mask);
 
+/* ---- direct analytical evaluation (Sec. 3.1.1, 3.2.1) ------------------- */
+
+/* The fields of `mask` at n arbitrary points by the modal sums themselves
+ * (every mode at every point, FP64 throughout; cost modes x points - an
+ * exact reference for the grid and interpolation path, or for small point
+ * sets).  xyz: device FP64 [3][n] (x row, y row, z row); any z, including
+ * above the mean level (the continued fields).  out: device FP64 [F][n] in
+ * point order, fields in bit order.  Uses the mean-level modes of the
+ * current state (computed if stale).  Asynchronous on the handle's stream. */
+int swense_eval_points_direct(swense_hos* h, long long n, const double* xyz, unsigned mask, double* out);
+
 /* ---- interpolation to cell centres (Sec. 3.2.2) ------------------------ */
 
 /* Bind a static point cloud to a grid: xyz is device FP64 [3][n] (x row, y

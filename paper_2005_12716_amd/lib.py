@@ -94,6 +94,7 @@ def load():
         "swense_eval_grid_size": (C.c_size_t, [vp, C.POINTER(GridDesc), C.c_uint]),
         "swense_cells_bind": (C.c_int, [vp, C.POINTER(GridDesc), C.c_longlong, vp, C.POINTER(vp)]),
         "swense_interp_cells": (C.c_int, [vp, vp, C.c_uint, fp, C.POINTER(C.c_longlong)]),
+        "swense_eval_points_direct": (C.c_int, [vp, C.c_longlong, vp, C.c_uint, vp]),
         "swense_interp_divergence": (C.c_int, [vp, vp, fp]),
         "swense_interp_step": (C.c_int, [vp, vp, C.c_uint, fp, C.c_int]),
         "swense_fv_divergence": (C.c_int, [vp, C.POINTER(GridDesc), vp, C.c_int, vp, C.c_int, vp, C.c_int, fp,
@@ -138,7 +139,7 @@ def load():
 EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swense_hos_init",
             "swense_hos_set_state", "swense_hos_step", "swense_hos_step_exp", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
-            "swense_cells_bind", "swense_interp_cells", "swense_interp_divergence", "swense_interp_step", "swense_fv_divergence", "swense_profile_enable",
+            "swense_cells_bind", "swense_interp_cells", "swense_eval_points_direct", "swense_interp_divergence", "swense_interp_step", "swense_fv_divergence", "swense_profile_enable",
             "swense_profile_read", "swense_profile_bytes", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
             "swense_batch_last_error", "swense_batch_destroy", "swense_hos_destroy",
             "swense_cells_destroy", "swense_fno_param_count", "swense_fno_create", "swense_fno_forward",
@@ -279,6 +280,19 @@ class Hos:
             out = torch.empty(n, dtype=torch.float32, device="cuda")
         assert out.is_cuda and out.dtype == torch.float32 and out.numel() >= n
         self._check(self.L.swense_eval_grid(self.h, C.byref(gd), mask, _ptr(out)), "eval_grid")
+        return out
+
+    def eval_points_direct(self, xyz: torch.Tensor, mask, out=None):
+        """Fields of `mask` at device FP64 points [3][n] by the modal sums
+        themselves (FP64 [F][n], fields in bit order)."""
+        assert xyz.is_cuda and xyz.dtype == torch.float64 and xyz.dim() == 2 and xyz.shape[0] == 3
+        xyz = xyz.contiguous()
+        n = xyz.shape[1]
+        nf = bin(mask).count("1")
+        if out is None:
+            out = torch.empty((nf, n), dtype=torch.float64, device="cuda")
+        assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and tuple(out.shape) == (nf, n)
+        self._check(self.L.swense_eval_points_direct(self.h, n, _ptr(xyz), mask, _ptr(out)), "eval_points_direct")
         return out
 
     def bind(self, gd, xyz: torch.Tensor):
