@@ -474,6 +474,18 @@ def main():
         "roofline": roof,
         "kernels": breakdown,
     }
+    # direct analytical evaluation (the exact FP64 modal sums, every mode at
+    # every point) at the first 65536 cell centres, at the same state
+    sub = cells._xyz[:, :65536].contiguous()
+    h.eval_points_direct(sub, lib.ALL_FIELDS)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.eval_points_direct(sub, lib.ALL_FIELDS)
+    torch.cuda.synchronize()
+    ms_direct = (time.perf_counter() - t0) * 1e3
+    nmodes = NY * (NX // 2 + 1)
+    res["direct_eval"] = {"points": int(sub.shape[1]), "modes": nmodes, "fields": NFIELDS, "dtype": "f64",
+                          "ms": ms_direct, "point_modes_per_s": sub.shape[1] * nmodes / (ms_direct / 1e3)}
     cells.close()
     h.close()
     res["fv_divergence_paper_demo"] = run_fv_divergence(lib, torch)

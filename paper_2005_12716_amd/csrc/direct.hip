@@ -13,8 +13,12 @@
 // and no vertical factor; p = -rho (phi_t + |u|^2/2 + g z) at the point.
 //
 // One thread per point; the modes pass through LDS in chunks, each thread
-// accumulating its point's sums in registers (FP64 phase, sin/cos and
-// exponential per mode and point: bound by the FP64 vector units).
+// accumulating its point's sums in registers.  Along a row of modes (fixed
+// q, p = 0, 1, ...) the phase e^{i(kx x + ky y)} advances by e^{i dkx x}, one
+// complex product; sin/cos are evaluated afresh at each row start and
+// chunk start (the rounding drift over a row of at most nx/2 products stays
+// near 1e-13).  The vertical factor takes one exponential per mode and
+// point: bound by the FP64 vector units.
 #include <cmath>
 #include <cstring>
 
@@ -35,6 +39,8 @@ struct DirectArgs {
   int slot[kNumFields];  // output row of each field, -1: not requested
 };
 
+// FINITE: finite depth (the vertical factors take the seabed image term).
+template <bool FINITE>
 __global__ void __launch_bounds__(kDirectBlock) k_direct_points(DirectArgs D, Geom G, const double* __restrict__ xyz,
                                                                  long long n, double* __restrict__ out) {
   __shared__ double s_kx[kDirectChunk], s_ky[kDirectChunk], s_k[kDirectChunk];
@@ -43,7 +49,9 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_points(DirectArgs D, Ge
   const long long i = (long long)blockIdx.x * kDirectBlock + threadIdx.x;
   const bool live = i < n;
   const double x = live ? xyz[i] : 0.0, y = live ? xyz[n + i] : 0.0, z = live ? xyz[2 * n + i] : 0.0;
-  const bool finite = G.depth > 0.0;
+  double c1, s1;  // e^{i dkx x}
+  sincos(2.0 * M_PI * x / G.lx, &s1, &c1);
+  double cs = 1.0, sn = 0.0;  // e^{i theta} of the current mode
   double phi = 0.0, u = 0.0, v = 0.0, w = 0.0, phit = 0.0, ut = 0.0, vt = 0.0, wt = 0.0, eta = 0.0, etat = 0.0;
   const long long nmodes = (long long)G.ny * G.nxh;
   for (long long m0 = 0; m0 < nmodes; m0 += kDirectChunk) {
@@ -57,7 +65,7 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_points(DirectArgs D, Ge
         kx = 2.0 * M_PI * (double)p / G.lx;
         ky = G.ny > 1 ? 2.0 * M_PI * (double)signed_q(q, G.ny) / G.ly : 0.0;
         k = sqrt(kx * kx + ky * ky);
-        if (finite) {
+        if (FINITE) {
           e2h = exp(-2.0 * k * G.depth);
           dinv = 1.0 / (1.0 + e2h);
         }
@@ -81,8 +89,15 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_points(DirectArgs D, Ge
     const int cnt = (int)min((long long)kDirectChunk, nmodes - m0);
     for (int j = 0; j < cnt; ++j) {
       const double kx = s_kx[j], ky = s_ky[j];
-      double sn, cs;
-      sincos(kx * x + ky * y, &sn, &cs);
+      if (j == 0 || kx == 0.0) {
+        // chunk start or row start (p = 0): the phase afresh
+        sincos(kx * x + ky * y, &sn, &cs);
+      } else {
+        // mode (q, p) follows (q, p - 1) in the chunk
+        const double c2 = cs * c1 - sn * s1;
+        sn = sn * c1 + cs * s1;
+        cs = c2;
+      }
       if (D.need_e) {
         const cd e = s_e[j];
         eta += e.x * cs - e.y * sn;
@@ -95,7 +110,7 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_points(DirectArgs D, Ge
         const double k = s_k[j];
         const double ez = exp(k * z);
         double C = ez, S = ez;
-        if (finite) {
+        if constexpr (FINITE) {
           const double b = s_e2h[j] / ez;  // e^{-k(z + 2h)}
           C = (ez + b) * s_dinv[j];
           S = (ez - b) * s_dinv[j];
@@ -154,8 +169,12 @@ int swense_eval_points_direct(swense_hos* h, long long n, const double* xyz, uns
     D.et = h->kk[0];
     const long long nblk = (n + kDirectBlock - 1) / kDirectBlock;
     SW_REQUIRE(nblk <= 0x7fffffffll, "too many points for one launch");
-    SW_LAUNCH(h, SWENSE_K_AUX, k_direct_points, dim3((unsigned)nblk), dim3(kDirectBlock), 0, h->st, D, h->G, xyz,
-              n, out);
+    if (h->G.depth > 0.0)
+      SW_LAUNCH(h, SWENSE_K_AUX, k_direct_points<true>, dim3((unsigned)nblk), dim3(kDirectBlock), 0, h->st, D, h->G,
+                xyz, n, out);
+    else
+      SW_LAUNCH(h, SWENSE_K_AUX, k_direct_points<false>, dim3((unsigned)nblk), dim3(kDirectBlock), 0, h->st, D, h->G,
+                xyz, n, out);
     SW_HIP(hipGetLastError());
     return (int)SWENSE_OK;
   });
