@@ -863,6 +863,110 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
   }
 }
 
+// Series stages of the x pass (the products -sum_j eta^j / j! g_j of one
+// order) on rows of 3Q points: each input pair is transformed by the whole
+// workgroup (the three sub-transforms on wavefronts 0-2, the radix-3
+// combine on every thread) in a single LDS buffer, so that a launch with one
+// to three pairs keeps the wavefronts busy and several workgroups share a
+// CU; per point only eta and the running sum are held.  The inputs are
+// folded in index order with the same arithmetic as the rounds kernel.
+template <typename R, int Q>
+__global__ void __launch_bounds__(256) k_xpass_series3(XArgs A, Geom G, WPlan plan) {
+  constexpr int Px = 3 * Q;
+  constexpr int PPT = Px / 256;              // points per thread
+  constexpr int KP = (Px / 2 + 255) / 256;   // kept modes per thread (p < Px / 2)
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  C* buf = reinterpret_cast<C*>(smem);
+  const C* tw = reinterpret_cast<const C*>(plan.tw);
+  const int y = blockIdx.x;
+  const int hx = G.nx / 2;
+  const int tid = threadIdx.x;
+  __shared__ int s_code[kMaxXIn];
+  if (tid < A.nin) {
+    const XIn& f = A.in[tid];
+    s_code[tid] = f.role | (f.pw << 8);
+  }
+  R eta[PPT], w0[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) eta[j] = w0[j] = (R)0;
+  const int npairs = (A.nin + 1) / 2;
+  for (int pi = 0; pi < npairs; ++pi) {
+    const bool hasb = 2 * pi + 1 < A.nin;
+    const XIn& fa = A.in[2 * pi];
+    const XIn& fb = A.in[hasb ? 2 * pi + 1 : 2 * pi];
+    const C* ra = reinterpret_cast<const C*>(fa.src) + (size_t)y * G.nxh;
+    const C* rb = reinterpret_cast<const C*>(fb.src) + (size_t)y * G.nxh;
+    const int dxa = fa.dx, dxb = hasb ? fb.dx : 0;
+    C va[KP], vb[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int p = tid + 256 * k;
+      va[k] = vb[k] = mk((R)0, (R)0);
+      if (p < hx) {
+        va[k] = ra[p];
+        if (hasb) vb[k] = rb[p];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < PPT; ++t) {
+      const int s = tid + 256 * t;
+      if (s >= hx && s <= Px - hx) buf[b3_in<Q>(s)] = mk((R)0, (R)0);
+    }
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int p = tid + 256 * k;
+      if (p < hx) {
+        C a = va[k], b = vb[k];
+        if (dxa) a = times_ikx<R>(a, p, G);
+        if (dxb) b = times_ikx<R>(b, p, G);
+        buf[b3_in<Q>(p)] = mk(a.x - b.y, a.y + b.x);                 // a + i b
+        if (p > 0) buf[b3_in<Q>(Px - p)] = mk(a.x + b.y, b.x - a.y);  // conj(a) + i conj(b)
+      }
+    }
+    block3_fft<R, Q>(buf, tw, +1);
+    const int i1 = min(A.nin, 2 * pi + 2);
+    for (int i = 2 * pi; i < i1; ++i) {
+      const int code = s_code[i];
+      const int role = code & 255, pw = (code >> 8) & 255;
+      const bool hi = i & 1;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const C zx = buf[b3_out<Q>(tid + 256 * j)];
+        const R v = hi ? zx.y : zx.x;
+        if (role == XR_ETA) {
+          eta[j] = v;
+        } else if (role == XR_G) {
+          R c = (R)1;
+#pragma unroll
+          for (int k = 1; k <= kMaxM; ++k)
+            if (k <= pw) c *= eta[j] / (R)k;
+          w0[j] += c * v;
+        }
+      }
+    }
+    __syncthreads();  // the buffer is refilled by the next pair
+  }
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) buf[b3_in<Q>(tid + 256 * j)] = mk(-w0[j], (R)0);
+  block3_fft<R, Q>(buf, tw, -1);
+  const R sc = (R)(0.5 / (double)Px);
+  C* d0 = reinterpret_cast<C*>(A.out0);
+  C* d1 = reinterpret_cast<C*>(A.out1);
+  for (int p = tid; p < G.nxh; p += 256) {
+    C o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
+    if (p < hx) {
+      C zp = buf[b3_out<Q>(p)];
+      C zm = conjg(buf[b3_out<Q>((Px - p) % Px)]);
+      C sum = zp + zm, t = zp - zm;
+      o0 = cscale(sum, sc);
+      o1 = mk(t.y * sc, -t.x * sc);
+    }
+    d0[(size_t)y * G.nxh + p] = o0;
+    if (d1) d1[(size_t)y * G.nxh + p] = o1;
+  }
+}
+
 // Physical rows <-> spectra on the mode grid (FP64, state in/out only).
 __global__ void __launch_bounds__(256) k_phys_out(const cd* e_rows, const cd* p_rows, double* out_e, double* out_p,
                                                   Geom G, FftPlan plan) {
@@ -1146,9 +1250,21 @@ void xpass_t(swense_hos* h, const XArgs& a) {
     }
     return;
   }
-  // rounds version for FP32 rows of 768, 1536 and 3072 points (three-way
-  // transforms), order <= 5
+  // FP32 rows of 768, 1536 and 3072 points (three-way transforms): series
+  // stages on the workgroup-transform kernel, the others in rounds (order <= 5)
   if constexpr (sizeof(R) == 4) {
+    bool series_ok = a.stage == XS_SERIES && h->G.nx <= Px && (Px == 768 || Px == 1536 || Px == 3072);
+    for (int i = 0; i < a.nin && series_ok; ++i)
+      series_ok = a.in[i].role == XR_ETA || (a.in[i].role == XR_G && a.in[i].wi == 0 && a.in[i].pw <= kMaxM);
+    if (series_ok) {
+      const WPlan wp = make_wplan(h->plan_px);
+      switch (Px) {
+        case 768: sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, 256>, dim3(h->Py), dim3(256), b3_len<256>() * sizeof(cpx<R>), h->st, a, h->G, wp); break;
+        case 1536: sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, 512>, dim3(h->Py), dim3(256), b3_len<512>() * sizeof(cpx<R>), h->st, a, h->G, wp); break;
+        default: sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, 1024>, dim3(h->Py), dim3(256), b3_len<1024>() * sizeof(cpx<R>), h->st, a, h->G, wp); break;
+      }
+      return;
+    }
     if (pairs_ok && a.M <= 5 && h->G.nx <= Px && (Px == 768 || Px == 1536 || Px == 3072)) {
       const WPlan wp = make_wplan(h->plan_px);
       const size_t wl = Px == 768 ? b3_len<256>() : (Px == 1536 ? b3_len<512>() : b3_len<1024>());
