@@ -967,6 +967,133 @@ __global__ void __launch_bounds__(256) k_xpass_series3(XArgs A, Geom G, WPlan pl
   }
 }
 
+// Final stage of the x pass on rows of 3Q points, in the same form: each
+// input pair transformed by the workgroup, the order-M products (eta,
+// |grad eta|^2, grad eta . grad phi, |grad phi|^2 and W_1 .. W_M, M <= MW)
+// held per point; same fold and output arithmetic as the rounds kernel.
+template <typename R, int Q, int MW>
+__global__ void __launch_bounds__(256, 2) k_xpass_final3(XArgs A, Geom G, WPlan plan) {
+  constexpr int Px = 3 * Q;
+  constexpr int PPT = Px / 256;
+  constexpr int KP = (Px / 2 + 255) / 256;
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  C* buf = reinterpret_cast<C*>(smem);
+  const C* tw = reinterpret_cast<const C*>(plan.tw);
+  const int y = blockIdx.x;
+  const int hx = G.nx / 2;
+  const int tid = threadIdx.x;
+  __shared__ int s_code[kMaxXIn];
+  if (tid < A.nin) {
+    const XIn& f = A.in[tid];
+    s_code[tid] = f.role | (f.pw << 8) | (f.wi << 16);
+  }
+  R eta[PPT], ge2[PPT], dot[PPT], gp2[PPT], W[PPT][MW];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    eta[j] = ge2[j] = dot[j] = gp2[j] = (R)0;
+#pragma unroll
+    for (int m = 0; m < MW; ++m) W[j][m] = (R)0;
+  }
+  const int npairs = (A.nin + 1) / 2;
+  for (int pi = 0; pi < npairs; ++pi) {
+    const bool hasb = 2 * pi + 1 < A.nin;
+    const XIn& fa = A.in[2 * pi];
+    const XIn& fb = A.in[hasb ? 2 * pi + 1 : 2 * pi];
+    const C* ra = reinterpret_cast<const C*>(fa.src) + (size_t)y * G.nxh;
+    const C* rb = reinterpret_cast<const C*>(fb.src) + (size_t)y * G.nxh;
+    const int dxa = fa.dx, dxb = hasb ? fb.dx : 0;
+    C va[KP], vb[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int p = tid + 256 * k;
+      va[k] = vb[k] = mk((R)0, (R)0);
+      if (p < hx) {
+        va[k] = ra[p];
+        if (hasb) vb[k] = rb[p];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < PPT; ++t) {
+      const int s = tid + 256 * t;
+      if (s >= hx && s <= Px - hx) buf[b3_in<Q>(s)] = mk((R)0, (R)0);
+    }
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int p = tid + 256 * k;
+      if (p < hx) {
+        C a = va[k], b = vb[k];
+        if (dxa) a = times_ikx<R>(a, p, G);
+        if (dxb) b = times_ikx<R>(b, p, G);
+        buf[b3_in<Q>(p)] = mk(a.x - b.y, a.y + b.x);
+        if (p > 0) buf[b3_in<Q>(Px - p)] = mk(a.x + b.y, b.x - a.y);
+      }
+    }
+    block3_fft<R, Q>(buf, tw, +1);
+    const int i1 = min(A.nin, 2 * pi + 2);
+    for (int i = 2 * pi; i < i1; ++i) {
+      const int code = s_code[i];
+      const int role = code & 255, pw = (code >> 8) & 255, wi = code >> 16;
+      const bool hi = i & 1;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const C zx = buf[b3_out<Q>(tid + 256 * j)];
+        const R v = hi ? zx.y : zx.x;
+        if (role == XR_ETA) {
+          eta[j] = v;
+        } else if (role == XR_GRADPAIR) {
+          const R b = zx.y;
+          ge2[j] += v * v;
+          dot[j] += v * b;
+          gp2[j] += b * b;
+        } else if (role == XR_G) {
+          R c = (R)1;
+#pragma unroll
+          for (int k = 1; k <= MW; ++k)
+            if (k <= pw) c *= eta[j] / (R)k;
+#pragma unroll
+          for (int m = 0; m < MW; ++m)
+            if (m == wi) W[j][m] += c * v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int M = A.M;
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    R wm = (R)0, wm2 = (R)0;
+#pragma unroll
+    for (int m = 0; m < MW; ++m) {
+      if (m < M) wm += W[j][m];
+      if (m < M - 2) wm2 += W[j][m];
+    }
+    R o0 = wm - W[j][0];
+    if (M >= 3) o0 += ge2[j] * wm2;
+    if (M >= 2) o0 -= dot[j];
+    R o1 = (R)0.5 * w2sum_n<MW>(W[j], M);
+    if (M >= 2) o1 -= (R)0.5 * gp2[j];
+    if (M >= 4) o1 += (R)0.5 * ge2[j] * w2sum_n<MW>(W[j], M - 2);
+    buf[b3_in<Q>(tid + 256 * j)] = mk(o0, o1);
+  }
+  block3_fft<R, Q>(buf, tw, -1);
+  const R sc = (R)(0.5 / (double)Px);
+  C* d0 = reinterpret_cast<C*>(A.out0);
+  C* d1 = reinterpret_cast<C*>(A.out1);
+  for (int p = tid; p < G.nxh; p += 256) {
+    C o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
+    if (p < hx) {
+      C zp = buf[b3_out<Q>(p)];
+      C zm = conjg(buf[b3_out<Q>((Px - p) % Px)]);
+      C sum = zp + zm, t = zp - zm;
+      o0 = cscale(sum, sc);
+      o1 = mk(t.y * sc, -t.x * sc);
+    }
+    d0[(size_t)y * G.nxh + p] = o0;
+    if (d1) d1[(size_t)y * G.nxh + p] = o1;
+  }
+}
+
 // Physical rows <-> spectra on the mode grid (FP64, state in/out only).
 __global__ void __launch_bounds__(256) k_phys_out(const cd* e_rows, const cd* p_rows, double* out_e, double* out_p,
                                                   Geom G, FftPlan plan) {
@@ -1256,6 +1383,13 @@ void xpass_t(swense_hos* h, const XArgs& a) {
     bool series_ok = a.stage == XS_SERIES && h->G.nx <= Px && (Px == 768 || Px == 1536 || Px == 3072);
     for (int i = 0; i < a.nin && series_ok; ++i)
       series_ok = a.in[i].role == XR_ETA || (a.in[i].role == XR_G && a.in[i].wi == 0 && a.in[i].pw <= kMaxM);
+    bool final_ok = a.stage == XS_FINAL && pairs_ok && a.M <= 5 && h->G.nx <= Px && Px == 3072;
+    if (final_ok) {
+      const WPlan wp = make_wplan(h->plan_px);
+      sw_launch(h, SWENSE_K_XPASS, &k_xpass_final3<R, 1024, 5>, dim3(h->Py), dim3(256),
+                b3_len<1024>() * sizeof(cpx<R>), h->st, a, h->G, wp);
+      return;
+    }
     if (series_ok) {
       const WPlan wp = make_wplan(h->plan_px);
       switch (Px) {
