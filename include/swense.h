@@ -222,6 +222,32 @@ int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div);
 int swense_fv_divergence(swense_hos* h, const swense_grid_desc* gd, const double* xe, int nx, const double* ye,
                          int ny, const double* ze, int nz, float* div, double* rms, double* maxabs);
 
+/* ---- cell-side use of the incident fields (Sec. 2.1.3, 3.2.2, 4.2) ------ */
+
+/* Incident volume fraction of n cells (Sec. 3.2.2, the VOF field rebuilt
+ * from eta_I): the share of each cell's height [zc - dz/2, zc + dz/2] below
+ * the elevation eta at its centre, clamped to [0, 1] (a flat interface
+ * across the cell).  eta, dz, alpha: device FP32 [n]; zc: device FP64 [n]
+ * (e.g. the z row of the bound coordinates).  Asynchronous. */
+int swense_cells_alpha(swense_hos* h, long long n, const float* eta, const double* zc, const float* dz,
+                       float* alpha);
+
+/* Modified incident pressure (Sec. 2.1.3, Eq. pIStar): pstar = rho p / rho_I
+ * with the mixture density rho = alpha rho_I + (1 - alpha) rho_air and rho_I
+ * the handle's water density.  p, alpha, pstar: device FP32 [n] (pstar may
+ * alias p).  Asynchronous. */
+int swense_cells_pstar(swense_hos* h, long long n, const float* p, const float* alpha, double rho_air, float* pstar);
+
+/* Relaxation zones (Sec. 4.2, Eq. weightFunction, swUcRelax, swVOFRelax), in
+ * place: with omega = -2 x^3 + 3 x^2 of the zone coordinate x (clamped to
+ * [0, 1]; 0 at the inner boundary, 1 at the outer one), alpha <- omega
+ * alpha_i + (1 - omega) alpha and each of the ncomp (<= 3) complementary
+ * velocity rows uc[c][n] <- (1 - omega) uc.  Cells with omega = 0 are left
+ * untouched.  alpha may be NULL (velocity only); uc may be NULL with
+ * ncomp = 0.  All device FP32.  Asynchronous. */
+int swense_cells_relax(swense_hos* h, long long n, int ncomp, const float* x, const float* alpha_i, float* alpha,
+                       float* uc);
+
 /* One CFD coupling step in one call (Sec. 4.3: the incident fields at the
  * current time are mapped to the cells, then the wave model advances): the
  * fields of the current state, as swense_interp_cells would produce them, go

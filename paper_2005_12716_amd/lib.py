@@ -95,6 +95,9 @@ def load():
         "swense_cells_bind": (C.c_int, [vp, C.POINTER(GridDesc), C.c_longlong, vp, C.POINTER(vp)]),
         "swense_interp_cells": (C.c_int, [vp, vp, C.c_uint, fp, C.POINTER(C.c_longlong)]),
         "swense_eval_points_direct": (C.c_int, [vp, C.c_longlong, vp, C.c_uint, vp]),
+        "swense_cells_alpha": (C.c_int, [vp, C.c_longlong, vp, vp, vp, vp]),
+        "swense_cells_pstar": (C.c_int, [vp, C.c_longlong, vp, vp, C.c_double, vp]),
+        "swense_cells_relax": (C.c_int, [vp, C.c_longlong, C.c_int, vp, vp, vp, vp]),
         "swense_interp_divergence": (C.c_int, [vp, vp, fp]),
         "swense_interp_step": (C.c_int, [vp, vp, C.c_uint, fp, C.c_int]),
         "swense_fv_divergence": (C.c_int, [vp, C.POINTER(GridDesc), vp, C.c_int, vp, C.c_int, vp, C.c_int, fp,
@@ -139,7 +142,8 @@ def load():
 EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swense_hos_init",
             "swense_hos_set_state", "swense_hos_step", "swense_hos_step_exp", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
-            "swense_cells_bind", "swense_interp_cells", "swense_eval_points_direct", "swense_interp_divergence", "swense_interp_step", "swense_fv_divergence", "swense_profile_enable",
+            "swense_cells_bind", "swense_interp_cells", "swense_eval_points_direct", "swense_cells_alpha", "swense_cells_pstar", "swense_cells_relax",
+            "swense_interp_divergence", "swense_interp_step", "swense_fv_divergence", "swense_profile_enable",
             "swense_profile_read", "swense_profile_bytes", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
             "swense_batch_last_error", "swense_batch_destroy", "swense_hos_destroy",
             "swense_cells_destroy", "swense_fno_param_count", "swense_fno_create", "swense_fno_forward",
@@ -294,6 +298,36 @@ class Hos:
         assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and tuple(out.shape) == (nf, n)
         self._check(self.L.swense_eval_points_direct(self.h, n, _ptr(xyz), mask, _ptr(out)), "eval_points_direct")
         return out
+
+    def cells_alpha(self, eta: torch.Tensor, zc: torch.Tensor, dz: torch.Tensor, out=None):
+        """Incident volume fraction of cells (FP32 eta, dz; FP64 zc; all [n])."""
+        n = eta.numel()
+        for t, dt in ((eta, torch.float32), (zc, torch.float64), (dz, torch.float32)):
+            assert t.is_cuda and t.dtype == dt and t.is_contiguous() and t.numel() == n
+        out = torch.empty(n, dtype=torch.float32, device="cuda") if out is None else out
+        self._check(self.L.swense_cells_alpha(self.h, n, _ptr(eta), _ptr(zc), _ptr(dz), _ptr(out)), "cells_alpha")
+        return out
+
+    def cells_pstar(self, p: torch.Tensor, alpha: torch.Tensor, rho_air: float, out=None):
+        """Modified incident pressure rho p / rho_water (FP32 [n])."""
+        n = p.numel()
+        for t in (p, alpha):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == n
+        out = torch.empty(n, dtype=torch.float32, device="cuda") if out is None else out
+        self._check(self.L.swense_cells_pstar(self.h, n, _ptr(p), _ptr(alpha), float(rho_air), _ptr(out)),
+                    "cells_pstar")
+        return out
+
+    def cells_relax(self, x: torch.Tensor, alpha_i=None, alpha=None, uc=None):
+        """Relaxation-zone blending in place (FP32): alpha [n] towards alpha_i,
+        uc [ncomp][n] towards zero."""
+        n = x.numel()
+        ncomp = 0 if uc is None else uc.shape[0]
+        for t in (x, alpha_i, alpha, uc):
+            if t is not None:
+                assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.shape[-1] == n
+        self._check(self.L.swense_cells_relax(self.h, n, ncomp, _ptr(x), _ptr(alpha_i), _ptr(alpha), _ptr(uc)),
+                    "cells_relax")
 
     def bind(self, gd, xyz: torch.Tensor):
         return Cells(self, gd, xyz)
