@@ -486,6 +486,41 @@ def main():
     nmodes = NY * (NX // 2 + 1)
     res["direct_eval"] = {"points": int(sub.shape[1]), "modes": nmodes, "fields": NFIELDS, "dtype": "f64",
                           "ms": ms_direct, "point_modes_per_s": sub.shape[1] * nmodes / (ms_direct / 1e3)}
+    # cell-side passes on every cell: incident volume fraction from the
+    # interpolated eta (cell heights of the mesh's z-levels), modified
+    # pressure, relaxation of alpha and three velocity rows (every cell in
+    # the zone); bytes = inputs read + outputs written
+    import numpy as np
+    import synth
+    ncell = cells.n
+    fl = cells.interp(lib.P | lib.ETA)[0]
+    p_c, eta_c = fl[0].contiguous(), fl[1].contiguous()  # bit order: P before ETA
+    dzc = np.diff(synth.cylinder_z_edges(HS, LAM)).astype(np.float32)
+    dz_c = torch.tensor(np.tile(dzc, ncell // dzc.size), device="cuda")
+    zc = cells._xyz[2].contiguous()
+    xr = torch.linspace(0.0, 1.0, ncell, dtype=torch.float32, device="cuda")
+    alpha = torch.empty(ncell, dtype=torch.float32, device="cuda")
+    ps = torch.empty_like(alpha)
+    ucv = torch.randn(3, ncell, dtype=torch.float32, device="cuda")
+    acfd = torch.rand(ncell, dtype=torch.float32, device="cuda")
+
+    def timed(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    cs = {}
+    for name, fn, nb in [("alpha", lambda: h.cells_alpha(eta_c, zc, dz_c, out=alpha), 20),
+                         ("pstar", lambda: h.cells_pstar(p_c, alpha, 1.2, out=ps), 12),
+                         ("relax", lambda: h.cells_relax(xr, alpha, acfd, ucv), 40)]:
+        ms = timed(fn)
+        cs[name] = {"ms": ms, "bytes_per_cell": nb, "GB_per_s": nb * ncell / (ms / 1e3) / 1e9,
+                    "frac_of_hbm_peak": nb * ncell / (ms / 1e3) / PEAK_HBM}
+    res["cell_side"] = {"cells": ncell, **cs}
     cells.close()
     h.close()
     res["fv_divergence_paper_demo"] = run_fv_divergence(lib, torch)
