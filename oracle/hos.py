@@ -228,3 +228,19 @@ def state_from_phys(grid: Grid, eta: np.ndarray, phis: np.ndarray):
 def state_to_phys(grid: Grid, eta_hat, phis_hat):
     shape = (grid.nx, grid.ny)
     return grid.to_phys(eta_hat, shape), grid.to_phys(phis_hat, shape)
+
+
+def hermite_in_time(y0, dy0, y1, dy1, t0: float, t1: float, t: float):
+    """Values between two outputs of the wave model (the CFD step is several
+    times shorter than the HOS step: Sec. 4.3 and the validation cases).
+    Reading (the paper is silent): cubic Hermite interpolation in time of a
+    modal amplitude from its values and time derivatives at t0 and t1 -
+    (A, A_t) and (eta_hat, eta_t_hat) - and the derivative of that cubic as
+    the time derivative at t.  Returns (y(t), y'(t))."""
+    dt = t1 - t0
+    s = (t - t0) / dt
+    h00, h10, h01, h11 = 2 * s**3 - 3 * s**2 + 1, s**3 - 2 * s**2 + s, -2 * s**3 + 3 * s**2, s**3 - s**2
+    d00, d10, d01, d11 = 6 * s**2 - 6 * s, 3 * s**2 - 4 * s + 1, -6 * s**2 + 6 * s, 3 * s**2 - 2 * s
+    y = h00 * y0 + h10 * dt * dy0 + h01 * y1 + h11 * dt * dy1
+    dy = (d00 * y0 + d10 * dt * dy0 + d01 * y1 + d11 * dt * dy1) / dt
+    return y, dy
