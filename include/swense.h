@@ -165,6 +165,25 @@ int swense_hos_modes(swense_hos* h, double* a_hat, double* a_t_hat, double* eta_
 /* Energy 1/2 int phis eta_t dA + 1/2 g int eta^2 dA.  Synchronises. */
 int swense_hos_energy(swense_hos* h, double* energy);
 
+/* ---- evaluation between two outputs of the wave model ------------------- */
+
+/* Record A, A_t, eta and eta_t of the current state and its time as the start
+ * of an interval (e.g. before advancing the wave model by one step).
+ * Asynchronous. */
+int swense_hos_snapshot(swense_hos* h);
+
+/* Evaluate at time t instead of the current time: swense_eval_grid,
+ * swense_interp_cells, swense_interp_divergence, swense_fv_divergence and
+ * swense_eval_points_direct then read spectra interpolated to t by cubic
+ * Hermite interpolation in time of (A, A_t) and (eta, eta_t) between the
+ * snapshot and the current state (the CFD step is shorter than the wave
+ * model's, Sec. 4.3; the paper does not say how the fields are taken in
+ * between).  t must lie in [snapshot time, current time]; t equal to the
+ * current time (or any change of the state, or swense_interp_step) returns
+ * to the current state.  SWENSE_EINVAL without an earlier snapshot.
+ * Asynchronous. */
+int swense_hos_set_eval_time(swense_hos* h, double t);
+
 /* ---- evaluation on the intermediate grid (Sec. 3.2.2, 3.2.4, 3.3) ------ */
 
 /* Fields of `mask` at the window nodes of every layer.  out: device FP32,

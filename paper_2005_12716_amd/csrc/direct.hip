@@ -163,10 +163,7 @@ int swense_eval_points_direct(swense_hos* h, long long n, const double* xyz, uns
     D.need_at = p || (mask & (SWENSE_PHI_T | SWENSE_U_T | SWENSE_V_T | SWENSE_W_T)) ? 1 : 0;
     D.need_e = (mask & SWENSE_ETA) ? 1 : 0;
     D.need_et = (mask & SWENSE_ETA_T) ? 1 : 0;
-    D.a = h->amod;
-    D.at = h->atmod;
-    D.e = h->xn[0];
-    D.et = h->kk[0];
+    eval_sources(h, &D.a, &D.at, &D.e, &D.et);
     const long long nblk = (n + kDirectBlock - 1) / kDirectBlock;
     SW_REQUIRE(nblk <= 0x7fffffffll, "too many points for one launch");
     if (h->G.depth > 0.0)

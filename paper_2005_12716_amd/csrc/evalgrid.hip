@@ -557,7 +557,9 @@ EvalWork* work(swense_hos* h) {
 void vol_source(swense_hos* h, int f, EvField& e) {
   const bool t = f >= F_PHIT;
   const int base = t ? f - F_PHIT : f;  // PHI U V W
-  e.src = t ? h->atmod : h->amod;
+  const cd *a, *at, *eta, *etat;
+  eval_sources(h, &a, &at, &eta, &etat);
+  e.src = t ? at : a;
   e.vf = base == 3 ? 1 : 0;
   e.mult = base == 0 ? 0 : (base == 1 ? 1 : (base == 2 ? 2 : 3));
 }
@@ -604,7 +606,9 @@ void plan_fields(swense_hos* h, unsigned mask, bool pre, EvArgs& A, int* out_of_
   for (int f : {F_ETA, F_ETAT}) {
     if (srf_slot_of[f] < 0) continue;
     EvField& e = A.f[nv + ns];
-    e.src = f == F_ETA ? (h->eta_src ? h->eta_src : h->xn[0]) : h->kk[0];
+    const cd *a, *at, *eta, *etat;
+    eval_sources(h, &a, &at, &eta, &etat);
+    e.src = f == F_ETA ? eta : etat;
     e.vf = 2;
     e.mult = 0;
     e.out_slot = srf_slot_of[f];

@@ -2043,6 +2043,8 @@ void swense_hos_destroy(swense_hos* h) {
   h->prof.release();
   eval_release(h);
   if (h->eta_snap) (void)hipFree(h->eta_snap);
+  if (h->snapm) (void)hipFree(h->snapm);
+  if (h->herm) (void)hipFree(h->herm);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->aux) (void)hipStreamDestroy(h->aux);

@@ -142,6 +142,16 @@ struct swense_hos {
   // an auxiliary stream and two events
   cd* eta_snap = nullptr;
   const cd* eta_src = nullptr;  // evaluation source of eta (null: the state)
+  // evaluation at a time between a snapshot and the current state
+  // (swense_hos_snapshot, swense_hos_set_eval_time): the snapshot's A, A_t,
+  // eta, eta_t, the interpolated ones, and the state version they were
+  // formed for (a later state change drops them)
+  cd* snapm = nullptr;   // [4][nc]
+  cd* herm = nullptr;    // [4][nc]
+  double snap_t = 0.0;
+  bool snap_ok = false;
+  bool herm_on = false;
+  long herm_version = -1;
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
@@ -213,6 +223,16 @@ void sw_launch(swense_hos* h, int kid, void (*kernel)(KArgs...), dim3 grid, dim3
 // ---- launch helpers implemented in hos.hip (templated on precision there)
 void launch_yinv(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, int row0, hipStream_t st);
 void launch_modes(swense_hos* h);  // A, A_t, eta_t at the current state (if stale)
+
+// Spectra the evaluation reads: A, A_t, eta, eta_t of the current state, or
+// the ones interpolated to the evaluation time set for this state.
+inline void eval_sources(const swense_hos* h, const cd** a, const cd** at, const cd** eta, const cd** etat) {
+  const bool tset = h->herm_on && h->herm_version == h->version;
+  *a = tset ? h->herm : h->amod;
+  *at = tset ? h->herm + h->nc : h->atmod;
+  *eta = tset ? h->herm + 2 * h->nc : (h->eta_src ? h->eta_src : h->xn[0]);
+  *etat = tset ? h->herm + 3 * h->nc : h->kk[0];
+}
 void set_error(swense_hos* h, const SwenseError& e);
 // Physical fields at h->phys ([ny][nx] FP64, eta then phis) -> half spectra
 // (e, p); add = true adds them into (e, p) instead of overwriting.

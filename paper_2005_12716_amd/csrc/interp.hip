@@ -776,7 +776,9 @@ int swense_interp_step(swense_hos* h, swense_cells* c, unsigned mask, float* out
     }
     if (!h->eta_snap) SW_HIP(hipMalloc(&h->eta_snap, h->nc * sizeof(cd)));
     // modes (and right-hand side) of the current state, and a copy of eta that
-    // the evaluation reads while the step rewrites the state
+    // the evaluation reads while the step rewrites the state (a set
+    // evaluation time does not apply: this call maps the current state)
+    h->herm_on = false;
     launch_modes(h);
     SW_HIP(hipMemcpyAsync(h->eta_snap, h->xn[0], h->nc * sizeof(cd), hipMemcpyDeviceToDevice, h->st));
     SW_HIP(hipEventRecord(h->ev_fork, h->st));

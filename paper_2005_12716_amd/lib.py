@@ -95,6 +95,8 @@ def load():
         "swense_cells_bind": (C.c_int, [vp, C.POINTER(GridDesc), C.c_longlong, vp, C.POINTER(vp)]),
         "swense_interp_cells": (C.c_int, [vp, vp, C.c_uint, fp, C.POINTER(C.c_longlong)]),
         "swense_eval_points_direct": (C.c_int, [vp, C.c_longlong, vp, C.c_uint, vp]),
+        "swense_hos_snapshot": (C.c_int, [vp]),
+        "swense_hos_set_eval_time": (C.c_int, [vp, C.c_double]),
         "swense_cells_alpha": (C.c_int, [vp, C.c_longlong, vp, vp, vp, vp]),
         "swense_cells_pstar": (C.c_int, [vp, C.c_longlong, vp, vp, C.c_double, vp]),
         "swense_cells_relax": (C.c_int, [vp, C.c_longlong, C.c_int, vp, vp, vp, vp]),
@@ -142,7 +144,7 @@ def load():
 EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swense_hos_init",
             "swense_hos_set_state", "swense_hos_step", "swense_hos_step_exp", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
-            "swense_cells_bind", "swense_interp_cells", "swense_eval_points_direct", "swense_cells_alpha", "swense_cells_pstar", "swense_cells_relax",
+            "swense_cells_bind", "swense_interp_cells", "swense_eval_points_direct", "swense_hos_snapshot", "swense_hos_set_eval_time", "swense_cells_alpha", "swense_cells_pstar", "swense_cells_relax",
             "swense_interp_divergence", "swense_interp_step", "swense_fv_divergence", "swense_profile_enable",
             "swense_profile_read", "swense_profile_bytes", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
             "swense_batch_last_error", "swense_batch_destroy", "swense_hos_destroy",
@@ -285,6 +287,14 @@ class Hos:
         assert out.is_cuda and out.dtype == torch.float32 and out.numel() >= n
         self._check(self.L.swense_eval_grid(self.h, C.byref(gd), mask, _ptr(out)), "eval_grid")
         return out
+
+    def snapshot(self):
+        """Record the current spectra and time as the start of an interval."""
+        self._check(self.L.swense_hos_snapshot(self.h), "snapshot")
+
+    def set_eval_time(self, t):
+        """Evaluate at time t in [snapshot time, current time] (Hermite in time)."""
+        self._check(self.L.swense_hos_set_eval_time(self.h, float(t)), "set_eval_time")
 
     def eval_points_direct(self, xyz: torch.Tensor, mask, out=None):
         """Fields of `mask` at device FP64 points [3][n] by the modal sums

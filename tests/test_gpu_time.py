@@ -1,0 +1,97 @@
+"""GPU evaluation between two outputs of the wave model (cubic Hermite in
+time of the mean-level spectra, the reading the oracle pins) against the
+oracle, on an FP64 state: the direct modal sums at points (1e-11) and the
+intermediate grid (FP32 outputs, 2e-6) at an interior time, the two ends,
+the error outside the interval, and the return to the current state after a
+step."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import Grid, hos
+from oracle import reconstruct as rc
+
+pytestmark = pytest.mark.gpu
+LAM = 2 * math.pi
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("depth", [-1.0, 1.3])
+def test_eval_between_outputs(gpu_lib, depth):
+    from paper_2005_12716_amd import lib
+    nx, ny = 32, 16
+    lx, ly = nx * LAM / 6.4, ny * LAM / 6.4
+    dt = LAM / 64
+    d = lib.hos_desc(3, nx, ny, lx, ly, depth, order_m=3, dt=dt, precision=1)
+    eh, ph = lib.sea_spectrum(d, kind=0, hs=0.03 * LAM, kp=1.0, gamma=3.3, phases=synth.mode_phases(17, ny, nx // 2 + 1))
+    g = Grid(nx=nx, ny=ny, lx=lx, ly=ly, depth=depth, order_m=3)
+    h = lib.Hos(d, eh, ph)
+    h.step(2)
+    h.snapshot()
+    h.step(3)
+    t0, t1 = 2 * dt, 5 * dt
+    e0, p0 = hos.run(g, eh, ph, dt, 2)
+    e1, p1 = hos.run(g, e0, p0, dt, 3)
+    A0, A1 = hos.mean_level_modes(g, e0, p0), hos.mean_level_modes(g, e1, p1)
+    (At0, et0), (At1, et1) = hos.mean_level_modes_t(g, e0, p0), hos.mean_level_modes_t(g, e1, p1)
+    pts = synth.box_cloud(8, 400, 0.0, 0.0, lx, ly, -1.0 if depth < 0 else -depth, 0.2)
+    xyz = torch.tensor(pts, device="cuda")
+    now = h.eval_points_direct(xyz, lib.ALL_FIELDS).cpu().numpy()
+    for s in (0.4, 0.0, 1.0):
+        t = t0 + s * (t1 - t0)
+        h.set_eval_time(t)
+        A, At = hos.hermite_in_time(A0, At0, A1, At1, t0, t1, t)
+        E, Et = hos.hermite_in_time(e0, et0, e1, et1, t0, t1, t)
+        got = h.eval_points_direct(xyz, lib.ALL_FIELDS).cpu().numpy()
+        ref = rc.analytic_at_points(g, A, At, E, Et, pts, list(range(11)))
+        for f in range(11):
+            assert rel(got[f], ref[f]) < 1e-10, (s, f, rel(got[f], ref[f]))
+        if s == 1.0:
+            assert np.array_equal(got, now)
+    # the intermediate grid at the interior time
+    t = t0 + 0.4 * (t1 - t0)
+    h.set_eval_time(t)
+    zl = np.array([-0.9, -0.4, -0.1, 0.0, 0.15])
+    gd = lib.grid_desc(2 * nx, 2 * ny, zl)
+    out = h.eval_grid(gd, lib.U | lib.W | lib.ETA | lib.PHI_T).cpu().numpy()
+    A, At = hos.hermite_in_time(A0, At0, A1, At1, t0, t1, t)
+    E, Et = hos.hermite_in_time(e0, et0, e1, et1, t0, t1, t)
+    ref = rc.eval_grid(g, A, At, E, Et, 2 * nx, 2 * ny, zl, [rc.U, rc.W, rc.PHI_T, rc.ETA])
+    nl, npt = zl.size, 4 * nx * ny
+    vol = out[: 3 * nl * npt].reshape(3, nl, 2 * ny, 2 * nx)
+    for k, f in enumerate((rc.U, rc.W, rc.PHI_T)):
+        assert rel(vol[k], ref[f]) < 2e-6, f
+    assert rel(out[3 * nl * npt:].reshape(2 * ny, 2 * nx), ref[rc.ETA]) < 2e-6
+    # outside the interval
+    with pytest.raises(lib.SwenseError):
+        h.set_eval_time(t0 - dt)
+    with pytest.raises(lib.SwenseError):
+        h.set_eval_time(t1 + dt)
+    # a state change returns the evaluation to the current state
+    h.set_eval_time(t)
+    h.step(1)
+    e2, p2 = hos.run(g, e1, p1, dt, 1)
+    A2 = hos.mean_level_modes(g, e2, p2)
+    At2, et2 = hos.mean_level_modes_t(g, e2, p2)
+    got = h.eval_points_direct(xyz, lib.U | lib.ETA).cpu().numpy()
+    ref = rc.analytic_at_points(g, A2, At2, e2, et2, pts, [rc.U, rc.ETA])
+    assert rel(got[0], ref[rc.U]) < 1e-10 and rel(got[1], ref[rc.ETA]) < 1e-10
+    h.close()
+
+
+def test_set_eval_time_without_snapshot(gpu_lib):
+    from paper_2005_12716_amd import lib
+    d = lib.hos_desc(3, 16, 8, 16 * LAM / 6.4, 8 * LAM / 6.4, -1.0, order_m=3, dt=LAM / 64)
+    eh, ph = lib.sea_spectrum(d, kind=0, hs=0.02 * LAM, kp=1.0, gamma=3.3, phases=synth.mode_phases(2, 8, 9))
+    h = lib.Hos(d, eh, ph)
+    h.step(1)
+    h.set_eval_time(LAM / 64)  # the current time: allowed
+    with pytest.raises(lib.SwenseError):
+        h.set_eval_time(0.5 * LAM / 64)
+    h.close()
