@@ -165,6 +165,33 @@ int swense_hos_modes(swense_hos* h, double* a_hat, double* a_t_hat, double* eta_
 /* Energy 1/2 int phis eta_t dA + 1/2 g int eta^2 dA.  Synchronises. */
 int swense_hos_energy(swense_hos* h, double* energy);
 
+/* ---- regular waves: stream-function theory (Sec. 3.1.1, 3.2.1) --------- */
+
+typedef struct swense_stream_desc {
+  double depth;       /* d > 0 (use a large kd for deep water)                 */
+  double height;      /* crest-to-trough height H > 0                          */
+  double wavelength;  /* L = 2 pi / k                                          */
+  double g, rho;      /* gravity, water density                                */
+  int n;              /* Fourier components N, 2..64                           */
+} swense_stream_desc;
+
+/* Solve the 2D steady regular wave (Fourier approximation of the stream
+ * function in the frame moving with the wave, no mean Eulerian current) on the
+ * host.  sol (host, 2N + 4 doubles) receives eta at the N + 1 surface points
+ * X_m = m L / (2N) from crest to trough (above the mean level), B_1..B_N, the
+ * phase speed c, the volume flux Q and the Bernoulli constant R (moving frame).
+ * Returns SWENSE_EINVAL for bad sizes and SWENSE_EUNSTABLE if Newton's method
+ * does not converge (e.g. a wave beyond breaking). */
+int swense_stream_solve(const swense_stream_desc* d, double* sol);
+
+/* Fields of `mask` at n points and time t for a solved wave travelling in +x
+ * (crest at x = c t): xyz device FP64 [3][n] (y ignored); out device FP64
+ * [F][n], fields in bit order (v and v_t are zero); p = rho (R - c^2/2) -
+ * rho (phi_t + |u|^2/2 + g z), zero on the free surface.  stream: a
+ * hipStream_t (NULL: the default stream).  Asynchronous. */
+int swense_stream_eval(const swense_stream_desc* d, const double* sol, double t, long long n, const double* xyz,
+                       unsigned mask, double* out, void* stream);
+
 /* ---- evaluation between two outputs of the wave model ------------------- */
 
 /* Record A, A_t, eta and eta_t of the current state and its time as the start

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libswense.so")
-SOURCES = ["hos.hip", "evalgrid.hip", "interp.hip", "direct.hip", "cells.hip", "tinterp.hip", "batch.hip", "fno.hip", "surrogate.hip", "sea.cpp"]
+SOURCES = ["hos.hip", "evalgrid.hip", "interp.hip", "direct.hip", "cells.hip", "tinterp.hip", "stream.hip", "batch.hip", "fno.hip", "surrogate.hip", "sea.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-mcode-object-version=5", "-O3", "-std=c++17", "-fPIC",

@@ -40,6 +40,11 @@ class SeaDesc(C.Structure):
                 ("spreading", C.c_int), ("mode", C.c_int), ("ka", C.c_double)]
 
 
+class StreamDesc(C.Structure):
+    _fields_ = [("depth", C.c_double), ("height", C.c_double), ("wavelength", C.c_double), ("g", C.c_double),
+                ("rho", C.c_double), ("n", C.c_int)]
+
+
 class FnoDesc(C.Structure):
     _fields_ = [("n", C.c_int), ("channels", C.c_int), ("layers", C.c_int), ("p_modes", C.c_int),
                 ("q_modes", C.c_int), ("hidden", C.c_int), ("in_channels", C.c_int), ("max_batch", C.c_int)]
@@ -96,6 +101,8 @@ def load():
         "swense_interp_cells": (C.c_int, [vp, vp, C.c_uint, fp, C.POINTER(C.c_longlong)]),
         "swense_eval_points_direct": (C.c_int, [vp, C.c_longlong, vp, C.c_uint, vp]),
         "swense_hos_snapshot": (C.c_int, [vp]),
+        "swense_stream_solve": (C.c_int, [C.POINTER(StreamDesc), vp]),
+        "swense_stream_eval": (C.c_int, [C.POINTER(StreamDesc), vp, C.c_double, C.c_longlong, vp, C.c_uint, vp, vp]),
         "swense_hos_set_eval_time": (C.c_int, [vp, C.c_double]),
         "swense_cells_alpha": (C.c_int, [vp, C.c_longlong, vp, vp, vp, vp]),
         "swense_cells_pstar": (C.c_int, [vp, C.c_longlong, vp, vp, C.c_double, vp]),
@@ -144,7 +151,7 @@ def load():
 EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swense_hos_init",
             "swense_hos_set_state", "swense_hos_step", "swense_hos_step_exp", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
-            "swense_cells_bind", "swense_interp_cells", "swense_eval_points_direct", "swense_hos_snapshot", "swense_hos_set_eval_time", "swense_cells_alpha", "swense_cells_pstar", "swense_cells_relax",
+            "swense_cells_bind", "swense_interp_cells", "swense_eval_points_direct", "swense_hos_snapshot", "swense_hos_set_eval_time", "swense_stream_solve", "swense_stream_eval", "swense_cells_alpha", "swense_cells_pstar", "swense_cells_relax",
             "swense_interp_divergence", "swense_interp_step", "swense_fv_divergence", "swense_profile_enable",
             "swense_profile_read", "swense_profile_bytes", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
             "swense_batch_last_error", "swense_batch_destroy", "swense_hos_destroy",
@@ -173,6 +180,35 @@ def grid_desc(gx, gy, z, window=None):
     gd = GridDesc(gx, gy, ix0, iy0, wx, wy, z.size, z.ctypes.data_as(C.POINTER(C.c_double)))
     gd._z = z  # keep alive
     return gd
+
+
+def stream_solve(depth, height, wavelength, n, g=1.0, rho=1.0):
+    """Stream-function regular wave (host solve): (desc, sol[2n+4]) with sol =
+    eta at the n+1 surface points (crest to trough), B_1..B_n, c, Q, R."""
+    d = StreamDesc(depth, height, wavelength, g, rho, n)
+    sol = np.zeros(2 * n + 4)
+    rc = load().swense_stream_solve(C.byref(d), _ptr(sol))
+    if rc != OK:
+        raise SwenseError(rc, "stream_solve")
+    return d, sol
+
+
+def stream_eval(desc: StreamDesc, sol, t, xyz: torch.Tensor, mask, out=None):
+    """Fields of `mask` of a solved regular wave at device FP64 points [3][n]
+    and time t (FP64 [F][n], fields in bit order)."""
+    assert xyz.is_cuda and xyz.dtype == torch.float64 and xyz.dim() == 2 and xyz.shape[0] == 3
+    xyz = xyz.contiguous()
+    n = xyz.shape[1]
+    nf = bin(mask).count("1")
+    if out is None:
+        out = torch.empty((nf, n), dtype=torch.float64, device="cuda")
+    sol = np.ascontiguousarray(sol, dtype=np.float64)
+    st = torch.cuda.current_stream()
+    rc = load().swense_stream_eval(C.byref(desc), _ptr(sol), float(t), n, _ptr(xyz), mask, _ptr(out),
+                                   C.c_void_p(st.cuda_stream))
+    if rc != OK:
+        raise SwenseError(rc, "stream_eval")
+    return out
 
 
 def sea_spectrum(desc: HosDesc, kind=0, hs=0.0, kp=1.0, gamma=3.3, spreading=0, mode=0, ka=0.0, phases=None):

@@ -112,3 +112,24 @@ def test_invalid_descriptors_are_rejected_before_any_device_work():
     assert L.swense_surrogate_create(None, None, None, C.byref(C.c_void_p())) == lib.EINVAL
     assert L.swense_hos_step(None, 1) == lib.EINVAL
     assert L.swense_gemm_bf16(0, 4, 4, None, None, None, None) == lib.EINVAL
+
+
+@pytest.mark.parametrize("depth,height,n", [(2.0, 0.2, 16), (1.0, 0.25, 12), (10.0, 0.5, 20)])
+def test_stream_solve_matches_oracle(depth, height, n):
+    """The library's host solve of the stream-function wave (its own Newton
+    iteration) against the oracle's, same collocation system."""
+    from paper_2005_12716_amd import lib
+    from oracle import stream
+    L = 2 * math.pi
+    _, sol = lib.stream_solve(depth, height, L, n)
+    ref = stream.solve(depth, height, L, n)
+    v = np.concatenate([ref["eta"], ref["B"], [ref["c"], ref["Q"], ref["R"]]])
+    assert np.abs(sol - v).max() < 1e-11 * max(1.0, np.abs(v).max())
+
+
+def test_stream_solve_rejects_bad_input():
+    from paper_2005_12716_amd import lib
+    with pytest.raises(lib.SwenseError):
+        lib.stream_solve(-1.0, 0.1, 2 * math.pi, 8)
+    with pytest.raises(lib.SwenseError):
+        lib.stream_solve(1.0, 0.1, 2 * math.pi, 100)
