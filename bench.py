@@ -521,6 +521,12 @@ def main():
         cs[name] = {"ms": ms, "bytes_per_cell": nb, "GB_per_s": nb * ncell / (ms / 1e3) / 1e9,
                     "frac_of_hbm_peak": nb * ncell / (ms / 1e3) / PEAK_HBM}
     res["cell_side"] = {"cells": ncell, **cs}
+    # stream-function regular wave (ka = 0.24, N = 9, kh = 2) at every cell, all fields
+    sd, ssol = lib.stream_solve(2.0, 0.48, LAM, 9)
+    sout = torch.empty((NFIELDS, ncell), dtype=torch.float64, device="cuda")
+    ms_stream = timed(lambda: lib.stream_eval(sd, ssol, 0.3, cells._xyz, lib.ALL_FIELDS, out=sout), reps=5)
+    res["stream_wave_eval"] = {"points": ncell, "modes": 9, "fields": NFIELDS, "dtype": "f64", "ms": ms_stream,
+                               "cell_field_pts_per_s": ncell * NFIELDS / (ms_stream / 1e3)}
     cells.close()
     h.close()
     res["fv_divergence_paper_demo"] = run_fv_divergence(lib, torch)
