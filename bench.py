@@ -107,6 +107,22 @@ def run_batched(lib, torch, steps):
     res = {"realisations": len(hoses), "points": npts, "branches": k, "ms_per_launch": ms,
            "realisation_steps_per_s": len(hoses) * 1e3 / ms,
            "cell_field_pts_per_s": npts * nf * 1e3 / ms}
+    # compulsory HBM bytes of one launch, lower bound: the HOS intermediates
+    # (the library's count, from one eager profiled step of every realisation)
+    # plus the interpolated outputs (4 B per point and field); coefficient
+    # grids and point data not counted
+    hos_bytes = 0.0
+    for h in hoses:
+        h.profile(True)
+        h.step(1)
+        torch.cuda.synchronize()
+        pb = h.profile_bytes()
+        h.profile(False)
+        hos_bytes += sum(pb.get(kk, 0.0) for kk in ("yinv", "xpass", "yfwd"))
+    out_bytes = 4.0 * npts * nf
+    res["compulsory_bytes_lower_bound"] = {"hos": hos_bytes, "interp_outputs": out_bytes,
+                                           "GB_per_s": (hos_bytes + out_bytes) / (ms / 1e3) / 1e9,
+                                           "frac_of_hbm_peak": (hos_bytes + out_bytes) / (ms / 1e3) / PEAK_HBM}
     b.close()
     for c in cells:
         c.close()
