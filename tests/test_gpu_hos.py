@@ -88,6 +88,22 @@ X3_CASES = [
 ]
 
 
+# Padded x lengths between the powers of two (5-smooth, up to 1024: the
+# batched configuration's sizes), on the runtime-planned wavefront FFT.
+RT_CASES = [
+    # dim, nx, ny, depth, M, dealias   -> padded Px
+    (3, 300, 8, -1.0, 3, 1),   # 600
+    (3, 360, 8, 1.5, 4, 1),    # 960, order 4
+    (2, 480, 1, -1.0, 3, 1),   # 960, 2D
+]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("dim,nx,ny,depth,M,dealias", RT_CASES)
+def test_rhs_parity_runtime_rows(gpu_lib, dim, nx, ny, depth, M, dealias, precision):
+    test_rhs_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision)
+
+
 @pytest.mark.parametrize("dim,nx,ny,depth,M,dealias,precisions", X3_CASES)
 def test_rhs_parity_three_way_x_transforms(gpu_lib, dim, nx, ny, depth, M, dealias, precisions):
     for precision in precisions:
