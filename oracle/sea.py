@@ -53,12 +53,22 @@ def stokes2(grid: Grid, mode: int, ka: float, phase: float = 0.0):
 
 
 def jonswap_omega(omega: np.ndarray, omega_p: float, gamma: float, g: float) -> np.ndarray:
-    """JONSWAP frequency spectrum with unit Phillips constant."""
+    """JONSWAP frequency spectrum with unit Phillips constant: the
+    Pierson-Moskowitz shape g^2 w^-5 exp(-5/4 (w_p/w)^4), which peaks at w_p,
+    times the peak enhancement gamma^r with r = exp(-(w - w_p)^2 / (2 s^2 w_p^2))
+    and the published widths s = 0.07 below the peak and 0.09 above it."""
     sig = np.where(omega <= omega_p, 0.07, 0.09)
     with np.errstate(divide="ignore", over="ignore", invalid="ignore"):
         s = g * g * omega ** -5.0 * np.exp(-1.25 * (omega_p / omega) ** 4) \
             * gamma ** np.exp(-((omega - omega_p) ** 2) / (2 * sig * sig * omega_p * omega_p))
     return np.where(omega > 0, s, 0.0)
+
+
+def spreading_cos2(theta: np.ndarray) -> np.ndarray:
+    """Directional spreading D(theta) = (2/pi) cos^2(theta) on |theta| < pi/2,
+    zero behind; theta is measured from the +x axis (the mean direction)."""
+    theta = np.asarray(theta, dtype=np.float64)
+    return np.where(np.abs(theta) < math.pi / 2, (2 / math.pi) * np.cos(theta) ** 2, 0.0)
 
 
 def jonswap(grid: Grid, hs: float, kp: float, gamma: float, phases: np.ndarray,
@@ -82,8 +92,7 @@ def jonswap(grid: Grid, hs: float, kp: float, gamma: float, phases: np.ndarray,
         # all energy on the ky = 0 row: a = sqrt(2 S_k(kx) dkx)
         dens = np.where((KY == 0) & (KX > 0), sk / dky, 0.0)
     else:
-        theta = np.arctan2(KY, KX)
-        d = np.where(np.abs(theta) < math.pi / 2, (2 / math.pi) * np.cos(theta) ** 2, 0.0)
+        d = spreading_cos2(np.arctan2(KY, KX))
         with np.errstate(divide="ignore", invalid="ignore"):
             dens = np.where((K > 0) & (KX > 0), sk * d / K, 0.0)
     amp = np.sqrt(2 * dens * dkx * dky)
