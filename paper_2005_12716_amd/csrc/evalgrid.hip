@@ -46,6 +46,8 @@ struct EvArgs {
   float* out;
   int nvol_out;   // volume output slots (incl. pressure)
   int p_slot;     // output slot of the pressure, -1 if not requested
+  const cd* srcs[4];       // distinct spectral sources of the fields
+  int sid[kMaxEvFields];   // source of each field (index into srcs)
 };
 
 // y-inverse for evaluation: job = (field, layer) for volume fields, then
@@ -88,6 +90,94 @@ __global__ void __launch_bounds__(256) k_yinv_eval_w(EvArgs A, Geom G, WPlan pla
   const YInvJob jb = eval_job(A, G, blockIdx.y, sizeof(cpx<R>));
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem) + (size_t)wave * wbuf_len(plan.n);
   yinv_wave<R, MAXE, NS0>(jb, G, plan, A.wy, A.iy0, p, buf, lane);
+}
+
+// Workgroup version for the lengths of the workgroup transforms, zero-padding
+// in y: block = (kx column p, layer l; l = nl: the surface fields), all of the
+// layer's fields in turn, each transformed by the whole workgroup.  The
+// column's values of the (at most two) sources and, per mode, the FP64
+// vertical factors C and S at z_l and the prefilter are formed once and
+// shared by the fields; each field's symbol-weighted value is formed in FP64
+// and rounded to the transform precision.  TQ >= ny / 256 modes per thread.
+template <typename R, int N, int TQ>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 3072 || TQ >= 4 ? 2 : 4))) k_yinv_eval_g(EvArgs A, Geom G, const cpx<R>* __restrict__ tw) {
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  constexpr int T = N / 256;  // slots per thread
+  C* buf = reinterpret_cast<C*>(smem);
+  const int p = xcd_tile(blockIdx.x, gridDim.x);
+  const int l = A.nvol > 0 ? (int)blockIdx.y : A.nl;
+  const bool surf = l == A.nl;
+  const int f0 = surf ? A.nvol : 0, f1 = surf ? A.nvol + A.nsurf : A.nvol;
+  const int tid = threadIdx.x, half = G.ny / 2;
+  const bool col = p < G.nxh && 2 * p != G.nx;
+  const int s0 = A.sid[f0];
+  int s1 = s0;
+  for (int f = f0; f < f1; ++f)
+    if (A.sid[f] != s0) s1 = A.sid[f];
+  cd v0[TQ], v1[TQ];
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) {
+    const int q = tid + 256 * t;
+    const int qs = q >= half ? q - G.ny : q;
+    const bool ok = col && q < G.ny && qs > -half;
+    v0[t] = ok ? A.srcs[s0][(size_t)q * G.nxh + p] : mk(0.0, 0.0);
+    v1[t] = ok ? A.srcs[s1][(size_t)q * G.nxh + p] : mk(0.0, 0.0);
+  }
+  const double kx = 2.0 * M_PI * (double)p / G.lx;
+  const double bx = A.pre ? (4.0 + 2.0 * cos(2.0 * M_PI * (double)p / (double)A.gx)) / 6.0 : 1.0;
+  const double z = surf ? 0.0 : A.z[l];
+  const double kys = 2.0 * M_PI / G.ly;
+  double fc[TQ], fsn[TQ];  // vertical factors times the prefilter
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) {
+    const int q = tid + 256 * t;
+    const int qs = q >= half ? q - G.ny : q;
+    const double ky = kys * (double)qs;
+    double c = 1.0, sn = 1.0;
+    if (!surf) vfactors(sqrt(kx * kx + ky * ky), z, G.depth, c, sn);
+    const double by = A.pre ? (4.0 + 2.0 * cos(2.0 * M_PI * (double)qs / (double)A.gy)) / 6.0 : 1.0;
+    const double pre = 1.0 / (bx * by);
+    fc[t] = c * pre;
+    fsn[t] = sn * pre;
+  }
+  for (int f = f0; f < f1; ++f) {
+    const EvField F = A.f[f];
+    const bool first = A.sid[f] == s0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int s = tid + 256 * t;
+      if (!col || (s >= half && s <= N - half)) buf[grp_in<N>(s)] = mk((R)0, (R)0);
+    }
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) {
+      const int q = tid + 256 * t;
+      const int qs = q >= half ? q - G.ny : q;
+      if (col && q < G.ny && qs > -half) {
+        // surface fields: no vertical factor (fc = fsn = prefilter there)
+        const double fac = F.vf == 1 ? fsn[t] : fc[t];
+        const double ky = kys * (double)qs;
+        cd m;
+        switch (F.mult) {
+          case 0: m = mk(fac, 0.0); break;
+          case 1: m = mk(0.0, kx * fac); break;
+          case 2: m = mk(0.0, ky * fac); break;
+          default: m = mk(sqrt(kx * kx + ky * ky) * fac, 0.0); break;
+        }
+        const cd w = cmul(first ? v0[t] : v1[t], m);
+        buf[grp_in<N>(qs >= 0 ? qs : qs + N)] = mk((R)w.x, (R)w.y);
+      }
+    }
+    grp_fft<R, N>(buf, tw, +1);
+    const int job = surf ? A.nvol * A.nl + (f - A.nvol) : f * A.nl + l;
+    C* dst = reinterpret_cast<C*>(A.inter) + (size_t)job * A.wy * G.nxh;
+    for (int r = tid; r < A.wy; r += 256) {
+      int y = A.iy0 + r;
+      if (y >= N) y -= N * (y / N);
+      dst[(size_t)r * G.nxh + p] = buf[grp_out<N>(y)];
+    }
+    __syncthreads();
+  }
 }
 
 // Complex length-gx sequence whose inverse transform is a + i b at the nodes,
@@ -183,7 +273,7 @@ __global__ void __launch_bounds__(256) k_xeval_surf(EvArgs A, Geom G, FftPlan pl
 }
 
 // x pass for interpolation coefficient grids, node-major layout: every
-// node's (field, layer) values are contiguous, coef[(r wx + xw) K + f L + l],
+// node's (layer, field) values are contiguous, coef[(r wx + xw) K + l Fv + f],
 // surface fields at offset L Fv + s.  Block (window row r, layer
 // group g); the last group index holds the surface fields.
 template <typename R>
@@ -227,8 +317,7 @@ __global__ void __launch_bounds__(256) k_xcoef(EvArgs A, Geom G, FftPlan plan, i
   }
   for (int e = threadIdx.x; e < A.wx * nitems; e += blockDim.x) {
     const int xw = e / nitems, j = e - xw * nitems;
-    const int off = surf ? base_off + j : (j % Fv) * A.nl + l0 + j / Fv;
-    coef[((size_t)r * A.wx + xw) * K + off] = stage[e];
+    coef[((size_t)r * A.wx + xw) * K + base_off + j] = stage[e];
   }
 }
 
@@ -282,8 +371,54 @@ __global__ void __launch_bounds__(256) k_xcoef_w(EvArgs A, Geom G, WPlan plan, i
   __syncthreads();
   for (int e = threadIdx.x; e < A.wx * nitems; e += blockDim.x) {
     const int xw = e / nitems, j = e - xw * nitems;
-    const int off = surf ? base_off + j : (j % Fv) * A.nl + l0 + j / Fv;
-    coef[((size_t)r * A.wx + xw) * K + off] = stage[e];
+    coef[((size_t)r * A.wx + xw) * K + base_off + j] = stage[e];
+  }
+}
+
+// Coefficient x pass in plane layout for the lengths of the workgroup
+// transforms: coef[c][wy][wx] with c = l Fv + f for volume field f of layer l
+// and c = L Fv + s for surface field s (the coefficient index of the
+// node-major layout).  Block = (window row r, group of ppb job pairs); each
+// pair of rows is transformed by the whole workgroup as one complex sequence
+// and its window columns are written as two contiguous rows.
+template <typename R, int N>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 3072 ? 3 : 4))) k_xplane_g(EvArgs A, Geom G, const cpx<R>* __restrict__ tw, int njobs, int ppb,
+                                                  float* __restrict__ coef) {
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  constexpr int T = N / 256;
+  C* buf = reinterpret_cast<C*>(smem);
+  const int r = blockIdx.x, hx = G.nx / 2, tid = threadIdx.x;
+  const size_t plane = (size_t)A.wx * A.wy;
+  const C* inter = reinterpret_cast<const C*>(A.inter);
+  const int npair = (njobs + 1) / 2;
+  const int pe = min(npair, (int)(blockIdx.y + 1) * ppb);
+  auto cidx = [&](int job) {
+    if (job >= A.nvol * A.nl) return job;  // surface: L Fv + s
+    const int f = job / A.nl, l = job - f * A.nl;
+    return l * A.nvol + f;
+  };
+  for (int pi = blockIdx.y * ppb; pi < pe; ++pi) {
+    const int ja = 2 * pi;
+    const bool hasb = ja + 1 < njobs;
+    const C* ra = inter + ((size_t)ja * A.wy + r) * G.nxh;
+    const C* rb = hasb ? ra + (size_t)A.wy * G.nxh : nullptr;
+#pragma unroll 4
+    for (int t = 0; t < T; ++t) {
+      const int s = tid + 256 * t;
+      buf[grp_in<N>(s)] = gather_x<R>(ra, rb, s, N, hx);
+    }
+    grp_fft<R, N>(buf, tw, +1);
+    float* oa = coef + (size_t)cidx(ja) * plane + (size_t)r * A.wx;
+    float* ob = hasb ? coef + (size_t)cidx(ja + 1) * plane + (size_t)r * A.wx : nullptr;
+    for (int xw = tid; xw < A.wx; xw += 256) {
+      int x = A.ix0 + xw;
+      if (x >= N) x -= N;
+      const C zx = buf[grp_out<N>(x)];
+      oa[xw] = (float)zx.x;
+      if (hasb) ob[xw] = (float)zx.y;
+    }
+    __syncthreads();
   }
 }
 
@@ -339,7 +474,7 @@ __global__ void __launch_bounds__(256) k_xcoef_skel(EvArgs A, Geom G, WPlan plan
     const int xw = e / L, l = e - xw * L;
     float acc = 0.f;
     for (int j = 0; j < skl.R; ++j) acc += T[l * skl.R + j] * stage[j * A.wx + xw];
-    coef[((size_t)r * A.wx + xw) * K + (size_t)f * L + l] = acc;
+    coef[((size_t)r * A.wx + xw) * K + (size_t)l * Fv + f] = acc;
   }
 }
 
@@ -489,7 +624,7 @@ __global__ void __launch_bounds__(256) k_xcoef_dft(EvArgs A, Geom G, const float
     if (kidx >= K) break;
     float* dst = coef + ((size_t)r * A.wx + x0) * K + kidx;
     if (kidx < nvk) {
-      const int f = kidx / L, l = kidx - f * L;
+      const int l = kidx / Fv, f = kidx - l * Fv;
       const float* T = Ts + (A.f[f].vf == 1 ? L * R : 0) + l;
       const float* srow = S + (f * R) * DX_SS;
       for (int n4 = 0; n4 < nodes; n4 += 4) {
@@ -620,11 +755,24 @@ void plan_fields(swense_hos* h, unsigned mask, bool pre, EvArgs& A, int* out_of_
 
 template <typename R>
 void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned mask, bool pre, float* out,
-            const Skel* skel) {
+            const Skel* skel, int* plane_out) {
   launch_modes(h);
   EvArgs A;
   int nvo = 0, nso = 0;
   plan_fields(h, mask, pre, A, nullptr, &nvo, &nso);
+  if (plane_out) *plane_out = 0;
+  {
+    int ns = 0;
+    for (int f = 0; f < A.nvol + A.nsurf; ++f) {
+      int k = 0;
+      while (k < ns && A.srcs[k] != A.f[f].src) ++k;
+      if (k == ns) {
+        SW_REQUIRE(ns < 4, "too many spectral sources");
+        A.srcs[ns++] = A.f[f].src;
+      }
+      A.sid[f] = k;
+    }
+  }
   const bool use_skel = pre && skel && skel->R > 0;
   A.z = use_skel ? skel->zeta : zdev;
   A.nl = use_skel ? skel->R : gd->nl;
@@ -661,7 +809,25 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
   FftPlan px = tc.get(A.gx, sizeof(R) == 8);
   // y pass
   SW_REQUIRE(njobs <= 65535, "too many (field, layer) pairs");
-  if (py.n <= (sizeof(R) == 4 ? 4096 : 2048)) {
+  const int tq = (h->G.ny + 255) / 256;
+  bool ydone = false;
+  if constexpr (sizeof(R) == 4) {
+    if (h->G.ny > 1 && grp_len_ok(py.n) && py.n >= h->G.ny && tq <= 4) {
+    // one workgroup per (column, layer): the layer's fields share the FP64 factors
+    const size_t lds = grp_lds_len(py.n) * csz;
+    dim3 grid(h->G.nxh, (A.nvol > 0 ? A.nl : 0) + (A.nsurf > 0 ? 1 : 0));
+    const cpx<R>* twy = reinterpret_cast<const cpx<R>*>(py.tw);
+#define L_YG(N)                                                                                              \
+  if (tq <= 1) sw_launch(h, SWENSE_K_YINV_EVAL, &k_yinv_eval_g<R, N, 1>, grid, dim3(256), lds, h->st, A, h->G, twy); \
+  else if (tq <= 2) sw_launch(h, SWENSE_K_YINV_EVAL, &k_yinv_eval_g<R, N, 2>, grid, dim3(256), lds, h->st, A, h->G, twy); \
+  else sw_launch(h, SWENSE_K_YINV_EVAL, &k_yinv_eval_g<R, N, 4>, grid, dim3(256), lds, h->st, A, h->G, twy);
+    SW_B4_DISPATCH(py.n, L_YG);
+#undef L_YG
+      ydone = true;
+    }
+  }
+  if (ydone) {
+  } else if (py.n <= (sizeof(R) == 4 ? 4096 : 2048)) {
     const WPlan wp = make_wplan(py);
     const size_t lds = 4ull * wbuf_len(py.n) * csz;
     dim3 grid((h->G.nxh + 3) / 4, njobs);
@@ -712,6 +878,21 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
 #undef L_XS
     return;
   }
+  if constexpr (sizeof(R) == 4) {
+  if (pre && grp_len_ok(px.n)) {
+    // plane layout: each pair of rows transformed by a whole workgroup
+    if (plane_out) *plane_out = 1;
+    constexpr int ppb = 4;
+    const int npair = (njobs + 1) / 2;
+    const size_t lds = grp_lds_len(px.n) * csz;
+    dim3 grid(A.wy, (npair + ppb - 1) / ppb);
+    const cpx<R>* twx = reinterpret_cast<const cpx<R>*>(px.tw);
+#define L_XP(N) sw_launch(h, SWENSE_K_XEVAL, &k_xplane_g<R, N>, grid, dim3(256), lds, h->st, A, h->G, twx, njobs, ppb, out)
+    SW_B4_DISPATCH(px.n, L_XP);
+#undef L_XP
+    return;
+  }
+  }
   if (pre) {
     const int Fv = A.nvol;
     const int LG = Fv > 0 ? std::max(1, 16 / Fv) : 1;
@@ -752,9 +933,9 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
 }
 
 void eval_dispatch(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned mask, bool pre,
-                   float* out, const Skel* skel = nullptr) {
-  if (h->fp64) eval_t<double>(h, gd, zdev, mask, pre, out, skel);
-  else eval_t<float>(h, gd, zdev, mask, pre, out, skel);
+                   float* out, const Skel* skel = nullptr, int* plane = nullptr) {
+  if (h->fp64) eval_t<double>(h, gd, zdev, mask, pre, out, skel, plane);
+  else eval_t<float>(h, gd, zdev, mask, pre, out, skel, plane);
 }
 
 size_t grid_floats(const swense_hos* h, const swense_grid_desc* gd, unsigned mask, bool pre) {
@@ -790,8 +971,8 @@ CoefLayout coef_layout(swense_hos* h, unsigned cm, int nl) {
 }
 
 void eval_coef(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned cm, float* coef,
-               const Skel* sk) {
-  eval_dispatch(h, gd, zdev, cm, true, coef, sk);
+               const Skel* sk, int* plane) {
+  eval_dispatch(h, gd, zdev, cm, true, coef, sk, plane);
 }
 
 size_t coef_floats(swense_hos* h, const swense_grid_desc* gd, unsigned cm) { return grid_floats(h, gd, cm, true); }

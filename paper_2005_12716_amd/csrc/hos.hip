@@ -362,30 +362,6 @@ __global__ void __launch_bounds__(256) k_yfwd_w(YFwdArgs A, Geom G, WPlan plan) 
 // the loads and epilogue spread over the 256 threads.
 // Lengths 768, 1536 and 3072 (three times a power of two) take the same
 // kernels with the three-way workgroup transform (block3_fft).
-__host__ __device__ constexpr bool b4_len_ok(int n) { return n >= 256 && n <= 4096 && (n & (n - 1)) == 0; }
-__host__ __device__ constexpr bool b3_len_ok(int n) { return n == 768 || n == 1536 || n == 3072; }
-__host__ __device__ constexpr bool grp_len_ok(int n) { return b4_len_ok(n) || b3_len_ok(n); }
-// LDS elements of a workgroup transform of length n
-inline size_t grp_lds_len(int n) {
-  if (b3_len_ok(n)) return n == 768 ? b3_len<256>() : (n == 1536 ? b3_len<512>() : b3_len<1024>());
-  return 4ull * wbuf_len(n / 4);
-}
-
-// Slot of element n of a workgroup transform's input, of element k of its
-// output, and the transform itself.
-template <int N>
-__device__ __forceinline__ int grp_in(int n) {
-  if constexpr (N % 3 == 0) return b3_in<N / 3>(n); else return b4_in<N / 4>(n);
-}
-template <int N>
-__device__ __forceinline__ int grp_out(int k) {
-  if constexpr (N % 3 == 0) return b3_out<N / 3>(k); else return b4_out<N / 4>(k);
-}
-template <typename R, int N>
-__device__ __forceinline__ void grp_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign) {
-  if constexpr (N % 3 == 0) block3_fft<R, N / 3>(buf, tw, sign); else block4_fft<R, N>(buf, tw, sign);
-}
-
 template <typename R, int N>
 __global__ void __launch_bounds__(256) k_yinv_b4(YInvArgs args, Geom G, WPlan plan, int nrows, int row0) {
   extern __shared__ unsigned char smem[];
@@ -488,18 +464,6 @@ __global__ void __launch_bounds__(256) k_yfwd_b4(YFwdArgs A, Geom G, WPlan plan)
     }
   }
 }
-
-#define SW_B4_DISPATCH(n, LAUNCH) \
-  switch (n) {                    \
-    case 256: LAUNCH(256); break;   \
-    case 512: LAUNCH(512); break;   \
-    case 1024: LAUNCH(1024); break; \
-    case 2048: LAUNCH(2048); break; \
-    case 768: LAUNCH(768); break;   \
-    case 1536: LAUNCH(1536); break; \
-    case 3072: LAUNCH(3072); break; \
-    default: LAUNCH(4096); break;   \
-  }
 
 // Fused x pass, wavefront version: block = physical row y, four wavefronts.
 // Field pairs are spread over the wavefronts (each transforms its pair in

@@ -256,8 +256,8 @@ void eval_release(swense_hos* h);
 void check_grid_desc(const swense_hos* h, const swense_grid_desc* gd);
 void ensure_device(void** p, size_t* cap, size_t bytes);
 // Node-major coefficient grid: per window node K = fv nl + fs floats, volume
-// field f at offsets f nl + l (its layers contiguous), surface field s at
-// fv nl + s; idx[bit] = field index, -1 when the field is absent (also v, v_t
+// field f of layer l at offset l fv + f (a band of layers holds every field
+// contiguously), surface field s at fv nl + s; idx[bit] = field index, -1 when the field is absent (also v, v_t
 // in 2D, which are zero).
 struct CoefLayout {
   int fv, fs, nl, k;
@@ -274,8 +274,10 @@ struct Skel {
   const float* tc;    // device [nl][R] for C-type fields (phi, u, v and their time derivatives)
   const float* ts;    // device [nl][R] for S-type fields (w, w_t)
 };
+// *plane: 0 node-major layout (above), 1 plane layout coef[c][wy][wx] with c
+// the same coefficient index (l fv + f, then fv nl + s).
 void eval_coef(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned cm, float* coef,
-               const Skel* sk);
+               const Skel* sk, int* plane);
 size_t coef_floats(swense_hos* h, const swense_grid_desc* gd, unsigned cm);
 
 // run a body and convert exceptions to error codes

@@ -13,12 +13,20 @@
 // columns are ordered by stencil node so neighbouring columns share cache
 // lines.
 //
-// Gather (every call): one 64-lane wavefront per column contracts the 16
-// horizontal taps once for every (layer, field) the column's points need -
-// the coefficient grid is node-major, so each tap is one contiguous vector
-// load across the wavefront - keeps the column profile in LDS, then each
-// point takes 4 vertical taps per field.  Pressure is formed at the point
-// from phi_t, u, v, w: p = -rho (phi_t + |u|^2/2) - rho g z.
+// Gather (every call), two forms chosen at binding:
+// * shared columns: one 64-lane wavefront per column contracts the 16
+//   horizontal taps once for every (layer, field) the column's points need -
+//   the coefficient grid is node-major, so each tap is one contiguous vector
+//   load across the wavefront - keeps the column profile in LDS, then each
+//   point takes 4 vertical taps per field;
+// * no shared columns (unstructured and jittered meshes, random clouds): the
+//   points are binned by a tile of stencil start nodes and a band of first
+//   layers; a workgroup stages its tile's coefficient block (tile + 3-node
+//   halo, band + 3 layers, every field) in LDS once, then one thread per
+//   point takes its 4 x 4 x 4 taps per field from LDS.  The tile shape is the
+//   one with the fewest staged bytes for the cloud's own point density.
+// Pressure is formed at the point from phi_t, u, v, w:
+// p = -rho (phi_t + |u|^2/2) - rho g z.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -47,8 +55,30 @@ struct PtDev {
 
 constexpr int kColsPerBlock = 4;
 
+// Work item of the tiled gather: the points [start, start + count) of the
+// sorted arrays whose stencil starts lie in the tile at (ix0, iy0) and whose
+// first layers lie in the band starting at layer lb (lb < 0: points outside
+// the grid or the layers, written as NaN); nlb layers are staged.
+struct TileItem {
+  int start, count;
+  int ix0, iy0;
+  int lb, nlb;
+};
+constexpr int kTileThreads = 256;
+constexpr int kTileMaxPts = 1024;  // points per item (larger bins are split)
+
+struct TileDev {
+  const TileItem* items;
+  const unsigned* hxy;  // per sorted point: stencil start ix | iy << 16 (window-local)
+  const float2* txy;    // per sorted point: fractional offsets
+  int nitems;
+  int sx, sy;           // staged nodes per axis (tile + 3)
+  int stride;           // LDS floats per staged node
+};
+
 struct GatherArgs {
-  const float* coef;
+  const float* coef;  // coefficient c of window node nd at nd ns + c ps
+  long long ns, ps;
   int K, fv, fs, nl;
   int wx, wy, gx, gy, three;
   int nout;
@@ -56,6 +86,9 @@ struct GatherArgs {
   int srf[11];  // output slot -> surface field index (-1: none)
   int zero[11]; // output slot is identically zero (v, v_t in 2D)
   int p_slot;
+  int vslot[8];   // volume field of the coefficient grid -> output slot (-1: none)
+  int sslot[2];   // surface field -> output slot (-1: none)
+  unsigned zmask; // output slots that are identically zero
   int c_phit, c_u, c_v, c_w;
   float rho;
   float* out;
@@ -87,7 +120,7 @@ __device__ __forceinline__ void stencil(const Col& c, const GatherArgs& A, long 
     for (int a = 0; a < 4; ++a) {
       const int yy = A.three ? wrapn(c.iy + b, A.wy, A.gy) : 0;
       const int xx = wrapn(c.ix + a, A.wx, A.gx);
-      off[b * 4 + a] = ((long long)yy * A.wx + xx) * A.K;
+      off[b * 4 + a] = ((long long)yy * A.wx + xx) * A.ns;
     }
 }
 
@@ -110,19 +143,14 @@ __global__ void __launch_bounds__(256) k_gather_col(GatherArgs A, const Col* __r
     stencil(c, A, off);
     const int nb = A.three ? 4 : 1;
     for (int j = lane; j < nv + A.fs; j += 64) {
-      // column profile h[f nlc + (l - lmin)], then the surface fields
-      int jj;
-      if (j < nv) {
-        const int f = j / c.nlc;
-        jj = f * A.nl + c.lmin + (j - f * c.nlc);
-      } else {
-        jj = A.nl * A.fv + (j - nv);
-      }
+      // column profile h[(l - lmin) fv + f] (the node record's layers lmin..
+      // contiguous), then the surface fields
+      const int jj = j < nv ? c.lmin * A.fv + j : A.nl * A.fv + (j - nv);
       // all 16 taps read before any is used (in 2D the rows b >= 1 repeat
       // row 0's nodes and are not summed)
       float tap[16];
 #pragma unroll
-      for (int t = 0; t < 16; ++t) tap[t] = A.coef[off[t] + jj];
+      for (int t = 0; t < 16; ++t) tap[t] = A.coef[off[t] + jj * A.ps];
       float acc = 0.f;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {  // unrolled so the weights stay in registers
@@ -154,8 +182,8 @@ __global__ void __launch_bounds__(256) k_gather_col(GatherArgs A, const Col* __r
     }
     const int base = l0 - c.lmin;
     auto vol = [&](int f) {
-      const float* hf = h + f * c.nlc + base;
-      return wz[0] * hf[0] + wz[1] * hf[1] + wz[2] * hf[2] + wz[3] * hf[3];
+      const float* hf = h + base * A.fv + f;
+      return wz[0] * hf[0] + wz[1] * hf[A.fv] + wz[2] * hf[2 * A.fv] + wz[3] * hf[3 * A.fv];
     };
     // unrolled over the output slots, so their field indices are read once
 #pragma unroll
@@ -173,6 +201,139 @@ __global__ void __launch_bounds__(256) k_gather_col(GatherArgs A, const Col* __r
       }
       A.out[(size_t)o * n + orig] = v;
     }
+  }
+}
+
+// Tiled gather for clouds without shared columns: one workgroup per work
+// item.  Staging: the item's nodes (tile + halo) x (the band's layers of
+// every field - one contiguous run of each node record - then the surface
+// fields), node-major in LDS with `stride` floats per node, eight global
+// loads in flight per thread.
+// Points: one thread each, 4 x 4 horizontal taps (4 x 1 in 2D) of 4 layers
+// per volume field, 16 (4) taps per surface field.
+template <int THREE>
+__global__ void __launch_bounds__(kTileThreads) k_gather_tile(GatherArgs A, TileDev T, PtDev pd) {
+  extern __shared__ float lds[];
+  const int it = xcd_tile(blockIdx.x, gridDim.x);
+  if (it >= T.nitems) return;  // uniform over the workgroup
+  const TileItem I = T.items[it];
+  const size_t n = (size_t)A.n;
+  if (I.lb < 0) {
+    for (int i = threadIdx.x; i < I.count; i += kTileThreads) {
+      const int orig = pd.perm[I.start + i];
+      for (int o = 0; o < A.nout; ++o) A.out[(size_t)o * n + orig] = __builtin_nanf("");
+    }
+    return;
+  }
+  const int tl = I.nlb;
+  const int nvr = A.fv * tl;  // the band's layers of every volume field: one run of the node record
+  const int rec = nvr + A.fs;
+  const int nodes = T.sx * T.sy;
+  int* nidx = reinterpret_cast<int*>(lds + (size_t)nodes * T.stride);  // window node of each staged node, -1: none
+  for (int nd = threadIdx.x; nd < nodes; nd += kTileThreads) {
+    const int by = THREE ? nd / T.sx : 0;
+    const int bx = nd - by * T.sx;
+    // full-period windows wrap; nodes past a partial window are never read
+    const int gxn = wrapn(I.ix0 + bx, A.wx, A.gx);
+    const int gyn = THREE ? wrapn(I.iy0 + by, A.wy, A.gy) : 0;
+    nidx[nd] = (gxn < A.wx && gyn < A.wy) ? gyn * A.wx + gxn : -1;
+  }
+  __syncthreads();
+  // element e = nd rec + r in the node-major layout (a node's record
+  // contiguous), e = r nodes + nd in the plane layout (a row of nodes
+  // contiguous); eight loads in flight per thread before their stores
+  const int total = nodes * rec;
+  const bool plane = A.ps != 1;
+  const int dv = plane ? nodes : rec;
+  const float inv_dv = 1.0f / (float)dv;
+  const int vbase = I.lb * A.fv, sbase = A.nl * A.fv - nvr;
+  for (int e0 = threadIdx.x; e0 < total; e0 += 8 * kTileThreads) {
+    float v[8];
+    int dst[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kTileThreads;
+      int hi = (int)((float)e * inv_dv);
+      int lo = e - hi * dv;
+      if (lo < 0) { --hi; lo += dv; }
+      if (lo >= dv) { ++hi; lo -= dv; }
+      const int nd = plane ? lo : hi, r = plane ? hi : lo;
+      const int ni = e < total ? nidx[nd] : -1;
+      dst[u] = ni >= 0 ? nd * T.stride + r : -1;
+      v[u] = ni >= 0 ? A.coef[(size_t)ni * A.ns + (size_t)((r < nvr ? vbase : sbase) + r) * A.ps] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (dst[u] >= 0) lds[dst[u]] = v[u];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < I.count; i += kTileThreads) {
+    const int sp = I.start + i;
+    // every per-point value is read before any is used
+    const int orig = pd.perm[sp];
+    const int l0 = pd.l0[sp];
+    const unsigned hp = T.hxy[sp];
+    const float2 t = T.txy[sp];
+    float wz[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) wz[a] = pd.wz[(size_t)a * n + sp];
+    const float pz = A.p_slot >= 0 ? pd.pz[sp] : 0.f;
+    float wx[4], wy[4] = {1.f, 0.f, 0.f, 0.f};
+    bsw(t.x, wx);
+    if (THREE) bsw(t.y, wy);
+    // the start node lies in the item's tile: local offsets in [0, tile)
+    const int lx = (int)(hp & 0xffffu) - I.ix0;
+    const int ly = THREE ? (int)(hp >> 16) - I.iy0 : 0;
+    const float* nb = lds + (ly * T.sx + lx) * T.stride;
+    const int lo = l0 - I.lb;
+    const int fv = A.fv;
+    auto vol = [&](int f) {
+      const float* q0 = nb + lo * fv + f;
+      float acc = 0.f;
+#pragma unroll
+      for (int b = 0; b < (THREE ? 4 : 1); ++b) {
+        float rb = 0.f;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const float* q = q0 + (b * T.sx + a) * T.stride;
+          rb += wx[a] * (wz[0] * q[0] + wz[1] * q[fv] + wz[2] * q[2 * fv] + wz[3] * q[3 * fv]);
+        }
+        acc += wy[b] * rb;
+      }
+      return acc;
+    };
+    auto srf = [&](int s) {
+      const float* q0 = nb + nvr + s;
+      float acc = 0.f;
+#pragma unroll
+      for (int b = 0; b < (THREE ? 4 : 1); ++b) {
+        float rb = 0.f;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) rb += wx[a] * q0[(b * T.sx + a) * T.stride];
+        acc += wy[b] * rb;
+      }
+      return acc;
+    };
+    // one field at a time (registers: one field's 64 taps in flight); the
+    // pressure's inputs are kept as they pass
+    float pt = 0.f, u = 0.f, vv = 0.f, w = 0.f;
+#pragma unroll 1
+    for (int f = 0; f < A.fv; ++f) {
+      const float v = vol(f);
+      const int o = A.vslot[f];
+      if (o >= 0) A.out[(size_t)o * n + orig] = v;
+      pt = f == A.c_phit ? v : pt;
+      u = f == A.c_u ? v : u;
+      vv = f == A.c_v ? v : vv;
+      w = f == A.c_w ? v : w;
+    }
+#pragma unroll 1
+    for (int s2 = 0; s2 < A.fs; ++s2) {
+      const int o = A.sslot[s2];
+      if (o >= 0) A.out[(size_t)o * n + orig] = srf(s2);
+    }
+    if (A.p_slot >= 0) A.out[(size_t)A.p_slot * n + orig] = -A.rho * (pt + 0.5f * (u * u + vv * vv + w * w)) - pz;
+    for (unsigned zm = A.zmask; zm; zm &= zm - 1) A.out[(size_t)__builtin_ctz(zm) * n + orig] = 0.f;
   }
 }
 
@@ -207,10 +368,10 @@ __global__ void __launch_bounds__(256) k_div_col(GatherArgs A, const Col* __rest
         if (b >= nb) continue;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          const long long o = off[b * 4 + a] + lay;
-          hdx += wy[b] * dwx[a] * inv_dx * A.coef[o + (long long)A.c_u * A.nl];
-          if (A.c_v >= 0) hdx += dwy[b] * wx[a] * inv_dy * A.coef[o + (long long)A.c_v * A.nl];
-          hw += wy[b] * wx[a] * A.coef[o + (long long)A.c_w * A.nl];
+          const long long o = off[b * 4 + a] + (long long)lay * A.fv * A.ps;
+          hdx += wy[b] * dwx[a] * inv_dx * A.coef[o + A.c_u * A.ps];
+          if (A.c_v >= 0) hdx += dwy[b] * wx[a] * inv_dy * A.coef[o + A.c_v * A.ps];
+          hw += wy[b] * wx[a] * A.coef[o + A.c_w * A.ps];
         }
       }
       h[l] = hdx;
@@ -254,6 +415,15 @@ struct swense_cells {
   size_t coef_bytes = 0;
   Skel skel{};            // skeleton heights of the layers (R = 0: none)
   void* skel_mem = nullptr;
+  // tiled gather (clouds without shared columns): tile of stencil start
+  // nodes per horizontal axis (1 in y for 2D), band of first layers
+  bool tiled = false;
+  bool coef_plane = false;  // layout the last evaluation wrote (plane or node-major)
+  int tile = 0, tile_l = 0;
+  int nitems = 0;
+  TileItem* items = nullptr;
+  unsigned* hxy = nullptr;
+  float2* txy = nullptr;
 };
 
 namespace {
@@ -416,10 +586,63 @@ bool build_skeleton(const std::vector<double>& z, double kmax, double depth, dou
   }
 }
 
+// Tile shape of the tiled gather: the candidate (tile of stencil start
+// nodes, band of first layers) with the least staged data over the cloud's
+// own bins (a sample of at most ~400k points), each item charged the cache
+// lines its staging reads plus a fixed 16 KB for its launch slot, so that
+// sparse clouds take large tiles and dense ones small tiles with less halo.  Sized
+// for the full field set (8 volume and 2 surface fields in 3D, 6 and 2 in
+// 2D); one block at most 53 KB, so that three workgroups share a CU.
+void choose_tile(swense_cells* c, const std::vector<int>& ixs, const std::vector<int>& iys,
+                 const std::vector<char>& okh, const std::vector<int>& l0, bool three) {
+  const int nl = c->gd.nl, wx = c->gd.wx, wy = three ? c->gd.wy : 1;
+  const long long n = c->n;
+  const long long step = std::max<long long>(1, n / 400000);
+  const int fv = three ? 8 : 6, fs = 2;
+  static const int t3[] = {4, 6, 8, 12, 16, 24, 32};
+  static const int t2[] = {16, 32, 64, 128, 256, 512};
+  static const int tls[] = {1, 2, 4, 8, 16, 32, 64};
+  double best = -1.0;
+  c->tile = three ? 8 : 64;
+  c->tile_l = 8;
+  std::vector<int> cnt;
+  for (int ti = 0; ti < (three ? 7 : 6); ++ti) {
+    const int T = three ? t3[ti] : t2[ti], TY = three ? T : 1;
+    for (int TL : tls) {
+      if (TL > nl - 3) continue;
+      const int tl = std::min(TL + 3, nl);
+      const long long stride = (long long)(fv * tl + fs) | 1;
+      const long long nodes = (long long)(T + 3) * (three ? T + 3 : 1);
+      const long long lds = nodes * (stride + 1) * 4;
+      if (lds > 53 * 1024) continue;
+      // bytes the staging moves through the caches: each node's band is one
+      // run of fv tl floats (whole 128-byte lines), its surface floats one more line
+      const double staged = (double)nodes * (std::ceil((fv * tl * 4.0 + 124.0) / 128.0) + 1.0) * 128.0;
+      const long long ntx = (wx + T - 1) / T, nty = (wy + TY - 1) / TY, nband = (nl - 4) / TL + 1;
+      if (ntx * nty * nband > (1ll << 24)) continue;
+      cnt.assign((size_t)(ntx * nty * nband), 0);
+      for (long long i = 0; i < n; i += step) {
+        if (!okh[i] || l0[i] < 0) continue;
+        ++cnt[(size_t)(((long long)(iys[i] / TY) * ntx + ixs[i] / T) * nband + l0[i] / TL)];
+      }
+      double items = 0.0;
+      for (int k : cnt)
+        if (k) items += std::ceil((double)k * step / kTileMaxPts);
+      const double cost = items * (staged + 16384.0);
+      if (best < 0 || cost < best) {
+        best = cost;
+        c->tile = T;
+        c->tile_l = TL;
+      }
+    }
+  }
+}
+
 // Host binding in FP64: stencils, column grouping, ordering.
 void bind_host(swense_cells* c, const std::vector<double>& xyz, double lx, double ly, bool three,
                std::vector<Col>& cols, std::vector<int>& perm, std::vector<int>& l0v, std::vector<float>& wzv,
-               std::vector<float>& dwzv, std::vector<float>& pzv, double rho_g) {
+               std::vector<float>& dwzv, std::vector<float>& pzv, double rho_g, std::vector<TileItem>& items,
+               std::vector<unsigned>& hxy, std::vector<float2>& txy) {
   const long long n = c->n;
   const swense_grid_desc& gd = c->gd;
   const int gx = gd.gx, gy = three ? gd.gy : 1;
@@ -498,6 +721,53 @@ void bind_host(swense_cells* c, const std::vector<double>& xyz, double lx, doubl
     if (Y[a] != Y[b]) return Y[a] < Y[b];
     return Z[a] < Z[b];
   });
+  long long nrun = 0;
+  for (long long i = 0; i < n;) {
+    const int p0 = perm[i];
+    long long j = i + 1;
+    while (okh[p0] && j < n && okh[perm[j]] && X[perm[j]] == X[p0] && Y[perm[j]] == Y[p0]) ++j;
+    ++nrun;
+    i = j;
+  }
+  // fewer than 4 points per exact column: the tiled gather (stencil-start
+  // tiles x first-layer bands, sorted by caller index within each bin)
+  c->tiled = 4 * nrun > n && gd.wx < 65536 && gd.wy < 65536;
+  items.clear();
+  if (c->tiled) {
+    choose_tile(c, ixs, iys, okh, l0_orig, three);
+    const int T = c->tile, TY = three ? c->tile : 1, TL = c->tile_l;
+    const long long ntx = (gd.wx + T - 1) / T;
+    const long long nband = (nl - 4) / TL + 1;
+    std::vector<unsigned long long> key(n);
+    for (long long i = 0; i < n; ++i) {
+      if (!okh[i] || l0_orig[i] < 0) {
+        key[i] = ~0ull;
+        continue;
+      }
+      const long long tile = (long long)(iys[i] / TY) * ntx + ixs[i] / T;
+      key[i] = (unsigned long long)(tile * nband + l0_orig[i] / TL);
+    }
+    std::sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] != key[b] ? key[a] < key[b] : a < b; });
+    for (long long i = 0; i < n;) {
+      const unsigned long long k0 = key[perm[i]];
+      long long j = i + 1;
+      while (j < n && key[perm[j]] == k0 && j - i < kTileMaxPts) ++j;
+      TileItem it{};
+      it.start = (int)i;
+      it.count = (int)(j - i);
+      if (k0 == ~0ull) {
+        it.lb = -1;
+      } else {
+        const long long tile = (long long)(k0 / nband), band = (long long)(k0 % nband);
+        it.ix0 = (int)(tile % ntx) * T;
+        it.iy0 = (int)(tile / ntx) * TY;
+        it.lb = (int)band * TL;
+        it.nlb = std::min(TL + 3, nl - it.lb);
+      }
+      items.push_back(it);
+      i = j;
+    }
+  }
   cols.clear();
   unsigned long long bad = 0;
   long long i = 0;
@@ -539,6 +809,15 @@ void bind_host(swense_cells* c, const std::vector<double>& xyz, double lx, doubl
     cols.push_back(col);
     i = j;
   }
+  if (c->tiled) {
+    hxy.resize(n);
+    txy.resize(n);
+    for (long long k = 0; k < n; ++k) {
+      const int q = perm[k];
+      hxy[k] = (unsigned)ixs[q] | ((unsigned)iys[q] << 16);
+      txy[k] = make_float2(txs[q], tys[q]);
+    }
+  }
   c->nbad = bad;
 }
 
@@ -546,6 +825,8 @@ void gather_args(swense_hos* h, swense_cells* c, unsigned mask, const CoefLayout
   std::memset(&A, 0, sizeof(A));
   const bool three = h->G.ny > 1;
   A.coef = reinterpret_cast<const float*>(c->coef);
+  A.ns = c->coef_plane ? 1 : L.k;
+  A.ps = c->coef_plane ? (long long)c->gd.wx * (three ? c->gd.wy : 1) : 1;
   A.K = L.k;
   A.fv = L.fv;
   A.fs = L.fs;
@@ -571,6 +852,15 @@ void gather_args(swense_hos* h, swense_cells* c, unsigned mask, const CoefLayout
     ++o;
   }
   A.nout = o;
+  for (int f = 0; f < 8; ++f) A.vslot[f] = -1;
+  A.sslot[0] = A.sslot[1] = -1;
+  A.zmask = 0;
+  for (int q = 0; q < o; ++q) {
+    if (q == A.p_slot) continue;
+    if (A.vol[q] >= 0) A.vslot[A.vol[q]] = q;
+    else if (A.srf[q] >= 0) A.sslot[A.srf[q]] = q;
+    else A.zmask |= 1u << q;
+  }
   A.rho = (float)h->G.rho;
   A.out = out;
   A.n = c->n;
@@ -581,7 +871,9 @@ void refresh(swense_hos* h, swense_cells* c, unsigned cm, CoefLayout* L) {
   *L = coef_layout(h, cm, c->gd.nl);
   const size_t nfl = std::max<size_t>(coef_floats(h, &c->gd, cm), 1);
   ensure_device(&c->coef, &c->coef_bytes, nfl * sizeof(float));
-  eval_coef(h, &c->gd, c->zdev, cm, reinterpret_cast<float*>(c->coef), c->skel.R > 0 ? &c->skel : nullptr);
+  int plane = 0;
+  eval_coef(h, &c->gd, c->zdev, cm, reinterpret_cast<float*>(c->coef), c->skel.R > 0 ? &c->skel : nullptr, &plane);
+  c->coef_plane = plane != 0;
 }
 
 unsigned coef_mask(unsigned mask, bool three) {
@@ -653,6 +945,20 @@ void interp_body(swense_hos* h, swense_cells* c, unsigned mask, float* out) {
   refresh(h, c, coef_mask(mask, h->G.ny > 1), &L);
   GatherArgs A;
   gather_args(h, c, mask, L, out, A);
+  if (c->tiled) {
+    const bool three = h->G.ny > 1;
+    TileDev T{c->items, c->hxy, c->txy, c->nitems, c->tile + 3, three ? c->tile + 3 : 1, 0};
+    T.stride = (L.fv * std::min(c->tile_l + 3, L.nl) + L.fs) | 1;
+    const size_t lds = (size_t)T.sx * T.sy * (T.stride + 1) * sizeof(float);
+    SW_REQUIRE(lds <= 64 * 1024, "tile block too large for LDS");
+    if (three)
+      SW_LAUNCH(h, SWENSE_K_INTERP, k_gather_tile<1>, dim3((unsigned)c->nitems), dim3(kTileThreads), lds, h->st, A,
+                T, c->pd);
+    else
+      SW_LAUNCH(h, SWENSE_K_INTERP, k_gather_tile<0>, dim3((unsigned)c->nitems), dim3(kTileThreads), lds, h->st, A,
+                T, c->pd);
+    return;
+  }
   const size_t lds = (size_t)kColsPerBlock * A.kmax * sizeof(float);
   SW_REQUIRE(lds <= 160 * 1024, "column profile too long for LDS");
   if (lds > 65536)
@@ -675,6 +981,8 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
     SW_REQUIRE(n >= 0 && n < (1ll << 31), "point count must be in [0, 2^31)");
     SW_REQUIRE(n == 0 || xyz != nullptr, "null coordinates");
     SW_REQUIRE(gd->nl >= 4, "interpolation needs at least 4 layers");
+    // a stencil of 4 nodes wraps at most once round a full period
+    SW_REQUIRE(gd->gx >= 4 && (h->G.ny == 1 || gd->gy >= 4), "interpolation needs at least 4 nodes per period");
     c = new swense_cells();
     c->h = h;
     c->gd = *gd;
@@ -689,13 +997,19 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
     std::vector<Col> cols;
     std::vector<int> perm, l0v;
     std::vector<float> wz, dwz, pz;
+    std::vector<TileItem> items;
+    std::vector<unsigned> hxy;
+    std::vector<float2> txy;
     const bool three = h->G.ny > 1;
-    bind_host(c, hx, h->G.lx, h->G.ly, three, cols, perm, l0v, wz, dwz, pz, h->G.rho * h->G.g);
+    bind_host(c, hx, h->G.lx, h->G.ly, three, cols, perm, l0v, wz, dwz, pz, h->G.rho * h->G.g, items, hxy, txy);
     c->ncols = (int)cols.size();
+    c->nitems = (int)items.size();
     for (const Col& col : cols) c->max_nlc = std::max(c->max_nlc, col.nlc);
     const size_t nn = (size_t)std::max<long long>(n, 1);
     const size_t nc = std::max<size_t>(cols.size(), 1);
-    const size_t sizes[] = {gd->nl * sizeof(double), nc * sizeof(Col), nn * 4, nn * 4, nn * 16, nn * 16, nn * 4};
+    const size_t nt = c->tiled ? nn : 0, ni = c->tiled ? std::max<size_t>(items.size(), 1) : 0;
+    const size_t sizes[] = {gd->nl * sizeof(double), nc * sizeof(Col), nn * 4, nn * 4, nn * 16, nn * 16, nn * 4,
+                            ni * sizeof(TileItem), nt * 4, nt * 8};
     size_t bytes = 0;
     for (size_t b : sizes) bytes += (b + 255) & ~size_t(255);
     SW_HIP(hipMalloc(&c->mem, bytes));
@@ -712,6 +1026,9 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
     c->pd.wz = reinterpret_cast<float*>(take(sizes[4]));
     c->pd.dwz = reinterpret_cast<float*>(take(sizes[5]));
     c->pd.pz = reinterpret_cast<float*>(take(sizes[6]));
+    c->items = reinterpret_cast<TileItem*>(take(sizes[7]));
+    c->hxy = reinterpret_cast<unsigned*>(take(sizes[8]));
+    c->txy = reinterpret_cast<float2*>(take(sizes[9]));
     SW_REQUIRE(p <= reinterpret_cast<char*>(c->mem) + bytes, "internal carve overflow");
     SW_HIP(hipMemcpy(c->zdev, gd->z, gd->nl * sizeof(double), hipMemcpyHostToDevice));
     if (n > 0) {
@@ -721,6 +1038,11 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
       SW_HIP(hipMemcpy(c->pd.wz, wz.data(), n * 16, hipMemcpyHostToDevice));
       SW_HIP(hipMemcpy(c->pd.dwz, dwz.data(), n * 16, hipMemcpyHostToDevice));
       SW_HIP(hipMemcpy(c->pd.pz, pz.data(), n * 4, hipMemcpyHostToDevice));
+      if (c->tiled) {
+        SW_HIP(hipMemcpy(c->items, items.data(), items.size() * sizeof(TileItem), hipMemcpyHostToDevice));
+        SW_HIP(hipMemcpy(c->hxy, hxy.data(), n * 4, hipMemcpyHostToDevice));
+        SW_HIP(hipMemcpy(c->txy, txy.data(), n * 8, hipMemcpyHostToDevice));
+      }
     }
     // skeleton heights for the coefficient grids: factors reproduced to 1e-7
     // of each wavenumber's scale, below the FP32 rounding of the transforms

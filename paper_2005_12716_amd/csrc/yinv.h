@@ -5,6 +5,45 @@
 #include "internal.h"
 #include "wfft.h"
 
+// Workgroup transforms (one sequence per 256-thread workgroup) exist for
+// power-of-two lengths in [256, 4096] (block4_fft) and for 768, 1536 and
+// 3072 points (block3_fft).
+__host__ __device__ constexpr bool b4_len_ok(int n) { return n >= 256 && n <= 4096 && (n & (n - 1)) == 0; }
+__host__ __device__ constexpr bool b3_len_ok(int n) { return n == 768 || n == 1536 || n == 3072; }
+__host__ __device__ constexpr bool grp_len_ok(int n) { return b4_len_ok(n) || b3_len_ok(n); }
+// LDS elements of a workgroup transform of length n
+inline size_t grp_lds_len(int n) {
+  if (b3_len_ok(n)) return n == 768 ? b3_len<256>() : (n == 1536 ? b3_len<512>() : b3_len<1024>());
+  return 4ull * wbuf_len(n / 4);
+}
+
+// Slot of element n of a workgroup transform's input, of element k of its
+// output, and the transform itself.
+template <int N>
+__device__ __forceinline__ int grp_in(int n) {
+  if constexpr (N % 3 == 0) return b3_in<N / 3>(n); else return b4_in<N / 4>(n);
+}
+template <int N>
+__device__ __forceinline__ int grp_out(int k) {
+  if constexpr (N % 3 == 0) return b3_out<N / 3>(k); else return b4_out<N / 4>(k);
+}
+template <typename R, int N>
+__device__ __forceinline__ void grp_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign) {
+  if constexpr (N % 3 == 0) block3_fft<R, N / 3>(buf, tw, sign); else block4_fft<R, N>(buf, tw, sign);
+}
+
+#define SW_B4_DISPATCH(n, LAUNCH) \
+  switch (n) {                    \
+    case 256: LAUNCH(256); break;   \
+    case 512: LAUNCH(512); break;   \
+    case 1024: LAUNCH(1024); break; \
+    case 2048: LAUNCH(2048); break; \
+    case 768: LAUNCH(768); break;   \
+    case 1536: LAUNCH(1536); break; \
+    case 3072: LAUNCH(3072); break; \
+    default: LAUNCH(4096); break;   \
+  }
+
 __device__ __forceinline__ cd symbol_of(const Geom& G, const YInvJob& jb, int p, int qs) {
   const double kx = 2.0 * M_PI * (double)p / G.lx;
   const double ky = G.ny > 1 ? 2.0 * M_PI * (double)qs / G.ly : 0.0;
@@ -38,42 +77,6 @@ __device__ __forceinline__ cd symbol_of(const Geom& G, const YInvJob& jb, int p,
       return m;
     }
   }
-}
-
-// Evaluation symbol in single precision, for FP32 transforms: the factors of
-// symbol_of's evaluation branch (vertical factor, multiplier, prefilter) in
-// float arithmetic.  Per column: kx, the x prefilter factor bx and the scale
-// kys = 2 pi / ly of ky.
-__device__ __forceinline__ cpx<float> symbol_eval_f32(const Geom& G, const YInvJob& jb, float kx, float bx, float kys,
-                                                      int qs) {
-  const float ky = G.ny > 1 ? kys * (float)qs : 0.f;
-  const float k = sqrtf(kx * kx + ky * ky);
-  float C = 1.f, S = 1.f;
-  if (jb.ev.vf != 2) {
-    const float z = (float)jb.z;
-    if (!(G.depth > 0.0)) {
-      C = S = expf(k * z);
-    } else {
-      const float h = (float)G.depth;
-      const float a = expf(k * z), b = expf(-k * (z + 2.f * h)), d = 1.f + expf(-2.f * k * h);
-      C = (a + b) / d;
-      S = (a - b) / d;
-    }
-  }
-  const float f = jb.ev.vf == 0 ? C : (jb.ev.vf == 1 ? S : 1.f);
-  cpx<float> m;
-  switch (jb.ev.mult) {
-    case 0: m = mk(f, 0.f); break;
-    case 1: m = mk(0.f, kx * f); break;
-    case 2: m = mk(0.f, ky * f); break;
-    default: m = mk(k * f, 0.f); break;
-  }
-  if (jb.ev.pre) {
-    const float by = G.ny > 1 ? (4.f + 2.f * cospif(2.f * (float)qs / (float)jb.ev.gy)) / 6.f : 1.f;
-    const float s = 1.f / (bx * by);
-    m = mk(m.x * s, m.y * s);
-  }
-  return m;
 }
 
 // y-inverse: grid (ceil(nxh / TW), njobs).  Slot s of the length-Ly
@@ -127,14 +130,6 @@ __device__ __forceinline__ void yinv_wave(const YInvJob& jb, const Geom& G, cons
         if (!col || (s >= half && s <= Ly - half)) buf[sk(s)] = mk((R)0, (R)0);
       }
       if (col) {
-        // FP32 transforms of evaluation jobs take the single-precision symbol
-        const bool f32sym = sizeof(R) == 4 && jb.sym == SYM_EVAL;
-        float kxf = 0.f, bxf = 1.f, kys = 0.f;
-        if (f32sym) {
-          kxf = (float)(2.0 * M_PI * (double)p / G.lx);
-          if (jb.ev.pre) bxf = (float)((4.0 + 2.0 * cos(2.0 * M_PI * (double)p / (double)jb.ev.gx)) / 6.0);
-          kys = (float)(2.0 * M_PI / G.ly);
-        }
         for (int k0 = 0; k0 < E && 64 * k0 < G.ny; k0 += B) {
           cd v[B];
 #pragma unroll
@@ -149,19 +144,9 @@ __device__ __forceinline__ void yinv_wave(const YInvJob& jb, const Geom& G, cons
             const int q = lane + 64 * (k0 + k);
             const int qs = q >= half ? q - G.ny : q;
             if (q < G.ny && qs > -half) {
-              cpx<R> o;
-              if (f32sym) {
-                const cpx<float> sy = symbol_eval_f32(G, jb, kxf, bxf, kys, qs);
-                const float vx = (float)v[k].x, vy = (float)v[k].y;
-                o = mk((R)(vx * sy.x - vy * sy.y), (R)(vx * sy.y + vy * sy.x));
-              } else {
-                const cd w = cmul(v[k], symbol_of(G, jb, p, qs));
-                double ax = 0.0, ay = 0.0;
-                ax += w.x;
-                ay += w.y;
-                o = mk((R)ax, (R)ay);
-              }
-              buf[sk(qs >= 0 ? qs : qs + Ly)] = o;
+              // symbol (vertical factor, multiplier, prefilter) in FP64
+              const cd w = cmul(v[k], symbol_of(G, jb, p, qs));
+              buf[sk(qs >= 0 ? qs : qs + Ly)] = mk((R)w.x, (R)w.y);
             }
           }
         }
