@@ -364,8 +364,23 @@ int swense_profile_read(swense_hos* h, int kernel, double* total_ms, long long* 
 /* Compulsory HBM bytes (every distinct input read once, every output written
  * once, by each launch's own arguments) of the launches of kernel class
  * `kernel` issued while profiling was enabled.  Counted for the HOS classes
- * (YINV, XPASS, YFWD); 0 for the others. */
+ * (YINV, XPASS, YFWD), the evaluation classes (YINV_EVAL: spectra read, window
+ * rows written; XEVAL: window rows read, grid written) and the gather
+ * (INTERP: per-point stencil data and outputs, grid read once); 0 for the
+ * others. */
 int swense_profile_bytes(swense_hos* h, int kernel, double* bytes);
+
+/* Algorithmic HBM bytes of the same launches under the two-pass transform
+ * model: every real two-dimensional transform of the HOS step (Sec. 3.1.2:
+ * the spectral derivatives, the series terms and the right-hand side, each
+ * a real field on the padded product grid) streams its field once per pass,
+ * read and written, i.e. 2 x (4 or 8) bytes per product-grid point in each of
+ * its y and x passes.  YINV and YFWD count their jobs, XPASS its inverse
+ * inputs plus forward outputs; the evaluation classes count every (field,
+ * layer) job on the whole refined grid (Sec. 3.2.4); the gather counts 16 B of
+ * coordinates and index plus 4 B per output field per point, and the grid
+ * read once.  0 for the other classes. */
+int swense_profile_transform_bytes(swense_hos* h, int kernel, double* bytes);
 
 /* ---- lifetime ---------------------------------------------------------- */
 void swense_hos_destroy(swense_hos* h);

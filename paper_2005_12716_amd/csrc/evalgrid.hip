@@ -807,6 +807,20 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
   TwiddleCache& tc = h->tw;
   FftPlan py = tc.get(A.gy, sizeof(R) == 8);
   FftPlan px = tc.get(A.gx, sizeof(R) == 8);
+  if (h->prof.on) {
+    // compulsory: each distinct spectrum read once, the window rows written
+    // once and read once by the x pass, the outputs written once; model: the
+    // two-pass transform bytes of every (field, layer) job on the refined grid
+    int nsrc = 0;
+    for (int f = 0; f < A.nvol + A.nsurf; ++f) nsrc = std::max(nsrc, A.sid[f] + 1);
+    const double rows = (double)njobs * A.wy * h->G.nxh * csz;
+    const double outb = (double)(pre ? A.nvol * gd->nl + A.nsurf : (size_t)(nvo * gd->nl + nso)) * plane * 4.0;
+    const double tb = (double)njobs * 2.0 * sizeof(R) * (double)A.gx * A.gy;
+    h->prof.bytes[SWENSE_K_YINV_EVAL] += (double)nsrc * h->nc * sizeof(cd) + rows;
+    h->prof.tbytes[SWENSE_K_YINV_EVAL] += tb;
+    h->prof.bytes[SWENSE_K_XEVAL] += rows + outb;
+    h->prof.tbytes[SWENSE_K_XEVAL] += tb;
+  }
   // y pass
   SW_REQUIRE(njobs <= 65535, "too many (field, layer) pairs");
   const int tq = (h->G.ny + 255) / 256;

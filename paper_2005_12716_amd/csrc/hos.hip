@@ -1242,6 +1242,7 @@ void yinv_t(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, in
       if (!seen) b += spec;
     }
     h->prof.bytes[SWENSE_K_YINV] += b;
+    h->prof.tbytes[SWENSE_K_YINV] += (double)a.njobs * 2.0 * sizeof(R) * (double)h->Px * h->Py;
   }
   if (grp_len_ok(plan.n) && h->G.ny > 1 && plan.n >= h->G.ny) {
     const WPlan wp = make_wplan(plan);
@@ -1286,6 +1287,7 @@ void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t s
       b += per * modes;
     }
     h->prof.bytes[SWENSE_K_YFWD] += b;
+    h->prof.tbytes[SWENSE_K_YFWD] += (double)a.njobs * 2.0 * sizeof(R) * (double)h->Px * h->Py;
   }
   if (grp_len_ok(plan.n) && h->G.ny <= 1024) {
     const WPlan wp = make_wplan(plan);
@@ -1325,6 +1327,8 @@ void xpass_t(swense_hos* h, const XArgs& a) {
       if (!seen) b += rows;
     }
     h->prof.bytes[SWENSE_K_XPASS] += b;
+    const int nout = (a.out0 ? 1 : 0) + (a.out1 ? 1 : 0);
+    h->prof.tbytes[SWENSE_K_XPASS] += (double)(a.nin + nout) * 2.0 * sizeof(R) * (double)h->Px * h->Py;
   }
   // rounds version: power-of-two rows up to 1024 points, order <= 4, every
   // gradient pair at an even input index
@@ -1970,6 +1974,7 @@ int swense_profile_enable(swense_hos* h, int enable) {
       h->prof.total_ms[k] = 0.0;
       h->prof.count[k] = 0;
       h->prof.bytes[k] = 0.0;
+      h->prof.tbytes[k] = 0.0;
     }
     h->prof.on = enable != 0;
     return SWENSE_OK;
@@ -1998,6 +2003,12 @@ int swense_profile_read(swense_hos* h, int kernel, double* total_ms, long long* 
 int swense_profile_bytes(swense_hos* h, int kernel, double* bytes) {
   if (!h || !bytes || kernel < 0 || kernel >= SWENSE_K_COUNT) return SWENSE_EINVAL;
   *bytes = h->prof.bytes[kernel];
+  return SWENSE_OK;
+}
+
+int swense_profile_transform_bytes(swense_hos* h, int kernel, double* bytes) {
+  if (!h || !bytes || kernel < 0 || kernel >= SWENSE_K_COUNT) return SWENSE_EINVAL;
+  *bytes = h->prof.tbytes[kernel];
   return SWENSE_OK;
 }
 

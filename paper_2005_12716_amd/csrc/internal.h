@@ -108,6 +108,8 @@ struct Profiler {
   double total_ms[SWENSE_K_COUNT] = {};
   long long count[SWENSE_K_COUNT] = {};
   double bytes[SWENSE_K_COUNT] = {};  // compulsory HBM bytes of the recorded launches
+  double tbytes[SWENSE_K_COUNT] = {}; // two-pass transform model: every real transform's product-grid
+                                      // field read and written once per pass (per pass 2 x precision B/point)
   hipEvent_t take() {
     if (used == pool.size()) {
       hipEvent_t e;

@@ -945,6 +945,15 @@ void interp_body(swense_hos* h, swense_cells* c, unsigned mask, float* out) {
   refresh(h, c, coef_mask(mask, h->G.ny > 1), &L);
   GatherArgs A;
   gather_args(h, c, mask, L, out, A);
+  if (h->prof.on) {
+    // compulsory: every point's stencil data read once, its outputs written
+    // once, the coefficient grid read once; model: 12 B of coordinates + 4 B of
+    // index + 4 B per output field per point, plus the grid
+    const double grid = (double)L.k * c->gd.wx * (h->G.ny > 1 ? c->gd.wy : 1) * 4.0;
+    const double per = 4.0 + 4.0 + 16.0 + (A.p_slot >= 0 ? 4.0 : 0.0) + (c->tiled ? 12.0 : 0.0);
+    h->prof.bytes[SWENSE_K_INTERP] += (double)c->n * (per + 4.0 * A.nout) + grid;
+    h->prof.tbytes[SWENSE_K_INTERP] += (double)c->n * (16.0 + 4.0 * A.nout) + grid;
+  }
   if (c->tiled) {
     const bool three = h->G.ny > 1;
     TileDev T{c->items, c->hxy, c->txy, c->nitems, c->tile + 3, three ? c->tile + 3 : 1, 0};
