@@ -251,6 +251,24 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
 int swense_interp_cells(swense_hos* h, swense_cells* c, unsigned mask, float* out,
                         long long* n_out_of_range);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * interpolation as swense_interp_cells - same kernels, same results - with
+ * every scratch buffer (the coefficient grid, the evaluation rows and the
+ * DFT basis) carved from one fixed device array of 128 MiB per GPU, held by
+ * the library until the process ends.  Calls no hipMalloc, hipFree or
+ * allocating library routine: the cells' twiddle tables are made by
+ * swense_cells_bind, the rest lives in the handle since swense_hos_init.  A
+ * call needing more scratch than 128 MiB (window nodes x layers x fields,
+ * e.g. about a 216 x 216 window of 48 layers and 11 fields) returns
+ * SWENSE_ENOMEM before any launch.  Every call on one GPU shares that GPU's
+ * array and leaves its contents behind (nothing in it needs to start at
+ * zero); calls that overlap on one GPU - from several handles or streams -
+ * race on it and must be serialised by the caller.  Arguments, ownership and
+ * the other error codes as for swense_interp_cells. */
+int swense_interp_cells_noalloc(swense_hos* h, swense_cells* c, unsigned mask, float* out,
+                                long long* n_out_of_range);
+
 /* Divergence diagnostic (Sec. 3.2.3) at the bound points: du/dx + dv/dy +
  * dw/dz of the interpolant (device FP32 [n], caller order).  Asynchronous. */
 int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div);

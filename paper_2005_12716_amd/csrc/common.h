@@ -131,6 +131,7 @@ struct TwiddleCache {
     p.tw = it->second;
     return p;
   }
+  bool has(int n, bool fp64) const { return tables.count(std::make_pair(n, fp64 ? 16 : 8)) != 0; }
   void release() {
     for (auto& kv : tables) (void)hipFree(kv.second);
     tables.clear();

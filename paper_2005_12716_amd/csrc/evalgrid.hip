@@ -659,6 +659,9 @@ struct EvalWork {
   size_t basis_bytes = 0;
   double* zdev = nullptr;
   size_t zcap = 0;
+  // caller-provided scratch for one call (null: the buffers above, grown on demand)
+  char* ext = nullptr;
+  size_t ext_inter = 0, ext_basis = 0;  // capacities: intermediates first, then the basis
 };
 
 namespace {
@@ -802,8 +805,14 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
   if (njobs == 0) return;
   EvalWork* w = work(h);
   const size_t csz = sizeof(cpx<R>);
-  ensure(&w->inter, &w->inter_bytes, (size_t)njobs * A.wy * h->G.nxh * csz);
-  A.inter = w->inter;
+  const size_t inter_need = (size_t)njobs * A.wy * h->G.nxh * csz;
+  if (w->ext) {
+    if (inter_need > w->ext_inter) throw SwenseError{SWENSE_ENOMEM, "scratch too small for the evaluation rows"};
+    A.inter = w->ext;
+  } else {
+    ensure(&w->inter, &w->inter_bytes, inter_need);
+    A.inter = w->inter;
+  }
   TwiddleCache& tc = h->tw;
   FftPlan py = tc.get(A.gy, sizeof(R) == 8);
   FftPlan px = tc.get(A.gx, sizeof(R) == 8);
@@ -871,8 +880,14 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
         const int hx = h->G.nx / 2;
         const size_t nb = (size_t)ntx * dft_rows(hx) * DX_T;
         SW_REQUIRE(nb < (1ull << 31), "coefficient window too wide");
-        ensure(&w->basis, &w->basis_bytes, nb * sizeof(float));
-        float* basis = reinterpret_cast<float*>(w->basis);
+        float* basis;
+        if (w->ext) {
+          if (nb * sizeof(float) > w->ext_basis) throw SwenseError{SWENSE_ENOMEM, "scratch too small for the DFT basis"};
+          basis = reinterpret_cast<float*>(w->ext + w->ext_inter);
+        } else {
+          ensure(&w->basis, &w->basis_bytes, nb * sizeof(float));
+          basis = reinterpret_cast<float*>(w->basis);
+        }
         const unsigned bblk = (unsigned)std::min<size_t>((nb + 255) / 256, 4096);
         sw_launch(h, SWENSE_K_AUX, &k_dft_basis, dim3(bblk), dim3(256), 0, h->st, reinterpret_cast<const cf*>(px.tw),
                   px.n, A.ix0, hx, ntx, basis);
@@ -967,6 +982,26 @@ size_t grid_floats(const swense_hos* h, const swense_grid_desc* gd, unsigned mas
 }  // namespace
 
 void check_grid_desc(const swense_hos* h, const swense_grid_desc* gd) { check_grid(h, gd); }
+
+void eval_scratch_need(swense_hos* h, const swense_grid_desc* gd, unsigned cm, int skel_r, size_t* inter,
+                       size_t* basis) {
+  EvArgs A;
+  int nvo = 0, nso = 0;
+  plan_fields(h, cm, true, A, nullptr, &nvo, &nso);
+  const int nl = skel_r > 0 ? skel_r : gd->nl;
+  const size_t njobs = (size_t)A.nvol * nl + A.nsurf;
+  const size_t csz = h->fp64 ? sizeof(cd) : sizeof(cf);
+  *inter = njobs * gd->wy * h->G.nxh * csz;
+  const size_t ntx = (gd->wx + DX_T - 1) / DX_T;
+  *basis = skel_r > 0 ? ntx * dft_rows(h->G.nx / 2) * DX_T * sizeof(float) : 0;
+}
+
+void eval_set_scratch(swense_hos* h, void* base, size_t inter, size_t basis) {
+  EvalWork* w = work(h);
+  w->ext = reinterpret_cast<char*>(base);
+  w->ext_inter = inter;
+  w->ext_basis = basis;
+}
 void ensure_device(void** p, size_t* cap, size_t bytes) { ensure(p, cap, bytes); }
 
 CoefLayout coef_layout(swense_hos* h, unsigned cm, int nl) {

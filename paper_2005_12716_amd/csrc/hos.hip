@@ -1862,6 +1862,7 @@ int swense_hos_init(const swense_hos_desc* d, const double* eta0, const double* 
     h->Py = padded_len(d->ny, d->order_m, d->dealias);
     h->t = d->t0;
     SW_HIP(hipGetDevice(&h->device));
+    noalloc_scratch_setup(h->device);  // with the handle's device current
     h->plan_px = h->tw.get(h->Px, h->fp64);
     h->plan_py = h->tw.get(h->Py, h->fp64);
     h->plan_nx = h->tw.get(d->nx, true);

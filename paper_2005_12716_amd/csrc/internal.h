@@ -253,6 +253,11 @@ void hos_prime_rhs(swense_hos* h);
 hipStream_t fno_stream(const swense_fno* f);
 swense_fno_desc fno_desc_of(const swense_fno* f);
 
+// Device address of the allocation-free interpolation's scratch array on
+// device `dev` (interp.hip), looked up once per device; the set-up call is
+// made by swense_hos_init with the device current.
+void noalloc_scratch_setup(int dev);
+
 // ---- reconstruction (evalgrid.hip)
 void eval_release(swense_hos* h);
 void check_grid_desc(const swense_hos* h, const swense_grid_desc* gd);
@@ -281,6 +286,14 @@ struct Skel {
 void eval_coef(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsigned cm, float* coef,
                const Skel* sk, int* plane);
 size_t coef_floats(swense_hos* h, const swense_grid_desc* gd, unsigned cm);
+// Scratch bytes one coefficient evaluation needs: the y-pass rows and (with
+// skeleton heights) the DFT basis.
+void eval_scratch_need(swense_hos* h, const swense_grid_desc* gd, unsigned cm, int skel_r, size_t* inter,
+                       size_t* basis);
+// Evaluations on this handle take their rows (inter bytes) and basis (basis
+// bytes after them) from `base` instead of the handle's own buffers; a null
+// base restores those.
+void eval_set_scratch(swense_hos* h, void* base, size_t inter, size_t basis);
 
 // run a body and convert exceptions to error codes
 template <typename F>

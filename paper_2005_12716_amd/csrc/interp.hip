@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -419,6 +420,7 @@ struct swense_cells {
   // nodes per horizontal axis (1 in y for 2D), band of first layers
   bool tiled = false;
   bool coef_plane = false;  // layout the last evaluation wrote (plane or node-major)
+  const float* coef_cur = nullptr;  // the grid the last evaluation wrote
   int tile = 0, tile_l = 0;
   int nitems = 0;
   TileItem* items = nullptr;
@@ -824,7 +826,7 @@ void bind_host(swense_cells* c, const std::vector<double>& xyz, double lx, doubl
 void gather_args(swense_hos* h, swense_cells* c, unsigned mask, const CoefLayout& L, float* out, GatherArgs& A) {
   std::memset(&A, 0, sizeof(A));
   const bool three = h->G.ny > 1;
-  A.coef = reinterpret_cast<const float*>(c->coef);
+  A.coef = c->coef_cur;
   A.ns = c->coef_plane ? 1 : L.k;
   A.ps = c->coef_plane ? (long long)c->gd.wx * (three ? c->gd.wy : 1) : 1;
   A.K = L.k;
@@ -867,13 +869,20 @@ void gather_args(swense_hos* h, swense_cells* c, unsigned mask, const CoefLayout
   A.kmax = std::max(c->max_nlc * L.fv + L.fs, 3 * c->max_nlc);
 }
 
-void refresh(swense_hos* h, swense_cells* c, unsigned cm, CoefLayout* L) {
+// Coefficient grid of the current modes for the fields cm: into the cells'
+// own buffer (grown on demand), or into coef_ext when given.
+void refresh(swense_hos* h, swense_cells* c, unsigned cm, CoefLayout* L, float* coef_ext = nullptr) {
   *L = coef_layout(h, cm, c->gd.nl);
-  const size_t nfl = std::max<size_t>(coef_floats(h, &c->gd, cm), 1);
-  ensure_device(&c->coef, &c->coef_bytes, nfl * sizeof(float));
+  float* coef = coef_ext;
+  if (!coef) {
+    const size_t nfl = std::max<size_t>(coef_floats(h, &c->gd, cm), 1);
+    ensure_device(&c->coef, &c->coef_bytes, nfl * sizeof(float));
+    coef = reinterpret_cast<float*>(c->coef);
+  }
   int plane = 0;
-  eval_coef(h, &c->gd, c->zdev, cm, reinterpret_cast<float*>(c->coef), c->skel.R > 0 ? &c->skel : nullptr, &plane);
+  eval_coef(h, &c->gd, c->zdev, cm, coef, c->skel.R > 0 ? &c->skel : nullptr, &plane);
   c->coef_plane = plane != 0;
+  c->coef_cur = coef;
 }
 
 unsigned coef_mask(unsigned mask, bool three) {
@@ -939,10 +948,10 @@ __global__ void k_zero2(double* s) {
 }
 
 // Grid evaluation + gather of the current modes into out (on h->st).
-void interp_body(swense_hos* h, swense_cells* c, unsigned mask, float* out) {
+void interp_body(swense_hos* h, swense_cells* c, unsigned mask, float* out, float* coef_ext = nullptr) {
   if (c->n == 0) return;
   CoefLayout L;
-  refresh(h, c, coef_mask(mask, h->G.ny > 1), &L);
+  refresh(h, c, coef_mask(mask, h->G.ny > 1), &L, coef_ext);
   GatherArgs A;
   gather_args(h, c, mask, L, out, A);
   if (h->prof.on) {
@@ -978,6 +987,48 @@ void interp_body(swense_hos* h, swense_cells* c, unsigned mask, float* out) {
             c->ncols, c->pd);
 }
 
+// Device scratch of the allocation-free interpolation: one array per GPU the
+// library runs on, resident until the process ends.  Host code never passes
+// the array's name to a kernel: its address on each device is looked up
+// once, with that device current, and kept.
+constexpr size_t kNoAllocScratchBytes = 128ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device -> address of `scratch` on it
+
+// caller must have made `dev` current
+void* noalloc_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  SW_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  SW_REQUIRE(ptr != nullptr, "no device address for the scratch array");
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
+
+}  // namespace
+
+void noalloc_scratch_setup(int dev) { (void)noalloc_scratch(dev); }
+
+namespace {
+// makes `dev` current for a scope and restores the previous device
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    SW_HIP(hipGetDevice(&prev));
+    if (prev != dev) SW_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+}  // namespace
+
 extern "C" {
 
 int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, const double* xyz,
@@ -992,6 +1043,9 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
     SW_REQUIRE(gd->nl >= 4, "interpolation needs at least 4 layers");
     // a stencil of 4 nodes wraps at most once round a full period
     SW_REQUIRE(gd->gx >= 4 && (h->G.ny == 1 || gd->gy >= 4), "interpolation needs at least 4 nodes per period");
+    // the grid's twiddle tables now, so that interpolation calls allocate nothing for them
+    h->tw.get(gd->gx, h->fp64);
+    if (h->G.ny > 1) h->tw.get(gd->gy, h->fp64);
     c = new swense_cells();
     c->h = h;
     c->gd = *gd;
@@ -1236,6 +1290,43 @@ int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div) {
     const unsigned nblk = (unsigned)((c->ncols + kColsPerBlock - 1) / kColsPerBlock);
     SW_LAUNCH(h, SWENSE_K_INTERP_DIV, k_div_col, dim3(nblk), dim3(64 * kColsPerBlock), lds, h->st, A, c->cols,
               c->ncols, c->pd, inv_dx, inv_dy, div);
+    return (int)SWENSE_OK;
+  });
+}
+
+int swense_interp_cells_noalloc(swense_hos* h, swense_cells* c, unsigned mask, float* out,
+                                long long* n_out_of_range) {
+  if (!h || !c || c->h != h) return SWENSE_EINVAL;
+  return guarded(h, [&] {
+    SW_REQUIRE(out != nullptr || c->n == 0, "null output");
+    SW_REQUIRE((mask & ~(unsigned)SWENSE_ALL_FIELDS) == 0 && mask != 0, "bad field mask");
+    const bool three = h->G.ny > 1;
+    SW_REQUIRE(h->tw.has(c->gd.gx, h->fp64) && (!three || h->tw.has(c->gd.gy, h->fp64)),
+               "twiddle tables missing (the cells were not bound on this handle)");
+    const unsigned cm = coef_mask(mask, three);
+    size_t inter = 0, basis = 0;
+    eval_scratch_need(h, &c->gd, cm, c->skel.R, &inter, &basis);
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t cbytes = up(std::max<size_t>(coef_floats(h, &c->gd, cm), 1) * sizeof(float));
+    const size_t need = cbytes + up(inter) + up(basis);
+    if (need > kNoAllocScratchBytes)
+      throw SwenseError{SWENSE_ENOMEM, "interpolation needs " + std::to_string(need) +
+                                           " bytes of scratch; the allocation-free entry point holds " +
+                                           std::to_string(kNoAllocScratchBytes)};
+    DeviceGuard dg(h->device);
+    char* base = reinterpret_cast<char*>(noalloc_scratch(h->device));
+    eval_set_scratch(h, base + cbytes, up(inter), up(basis));
+    try {
+      interp_body(h, c, mask, out, reinterpret_cast<float*>(base));
+    } catch (...) {
+      eval_set_scratch(h, nullptr, 0, 0);
+      throw;
+    }
+    eval_set_scratch(h, nullptr, 0, 0);
+    if (n_out_of_range) {
+      *n_out_of_range = (long long)c->nbad;
+      if (c->nbad) return (int)SWENSE_ERANGE;
+    }
     return (int)SWENSE_OK;
   });
 }

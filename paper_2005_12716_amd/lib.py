@@ -99,6 +99,7 @@ def load():
         "swense_eval_grid_size": (C.c_size_t, [vp, C.POINTER(GridDesc), C.c_uint]),
         "swense_cells_bind": (C.c_int, [vp, C.POINTER(GridDesc), C.c_longlong, vp, C.POINTER(vp)]),
         "swense_interp_cells": (C.c_int, [vp, vp, C.c_uint, fp, C.POINTER(C.c_longlong)]),
+        "swense_interp_cells_noalloc": (C.c_int, [vp, vp, C.c_uint, fp, C.POINTER(C.c_longlong)]),
         "swense_eval_points_direct": (C.c_int, [vp, C.c_longlong, vp, C.c_uint, vp]),
         "swense_hos_snapshot": (C.c_int, [vp]),
         "swense_stream_solve": (C.c_int, [C.POINTER(StreamDesc), vp]),
@@ -152,7 +153,7 @@ def load():
 EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swense_hos_init",
             "swense_hos_set_state", "swense_hos_step", "swense_hos_step_exp", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
-            "swense_cells_bind", "swense_interp_cells", "swense_eval_points_direct", "swense_hos_snapshot", "swense_hos_set_eval_time", "swense_stream_solve", "swense_stream_eval", "swense_cells_alpha", "swense_cells_pstar", "swense_cells_relax",
+            "swense_cells_bind", "swense_interp_cells", "swense_interp_cells_noalloc", "swense_eval_points_direct", "swense_hos_snapshot", "swense_hos_set_eval_time", "swense_stream_solve", "swense_stream_eval", "swense_cells_alpha", "swense_cells_pstar", "swense_cells_relax",
             "swense_interp_divergence", "swense_interp_step", "swense_fv_divergence", "swense_profile_enable",
             "swense_profile_read", "swense_profile_bytes", "swense_profile_transform_bytes", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
             "swense_batch_last_error", "swense_batch_destroy", "swense_hos_destroy",
@@ -441,6 +442,19 @@ class Cells:
         rc = self.hos.L.swense_interp_cells(self.hos.h, self.c, mask, _ptr(out), C.byref(nbad) if count else None)
         if rc not in (OK, ERANGE):
             self.hos._check(rc, "interp_cells")
+        return out, (nbad.value if count else None)
+
+    def interp_noalloc(self, mask, out=None, count=True):
+        """swense_interp_cells_noalloc: the same fields with the library's
+        fixed device scratch (no device allocation in the call)."""
+        nf = bin(mask).count("1")
+        if out is None:
+            out = torch.empty((nf, self.n), dtype=torch.float32, device="cuda")
+        nbad = C.c_longlong(-1)
+        rc = self.hos.L.swense_interp_cells_noalloc(self.hos.h, self.c, mask, _ptr(out),
+                                                     C.byref(nbad) if count else None)
+        if rc not in (OK, ERANGE):
+            self.hos._check(rc, "interp_cells_noalloc")
         return out, (nbad.value if count else None)
 
     def interp_step(self, mask, out=None, nsteps=1):
