@@ -132,6 +132,24 @@ int swense_sea_spectrum(const swense_hos_desc* d, const swense_sea_desc* sea,
 int swense_hos_init(const swense_hos_desc* d, const double* eta0, const double* phis0, int layout,
                     void* stream, swense_hos** out);
 
+/* Bytes of device workspace a realisation needs when its caller owns the
+ * memory (swense_hos_init_ws): the FP64 state and spectral buffers, the
+ * transform-precision intermediates of the HOS step (Sec. 3.1.2), physical
+ * staging, the twiddle tables of the product and mode grids, and the
+ * buffers of the concurrent interpolation and of evaluation between two
+ * outputs.  EINVAL on a bad descriptor. */
+int swense_hos_workspace_bytes(const swense_hos_desc* d, size_t* bytes);
+
+/* swense_hos_init on a caller-owned device workspace: ws (256-byte aligned,
+ * on the current device) of ws_bytes >= swense_hos_workspace_bytes.  The
+ * handle keeps pointers into it and frees none of it; the caller frees it
+ * after swense_hos_destroy.  No later call on the handle allocates device
+ * memory except swense_eval_grid (value grids) and, for cells bound by
+ * swense_cells_bind, the interpolation scratch (use swense_cells_bind_ws).
+ * ENOMEM when ws_bytes is too small, EINVAL when ws is null or misaligned. */
+int swense_hos_init_ws(const swense_hos_desc* d, const double* eta0, const double* phis0, int layout,
+                       void* stream, void* ws, size_t ws_bytes, swense_hos** out);
+
 /* Replace the state (host arrays in `layout`) and set the time to t. */
 int swense_hos_set_state(swense_hos* h, const double* eta, const double* phis, int layout, double t);
 
@@ -242,6 +260,26 @@ int swense_eval_points_direct(swense_hos* h, long long n, const double* xyz, uns
  * array) is copied.  Synchronises. */
 int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, const double* xyz,
                       swense_cells** out);
+
+/* Bytes of device workspace for swense_cells_bind_ws: n points bound to the
+ * grid gd and interpolated with field masks within `mask` (Sec. 3.2.2): the
+ * per-point stencil records, the coefficient grid of those fields on the
+ * window, the evaluation rows, the DFT basis and the grid's twiddle tables.
+ * An upper bound that needs no binning (one column and one tile per point at
+ * most, skeleton coefficients for every layer). */
+int swense_cells_workspace_bytes(swense_hos* h, const swense_grid_desc* gd, long long n, unsigned mask,
+                                 size_t* bytes);
+
+/* swense_cells_bind on a caller-owned device workspace: ws (256-byte
+ * aligned, current device) of ws_bytes >= swense_cells_workspace_bytes for
+ * the same (gd, n, mask).  Every device buffer of the handle and of its
+ * interpolation calls (swense_interp_cells, swense_interp_step,
+ * swense_interp_divergence) is carved from it, so those calls allocate
+ * nothing; a call whose mask needs more coefficient fields than `mask`
+ * returns ENOMEM.  The handle frees none of it.  Synchronises.  ENOMEM when
+ * ws_bytes is too small, EINVAL on a null or misaligned ws or a bad mask. */
+int swense_cells_bind_ws(swense_hos* h, const swense_grid_desc* gd, long long n, const double* xyz, unsigned mask,
+                         void* ws, size_t ws_bytes, swense_cells** out);
 
 /* Interpolate the fields of `mask` at the bound points of the current state.
  * out: device FP32 [F][n] in the caller's point order (field-bit order).

@@ -28,6 +28,7 @@ struct swense_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int k = 0;  // branches of the current graph
+  std::vector<long> epochs;  // each realisation's scratch epoch when the graph was captured
   std::string err;
   std::string signature;
 };
@@ -112,6 +113,8 @@ void capture(swense_batch* b, int k) {
   SW_HIP(hipStreamEndCapture(b->cap, &b->graph));
   SW_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   b->k = k;
+  b->epochs.clear();
+  for (swense_hos* h : b->hos) b->epochs.push_back(h->scratch_epoch);
 }
 
 // Host bookkeeping after the graph ran once: every realisation advanced.
@@ -305,6 +308,13 @@ int swense_batch_create(swense_hos* const* hos, swense_cells* const* cells, cons
 int swense_batch_run(swense_batch* b) {
   if (!b || !b->exec) return SWENSE_EINVAL;
   return guarded_b(b, [&] {
+    // a call outside the graph reallocated a buffer the graph writes (a larger
+    // evaluation, mask or window since the capture): capture again, which
+    // records the new addresses (buffers only grow, so nothing is allocated
+    // while capturing)
+    bool stale = b->epochs.size() != b->hos.size();
+    for (size_t i = 0; i < b->hos.size() && !stale; ++i) stale = b->hos[i]->scratch_epoch != b->epochs[i];
+    if (stale) capture(b, b->k);
     prime(b);
     SW_HIP(hipGraphLaunch(b->exec, b->st));
     advance_host(b);

@@ -98,6 +98,42 @@ inline std::vector<int> factor_radices(int n) {
 // Twiddle-table cache owned by a handle (device memory, freed with it).
 struct TwiddleCache {
   std::map<std::pair<int, int>, void*> tables;  // (n, bytes per complex)
+  // caller-owned memory tables may be carved from (not freed by release)
+  char* arena = nullptr;
+  size_t arena_left = 0;
+  std::vector<void*> borrowed;
+  static size_t table_bytes(int n, bool fp64) { return ((size_t)n * (fp64 ? sizeof(cd) : sizeof(cf)) + 255) & ~size_t(255); }
+  // The table exp(-2 pi i m / n), m < n, written to caller memory `dst`
+  // (synchronous copy), and its plan.
+  static FftPlan fill(int n, bool fp64, void* dst) {
+    FftPlan p{};
+    p.n = n;
+    auto rs = factor_radices(n);
+    SW_REQUIRE((int)rs.size() <= kMaxRad, "transform length has too many factors");
+    p.nrad = (int)rs.size();
+    for (int i = 0; i < p.nrad; ++i) p.rad[i] = rs[i];
+    if (fp64) {
+      std::vector<cd> h(n);
+      for (int m = 0; m < n; ++m) h[m] = mk(std::cos(-2.0 * M_PI * m / n), std::sin(-2.0 * M_PI * m / n));
+      SW_HIP(hipMemcpy(dst, h.data(), (size_t)n * sizeof(cd), hipMemcpyHostToDevice));
+    } else {
+      std::vector<cf> h(n);
+      for (int m = 0; m < n; ++m)
+        h[m] = mk((float)std::cos(-2.0 * M_PI * m / n), (float)std::sin(-2.0 * M_PI * m / n));
+      SW_HIP(hipMemcpy(dst, h.data(), (size_t)n * sizeof(cf), hipMemcpyHostToDevice));
+    }
+    p.tw = dst;
+    return p;
+  }
+  static FftPlan plan_with(int n, void* tw) {
+    FftPlan p{};
+    p.n = n;
+    auto rs = factor_radices(n);
+    p.nrad = (int)rs.size();
+    for (int i = 0; i < p.nrad; ++i) p.rad[i] = rs[i];
+    p.tw = tw;
+    return p;
+  }
   FftPlan get(int n, bool fp64) {
     FftPlan p{};
     p.n = n;
@@ -110,7 +146,14 @@ struct TwiddleCache {
     if (it == tables.end()) {
       void* d = nullptr;
       size_t bytes = (size_t)n * (fp64 ? sizeof(cd) : sizeof(cf));
-      SW_HIP(hipMalloc(&d, bytes));
+      if (arena && table_bytes(n, fp64) <= arena_left) {
+        d = arena;
+        arena += table_bytes(n, fp64);
+        arena_left -= table_bytes(n, fp64);
+        borrowed.push_back(d);
+      } else {
+        SW_HIP(hipMalloc(&d, bytes));
+      }
       if (fp64) {
         std::vector<cd> h(n);
         for (int m = 0; m < n; ++m) {
@@ -133,8 +176,13 @@ struct TwiddleCache {
   }
   bool has(int n, bool fp64) const { return tables.count(std::make_pair(n, fp64 ? 16 : 8)) != 0; }
   void release() {
-    for (auto& kv : tables) (void)hipFree(kv.second);
+    for (auto& kv : tables) {
+      bool b = false;
+      for (void* q : borrowed) b = b || q == kv.second;
+      if (!b) (void)hipFree(kv.second);
+    }
     tables.clear();
+    borrowed.clear();
   }
 };
 

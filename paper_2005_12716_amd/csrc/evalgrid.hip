@@ -93,14 +93,15 @@ __global__ void __launch_bounds__(256) k_yinv_eval_w(EvArgs A, Geom G, WPlan pla
 }
 
 // Workgroup version for the lengths of the workgroup transforms, zero-padding
-// in y: block = (kx column p, layer l; l = nl: the surface fields), all of the
-// layer's fields in turn, each transformed by the whole workgroup.  The
-// column's values of the (at most two) sources and, per mode, the FP64
-// vertical factors C and S at z_l and the prefilter are formed once and
-// shared by the fields; each field's symbol-weighted value is formed in FP64
-// and rounded to the transform precision.  TQ >= ny / 256 modes per thread.
+// in y (single-precision transforms): block = (kx column p, layer l; l = nl:
+// the surface fields), all of the layer's fields in turn, each transformed by
+// the whole workgroup.  The column's values of the (at most two) sources and,
+// per mode, the vertical factors C and S at z_l times the prefilter -
+// computed in FP64 and rounded once - are formed once and shared by the
+// fields; each field's value is their single-precision product with its
+// multiplier.  TQ >= ny / 256 modes per thread.
 template <typename R, int N, int TQ>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 3072 || TQ >= 4 ? 2 : 4))) k_yinv_eval_g(EvArgs A, Geom G, const cpx<R>* __restrict__ tw) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 3072 || (N >= 1536 && TQ >= 2) || (N == 768 && TQ >= 4) || (N == 2048 && TQ >= 2) ? 2 : 4))) k_yinv_eval_g(EvArgs A, Geom G, const cpx<R>* __restrict__ tw) {
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
   constexpr int T = N / 256;  // slots per thread
@@ -115,20 +116,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 3
   int s1 = s0;
   for (int f = f0; f < f1; ++f)
     if (A.sid[f] != s0) s1 = A.sid[f];
-  cd v0[TQ], v1[TQ];
+  // per mode of this thread: the source values and the FP64 products of
+  // vertical factor and prefilter, each rounded once to single precision
+  cpx<float> v0[TQ], v1[TQ];
+  float fc[TQ], fsn[TQ];
+  const double kx = 2.0 * M_PI * (double)p / G.lx;
+  const double bx = A.pre ? (4.0 + 2.0 * cos(2.0 * M_PI * (double)p / (double)A.gx)) / 6.0 : 1.0;
+  const double z = surf ? 0.0 : A.z[l];
+  const double kys = 2.0 * M_PI / G.ly;
 #pragma unroll
   for (int t = 0; t < TQ; ++t) {
     const int q = tid + 256 * t;
     const int qs = q >= half ? q - G.ny : q;
     const bool ok = col && q < G.ny && qs > -half;
-    v0[t] = ok ? A.srcs[s0][(size_t)q * G.nxh + p] : mk(0.0, 0.0);
-    v1[t] = ok ? A.srcs[s1][(size_t)q * G.nxh + p] : mk(0.0, 0.0);
+    const cd a = ok ? A.srcs[s0][(size_t)q * G.nxh + p] : mk(0.0, 0.0);
+    const cd b = ok ? A.srcs[s1][(size_t)q * G.nxh + p] : mk(0.0, 0.0);
+    v0[t] = mk((float)a.x, (float)a.y);
+    v1[t] = mk((float)b.x, (float)b.y);
   }
-  const double kx = 2.0 * M_PI * (double)p / G.lx;
-  const double bx = A.pre ? (4.0 + 2.0 * cos(2.0 * M_PI * (double)p / (double)A.gx)) / 6.0 : 1.0;
-  const double z = surf ? 0.0 : A.z[l];
-  const double kys = 2.0 * M_PI / G.ly;
-  double fc[TQ], fsn[TQ];  // vertical factors times the prefilter
 #pragma unroll
   for (int t = 0; t < TQ; ++t) {
     const int q = tid + 256 * t;
@@ -138,9 +143,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 3
     if (!surf) vfactors(sqrt(kx * kx + ky * ky), z, G.depth, c, sn);
     const double by = A.pre ? (4.0 + 2.0 * cos(2.0 * M_PI * (double)qs / (double)A.gy)) / 6.0 : 1.0;
     const double pre = 1.0 / (bx * by);
-    fc[t] = c * pre;
-    fsn[t] = sn * pre;
+    fc[t] = (float)(c * pre);
+    fsn[t] = (float)(sn * pre);
   }
+  const float kxf = (float)kx, kysf = (float)kys;
   for (int f = f0; f < f1; ++f) {
     const EvField F = A.f[f];
     const bool first = A.sid[f] == s0;
@@ -155,16 +161,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 3
       const int qs = q >= half ? q - G.ny : q;
       if (col && q < G.ny && qs > -half) {
         // surface fields: no vertical factor (fc = fsn = prefilter there)
-        const double fac = F.vf == 1 ? fsn[t] : fc[t];
-        const double ky = kys * (double)qs;
-        cd m;
+        const float fac = F.vf == 1 ? fsn[t] : fc[t];
+        const float ky = kysf * (float)qs;
+        cpx<float> m;
         switch (F.mult) {
-          case 0: m = mk(fac, 0.0); break;
-          case 1: m = mk(0.0, kx * fac); break;
-          case 2: m = mk(0.0, ky * fac); break;
-          default: m = mk(sqrt(kx * kx + ky * ky) * fac, 0.0); break;
+          case 0: m = mk(fac, 0.f); break;
+          case 1: m = mk(0.f, kxf * fac); break;
+          case 2: m = mk(0.f, ky * fac); break;
+          default: m = mk(sqrtf(kxf * kxf + ky * ky) * fac, 0.f); break;
         }
-        const cd w = cmul(first ? v0[t] : v1[t], m);
+        const cpx<float> w = cmul(first ? v0[t] : v1[t], m);
         buf[grp_in<N>(qs >= 0 ? qs : qs + N)] = mk((R)w.x, (R)w.y);
       }
     }
@@ -662,6 +668,10 @@ struct EvalWork {
   // caller-provided scratch for one call (null: the buffers above, grown on demand)
   char* ext = nullptr;
   size_t ext_inter = 0, ext_basis = 0;  // capacities: intermediates first, then the basis
+  // caller-provided twiddle tables of the grid for one call (null: the handle's cache)
+  void* ext_twx = nullptr;
+  void* ext_twy = nullptr;
+  int ext_gx = 0, ext_gy = 0;
 };
 
 namespace {
@@ -810,12 +820,14 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     if (inter_need > w->ext_inter) throw SwenseError{SWENSE_ENOMEM, "scratch too small for the evaluation rows"};
     A.inter = w->ext;
   } else {
+    void* before = w->inter;
     ensure(&w->inter, &w->inter_bytes, inter_need);
+    if (w->inter != before) ++h->scratch_epoch;
     A.inter = w->inter;
   }
   TwiddleCache& tc = h->tw;
-  FftPlan py = tc.get(A.gy, sizeof(R) == 8);
-  FftPlan px = tc.get(A.gx, sizeof(R) == 8);
+  FftPlan py = (w->ext_twy && w->ext_gy == A.gy) ? TwiddleCache::plan_with(A.gy, w->ext_twy) : tc.get(A.gy, sizeof(R) == 8);
+  FftPlan px = (w->ext_twx && w->ext_gx == A.gx) ? TwiddleCache::plan_with(A.gx, w->ext_twx) : tc.get(A.gx, sizeof(R) == 8);
   if (h->prof.on) {
     // compulsory: each distinct spectrum read once, the window rows written
     // once and read once by the x pass, the outputs written once; model: the
@@ -885,7 +897,9 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
           if (nb * sizeof(float) > w->ext_basis) throw SwenseError{SWENSE_ENOMEM, "scratch too small for the DFT basis"};
           basis = reinterpret_cast<float*>(w->ext + w->ext_inter);
         } else {
+          void* before = w->basis;
           ensure(&w->basis, &w->basis_bytes, nb * sizeof(float));
+          if (w->basis != before) ++h->scratch_epoch;
           basis = reinterpret_cast<float*>(w->basis);
         }
         const unsigned bblk = (unsigned)std::min<size_t>((nb + 255) / 256, 4096);
@@ -1001,6 +1015,14 @@ void eval_set_scratch(swense_hos* h, void* base, size_t inter, size_t basis) {
   w->ext = reinterpret_cast<char*>(base);
   w->ext_inter = inter;
   w->ext_basis = basis;
+}
+
+void eval_set_twiddles(swense_hos* h, int gx, void* twx, int gy, void* twy) {
+  EvalWork* w = work(h);
+  w->ext_twx = twx;
+  w->ext_twy = twy;
+  w->ext_gx = gx;
+  w->ext_gy = gy;
 }
 void ensure_device(void** p, size_t* cap, size_t bytes) { ensure(p, cap, bytes); }
 

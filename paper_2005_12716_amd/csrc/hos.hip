@@ -834,11 +834,11 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
 // to three pairs keeps the wavefronts busy and several workgroups share a
 // CU; per point only eta and the running sum are held.  The inputs are
 // folded in index order with the same arithmetic as the rounds kernel.
-template <typename R, int Q>
-__global__ void __launch_bounds__(256) k_xpass_series3(XArgs A, Geom G, WPlan plan) {
+template <typename R, int Q, int NT>
+__global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan plan) {
   constexpr int Px = 3 * Q;
-  constexpr int PPT = Px / 256;              // points per thread
-  constexpr int KP = (Px / 2 + 255) / 256;   // kept modes per thread (p < Px / 2)
+  constexpr int PPT = Px / NT;               // points per thread
+  constexpr int KP = (Px / 2 + NT - 1) / NT;  // kept modes per thread (p < Px / 2)
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
   C* buf = reinterpret_cast<C*>(smem);
@@ -865,7 +865,7 @@ __global__ void __launch_bounds__(256) k_xpass_series3(XArgs A, Geom G, WPlan pl
     C va[KP], vb[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int p = tid + 256 * k;
+      const int p = tid + NT * k;
       va[k] = vb[k] = mk((R)0, (R)0);
       if (p < hx) {
         va[k] = ra[p];
@@ -874,12 +874,12 @@ __global__ void __launch_bounds__(256) k_xpass_series3(XArgs A, Geom G, WPlan pl
     }
 #pragma unroll
     for (int t = 0; t < PPT; ++t) {
-      const int s = tid + 256 * t;
+      const int s = tid + NT * t;
       if (s >= hx && s <= Px - hx) buf[b3_in<Q>(s)] = mk((R)0, (R)0);
     }
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int p = tid + 256 * k;
+      const int p = tid + NT * k;
       if (p < hx) {
         C a = va[k], b = vb[k];
         if (dxa) a = times_ikx<R>(a, p, G);
@@ -888,7 +888,7 @@ __global__ void __launch_bounds__(256) k_xpass_series3(XArgs A, Geom G, WPlan pl
         if (p > 0) buf[b3_in<Q>(Px - p)] = mk(a.x + b.y, b.x - a.y);  // conj(a) + i conj(b)
       }
     }
-    block3_fft<R, Q>(buf, tw, +1);
+    block3_fft<R, Q, NT>(buf, tw, +1);
     const int i1 = min(A.nin, 2 * pi + 2);
     for (int i = 2 * pi; i < i1; ++i) {
       const int code = s_code[i];
@@ -896,7 +896,7 @@ __global__ void __launch_bounds__(256) k_xpass_series3(XArgs A, Geom G, WPlan pl
       const bool hi = i & 1;
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        const C zx = buf[b3_out<Q>(tid + 256 * j)];
+        const C zx = buf[b3_out<Q>(tid + NT * j)];
         const R v = hi ? zx.y : zx.x;
         if (role == XR_ETA) {
           eta[j] = v;
@@ -912,12 +912,12 @@ __global__ void __launch_bounds__(256) k_xpass_series3(XArgs A, Geom G, WPlan pl
     __syncthreads();  // the buffer is refilled by the next pair
   }
 #pragma unroll
-  for (int j = 0; j < PPT; ++j) buf[b3_in<Q>(tid + 256 * j)] = mk(-w0[j], (R)0);
-  block3_fft<R, Q>(buf, tw, -1);
+  for (int j = 0; j < PPT; ++j) buf[b3_in<Q>(tid + NT * j)] = mk(-w0[j], (R)0);
+  block3_fft<R, Q, NT>(buf, tw, -1);
   const R sc = (R)(0.5 / (double)Px);
   C* d0 = reinterpret_cast<C*>(A.out0);
   C* d1 = reinterpret_cast<C*>(A.out1);
-  for (int p = tid; p < G.nxh; p += 256) {
+  for (int p = tid; p < G.nxh; p += NT) {
     C o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
     if (p < hx) {
       C zp = buf[b3_out<Q>(p)];
@@ -935,11 +935,11 @@ __global__ void __launch_bounds__(256) k_xpass_series3(XArgs A, Geom G, WPlan pl
 // input pair transformed by the workgroup, the order-M products (eta,
 // |grad eta|^2, grad eta . grad phi, |grad phi|^2 and W_1 .. W_M, M <= MW)
 // held per point; same fold and output arithmetic as the rounds kernel.
-template <typename R, int Q, int MW>
-__global__ void __launch_bounds__(256, 2) k_xpass_final3(XArgs A, Geom G, WPlan plan) {
+template <typename R, int Q, int MW, int NT>
+__global__ void __launch_bounds__(NT, NT == 256 ? 2 : 1) k_xpass_final3(XArgs A, Geom G, WPlan plan) {
   constexpr int Px = 3 * Q;
-  constexpr int PPT = Px / 256;
-  constexpr int KP = (Px / 2 + 255) / 256;
+  constexpr int PPT = Px / NT;
+  constexpr int KP = (Px / 2 + NT - 1) / NT;
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
   C* buf = reinterpret_cast<C*>(smem);
@@ -970,7 +970,7 @@ __global__ void __launch_bounds__(256, 2) k_xpass_final3(XArgs A, Geom G, WPlan 
     C va[KP], vb[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int p = tid + 256 * k;
+      const int p = tid + NT * k;
       va[k] = vb[k] = mk((R)0, (R)0);
       if (p < hx) {
         va[k] = ra[p];
@@ -979,12 +979,12 @@ __global__ void __launch_bounds__(256, 2) k_xpass_final3(XArgs A, Geom G, WPlan 
     }
 #pragma unroll
     for (int t = 0; t < PPT; ++t) {
-      const int s = tid + 256 * t;
+      const int s = tid + NT * t;
       if (s >= hx && s <= Px - hx) buf[b3_in<Q>(s)] = mk((R)0, (R)0);
     }
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int p = tid + 256 * k;
+      const int p = tid + NT * k;
       if (p < hx) {
         C a = va[k], b = vb[k];
         if (dxa) a = times_ikx<R>(a, p, G);
@@ -993,7 +993,7 @@ __global__ void __launch_bounds__(256, 2) k_xpass_final3(XArgs A, Geom G, WPlan 
         if (p > 0) buf[b3_in<Q>(Px - p)] = mk(a.x + b.y, b.x - a.y);
       }
     }
-    block3_fft<R, Q>(buf, tw, +1);
+    block3_fft<R, Q, NT>(buf, tw, +1);
     const int i1 = min(A.nin, 2 * pi + 2);
     for (int i = 2 * pi; i < i1; ++i) {
       const int code = s_code[i];
@@ -1001,7 +1001,7 @@ __global__ void __launch_bounds__(256, 2) k_xpass_final3(XArgs A, Geom G, WPlan 
       const bool hi = i & 1;
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        const C zx = buf[b3_out<Q>(tid + 256 * j)];
+        const C zx = buf[b3_out<Q>(tid + NT * j)];
         const R v = hi ? zx.y : zx.x;
         if (role == XR_ETA) {
           eta[j] = v;
@@ -1038,13 +1038,13 @@ __global__ void __launch_bounds__(256, 2) k_xpass_final3(XArgs A, Geom G, WPlan 
     R o1 = (R)0.5 * w2sum_n<MW>(W[j], M);
     if (M >= 2) o1 -= (R)0.5 * gp2[j];
     if (M >= 4) o1 += (R)0.5 * ge2[j] * w2sum_n<MW>(W[j], M - 2);
-    buf[b3_in<Q>(tid + 256 * j)] = mk(o0, o1);
+    buf[b3_in<Q>(tid + NT * j)] = mk(o0, o1);
   }
-  block3_fft<R, Q>(buf, tw, -1);
+  block3_fft<R, Q, NT>(buf, tw, -1);
   const R sc = (R)(0.5 / (double)Px);
   C* d0 = reinterpret_cast<C*>(A.out0);
   C* d1 = reinterpret_cast<C*>(A.out1);
-  for (int p = tid; p < G.nxh; p += 256) {
+  for (int p = tid; p < G.nxh; p += NT) {
     C o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
     if (p < hx) {
       C zp = buf[b3_out<Q>(p)];
@@ -1354,16 +1354,19 @@ void xpass_t(swense_hos* h, const XArgs& a) {
     bool final_ok = a.stage == XS_FINAL && pairs_ok && a.M <= 5 && h->G.nx <= Px && Px == 3072;
     if (final_ok) {
       const WPlan wp = make_wplan(h->plan_px);
-      sw_launch(h, SWENSE_K_XPASS, &k_xpass_final3<R, 1024, 5>, dim3(h->Py), dim3(256),
+      // 256 threads (two workgroups per CU, 180 B per lane of spills) measured
+      // faster than 512 threads without spills (one workgroup per CU, five of
+      // eight wavefronts idle during the sub-transforms): 1.05 against 1.39 ms
+      sw_launch(h, SWENSE_K_XPASS, &k_xpass_final3<R, 1024, 5, 256>, dim3(h->Py), dim3(256),
                 b3_len<1024>() * sizeof(cpx<R>), h->st, a, h->G, wp);
       return;
     }
     if (series_ok) {
       const WPlan wp = make_wplan(h->plan_px);
       switch (Px) {
-        case 768: sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, 256>, dim3(h->Py), dim3(256), b3_len<256>() * sizeof(cpx<R>), h->st, a, h->G, wp); break;
-        case 1536: sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, 512>, dim3(h->Py), dim3(256), b3_len<512>() * sizeof(cpx<R>), h->st, a, h->G, wp); break;
-        default: sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, 1024>, dim3(h->Py), dim3(256), b3_len<1024>() * sizeof(cpx<R>), h->st, a, h->G, wp); break;
+        case 768: sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, 256, 256>, dim3(h->Py), dim3(256), b3_len<256>() * sizeof(cpx<R>), h->st, a, h->G, wp); break;
+        case 1536: sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, 512, 256>, dim3(h->Py), dim3(256), b3_len<512>() * sizeof(cpx<R>), h->st, a, h->G, wp); break;
+        default: sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, 1024, 256>, dim3(h->Py), dim3(256), b3_len<1024>() * sizeof(cpx<R>), h->st, a, h->G, wp); break;
       }
       return;
     }
@@ -1663,19 +1666,44 @@ int padded_len(int n, int M, int dealias) {
   return v;
 }
 
-void allocate(swense_hos* h) {
+size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Bytes of the handle's pool: FP64 spectral buffers, transform-precision
+// intermediates, physical staging, a state-check flag.
+size_t pool_bytes(const swense_hos_desc* d) {
+  const int M = d->order_m;
+  const size_t ny = d->dim == 2 ? 1 : d->ny, nxh = d->nx / 2 + 1;
+  const size_t nc = ny * nxh, ni = (size_t)padded_len(d->ny, M, d->dealias) * nxh;
+  const size_t isz = d->precision == 1 ? sizeof(cd) : sizeof(cf);
+  const size_t ncd = 2 * 5 + (size_t)(M + 1) * 2 + 2;  // xn sa sb acc kk, phim bm, amod atmod
+  size_t ngb = 0;
+  for (int m = 1; m <= M; ++m) ngb += M + 2 - m;
+  const size_t nint = 4 + ngb + 5;
+  const size_t nphys = (size_t)d->nx * ny;
+  return up256(ncd * nc * sizeof(cd) + nint * ni * isz + 2 * nphys * sizeof(double) + 2 * nc * sizeof(cd) + 1024 + 256);
+}
+
+// Whole workspace of a handle: pool, twiddle tables of the product and mode
+// grids, the surface copy of the concurrent interpolation, the snapshot and
+// the spectra interpolated in time.
+size_t workspace_bytes(const swense_hos_desc* d) {
+  const size_t ny = d->dim == 2 ? 1 : d->ny, nc = ny * (d->nx / 2 + 1);
+  const bool fp64 = d->precision == 1;
+  const int px = padded_len(d->nx, d->order_m, d->dealias), py = padded_len(d->dim == 2 ? 1 : d->ny, d->order_m, d->dealias);
+  return pool_bytes(d) + TwiddleCache::table_bytes(px, fp64) + TwiddleCache::table_bytes(py, fp64) +
+         TwiddleCache::table_bytes(d->nx, true) + TwiddleCache::table_bytes(d->dim == 2 ? 1 : d->ny, true) +
+         up256(nc * sizeof(cd)) + 2 * up256(4 * nc * sizeof(cd));
+}
+
+void allocate(swense_hos* h, void* ws) {
   const int M = h->d.order_m;
   h->nc = (size_t)h->G.ny * h->G.nxh;
   h->ni = (size_t)h->Py * h->G.nxh;
-  const size_t ncd = 2 * 5 + (size_t)(M + 1) * 2 + 2;  // xn sa sb acc kk, phim bm, amod atmod
-  int ngb = 0;
-  for (int m = 1; m <= M; ++m) ngb += M + 2 - m;
-  const size_t nint = 4 + (size_t)ngb + 5;
-  const size_t nphys = (size_t)h->G.nx * h->G.ny;
-  size_t bytes = ncd * h->nc * sizeof(cd) + nint * h->ni * h->isz() + 2 * nphys * sizeof(double) +
-                 2 * h->nc * sizeof(cd) + 1024;
-  SW_HIP(hipMalloc(&h->pool, bytes));
+  const size_t bytes = pool_bytes(&h->d);
+  if (ws) h->pool = ws;
+  else SW_HIP(hipMalloc(&h->pool, bytes));
   SW_HIP(hipMemsetAsync(h->pool, 0, bytes, h->st));
+  h->flag = reinterpret_cast<int*>(reinterpret_cast<char*>(h->pool) + bytes - 256);
   char* p = reinterpret_cast<char*>(h->pool);
   auto take_cd = [&]() {
     cd* r = reinterpret_cast<cd*>(p);
@@ -1846,14 +1874,70 @@ const char* swense_last_error(const swense_hos* h) {
   return h->err.c_str();
 }
 
+}  // extern "C"
+
+namespace {
+int hos_init_impl(const swense_hos_desc* d, const double* eta0, const double* phis0, int layout, void* stream,
+                  void* ws, swense_hos** out);
+}  // namespace
+
+extern "C" {
+
+int swense_hos_workspace_bytes(const swense_hos_desc* d, size_t* bytes) {
+  if (!bytes) return SWENSE_EINVAL;
+  *bytes = 0;
+  try {
+    check_desc(d);
+    *bytes = workspace_bytes(d);
+    return SWENSE_OK;
+  } catch (const SwenseError& e) {
+    return e.code;
+  }
+}
+
+int swense_hos_init_ws(const swense_hos_desc* d, const double* eta0, const double* phis0, int layout, void* stream,
+                       void* ws, size_t ws_bytes, swense_hos** out) {
+  if (!out) return SWENSE_EINVAL;
+  *out = nullptr;
+  try {
+    check_desc(d);
+  } catch (const SwenseError& e) {
+    return e.code;
+  }
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return SWENSE_EINVAL;
+  if (ws_bytes < workspace_bytes(d)) return SWENSE_ENOMEM;
+  return hos_init_impl(d, eta0, phis0, layout, stream, ws, out);
+}
+
 int swense_hos_init(const swense_hos_desc* d, const double* eta0, const double* phis0, int layout, void* stream,
                     swense_hos** out) {
   if (!out) return SWENSE_EINVAL;
+  return hos_init_impl(d, eta0, phis0, layout, stream, nullptr, out);
+}
+
+}  // extern "C"
+
+namespace {
+int hos_init_impl(const swense_hos_desc* d, const double* eta0, const double* phis0, int layout, void* stream,
+                  void* ws, swense_hos** out) {
   *out = nullptr;
   swense_hos* h = nullptr;
   try {
     check_desc(d);
     h = new swense_hos();
+    if (ws) {
+      // the caller's workspace: pool first, then the tables and buffers
+      char* base = reinterpret_cast<char*>(ws);
+      const size_t pb = pool_bytes(d), nc = (size_t)(d->dim == 2 ? 1 : d->ny) * (d->nx / 2 + 1);
+      const size_t tail = workspace_bytes(d) - pb - up256(nc * sizeof(cd)) - 2 * up256(4 * nc * sizeof(cd));
+      h->own_mem = false;
+      h->tw.arena = base + pb;
+      h->tw.arena_left = tail;
+      char* q = base + pb + tail;
+      h->eta_snap = reinterpret_cast<cd*>(q);
+      h->snapm = reinterpret_cast<cd*>(q + up256(nc * sizeof(cd)));
+      h->herm = reinterpret_cast<cd*>(q + up256(nc * sizeof(cd)) + up256(4 * nc * sizeof(cd)));
+    }
     h->d = *d;
     h->st = reinterpret_cast<hipStream_t>(stream);
     h->fp64 = d->precision == 1;
@@ -1867,7 +1951,9 @@ int swense_hos_init(const swense_hos_desc* d, const double* eta0, const double* 
     h->plan_py = h->tw.get(h->Py, h->fp64);
     h->plan_nx = h->tw.get(d->nx, true);
     h->plan_ny = h->tw.get(d->ny, true);
-    allocate(h);
+    h->tw.arena = nullptr;  // later tables (evaluation grids) are the library's
+    h->tw.arena_left = 0;
+    allocate(h, ws);
     load_state(h, eta0, phis0, layout);
     *out = h;
     return SWENSE_OK;
@@ -1881,6 +1967,9 @@ int swense_hos_init(const swense_hos_desc* d, const double* eta0, const double* 
     return SWENSE_EHIP;
   }
 }
+}  // namespace
+
+extern "C" {
 
 int swense_hos_set_state(swense_hos* h, const double* eta, const double* phis, int layout, double t) {
   if (!h) return SWENSE_EINVAL;
@@ -1911,14 +2000,12 @@ int swense_hos_step_exp(swense_hos* h, double tau, int nsub) {
 int swense_hos_get_state(swense_hos* h, double* eta, double* phis, double* t, int layout) {
   if (!h) return SWENSE_EINVAL;
   return guarded(h, [&] {
-    int* bad = nullptr;
-    SW_HIP(hipMalloc(&bad, sizeof(int)));
+    int* bad = h->flag;
     SW_HIP(hipMemsetAsync(bad, 0, sizeof(int), h->st));
     SW_LAUNCH(h, SWENSE_K_AUX, k_finite, dim3((h->nc + 255) / 256), dim3(256), 0, h->st, h->xn[0], h->xn[1], h->nc, bad);
     int hb = 0;
     SW_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, h->st));
     SW_HIP(hipStreamSynchronize(h->st));
-    SW_HIP(hipFree(bad));
     if (layout == SWENSE_SPECTRAL) {
       if (eta) SW_HIP(hipMemcpyAsync(eta, h->xn[0], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
       if (phis) SW_HIP(hipMemcpyAsync(phis, h->xn[1], h->nc * sizeof(cd), hipMemcpyDeviceToHost, h->st));
@@ -2018,13 +2105,15 @@ void swense_hos_destroy(swense_hos* h) {
   if (h->aux) (void)hipStreamSynchronize(h->aux);
   h->prof.release();
   eval_release(h);
-  if (h->eta_snap) (void)hipFree(h->eta_snap);
-  if (h->snapm) (void)hipFree(h->snapm);
-  if (h->herm) (void)hipFree(h->herm);
+  if (h->own_mem) {
+    if (h->eta_snap) (void)hipFree(h->eta_snap);
+    if (h->snapm) (void)hipFree(h->snapm);
+    if (h->herm) (void)hipFree(h->herm);
+  }
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->aux) (void)hipStreamDestroy(h->aux);
-  if (h->pool) (void)hipFree(h->pool);
+  if (h->pool && h->own_mem) (void)hipFree(h->pool);
   h->tw.release();
   delete h;
 }

@@ -158,6 +158,11 @@ struct swense_hos {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   int device = 0;
+  bool own_mem = true;  // false: pool, twiddles and snapshot buffers live in a caller's workspace
+  // bumped whenever a device buffer that evaluations or interpolations write
+  // is reallocated (captured graphs hold the old addresses)
+  long scratch_epoch = 0;
+  int* flag = nullptr;  // one device int for state checks
 
   // FP64 spectral buffers, each [ny][nxh]
   size_t nc = 0;
@@ -294,6 +299,9 @@ void eval_scratch_need(swense_hos* h, const swense_grid_desc* gd, unsigned cm, i
 // bytes after them) from `base` instead of the handle's own buffers; a null
 // base restores those.
 void eval_set_scratch(swense_hos* h, void* base, size_t inter, size_t basis);
+// Evaluations on this handle take the twiddle tables of grid lengths gx, gy
+// from twx, twy (null: the handle's cache).
+void eval_set_twiddles(swense_hos* h, int gx, void* twx, int gy, void* twy);
 
 // run a body and convert exceptions to error codes
 template <typename F>

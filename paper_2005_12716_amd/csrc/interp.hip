@@ -416,6 +416,16 @@ struct swense_cells {
   size_t coef_bytes = 0;
   Skel skel{};            // skeleton heights of the layers (R = 0: none)
   void* skel_mem = nullptr;
+  // caller-owned workspace (swense_cells_bind_ws): every device buffer of
+  // the handle and of its interpolation calls lives there
+  bool ws_mode = false;
+  unsigned ws_mask = 0;
+  float* ws_coef = nullptr;
+  size_t ws_coef_cap = 0;
+  char* ws_eval = nullptr;
+  size_t ws_inter_cap = 0, ws_basis_cap = 0;
+  void* ws_twx = nullptr;
+  void* ws_twy = nullptr;
   // tiled gather (clouds without shared columns): tile of stencil start
   // nodes per horizontal axis (1 in y for 2D), band of first layers
   bool tiled = false;
@@ -876,7 +886,9 @@ void refresh(swense_hos* h, swense_cells* c, unsigned cm, CoefLayout* L, float* 
   float* coef = coef_ext;
   if (!coef) {
     const size_t nfl = std::max<size_t>(coef_floats(h, &c->gd, cm), 1);
+    void* before = c->coef;
     ensure_device(&c->coef, &c->coef_bytes, nfl * sizeof(float));
+    if (c->coef != before) ++h->scratch_epoch;
     coef = reinterpret_cast<float*>(c->coef);
   }
   int plane = 0;
@@ -948,10 +960,35 @@ __global__ void k_zero2(double* s) {
 }
 
 // Grid evaluation + gather of the current modes into out (on h->st).
+// Scratch of a cells handle bound on a caller's workspace: the coefficient
+// grid, the evaluation rows, the DFT basis and the grid's twiddle tables
+// come from it for the duration of the evaluation (restored on exit).
+struct WsScope {
+  swense_hos* h;
+  bool on;
+  WsScope(swense_hos* hh, swense_cells* c, bool use_tw) : h(hh), on(c->ws_mode) {
+    if (!on) return;
+    eval_set_scratch(h, c->ws_eval, c->ws_inter_cap, c->ws_basis_cap);
+    if (use_tw) eval_set_twiddles(h, c->gd.gx, c->ws_twx, c->gd.gy, c->ws_twy);
+  }
+  ~WsScope() {
+    if (!on) return;
+    eval_set_scratch(h, nullptr, 0, 0);
+    eval_set_twiddles(h, 0, nullptr, 0, nullptr);
+  }
+};
+
 void interp_body(swense_hos* h, swense_cells* c, unsigned mask, float* out, float* coef_ext = nullptr) {
   if (c->n == 0) return;
   CoefLayout L;
-  refresh(h, c, coef_mask(mask, h->G.ny > 1), &L, coef_ext);
+  const unsigned cm0 = coef_mask(mask, h->G.ny > 1);
+  WsScope scope(h, c, true);
+  if (c->ws_mode && !coef_ext) {
+    if (coef_floats(h, &c->gd, cm0) * sizeof(float) > c->ws_coef_cap)
+      throw SwenseError{SWENSE_ENOMEM, "field mask needs a larger coefficient grid than the cells' workspace holds"};
+    coef_ext = c->ws_coef;
+  }
+  refresh(h, c, cm0, &L, coef_ext);
   GatherArgs A;
   gather_args(h, c, mask, L, out, A);
   if (h->prof.on) {
@@ -1029,24 +1066,124 @@ struct DeviceGuard {
 };
 }  // namespace
 
+namespace {
+// Byte offsets of a cells workspace (all 256-aligned), upper bounds that
+// need no binning: per point its stencil records (and, tiled, its tile
+// position), one column and one tile item per point at most, skeleton
+// coefficients for every layer, the coefficient grid of `mask`, the
+// evaluation rows without skeleton heights, the DFT basis, two twiddle tables.
+struct WsPlan {
+  size_t points = 0, points_bytes = 0, skel = 0, skel_bytes = 0, coef = 0, coef_bytes = 0, eval = 0,
+         inter_bytes = 0, basis_bytes = 0, twx = 0, twy = 0, total = 0;
+};
+
+WsPlan cells_ws_plan(swense_hos* h, const swense_grid_desc* gd, long long n, unsigned mask) {
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const bool three = h->G.ny > 1;
+  const size_t nn = (size_t)std::max<long long>(n, 1), L = gd->nl;
+  WsPlan w;
+  size_t o = 0;
+  w.points = o;
+  w.points_bytes = up(L * sizeof(double)) + up(nn * sizeof(Col)) + 2 * up(nn * 4) + 2 * up(nn * 16) + up(nn * 4) +
+                   up(nn * sizeof(TileItem)) + up(nn * 4) + up(nn * 8);
+  o += w.points_bytes;
+  w.skel = o;
+  w.skel_bytes = up(L * sizeof(double)) + 2 * up(L * L * sizeof(float));
+  o += w.skel_bytes;
+  const unsigned cm = coef_mask(mask, three);
+  w.coef = o;
+  w.coef_bytes = up(std::max<size_t>(coef_floats(h, gd, cm), 1) * sizeof(float));
+  o += w.coef_bytes;
+  size_t inter = 0, basis = 0;
+  eval_scratch_need(h, gd, cm, 0, &inter, &basis);
+  size_t inter_s = 0, basis_s = 0;
+  eval_scratch_need(h, gd, cm, 1, &inter_s, &basis_s);  // a skeleton's basis (any R)
+  w.eval = o;
+  w.inter_bytes = up(inter);
+  w.basis_bytes = up(basis_s);
+  o += w.inter_bytes + w.basis_bytes;
+  w.twx = o;
+  o += TwiddleCache::table_bytes(gd->gx, h->fp64);
+  w.twy = o;
+  o += three ? TwiddleCache::table_bytes(gd->gy, h->fp64) : 0;
+  w.total = o;
+  return w;
+}
+
+int cells_bind_impl(swense_hos* h, const swense_grid_desc* gd, long long n, const double* xyz, unsigned ws_mask,
+                    char* ws, size_t ws_bytes, swense_cells** out);
+}  // namespace
+
 extern "C" {
 
 int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, const double* xyz,
                       swense_cells** out) {
+  return cells_bind_impl(h, gd, n, xyz, 0u, nullptr, 0, out);
+}
+
+int swense_cells_workspace_bytes(swense_hos* h, const swense_grid_desc* gd, long long n, unsigned mask,
+                                 size_t* bytes) {
+  if (!h || !bytes) return SWENSE_EINVAL;
+  *bytes = 0;
+  return guarded(h, [&] {
+    check_grid_desc(h, gd);
+    SW_REQUIRE(n >= 0 && n < (1ll << 31), "point count must be in [0, 2^31)");
+    SW_REQUIRE((mask & ~(unsigned)SWENSE_ALL_FIELDS) == 0 && mask != 0, "bad field mask");
+    *bytes = cells_ws_plan(h, gd, n, mask).total;
+    return (int)SWENSE_OK;
+  });
+}
+
+int swense_cells_bind_ws(swense_hos* h, const swense_grid_desc* gd, long long n, const double* xyz, unsigned mask,
+                         void* ws, size_t ws_bytes, swense_cells** out) {
+  if (!h || !out || !ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return SWENSE_EINVAL;
+  if ((mask & ~(unsigned)SWENSE_ALL_FIELDS) != 0 || mask == 0) return SWENSE_EINVAL;
+  return cells_bind_impl(h, gd, n, xyz, mask, reinterpret_cast<char*>(ws), ws_bytes, out);
+}
+
+}  // extern "C"
+
+namespace {
+int cells_bind_impl(swense_hos* h, const swense_grid_desc* gd, long long n, const double* xyz, unsigned ws_mask,
+                    char* ws, size_t ws_bytes, swense_cells** out) {
   if (!h || !out) return SWENSE_EINVAL;
   *out = nullptr;
   swense_cells* c = nullptr;
   int rc = guarded(h, [&] {
+    if (ws) {
+      check_grid_desc(h, gd);
+      SW_REQUIRE(n >= 0 && n < (1ll << 31), "point count must be in [0, 2^31)");
+      if (ws_bytes < cells_ws_plan(h, gd, n, ws_mask).total)
+        throw SwenseError{SWENSE_ENOMEM, "cells workspace smaller than swense_cells_workspace_bytes"};
+    }
     check_grid_desc(h, gd);
     SW_REQUIRE(n >= 0 && n < (1ll << 31), "point count must be in [0, 2^31)");
     SW_REQUIRE(n == 0 || xyz != nullptr, "null coordinates");
     SW_REQUIRE(gd->nl >= 4, "interpolation needs at least 4 layers");
     // a stencil of 4 nodes wraps at most once round a full period
     SW_REQUIRE(gd->gx >= 4 && (h->G.ny == 1 || gd->gy >= 4), "interpolation needs at least 4 nodes per period");
-    // the grid's twiddle tables now, so that interpolation calls allocate nothing for them
-    h->tw.get(gd->gx, h->fp64);
-    if (h->G.ny > 1) h->tw.get(gd->gy, h->fp64);
+    // the grid's twiddle tables now, so that interpolation calls allocate
+    // nothing for them (in the caller's workspace when there is one)
+    const WsPlan wp = ws ? cells_ws_plan(h, gd, n, ws_mask) : WsPlan{};
     c = new swense_cells();
+    if (ws) {
+      c->ws_mode = true;
+      c->ws_mask = ws_mask;
+      c->ws_coef = reinterpret_cast<float*>(ws + wp.coef);
+      c->ws_coef_cap = wp.coef_bytes;
+      c->ws_eval = ws + wp.eval;
+      c->ws_inter_cap = wp.inter_bytes;
+      c->ws_basis_cap = wp.basis_bytes;
+      TwiddleCache::fill(gd->gx, h->fp64, ws + wp.twx);
+      c->ws_twx = ws + wp.twx;
+      if (h->G.ny > 1) {
+        TwiddleCache::fill(gd->gy, h->fp64, ws + wp.twy);
+        c->ws_twy = ws + wp.twy;
+      }
+    } else {
+      h->tw.get(gd->gx, h->fp64);
+      if (h->G.ny > 1) h->tw.get(gd->gy, h->fp64);
+    }
     c->h = h;
     c->gd = *gd;
     c->z.assign(gd->z, gd->z + gd->nl);
@@ -1075,8 +1212,15 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
                             ni * sizeof(TileItem), nt * 4, nt * 8};
     size_t bytes = 0;
     for (size_t b : sizes) bytes += (b + 255) & ~size_t(255);
-    SW_HIP(hipMalloc(&c->mem, bytes));
-    char* p = reinterpret_cast<char*>(c->mem);
+    char* p;
+    if (ws) {
+      SW_REQUIRE(bytes <= wp.points_bytes, "internal: point records exceed their workspace bound");
+      p = ws + wp.points;
+    } else {
+      SW_HIP(hipMalloc(&c->mem, bytes));
+      p = reinterpret_cast<char*>(c->mem);
+    }
+    char* const p0 = p;
     auto take = [&](size_t b) {
       void* r = p;
       p += (b + 255) & ~size_t(255);
@@ -1092,7 +1236,7 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
     c->items = reinterpret_cast<TileItem*>(take(sizes[7]));
     c->hxy = reinterpret_cast<unsigned*>(take(sizes[8]));
     c->txy = reinterpret_cast<float2*>(take(sizes[9]));
-    SW_REQUIRE(p <= reinterpret_cast<char*>(c->mem) + bytes, "internal carve overflow");
+    SW_REQUIRE(p <= p0 + bytes, "internal carve overflow");
     SW_HIP(hipMemcpy(c->zdev, gd->z, gd->nl * sizeof(double), hipMemcpyHostToDevice));
     if (n > 0) {
       SW_HIP(hipMemcpy(c->cols, cols.data(), cols.size() * sizeof(Col), hipMemcpyHostToDevice));
@@ -1119,8 +1263,14 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
         for (int j = 0; j < R; ++j) zeta[j] = c->z[sel[j]];
         const size_t b0 = ((R * sizeof(double)) + 255) & ~size_t(255);
         const size_t b1 = ((size_t)L * R * sizeof(float) + 255) & ~size_t(255);
-        SW_HIP(hipMalloc(&c->skel_mem, b0 + 2 * b1));
-        char* q = reinterpret_cast<char*>(c->skel_mem);
+        char* q;
+        if (ws) {
+          SW_REQUIRE(b0 + 2 * b1 <= wp.skel_bytes, "internal: skeleton exceeds its workspace bound");
+          q = ws + wp.skel;
+        } else {
+          SW_HIP(hipMalloc(&c->skel_mem, b0 + 2 * b1));
+          q = reinterpret_cast<char*>(c->skel_mem);
+        }
         SW_HIP(hipMemcpy(q, zeta.data(), R * sizeof(double), hipMemcpyHostToDevice));
         SW_HIP(hipMemcpy(q + b0, tc.data(), (size_t)L * R * sizeof(float), hipMemcpyHostToDevice));
         SW_HIP(hipMemcpy(q + b0 + b1, ts.data(), (size_t)L * R * sizeof(float), hipMemcpyHostToDevice));
@@ -1134,6 +1284,9 @@ int swense_cells_bind(swense_hos* h, const swense_grid_desc* gd, long long n, co
   if (rc != SWENSE_OK && c) swense_cells_destroy(c);
   return rc;
 }
+}  // namespace
+
+extern "C" {
 
 int swense_interp_cells(swense_hos* h, swense_cells* c, unsigned mask, float* out, long long* n_out_of_range) {
   if (!h || !c || c->h != h) return SWENSE_EINVAL;
@@ -1277,7 +1430,14 @@ int swense_interp_divergence(swense_hos* h, swense_cells* c, float* div) {
     const bool three = h->G.ny > 1;
     const unsigned m = SWENSE_U | SWENSE_W | (three ? SWENSE_V : 0u);
     CoefLayout L;
-    refresh(h, c, m, &L);
+    WsScope scope(h, c, true);
+    float* cx = nullptr;
+    if (c->ws_mode) {
+      if (coef_floats(h, &c->gd, m) * sizeof(float) > c->ws_coef_cap)
+        throw SwenseError{SWENSE_ENOMEM, "the divergence needs a larger coefficient grid than the cells' workspace holds"};
+      cx = c->ws_coef;
+    }
+    refresh(h, c, m, &L, cx);
     GatherArgs A;
     gather_args(h, c, m, L, nullptr, A);
     const float inv_dx = (float)(c->gd.gx / h->G.lx);
@@ -1333,7 +1493,7 @@ int swense_interp_cells_noalloc(swense_hos* h, swense_cells* c, unsigned mask, f
 
 void swense_cells_destroy(swense_cells* c) {
   if (!c) return;
-  if (c->mem) (void)hipFree(c->mem);
+  if (c->mem) (void)hipFree(c->mem);      // null when bound on a caller's workspace
   if (c->coef) (void)hipFree(c->coef);
   if (c->skel_mem) (void)hipFree(c->skel_mem);
   delete c;

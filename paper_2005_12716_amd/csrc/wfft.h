@@ -384,21 +384,22 @@ __device__ __forceinline__ void wave_fft3(cpx<R>* buf, const cpx<R>* __restrict_
   wave_sync();
 }
 
-// The workgroup (256 threads, all must call): wavefronts 0-2 take one
-// sub-transform each, every thread combines.  Starts and ends with a block
-// barrier.
-template <typename R, int Q>
+// The workgroup (NT threads, all must call; NT a multiple of 64, at least
+// 192): wavefronts 0-2 take one sub-transform each, every thread combines.
+// Starts and ends with a block barrier.
+template <typename R, int Q, int NT = 256>
 __device__ __forceinline__ void block3_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign) {
   static_assert(Q >= 64 && Q <= 1024 && (Q & (Q - 1)) == 0, "N = 3Q with Q a power of two in [64, 1024]");
+  static_assert(NT % 64 == 0 && NT >= 192, "three wavefronts at least");
   constexpr int WL = Q + Q / 16 + 1;
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
   __syncthreads();
   if (wave < 3) wave_fft_static<R, Q, 3>(buf + wave * WL, tw, sign, lane);
   __syncthreads();
 #pragma unroll
-  for (int k0 = 0; k0 < Q; k0 += 256) {
+  for (int k0 = 0; k0 < Q; k0 += NT) {
     const int kq = k0 + (int)threadIdx.x;
-    if (Q % 256 == 0 || kq < Q) b3_combine<R, Q>(buf, tw, sign, kq);
+    if (Q % NT == 0 || kq < Q) b3_combine<R, Q>(buf, tw, sign, kq);
   }
   __syncthreads();
 }

@@ -88,6 +88,8 @@ def load():
         "swense_last_error": (C.c_char_p, [vp]),
         "swense_sea_spectrum": (C.c_int, [C.POINTER(HosDesc), C.POINTER(SeaDesc), vp, vp, vp]),
         "swense_hos_init": (C.c_int, [C.POINTER(HosDesc), vp, vp, C.c_int, vp, C.POINTER(vp)]),
+        "swense_hos_workspace_bytes": (C.c_int, [C.POINTER(HosDesc), C.POINTER(C.c_size_t)]),
+        "swense_hos_init_ws": (C.c_int, [C.POINTER(HosDesc), vp, vp, C.c_int, vp, vp, C.c_size_t, C.POINTER(vp)]),
         "swense_hos_set_state": (C.c_int, [vp, vp, vp, C.c_int, C.c_double]),
         "swense_hos_step": (C.c_int, [vp, C.c_int]),
         "swense_hos_step_exp": (C.c_int, [vp, C.c_double, C.c_int]),
@@ -98,6 +100,10 @@ def load():
         "swense_eval_grid": (C.c_int, [vp, C.POINTER(GridDesc), C.c_uint, fp]),
         "swense_eval_grid_size": (C.c_size_t, [vp, C.POINTER(GridDesc), C.c_uint]),
         "swense_cells_bind": (C.c_int, [vp, C.POINTER(GridDesc), C.c_longlong, vp, C.POINTER(vp)]),
+        "swense_cells_workspace_bytes": (C.c_int, [vp, C.POINTER(GridDesc), C.c_longlong, C.c_uint,
+                                                   C.POINTER(C.c_size_t)]),
+        "swense_cells_bind_ws": (C.c_int, [vp, C.POINTER(GridDesc), C.c_longlong, vp, C.c_uint, vp, C.c_size_t,
+                                           C.POINTER(vp)]),
         "swense_interp_cells": (C.c_int, [vp, vp, C.c_uint, fp, C.POINTER(C.c_longlong)]),
         "swense_interp_cells_noalloc": (C.c_int, [vp, vp, C.c_uint, fp, C.POINTER(C.c_longlong)]),
         "swense_eval_points_direct": (C.c_int, [vp, C.c_longlong, vp, C.c_uint, vp]),
@@ -151,6 +157,7 @@ def load():
 
 
 EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swense_hos_init",
+            "swense_hos_workspace_bytes", "swense_hos_init_ws", "swense_cells_workspace_bytes", "swense_cells_bind_ws",
             "swense_hos_set_state", "swense_hos_step", "swense_hos_step_exp", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
             "swense_cells_bind", "swense_interp_cells", "swense_interp_cells_noalloc", "swense_eval_points_direct", "swense_hos_snapshot", "swense_hos_set_eval_time", "swense_stream_solve", "swense_stream_eval", "swense_cells_alpha", "swense_cells_pstar", "swense_cells_relax",
@@ -213,6 +220,15 @@ def stream_eval(desc: StreamDesc, sol, t, xyz: torch.Tensor, mask, out=None):
     return out
 
 
+def hos_workspace_bytes(desc: HosDesc):
+    """Device bytes of a realisation's workspace (swense_hos_workspace_bytes)."""
+    b = C.c_size_t()
+    rc = load().swense_hos_workspace_bytes(C.byref(desc), C.byref(b))
+    if rc != OK:
+        raise SwenseError(rc, "hos_workspace_bytes")
+    return b.value
+
+
 def sea_spectrum(desc: HosDesc, kind=0, hs=0.0, kp=1.0, gamma=3.3, spreading=0, mode=0, ka=0.0, phases=None):
     """Initial half spectra (eta_hat, phis_hat) as complex128 [ny][nx/2+1]."""
     L = load()
@@ -231,7 +247,7 @@ def sea_spectrum(desc: HosDesc, kind=0, hs=0.0, kp=1.0, gamma=3.3, spreading=0, 
 class Hos:
     """One HOS realisation on the current torch device and stream."""
 
-    def __init__(self, desc: HosDesc, eta, phis, layout=SPECTRAL, stream=None):
+    def __init__(self, desc: HosDesc, eta, phis, layout=SPECTRAL, stream=None, workspace=None):
         self.L = load()
         self.desc = desc
         self.ny = 1 if desc.dim == 2 else desc.ny
@@ -241,8 +257,15 @@ class Hos:
         st = stream if stream is not None else torch.cuda.current_stream()
         self.stream = st
         h = C.c_void_p()
-        rc = self.L.swense_hos_init(C.byref(desc), _ptr(eta), _ptr(phis), layout, C.c_void_p(st.cuda_stream),
-                                    C.byref(h))
+        self.workspace = workspace
+        if workspace is None:
+            rc = self.L.swense_hos_init(C.byref(desc), _ptr(eta), _ptr(phis), layout, C.c_void_p(st.cuda_stream),
+                                        C.byref(h))
+        else:
+            # caller-owned device memory (a torch uint8 buffer kept alive by this object)
+            assert workspace.is_cuda and workspace.dtype == torch.uint8
+            rc = self.L.swense_hos_init_ws(C.byref(desc), _ptr(eta), _ptr(phis), layout, C.c_void_p(st.cuda_stream),
+                                           _ptr(workspace), workspace.numel(), C.byref(h))
         if rc != OK:
             raise SwenseError(rc, "hos_init")
         self.h = h
@@ -386,8 +409,14 @@ class Hos:
         self._check(self.L.swense_cells_relax(self.h, n, ncomp, _ptr(x), _ptr(alpha_i), _ptr(alpha), _ptr(uc)),
                     "cells_relax")
 
-    def bind(self, gd, xyz: torch.Tensor):
-        return Cells(self, gd, xyz)
+    def bind(self, gd, xyz: torch.Tensor, workspace=None, ws_mask=None):
+        return Cells(self, gd, xyz, workspace, ws_mask)
+
+    def cells_workspace_bytes(self, gd, n, mask=None):
+        b = C.c_size_t()
+        self._check(self.L.swense_cells_workspace_bytes(self.h, C.byref(gd), n, ALL_FIELDS if mask is None else mask,
+                                                        C.byref(b)), "cells_workspace_bytes")
+        return b.value
 
     def fv_divergence(self, gd, xe, ye, ze):
         """Finite-volume divergence on the structured mesh with edges xe, ye
@@ -418,13 +447,20 @@ class Hos:
 class Cells:
     """A bound static point cloud (device FP64 coordinates [3][n])."""
 
-    def __init__(self, hos: Hos, gd, xyz: torch.Tensor):
+    def __init__(self, hos: Hos, gd, xyz: torch.Tensor, workspace=None, ws_mask=None):
         assert xyz.is_cuda and xyz.dtype == torch.float64 and xyz.dim() == 2 and xyz.shape[0] == 3
         xyz = xyz.contiguous()
         self.hos = hos
         self.n = xyz.shape[1]
         c = C.c_void_p()
-        rc = hos.L.swense_cells_bind(hos.h, C.byref(gd), self.n, _ptr(xyz), C.byref(c))
+        self.workspace = workspace
+        if workspace is None:
+            rc = hos.L.swense_cells_bind(hos.h, C.byref(gd), self.n, _ptr(xyz), C.byref(c))
+        else:
+            assert workspace.is_cuda and workspace.dtype == torch.uint8
+            rc = hos.L.swense_cells_bind_ws(hos.h, C.byref(gd), self.n, _ptr(xyz),
+                                            ALL_FIELDS if ws_mask is None else ws_mask, _ptr(workspace),
+                                            workspace.numel(), C.byref(c))
         hos._check(rc, "cells_bind")
         self.c = c
         self.gd = gd

@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "splitmix64_uniform", "mode_phases", "uniform_points_2d",
-    "cylinder_cloud", "hex_cloud", "box_cloud", "clustered_layers",
+    "cylinder_cloud", "hex_cloud", "hex_cloud_z_edges", "box_cloud", "clustered_layers",
     "uniform_layers", "batch_realisations", "even_5smooth",
 ]
 
@@ -143,6 +143,12 @@ def _tanh_levels(z0: float, z1: float, n: int, zc: float, dz_min: float) -> np.n
     return edges(lo_b)
 
 
+def hex_cloud_z_edges(z0: float, z1: float, nz: int, dz_min: float) -> np.ndarray:
+    """Unjittered vertical cell edges of hex_cloud (nz cells on [z0, z1],
+    clustered about z = 0 with smallest cell dz_min)."""
+    return _tanh_levels(z0, z1, nz, 0.0, dz_min)
+
+
 def hex_cloud(seed: int, x0: float, y0: float, wx: float, wy: float, z0: float, z1: float,
               nx: int, ny: int, nz: int, dz_min: float, jitter: float = 0.1) -> tuple[np.ndarray, dict]:
     """Cell centres of a box mesh (uniform horizontally, sinh-clustered about
@@ -151,7 +157,7 @@ def hex_cloud(seed: int, x0: float, y0: float, wx: float, wy: float, z0: float, 
     ([3][n] float64 points, mesh dict with the unjittered edges)."""
     xe = x0 + wx * np.arange(nx + 1) / nx
     ye = y0 + wy * np.arange(ny + 1) / ny
-    ze = _tanh_levels(z0, z1, nz, 0.0, dz_min)
+    ze = hex_cloud_z_edges(z0, z1, nz, dz_min)
     xc, yc, zc = (0.5 * (e[1:] + e[:-1]) for e in (xe, ye, ze))
     dzc = np.diff(ze)
     n = nx * ny * nz

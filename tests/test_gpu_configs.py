@@ -1,0 +1,199 @@
+"""GPU parity of whole configurations against the FP64 oracle, through the
+C ABI, with both error measures of the parity bar (relative L2 over all
+outputs, and max-abs error over the largest reference magnitude):
+
+* the 2D regular wave: Stokes-2 start, ka = 0.1, kh = 2, 256 modes over four
+  wavelengths, M = 3, FP64, 128 RK4 steps of T/64; then the fold to 64 nodes
+  x 32 layers on [-h, 0] (every field) and the interpolation to 10,000
+  points uniform in x in [0, 4 lambda), z in [-h, 0) (seed 0); the oracle
+  runs here;
+* the 512 x 256, M = 3 irregular sea after 128 steps (two peak periods),
+  and all 11 fields at 2000 cell centres of its cylinder O-mesh;
+* the 1024^2, M = 5 steep sea after 16 steps, and all 11 fields at 2000
+  cell centres of its 20M-point hex mesh.
+For the two 3D seas the oracle's reference was written once by the scripts
+beside the stored files in tests/golden (they call only the oracle); the
+GPU runs from the oracle's own initial spectra.  The steep sea's mesh
+reaches 0.2 lambda_p above the mean level, where the continued fields are
+sums of terms grown by e^{kz} (up to 1e10 at its largest wavenumber): there
+every point's error is taken relative to the larger of its value and the
+field's RMS over the plane at its height (single-precision transforms are
+accurate relative to that size), and both C18 measures over the points up
+to 2 Hs.
+
+Bars: state and fields 1e-5 (FP32 transforms of the nonlinear remainder,
+FP64 state); in FP64 the 2D state to 1e-11 and its FP32 outputs to 1e-6."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import c18
+import synth
+from oracle import Grid, hos, sea
+from oracle import reconstruct as rc
+
+pytestmark = pytest.mark.gpu
+LAM = 2 * math.pi
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _check(got, ref, tol, what):
+    l2, mx = c18.rel_l2(got, ref), c18.max_ratio(got, ref)
+    assert l2 < tol and mx < tol, (what, l2, mx)
+    return l2, mx
+
+
+def test_regular_wave_end_to_end(gpu_lib):
+    import torch
+    from paper_2005_12716_amd import lib
+    h0 = 2.0  # k = 1: depth kh = 2
+    d = lib.hos_desc(2, 256, 1, 4 * LAM, 1.0, h0, order_m=3, precision=1)
+    eh, ph = lib.sea_spectrum(d, kind=1, mode=4, ka=0.1)
+    d.dt = 2 * math.pi / math.sqrt(math.tanh(h0)) / 64
+    h = lib.Hos(d, eh, ph)
+    h.step(128)
+    e, p, _ = h.state()
+    g = Grid(nx=256, ny=1, lx=4 * LAM, ly=1.0, depth=h0, order_m=3)
+    er, pr = hos.run(g, eh, ph, d.dt, 128)
+    _check(e, er, 1e-11, "eta")
+    _check(p, pr, 1e-11, "phis")
+    A = hos.mean_level_modes(g, er, pr)
+    At, eth = hos.mean_level_modes_t(g, er, pr)
+    # value grid: 256 modes folded to 64 nodes, 32 layers z_l = -h + l h / 31
+    zl = -h0 + np.arange(32) * h0 / 31
+    gd = lib.grid_desc(64, 1, zl)
+    out = h.eval_grid(gd, lib.ALL_FIELDS).cpu().numpy().astype(np.float64)
+    ref = rc.eval_grid(g, A, At, er, eth, 64, 1, zl, list(range(11)))
+    vol = out[: 9 * 32 * 64].reshape(9, 32, 1, 64)
+    srf = out[9 * 32 * 64:].reshape(2, 1, 64)
+    for f in range(9):
+        if f in (rc.V, rc.V_T):
+            assert np.abs(vol[f]).max() == 0
+            continue
+        _check(vol[f], ref[f], 1e-6, ("grid", f))
+    for k, f in enumerate((rc.ETA, rc.ETA_T)):
+        _check(srf[k], ref[f], 1e-6, ("grid", f))
+    # 10,000 points of the lower half-domain (the water below the still level)
+    pts = synth.uniform_points_2d(0, 10000, 0.0, 4 * LAM, -h0, 0.0)
+    cells = h.bind(gd, torch.tensor(pts, device="cuda"))
+    got, nbad = cells.interp(lib.ALL_FIELDS)
+    assert nbad == 0
+    got = got.cpu().numpy().astype(np.float64)
+    coef = rc.eval_grid(g, A, At, er, eth, 64, 1, zl, [f for f in range(11) if f != rc.P], prefilter=True)
+    vr, nb = rc.interp_points(g, coef, zl, 64, 1, None, pts, list(range(11)))
+    assert nb == 0
+    for f in range(11):
+        if f in (rc.V, rc.V_T):
+            assert np.abs(got[f]).max() == 0
+            continue
+        _check(got[f], vr[f], 1e-6, ("points", f))
+    cells.close()
+    h.close()
+
+
+def _stored(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.fail(f"missing reference {path}: run the script beside it")
+    return np.load(path)
+
+
+def _state_vs_stored(z, e, p):
+    """Block of stored modes compared mode by mode; the rest by its norm."""
+    rows, cols = z["block_rows"], z["block_cols"]
+    out = {}
+    for name, got in (("eta", e), ("phis", p)):
+        blk = got[np.ix_(rows, cols)]
+        ref = z[f"{name}_block"]
+        full = float(z[f"{name}_norm"])
+        mask = np.ones(got.shape, dtype=bool)
+        mask[np.ix_(rows, cols)] = False
+        l2 = float(np.linalg.norm(blk - ref)) / full
+        mx = float(np.abs(blk - ref).max() / np.abs(ref).max())
+        rest = abs(float(np.linalg.norm(got[mask])) - float(z[f"{name}_outside_norm"])) / full
+        out[name] = (l2, mx, rest)
+    return out
+
+
+def _points_vs_stored(lib, h, gd, z, tol, zmax=None):
+    """All 11 fields at the stored points.  Without plane RMS values: both
+    C18 measures over all points.  With them (the steep sea, whose mesh
+    reaches far above the crests): every point's error relative to the
+    larger of its value and the field's RMS over the plane at its height,
+    and both C18 measures over the points at or below zmax."""
+    import torch
+    cells = h.bind(gd, torch.tensor(np.ascontiguousarray(z["points"]), device="cuda"))
+    got, nbad = cells.interp(lib.ALL_FIELDS)
+    assert nbad == 0
+    got = got.cpu().numpy().astype(np.float64)
+    ref = z["values"]
+    errs = {}
+    if "plane_rms" not in z:
+        for f in range(11):
+            errs[rc.FIELD_NAMES[f]] = _check(got[f], ref[f], tol, ("points", f))
+    else:
+        low = z["points"][2] <= zmax
+        for f in range(11):
+            scale = np.maximum(np.abs(ref[f]), z["plane_rms"][f])
+            local = float(np.max(np.abs(got[f] - ref[f]) / scale))
+            assert local < tol, (rc.FIELD_NAMES[f], "per point", local)
+            l2, mx = _check(got[f][low], ref[f][low], tol, ("points below zmax", f))
+            errs[rc.FIELD_NAMES[f]] = (local, l2, mx, c18.rel_l2(got[f], ref[f]), c18.max_ratio(got[f], ref[f]))
+    cells.close()
+    return errs
+
+
+def test_cylinder_sea_128_steps(gpu_lib):
+    from paper_2005_12716_amd import lib
+    z = _stored("cylinder_sea_128steps.npz")
+    nx, ny = 512, 256
+    g = Grid(nx=nx, ny=ny, lx=40 * LAM, ly=20 * LAM, depth=-1.0, order_m=3)
+    e0, p0 = sea.jonswap(g, 0.02 * LAM, 1.0, 3.3, synth.mode_phases(1, ny, nx // 2 + 1), "cos2")
+    d = lib.hos_desc(3, nx, ny, g.lx, g.ly, -1.0, order_m=3, dt=LAM / 64)
+    h = lib.Hos(d, e0, p0)
+    h.step(128)
+    e, p, _ = h.state()
+    st = _state_vs_stored(z, e, p)
+    for name, (l2, mx, rest) in st.items():
+        assert l2 < 1e-5 and mx < 1e-5 and rest < 1e-5, (name, l2, mx, rest)
+    pts = synth.cylinder_cloud(g.lx, g.ly, 0.02 * LAM)
+    gx, gy = 4 * nx, 4 * ny
+    dx = g.lx / gx
+    ix0 = int(math.floor((g.lx / 2 - 2.05 * LAM) / dx)) - 2
+    wx = int(math.ceil(4.1 * LAM / dx)) + 6
+    iy0 = int(math.floor((g.ly / 2 - 2.05 * LAM) / dx)) - 2
+    zl = synth.clustered_layers(pts[2].min() - 1e-9, pts[2].max() + 1e-9, 48, 0.02 * LAM / 16)
+    errs = _points_vs_stored(lib, h, lib.grid_desc(gx, gy, zl, (ix0, iy0, wx, wx)), z, 1e-5)
+    print("state", st, "fields", errs)
+    h.close()
+
+
+def test_steep_sea_16_steps(gpu_lib):
+    from paper_2005_12716_amd import lib
+    z = _stored("steep_sea_16steps.npz")
+    n = 1024
+    L = 40 * LAM
+    hs = 0.04 * LAM
+    g = Grid(nx=n, ny=n, lx=L, ly=L, depth=-1.0, order_m=5)
+    e0, p0 = sea.jonswap(g, hs, 1.0, 5.0, synth.mode_phases(5, n, n // 2 + 1), "cos2")
+    d = lib.hos_desc(3, n, n, L, L, -1.0, order_m=5, dt=LAM / 64)
+    h = lib.Hos(d, e0, p0)
+    h.step(16)
+    e, p, _ = h.state()
+    st = _state_vs_stored(z, e, p)
+    for name, (l2, mx, rest) in st.items():
+        assert l2 < 1e-5 and mx < 1e-5 and rest < 1e-5, (name, l2, mx, rest)
+    x0, y0, wx, wy = L / 2 - 4 * LAM, L / 2 - 2 * LAM, 8 * LAM, 4 * LAM
+    gx = 4 * n
+    dx = L / gx
+    win = (int(math.floor(x0 / dx)) - 2, int(math.floor(y0 / dx)) - 2, int(math.ceil(wx / dx)) + 6,
+           int(math.ceil(wy / dx)) + 6)
+    ze = synth.hex_cloud_z_edges(-0.5 * LAM, 0.2 * LAM, 160, hs / 16)
+    zl = synth.clustered_layers(ze[0] - 1e-9, ze[-1] + 1e-9, 64, hs / 16)
+    # per point relative to the plane RMS everywhere; both C18 measures over
+    # the water and the crest zone (z <= 2 Hs)
+    errs = _points_vs_stored(lib, h, lib.grid_desc(gx, gx, zl, win), z, 1e-5, zmax=2 * hs)
+    print("state", st, "fields", errs)
+    h.close()
