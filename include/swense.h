@@ -438,6 +438,14 @@ int swense_profile_bytes(swense_hos* h, int kernel, double* bytes);
  * read once.  0 for the other classes. */
 int swense_profile_transform_bytes(swense_hos* h, int kernel, double* bytes);
 
+/* ---- host self-check ----------------------------------------------------- */
+
+/* Host-only consistency check of launch geometry (no device work): for every
+ * even mode count up to max_nx, the DFT coefficient pass of the evaluation
+ * reads no row of its basis operand past the rows allocated per node tile.
+ * Returns 0, or the first mode count that fails. */
+int swense_selfcheck_launch_geometry(int max_nx);
+
 /* ---- lifetime ---------------------------------------------------------- */
 void swense_hos_destroy(swense_hos* h);
 void swense_cells_destroy(swense_cells* c);

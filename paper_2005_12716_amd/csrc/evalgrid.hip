@@ -507,6 +507,23 @@ constexpr int DX_SA = DX_KC + 4, DX_SB = DX_T + 16, DX_SS = DX_T + 4;
 // evaluation instead of once per workgroup.  basis: [ntx][dft_rows(hx)][DX_T].
 __host__ __device__ constexpr int dft_rows(int hx) { return (2 * hx + DX_KC - 1) / DX_KC * DX_KC; }
 
+// Host mirror of the basis rows k_xcoef_dft reads for hx kept x modes: chunk
+// k0 (a multiple of DX_KC below 2 hx) reads rows 2 p0 + brow, p0 = k0 / 2,
+// brow < DX_KC, and prefetches the next chunk the same way.  Returns the
+// largest row read; it must stay below dft_rows(hx), the rows per node tile
+// of the basis (a basis sized by the unpadded 2 hx rows once let the last
+// chunk read past the allocation).
+int dft_last_row_read(int hx) {
+  const int Kr = 2 * hx;
+  int last = -1;
+  for (int k0 = 0; k0 < Kr; k0 += DX_KC) {
+    const int p0 = k0 >> 1;
+    last = std::max(last, 2 * p0 + DX_KC - 1);
+    if (k0 + DX_KC < Kr) last = std::max(last, 2 * (p0 + DX_KC / 2) + DX_KC - 1);
+  }
+  return last;
+}
+
 __global__ void __launch_bounds__(256) k_dft_basis(const cf* __restrict__ tw, int gx, int ix0, int hx, int ntx,
                                                    float* __restrict__ basis) {
   const int Kp = dft_rows(hx);
@@ -890,6 +907,7 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
       if (nitems <= DX_MAXMT * 16 && lds_dft <= 160 * 1024) {
         const int ntx = (A.wx + DX_T - 1) / DX_T;
         const int hx = h->G.nx / 2;
+        SW_REQUIRE(dft_last_row_read(hx) < dft_rows(hx), "DFT basis rows do not cover the rows the pass reads");
         const size_t nb = (size_t)ntx * dft_rows(hx) * DX_T;
         SW_REQUIRE(nb < (1ull << 31), "coefficient window too wide");
         float* basis;
@@ -996,6 +1014,16 @@ size_t grid_floats(const swense_hos* h, const swense_grid_desc* gd, unsigned mas
 }  // namespace
 
 void check_grid_desc(const swense_hos* h, const swense_grid_desc* gd) { check_grid(h, gd); }
+
+extern "C" int swense_selfcheck_launch_geometry(int max_nx) {
+  // host-only: for every even mode count up to max_nx, the DFT coefficient
+  // pass reads no basis row past the ones allocated per node tile
+  for (int nx = 2; nx <= max_nx; nx += 2) {
+    const int hx = nx / 2;
+    if (dft_last_row_read(hx) >= dft_rows(hx)) return nx;
+  }
+  return 0;
+}
 
 void eval_scratch_need(swense_hos* h, const swense_grid_desc* gd, unsigned cm, int skel_r, size_t* inter,
                        size_t* basis) {

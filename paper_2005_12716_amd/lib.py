@@ -122,6 +122,7 @@ def load():
         "swense_profile_read": (C.c_int, [vp, C.c_int, dp, C.POINTER(C.c_longlong)]),
         "swense_profile_bytes": (C.c_int, [vp, C.c_int, dp]),
         "swense_profile_transform_bytes": (C.c_int, [vp, C.c_int, dp]),
+        "swense_selfcheck_launch_geometry": (C.c_int, [C.c_int]),
         "swense_batch_create": (C.c_int, [C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_uint), C.POINTER(vp),
                                           C.c_int, C.c_int, vp, C.POINTER(vp)]),
         "swense_batch_run": (C.c_int, [vp]),
@@ -162,7 +163,8 @@ EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swens
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
             "swense_cells_bind", "swense_interp_cells", "swense_interp_cells_noalloc", "swense_eval_points_direct", "swense_hos_snapshot", "swense_hos_set_eval_time", "swense_stream_solve", "swense_stream_eval", "swense_cells_alpha", "swense_cells_pstar", "swense_cells_relax",
             "swense_interp_divergence", "swense_interp_step", "swense_fv_divergence", "swense_profile_enable",
-            "swense_profile_read", "swense_profile_bytes", "swense_profile_transform_bytes", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
+            "swense_profile_read", "swense_profile_bytes", "swense_profile_transform_bytes",
+            "swense_selfcheck_launch_geometry", "swense_batch_create", "swense_batch_run", "swense_batch_autotune",
             "swense_batch_last_error", "swense_batch_destroy", "swense_hos_destroy",
             "swense_cells_destroy", "swense_fno_param_count", "swense_fno_create", "swense_fno_forward",
             "swense_fno_loss", "swense_fno_backward", "swense_fno_train_step", "swense_fno_get", "swense_fno_set",

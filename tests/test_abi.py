@@ -160,3 +160,11 @@ def test_hos_workspace_query_and_too_small_workspace():
     bad = lib.hos_desc(3, 63, 32, 1.0, 1.0, -1.0)
     with pytest.raises(lib.SwenseError):
         lib.hos_workspace_bytes(bad)
+
+
+def test_dft_basis_covers_the_rows_read():
+    """Host-only check of the evaluation's DFT coefficient pass: for every
+    even mode count up to 8192, the rows its chunks read stay inside the
+    basis rows allocated per node tile."""
+    from paper_2005_12716_amd import lib
+    assert lib.load().swense_selfcheck_launch_geometry(8192) == 0
