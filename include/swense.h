@@ -198,8 +198,11 @@ typedef struct swense_stream_desc {
  * host.  sol (host, 2N + 4 doubles) receives eta at the N + 1 surface points
  * X_m = m L / (2N) from crest to trough (above the mean level), B_1..B_N, the
  * phase speed c, the volume flux Q and the Bernoulli constant R (moving frame).
- * Returns SWENSE_EINVAL for bad sizes and SWENSE_EUNSTABLE if Newton's method
- * does not converge (e.g. a wave beyond breaking). */
+ * Any consistent units (SI or nondimensional): Newton's method runs on the
+ * system scaled to g = k = 1 and converges to residuals of ~1e-14 relative to
+ * each equation's terms.  Returns SWENSE_EINVAL for bad sizes and
+ * SWENSE_EUNSTABLE if Newton's method does not converge (e.g. a wave beyond
+ * breaking). */
 int swense_stream_solve(const swense_stream_desc* d, double* sol);
 
 /* Fields of `mask` at n points and time t for a solved wave travelling in +x

@@ -827,67 +827,116 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
   }
 }
 
-// Series stages of the x pass (the products -sum_j eta^j / j! g_j of one
-// order) on rows of 3Q points: each input pair is transformed by the whole
-// workgroup (the three sub-transforms on wavefronts 0-2, the radix-3
-// combine on every thread) in a single LDS buffer, so that a launch with one
-// to three pairs keeps the wavefronts busy and several workgroups share a
-// CU; per point only eta and the running sum are held.  The inputs are
-// folded in index order with the same arithmetic as the rounds kernel.
+// Rows of 3Q points transformed by the whole workgroup (the three
+// sub-transforms on wavefronts 0-2, the radix-3 combine on every thread) in a
+// single LDS buffer: an input pair (a, b) is transformed as a + i b, so that
+// the real part of the result is a's row and the imaginary part b's.  The
+// kept modes of the next pair are read into registers while the current pair
+// is transformed (the block barriers of the transform wait on LDS operations
+// only, so the loads stay in flight).
 template <typename R, int Q, int NT>
-__global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan plan) {
-  constexpr int Px = 3 * Q;
-  constexpr int PPT = Px / NT;               // points per thread
-  constexpr int KP = (Px / 2 + NT - 1) / NT;  // kept modes per thread (p < Px / 2)
-  extern __shared__ unsigned char smem[];
-  using C = cpx<R>;
-  C* buf = reinterpret_cast<C*>(smem);
-  const C* tw = reinterpret_cast<const C*>(plan.tw);
-  const int y = blockIdx.x;
-  const int hx = G.nx / 2;
-  const int tid = threadIdx.x;
-  __shared__ int s_code[kMaxXIn];
-  if (tid < A.nin) {
-    const XIn& f = A.in[tid];
-    s_code[tid] = f.role | (f.pw << 8);
-  }
-  R eta[PPT], w0[PPT];
-#pragma unroll
-  for (int j = 0; j < PPT; ++j) eta[j] = w0[j] = (R)0;
-  const int npairs = (A.nin + 1) / 2;
-  for (int pi = 0; pi < npairs; ++pi) {
-    const bool hasb = 2 * pi + 1 < A.nin;
-    const XIn& fa = A.in[2 * pi];
-    const XIn& fb = A.in[hasb ? 2 * pi + 1 : 2 * pi];
-    const C* ra = reinterpret_cast<const C*>(fa.src) + (size_t)y * G.nxh;
-    const C* rb = reinterpret_cast<const C*>(fb.src) + (size_t)y * G.nxh;
-    const int dxa = fa.dx, dxb = hasb ? fb.dx : 0;
-    C va[KP], vb[KP];
+struct Rows3 {
+  static constexpr int Px = 3 * Q;
+  static constexpr int PPT = Px / NT;               // points per thread
+  static constexpr int KP = (Px / 2 + NT - 1) / NT;  // kept modes per thread (p < Px / 2)
+  cpx<R> va[KP], vb[KP];
+
+  __device__ __forceinline__ void load(const XArgs& A, const Geom& G, int y, int ia, int ib) {
+    const int hx = G.nx / 2;
+    const cpx<R>* ra = reinterpret_cast<const cpx<R>*>(A.in[ia].src) + (size_t)y * G.nxh;
+    const cpx<R>* rb = reinterpret_cast<const cpx<R>*>(A.in[ib < 0 ? ia : ib].src) + (size_t)y * G.nxh;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int p = tid + NT * k;
+      const int p = (int)threadIdx.x + NT * k;
       va[k] = vb[k] = mk((R)0, (R)0);
       if (p < hx) {
         va[k] = ra[p];
-        if (hasb) vb[k] = rb[p];
+        if (ib >= 0) vb[k] = rb[p];
       }
     }
+  }
+
+  // Writes the held pair into buf (the caller has passed a barrier since
+  // buf was last read).
+  __device__ __forceinline__ void store(cpx<R>* buf, const XArgs& A, const Geom& G, int ia, int ib) const {
+    const int hx = G.nx / 2;
+    const int dxa = A.in[ia].dx, dxb = ib >= 0 ? A.in[ib].dx : 0;
 #pragma unroll
     for (int t = 0; t < PPT; ++t) {
-      const int s = tid + NT * t;
+      const int s = (int)threadIdx.x + NT * t;
       if (s >= hx && s <= Px - hx) buf[b3_in<Q>(s)] = mk((R)0, (R)0);
     }
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      const int p = tid + NT * k;
+      const int p = (int)threadIdx.x + NT * k;
       if (p < hx) {
-        C a = va[k], b = vb[k];
+        cpx<R> a = va[k], b = vb[k];
         if (dxa) a = times_ikx<R>(a, p, G);
         if (dxb) b = times_ikx<R>(b, p, G);
         buf[b3_in<Q>(p)] = mk(a.x - b.y, a.y + b.x);                 // a + i b
         if (p > 0) buf[b3_in<Q>(Px - p)] = mk(a.x + b.y, b.x - a.y);  // conj(a) + i conj(b)
       }
     }
+  }
+};
+
+// Forward transform of the per-point results already in buf (real part o0,
+// imaginary part o1) and the kept modes of the two real rows to out0/out1.
+template <typename R, int Q, int NT>
+__device__ __forceinline__ void rows3_out(cpx<R>* buf, const cpx<R>* tw, const XArgs& A, const Geom& G, int y) {
+  constexpr int Px = 3 * Q;
+  block3_fft<R, Q, NT>(buf, tw, -1);
+  const int hx = G.nx / 2;
+  const R sc = (R)(0.5 / (double)Px);
+  cpx<R>* d0 = reinterpret_cast<cpx<R>*>(A.out0);
+  cpx<R>* d1 = reinterpret_cast<cpx<R>*>(A.out1);
+  for (int p = threadIdx.x; p < G.nxh; p += NT) {
+    cpx<R> o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
+    if (p < hx) {
+      cpx<R> zp = buf[b3_out<Q>(p)];
+      cpx<R> zm = conjg(buf[b3_out<Q>((Px - p) % Px)]);
+      cpx<R> sum = zp + zm, t = zp - zm;
+      o0 = cscale(sum, sc);
+      o1 = mk(t.y * sc, -t.x * sc);
+    }
+    d0[(size_t)y * G.nxh + p] = o0;
+    if (d1) d1[(size_t)y * G.nxh + p] = o1;
+  }
+}
+
+// Series stages of the x pass on rows of 3Q points: the product
+// -sum_j eta^j / j! g_j of one order, or (FT) the product
+// phis_t - [M >= 2] eta_t sum_j eta^j / j! g_j that the time derivative of
+// the mean-level modes takes.  Per point only eta, the running sum and (FT)
+// eta_t and phis_t are held; the inputs are folded in index order with the
+// arithmetic of the rounds kernel.
+template <typename R, int Q, int NT, bool FT>
+__global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan plan) {
+  using Rw = Rows3<R, Q, NT>;
+  constexpr int PPT = Rw::PPT;
+  extern __shared__ unsigned char smem[];
+  using C = cpx<R>;
+  C* buf = reinterpret_cast<C*>(smem);
+  const C* tw = reinterpret_cast<const C*>(plan.tw);
+  const int y = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ int s_code[kMaxXIn];
+  if (tid < A.nin) {
+    const XIn& f = A.in[tid];
+    s_code[tid] = f.role | (f.pw << 8);
+  }
+  R eta[PPT], w0[PPT], et[FT ? PPT : 1], pt[FT ? PPT : 1];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) eta[j] = w0[j] = (R)0;
+#pragma unroll
+  for (int j = 0; j < (FT ? PPT : 1); ++j) et[j] = pt[j] = (R)0;
+  const int npairs = (A.nin + 1) / 2;
+  Rw rows;
+  rows.load(A, G, y, 0, 1 < A.nin ? 1 : -1);
+  for (int pi = 0; pi < npairs; ++pi) {
+    const int ib = 2 * pi + 1 < A.nin ? 2 * pi + 1 : -1;
+    rows.store(buf, A, G, 2 * pi, ib);
+    if (pi + 1 < npairs) rows.load(A, G, y, 2 * pi + 2, 2 * pi + 3 < A.nin ? 2 * pi + 3 : -1);
     block3_fft<R, Q, NT>(buf, tw, +1);
     const int i1 = min(A.nin, 2 * pi + 2);
     for (int i = 2 * pi; i < i1; ++i) {
@@ -906,156 +955,125 @@ __global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan pla
           for (int k = 1; k <= kMaxM; ++k)
             if (k <= pw) c *= eta[j] / (R)k;
           w0[j] += c * v;
+        } else if (FT && role == XR_ETAT) {
+          et[j] = v;
+        } else if (FT && role == XR_PHIT) {
+          pt[j] = v;
         }
       }
     }
     __syncthreads();  // the buffer is refilled by the next pair
   }
 #pragma unroll
-  for (int j = 0; j < PPT; ++j) buf[b3_in<Q>(tid + NT * j)] = mk(-w0[j], (R)0);
-  block3_fft<R, Q, NT>(buf, tw, -1);
-  const R sc = (R)(0.5 / (double)Px);
-  C* d0 = reinterpret_cast<C*>(A.out0);
-  C* d1 = reinterpret_cast<C*>(A.out1);
-  for (int p = tid; p < G.nxh; p += NT) {
-    C o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
-    if (p < hx) {
-      C zp = buf[b3_out<Q>(p)];
-      C zm = conjg(buf[b3_out<Q>((Px - p) % Px)]);
-      C sum = zp + zm, t = zp - zm;
-      o0 = cscale(sum, sc);
-      o1 = mk(t.y * sc, -t.x * sc);
+  for (int j = 0; j < PPT; ++j) {
+    R o = -w0[j];
+    if constexpr (FT) {
+      o = pt[j];
+      if (A.M >= 2) o -= w0[j] * et[j];
     }
-    d0[(size_t)y * G.nxh + p] = o0;
-    if (d1) d1[(size_t)y * G.nxh + p] = o1;
+    buf[b3_in<Q>(tid + NT * j)] = mk(o, (R)0);
   }
+  rows3_out<R, Q, NT>(buf, tw, A, G, y);
 }
 
-// Final stage of the x pass on rows of 3Q points, in the same form: each
-// input pair transformed by the workgroup, the order-M products (eta,
-// |grad eta|^2, grad eta . grad phi, |grad phi|^2 and W_1 .. W_M, M <= MW)
-// held per point; same fold and output arithmetic as the rounds kernel.
+// Final stage of the x pass on rows of 3Q points, in the same form.  The
+// host orders the inputs as eta and the W terms first (A.ng of them), then
+// the gradient pairs (each XR_GRADPAIR followed by its partner).  Phase one
+// holds eta and W_1 .. W_M (M <= MW) per point; once the W are complete they
+// are folded into the two outputs and the two multipliers of |grad eta|^2,
+// so that phase two adds each gradient pair straight into the outputs:
+// o0 = sum_{m>1} W_m + |grad eta|^2 sum_{m<=M-2} W_m - grad eta . grad phi,
+// o1 = [W^2]_M / 2 - |grad phi|^2 / 2 + |grad eta|^2 [W^2]_{M-2} / 2
+// (the order-M truncation of the rounds kernel, |grad eta|^2 and the dot
+// product summed per gradient direction).
 template <typename R, int Q, int MW, int NT>
-__global__ void __launch_bounds__(NT, NT == 256 ? 2 : 1) k_xpass_final3(XArgs A, Geom G, WPlan plan) {
-  constexpr int Px = 3 * Q;
-  constexpr int PPT = Px / NT;
-  constexpr int KP = (Px / 2 + NT - 1) / NT;
+__global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan plan) {
+  using Rw = Rows3<R, Q, NT>;
+  constexpr int PPT = Rw::PPT;
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
   C* buf = reinterpret_cast<C*>(smem);
   const C* tw = reinterpret_cast<const C*>(plan.tw);
   const int y = blockIdx.x;
-  const int hx = G.nx / 2;
   const int tid = threadIdx.x;
+  const int M = A.M, ng = A.ng;
   __shared__ int s_code[kMaxXIn];
   if (tid < A.nin) {
     const XIn& f = A.in[tid];
     s_code[tid] = f.role | (f.pw << 8) | (f.wi << 16);
   }
-  R eta[PPT], ge2[PPT], dot[PPT], gp2[PPT], W[PPT][MW];
+  R o0[PPT], o1[PPT], c2[PPT], s2[PPT];
+  Rw rows;
+  rows.load(A, G, y, 0, 1 < ng ? 1 : -1);
+  {
+    R eta[PPT], W[PPT][MW];
 #pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    eta[j] = ge2[j] = dot[j] = gp2[j] = (R)0;
+    for (int j = 0; j < PPT; ++j) {
+      eta[j] = (R)0;
 #pragma unroll
-    for (int m = 0; m < MW; ++m) W[j][m] = (R)0;
-  }
-  const int npairs = (A.nin + 1) / 2;
-  for (int pi = 0; pi < npairs; ++pi) {
-    const bool hasb = 2 * pi + 1 < A.nin;
-    const XIn& fa = A.in[2 * pi];
-    const XIn& fb = A.in[hasb ? 2 * pi + 1 : 2 * pi];
-    const C* ra = reinterpret_cast<const C*>(fa.src) + (size_t)y * G.nxh;
-    const C* rb = reinterpret_cast<const C*>(fb.src) + (size_t)y * G.nxh;
-    const int dxa = fa.dx, dxb = hasb ? fb.dx : 0;
-    C va[KP], vb[KP];
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const int p = tid + NT * k;
-      va[k] = vb[k] = mk((R)0, (R)0);
-      if (p < hx) {
-        va[k] = ra[p];
-        if (hasb) vb[k] = rb[p];
-      }
+      for (int m = 0; m < MW; ++m) W[j][m] = (R)0;
     }
+    const int np1 = (ng + 1) / 2;
+    for (int pi = 0; pi < np1; ++pi) {
+      rows.store(buf, A, G, 2 * pi, 2 * pi + 1 < ng ? 2 * pi + 1 : -1);
+      if (pi + 1 < np1) rows.load(A, G, y, 2 * pi + 2, 2 * pi + 3 < ng ? 2 * pi + 3 : -1);
+      else if (ng < A.nin) rows.load(A, G, y, ng, ng + 1);
+      block3_fft<R, Q, NT>(buf, tw, +1);
+      const int i1 = min(ng, 2 * pi + 2);
+      for (int i = 2 * pi; i < i1; ++i) {
+        const int code = s_code[i];
+        const int role = code & 255, pw = (code >> 8) & 255, wi = code >> 16;
+        const bool hi = i & 1;
 #pragma unroll
-    for (int t = 0; t < PPT; ++t) {
-      const int s = tid + NT * t;
-      if (s >= hx && s <= Px - hx) buf[b3_in<Q>(s)] = mk((R)0, (R)0);
-    }
+        for (int j = 0; j < PPT; ++j) {
+          const C zx = buf[b3_out<Q>(tid + NT * j)];
+          const R v = hi ? zx.y : zx.x;
+          if (role == XR_ETA) {
+            eta[j] = v;
+          } else if (role == XR_G) {
+            R c = (R)1;
 #pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const int p = tid + NT * k;
-      if (p < hx) {
-        C a = va[k], b = vb[k];
-        if (dxa) a = times_ikx<R>(a, p, G);
-        if (dxb) b = times_ikx<R>(b, p, G);
-        buf[b3_in<Q>(p)] = mk(a.x - b.y, a.y + b.x);
-        if (p > 0) buf[b3_in<Q>(Px - p)] = mk(a.x + b.y, b.x - a.y);
-      }
-    }
-    block3_fft<R, Q, NT>(buf, tw, +1);
-    const int i1 = min(A.nin, 2 * pi + 2);
-    for (int i = 2 * pi; i < i1; ++i) {
-      const int code = s_code[i];
-      const int role = code & 255, pw = (code >> 8) & 255, wi = code >> 16;
-      const bool hi = i & 1;
+            for (int k = 1; k <= MW; ++k)
+              if (k <= pw) c *= eta[j] / (R)k;
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        const C zx = buf[b3_out<Q>(tid + NT * j)];
-        const R v = hi ? zx.y : zx.x;
-        if (role == XR_ETA) {
-          eta[j] = v;
-        } else if (role == XR_GRADPAIR) {
-          const R b = zx.y;
-          ge2[j] += v * v;
-          dot[j] += v * b;
-          gp2[j] += b * b;
-        } else if (role == XR_G) {
-          R c = (R)1;
-#pragma unroll
-          for (int k = 1; k <= MW; ++k)
-            if (k <= pw) c *= eta[j] / (R)k;
-#pragma unroll
-          for (int m = 0; m < MW; ++m)
-            if (m == wi) W[j][m] += c * v;
+            for (int m = 0; m < MW; ++m)
+              if (m == wi) W[j][m] += c * v;
+          }
         }
       }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      R wm = (R)0, wm2 = (R)0;
+#pragma unroll
+      for (int m = 0; m < MW; ++m) {
+        if (m < M) wm += W[j][m];
+        if (m < M - 2) wm2 += W[j][m];
+      }
+      o0[j] = wm - W[j][0];
+      o1[j] = (R)0.5 * w2sum_n<MW>(W[j], M);
+      c2[j] = M >= 3 ? wm2 : (R)0;
+      s2[j] = M >= 4 ? (R)0.5 * w2sum_n<MW>(W[j], M - 2) : (R)0;
+    }
+  }
+  const R dm = M >= 2 ? (R)1 : (R)0;
+  for (int i = ng; i < A.nin; i += 2) {
+    rows.store(buf, A, G, i, i + 1);
+    if (i + 2 < A.nin) rows.load(A, G, y, i + 2, i + 3);
+    block3_fft<R, Q, NT>(buf, tw, +1);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const C zx = buf[b3_out<Q>(tid + NT * j)];
+      const R ge = zx.x * zx.x;
+      o0[j] += ge * c2[j] - dm * (zx.x * zx.y);
+      o1[j] += ge * s2[j] - dm * (R)0.5 * (zx.y * zx.y);
     }
     __syncthreads();
   }
-  const int M = A.M;
 #pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    R wm = (R)0, wm2 = (R)0;
-#pragma unroll
-    for (int m = 0; m < MW; ++m) {
-      if (m < M) wm += W[j][m];
-      if (m < M - 2) wm2 += W[j][m];
-    }
-    R o0 = wm - W[j][0];
-    if (M >= 3) o0 += ge2[j] * wm2;
-    if (M >= 2) o0 -= dot[j];
-    R o1 = (R)0.5 * w2sum_n<MW>(W[j], M);
-    if (M >= 2) o1 -= (R)0.5 * gp2[j];
-    if (M >= 4) o1 += (R)0.5 * ge2[j] * w2sum_n<MW>(W[j], M - 2);
-    buf[b3_in<Q>(tid + NT * j)] = mk(o0, o1);
-  }
-  block3_fft<R, Q, NT>(buf, tw, -1);
-  const R sc = (R)(0.5 / (double)Px);
-  C* d0 = reinterpret_cast<C*>(A.out0);
-  C* d1 = reinterpret_cast<C*>(A.out1);
-  for (int p = tid; p < G.nxh; p += NT) {
-    C o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
-    if (p < hx) {
-      C zp = buf[b3_out<Q>(p)];
-      C zm = conjg(buf[b3_out<Q>((Px - p) % Px)]);
-      C sum = zp + zm, t = zp - zm;
-      o0 = cscale(sum, sc);
-      o1 = mk(t.y * sc, -t.x * sc);
-    }
-    d0[(size_t)y * G.nxh + p] = o0;
-    if (d1) d1[(size_t)y * G.nxh + p] = o1;
-  }
+  for (int j = 0; j < PPT; ++j) buf[b3_in<Q>(tid + NT * j)] = mk(o0[j], o1[j]);
+  rows3_out<R, Q, NT>(buf, tw, A, G, y);
 }
 
 // Physical rows <-> spectra on the mode grid (FP64, state in/out only).
@@ -1348,26 +1366,43 @@ void xpass_t(swense_hos* h, const XArgs& a) {
   // FP32 rows of 768, 1536 and 3072 points (three-way transforms): series
   // stages on the workgroup-transform kernel, the others in rounds (order <= 5)
   if constexpr (sizeof(R) == 4) {
-    bool series_ok = a.stage == XS_SERIES && h->G.nx <= Px && (Px == 768 || Px == 1536 || Px == 3072);
+    const bool ft = a.stage == XS_FTILDE;
+    bool series_ok = (a.stage == XS_SERIES || ft) && h->G.nx <= Px && (Px == 768 || Px == 1536 || Px == 3072);
     for (int i = 0; i < a.nin && series_ok; ++i)
-      series_ok = a.in[i].role == XR_ETA || (a.in[i].role == XR_G && a.in[i].wi == 0 && a.in[i].pw <= kMaxM);
+      series_ok = a.in[i].role == XR_ETA || (a.in[i].role == XR_G && a.in[i].wi == 0 && a.in[i].pw <= kMaxM) ||
+                  (ft && (a.in[i].role == XR_ETAT || a.in[i].role == XR_PHIT));
     bool final_ok = a.stage == XS_FINAL && pairs_ok && a.M <= 5 && h->G.nx <= Px && Px == 3072;
+    for (int i = 0; i < a.nin && final_ok; ++i)
+      final_ok = a.in[i].role == XR_ETA || a.in[i].role == XR_G || a.in[i].role == XR_GRADPAIR ||
+                 (a.in[i].role == XR_NONE && i > 0 && a.in[i - 1].role == XR_GRADPAIR);
     if (final_ok) {
+      // eta and the W terms first (their order kept), then the gradient pairs
+      XArgs b = a;
+      b.nin = 0;
+      for (int i = 0; i < a.nin; ++i)
+        if (a.in[i].role == XR_ETA || a.in[i].role == XR_G) b.in[b.nin++] = a.in[i];
+      b.ng = b.nin;
+      for (int i = 0; i < a.nin; ++i)
+        if (a.in[i].role == XR_GRADPAIR) {
+          b.in[b.nin++] = a.in[i];
+          b.in[b.nin++] = a.in[i + 1];
+        }
+      SW_REQUIRE(b.nin == a.nin && b.ng >= 1 && b.in[0].role == XR_ETA, "final-stage inputs out of order");
       const WPlan wp = make_wplan(h->plan_px);
-      // 256 threads (two workgroups per CU, 180 B per lane of spills) measured
-      // faster than 512 threads without spills (one workgroup per CU, five of
-      // eight wavefronts idle during the sub-transforms): 1.05 against 1.39 ms
       sw_launch(h, SWENSE_K_XPASS, &k_xpass_final3<R, 1024, 5, 256>, dim3(h->Py), dim3(256),
-                b3_len<1024>() * sizeof(cpx<R>), h->st, a, h->G, wp);
+                b3_len<1024>() * sizeof(cpx<R>), h->st, b, h->G, wp);
       return;
     }
     if (series_ok) {
       const WPlan wp = make_wplan(h->plan_px);
+#define L_S3(Q, FT) sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, Q, 256, FT>, dim3(h->Py), dim3(256), \
+                              b3_len<Q>() * sizeof(cpx<R>), h->st, a, h->G, wp)
       switch (Px) {
-        case 768: sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, 256, 256>, dim3(h->Py), dim3(256), b3_len<256>() * sizeof(cpx<R>), h->st, a, h->G, wp); break;
-        case 1536: sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, 512, 256>, dim3(h->Py), dim3(256), b3_len<512>() * sizeof(cpx<R>), h->st, a, h->G, wp); break;
-        default: sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, 1024, 256>, dim3(h->Py), dim3(256), b3_len<1024>() * sizeof(cpx<R>), h->st, a, h->G, wp); break;
+        case 768: if (ft) L_S3(256, true); else L_S3(256, false); break;
+        case 1536: if (ft) L_S3(512, true); else L_S3(512, false); break;
+        default: if (ft) L_S3(1024, true); else L_S3(1024, false); break;
       }
+#undef L_S3
       return;
     }
     if (pairs_ok && a.M <= 5 && h->G.nx <= Px && (Px == 768 || Px == 1536 || Px == 3072)) {

@@ -56,6 +56,7 @@ struct XArgs {
   int stage;
   int M;
   int nslots;
+  int ng;  // final stage on rows of 3Q points: leading inputs before the gradient pairs
   int s_eta, s_ge2, s_dot, s_gp2, s_etat, s_phit;
   int s_w[kMaxM];
   void* out0;

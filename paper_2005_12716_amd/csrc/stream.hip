@@ -8,7 +8,10 @@
 // (crest to trough) the surface is a streamline (psi = -Q) and Bernoulli holds
 // (|grad psi|^2/2 + g eta = R); the trapezoidal mean of eta is zero and
 // eta_0 - eta_N = H; no mean Eulerian current (c = ubar).  The height is
-// raised in four steps from the linear wave.
+// raised in four steps from the linear wave.  Newton's method runs on the
+// nondimensional system (lengths times k, velocities over sqrt(g/k), so
+// g = k = 1), whose residuals are O(1) for any wavelength, depth and g; the
+// stream-function rows are O(kd) there and their tolerance scales with it.
 //
 // Device: one thread per point sums the N modes (FP64): u, w, phi in the fixed
 // frame, eta from its cosine series through the surface points, time
@@ -135,37 +138,42 @@ int swense_stream_solve(const swense_stream_desc* d, double* sol) {
   if (N < 2 || N > kMaxStreamN || !(d->depth > 0.0) || !(d->height > 0.0) || !(d->wavelength > 0.0) ||
       !(d->g > 0.0))
     return SWENSE_EINVAL;
-  const double k = 2.0 * M_PI / d->wavelength, dep = d->depth, g = d->g;
-  const double th = std::tanh(k * dep), c0 = std::sqrt(g * th / k);
+  const double k = 2.0 * M_PI / d->wavelength;
+  const double vs = std::sqrt(d->g / k);  // velocity scale
+  const double dep = k * d->depth;        // nondimensional depth kd
+  const double th = std::tanh(dep), c0 = std::sqrt(th);
   const int nv = 2 * N + 4;
+  // residual tolerance per row: the stream-function rows carry terms of size
+  // ubar (Y + d) ~ kd, the others O(1)
+  std::vector<double> tol(nv, 1.0);
+  for (int m = 0; m <= N; ++m) tol[m] = std::fmax(1.0, dep);
+  auto converged = [&](const std::vector<double>& r, double eps) {
+    for (int i = 0; i < nv; ++i)
+      if (!(std::fabs(r[i]) < eps * tol[i])) return false;
+    return true;
+  };
   std::vector<double> v(nv, 0.0), r, rp, rm, A((size_t)nv * nv);
   const int steps = 4;
   for (int st = 1; st <= steps; ++st) {
-    const double H = d->height * st / steps;
+    const double H = k * d->height * st / steps;
     if (st == 1) {
       for (int m = 0; m <= N; ++m) v[m] = 0.5 * H * std::cos(m * M_PI / N);
-      v[N + 1] = 0.5 * k * H / std::sqrt(th);
+      v[N + 1] = 0.5 * H / std::sqrt(th);
       v[2 * N + 1] = c0;
       v[2 * N + 2] = c0 * dep;
       v[2 * N + 3] = 0.5 * c0 * c0;
     } else {
       for (int i = 0; i < 2 * N + 1; ++i) v[i] *= (double)st / (st - 1);
     }
-    bool done = false;
-    for (int it = 0; it < 60 && !done; ++it) {
-      stream_residual(v, N, k, dep, H, g, r);
-      double mx = 0.0;
-      for (double x : r) mx = std::fmax(mx, std::fabs(x));
-      if (mx < 1e-14) {
-        done = true;
-        break;
-      }
+    for (int it = 0; it < 60; ++it) {
+      stream_residual(v, N, 1.0, dep, H, 1.0, r);
+      if (converged(r, 1e-14)) break;
       for (int c = 0; c < nv; ++c) {
         const double h = 1e-7 * std::fmax(1.0, std::fabs(v[c])), keep = v[c];
         v[c] = keep + h;
-        stream_residual(v, N, k, dep, H, g, rp);
+        stream_residual(v, N, 1.0, dep, H, 1.0, rp);
         v[c] = keep - h;
-        stream_residual(v, N, k, dep, H, g, rm);
+        stream_residual(v, N, 1.0, dep, H, 1.0, rm);
         v[c] = keep;
         for (int i = 0; i < nv; ++i) A[(size_t)i * nv + c] = (rp[i] - rm[i]) / (2.0 * h);
       }
@@ -173,12 +181,16 @@ int swense_stream_solve(const swense_stream_desc* d, double* sol) {
       if (!dense_solve(A, b, nv)) return SWENSE_EUNSTABLE;
       for (int i = 0; i < nv; ++i) v[i] -= b[i];
     }
-    stream_residual(v, N, k, dep, H, g, r);
-    double mx = 0.0;
-    for (double x : r) mx = std::fmax(mx, std::fabs(x));
-    if (!(mx < 1e-12)) return SWENSE_EUNSTABLE;
+    stream_residual(v, N, 1.0, dep, H, 1.0, r);
+    if (!converged(r, 1e-12)) return SWENSE_EUNSTABLE;
   }
-  std::memcpy(sol, v.data(), nv * sizeof(double));
+  // back to the caller's units: eta / k, B as is, ubar and c in vs, Q in
+  // vs / k, R in vs^2
+  for (int m = 0; m <= N; ++m) sol[m] = v[m] / k;
+  for (int j = 1; j <= N; ++j) sol[N + j] = v[N + j];
+  sol[2 * N + 1] = v[2 * N + 1] * vs;
+  sol[2 * N + 2] = v[2 * N + 2] * vs / k;
+  sol[2 * N + 3] = v[2 * N + 3] * vs * vs;
   return SWENSE_OK;
 }
 

@@ -127,6 +127,35 @@ def test_stream_solve_matches_oracle(depth, height, n):
     assert np.abs(sol - v).max() < 1e-11 * max(1.0, np.abs(v).max())
 
 
+def _oracle_stream_si(depth, height, wavelength, n, g):
+    """The oracle's solve of the same wave in nondimensional form (g = k = 1)
+    and its unknowns taken back to the wave's own units by dimensional
+    analysis (lengths / k, velocities x sqrt(g/k))."""
+    from oracle import stream
+    k = 2 * math.pi / wavelength
+    vs = math.sqrt(g / k)
+    nd = stream.solve(k * depth, k * height, 2 * math.pi, n, g=1.0)
+    return {"eta": nd["eta"] / k, "B": nd["B"], "c": nd["c"] * vs, "Q": nd["Q"] * vs / k, "R": nd["R"] * vs * vs,
+            "k": k, "d": depth, "N": n, "g": g}
+
+
+@pytest.mark.parametrize("depth,height,wavelength,n", [(50.0, 4.0, 150.0, 16), (200.0, 8.0, 300.0, 16),
+                                                      (500.0, 30.0, 1000.0, 20), (20.0, 2.0, 100.0, 12)])
+def test_stream_solve_full_scale_si(depth, height, wavelength, n):
+    """Ocean-scale waves in SI units (g = 9.81): the host solve converges and
+    its unknowns equal the oracle's nondimensional solution taken back to SI
+    units, each block to 1e-11 of its own scale."""
+    from paper_2005_12716_amd import lib
+    _, sol = lib.stream_solve(depth, height, wavelength, n, g=9.81, rho=1025.0)
+    ref = _oracle_stream_si(depth, height, wavelength, n, 9.81)
+    N = n
+    assert np.abs(sol[: N + 1] - ref["eta"]).max() < 1e-11 * height
+    assert np.abs(sol[N + 1: 2 * N + 1] - ref["B"]).max() < 1e-11 * np.abs(ref["B"]).max()
+    for i, name in enumerate(["c", "Q", "R"]):
+        assert abs(sol[2 * N + 1 + i] - ref[name]) < 1e-11 * abs(ref[name]), name
+    assert sol[0] - sol[N] == pytest.approx(height, rel=1e-12)
+
+
 def test_stream_solve_rejects_bad_input():
     from paper_2005_12716_amd import lib
     with pytest.raises(lib.SwenseError):
