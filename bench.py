@@ -182,27 +182,31 @@ def run_surrogate(lib, torch, steps, train_trajectories=100, train_iters=1000, b
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del store
-    zero = lib.Fno(desc, T.zero_output(desc, vec0))
-    errs = T.one_call_errors(net, scales, range(3000, 3003), 5, 20.0, zero)
-    zero.close()
-    # network-only calls (no audits) and plain HOS on the same sea
-    h = T.sea_hos(256, 20.0, 3000)
-    sd = lib.surrogate_desc(tol=1e30, audit_every=1 << 30, cooldown=0, probation=0, **scales)
-    sur = lib.Surrogate(h, net, sd)
-    sur.advance(2)
-    torch.cuda.synchronize()
+    errs = T.one_call_errors(net, scales, range(3000, 3003), 5, 20.0)
+    # network-only calls and base-only calls (no audits), plain HOS on the same sea
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    sur.advance(steps)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_call = e0.elapsed_time(e1) / steps
+    ms_by = {}
+    for only in (False, True):
+        h = T.sea_hos(256, 20.0, 3000)
+        sd = lib.surrogate_desc(tol=1e30, audit_every=1 << 30, cooldown=0, probation=0, drift_tol=0.0,
+                                base_only=only, **scales)
+        sur = lib.Surrogate(h, net, sd)
+        sur.advance(2)
+        torch.cuda.synchronize()
+        e0.record()
+        sur.advance(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_by[only] = e0.elapsed_time(e1) / steps
+        sur.close()
+        h.close()
+    ms_call, ms_base = ms_by[False], ms_by[True]
+    h = T.sea_hos(256, 20.0, 3000)
     e0.record()
     h.step(10 * steps)
     e1.record()
     torch.cuda.synchronize()
     ms_hos = e0.elapsed_time(e1) / (10 * steps)
-    sur.close()
     h.close()
     x = torch.zeros((8, 4, 256, 256), dtype=torch.float32, device="cuda")
     y = torch.empty((8, 2, 256, 256), dtype=torch.float32, device="cuda")
@@ -214,7 +218,11 @@ def run_surrogate(lib, torch, steps, train_trajectories=100, train_iters=1000, b
     torch.cuda.synchronize()
     ms_fwd8 = e0.elapsed_time(e1) / steps
     roll = T.rollout(net, scales, range(3000, 3003), 20, 20.0, tol=1e-3, audit_every=4, cooldown=4)
+    roll_base = T.rollout(net, scales, range(3000, 3003), 20, 20.0, tol=1e-3, audit_every=4, cooldown=4,
+                          base_only=True)
     net.close()
+    keys = ("seed", "calls", "surrogate_calls", "hos_calls", "bound_calls", "audits", "fallbacks", "max_audit_err",
+            "drift_est", "offline_err", "effective_steps_per_s")
     return {
         "network": {"n": 256, "channels": 64, "layers": 8, "p_modes": 32, "q_modes": 31, "hidden": 128,
                     "in_channels": 4, "params": int(vec0.size)},
@@ -228,13 +236,16 @@ def run_surrogate(lib, torch, steps, train_trajectories=100, train_iters=1000, b
         "one_call_rel_err": {"network": float(errs["network"].mean()),
                              "base_only": float(errs["base_only"].mean())},
         "ms_per_network_call": ms_call,
+        "ms_per_base_only_call": ms_base,
         "network_forward_ms_per_sample_b8": ms_fwd8 / 8,
         "hos_ms_per_step_256": ms_hos,
         "network_only_steps_per_s": 10 * 1e3 / ms_call,
+        "base_only_steps_per_s": 10 * 1e3 / ms_base,
         "plain_hos_steps_per_s": 1e3 / ms_hos,
-        "judged_rollout": [{k: r[k] for k in ("seed", "calls", "surrogate_calls", "hos_calls", "audits", "fallbacks",
-                                              "max_audit_err", "offline_err", "effective_steps_per_s")}
-                           for r in roll],
+        "judge": "tol 1e-3 per judged call, drift bound 1e-3 on the estimated accumulated error, every 4th call "
+                 "judged, probation 2, cool-down 4",
+        "judged_rollout": [{k: r[k] for k in keys} for r in roll],
+        "judged_rollout_base_only": [{k: r[k] for k in keys} for r in roll_base],
     }
 
 

@@ -132,6 +132,13 @@ typedef struct swense_surrogate_desc {
   int base_substeps;  /* base prediction B: 0 = Lin_{s dt} (exact linear        */
                       /* propagation); n > 0 = n integrating-factor RK4        */
                       /* substeps over s dt (swense_hos_step_exp)              */
+  double drift_tol;   /* bound on the estimated error accumulated against     */
+                      /* plain HOS since creation or the last reset (<= 0:   */
+                      /* none): each unjudged call adds the largest judged   */
+                      /* error so far; a call that would pass the bound, and */
+                      /* every call after it, is advanced by HOS             */
+  int base_only;      /* 1: each call is the base prediction B alone (the     */
+                      /* network is not evaluated), judged the same way     */
 } swense_surrogate_desc;
 
 /* Counters accumulated by swense_surrogate_advance (zero them before use). */
@@ -144,6 +151,8 @@ typedef struct swense_surrogate_stats {
   long long guard_trips;     /* non-finite state or energy change above its bound */
   double max_audit_err;      /* largest audited relative error                    */
   double last_audit_err;
+  long long bound_calls;     /* calls advanced by HOS because of drift_tol        */
+  double drift_est;          /* estimated accumulated error after the last call  */
 } swense_surrogate_stats;
 
 typedef struct swense_surrogate swense_surrogate; /* (opaque) */
@@ -170,11 +179,22 @@ int swense_surrogate_target(swense_surrogate* s, const float* x_next, const floa
  * (cool-down after a fallback).  A network call is judged when its guard
  * trips, when it is the A-th since the last judged one, or while fewer than
  * `probation` judged calls have passed in a row (from creation and after
- * every fallback): HOS re-runs the s steps from the saved state, the relative
+ * every fallback), and, with a drift bound, while no call has been judged
+ * since the reset: HOS re-runs the s steps from the saved state, the relative
  * L2 error of the network's state against it is recorded, and the HOS state
  * is kept; an error above tol (tol = 0: always) or a tripped guard counts as
- * a fallback and starts the cool-down.  Synchronises per call. */
+ * a fallback and starts the cool-down.  A judged call adds no error of its
+ * own to the rollout (its HOS state is kept); an unjudged one adds, to the
+ * estimate, the largest judged error since the reset.  With drift_tol > 0,
+ * once the next unjudged call would take the estimate past drift_tol the
+ * rollout continues with HOS alone until swense_surrogate_reset.
+ * Synchronises per call. */
 int swense_surrogate_advance(swense_surrogate* s, int ncalls, swense_surrogate_stats* stats);
+
+/* Start a new rollout (e.g. after the realisation's state was set): clears
+ * the cool-down, the probation record, the audit counter, the largest judged
+ * error and the drift estimate. */
+int swense_surrogate_reset(swense_surrogate* s);
 
 const char* swense_surrogate_last_error(const swense_surrogate* s);
 void swense_surrogate_destroy(swense_surrogate* s);

@@ -4,6 +4,7 @@
 // spectral), cheap guards run (non-finite values, energy change), and every
 // A-th call (or a guarded one) HOS re-runs the same steps from the saved
 // state, the error is measured and the HOS state is kept.
+#include <cmath>
 #include <cstring>
 #include <string>
 
@@ -25,6 +26,9 @@ struct swense_surrogate {
   int cool = 0;            // cool-down calls left
   int trust = 0;           // judged calls passed in a row
   long long nsur = 0;      // network calls so far (audit counter)
+  double drift = 0.0;      // estimated error accumulated by unjudged calls since the reset
+  double est = -1.0;       // largest judged error since the reset (< 0: none yet)
+  bool spent = false;      // drift bound reached: HOS alone until the next reset
 };
 
 namespace {
@@ -193,22 +197,28 @@ double rel_error(swense_surrogate* s, const cd* a0, const cd* a1) {
 // s HOS steps from the current state, time advanced step by step as in HOS
 void hos_call(swense_surrogate* s) { hos_step(s->h, s->d.stride_s); }
 
-void network_call(swense_surrogate* s, swense_surrogate_stats* st) {
+// One call of the learned step (or, with base_only, of the base prediction
+// alone); judged when forced, guarded, on probation or the A-th.
+void network_call(swense_surrogate* s, swense_surrogate_stats* st, bool force_audit) {
   swense_hos* h = s->h;
   const double t0 = h->t;
   copy_state(s, h->xn[0], h->xn[1], s->backup[0], s->backup[1]);
   const bool eguard = s->d.energy_tol > 0.0;
   const double E0 = eguard ? hos_energy(h) : 0.0;
   const long long np = (long long)h->G.nx * h->G.ny;
-  features_of(s, s->backup[0], s->backup[1], s->x);
-  base_into_state(s, s->backup[0], s->backup[1]);
-  if (s->in_channels == 4) features_of(s, h->xn[0], h->xn[1], s->x + 2 * np);
-  const int rc = swense_fno_forward(s->f, s->x, s->y, 1);
-  if (rc != SWENSE_OK) throw SwenseError{rc, "network forward failed"};
-  hipLaunchKernelGGL(k_residual_in, dim3(nblk(np)), dim3(256), 0, h->st, s->y, h->phys, h->phys + np, np,
-                     s->d.rho * s->d.sigma_eta, s->d.rho * s->d.sigma_phi);
-  SW_HIP(hipGetLastError());
-  hos_phys_to_spec(h, h->xn[0], h->xn[1], true);
+  if (s->d.base_only) {
+    base_into_state(s, s->backup[0], s->backup[1]);
+  } else {
+    features_of(s, s->backup[0], s->backup[1], s->x);
+    base_into_state(s, s->backup[0], s->backup[1]);
+    if (s->in_channels == 4) features_of(s, h->xn[0], h->xn[1], s->x + 2 * np);
+    const int rc = swense_fno_forward(s->f, s->x, s->y, 1);
+    if (rc != SWENSE_OK) throw SwenseError{rc, "network forward failed"};
+    hipLaunchKernelGGL(k_residual_in, dim3(nblk(np)), dim3(256), 0, h->st, s->y, h->phys, h->phys + np, np,
+                       s->d.rho * s->d.sigma_eta, s->d.rho * s->d.sigma_phi);
+    SW_HIP(hipGetLastError());
+    hos_phys_to_spec(h, h->xn[0], h->xn[1], true);
+  }
   hipLaunchKernelGGL(k_keep_mean, dim3(1), dim3(1), 0, h->st, h->xn[0], s->backup[0]);
   SW_HIP(hipGetLastError());
   double t = t0;
@@ -222,8 +232,13 @@ void network_call(swense_surrogate* s, swense_surrogate_stats* st) {
   }
   st->surrogate_calls++;
   s->nsur++;
-  const bool audit = guard || s->trust < s->d.probation || (s->nsur % s->d.audit_every == 0);
-  if (!audit) return;
+  const bool audit = force_audit || guard || s->trust < s->d.probation || (s->nsur % s->d.audit_every == 0);
+  if (!audit) {
+    // an unjudged call adds the largest judged error since the reset to the
+    // estimate of the error accumulated against plain HOS
+    if (s->est > 0.0) s->drift += s->est;
+    return;
+  }
   // judge: HOS from the saved state; its result is kept
   copy_state(s, h->xn[0], h->xn[1], s->sur[0], s->sur[1]);
   copy_state(s, s->backup[0], s->backup[1], h->xn[0], h->xn[1]);
@@ -234,6 +249,7 @@ void network_call(swense_surrogate* s, swense_surrogate_stats* st) {
   st->audits++;
   st->last_audit_err = err;
   if (err == err && err > st->max_audit_err) st->max_audit_err = err;
+  s->est = err == err ? std::max(s->est, err) : INFINITY;
   if (guard) st->guard_trips++;
   if (guard || !(err <= s->d.tol)) {
     st->fallbacks++;
@@ -275,6 +291,7 @@ int swense_surrogate_create(swense_hos* h, swense_fno* f, const swense_surrogate
                    d->base_substeps >= 0 && d->base_substeps <= 64,
                "stride, audit period, cool-down, probation or base substeps");
     SW_REQUIRE(d->sigma_eta > 0.0 && d->sigma_phi > 0.0 && d->rho > 0.0 && d->tol >= 0.0, "scales and tol");
+    SW_REQUIRE(d->base_only == 0 || d->base_only == 1, "base_only must be 0 or 1");
     s->h = h;
     s->f = f;
     s->d = *d;
@@ -342,6 +359,7 @@ int swense_surrogate_target(swense_surrogate* s, const float* x_next, const floa
 int swense_surrogate_advance(swense_surrogate* s, int ncalls, swense_surrogate_stats* st) {
   if (!s || !st || ncalls < 0) return SWENSE_EINVAL;
   return guarded_s(s, [&] {
+    const bool bound = s->d.drift_tol > 0.0;
     for (int c = 0; c < ncalls; ++c) {
       st->calls++;
       if (s->cool > 0) {
@@ -350,10 +368,34 @@ int swense_surrogate_advance(swense_surrogate* s, int ncalls, swense_surrogate_s
         st->hos_calls++;
         continue;
       }
-      network_call(s, st);
+      if (bound && !s->spent && s->est >= 0.0) {
+        // the next call goes unjudged unless on probation or the A-th: stop
+        // the learned calls when its estimated error would pass the bound
+        const bool judged = s->trust < s->d.probation || ((s->nsur + 1) % s->d.audit_every == 0);
+        if (!judged && !(s->drift + s->est <= s->d.drift_tol)) s->spent = true;
+      }
+      if (s->spent) {
+        hos_call(s);
+        st->hos_calls++;
+        st->bound_calls++;
+        continue;
+      }
+      network_call(s, st, bound && s->est < 0.0);
     }
+    st->drift_est = s->drift;
     return (int)SWENSE_OK;
   });
+}
+
+int swense_surrogate_reset(swense_surrogate* s) {
+  if (!s) return SWENSE_EINVAL;
+  s->cool = 0;
+  s->trust = 0;
+  s->nsur = 0;
+  s->drift = 0.0;
+  s->est = -1.0;
+  s->spent = false;
+  return SWENSE_OK;
 }
 
 const char* swense_surrogate_last_error(const swense_surrogate* s) { return s ? s->err.c_str() : "no handle"; }

@@ -53,13 +53,15 @@ class FnoDesc(C.Structure):
 class SurrogateDesc(C.Structure):
     _fields_ = [("stride_s", C.c_int), ("sigma_eta", C.c_double), ("sigma_phi", C.c_double), ("rho", C.c_double),
                 ("tol", C.c_double), ("audit_every", C.c_int), ("cooldown", C.c_int), ("energy_tol", C.c_double),
-                ("probation", C.c_int), ("base_substeps", C.c_int)]
+                ("probation", C.c_int), ("base_substeps", C.c_int), ("drift_tol", C.c_double),
+                ("base_only", C.c_int)]
 
 
 class SurrogateStats(C.Structure):
     _fields_ = [("calls", C.c_longlong), ("surrogate_calls", C.c_longlong), ("hos_calls", C.c_longlong),
                 ("audits", C.c_longlong), ("fallbacks", C.c_longlong), ("guard_trips", C.c_longlong),
-                ("max_audit_err", C.c_double), ("last_audit_err", C.c_double)]
+                ("max_audit_err", C.c_double), ("last_audit_err", C.c_double), ("bound_calls", C.c_longlong),
+                ("drift_est", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -146,6 +148,7 @@ def load():
         "swense_surrogate_features": (C.c_int, [vp, vp, vp]),
         "swense_surrogate_target": (C.c_int, [vp, vp, vp, vp]),
         "swense_surrogate_advance": (C.c_int, [vp, C.c_int, C.POINTER(SurrogateStats)]),
+        "swense_surrogate_reset": (C.c_int, [vp]),
         "swense_surrogate_last_error": (C.c_char_p, [vp]),
         "swense_surrogate_destroy": (None, [vp]),
     }
@@ -169,7 +172,7 @@ EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swens
             "swense_cells_destroy", "swense_fno_param_count", "swense_fno_create", "swense_fno_forward",
             "swense_fno_loss", "swense_fno_backward", "swense_fno_train_step", "swense_fno_get", "swense_fno_set",
             "swense_fno_last_error", "swense_fno_destroy", "swense_gemm_bf16", "swense_surrogate_create",
-            "swense_surrogate_features", "swense_surrogate_target", "swense_surrogate_advance",
+            "swense_surrogate_features", "swense_surrogate_target", "swense_surrogate_advance", "swense_surrogate_reset",
             "swense_surrogate_last_error", "swense_surrogate_destroy"]
 
 
@@ -710,9 +713,11 @@ def gemm_bf16(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
 
 
 def surrogate_desc(stride_s=10, sigma_eta=1.0, sigma_phi=1.0, rho=1.0, tol=1e-3, audit_every=4, cooldown=4,
-                   energy_tol=0.0, probation=2, base_substeps=0):
+                   energy_tol=0.0, probation=2, base_substeps=0, drift_tol=None, base_only=False):
+    """drift_tol defaults to tol (the accumulated error held to the same
+    bound as one call's); 0 switches the bound off."""
     return SurrogateDesc(stride_s, sigma_eta, sigma_phi, rho, tol, audit_every, cooldown, energy_tol, probation,
-                         base_substeps)
+                         base_substeps, tol if drift_tol is None else drift_tol, 1 if base_only else 0)
 
 
 class Surrogate:
@@ -751,6 +756,11 @@ class Surrogate:
     def advance(self, ncalls):
         self._check(load().swense_surrogate_advance(self.h, ncalls, C.byref(self.stats)), "advance")
         return self.stats.as_dict()
+
+    def reset(self):
+        """New rollout: judge state and drift estimate cleared (stats too)."""
+        self._check(load().swense_surrogate_reset(self.h), "reset")
+        self.stats = SurrogateStats()
 
     def close(self):
         if getattr(self, "h", None):

@@ -114,19 +114,19 @@ def train(net: lib.Fno, store: Pairs, iters: int, batch: int, lr: float, seed: i
     return hist
 
 
-def one_call_errors(net: lib.Fno, scales: dict, seeds, calls: int, periods: float, zero_net: lib.Fno = None):
+def one_call_errors(net: lib.Fno, scales: dict, seeds, calls: int, periods: float, base_only: bool = True):
     """Per-call relative state error of the network (and of the base
-    prediction alone, through a network whose output is zero) on held-out
-    seas: every call judged by HOS, whose state is kept (tol = inf)."""
+    prediction alone, the network not evaluated) on held-out seas: every
+    call judged by HOS, whose state is kept (tol = inf)."""
     n = net.desc.n
     out = {"network": [], "base_only": []}
-    for name, m in (("network", net), ("base_only", zero_net)):
-        if m is None:
+    for name, only in (("network", False), ("base_only", True)):
+        if only and not base_only:
             continue
-        sd = lib.surrogate_desc(tol=1e30, audit_every=1, cooldown=0, **scales)
+        sd = lib.surrogate_desc(tol=1e30, audit_every=1, cooldown=0, drift_tol=0.0, base_only=only, **scales)
         for seed in seeds:
             h = sea_hos(n, periods, seed)
-            sur = lib.Surrogate(h, m, sd)
+            sur = lib.Surrogate(h, net, sd)
             errs = []
             for _ in range(calls):
                 sur.advance(1)
@@ -137,6 +137,19 @@ def one_call_errors(net: lib.Fno, scales: dict, seeds, calls: int, periods: floa
     return {k: np.array(v) for k, v in out.items() if v}
 
 
+def rel_state_error(e, p, er, pr) -> float:
+    """Relative L2 error of the half spectra (e, p) against (er, pr), max over
+    the two fields, with the Parseval weights of the half spectrum (1 for the
+    p = 0 column, 2 for the others): the measure of the rollout's judge."""
+    w = np.full(er.shape[1], 2.0)
+    w[0] = 1.0
+
+    def one(a, b):
+        return math.sqrt(float(np.sum(w * np.abs(a - b) ** 2)) / float(np.sum(w * np.abs(b) ** 2)))
+
+    return max(one(e, er), one(p, pr))
+
+
 def zero_output(desc: lib.FnoDesc, vec: np.ndarray) -> np.ndarray:
     P = lib.fno_unpack(desc, vec)
     P["Q2"] = np.zeros_like(P["Q2"])
@@ -145,15 +158,18 @@ def zero_output(desc: lib.FnoDesc, vec: np.ndarray) -> np.ndarray:
 
 
 def rollout(net: lib.Fno, scales: dict, seeds, calls: int, periods: float, tol: float, audit_every: int,
-            cooldown: int):
-    """Rollout with the HOS fallback/judge; offline error against a plain HOS
-    run of the same seas; effective HOS steps per second."""
+            cooldown: int, base_only: bool = False, drift_tol=None):
+    """Rollout with the HOS fallback/judge (drift bound drift_tol, default
+    tol), of the network or (base_only) of the base prediction alone;
+    offline error against a plain HOS run of the same seas; effective HOS
+    steps per second."""
     n = net.desc.n
     res = []
     for seed in seeds:
         h = sea_hos(n, periods, seed)
         ref = sea_hos(n, periods, seed)
-        sd = lib.surrogate_desc(tol=tol, audit_every=audit_every, cooldown=cooldown, **scales)
+        sd = lib.surrogate_desc(tol=tol, audit_every=audit_every, cooldown=cooldown, base_only=base_only,
+                                drift_tol=drift_tol, **scales)
         sur = lib.Surrogate(h, net, sd)
         torch.cuda.synchronize()
         t0 = time.time()
@@ -163,7 +179,7 @@ def rollout(net: lib.Fno, scales: dict, seeds, calls: int, periods: float, tol: 
         ref.step(calls * scales["stride_s"])
         e, p, _ = h.state()
         er, pr, _ = ref.state()
-        off = max(np.linalg.norm(e - er) / np.linalg.norm(er), np.linalg.norm(p - pr) / np.linalg.norm(pr))
+        off = rel_state_error(e, p, er, pr)
         st = dict(st)
         st.update(seed=seed, offline_err=float(off), seconds=dt,
                   effective_steps_per_s=calls * scales["stride_s"] / dt)
@@ -217,9 +233,9 @@ def main(argv=None):
     t_train = time.time() - t0
     del store
     test = range(3000, 3000 + a.test_seeds)
-    zero = lib.Fno(desc, zero_output(desc, vec0))
-    errs = one_call_errors(net, scales, test, a.calls, a.periods, zero)
+    errs = one_call_errors(net, scales, test, a.calls, a.periods)
     roll = rollout(net, scales, test, a.calls, a.periods, tol=1e-3, audit_every=4, cooldown=4)
+    roll_base = rollout(net, scales, test, a.calls, a.periods, tol=1e-3, audit_every=4, cooldown=4, base_only=True)
     rep = {
         "config": vars(a), "scales": scales, "pairs": a.trajectories * (a.steps // a.stride),
         "generate_s": t_gen, "train_s": t_train, "train_ms_per_iter": 1e3 * t_train / max(1, a.iters),
@@ -229,9 +245,10 @@ def main(argv=None):
         "one_call_err_base_mean": float(errs["base_only"].mean()),
         "one_call_err_base_max": float(errs["base_only"].max()),
         "rollout": roll,
+        "rollout_base_only": roll_base,
     }
     log(json.dumps({k: v for k, v in rep.items() if k != "rollout"}))
-    for r in roll:
+    for r in roll + roll_base:
         log(json.dumps(r))
     if a.report:
         with open(a.report, "w") as f:
@@ -240,7 +257,6 @@ def main(argv=None):
         np.savez(a.out, params=net.get(0), adam_m=net.get(2), adam_v=net.get(3),
                  desc=np.array([a.n, a.channels, a.layers, a.p_modes, a.q_modes, a.hidden, a.in_channels]),
                  scales=json.dumps(scales))
-    zero.close()
     net.close()
     return rep
 
