@@ -121,19 +121,34 @@ def _cp(cfg):
     return c
 
 
+def _quant(bf16: bool):
+    """The rounding applied to every GEMM input: BF16 (nearest even) or none."""
+    if bf16:
+        return to_bf16, cbf16
+    return (lambda a: a), (lambda a: a)
+
+
+def layer_forward(P: dict, l: int, v: np.ndarray, cfg: FnoConfig, bf16: bool = False):
+    """Fourier layer l on its input v [B, C, n, n]: the pre-activation
+    z = W_l v + b_l + (inverse transform of R_l times the retained modes of
+    v); returns (z, retained modes of v)."""
+    q, qc = _quant(bf16)
+    Uh = spec_forward(v, cfg)                                   # [B, nq, P, C]
+    Yh = np.einsum("bqpi,qpio->bqpo", qc(Uh), qc(P[f"R{l}"]))
+    Yh = hermitian_p0(Yh, cfg)
+    s = spec_inverse(Yh, cfg)
+    z = np.einsum("oi,bixy->boxy", q(P[f"W{l}"]), q(v)) + P[f"b{l}"][None, :, None, None] + s
+    return z, Uh
+
+
 def forward(P: dict, x: np.ndarray, cfg: FnoConfig, bf16: bool = False):
     """x [B, in_channels, n, n] -> y [B, 2, n, n]; returns (y, cache)."""
-    q = to_bf16 if bf16 else (lambda a: a)
-    qc = cbf16 if bf16 else (lambda a: a)
+    q, _ = _quant(bf16)
     cache = {"x": x}
     v = np.einsum("oi,bixy->boxy", q(P["W0"]), q(x)) + P["b0"][None, :, None, None]
     cache["v0"] = v
     for l in range(1, cfg.layers + 1):
-        Uh = spec_forward(v, cfg)                                   # [B, nq, P, C]
-        Yh = np.einsum("bqpi,qpio->bqpo", qc(Uh), qc(P[f"R{l}"]))
-        Yh = hermitian_p0(Yh, cfg)
-        s = spec_inverse(Yh, cfg)
-        z = np.einsum("oi,bixy->boxy", q(P[f"W{l}"]), q(v)) + P[f"b{l}"][None, :, None, None] + s
+        z, Uh = layer_forward(P, l, v, cfg, bf16)
         cache[f"u{l}"] = v
         cache[f"U{l}"] = Uh
         cache[f"z{l}"] = z
@@ -157,39 +172,59 @@ def loss(y: np.ndarray, t: np.ndarray):
     return L, g
 
 
-def backward(P: dict, cache: dict, gy: np.ndarray, cfg: FnoConfig, bf16: bool = False) -> dict:
-    q = to_bf16 if bf16 else (lambda a: a)
-    qc = cbf16 if bf16 else (lambda a: a)
+def head_backward(P: dict, gy: np.ndarray, h: np.ndarray, zq: np.ndarray, vL: np.ndarray, bf16: bool = False):
+    """Projection (Q1, c1, GELU, Q2, c2) backward from dL/dy: returns the
+    head's parameter gradients, dL/dzq and dL/dv_L."""
+    q, _ = _quant(bf16)
     G = {}
-    h = cache["h"]
     G["Q2"] = np.einsum("boxy,bixy->oi", q(gy), q(h))
     G["c2"] = gy.sum(axis=(0, 2, 3))
     gh = np.einsum("oi,boxy->bixy", q(P["Q2"]), q(gy))
-    gz1 = gh * gelu_grad(cache["zq"])
-    v = cache["vL"]
-    G["Q1"] = np.einsum("boxy,bixy->oi", q(gz1), q(v))
+    gz1 = gh * gelu_grad(zq)
+    G["Q1"] = np.einsum("boxy,bixy->oi", q(gz1), q(vL))
     G["c1"] = gz1.sum(axis=(0, 2, 3))
     gv = np.einsum("oi,boxy->bixy", q(P["Q1"]), q(gz1))
+    return G, gz1, gv
+
+
+def layer_backward(P: dict, l: int, u: np.ndarray, Uh: np.ndarray, gz: np.ndarray, cfg: FnoConfig,
+                   bf16: bool = False):
+    """Fourier layer l backward from dL/dz (its input u and retained modes Uh
+    from the forward pass): returns the gradients of W_l, b_l, R_l and dL/du."""
+    q, qc = _quant(bf16)
     cp = _cp(cfg)
+    G = {}
+    G[f"W{l}"] = np.einsum("boxy,bixy->oi", q(gz), q(u))
+    G[f"b{l}"] = gz.sum(axis=(0, 2, 3))
+    gu = np.einsum("oi,boxy->bixy", q(P[f"W{l}"]), q(gz))
+    # spectral branch: gY = P(c_p n^2 rfft2(gz)/n^2) on S
+    gY = spec_forward(gz, cfg) * (cfg.n * cfg.n) * cp[None, None, :, None]
+    gY = hermitian_p0(gY, cfg)
+    G[f"R{l}"] = np.einsum("bqpi,bqpo->qpio", np.conj(qc(Uh)), qc(gY))
+    gU = np.einsum("bqpo,qpio->bqpi", qc(gY), np.conj(qc(P[f"R{l}"])))
+    # adjoint of u -> rfft2(u)/n^2 on S: (1/n^2) Re sum_S gU e^{ik.x}
+    stored = hermitian_p0(gU / cp[None, None, :, None], cfg)
+    gu = gu + spec_inverse(stored, cfg) / (cfg.n * cfg.n)
+    return G, gu
+
+
+def lift_backward(P: dict, gv0: np.ndarray, x: np.ndarray, bf16: bool = False):
+    """Lift (W0, b0) backward from dL/dv_0: its gradients and dL/dx."""
+    q, _ = _quant(bf16)
+    G = {}
+    G["W0"] = np.einsum("boxy,bixy->oi", q(gv0), q(x))
+    G["b0"] = gv0.sum(axis=(0, 2, 3))
+    G["x"] = np.einsum("oi,boxy->bixy", q(P["W0"]), q(gv0))
+    return G
+
+
+def backward(P: dict, cache: dict, gy: np.ndarray, cfg: FnoConfig, bf16: bool = False) -> dict:
+    G, _, gv = head_backward(P, gy, cache["h"], cache["zq"], cache["vL"], bf16)
     for l in range(cfg.layers, 0, -1):
         gz = gv * gelu_grad(cache[f"z{l}"])
-        u = cache[f"u{l}"]
-        G[f"W{l}"] = np.einsum("boxy,bixy->oi", q(gz), q(u))
-        G[f"b{l}"] = gz.sum(axis=(0, 2, 3))
-        gu = np.einsum("oi,boxy->bixy", q(P[f"W{l}"]), q(gz))
-        # spectral branch: gY = P(c_p n^2 rfft2(gz)/n^2) on S
-        gY = spec_forward(gz, cfg) * (cfg.n * cfg.n) * cp[None, None, :, None]
-        gY = hermitian_p0(gY, cfg)
-        Uh = cache[f"U{l}"]
-        G[f"R{l}"] = np.einsum("bqpi,bqpo->qpio", np.conj(qc(Uh)), qc(gY))
-        gU = np.einsum("bqpo,qpio->bqpi", qc(gY), np.conj(qc(P[f"R{l}"])))
-        # adjoint of u -> rfft2(u)/n^2 on S: (1/n^2) Re sum_S gU e^{ik.x}
-        stored = hermitian_p0(gU / cp[None, None, :, None], cfg)
-        gu = gu + spec_inverse(stored, cfg) / (cfg.n * cfg.n)
-        gv = gu
-    G["W0"] = np.einsum("boxy,bixy->oi", q(gv), q(cache["x"]))
-    G["b0"] = gv.sum(axis=(0, 2, 3))
-    G["x"] = np.einsum("oi,boxy->bixy", q(P["W0"]), q(gv))
+        Gl, gv = layer_backward(P, l, cache[f"u{l}"], cache[f"U{l}"], gz, cfg, bf16)
+        G.update(Gl)
+    G.update(lift_backward(P, gv, cache["x"], bf16))
     return G
 
 
