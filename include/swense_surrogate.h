@@ -96,6 +96,21 @@ int swense_fno_get(swense_fno* f, int what, float* host);
  * a checkpoint).  Synchronises. */
 int swense_fno_set(swense_fno* f, int what, const float* host);
 
+/* Activations of the last forward pass, for checking a layer on its own
+ * inputs (host): v_0 .. v_L and z_1 .. z_L ([batch][C][n][n] each, v_l the
+ * input of layer l + 1 and z_l the pre-activation of layer l), then zq and h
+ * ([batch][H][n][n]: the projection's pre-activation and its GELU), for the
+ * last forward's batch, in that order: (2L + 1) batch C n^2 + 2 batch H n^2
+ * floats.  Synchronises. */
+int swense_fno_get_activations(swense_fno* f, float* host);
+
+/* Intermediate gradients of the backward passes, for checking a layer on its
+ * own upstream gradient: trace (device, caller-owned, at least
+ * (L + 1) max_batch C n^2 + max_batch H n^2 floats; NULL: off) receives from
+ * each later backward dL/dz_1 .. dL/dz_L and dL/dv_0 ([batch][C][n][n] each),
+ * then dL/dzq ([batch][H][n][n]), in that order. */
+int swense_fno_set_trace(swense_fno* f, float* trace);
+
 const char* swense_fno_last_error(const swense_fno* f);
 void swense_fno_destroy(swense_fno* f);
 

@@ -651,6 +651,7 @@ struct swense_fno {
   size_t npart = 0;
   float* sums = nullptr;
   int last_batch = 0;
+  float* trace = nullptr;  // caller's buffer for the backward's intermediate gradients (checking)
   void* mem = nullptr;
 };
 
@@ -1060,6 +1061,13 @@ void backward_impl(swense_fno* f, const float* x, const float* gy, float* gx, in
   bias_grad(f, gy, f->g + f->oc2, B, 2);
   conv1x1_dx(f, f->wb + f->oQ2, 2, H, gy, gh, B, 0.f);
   gelu_back(f, gh, zq_of(f), gh, (long long)B * H * plane);
+  const size_t cplane = (size_t)B * C * plane;  // one traced [B][C][n][n] block
+  auto trace = [&](const float* src, size_t slot, size_t count) {
+    if (f->trace)
+      SW_HIP(hipMemcpyAsync(f->trace + slot * (size_t)d.max_batch * C * plane, src, count * sizeof(float),
+                            hipMemcpyDeviceToDevice, f->st));
+  };
+  trace(gh, (size_t)d.layers + 1, (size_t)B * H * plane);
   conv1x1_dw(f, gh, v_of(f, d.layers), H, C, B, f->g + f->oQ1);
   bias_grad(f, gh, f->g + f->oc1, B, H);
   conv1x1_dx(f, f->wb + f->oQ1, H, C, gh, gv, B, 0.f);
@@ -1068,6 +1076,7 @@ void backward_impl(swense_fno* f, const float* x, const float* gy, float* gx, in
   cf* gU = f->Y + (size_t)d.max_batch * S * C;
   for (int l = d.layers; l >= 1; --l) {
     gelu_back(f, gv, z_of(f, l), gz, (long long)B * C * plane);
+    trace(gz, (size_t)l - 1, cplane);
     const float* u = v_of(f, l - 1);
     conv1x1_dw(f, gz, u, C, C, B, f->g + f->oW[l - 1]);
     bias_grad(f, gz, f->g + f->ob[l - 1], B, C);
@@ -1082,6 +1091,7 @@ void backward_impl(swense_fno* f, const float* x, const float* gy, float* gx, in
     conv1x1_dx(f, f->wb + f->oW[l - 1], C, C, gz, gv, B, 0.f);
     spec_inv(f, gU, gv, B, 1.f / ((float)plane), 1.f);
   }
+  trace(gv, (size_t)d.layers, cplane);
   conv1x1_dw(f, gv, x, C, d.in_channels, B, f->g + f->oW0);
   bias_grad(f, gv, f->g + f->ob0, B, C);
   if (gx) conv1x1_dx(f, f->wb + f->oW0, C, d.in_channels, gv, gx, B, 0.f);
@@ -1211,6 +1221,28 @@ int swense_fno_get(swense_fno* f, int what, float* host) {
     SW_HIP(hipMemcpy(host, src, f->nparam * 4, hipMemcpyDeviceToHost));
     return (int)SWENSE_OK;
   });
+}
+
+int swense_fno_get_activations(swense_fno* f, float* host) {
+  if (!f || !host) return SWENSE_EINVAL;
+  return guarded_f(f, [&] {
+    SW_REQUIRE(f->last_batch >= 1, "no forward pass yet");
+    const size_t B = f->last_batch, plane = (size_t)f->d.n * f->d.n;
+    const size_t cblk = B * f->d.channels * plane, hblk = B * f->d.hidden * plane;
+    SW_HIP(hipStreamSynchronize(f->st));
+    float* o = host;
+    for (int l = 0; l <= f->d.layers; ++l, o += cblk) SW_HIP(hipMemcpy(o, v_of(f, l), cblk * 4, hipMemcpyDeviceToHost));
+    for (int l = 1; l <= f->d.layers; ++l, o += cblk) SW_HIP(hipMemcpy(o, z_of(f, l), cblk * 4, hipMemcpyDeviceToHost));
+    SW_HIP(hipMemcpy(o, zq_of(f), hblk * 4, hipMemcpyDeviceToHost));
+    SW_HIP(hipMemcpy(o + hblk, h_of(f), hblk * 4, hipMemcpyDeviceToHost));
+    return (int)SWENSE_OK;
+  });
+}
+
+int swense_fno_set_trace(swense_fno* f, float* trace) {
+  if (!f) return SWENSE_EINVAL;
+  f->trace = trace;
+  return SWENSE_OK;
 }
 
 int swense_fno_set(swense_fno* f, int what, const float* host) {

@@ -141,6 +141,8 @@ def load():
         "swense_fno_train_step": (C.c_int, [vp, vp, vp, C.c_int, C.c_float, C.POINTER(C.c_float)]),
         "swense_fno_get": (C.c_int, [vp, C.c_int, vp]),
         "swense_fno_set": (C.c_int, [vp, C.c_int, vp]),
+        "swense_fno_get_activations": (C.c_int, [vp, vp]),
+        "swense_fno_set_trace": (C.c_int, [vp, vp]),
         "swense_fno_last_error": (C.c_char_p, [vp]),
         "swense_fno_destroy": (None, [vp]),
         "swense_gemm_bf16": (C.c_int, [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp]),
@@ -171,7 +173,7 @@ EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swens
             "swense_batch_last_error", "swense_batch_destroy", "swense_hos_destroy",
             "swense_cells_destroy", "swense_fno_param_count", "swense_fno_create", "swense_fno_forward",
             "swense_fno_loss", "swense_fno_backward", "swense_fno_train_step", "swense_fno_get", "swense_fno_set",
-            "swense_fno_last_error", "swense_fno_destroy", "swense_gemm_bf16", "swense_surrogate_create",
+            "swense_fno_get_activations", "swense_fno_set_trace", "swense_fno_last_error", "swense_fno_destroy", "swense_gemm_bf16", "swense_surrogate_create",
             "swense_surrogate_features", "swense_surrogate_target", "swense_surrogate_advance", "swense_surrogate_reset",
             "swense_surrogate_last_error", "swense_surrogate_destroy"]
 
@@ -687,6 +689,31 @@ class Fno:
         vec = np.ascontiguousarray(vec, dtype=np.float32)
         assert vec.size == self.n_params
         self._check(load().swense_fno_set(self.h, what, vec.ctypes.data_as(C.c_void_p)), "set")
+
+    def activations(self, batch):
+        """The last forward's activations (host FP32): v [L+1][batch][C][n][n],
+        z [L][batch][C][n][n] (z[l-1] is layer l's pre-activation), zq and h
+        [batch][H][n][n]."""
+        d = self.desc
+        C, H, n, L = d.channels, d.hidden, d.n, d.layers
+        cblk, hblk = batch * C * n * n, batch * H * n * n
+        buf = np.empty((2 * L + 1) * cblk + 2 * hblk, dtype=np.float32)
+        self._check(load().swense_fno_get_activations(self.h, _ptr(buf)), "get_activations")
+        v = buf[:(L + 1) * cblk].reshape(L + 1, batch, C, n, n)
+        z = buf[(L + 1) * cblk:(2 * L + 1) * cblk].reshape(L, batch, C, n, n)
+        o = (2 * L + 1) * cblk
+        return {"v": v, "z": z, "zq": buf[o:o + hblk].reshape(batch, H, n, n),
+                "h": buf[o + hblk:o + 2 * hblk].reshape(batch, H, n, n)}
+
+    def set_trace(self, trace):
+        """A device FP32 buffer of at least trace_floats() that later backward
+        passes fill with dL/dz_1..dL/dz_L, dL/dv_0 and dL/dzq (None: off)."""
+        self._trace = trace
+        self._check(load().swense_fno_set_trace(self.h, _ptr(trace) if trace is not None else None), "set_trace")
+
+    def trace_floats(self):
+        d = self.desc
+        return (d.layers + 1) * d.max_batch * d.channels * d.n * d.n + d.max_batch * d.hidden * d.n * d.n
 
     def close(self):
         if getattr(self, "h", None):
