@@ -48,6 +48,10 @@ struct EvArgs {
   int p_slot;     // output slot of the pressure, -1 if not requested
   const cd* srcs[4];       // distinct spectral sources of the fields
   int sid[kMaxEvFields];   // source of each field (index into srcs)
+  // field whose y transform this field reuses times i kx (the x derivative
+  // of a field of the same source and vertical factor: its symbol differs
+  // by i kx only, a constant along each kx column); -1: transformed itself
+  int alias[kMaxEvFields];
 };
 
 // y-inverse for evaluation: job = (field, layer) for volume fields, then
@@ -148,6 +152,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 3
   }
   const float kxf = (float)kx, kysf = (float)kys;
   for (int f = f0; f < f1; ++f) {
+    if (A.alias[f] >= 0) continue;  // formed by the x pass from its alias
     const EvField F = A.f[f];
     const bool first = A.sid[f] == s0;
 #pragma unroll
@@ -381,6 +386,34 @@ __global__ void __launch_bounds__(256) k_xcoef_w(EvArgs A, Geom G, WPlan plan, i
   }
 }
 
+// gather_x for the plane x pass, each row optionally multiplied by i kx
+// first (ka, kb: 2 pi / lx for a row formed from its alias, else 0).
+template <typename R>
+__device__ __forceinline__ cpx<R> gather_x_dx(const cpx<R>* ra, const cpx<R>* rb, int s, int gx, int hx, R ka, R kb) {
+  R zx = 0, zy = 0;
+  auto row = [&](const cpx<R>* r, int p, R k) {
+    cpx<R> v = r ? r[p] : mk((R)0, (R)0);
+    if (k != (R)0) {
+      const R kp = k * (R)p;
+      v = mk(-kp * v.y, kp * v.x);
+    }
+    return v;
+  };
+  for (int p = s; p < hx; p += gx) {
+    const cpx<R> va = row(ra, p, ka), vb = row(rb, p, kb);
+    zx += va.x - vb.y;
+    zy += va.y + vb.x;
+  }
+  int p0 = (gx - s) % gx;
+  if (p0 == 0) p0 = gx;
+  for (int p = p0; p < hx; p += gx) {
+    const cpx<R> va = conjg(row(ra, p, ka)), vb = conjg(row(rb, p, kb));
+    zx += va.x - vb.y;
+    zy += va.y + vb.x;
+  }
+  return mk(zx, zy);
+}
+
 // Coefficient x pass in plane layout for the lengths of the workgroup
 // transforms: coef[c][wy][wx] with c = l Fv + f for volume field f of layer l
 // and c = L Fv + s for surface field s (the coefficient index of the
@@ -404,15 +437,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 3
     const int f = job / A.nl, l = job - f * A.nl;
     return l * A.nvol + f;
   };
+  const R kunit = (R)(2.0 * M_PI / G.lx);
+  // the row a job's transform reads (its alias's for an x derivative) and
+  // the i kx factor applied to it
+  auto src_row = [&](int job, R& k) -> const C* {
+    int j = job;
+    k = (R)0;
+    if (job < A.nvol * A.nl) {
+      const int f = job / A.nl;
+      if (A.alias[f] >= 0) {
+        j = A.alias[f] * A.nl + (job - f * A.nl);
+        k = kunit;
+      }
+    }
+    return inter + ((size_t)j * A.wy + r) * G.nxh;
+  };
   for (int pi = blockIdx.y * ppb; pi < pe; ++pi) {
     const int ja = 2 * pi;
     const bool hasb = ja + 1 < njobs;
-    const C* ra = inter + ((size_t)ja * A.wy + r) * G.nxh;
-    const C* rb = hasb ? ra + (size_t)A.wy * G.nxh : nullptr;
+    R ka, kb = (R)0;
+    const C* ra = src_row(ja, ka);
+    const C* rb = hasb ? src_row(ja + 1, kb) : nullptr;
 #pragma unroll 4
     for (int t = 0; t < T; ++t) {
       const int s = tid + 256 * t;
-      buf[grp_in<N>(s)] = gather_x<R>(ra, rb, s, N, hx);
+      buf[grp_in<N>(s)] = gather_x_dx<R>(ra, rb, s, N, hx, ka, kb);
     }
     grp_fft<R, N>(buf, tw, +1);
     float* oa = coef + (size_t)cidx(ja) * plane + (size_t)r * A.wx;
@@ -803,6 +852,7 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
       A.sid[f] = k;
     }
   }
+  for (int f = 0; f < kMaxEvFields; ++f) A.alias[f] = -1;
   const bool use_skel = pre && skel && skel->R > 0;
   A.z = use_skel ? skel->zeta : zdev;
   A.nl = use_skel ? skel->R : gd->nl;
@@ -845,13 +895,30 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
   TwiddleCache& tc = h->tw;
   FftPlan py = (w->ext_twy && w->ext_gy == A.gy) ? TwiddleCache::plan_with(A.gy, w->ext_twy) : tc.get(A.gy, sizeof(R) == 8);
   FftPlan px = (w->ext_twx && w->ext_gx == A.gx) ? TwiddleCache::plan_with(A.gx, w->ext_twx) : tc.get(A.gx, sizeof(R) == 8);
+  int naliased = 0;
+  if constexpr (sizeof(R) == 4) {
+    // workgroup y pass and plane x pass: an x-derivative field reuses the y
+    // transform of the field of the same source and vertical factor
+    const bool ygrp = h->G.ny > 1 && grp_len_ok(py.n) && py.n >= h->G.ny && (h->G.ny + 255) / 256 <= 4;
+    const bool xplane = pre && !use_skel && grp_len_ok(px.n);
+    if (ygrp && xplane)
+      for (int f = 0; f < A.nvol; ++f) {
+        if (A.f[f].mult != 1) continue;
+        for (int g = 0; g < A.nvol; ++g)
+          if (A.f[g].mult == 0 && A.f[g].vf == A.f[f].vf && A.sid[g] == A.sid[f] && A.alias[g] < 0) {
+            A.alias[f] = g;
+            ++naliased;
+            break;
+          }
+      }
+  }
   if (h->prof.on) {
     // compulsory: each distinct spectrum read once, the window rows written
     // once and read once by the x pass, the outputs written once; model: the
     // two-pass transform bytes of every (field, layer) job on the refined grid
     int nsrc = 0;
     for (int f = 0; f < A.nvol + A.nsurf; ++f) nsrc = std::max(nsrc, A.sid[f] + 1);
-    const double rows = (double)njobs * A.wy * h->G.nxh * csz;
+    const double rows = (double)(njobs - naliased * A.nl) * A.wy * h->G.nxh * csz;
     const double outb = (double)(pre ? A.nvol * gd->nl + A.nsurf : (size_t)(nvo * gd->nl + nso)) * plane * 4.0;
     const double tb = (double)njobs * 2.0 * sizeof(R) * (double)A.gx * A.gy;
     h->prof.bytes[SWENSE_K_YINV_EVAL] += (double)nsrc * h->nc * sizeof(cd) + rows;
