@@ -882,10 +882,10 @@ struct Rows3 {
 
 // Forward transform of the per-point results already in buf (real part o0,
 // imaginary part o1) and the kept modes of the two real rows to out0/out1.
-template <typename R, int Q, int NT>
+template <typename R, int Q, int NT, bool HT = true>
 __device__ __forceinline__ void rows3_out(cpx<R>* buf, const cpx<R>* tw, const XArgs& A, const Geom& G, int y) {
   constexpr int Px = 3 * Q;
-  block3_fft<R, Q, NT>(buf, tw, -1);
+  block3_fft<R, Q, NT, HT>(buf, tw, -1);
   const int hx = G.nx / 2;
   const R sc = (R)(0.5 / (double)Px);
   cpx<R>* d0 = reinterpret_cast<cpx<R>*>(A.out0);
@@ -913,6 +913,9 @@ __device__ __forceinline__ void rows3_out(cpx<R>* buf, const cpx<R>* tw, const X
 template <typename R, int Q, int NT, bool FT>
 __global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan plan) {
   using Rw = Rows3<R, Q, NT>;
+  // twiddles read ahead at 3072 points (measured faster); not with the extra
+  // per-point state of FT, which leaves no registers for them
+  constexpr bool HT = Q >= 1024 && !FT;
   constexpr int PPT = Rw::PPT;
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
@@ -937,7 +940,7 @@ __global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan pla
     const int ib = 2 * pi + 1 < A.nin ? 2 * pi + 1 : -1;
     rows.store(buf, A, G, 2 * pi, ib);
     if (pi + 1 < npairs) rows.load(A, G, y, 2 * pi + 2, 2 * pi + 3 < A.nin ? 2 * pi + 3 : -1);
-    block3_fft<R, Q, NT>(buf, tw, +1);
+    block3_fft<R, Q, NT, HT>(buf, tw, +1);
     const int i1 = min(A.nin, 2 * pi + 2);
     for (int i = 2 * pi; i < i1; ++i) {
       const int code = s_code[i];
@@ -973,7 +976,7 @@ __global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan pla
     }
     buf[b3_in<Q>(tid + NT * j)] = mk(o, (R)0);
   }
-  rows3_out<R, Q, NT>(buf, tw, A, G, y);
+  rows3_out<R, Q, NT, HT>(buf, tw, A, G, y);
 }
 
 // Final stage of the x pass on rows of 3Q points, in the same form.  The
@@ -1018,7 +1021,7 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
       rows.store(buf, A, G, 2 * pi, 2 * pi + 1 < ng ? 2 * pi + 1 : -1);
       if (pi + 1 < np1) rows.load(A, G, y, 2 * pi + 2, 2 * pi + 3 < ng ? 2 * pi + 3 : -1);
       else if (ng < A.nin) rows.load(A, G, y, ng, ng + 1);
-      block3_fft<R, Q, NT>(buf, tw, +1);
+      block3_fft<R, Q, NT, false>(buf, tw, +1);
       const int i1 = min(ng, 2 * pi + 2);
       for (int i = 2 * pi; i < i1; ++i) {
         const int code = s_code[i];
@@ -1061,7 +1064,7 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
   for (int i = ng; i < A.nin; i += 2) {
     rows.store(buf, A, G, i, i + 1);
     if (i + 2 < A.nin) rows.load(A, G, y, i + 2, i + 3);
-    block3_fft<R, Q, NT>(buf, tw, +1);
+    block3_fft<R, Q, NT, false>(buf, tw, +1);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const C zx = buf[b3_out<Q>(tid + NT * j)];
@@ -1073,7 +1076,7 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
   }
 #pragma unroll
   for (int j = 0; j < PPT; ++j) buf[b3_in<Q>(tid + NT * j)] = mk(o0[j], o1[j]);
-  rows3_out<R, Q, NT>(buf, tw, A, G, y);
+  rows3_out<R, Q, NT, false>(buf, tw, A, G, y);
 }
 
 // Physical rows <-> spectra on the mode grid (FP64, state in/out only).

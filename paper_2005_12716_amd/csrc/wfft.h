@@ -165,7 +165,11 @@ __device__ void wave_fft(cpx<R>* buf, const WPlan& plan, int sign, int lane) {
 // passes with Ns = 1, 16, 256, then one radix 2/4/8/16 pass.  Every stride is
 // a constant, so the skewed LDS addresses reduce to one base register plus
 // immediate offsets.
-template <typename R, int N, int RAD, int NS, int TS = 1>
+// HT: read the pass's twiddles before its LDS loads, so that their latency
+// overlaps the loads (the wavefront fence after them keeps the compiler from
+// issuing later global reads early); costs the registers that hold them, so
+// it is chosen per kernel.
+template <typename R, int N, int RAD, int NS, int TS = 1, bool HT = false>
 __device__ __forceinline__ void spass(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int lane) {
   constexpr int NB = N / RAD;
   constexpr int MB = (NB + 63) / 64;
@@ -173,6 +177,17 @@ __device__ __forceinline__ void spass(cpx<R>* buf, const cpx<R>* __restrict__ tw
   static_assert(16 % RAD == 0 || RAD == 16, "radix must divide 16");
   static_assert(NS == 1 || NS % 16 == 0, "pass stride must be 1 or a multiple of 16");
   cpx<R> v[MB][RAD];
+  // twiddles read before the LDS loads: the wavefront fence after those
+  // loads keeps later global reads from being issued early
+  cpx<R> tws[MB][NS > 1 && HT ? RAD : 1];
+  if constexpr (NS > 1 && HT) {
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      const int k = (lane + 64 * m) & (NS - 1);
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) tws[m][r] = tw[k * r * TWS * TS];
+    }
+  }
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
     const int j = lane + 64 * m;
@@ -194,12 +209,16 @@ __device__ __forceinline__ void spass(cpx<R>* buf, const cpx<R>* __restrict__ tw
     const int j = lane + 64 * m;
     if (NB % 64 == 0 || j < NB) {
       const int k = j & (NS - 1);
-      if (NS > 1 && k > 0) {
+      if constexpr (NS > 1) {
+        if (k > 0) {
 #pragma unroll
-        for (int r = 1; r < RAD; ++r) {
-          cpx<R> w = tw[k * r * TWS * TS];
-          if (sign > 0) w.y = -w.y;
-          v[m][r] = cmul(v[m][r], w);
+          for (int r = 1; r < RAD; ++r) {
+            cpx<R> w;
+            if constexpr (HT) w = tws[m][r];
+            else w = tw[k * r * TWS * TS];
+            if (sign > 0) w.y = -w.y;
+            v[m][r] = cmul(v[m][r], w);
+          }
         }
       }
       dft_any<R, RAD>(v[m], sign);
@@ -220,18 +239,18 @@ __device__ __forceinline__ void spass(cpx<R>* buf, const cpx<R>* __restrict__ tw
 }
 
 // TS: stride of the twiddle table (the N TS-point table of a larger transform).
-template <typename R, int N, int TS = 1>
+template <typename R, int N, int TS = 1, bool HT = false>
 __device__ __forceinline__ void wave_fft_static(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int lane) {
   static_assert(N >= 64 && N <= 4096 && (N & (N - 1)) == 0, "power of two in [64, 4096]");
-  spass<R, N, 16, 1, TS>(buf, tw, sign, lane);
-  if constexpr (N == 64) spass<R, N, 4, 16, TS>(buf, tw, sign, lane);
-  else if constexpr (N == 128) spass<R, N, 8, 16, TS>(buf, tw, sign, lane);
+  spass<R, N, 16, 1, TS, HT>(buf, tw, sign, lane);
+  if constexpr (N == 64) spass<R, N, 4, 16, TS, HT>(buf, tw, sign, lane);
+  else if constexpr (N == 128) spass<R, N, 8, 16, TS, HT>(buf, tw, sign, lane);
   else {
-    spass<R, N, 16, 16, TS>(buf, tw, sign, lane);
-    if constexpr (N == 512) spass<R, N, 2, 256, TS>(buf, tw, sign, lane);
-    else if constexpr (N == 1024) spass<R, N, 4, 256, TS>(buf, tw, sign, lane);
-    else if constexpr (N == 2048) spass<R, N, 8, 256, TS>(buf, tw, sign, lane);
-    else if constexpr (N == 4096) spass<R, N, 16, 256, TS>(buf, tw, sign, lane);
+    spass<R, N, 16, 16, TS, HT>(buf, tw, sign, lane);
+    if constexpr (N == 512) spass<R, N, 2, 256, TS, HT>(buf, tw, sign, lane);
+    else if constexpr (N == 1024) spass<R, N, 4, 256, TS, HT>(buf, tw, sign, lane);
+    else if constexpr (N == 2048) spass<R, N, 8, 256, TS, HT>(buf, tw, sign, lane);
+    else if constexpr (N == 4096) spass<R, N, 16, 256, TS, HT>(buf, tw, sign, lane);
   }
 }
 
@@ -261,12 +280,21 @@ template <int Q>
 __device__ __forceinline__ int b4_out(int k) { return (k / Q) * (Q + Q / 16 + 1) + sk(k % Q); }
 
 // One Stockham pass of a length-Q wavefront transform, twiddles tw[TS m].
-template <typename R, int Q, int RAD, int NS, int TS>
+template <typename R, int Q, int RAD, int NS, int TS, bool HT = false>
 __device__ __forceinline__ void qpass(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int lane) {
   constexpr int NB = Q / RAD;
   constexpr int MB = (NB + 63) / 64;
   constexpr int TWS = Q / (NS * RAD);
   cpx<R> v[MB][RAD];
+  cpx<R> tws[MB][NS > 1 && HT ? RAD : 1];  // twiddles read before the LDS loads (HT)
+  if constexpr (NS > 1 && HT) {
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      const int k = (lane + 64 * m) & (NS - 1);
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) tws[m][r] = tw[k * r * TWS * TS];
+    }
+  }
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
     const int j = lane + 64 * m;
@@ -281,12 +309,16 @@ __device__ __forceinline__ void qpass(cpx<R>* buf, const cpx<R>* __restrict__ tw
     const int j = lane + 64 * m;
     if (NB % 64 == 0 || j < NB) {
       const int k = j & (NS - 1);
-      if (NS > 1 && k > 0) {
+      if constexpr (NS > 1) {
+        if (k > 0) {
 #pragma unroll
-        for (int r = 1; r < RAD; ++r) {
-          cpx<R> w = tw[k * r * TWS * TS];
-          if (sign > 0) w.y = -w.y;
-          v[m][r] = cmul(v[m][r], w);
+          for (int r = 1; r < RAD; ++r) {
+            cpx<R> w;
+            if constexpr (HT) w = tws[m][r];
+            else w = tw[k * r * TWS * TS];
+            if (sign > 0) w.y = -w.y;
+            v[m][r] = cmul(v[m][r], w);
+          }
         }
       }
       dft_any<R, RAD>(v[m], sign);
@@ -298,26 +330,26 @@ __device__ __forceinline__ void qpass(cpx<R>* buf, const cpx<R>* __restrict__ tw
   wave_sync();
 }
 
-template <typename R, int Q, int TS, int NS = 1>
+template <typename R, int Q, int TS, int NS = 1, bool HT = false>
 __device__ __forceinline__ void wave_fft_r4(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int lane) {
   if constexpr (NS * 4 <= Q) {
-    qpass<R, Q, 4, NS, TS>(buf, tw, sign, lane);
-    wave_fft_r4<R, Q, TS, NS * 4>(buf, tw, sign, lane);
+    qpass<R, Q, 4, NS, TS, HT>(buf, tw, sign, lane);
+    wave_fft_r4<R, Q, TS, NS * 4, HT>(buf, tw, sign, lane);
   } else if constexpr (NS * 2 == Q) {
-    qpass<R, Q, 2, NS, TS>(buf, tw, sign, lane);
+    qpass<R, Q, 2, NS, TS, HT>(buf, tw, sign, lane);
   }
 }
 
 // All 256 threads of the workgroup must call this; it starts with a block
 // barrier (the inputs may have been written by any thread) and ends with one.
-template <typename R, int N>
+template <typename R, int N, bool HT = false>
 __device__ __forceinline__ void block4_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign) {
   constexpr int Q = N / 4;
   static_assert(Q >= 64 && Q <= 1024 && (Q & (Q - 1)) == 0, "N = 4Q with Q a power of two in [64, 1024]");
   constexpr int WL = Q + Q / 16 + 1;
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
   __syncthreads();
-  wave_fft_r4<R, Q, 4>(buf + wave * WL, tw, sign, lane);
+  wave_fft_r4<R, Q, 4, 1, HT>(buf + wave * WL, tw, sign, lane);
   __syncthreads();
 #pragma unroll
   for (int k0 = 0; k0 < Q; k0 += 256) {
@@ -387,14 +419,14 @@ __device__ __forceinline__ void wave_fft3(cpx<R>* buf, const cpx<R>* __restrict_
 // The workgroup (NT threads, all must call; NT a multiple of 64, at least
 // 192): wavefronts 0-2 take one sub-transform each, every thread combines.
 // Starts and ends with a block barrier.
-template <typename R, int Q, int NT = 256>
+template <typename R, int Q, int NT = 256, bool HT = false>
 __device__ __forceinline__ void block3_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign) {
   static_assert(Q >= 64 && Q <= 1024 && (Q & (Q - 1)) == 0, "N = 3Q with Q a power of two in [64, 1024]");
   static_assert(NT % 64 == 0 && NT >= 192, "three wavefronts at least");
   constexpr int WL = Q + Q / 16 + 1;
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
   __syncthreads();
-  if (wave < 3) wave_fft_static<R, Q, 3>(buf + wave * WL, tw, sign, lane);
+  if (wave < 3) wave_fft_static<R, Q, 3, HT>(buf + wave * WL, tw, sign, lane);
   __syncthreads();
 #pragma unroll
   for (int k0 = 0; k0 < Q; k0 += NT) {

@@ -29,7 +29,11 @@ __device__ __forceinline__ int grp_out(int k) {
 }
 template <typename R, int N>
 __device__ __forceinline__ void grp_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign) {
-  if constexpr (N % 3 == 0) block3_fft<R, N / 3>(buf, tw, sign); else block4_fft<R, N>(buf, tw, sign);
+  // twiddles read ahead of each pass's LDS loads for the long transforms
+  // (measured faster at 3072 and 4096 points; the shorter ones keep their
+  // occupancy instead)
+  constexpr bool HT = N >= 3072;
+  if constexpr (N % 3 == 0) block3_fft<R, N / 3, 256, HT>(buf, tw, sign); else block4_fft<R, N, HT>(buf, tw, sign);
 }
 
 #define SW_B4_DISPATCH(n, LAUNCH) \

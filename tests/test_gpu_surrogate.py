@@ -243,8 +243,10 @@ def test_drift_bound_stops_learned_calls(gpu_lib):
     net.set(_with_output(lib, vec, desc, shift))
     st = sur.advance(8)
     assert st["surrogate_calls"] == 4 and st["audits"] == 1 and st["bound_calls"] == 4 and st["hos_calls"] == 4, st
-    assert st["max_audit_err"] == e1
-    assert st["drift_est"] == pytest.approx(3 * e1, rel=1e-12)
+    # the judged error is a sum reduced across blocks in no fixed order: the
+    # same call's error agrees with the first run's to rounding
+    assert st["max_audit_err"] == pytest.approx(e1, rel=1e-9)
+    assert st["drift_est"] == pytest.approx(3 * st["max_audit_err"], rel=1e-12)
     e, p, t = h.state()
     er, pr, tr = _hos_ref(lib, d, eh, ph, 8 * S)
     off = _rel_state(e, p, er, pr)
