@@ -979,9 +979,11 @@ __global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan pla
   rows3_out<R, Q, NT, HT>(buf, tw, A, G, y);
 }
 
-// Final stage of the x pass on rows of 3Q points, in the same form.  The
-// host orders the inputs as eta and the W terms first (A.ng of them), then
-// the gradient pairs (each XR_GRADPAIR followed by its partner).  Phase one
+// Final stage of the x pass on rows of 3Q points, in the same form but with
+// each pair's rows read just before they are stored (no read-ahead: the
+// registers go to the per-point state).  The host orders the inputs as eta
+// and the W terms first (A.ng of them), then the gradient pairs (each
+// XR_GRADPAIR followed by its partner).  Phase one
 // holds eta and W_1 .. W_M (M <= MW) per point; once the W are complete they
 // are folded into the two outputs and the two multipliers of |grad eta|^2,
 // so that phase two adds each gradient pair straight into the outputs:
@@ -1007,7 +1009,6 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
   }
   R o0[PPT], o1[PPT], c2[PPT], s2[PPT];
   Rw rows;
-  rows.load(A, G, y, 0, 1 < ng ? 1 : -1);
   {
     R eta[PPT], W[PPT][MW];
 #pragma unroll
@@ -1018,9 +1019,8 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
     }
     const int np1 = (ng + 1) / 2;
     for (int pi = 0; pi < np1; ++pi) {
+      rows.load(A, G, y, 2 * pi, 2 * pi + 1 < ng ? 2 * pi + 1 : -1);
       rows.store(buf, A, G, 2 * pi, 2 * pi + 1 < ng ? 2 * pi + 1 : -1);
-      if (pi + 1 < np1) rows.load(A, G, y, 2 * pi + 2, 2 * pi + 3 < ng ? 2 * pi + 3 : -1);
-      else if (ng < A.nin) rows.load(A, G, y, ng, ng + 1);
       block3_fft<R, Q, NT, false>(buf, tw, +1);
       const int i1 = min(ng, 2 * pi + 2);
       for (int i = 2 * pi; i < i1; ++i) {
@@ -1060,11 +1060,13 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
       s2[j] = M >= 4 ? (R)0.5 * w2sum_n<MW>(W[j], M - 2) : (R)0;
     }
   }
+  // phase two and the output transform hold less per point: their passes
+  // read the twiddles ahead of the LDS loads
   const R dm = M >= 2 ? (R)1 : (R)0;
   for (int i = ng; i < A.nin; i += 2) {
+    rows.load(A, G, y, i, i + 1);
     rows.store(buf, A, G, i, i + 1);
-    if (i + 2 < A.nin) rows.load(A, G, y, i + 2, i + 3);
-    block3_fft<R, Q, NT, false>(buf, tw, +1);
+    block3_fft<R, Q, NT, true>(buf, tw, +1);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const C zx = buf[b3_out<Q>(tid + NT * j)];
@@ -1076,7 +1078,7 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
   }
 #pragma unroll
   for (int j = 0; j < PPT; ++j) buf[b3_in<Q>(tid + NT * j)] = mk(o0[j], o1[j]);
-  rows3_out<R, Q, NT, false>(buf, tw, A, G, y);
+  rows3_out<R, Q, NT, true>(buf, tw, A, G, y);
 }
 
 // Physical rows <-> spectra on the mode grid (FP64, state in/out only).
