@@ -316,7 +316,7 @@ def hos_model_bytes(kernels, m, px, py):
     return kernels
 
 
-def roofline_of(kernels):
+def roofline_of(kernels, traffic_file=False):
     """Roofline entry of the dominant kernel class (largest share of the
     profiled step): achieved = algorithmic bytes per launch under the
     two-pass transform model (the HOS, evaluation and gather byte model) /
@@ -329,7 +329,7 @@ def roofline_of(kernels):
     ach = d["model_bytes_per_launch"] / t / 1e9
     comp = d["compulsory_bytes_per_launch"] / t / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-            "frac": ach / (PEAK_HBM / 1e9), "traffic": measured_traffic(dom),
+            "frac": ach / (PEAK_HBM / 1e9), "traffic": measured_traffic(dom) if traffic_file else None,
             "byte_model": ("two-pass transform bytes: every real transform of the step (4 right-hand sides + the "
                            "mean-level modes; evaluation: every (field, layer) job on the refined grid) streams its "
                            "grid field once per pass, read and written; gather: 16 B + 4 B per field per point + grid"),
@@ -704,6 +704,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-trajectories", type=int, default=100)
     ap.add_argument("--surrogate-iters", type=int, default=1000)
+    ap.add_argument("--only", choices=["cylinder", "regular_wave_2d", "batched", "surrogate"], default=None,
+                    help="run one secondary configuration alone and print its record (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 256 MiB device copies (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -720,6 +722,17 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the workload is a single "
               "realisation and the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        import torch
+        from paper_2005_12716_amd import lib
+        torch.cuda.set_device(0)
+        run = {"cylinder": lambda: run_cylinder(lib, torch, max(20, args.steps), args.warmup),
+               "regular_wave_2d": lambda: run_regular_2d(lib, torch, args.steps),
+               "batched": lambda: run_batched(lib, torch, max(2, args.steps // 4)),
+               "surrogate": lambda: run_surrogate(lib, torch, max(5, args.steps), args.surrogate_trajectories,
+                                                  args.surrogate_iters)}[args.only]
+        print(json.dumps({args.only: run()}))
+        return
 
     # the oracle first, before anything touches the GPU, so that its pool
     # workers fork from a process without a GPU context
@@ -765,7 +778,7 @@ def main():
         "hos_mode_steps_per_s": N5 * N5 * 1e3 / st["ms_hos"],
         "interp_eval_ms": st["ms_interp"],
         "bind_s": st["bind_s"],
-        "roofline": roofline_of(st["kernels"]),
+        "roofline": roofline_of(st["kernels"], traffic_file=True),
         "kernels": st["kernels"],
     }
     if not args.no_extra:
