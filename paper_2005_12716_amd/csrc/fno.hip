@@ -402,7 +402,7 @@ __global__ void __launch_bounds__(256) k_fno_fx(const float* __restrict__ v, cf*
   const float* c = a + (size_t)N * N;
   for (int x = lane; x < N; x += 64) buf[sk(x)] = mk(a[x], c[x]);
   wave_sync();
-  wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N>(buf, plan, -1, lane);
+  wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N, true>(buf, plan, -1, lane);
   const float sc = 0.5f;
   for (int p = lane; p < d.P; p += 64) {
     const cf zp = buf[sk(p)], zm = conjg(buf[sk((N - p) % N)]);
@@ -426,7 +426,7 @@ __global__ void __launch_bounds__(256) k_fno_fy(const cf* __restrict__ xi, cf* _
   const cf* src = xi + ((size_t)b * d.C + c) * N * d.P + p;
   for (int y = lane; y < N; y += 64) buf[sk(y)] = src[(size_t)y * d.P];
   wave_sync();
-  wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N>(buf, plan, -1, lane);
+  wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N, true>(buf, plan, -1, lane);
   const float s = scale * ((cp_flag && p > 0) ? 2.f : 1.f);
   const int nq = nq_of(d);
   for (int a = lane; a < nq; a += 64) {
@@ -483,7 +483,7 @@ __global__ void __launch_bounds__(256) k_fno_iy(const cf* __restrict__ Y, cf* __
     buf[sk((q + N) % N)] = Y[((size_t)b * nq * d.P + (size_t)a * d.P + p) * d.C + c];
   }
   wave_sync();
-  wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N>(buf, plan, +1, lane);
+  wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N, true>(buf, plan, +1, lane);
   cf* dst = xi + ((size_t)b * d.C + c) * N * d.P + p;
   for (int y = lane; y < N; y += 64) dst[(size_t)y * d.P] = buf[sk(y)];
 }
@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(256) k_fno_ix(const cf* __restrict__ xi, float
     buf[sk(s)] = z;
   }
   wave_sync();
-  wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N>(buf, plan, +1, lane);
+  wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N, true>(buf, plan, +1, lane);
   float* oa = out + (((size_t)b * d.C + 2 * cp) * N + row) * N;
   float* ob = oa + (size_t)N * N;
   for (int x = lane; x < N; x += 64) {

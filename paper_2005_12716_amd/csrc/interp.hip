@@ -315,18 +315,60 @@ __global__ void __launch_bounds__(kTileThreads) k_gather_tile(GatherArgs A, Tile
       }
       return acc;
     };
-    // one field at a time (registers: one field's 64 taps in flight); the
-    // pressure's inputs are kept as they pass
     float pt = 0.f, u = 0.f, vv = 0.f, w = 0.f;
-#pragma unroll 1
-    for (int f = 0; f < A.fv; ++f) {
-      const float v = vol(f);
+    auto put = [&](int f, float v) {
       const int o = A.vslot[f];
       if (o >= 0) A.out[(size_t)o * n + orig] = v;
       pt = f == A.c_phit ? v : pt;
       u = f == A.c_u ? v : u;
       vv = f == A.c_v ? v : vv;
       w = f == A.c_w ? v : w;
+    };
+    if (fv == 8 && (T.stride & 3) == 0) {
+      // all 8 volume fields: each (node, layer) record read as two 16-byte
+      // loads, the 8 fields accumulated together
+      float acc[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[k] = 0.f;
+      auto pick = [](const float* w4, int i) { return i == 0 ? w4[0] : i == 1 ? w4[1] : i == 2 ? w4[2] : w4[3]; };
+#pragma unroll 1
+      for (int b = 0; b < (THREE ? 4 : 1); ++b) {
+        float rb[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) rb[k] = 0.f;
+#pragma unroll 1
+        for (int a = 0; a < 4; ++a) {
+          const float4* q = reinterpret_cast<const float4*>(nb + (b * T.sx + a) * T.stride + lo * 8);
+          float rl[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) rl[k] = 0.f;
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {
+            const float4 v0 = q[2 * l], v1 = q[2 * l + 1];
+            rl[0] += wz[l] * v0.x;
+            rl[1] += wz[l] * v0.y;
+            rl[2] += wz[l] * v0.z;
+            rl[3] += wz[l] * v0.w;
+            rl[4] += wz[l] * v1.x;
+            rl[5] += wz[l] * v1.y;
+            rl[6] += wz[l] * v1.z;
+            rl[7] += wz[l] * v1.w;
+          }
+          const float wa = pick(wx, a);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) rb[k] += wa * rl[k];
+        }
+        const float wb = pick(wy, b);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += wb * rb[k];
+      }
+#pragma unroll
+      for (int f = 0; f < 8; ++f) put(f, acc[f]);
+    } else {
+      // one field at a time (registers: one field's 64 taps in flight); the
+      // pressure's inputs are kept as they pass
+#pragma unroll 1
+      for (int f = 0; f < A.fv; ++f) put(f, vol(f));
     }
 #pragma unroll 1
     for (int s2 = 0; s2 < A.fs; ++s2) {
@@ -598,6 +640,17 @@ bool build_skeleton(const std::vector<double>& z, double kmax, double depth, dou
   }
 }
 
+// LDS floats per staged node of the tiled gather: odd (the scalar reads of
+// neighbouring nodes then fall in different banks), or, with all 8 volume
+// fields, a multiple of 4 that is not a multiple of 8 so that each (node,
+// layer) record of 8 fields is two aligned 16-byte reads.
+long long tile_stride(int fv, int tl, int fs) {
+  const long long rec = (long long)fv * tl + fs;
+  if (fv != 8) return rec | 1;
+  long long s4 = (rec + 3) & ~3ll;
+  return (s4 & 7) ? s4 : s4 + 4;
+}
+
 // Tile shape of the tiled gather: the candidate (tile of stencil start
 // nodes, band of first layers) with the least staged data over the cloud's
 // own bins (a sample of at most ~400k points), each item charged the cache
@@ -623,7 +676,7 @@ void choose_tile(swense_cells* c, const std::vector<int>& ixs, const std::vector
     for (int TL : tls) {
       if (TL > nl - 3) continue;
       const int tl = std::min(TL + 3, nl);
-      const long long stride = (long long)(fv * tl + fs) | 1;
+      const long long stride = tile_stride(fv, tl, fs);
       const long long nodes = (long long)(T + 3) * (three ? T + 3 : 1);
       const long long lds = nodes * (stride + 1) * 4;
       if (lds > 53 * 1024) continue;
@@ -1003,7 +1056,7 @@ void interp_body(swense_hos* h, swense_cells* c, unsigned mask, float* out, floa
   if (c->tiled) {
     const bool three = h->G.ny > 1;
     TileDev T{c->items, c->hxy, c->txy, c->nitems, c->tile + 3, three ? c->tile + 3 : 1, 0};
-    T.stride = (L.fv * std::min(c->tile_l + 3, L.nl) + L.fs) | 1;
+    T.stride = (int)tile_stride(L.fv, std::min(c->tile_l + 3, L.nl), L.fs);
     const size_t lds = (size_t)T.sx * T.sy * (T.stride + 1) * sizeof(float);
     SW_REQUIRE(lds <= 64 * 1024, "tile block too large for LDS");
     if (three)

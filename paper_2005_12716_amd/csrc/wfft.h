@@ -255,9 +255,9 @@ __device__ __forceinline__ void wave_fft_static(cpx<R>* buf, const cpx<R>* __res
 }
 
 // Transform with compile-time length NS0 when NS0 > 0, else the runtime plan.
-template <typename R, int MAXE, int NS0>
+template <typename R, int MAXE, int NS0, bool HT = false>
 __device__ __forceinline__ void wave_fft_any(cpx<R>* buf, const WPlan& plan, int sign, int lane) {
-  if constexpr (NS0 > 0) wave_fft_static<R, NS0>(buf, reinterpret_cast<const cpx<R>*>(plan.tw), sign, lane);
+  if constexpr (NS0 > 0) wave_fft_static<R, NS0, 1, HT>(buf, reinterpret_cast<const cpx<R>*>(plan.tw), sign, lane);
   else wave_fft<R, MAXE>(buf, plan, sign, lane);
 }
 
