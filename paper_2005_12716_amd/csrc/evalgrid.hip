@@ -191,6 +191,116 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 3
   }
 }
 
+// Residue form of the zero-padded y pass, for grid lengths N = RS ny (RS in
+// {2, 3, 4}, ny a power of two): with y = RS s + r the inverse transform
+// splits into RS independent ny-point transforms,
+//   X[RS s + r] = sum_q (x_q e^{2 pi i q r / N}) e^{2 pi i q s / ny},
+// one per residue r, so wavefront r transforms the modulated modes in its own
+// buffer (no zero entries, no combine, no block barrier inside the
+// transform) and stores the window rows y = r (mod RS).  Same per-mode
+// values, factors and fields as k_yinv_eval_g.  The passes read their
+// twiddles after the LDS loads here: the registers go to occupancy (three
+// waves per SIMD at 1024 modes; measured 2.3 against 2.6 ms with them read
+// ahead at two).
+template <int RS, int NY, int TQ>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NY >= 1024 ? 3 : 4))) k_yinv_eval_r(
+    EvArgs A, Geom G, const cpx<float>* __restrict__ tw) {
+  static_assert(RS >= 2 && RS <= 4 && TQ * 256 >= NY, "residues and modes per thread");
+  constexpr int N = RS * NY;
+  constexpr int WL = NY + NY / 16 + 1;
+  using C = cpx<float>;
+  extern __shared__ unsigned char smem[];
+  C* buf = reinterpret_cast<C*>(smem);
+  const int p = xcd_tile(blockIdx.x, gridDim.x);
+  const int l = A.nvol > 0 ? (int)blockIdx.y : A.nl;
+  const bool surf = l == A.nl;
+  const int f0 = surf ? A.nvol : 0, f1 = surf ? A.nvol + A.nsurf : A.nvol;
+  const int tid = threadIdx.x, half = G.ny / 2;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const bool col = p < G.nxh && 2 * p != G.nx;
+  const int s0 = A.sid[f0];
+  int s1 = s0;
+  for (int f = f0; f < f1; ++f)
+    if (A.sid[f] != s0) s1 = A.sid[f];
+  cpx<float> v0[TQ], v1[TQ], md[TQ];  // md: e^{2 pi i qs / N}; residue r takes its r-th power
+  float fc[TQ], fsn[TQ];
+  const double kx = 2.0 * M_PI * (double)p / G.lx;
+  const double bx = A.pre ? (4.0 + 2.0 * cos(2.0 * M_PI * (double)p / (double)A.gx)) / 6.0 : 1.0;
+  const double z = surf ? 0.0 : A.z[l];
+  const double kys = 2.0 * M_PI / G.ly;
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) {
+    const int q = tid + 256 * t;
+    const int qs = q >= half ? q - G.ny : q;
+    const bool ok = col && q < G.ny && qs > -half;
+    const cd a = ok ? A.srcs[s0][(size_t)q * G.nxh + p] : mk(0.0, 0.0);
+    const cd b = ok ? A.srcs[s1][(size_t)q * G.nxh + p] : mk(0.0, 0.0);
+    v0[t] = mk((float)a.x, (float)a.y);
+    v1[t] = mk((float)b.x, (float)b.y);
+    // modulation e^{+2 pi i qs / N} (the table holds e^{-2 pi i m / N})
+    const C w = tw[(qs + N) % N];
+    md[t] = mk(w.x, -w.y);
+  }
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) {
+    const int q = tid + 256 * t;
+    const int qs = q >= half ? q - G.ny : q;
+    const double ky = kys * (double)qs;
+    double c = 1.0, sn = 1.0;
+    if (!surf) vfactors(sqrt(kx * kx + ky * ky), z, G.depth, c, sn);
+    const double by = A.pre ? (4.0 + 2.0 * cos(2.0 * M_PI * (double)qs / (double)A.gy)) / 6.0 : 1.0;
+    const double pre = 1.0 / (bx * by);
+    fc[t] = (float)(c * pre);
+    fsn[t] = (float)(sn * pre);
+  }
+  const float kxf = (float)kx, kysf = (float)kys;
+  for (int f = f0; f < f1; ++f) {
+    if (A.alias[f] >= 0) continue;  // formed by the x pass from its alias
+    const EvField F = A.f[f];
+    const bool first = A.sid[f] == s0;
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) {
+      const int q = tid + 256 * t;
+      if (q >= NY) continue;
+      const int qs = q >= half ? q - G.ny : q;
+      cpx<float> w = mk(0.f, 0.f);
+      if (col && q < G.ny && qs > -half) {
+        const float fac = F.vf == 1 ? fsn[t] : fc[t];
+        const float ky = kysf * (float)qs;
+        cpx<float> m;
+        switch (F.mult) {
+          case 0: m = mk(fac, 0.f); break;
+          case 1: m = mk(0.f, kxf * fac); break;
+          case 2: m = mk(0.f, ky * fac); break;
+          default: m = mk(sqrtf(kxf * kxf + ky * ky) * fac, 0.f); break;
+        }
+        w = cmul(first ? v0[t] : v1[t], m);
+      }
+      const int slot = q;  // qs mod ny (q itself: the mode grid's own index)
+#pragma unroll
+      for (int r = 0; r < RS; ++r) {
+        buf[r * WL + sk(slot)] = w;
+        w = cmul(w, md[t]);
+      }
+    }
+    __syncthreads();
+    const int job = surf ? A.nvol * A.nl + (f - A.nvol) : f * A.nl + l;
+    C* dst = reinterpret_cast<C*>(A.inter) + (size_t)job * A.wy * G.nxh;
+    if (wave < RS) {
+      C* b = buf + wave * WL;
+      wave_fft_static<float, NY, RS, false>(b, tw, +1, lane);
+      // window rows y = iy0 + rr (mod N) with y = wave (mod RS)
+      const int r0 = ((wave - A.iy0) % RS + RS) % RS;
+      for (int rr = r0 + RS * lane; rr < A.wy; rr += RS * 64) {
+        int y = A.iy0 + rr;
+        if (y >= N) y -= N * (y / N);
+        dst[(size_t)rr * G.nxh + p] = b[sk((y - wave) / RS)];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Complex length-gx sequence whose inverse transform is a + i b at the nodes,
 // from two rows of half spectra (x modes p < nx/2), padding or folding.
 template <typename R>
@@ -472,6 +582,107 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 3
       const C zx = buf[grp_out<N>(x)];
       oa[xw] = (float)zx.x;
       if (hasb) ob[xw] = (float)zx.y;
+    }
+    __syncthreads();
+  }
+}
+
+// Residue form of the plane x pass for grid lengths N = RS nx (RS in
+// {2, 3, 4}, nx a power of two): each pair of rows, Hermitian-completed as
+// one complex sequence of nx modes, gives X[RS s + r] as the nx-point
+// transform of its modes times e^{2 pi i p r / N}; wavefront r transforms
+// residue r and stores the window columns x = r (mod RS).  Same jobs,
+// aliases and plane layout as k_xplane_g.
+template <int RS, int NX>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NX >= 1024 ? 3 : 4))) k_xplane_r(
+    EvArgs A, Geom G, const cpx<float>* __restrict__ tw, int njobs, int ppb, float* __restrict__ coef) {
+  static_assert(RS >= 2 && RS <= 4, "residues");
+  constexpr int N = RS * NX;
+  constexpr int WL = NX + NX / 16 + 1;
+  constexpr int PT = (NX / 2 + 255) / 256;  // kept modes p < nx/2 per thread
+  using C = cpx<float>;
+  extern __shared__ unsigned char smem[];
+  C* buf = reinterpret_cast<C*>(smem);
+  const int r = blockIdx.x, hx = G.nx / 2, tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const size_t plane = (size_t)A.wx * A.wy;
+  const C* inter = reinterpret_cast<const C*>(A.inter);
+  const int npair = (njobs + 1) / 2;
+  const int pe = min(npair, (int)(blockIdx.y + 1) * ppb);
+  auto cidx = [&](int job) {
+    if (job >= A.nvol * A.nl) return job;  // surface: L Fv + s
+    const int f = job / A.nl, l = job - f * A.nl;
+    return l * A.nvol + f;
+  };
+  const float kunit = (float)(2.0 * M_PI / G.lx);
+  auto src_row = [&](int job, float& k) -> const C* {
+    int j = job;
+    k = 0.f;
+    if (job < A.nvol * A.nl) {
+      const int f = job / A.nl;
+      if (A.alias[f] >= 0) {
+        j = A.alias[f] * A.nl + (job - f * A.nl);
+        k = kunit;
+      }
+    }
+    return inter + ((size_t)j * A.wy + r) * G.nxh;
+  };
+  // modulation e^{2 pi i p / N} of this thread's modes p (the table holds e^{-2 pi i m / N})
+  C md[PT];
+#pragma unroll
+  for (int t = 0; t < PT; ++t) {
+    const int pp = tid + 256 * t;
+    const C w = tw[pp % N];
+    md[t] = mk(w.x, -w.y);
+  }
+  for (int pi = blockIdx.y * ppb; pi < pe; ++pi) {
+    const int ja = 2 * pi;
+    const bool hasb = ja + 1 < njobs;
+    float ka, kb = 0.f;
+    const C* ra = src_row(ja, ka);
+    const C* rb = hasb ? src_row(ja + 1, kb) : nullptr;
+    // slot p (0 <= p < hx): a + i b; slot nx - p: conj(a) + i conj(b); the
+    // Nyquist slot nx/2 stays zero
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int pp = tid + 256 * t;
+      if (pp < NX / 2) {
+        C va = mk(0.f, 0.f), vb = mk(0.f, 0.f);
+        if (pp < hx) {
+          va = ra[pp];
+          if (rb) vb = rb[pp];
+          if (ka != 0.f) va = mk(-ka * (float)pp * va.y, ka * (float)pp * va.x);
+          if (kb != 0.f) vb = mk(-kb * (float)pp * vb.y, kb * (float)pp * vb.x);
+        }
+        C zp = mk(va.x - vb.y, va.y + vb.x);                       // a + i b at +p
+        C zm = pp > 0 ? mk(va.x + vb.y, vb.x - va.y) : mk(0.f, 0.f);  // conj(a) + i conj(b) at -p
+        const C mc = conjg(md[t]);
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+          buf[q * WL + sk(pp)] = zp;
+          if (pp > 0) buf[q * WL + sk(NX - pp)] = zm;
+          zp = cmul(zp, md[t]);
+          zm = cmul(zm, mc);
+        }
+        if (pp == 0)
+#pragma unroll
+          for (int q = 0; q < RS; ++q) buf[q * WL + sk(NX / 2)] = mk(0.f, 0.f);
+      }
+    }
+    __syncthreads();
+    if (wave < RS) {
+      C* b = buf + wave * WL;
+      wave_fft_static<float, NX, RS, false>(b, tw, +1, lane);
+      float* oa = coef + (size_t)cidx(ja) * plane + (size_t)r * A.wx;
+      float* ob = hasb ? coef + (size_t)cidx(ja + 1) * plane + (size_t)r * A.wx : nullptr;
+      const int x0 = ((wave - A.ix0) % RS + RS) % RS;
+      for (int xw = x0 + RS * lane; xw < A.wx; xw += RS * 64) {
+        int x = A.ix0 + xw;
+        if (x >= N) x -= N;
+        const C zx = b[sk((x - wave) / RS)];
+        oa[xw] = zx.x;
+        if (hasb) ob[xw] = zx.y;
+      }
     }
     __syncthreads();
   }
@@ -931,7 +1142,28 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
   const int tq = (h->G.ny + 255) / 256;
   bool ydone = false;
   if constexpr (sizeof(R) == 4) {
-    if (h->G.ny > 1 && grp_len_ok(py.n) && py.n >= h->G.ny && tq <= 4) {
+    const int ny = h->G.ny, rs = py.n / std::max(ny, 1);
+    if ((ny == 256 || ny == 512 || ny == 1024) && rs >= 2 && rs <= 4 && rs * ny == py.n) {
+      // residue form: one wavefront per output residue y mod rs
+      const size_t lds = (size_t)rs * (ny + ny / 16 + 1) * csz;
+      dim3 grid(h->G.nxh, (A.nvol > 0 ? A.nl : 0) + (A.nsurf > 0 ? 1 : 0));
+      const cpx<float>* twy = reinterpret_cast<const cpx<float>*>(py.tw);
+#define L_YR(RS, NY) sw_launch(h, SWENSE_K_YINV_EVAL, &k_yinv_eval_r<RS, NY, NY / 256>, grid, dim3(256), lds, h->st, A, h->G, twy)
+#define L_YRN(RS)                  \
+  switch (ny) {                    \
+    case 256: L_YR(RS, 256); break;  \
+    case 512: L_YR(RS, 512); break;  \
+    default: L_YR(RS, 1024); break;  \
+  }
+      switch (rs) {
+        case 2: L_YRN(2); break;
+        case 3: L_YRN(3); break;
+        default: L_YRN(4); break;
+      }
+#undef L_YRN
+#undef L_YR
+      ydone = true;
+    } else if (h->G.ny > 1 && grp_len_ok(py.n) && py.n >= h->G.ny && tq <= 4) {
     // one workgroup per (column, layer): the layer's fields share the FP64 factors
     const size_t lds = grp_lds_len(py.n) * csz;
     dim3 grid(h->G.nxh, (A.nvol > 0 ? A.nl : 0) + (A.nsurf > 0 ? 1 : 0));
@@ -1007,6 +1239,31 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     return;
   }
   if constexpr (sizeof(R) == 4) {
+  const int nxm = h->G.nx, rsx = px.n / std::max(nxm, 1);
+  if (pre && (nxm == 256 || nxm == 512 || nxm == 1024) && rsx >= 2 && rsx <= 4 && rsx * nxm == px.n) {
+    // plane layout, residue form: one wavefront per output residue x mod rsx
+    if (plane_out) *plane_out = 1;
+    constexpr int ppb = 4;
+    const int npair = (njobs + 1) / 2;
+    const size_t lds = (size_t)rsx * (nxm + nxm / 16 + 1) * csz;
+    dim3 grid(A.wy, (npair + ppb - 1) / ppb);
+    const cpx<float>* twx = reinterpret_cast<const cpx<float>*>(px.tw);
+#define L_XR(RS, NX) sw_launch(h, SWENSE_K_XEVAL, &k_xplane_r<RS, NX>, grid, dim3(256), lds, h->st, A, h->G, twx, njobs, ppb, out)
+#define L_XRN(RS)                  \
+  switch (nxm) {                   \
+    case 256: L_XR(RS, 256); break;  \
+    case 512: L_XR(RS, 512); break;  \
+    default: L_XR(RS, 1024); break;  \
+  }
+    switch (rsx) {
+      case 2: L_XRN(2); break;
+      case 3: L_XRN(3); break;
+      default: L_XRN(4); break;
+    }
+#undef L_XRN
+#undef L_XR
+    return;
+  }
   if (pre && grp_len_ok(px.n)) {
     // plane layout: each pair of rows transformed by a whole workgroup
     if (plane_out) *plane_out = 1;
