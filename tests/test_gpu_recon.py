@@ -127,6 +127,38 @@ def test_interp_parity(gpu_lib, dim, nx, ny, gx, gy, win):
     h.close()
 
 
+@pytest.mark.parametrize("nx,ny,gx,gy", [(256, 256, 512, 768), (512, 256, 1536, 1024), (1024, 256, 2048, 512)])
+def test_interp_residue_forms(gpu_lib, nx, ny, gx, gy):
+    """Refinements of 2, 3 and 4 times the mode count at 256 to 1024 modes:
+    the evaluation's residue-form transforms (one wavefront per output
+    residue of the refined grid) in both directions, with 6 layers (below
+    the skeleton threshold, so the plane x pass runs): all 11 fields at 4000
+    points of a window against the oracle."""
+    from paper_2005_12716_amd import lib
+    h, g, (er, pr, A, At, eth) = _state(lib, 3, nx, ny, -1.0, steps=2)
+    zl = np.linspace(-1.0, 0.2, 6)
+    win = (gx // 3, gy // 3, gx // 4, gy // 4)
+    gd = lib.grid_desc(gx, gy, zl, win)
+    ix0, iy0, wx, wy = win
+    rng = np.random.default_rng(nx + gx)
+    n = 4000
+    dx, dy = g.lx / gx, g.ly / gy
+    pts = np.stack([rng.uniform((ix0 + 1) * dx, (ix0 + wx - 2) * dx, n),
+                    rng.uniform((iy0 + 1) * dy, (iy0 + wy - 2) * dy, n), rng.uniform(-1.0, 0.2, n)])
+    cells = h.bind(gd, torch.tensor(pts, device="cuda"))
+    out, nbad = cells.interp(lib.ALL_FIELDS)
+    out = out.cpu().numpy()
+    assert nbad == 0
+    coef = rc.eval_grid(g, A, At, er, eth, gx, gy, zl, [f for f in range(11) if f != rc.P], prefilter=True,
+                        window=win)
+    ref, nb = rc.interp_points(g, coef, zl, gx, gy, win, pts, list(range(11)))
+    assert nb == 0
+    for f in range(11):
+        assert rel(out[f], ref[f]) < 1e-5, (f, rel(out[f], ref[f]))
+    cells.close()
+    h.close()
+
+
 def test_out_of_range_and_empty(gpu_lib):
     from paper_2005_12716_amd import lib
     h, g, _ = _state(lib, 3, 16, 8, -1.0)
