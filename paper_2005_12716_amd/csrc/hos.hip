@@ -834,11 +834,12 @@ __global__ void __launch_bounds__(256) k_xpass_r(XArgs A, Geom G, WPlan plan) {
 // kept modes of the next pair are read into registers while the current pair
 // is transformed (the block barriers of the transform wait on LDS operations
 // only, so the loads stay in flight).
-template <typename R, int Q, int NT>
+template <typename R, int Q, int NT, bool RES = false>
 struct Rows3 {
   static constexpr int Px = 3 * Q;
-  static constexpr int PPT = Px / NT;               // points per thread
-  static constexpr int KP = (Px / 2 + NT - 1) / NT;  // kept modes per thread (p < Px / 2)
+  static constexpr int PPT = Px / NT;  // points per thread
+  // kept modes per thread: p < Px / 2, or with RES (nx = Q) p < Q / 2
+  static constexpr int KP = ((RES ? Q : Px) / 2 + NT - 1) / NT;
   cpx<R> va[KP], vb[KP];
 
   __device__ __forceinline__ void load(const XArgs& A, const Geom& G, int y, int ia, int ib) {
@@ -857,10 +858,41 @@ struct Rows3 {
   }
 
   // Writes the held pair into buf (the caller has passed a barrier since
-  // buf was last read).
-  __device__ __forceinline__ void store(cpx<R>* buf, const XArgs& A, const Geom& G, int ia, int ib) const {
+  // buf was last read).  Without RES: the zero-padded Px-point sequence in
+  // the decimated input layout of block3_fft.  With RES: the three residue
+  // sequences, mode p of sub-buffer r times e^{2 pi i p r / Px} (tw holds
+  // e^{-2 pi i m / Px}), so that sub-buffer r's Q-point inverse transform is
+  // the row at the points x = 3 s + r.
+  __device__ __forceinline__ void store(cpx<R>* buf, const cpx<R>* __restrict__ tw, const XArgs& A, const Geom& G,
+                                        int ia, int ib) const {
     const int hx = G.nx / 2;
     const int dxa = A.in[ia].dx, dxb = ib >= 0 ? A.in[ib].dx : 0;
+    if constexpr (RES) {
+      constexpr int WL = Q + Q / 16 + 1;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        const int p = (int)threadIdx.x + NT * k;
+        if (p < Q / 2) {
+          cpx<R> a = va[k], b = vb[k];
+          if (dxa) a = times_ikx<R>(a, p, G);
+          if (dxb) b = times_ikx<R>(b, p, G);
+          const cpx<R> zp = mk(a.x - b.y, a.y + b.x), zm = mk(a.x + b.y, b.x - a.y);
+          const cpx<R> w1 = conjg(tw[p]), w2 = conjg(tw[2 * p]);
+          buf[sk(p)] = zp;
+          buf[WL + sk(p)] = cmul(zp, w1);
+          buf[2 * WL + sk(p)] = cmul(zp, w2);
+          if (p > 0) {
+            buf[sk(Q - p)] = zm;
+            buf[WL + sk(Q - p)] = cmul(zm, conjg(w1));
+            buf[2 * WL + sk(Q - p)] = cmul(zm, conjg(w2));
+          } else {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) buf[r * WL + sk(Q / 2)] = mk((R)0, (R)0);  // the Nyquist slot
+          }
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int t = 0; t < PPT; ++t) {
       const int s = (int)threadIdx.x + NT * t;
@@ -880,16 +912,60 @@ struct Rows3 {
   }
 };
 
+// Inverse transform of the stored pair: physical point x then sits at
+// b3_out(x) (block3_fft), or with RES at b3_in(x) (one residue per
+// wavefront, no combine).
+template <typename R, int Q, int NT, bool HT, bool RES>
+__device__ __forceinline__ void rows3_inv(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
+  if constexpr (RES) {
+    constexpr int WL = Q + Q / 16 + 1;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+    __syncthreads();
+    if (wave < 3) wave_fft_static<R, Q, 3, HT>(buf + wave * WL, tw, +1, lane);
+    __syncthreads();
+  } else {
+    block3_fft<R, Q, NT, HT>(buf, tw, +1);
+  }
+}
+
+template <int Q, bool RES>
+__device__ __forceinline__ int rows3_pt(int x) { return RES ? b3_in<Q>(x) : b3_out<Q>(x); }
+
 // Forward transform of the per-point results already in buf (real part o0,
 // imaginary part o1) and the kept modes of the two real rows to out0/out1.
-template <typename R, int Q, int NT, bool HT = true>
+template <typename R, int Q, int NT, bool HT = true, bool RES = false>
 __device__ __forceinline__ void rows3_out(cpx<R>* buf, const cpx<R>* tw, const XArgs& A, const Geom& G, int y) {
   constexpr int Px = 3 * Q;
-  block3_fft<R, Q, NT, HT>(buf, tw, -1);
+  constexpr int WL = Q + Q / 16 + 1;
   const int hx = G.nx / 2;
   const R sc = (R)(0.5 / (double)Px);
   cpx<R>* d0 = reinterpret_cast<cpx<R>*>(A.out0);
   cpx<R>* d1 = reinterpret_cast<cpx<R>*>(A.out1);
+  if constexpr (RES) {
+    // the three residue sequences' forward transforms, then only the kept
+    // modes p and Px - p (p < hx) combined: Y[k] = sum_r e^{-2 pi i k r / Px} Z_r[k mod Q]
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+    __syncthreads();
+    if (wave < 3) wave_fft_static<R, Q, 3, HT>(buf + wave * WL, tw, -1, lane);
+    __syncthreads();
+    for (int p = threadIdx.x; p < G.nxh; p += NT) {
+      cpx<R> o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
+      if (p < hx) {
+        const cpx<R> w1 = tw[p], w2 = tw[2 * p];
+        const int q = p == 0 ? 0 : Q - p;
+        const cpx<R> zp = buf[sk(p)] + cmul(buf[WL + sk(p)], w1) + cmul(buf[2 * WL + sk(p)], w2);
+        const cpx<R> ym = buf[sk(q)] + cmul(buf[WL + sk(q)], conjg(w1)) + cmul(buf[2 * WL + sk(q)], conjg(w2));
+        const cpx<R> zm = conjg(ym);
+        const cpx<R> sum = zp + zm, t = zp - zm;
+        o0 = cscale(sum, sc);
+        o1 = mk(t.y * sc, -t.x * sc);
+      }
+      d0[(size_t)y * G.nxh + p] = o0;
+      if (d1) d1[(size_t)y * G.nxh + p] = o1;
+    }
+    return;
+  }
+  block3_fft<R, Q, NT, HT>(buf, tw, -1);
   for (int p = threadIdx.x; p < G.nxh; p += NT) {
     cpx<R> o0 = mk((R)0, (R)0), o1 = mk((R)0, (R)0);
     if (p < hx) {
@@ -910,9 +986,9 @@ __device__ __forceinline__ void rows3_out(cpx<R>* buf, const cpx<R>* tw, const X
 // the mean-level modes takes.  Per point only eta, the running sum and (FT)
 // eta_t and phis_t are held; the inputs are folded in index order with the
 // arithmetic of the rounds kernel.
-template <typename R, int Q, int NT, bool FT>
+template <typename R, int Q, int NT, bool FT, bool RES>
 __global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan plan) {
-  using Rw = Rows3<R, Q, NT>;
+  using Rw = Rows3<R, Q, NT, RES>;
   // twiddles read ahead at 3072 points (measured faster); not with the extra
   // per-point state of FT, which leaves no registers for them
   constexpr bool HT = Q >= 1024 && !FT;
@@ -938,9 +1014,9 @@ __global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan pla
   rows.load(A, G, y, 0, 1 < A.nin ? 1 : -1);
   for (int pi = 0; pi < npairs; ++pi) {
     const int ib = 2 * pi + 1 < A.nin ? 2 * pi + 1 : -1;
-    rows.store(buf, A, G, 2 * pi, ib);
+    rows.store(buf, tw, A, G, 2 * pi, ib);
     if (pi + 1 < npairs) rows.load(A, G, y, 2 * pi + 2, 2 * pi + 3 < A.nin ? 2 * pi + 3 : -1);
-    block3_fft<R, Q, NT, HT>(buf, tw, +1);
+    rows3_inv<R, Q, NT, HT, RES>(buf, tw);
     const int i1 = min(A.nin, 2 * pi + 2);
     for (int i = 2 * pi; i < i1; ++i) {
       const int code = s_code[i];
@@ -948,7 +1024,7 @@ __global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan pla
       const bool hi = i & 1;
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        const C zx = buf[b3_out<Q>(tid + NT * j)];
+        const C zx = buf[rows3_pt<Q, RES>(tid + NT * j)];
         const R v = hi ? zx.y : zx.x;
         if (role == XR_ETA) {
           eta[j] = v;
@@ -976,7 +1052,7 @@ __global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan pla
     }
     buf[b3_in<Q>(tid + NT * j)] = mk(o, (R)0);
   }
-  rows3_out<R, Q, NT, HT>(buf, tw, A, G, y);
+  rows3_out<R, Q, NT, HT, RES>(buf, tw, A, G, y);
 }
 
 // Final stage of the x pass on rows of 3Q points, in the same form but with
@@ -991,9 +1067,9 @@ __global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan pla
 // o1 = [W^2]_M / 2 - |grad phi|^2 / 2 + |grad eta|^2 [W^2]_{M-2} / 2
 // (the order-M truncation of the rounds kernel, |grad eta|^2 and the dot
 // product summed per gradient direction).
-template <typename R, int Q, int MW, int NT>
+template <typename R, int Q, int MW, int NT, bool RES>
 __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan plan) {
-  using Rw = Rows3<R, Q, NT>;
+  using Rw = Rows3<R, Q, NT, RES>;
   constexpr int PPT = Rw::PPT;
   extern __shared__ unsigned char smem[];
   using C = cpx<R>;
@@ -1020,8 +1096,8 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
     const int np1 = (ng + 1) / 2;
     for (int pi = 0; pi < np1; ++pi) {
       rows.load(A, G, y, 2 * pi, 2 * pi + 1 < ng ? 2 * pi + 1 : -1);
-      rows.store(buf, A, G, 2 * pi, 2 * pi + 1 < ng ? 2 * pi + 1 : -1);
-      block3_fft<R, Q, NT, false>(buf, tw, +1);
+      rows.store(buf, tw, A, G, 2 * pi, 2 * pi + 1 < ng ? 2 * pi + 1 : -1);
+      rows3_inv<R, Q, NT, false, RES>(buf, tw);
       const int i1 = min(ng, 2 * pi + 2);
       for (int i = 2 * pi; i < i1; ++i) {
         const int code = s_code[i];
@@ -1029,7 +1105,7 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
         const bool hi = i & 1;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-          const C zx = buf[b3_out<Q>(tid + NT * j)];
+          const C zx = buf[rows3_pt<Q, RES>(tid + NT * j)];
           const R v = hi ? zx.y : zx.x;
           if (role == XR_ETA) {
             eta[j] = v;
@@ -1065,11 +1141,11 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
   const R dm = M >= 2 ? (R)1 : (R)0;
   for (int i = ng; i < A.nin; i += 2) {
     rows.load(A, G, y, i, i + 1);
-    rows.store(buf, A, G, i, i + 1);
-    block3_fft<R, Q, NT, true>(buf, tw, +1);
+    rows.store(buf, tw, A, G, i, i + 1);
+    rows3_inv<R, Q, NT, true, RES>(buf, tw);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      const C zx = buf[b3_out<Q>(tid + NT * j)];
+      const C zx = buf[rows3_pt<Q, RES>(tid + NT * j)];
       const R ge = zx.x * zx.x;
       o0[j] += ge * c2[j] - dm * (zx.x * zx.y);
       o1[j] += ge * s2[j] - dm * (R)0.5 * (zx.y * zx.y);
@@ -1078,7 +1154,7 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
   }
 #pragma unroll
   for (int j = 0; j < PPT; ++j) buf[b3_in<Q>(tid + NT * j)] = mk(o0[j], o1[j]);
-  rows3_out<R, Q, NT, true>(buf, tw, A, G, y);
+  rows3_out<R, Q, NT, true, RES>(buf, tw, A, G, y);
 }
 
 // Physical rows <-> spectra on the mode grid (FP64, state in/out only).
@@ -1394,20 +1470,28 @@ void xpass_t(swense_hos* h, const XArgs& a) {
         }
       SW_REQUIRE(b.nin == a.nin && b.ng >= 1 && b.in[0].role == XR_ETA, "final-stage inputs out of order");
       const WPlan wp = make_wplan(h->plan_px);
-      sw_launch(h, SWENSE_K_XPASS, &k_xpass_final3<R, 1024, 5, 256>, dim3(h->Py), dim3(256),
-                b3_len<1024>() * sizeof(cpx<R>), h->st, b, h->G, wp);
+      // residue form when the row is three times the mode count
+      if (h->G.nx == 1024)
+        sw_launch(h, SWENSE_K_XPASS, &k_xpass_final3<R, 1024, 5, 256, true>, dim3(h->Py), dim3(256),
+                  b3_len<1024>() * sizeof(cpx<R>), h->st, b, h->G, wp);
+      else
+        sw_launch(h, SWENSE_K_XPASS, &k_xpass_final3<R, 1024, 5, 256, false>, dim3(h->Py), dim3(256),
+                  b3_len<1024>() * sizeof(cpx<R>), h->st, b, h->G, wp);
       return;
     }
     if (series_ok) {
       const WPlan wp = make_wplan(h->plan_px);
-#define L_S3(Q, FT) sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, Q, 256, FT>, dim3(h->Py), dim3(256), \
-                              b3_len<Q>() * sizeof(cpx<R>), h->st, a, h->G, wp)
+#define L_S3R(Q, FT, RES) sw_launch(h, SWENSE_K_XPASS, &k_xpass_series3<R, Q, 256, FT, RES>, dim3(h->Py), dim3(256), \
+                                   b3_len<Q>() * sizeof(cpx<R>), h->st, a, h->G, wp)
+#define L_S3(Q, FT) \
+  if (h->G.nx == Q) L_S3R(Q, FT, true); else L_S3R(Q, FT, false)
       switch (Px) {
         case 768: if (ft) L_S3(256, true); else L_S3(256, false); break;
         case 1536: if (ft) L_S3(512, true); else L_S3(512, false); break;
         default: if (ft) L_S3(1024, true); else L_S3(1024, false); break;
       }
 #undef L_S3
+#undef L_S3R
       return;
     }
     if (pairs_ok && a.M <= 5 && h->G.nx <= Px && (Px == 768 || Px == 1536 || Px == 3072)) {
