@@ -1055,9 +1055,12 @@ __global__ void __launch_bounds__(NT) k_xpass_series3(XArgs A, Geom G, WPlan pla
   rows3_out<R, Q, NT, HT, RES>(buf, tw, A, G, y);
 }
 
-// Final stage of the x pass on rows of 3Q points, in the same form but with
-// each pair's rows read just before they are stored (no read-ahead: the
-// registers go to the per-point state).  The host orders the inputs as eta
+// Final stage of the x pass on rows of 3Q points, in the same form.  In the
+// residue layout (nx = Q: two kept modes per thread instead of six) the next
+// pair is read ahead and every transform reads its twiddles ahead; in the
+// decimated layout each pair's rows are read just before they are stored and
+// only the lighter phases read twiddles ahead (the registers go to the
+// per-point state).  The host orders the inputs as eta
 // and the W terms first (A.ng of them), then the gradient pairs (each
 // XR_GRADPAIR followed by its partner).  Phase one
 // holds eta and W_1 .. W_M (M <= MW) per point; once the W are complete they
@@ -1085,6 +1088,7 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
   }
   R o0[PPT], o1[PPT], c2[PPT], s2[PPT];
   Rw rows;
+  if constexpr (RES) rows.load(A, G, y, 0, 1 < ng ? 1 : -1);
   {
     R eta[PPT], W[PPT][MW];
 #pragma unroll
@@ -1095,9 +1099,13 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
     }
     const int np1 = (ng + 1) / 2;
     for (int pi = 0; pi < np1; ++pi) {
-      rows.load(A, G, y, 2 * pi, 2 * pi + 1 < ng ? 2 * pi + 1 : -1);
+      if constexpr (!RES) rows.load(A, G, y, 2 * pi, 2 * pi + 1 < ng ? 2 * pi + 1 : -1);
       rows.store(buf, tw, A, G, 2 * pi, 2 * pi + 1 < ng ? 2 * pi + 1 : -1);
-      rows3_inv<R, Q, NT, false, RES>(buf, tw);
+      if constexpr (RES) {
+        if (pi + 1 < np1) rows.load(A, G, y, 2 * pi + 2, 2 * pi + 3 < ng ? 2 * pi + 3 : -1);
+        else if (ng < A.nin) rows.load(A, G, y, ng, ng + 1);
+      }
+      rows3_inv<R, Q, NT, RES, RES>(buf, tw);
       const int i1 = min(ng, 2 * pi + 2);
       for (int i = 2 * pi; i < i1; ++i) {
         const int code = s_code[i];
@@ -1140,8 +1148,10 @@ __global__ void __launch_bounds__(NT, 2) k_xpass_final3(XArgs A, Geom G, WPlan p
   // read the twiddles ahead of the LDS loads
   const R dm = M >= 2 ? (R)1 : (R)0;
   for (int i = ng; i < A.nin; i += 2) {
-    rows.load(A, G, y, i, i + 1);
+    if constexpr (!RES) rows.load(A, G, y, i, i + 1);
     rows.store(buf, tw, A, G, i, i + 1);
+    if constexpr (RES)
+      if (i + 2 < A.nin) rows.load(A, G, y, i + 2, i + 3);
     rows3_inv<R, Q, NT, true, RES>(buf, tw);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
