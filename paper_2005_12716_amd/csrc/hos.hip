@@ -465,6 +465,121 @@ __global__ void __launch_bounds__(256) k_yfwd_b4(YFwdArgs A, Geom G, WPlan plan)
   }
 }
 
+// Residue forms of the workgroup y passes for padded lengths N = RS ny (RS in
+// {2, 3, 4}, ny a power of two, single precision).  Inverse: with y = RS s +
+// r, X[y] = sum_q (x_q e^{2 pi i q r / N}) e^{2 pi i q s / ny}, so wavefront
+// r transforms the modulated kept modes (no zero slots, no combine) and
+// stores the rows of its residue.  Forward: the column's residue sequences
+// x[RS s + r] transformed one per wavefront, then only the kept modes
+// combined, Y[q] = sum_r e^{-2 pi i q r / N} Z_r[q mod ny].
+template <int RS, int NY>
+__global__ void __launch_bounds__(256) k_yinv_r(YInvArgs args, Geom G, WPlan plan, int nrows, int row0) {
+  static_assert(RS >= 2 && RS <= 4 && NY >= 256 && NY <= 1024, "residues and lengths");
+  constexpr int N = RS * NY;
+  constexpr int WL = NY + NY / 16 + 1;
+  constexpr int TQ = NY / 256;
+  using C = cpx<float>;
+  extern __shared__ unsigned char smem[];
+  C* buf = reinterpret_cast<C*>(smem);
+  const C* tw = reinterpret_cast<const C*>(plan.tw);
+  const int p = xcd_tile(blockIdx.x, gridDim.x);
+  const YInvJob& jb = args.job[blockIdx.y];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int half = G.ny / 2;
+  const bool col = p < G.nxh && 2 * p != G.nx;
+  cd v[TQ];
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) {
+    const int q = tid + 256 * t;
+    const int qs = q >= half ? q - G.ny : q;
+    v[t] = mk(0.0, 0.0);
+    if (col && qs > -half) v[t] = jb.src[(size_t)q * G.nxh + p];
+  }
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) {
+    const int q = tid + 256 * t;
+    const int qs = q >= half ? q - G.ny : q;
+    C w = mk(0.f, 0.f);
+    if (col && qs > -half) {
+      const cd x = cmul(v[t], symbol_of(G, jb, p, qs));
+      w = mk((float)x.x, (float)x.y);
+    }
+    const C tm = tw[(qs + N) % N];
+    const C md = mk(tm.x, -tm.y);  // e^{2 pi i qs / N}
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+      buf[r * WL + sk(q)] = w;
+      w = cmul(w, md);
+    }
+  }
+  __syncthreads();
+  if (wave >= RS || p >= G.nxh) return;
+  C* b = buf + wave * WL;
+  wave_fft_static<float, NY, RS, true>(b, tw, +1, lane);
+  C* dst = reinterpret_cast<C*>(jb.dst);
+  const int r0 = ((wave - row0) % RS + RS) % RS;
+  for (int rr = r0 + RS * lane; rr < nrows; rr += RS * 64) {
+    int y = row0 + rr;
+    if (y >= N) y -= N * (y / N);
+    dst[(size_t)rr * G.nxh + p] = b[sk((y - wave) / RS)];
+  }
+}
+
+template <int RS, int NY>
+__global__ void __launch_bounds__(256) k_yfwd_r(YFwdArgs A, Geom G, WPlan plan) {
+  static_assert(RS >= 2 && RS <= 4 && NY >= 256 && NY <= 1024, "residues and lengths");
+  constexpr int N = RS * NY;
+  constexpr int WL = NY + NY / 16 + 1;
+  constexpr int T = N / 256;
+  constexpr int TQ = NY / 256;
+  using C = cpx<float>;
+  extern __shared__ unsigned char smem[];
+  C* buf = reinterpret_cast<C*>(smem);
+  const C* tw = reinterpret_cast<const C*>(plan.tw);
+  const int p = xcd_tile(blockIdx.x, gridDim.x);
+  const YFwdJob& jb = A.job[blockIdx.y];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const bool colp = p < G.nxh;
+  const C* src = reinterpret_cast<const C*>(jb.src);
+  C colv[T];
+  EpiOps o[TQ];
+  if (colp) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) colv[t] = src[(size_t)(tid + 256 * t) * G.nxh + p];
+#pragma unroll
+    for (int k = 0; k < TQ; ++k) o[k] = yfwd_epi_load(jb, A.rk, (size_t)(tid + 256 * k) * G.nxh + p);
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int y = tid + 256 * t;
+      buf[(y % RS) * WL + sk(y / RS)] = colv[t];
+    }
+  }
+  __syncthreads();
+  if (wave < RS) wave_fft_static<float, NY, RS, true>(buf + wave * WL, tw, -1, lane);
+  __syncthreads();
+  if (!colp) return;
+  const double inv = 1.0 / (double)N;
+#pragma unroll
+  for (int k = 0; k < TQ; ++k) {
+    const int q = tid + 256 * k;
+    const int qs = signed_q(q, G.ny);
+    cd v = mk(0.0, 0.0);
+    if (2 * p != G.nx && !(G.ny > 1 && 2 * q == G.ny)) {
+      const C w1 = tw[(qs + N) % N];  // e^{-2 pi i qs / N}
+      C acc = buf[sk(q)], w = w1;
+#pragma unroll
+      for (int r = 1; r < RS; ++r) {
+        acc = acc + cmul(buf[r * WL + sk(q)], w);
+        w = cmul(w, w1);
+      }
+      v = mk((double)acc.x * inv, (double)acc.y * inv);
+    }
+    yfwd_epi_store(jb, A.rk, G, p, q, qs, v, o[k]);
+  }
+}
+
 // Fused x pass, wavefront version: block = physical row y, four wavefronts.
 // Field pairs are spread over the wavefronts (each transforms its pair in
 // its own LDS buffer and leaves the two real rows in LDS); after one block
@@ -1353,6 +1468,30 @@ void yinv_t(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, in
     h->prof.bytes[SWENSE_K_YINV] += b;
     h->prof.tbytes[SWENSE_K_YINV] += (double)a.njobs * 2.0 * sizeof(R) * (double)h->Px * h->Py;
   }
+  if constexpr (sizeof(R) == 4) {
+    const int ny = h->G.ny, rs = plan.n / std::max(ny, 1);
+    if ((ny == 256 || ny == 512 || ny == 1024) && rs >= 2 && rs <= 4 && rs * ny == plan.n) {
+      // residue form: one wavefront per output residue
+      const WPlan wp = make_wplan(plan);
+      const size_t lds = (size_t)rs * (ny + ny / 16 + 1) * sizeof(cpx<R>);
+      dim3 grid(h->G.nxh, a.njobs);
+#define L_YIR(RS, NY) sw_launch(h, SWENSE_K_YINV, &k_yinv_r<RS, NY>, grid, dim3(256), lds, st, a, h->G, wp, nrows, row0)
+#define L_YIRN(RS)                  \
+  switch (ny) {                     \
+    case 256: L_YIR(RS, 256); break;  \
+    case 512: L_YIR(RS, 512); break;  \
+    default: L_YIR(RS, 1024); break;  \
+  }
+      switch (rs) {
+        case 2: L_YIRN(2); break;
+        case 3: L_YIRN(3); break;
+        default: L_YIRN(4); break;
+      }
+#undef L_YIRN
+#undef L_YIR
+      return;
+    }
+  }
   if (grp_len_ok(plan.n) && h->G.ny > 1 && plan.n >= h->G.ny) {
     const WPlan wp = make_wplan(plan);
     const size_t lds = grp_lds_len(plan.n) * sizeof(cpx<R>);
@@ -1397,6 +1536,30 @@ void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t s
     }
     h->prof.bytes[SWENSE_K_YFWD] += b;
     h->prof.tbytes[SWENSE_K_YFWD] += (double)a.njobs * 2.0 * sizeof(R) * (double)h->Px * h->Py;
+  }
+  if constexpr (sizeof(R) == 4) {
+    const int ny = h->G.ny, rs = plan.n / std::max(ny, 1);
+    if ((ny == 256 || ny == 512 || ny == 1024) && rs >= 2 && rs <= 4 && rs * ny == plan.n) {
+      // residue form: the column's residue sequences one per wavefront, kept modes combined
+      const WPlan wp = make_wplan(plan);
+      const size_t lds = (size_t)rs * (ny + ny / 16 + 1) * sizeof(cpx<R>);
+      dim3 grid(h->G.nxh, a.njobs);
+#define L_YFR(RS, NY) sw_launch(h, SWENSE_K_YFWD, &k_yfwd_r<RS, NY>, grid, dim3(256), lds, st, a, h->G, wp)
+#define L_YFRN(RS)                  \
+  switch (ny) {                     \
+    case 256: L_YFR(RS, 256); break;  \
+    case 512: L_YFR(RS, 512); break;  \
+    default: L_YFR(RS, 1024); break;  \
+  }
+      switch (rs) {
+        case 2: L_YFRN(2); break;
+        case 3: L_YFRN(3); break;
+        default: L_YFRN(4); break;
+      }
+#undef L_YFRN
+#undef L_YFR
+      return;
+    }
   }
   if (grp_len_ok(plan.n) && h->G.ny <= 1024) {
     const WPlan wp = make_wplan(plan);
