@@ -81,22 +81,36 @@ def workload():
     return pts, (gx, gy, ix0, iy0, wx, wy), np.asarray(zl), phases
 
 
-def batched_setup(lib, torch, pts_scale=1.0, fields=None, streams=None):
+padding_choice = {}
+
+
+def batched_setup(lib, torch, pts_scale=1.0, fields=None, streams=None, padding=None):
     """The batched configuration: 64 seeded JONSWAP realisations with mode
     grids uniform over the even 5-smooth sizes in [128, 512] per axis,
     Hs/lambda_p ~ U[0.01, 0.03], M = 3, each interpolated (n = 4 window, 32
-    layers) to 100k..1M box-cloud points clustered toward z = 0."""
+    layers) to 100k..1M box-cloud points clustered toward z = 0.  padding:
+    the product-grid policy of every realisation (1 or 2), or "tune" for the
+    library's timed choice per grid size (the choices are returned in
+    `padding_choice`, keyed "nx x ny")."""
     import numpy as np
     import synth
     reals = synth.batch_realisations(3)
     hoses, cells, outs, npts = [], [], [], 0
     mask = lib.ALL_FIELDS if fields is None else fields
     nf = bin(mask).count("1")
+    padding_choice.clear()
     for r in reals:
         nx, ny = r["nx"], r["ny"]
         lx, ly = nx * LAM / 12.8, ny * LAM / 12.8
         hs = r["hs_over_lambda"] * LAM
         d = lib.hos_desc(3, nx, ny, lx, ly, -1.0, order_m=M, dt=LAM / 64)
+        if padding == "tune":
+            key = f"{nx}x{ny}"
+            if key not in padding_choice:
+                padding_choice[key] = lib.tune_padding(d)[0]
+            d.dealias = padding_choice[key]
+        elif padding is not None:
+            d.dealias = padding
         eh, ph = lib.sea_spectrum(d, kind=0, hs=hs, kp=1.0, gamma=3.3,
                                   phases=synth.mode_phases(r["phase_seed"], ny, nx // 2 + 1))
         h = lib.Hos(d, eh, ph, stream=streams[len(hoses) % len(streams)] if streams else None)
@@ -119,7 +133,9 @@ def batched_setup(lib, torch, pts_scale=1.0, fields=None, streams=None):
 
 def run_batched(lib, torch, steps):
     import tempfile
-    hoses, cells, outs, npts, mask, nf = batched_setup(lib, torch)
+    t0 = time.time()
+    hoses, cells, outs, npts, mask, nf = batched_setup(lib, torch, padding="tune")
+    setup_s = time.time() - t0
     b = lib.Batch(hoses, cells, [mask] * len(hoses), outs, nsteps=1)
     with tempfile.TemporaryDirectory() as td:
         k, tune_ms = b.autotune(os.path.join(td, "tune.json"))
@@ -133,6 +149,8 @@ def run_batched(lib, torch, steps):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     res = {"realisations": len(hoses), "points": npts, "branches": k, "ms_per_launch": ms,
+           "setup_s": setup_s, "padding_2_sizes": sorted(kk for kk, v in padding_choice.items() if v == 2),
+           "padding_1_sizes": sorted(kk for kk, v in padding_choice.items() if v == 1),
            "realisation_steps_per_s": len(hoses) * 1e3 / ms,
            "cell_field_pts_per_s": npts * nf * 1e3 / ms}
     # compulsory HBM bytes of one launch, lower bound: the HOS intermediates

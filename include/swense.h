@@ -75,7 +75,10 @@ typedef struct swense_cells swense_cells; /* a bound, static point cloud (opaque
  *   dim: 2 (x, z; ny must be 1) or 3.  nx, ny: modes per direction, even and
  *   2/3/5-smooth (ny = 1 for dim 2).  depth <= 0 selects infinite depth.
  *   order_m >= 1: order of the vertical-velocity series.  dealias: 1 forms
- *   products on the (M+1)/2 zero-padded grid, 0 on the mode grid.
+ *   products on the (M+1)/2 zero-padded grid (the smallest even 2/3/5-smooth
+ *   length past (M+1) n / 2), 2 on the smallest 2^k or 3 2^k length past it
+ *   (more points, transforms compiled for the length; the truncated products
+ *   are the same), 0 on the mode grid.
  *   precision: 0 = FP32 transforms with FP64 state, symbols and time
  *   integration; 1 = FP64 throughout.  dt: RK4 time step; t0: initial time. */
 typedef struct {
@@ -179,6 +182,14 @@ int swense_hos_rhs(swense_hos* h, double* eta_t_hat, double* phis_t_hat);
  * time derivative A_t, plus eta_t, as half spectra (host outputs; any may be
  * NULL).  Synchronises. */
 int swense_hos_modes(swense_hos* h, double* a_hat, double* a_t_hat, double* eta_t_hat);
+
+/* Choice of the product-grid length for a realisation of descriptor d
+ * (dealias 1 or 2): when the two lengths differ, one HOS step of each is
+ * timed (nsteps steps after one warm-up, on a scratch realisation of zero
+ * state, with hipEvents on `stream`) and *dealias receives the faster one
+ * (1 when they are the same length); ms (may be NULL) receives both times per
+ * step, -1 when not timed.  Allocates and frees device memory.  Synchronises. */
+int swense_hos_tune_padding(const swense_hos_desc* d, int nsteps, void* stream, int* dealias, double* ms);
 
 /* Energy 1/2 int phis eta_t dA + 1/2 g int eta^2 dA.  Synchronises. */
 int swense_hos_energy(swense_hos* h, double* energy);

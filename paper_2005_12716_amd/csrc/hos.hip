@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 namespace {
 
@@ -1951,14 +1952,27 @@ void check_desc(const swense_hos_desc* d) {
   SW_REQUIRE(d->order_m >= 1 && d->order_m <= kMaxM, "order_m must be in [1, 8]");
   SW_REQUIRE(d->lx > 0 && d->ly > 0 && d->g > 0 && d->rho > 0, "lengths, g and rho must be positive");
   SW_REQUIRE(d->precision == 0 || d->precision == 1, "precision must be 0 or 1");
-  SW_REQUIRE(d->dealias == 0 || d->dealias == 1, "dealias must be 0 or 1");
+  SW_REQUIRE(d->dealias >= 0 && d->dealias <= 2, "dealias must be 0, 1 or 2");
 }
 
+// Product-grid length: the mode count (dealias 0), the smallest even
+// 2/3/5-smooth length >= (M + 1) n / 2 (1), or the smallest 2^k or 3 2^k
+// length >= (M + 1) n / 2 (2: the lengths with compile-time transforms; any
+// length past the bound gives the same truncated products).
 int padded_len(int n, int M, int dealias) {
   if (n == 1) return 1;
   if (!dealias) return n;
   int v = ((M + 1) * n + 1) / 2;
   v += v & 1;
+  if (dealias == 2) {
+    long long best = 0;
+    for (long long b : {2ll, 6ll}) {
+      long long c = b;
+      while (c < v) c *= 2;
+      if (best == 0 || c < best) best = c;
+    }
+    return (int)best;
+  }
   while (!is_235_smooth(v)) v += 2;
   return v;
 }
@@ -2275,6 +2289,64 @@ int swense_hos_set_state(swense_hos* h, const double* eta, const double* phis, i
     h->t = t;
     return SWENSE_OK;
   });
+}
+
+int swense_hos_tune_padding(const swense_hos_desc* d, int nsteps, void* stream, int* dealias, double* ms) {
+  if (!d || !dealias || nsteps < 1) return SWENSE_EINVAL;
+  try {
+    check_desc(d);
+    SW_REQUIRE(d->dealias != 0, "padding is tuned for dealiased products only");
+    const int ny = d->dim == 2 ? 1 : d->ny;
+    int px[2], py[2];
+    for (int k = 0; k < 2; ++k) {
+      px[k] = padded_len(d->nx, d->order_m, 1 + k);
+      py[k] = padded_len(ny, d->order_m, 1 + k);
+    }
+    double t[2] = {-1.0, -1.0};
+    *dealias = 1;
+    if (px[0] != px[1] || py[0] != py[1]) {
+      // a zero state costs what any state does: the step is data-independent work
+      const size_t nc = (size_t)ny * (d->nx / 2 + 1);
+      std::vector<double> zero(2 * nc, 0.0);
+      for (int k = 0; k < 2; ++k) {
+        swense_hos_desc e = *d;
+        e.dealias = 1 + k;
+        swense_hos* h = nullptr;
+        const int rc = hos_init_impl(&e, zero.data(), zero.data(), SWENSE_SPECTRAL, stream, nullptr, &h);
+        if (rc != SWENSE_OK) return rc;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        float el = 0.f;
+        bool ok = true;
+        try {
+          hos_step(h, 1);  // plans and tables
+          SW_HIP(hipEventCreate(&e0));
+          SW_HIP(hipEventCreate(&e1));
+          SW_HIP(hipEventRecord(e0, h->st));
+          hos_step(h, nsteps);
+          SW_HIP(hipEventRecord(e1, h->st));
+          SW_HIP(hipEventSynchronize(e1));
+          SW_HIP(hipEventElapsedTime(&el, e0, e1));
+        } catch (...) {
+          ok = false;
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        swense_hos_destroy(h);
+        if (!ok) return SWENSE_EHIP;
+        t[k] = (double)el / nsteps;
+      }
+      *dealias = t[1] < t[0] ? 2 : 1;
+    }
+    if (ms) {
+      ms[0] = t[0];
+      ms[1] = t[1];
+    }
+    return SWENSE_OK;
+  } catch (const SwenseError& e) {
+    return e.code;
+  } catch (...) {
+    return SWENSE_EHIP;
+  }
 }
 
 int swense_hos_step(swense_hos* h, int nsteps) {

@@ -94,6 +94,7 @@ def load():
         "swense_hos_init_ws": (C.c_int, [C.POINTER(HosDesc), vp, vp, C.c_int, vp, vp, C.c_size_t, C.POINTER(vp)]),
         "swense_hos_set_state": (C.c_int, [vp, vp, vp, C.c_int, C.c_double]),
         "swense_hos_step": (C.c_int, [vp, C.c_int]),
+        "swense_hos_tune_padding": (C.c_int, [C.POINTER(HosDesc), C.c_int, vp, C.POINTER(C.c_int), dp]),
         "swense_hos_step_exp": (C.c_int, [vp, C.c_double, C.c_int]),
         "swense_hos_get_state": (C.c_int, [vp, vp, vp, dp, C.c_int]),
         "swense_hos_rhs": (C.c_int, [vp, vp, vp]),
@@ -164,7 +165,7 @@ def load():
 
 EXPORTED = ["swense_version", "swense_last_error", "swense_sea_spectrum", "swense_hos_init",
             "swense_hos_workspace_bytes", "swense_hos_init_ws", "swense_cells_workspace_bytes", "swense_cells_bind_ws",
-            "swense_hos_set_state", "swense_hos_step", "swense_hos_step_exp", "swense_hos_get_state", "swense_hos_rhs",
+            "swense_hos_set_state", "swense_hos_step", "swense_hos_tune_padding", "swense_hos_step_exp", "swense_hos_get_state", "swense_hos_rhs",
             "swense_hos_modes", "swense_hos_energy", "swense_eval_grid", "swense_eval_grid_size",
             "swense_cells_bind", "swense_interp_cells", "swense_interp_cells_noalloc", "swense_eval_points_direct", "swense_hos_snapshot", "swense_hos_set_eval_time", "swense_stream_solve", "swense_stream_eval", "swense_cells_alpha", "swense_cells_pstar", "swense_cells_relax",
             "swense_interp_divergence", "swense_interp_step", "swense_fv_divergence", "swense_profile_enable",
@@ -188,6 +189,19 @@ def _ptr(a):
 
 def hos_desc(dim, nx, ny, lx, ly, depth, order_m=3, dt=0.1, g=1.0, rho=1.0, dealias=1, precision=0, t0=0.0):
     return HosDesc(dim, nx, ny, lx, ly, depth, g, rho, order_m, dealias, precision, dt, t0)
+
+
+def tune_padding(desc, nsteps=3, stream=None):
+    """Faster product-grid policy for this descriptor (1 or 2) and the timed
+    ms per step of each (-1: not timed, the lengths coincide)."""
+    best = C.c_int(0)
+    ms = np.zeros(2)
+    st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    rc = load().swense_hos_tune_padding(C.byref(desc), nsteps, C.c_void_p(st), C.byref(best),
+                                        ms.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != OK:
+        raise SwenseError(rc, "swense_hos_tune_padding failed")
+    return best.value, ms
 
 
 def grid_desc(gx, gy, z, window=None):

@@ -97,7 +97,8 @@ def test_invalid_descriptors_are_rejected_before_any_device_work():
            lib.hos_desc(3, 32, 16, 1.0, 1.0, -1.0, order_m=0),  # order 0
            lib.hos_desc(3, 32, 16, -1.0, 1.0, -1.0),         # negative length
            lib.hos_desc(2, 32, 4, 1.0, 1.0, -1.0),           # 2D with ny > 1
-           lib.hos_desc(3, 32, 16, 1.0, 1.0, -1.0, precision=2)]
+           lib.hos_desc(3, 32, 16, 1.0, 1.0, -1.0, precision=2),
+           lib.hos_desc(3, 32, 16, 1.0, 1.0, -1.0, dealias=3)]
     for d in bad:
         h = C.c_void_p()
         rc = L.swense_hos_init(C.byref(d), eh.ctypes.data_as(C.c_void_p), eh.ctypes.data_as(C.c_void_p), lib.SPECTRAL,
@@ -111,6 +112,10 @@ def test_invalid_descriptors_are_rejected_before_any_device_work():
         assert not f.value
     assert L.swense_surrogate_create(None, None, None, C.byref(C.c_void_p())) == lib.EINVAL
     assert L.swense_hos_step(None, 1) == lib.EINVAL
+    best, ms = C.c_int(-5), np.zeros(2)
+    for d, n in [(bad[0], 3), (lib.hos_desc(3, 32, 16, 1.0, 1.0, -1.0, dealias=0), 3),
+                 (lib.hos_desc(3, 32, 16, 1.0, 1.0, -1.0), 0)]:
+        assert L.swense_hos_tune_padding(C.byref(d), n, None, C.byref(best), ms.ctypes.data_as(C.POINTER(C.c_double))) == lib.EINVAL
     assert L.swense_gemm_bf16(0, 4, 4, None, None, None, None) == lib.EINVAL
 
 

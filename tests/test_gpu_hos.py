@@ -114,6 +114,51 @@ def test_rhs_parity_three_way_x_transforms(gpu_lib, dim, nx, ny, depth, M, deali
         test_rhs_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision)
 
 
+# Product grids of policy 2 (the smallest 2^k or 3 2^k at or above the
+# (M+1)/2 rule) against the oracle on its own 5-smooth grid: any product
+# length at or above the rule aliases nothing into the kept band, so the
+# kept modes agree to rounding.
+P2_CASES = [
+    # dim, nx, ny, depth, M, dealias   -> padded (policy 1 -> policy 2)
+    (3, 40, 10, -1.0, 5, 2),   # 120 x 30 -> 128 x 32
+    (3, 24, 20, 2.0, 4, 2),    # 60 x 50 -> 64 x 64, finite depth
+    (3, 300, 8, -1.0, 3, 2),   # 600 x 16 -> 768 x 16
+    (2, 480, 1, -1.0, 3, 2),   # 960 -> 1024, 2D
+    (3, 144, 200, 1.5, 3, 2),  # 288 x 400 -> 384 x 512
+]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("dim,nx,ny,depth,M,dealias", P2_CASES)
+def test_rhs_parity_padding_policy_2(gpu_lib, dim, nx, ny, depth, M, dealias, precision):
+    test_rhs_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision)
+
+
+@pytest.mark.parametrize("dim,nx,ny,depth,M,dealias", P2_CASES[:2])
+def test_steps_parity_padding_policy_2(gpu_lib, dim, nx, ny, depth, M, dealias):
+    test_steps_parity(gpu_lib, dim, nx, ny, depth, M, dealias, 0)
+
+
+def test_padding_tuner(gpu_lib):
+    """The tuner times both policies where their lengths differ and returns
+    the faster; where they coincide it returns 1 untimed.  A realisation
+    built with its choice steps like one built with the other policy."""
+    from paper_2005_12716_amd import lib
+    d, g, eh, ph = _case(lib, 3, 144, 200, 1.5, 3)
+    best, ms = lib.tune_padding(d, nsteps=2)
+    assert best in (1, 2) and np.all(ms > 0) and ms[best - 1] <= ms[2 - best]
+    same, ms1 = lib.tune_padding(_case(lib, 3, 64, 64, -1.0, 3)[0])
+    assert same == 1 and np.all(ms1 == -1.0)
+    outs = []
+    for pol in (1, 2):
+        d.dealias = pol
+        h = lib.Hos(d, eh, ph)
+        h.step(4)
+        outs.append(h.state()[:2])
+        h.close()
+    assert rel(outs[0][0], outs[1][0]) < 1e-6 and rel(outs[0][1], outs[1][1]) < 1e-6
+
+
 @pytest.mark.parametrize("precision", [1, 0])
 @pytest.mark.parametrize("dim,nx,ny,depth,M,dealias", CASES[:4])
 def test_steps_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision):
