@@ -23,6 +23,8 @@
 #include "wfft.h"
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 namespace {
@@ -267,8 +269,11 @@ __device__ __forceinline__ void gemm_store(const GemmArgs& g, int tid, const flo
 }
 
 // One 64 x 64 output tile per block (4 waves, 32 x 32 each as 2 x 2 MFMA
-// 16x16x16 tiles); the next K tile is fetched into registers while the
-// current one is multiplied.  AM, BM: load modes (see GemmArgs).
+// 16x16x32 tiles, one instruction per tile and K tile); the next K tile is
+// fetched into registers while the current one is multiplied.  Lane l holds
+// row (or column) l % 16 and the eight k = 8 (l / 16) .. + 7 of A and of B
+// alike, so the contraction covers every k once.  AM, BM: load modes (see
+// GemmArgs).
 template <int AM, int BM>
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
   __shared__ __align__(16) unsigned short As[TM][TK + 4];  // [m][k]
@@ -293,19 +298,23 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     gemm_store<AM, BM>(g, tid, ra, rb, As, Bs);
     __syncthreads();
     if (k0 + TK < g.K) gemm_load<AM, BM>(g, aoff, boff, m0, n0, k0 + TK, tid, ra, rb);
-#pragma unroll
-    for (int kk = 0; kk < TK; kk += 16) {
-      const int kq = kk + 4 * (lane >> 4);
-      v4s af[2], bfr[2];
+    {
+      static_assert(TK == 32, "one 16x16x32 MFMA per K tile");
+      const int kq = 8 * (lane >> 4);
+      v8bf af[2], bfr[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        af[i] = *reinterpret_cast<const v4s*>(&As[wm + 16 * i + (lane & 15)][kq]);
-        bfr[i] = *reinterpret_cast<const v4s*>(&Bs[wn + 16 * i + (lane & 15)][kq]);
+        // two 8-byte LDS reads each (the padded rows keep 8-byte alignment)
+        const v4s* pa = reinterpret_cast<const v4s*>(&As[wm + 16 * i + (lane & 15)][kq]);
+        const v4s* pb = reinterpret_cast<const v4s*>(&Bs[wn + 16 * i + (lane & 15)][kq]);
+        const v4s a0 = pa[0], a1 = pa[1], b0 = pb[0], b1 = pb[1];
+        af[i] = __builtin_bit_cast(v8bf, v8s{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]});
+        bfr[i] = __builtin_bit_cast(v8bf, v8s{b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]});
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -465,10 +474,13 @@ __global__ void k_fno_herm(cf* Y, FnoDims d, int div_cp) {
   *f = conjg(avg);
 }
 
-// y pass inverse: xi[b][c][row][p] = F_y^-1 of the retained q values of Y[b][:, p][c]
+// y pass inverse: xi[b][c][row][p] = F_y^-1 of the retained q values of Y[b][:, p][c].
+// hmode 1 reads Y through the Hermitian projection of its p = 0 column (the
+// +q and -q entries averaged as k_fno_herm does, q = 0 made real); hmode 2
+// also halves the p > 0 modes (the projection with the division by c_p).
 template <int N>
 __global__ void __launch_bounds__(256) k_fno_iy(const cf* __restrict__ Y, cf* __restrict__ xi, FnoDims d,
-                                                WPlan plan) {
+                                                WPlan plan, int hmode) {
   extern __shared__ unsigned char smem[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int job = blockIdx.x * 4 + wave;
@@ -480,7 +492,19 @@ __global__ void __launch_bounds__(256) k_fno_iy(const cf* __restrict__ Y, cf* __
   wave_sync();
   for (int a = lane; a < nq; a += 64) {
     const int q = a <= d.Q ? a : a - nq;
-    buf[sk((q + N) % N)] = Y[((size_t)b * nq * d.P + (size_t)a * d.P + p) * d.C + c];
+    cf v = Y[((size_t)b * nq * d.P + (size_t)a * d.P + p) * d.C + c];
+    if (hmode && p == 0) {
+      if (a == 0) {
+        v.y = 0.f;
+      } else {
+        // 0.5 (Y(q) + conj Y(-q)) at +q, its conjugate at -q
+        const cf w = Y[((size_t)b * nq * d.P + (size_t)(nq - a) * d.P) * d.C + c];
+        v = a <= d.Q ? mk(0.5f * (v.x + w.x), 0.5f * (v.y - w.y)) : mk(0.5f * (w.x + v.x), -(0.5f * (w.y - v.y)));
+      }
+    } else if (hmode == 2) {
+      v = cscale(v, 0.5f);
+    }
+    buf[sk((q + N) % N)] = v;
   }
   wave_sync();
   wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N, true>(buf, plan, +1, lane);
@@ -531,6 +555,77 @@ __global__ void __launch_bounds__(256) k_fno_ix(const cf* __restrict__ xi, float
 // with both factors rounded to BF16.  A handful of samples per mode makes
 // this an outer-product sum bound by the store of gR, so it runs on plain
 // FP32 FMAs, one block per mode, the factors staged in LDS.
+// Spectral mixing at small batch, Y[b][s][o] = sum_i U[b][s][i] R[s][i][o]
+// for b < B <= BB: a weight-bandwidth-bound product (each mode's C x C
+// complex BF16 block is read once and used B times), so it runs on the vector
+// ALUs with one wavefront per mode instead of a mostly empty MFMA tile.  Lane
+// (o4, ig) holds four consecutive outputs o and the rows i = ig (mod G),
+// G = 256 / C; its 16-byte weight loads of a row group are contiguous across
+// the wavefront.  Operands are the GEMM's: U rounded to BF16, products exact
+// in FP32, sums in FP32 (per lane over its rows, then across the G lanes of
+// an output quad).
+template <int C, int BB>
+__global__ void __launch_bounds__(256) k_mix_small(const cf* __restrict__ U, const unsigned* __restrict__ R,
+                                                   cf* __restrict__ Y, int B, int S) {
+  constexpr int Q4 = C / 4, G = 64 / Q4, ROWS = C / G;
+  __shared__ float2 su[4][C][BB];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + wave;
+  if (s >= S) return;
+  for (int e = lane; e < BB * C; e += 64) {
+    const int b = e / C, i = e - b * C;
+    cf u = mk(0.f, 0.f);
+    if (b < B) u = U[((size_t)b * S + s) * C + i];
+    su[wave][i][b] = make_float2(bf2f(f2bf(u.x)), bf2f(f2bf(u.y)));
+  }
+  wave_sync();
+  const int o4 = lane % Q4, ig = lane / Q4;
+  const uint4* w = reinterpret_cast<const uint4*>(R + (size_t)s * C * C) + o4;
+  float2 acc[BB][4];
+#pragma unroll
+  for (int b = 0; b < BB; ++b)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[b][j] = make_float2(0.f, 0.f);
+  constexpr int CH = ROWS < 16 ? ROWS : 16;
+#pragma unroll 1
+  for (int t0 = 0; t0 < ROWS; t0 += CH) {
+    uint4 r[CH];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) r[t] = w[(size_t)(ig + G * (t0 + t)) * Q4];
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int i = ig + G * (t0 + t);
+      const unsigned rv[4] = {r[t].x, r[t].y, r[t].z, r[t].w};
+#pragma unroll
+      for (int b = 0; b < BB; ++b) {
+        const float2 u = su[wave][i][b];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float re = __uint_as_float(rv[j] << 16), im = __uint_as_float(rv[j] & 0xFFFF0000u);
+          acc[b][j].x = fmaf(u.x, re, fmaf(-u.y, im, acc[b][j].x));
+          acc[b][j].y = fmaf(u.x, im, fmaf(u.y, re, acc[b][j].y));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int m = Q4; m < 64; m <<= 1)
+#pragma unroll
+    for (int b = 0; b < BB; ++b)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[b][j].x += __shfl_xor(acc[b][j].x, m);
+        acc[b][j].y += __shfl_xor(acc[b][j].y, m);
+      }
+#pragma unroll
+  for (int b = 0; b < BB; ++b)
+    if (b % G == ig && b < B) {
+      float4* dst = reinterpret_cast<float4*>(Y + ((size_t)b * S + s) * C + 4 * o4);
+      dst[0] = make_float4(acc[b][0].x, acc[b][0].y, acc[b][1].x, acc[b][1].y);
+      dst[1] = make_float4(acc[b][2].x, acc[b][2].y, acc[b][3].x, acc[b][3].y);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_mix_dw(const cf* __restrict__ U, const cf* __restrict__ gY,
                                                 float* __restrict__ gR, int B, int S, int C) {
   extern __shared__ unsigned char smem[];
@@ -846,11 +941,11 @@ void spec_fwd_n(swense_fno* f, const float* v, cf* U, int B, float scale, int cp
 }
 
 template <int N>
-void spec_inv_n(swense_fno* f, const cf* Y, float* out, int B, float scale, float beta) {
+void spec_inv_n(swense_fno* f, const cf* Y, float* out, int B, float scale, float beta, int hmode) {
   const FnoDims dd{N, f->d.channels, f->d.p_modes, f->d.q_modes, B};
   const size_t lds = 4ull * wbuf_len(N) * sizeof(cf);
   const int jy = B * f->d.channels * f->d.p_modes;
-  hipLaunchKernelGGL(k_fno_iy<N>, dim3((jy + 3) / 4), dim3(256), lds, f->st, Y, f->xi, dd, f->plan);
+  hipLaunchKernelGGL(k_fno_iy<N>, dim3((jy + 3) / 4), dim3(256), lds, f->st, Y, f->xi, dd, f->plan, hmode);
   SW_HIP(hipGetLastError());
   const int jx = B * (f->d.channels / 2) * N;
   hipLaunchKernelGGL(k_fno_ix<N>, dim3((jx + 3) / 4), dim3(256), lds, f->st, f->xi, out, dd, f->plan, scale, beta);
@@ -867,13 +962,15 @@ void spec_fwd(swense_fno* f, const float* v, cf* U, int B, float scale, int cp_f
   }
 }
 
-void spec_inv(swense_fno* f, const cf* Y, float* out, int B, float scale, float beta) {
+// out = beta out + scale * inverse transform of Y; hmode as k_fno_iy (the
+// Hermitian projection applied on the way in, Y itself untouched)
+void spec_inv(swense_fno* f, const cf* Y, float* out, int B, float scale, float beta, int hmode) {
   switch (f->d.n) {
-    case 64: spec_inv_n<64>(f, Y, out, B, scale, beta); break;
-    case 128: spec_inv_n<128>(f, Y, out, B, scale, beta); break;
-    case 256: spec_inv_n<256>(f, Y, out, B, scale, beta); break;
-    case 512: spec_inv_n<512>(f, Y, out, B, scale, beta); break;
-    default: spec_inv_n<1024>(f, Y, out, B, scale, beta); break;
+    case 64: spec_inv_n<64>(f, Y, out, B, scale, beta, hmode); break;
+    case 128: spec_inv_n<128>(f, Y, out, B, scale, beta, hmode); break;
+    case 256: spec_inv_n<256>(f, Y, out, B, scale, beta, hmode); break;
+    case 512: spec_inv_n<512>(f, Y, out, B, scale, beta, hmode); break;
+    default: spec_inv_n<1024>(f, Y, out, B, scale, beta, hmode); break;
   }
 }
 
@@ -884,9 +981,26 @@ void herm(swense_fno* f, cf* Y, int B, int div_cp) {
   SW_HIP(hipGetLastError());
 }
 
+template <int C>
+bool mix_small_c(swense_fno* f, const cf* U, const unsigned short* R, cf* Y, int B, int S) {
+  const dim3 grid((S + 3) / 4);
+  const unsigned* r = reinterpret_cast<const unsigned*>(R);
+  if (B <= 1) hipLaunchKernelGGL((k_mix_small<C, 1>), grid, dim3(256), 0, f->st, U, r, Y, B, S);
+  else if (B <= 2) hipLaunchKernelGGL((k_mix_small<C, 2>), grid, dim3(256), 0, f->st, U, r, Y, B, S);
+  else if (B <= 4) hipLaunchKernelGGL((k_mix_small<C, 4>), grid, dim3(256), 0, f->st, U, r, Y, B, S);
+  else hipLaunchKernelGGL((k_mix_small<C, 8>), grid, dim3(256), 0, f->st, U, r, Y, B, S);
+  SW_HIP(hipGetLastError());
+  return true;
+}
+
 // Y[b][s][o] = sum_i U[b][s][i] R[s][i][o] (complex), per mode s
 void mix(swense_fno* f, const cf* U, const unsigned short* R, cf* Y, int B) {
   const int C = f->d.channels, S = (2 * f->d.q_modes + 1) * f->d.p_modes;
+  if (B <= 8 && aligned(R, 16) && aligned(Y, 16)) {
+    if (C == 32 && mix_small_c<32>(f, U, R, Y, B, S)) return;
+    if (C == 64 && mix_small_c<64>(f, U, R, Y, B, S)) return;
+    if (C == 128 && mix_small_c<128>(f, U, R, Y, B, S)) return;
+  }
   GemmArgs g = gemm0();
   g.M = B;
   g.N = 2 * C;
@@ -1023,8 +1137,7 @@ void forward_impl(swense_fno* f, const float* x, float* y, int B) {
     cf* U = f->U + (size_t)(l - 1) * d.max_batch * (2 * d.q_modes + 1) * d.p_modes * C;
     spec_fwd(f, v, U, B, 1.f / ((float)d.n * d.n), 0);
     mix(f, U, f->wb + f->oR[l - 1], f->Y, B);
-    herm(f, f->Y, B, 0);
-    spec_inv(f, f->Y, tS, B, 1.f, 0.f);
+    spec_inv(f, f->Y, tS, B, 1.f, 0.f, 1);
     conv1x1(f, f->wb + f->oW[l - 1], C, C, v, v_of(f, l), B, f->w + f->ob[l - 1], tS, z_of(f, l), 1);
   }
   conv1x1(f, f->wb + f->oQ1, H, C, v_of(f, d.layers), h_of(f), B, f->w + f->oc1, nullptr, zq_of(f), 1);
@@ -1086,10 +1199,9 @@ void backward_impl(swense_fno* f, const float* x, const float* gy, float* gx, in
     const cf* U = f->U + (size_t)(l - 1) * d.max_batch * S * C;
     mix_dw(f, U, gY, f->g + f->oR[l - 1], B);
     mix_dx(f, gY, f->wb + f->oR[l - 1], gU, B);
-    herm(f, gU, B, 1);  // P(gU / c_p)
-    // gv = W^T gz + (1/n^2) Re sum gU e^{ik.x}
+    // gv = W^T gz + (1/n^2) Re sum P(gU / c_p) e^{ik.x}
     conv1x1_dx(f, f->wb + f->oW[l - 1], C, C, gz, gv, B, 0.f);
-    spec_inv(f, gU, gv, B, 1.f / ((float)plane), 1.f);
+    spec_inv(f, gU, gv, B, 1.f / ((float)plane), 1.f, 2);
   }
   trace(gv, (size_t)d.layers, cplane);
   conv1x1_dw(f, gv, x, C, d.in_channels, B, f->g + f->oW0);

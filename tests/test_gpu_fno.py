@@ -92,6 +92,29 @@ def test_fno_forward_backward_parity(gpu_lib, cfg):
     net.close()
 
 
+# Channel counts 32, 64 and 128 at batches up to 8 take the small-batch
+# spectral mixing (vector ALUs, one wavefront per mode); batch 3 runs the
+# batch-4 form with one sample masked.
+MIX_SMALL = [(F.FnoConfig(n=64, channels=32, layers=2, p_modes=8, q_modes=7, hidden=16), 1),
+             (F.FnoConfig(n=64, channels=128, layers=1, p_modes=6, q_modes=5, hidden=16), 3),
+             (F.FnoConfig(n=64, channels=64, layers=1, p_modes=5, q_modes=4, hidden=8, in_channels=4), 8)]
+
+
+@pytest.mark.parametrize("cfg,B", MIX_SMALL, ids=["c32b1", "c128b3", "c64b8"])
+def test_fno_forward_parity_small_batch_mixing(gpu_lib, cfg, B):
+    from paper_2005_12716_amd import lib
+    desc, vec, P, x = _setup(lib, cfg, B, 13)
+    net = lib.Fno(desc, vec)
+    y = net.forward(torch.tensor(x, device="cuda")).cpu().numpy()
+    yr, _ = F.forward(P, x.astype(np.float64), cfg, bf16=True)
+    assert rel(y, yr) < TOL
+    # each sample as computed alone
+    for b in range(B):
+        yb = net.forward(torch.tensor(x[b:b + 1], device="cuda")).cpu().numpy()
+        assert rel(yb[0], yr[b]) < TOL
+    net.close()
+
+
 def test_fno_adam_step_and_bf16_refresh(gpu_lib):
     from paper_2005_12716_amd import lib
     cfg = SMALL[0]
