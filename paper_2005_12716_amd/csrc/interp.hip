@@ -240,14 +240,45 @@ __global__ void __launch_bounds__(kTileThreads) k_gather_tile(GatherArgs A, Tile
     nidx[nd] = (gxn < A.wx && gyn < A.wy) ? gyn * A.wx + gxn : -1;
   }
   __syncthreads();
-  // element e = nd rec + r in the node-major layout (a node's record
-  // contiguous), e = r nodes + nd in the plane layout (a row of nodes
-  // contiguous); eight loads in flight per thread before their stores
-  const int total = nodes * rec;
   const bool plane = A.ps != 1;
-  const int dv = plane ? nodes : rec;
-  const float inv_dv = 1.0f / (float)dv;
   const int vbase = I.lb * A.fv, sbase = A.nl * A.fv - nvr;
+  if (plane) {
+    // plane layout (a row of nodes contiguous for each field-layer): thread
+    // -> (node nd, residue class rg of r modulo G), consecutive threads on
+    // consecutive nodes; each thread walks its node's record with pointer
+    // steps, eight loads in flight before their stores
+    const int G = nodes < kTileThreads ? kTileThreads / nodes : 1;
+    for (int slot = threadIdx.x; slot < G * nodes; slot += kTileThreads) {
+      const int nd = slot % nodes, rg = slot / nodes;
+      const int ni = nidx[nd];
+      if (ni < 0) continue;
+      const long long step = (long long)G * A.ps;
+      const float* src = A.coef + ni + (long long)(vbase + rg) * A.ps;
+      float* dst = lds + nd * T.stride + rg;
+      int r = rg;
+      for (; r + 7 * G < nvr; r += 8 * G) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[u * step];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dst[u * G] = v[u];
+        src += 8 * step;
+        dst += 8 * G;
+      }
+      for (; r < nvr; r += G) {
+        *dst = *src;
+        src += step;
+        dst += G;
+      }
+      // the surface fields (r in [nvr, rec), at sbase + r)
+      for (; r < rec; r += G) lds[nd * T.stride + r] = A.coef[ni + (long long)(sbase + r) * A.ps];
+    }
+  }
+  // node-major layout (a node's record contiguous): element e = nd rec + r,
+  // eight loads in flight per thread before their stores
+  const int total = plane ? 0 : nodes * rec;
+  const int dv = rec;
+  const float inv_dv = 1.0f / (float)dv;
   for (int e0 = threadIdx.x; e0 < total; e0 += 8 * kTileThreads) {
     float v[8];
     int dst[8];
@@ -258,7 +289,7 @@ __global__ void __launch_bounds__(kTileThreads) k_gather_tile(GatherArgs A, Tile
       int lo = e - hi * dv;
       if (lo < 0) { --hi; lo += dv; }
       if (lo >= dv) { ++hi; lo -= dv; }
-      const int nd = plane ? lo : hi, r = plane ? hi : lo;
+      const int nd = hi, r = lo;
       const int ni = e < total ? nidx[nd] : -1;
       dst[u] = ni >= 0 ? nd * T.stride + r : -1;
       v[u] = ni >= 0 ? A.coef[(size_t)ni * A.ns + (size_t)((r < nvr ? vbase : sbase) + r) * A.ps] : 0.f;
