@@ -274,29 +274,37 @@ __global__ void __launch_bounds__(kTileThreads) k_gather_tile(GatherArgs A, Tile
       for (; r < rec; r += G) lds[nd * T.stride + r] = A.coef[ni + (long long)(sbase + r) * A.ps];
     }
   }
-  // node-major layout (a node's record contiguous): element e = nd rec + r,
-  // eight loads in flight per thread before their stores
-  const int total = plane ? 0 : nodes * rec;
-  const int dv = rec;
-  const float inv_dv = 1.0f / (float)dv;
-  for (int e0 = threadIdx.x; e0 < total; e0 += 8 * kTileThreads) {
-    float v[8];
-    int dst[8];
+  if (!plane) {
+    // node-major layout (a node's record contiguous): a wavefront reads one
+    // record in 64-lane runs, four nodes at a time (eight loads in flight)
+    constexpr int NW = kTileThreads / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int nd0 = wave; nd0 < nodes; nd0 += 4 * NW) {
+      long long nb[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * kTileThreads;
-      int hi = (int)((float)e * inv_dv);
-      int lo = e - hi * dv;
-      if (lo < 0) { --hi; lo += dv; }
-      if (lo >= dv) { ++hi; lo -= dv; }
-      const int nd = hi, r = lo;
-      const int ni = e < total ? nidx[nd] : -1;
-      dst[u] = ni >= 0 ? nd * T.stride + r : -1;
-      v[u] = ni >= 0 ? A.coef[(size_t)ni * A.ns + (size_t)((r < nvr ? vbase : sbase) + r) * A.ps] : 0.f;
+      for (int j = 0; j < 4; ++j) {
+        const int nd = nd0 + j * NW;
+        const int ni = nd < nodes ? nidx[nd] : -1;
+        nb[j] = ni >= 0 ? (long long)ni * A.ns : -1;
+      }
+      for (int r0 = 0; r0 < rec; r0 += 128) {
+        float v[4][2];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int r = r0 + lane + 64 * hh;
+            v[j][hh] = nb[j] >= 0 && r < rec ? A.coef[nb[j] + (r < nvr ? vbase : sbase) + r] : 0.f;
+          }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int r = r0 + lane + 64 * hh;
+            if (nb[j] >= 0 && r < rec) lds[(nd0 + j * NW) * T.stride + r] = v[j][hh];
+          }
+      }
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (dst[u] >= 0) lds[dst[u]] = v[u];
   }
   __syncthreads();
   for (int i = threadIdx.x; i < I.count; i += kTileThreads) {
