@@ -211,8 +211,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NY >= 
   using C = cpx<float>;
   extern __shared__ unsigned char smem[];
   C* buf = reinterpret_cast<C*>(smem);
-  const int p = xcd_tile(blockIdx.x, gridDim.x);
-  const int l = A.nvol > 0 ? (int)blockIdx.y : A.nl;
+  // one-dimensional grid over (column, layer slot), grouped by columns
+  int p, ly;
+  grouped_tile<32>(blockIdx.x, G.nxh, A.nvol > 0 ? A.nl + (A.nsurf > 0 ? 1 : 0) : 1, p, ly);
+  const int l = A.nvol > 0 ? ly : A.nl;
   const bool surf = l == A.nl;
   const int f0 = surf ? A.nvol : 0, f1 = surf ? A.nvol + A.nsurf : A.nvol;
   const int tid = threadIdx.x, half = G.ny / 2;
@@ -1146,7 +1148,8 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     if ((ny == 256 || ny == 512 || ny == 1024) && rs >= 2 && rs <= 4 && rs * ny == py.n) {
       // residue form: one wavefront per output residue y mod rs
       const size_t lds = (size_t)rs * (ny + ny / 16 + 1) * csz;
-      dim3 grid(h->G.nxh, (A.nvol > 0 ? A.nl : 0) + (A.nsurf > 0 ? 1 : 0));
+      const int nly = (A.nvol > 0 ? A.nl : 0) + (A.nsurf > 0 ? 1 : 0);
+      dim3 grid((unsigned)(h->G.nxh * nly));  // nly = 0: no fields, nothing launched
       const cpx<float>* twy = reinterpret_cast<const cpx<float>*>(py.tw);
 #define L_YR(RS, NY) sw_launch(h, SWENSE_K_YINV_EVAL, &k_yinv_eval_r<RS, NY, NY / 256>, grid, dim3(256), lds, h->st, A, h->G, twy)
 #define L_YRN(RS)                  \
@@ -1155,11 +1158,11 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
     case 512: L_YR(RS, 512); break;  \
     default: L_YR(RS, 1024); break;  \
   }
-      switch (rs) {
-        case 2: L_YRN(2); break;
-        case 3: L_YRN(3); break;
-        default: L_YRN(4); break;
-      }
+      if (nly > 0) switch (rs) {
+          case 2: L_YRN(2); break;
+          case 3: L_YRN(3); break;
+          default: L_YRN(4); break;
+        }
 #undef L_YRN
 #undef L_YR
       ydone = true;

@@ -463,3 +463,19 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   const int xcd = b & 7, k = b >> 3;
   return xcd * q + min(xcd, r) + k;
 }
+
+// Block b of a one-dimensional grid of ncol x nly blocks -> (column p, slot
+// ly), a bijection: each XCD takes a contiguous run of the sequence (group of
+// GW adjacent columns, slot, column in the group), so a group's per-column
+// inputs stay in that XCD's L2 across the slots and the GW blocks that write
+// one slot's rows at adjacent columns run back to back.
+template <int GW>
+__device__ __forceinline__ void grouped_tile(int b, int ncol, int nly, int& p, int& ly) {
+  const int seq = xcd_tile(b, ncol * nly);
+  const int per = GW * nly;
+  const int cg = seq / per;
+  const int rem = seq - cg * per;
+  const int w = min(GW, ncol - cg * GW);
+  ly = rem / w;
+  p = cg * GW + (rem - ly * w);
+}
