@@ -303,6 +303,106 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NY >= 
   }
 }
 
+// The same residue form for mode counts whose transform has a runtime plan
+// (ny up to 64 MAXE points, any 2/3/5-smooth length): wavefront r runs the
+// ny-point transform of its modulated modes with the plan `pny`, whose
+// twiddles are every RS-th entry of the N = RS ny table `tw` that also gives
+// the modulations.
+template <int RS, int TQ, int MAXE>
+__global__ void __launch_bounds__(256) k_yinv_eval_rr(EvArgs A, Geom G, const cpx<float>* __restrict__ tw, WPlan pny) {
+  static_assert(RS >= 2 && RS <= 4, "residues");
+  using C = cpx<float>;
+  extern __shared__ unsigned char smem[];
+  C* buf = reinterpret_cast<C*>(smem);
+  const int ny = G.ny, N = RS * ny, WL = wbuf_len(ny);
+  int p, ly;
+  grouped_tile<32>(blockIdx.x, G.nxh, A.nvol > 0 ? A.nl + (A.nsurf > 0 ? 1 : 0) : 1, p, ly);
+  const int l = A.nvol > 0 ? ly : A.nl;
+  const bool surf = l == A.nl;
+  const int f0 = surf ? A.nvol : 0, f1 = surf ? A.nvol + A.nsurf : A.nvol;
+  const int tid = threadIdx.x, half = ny / 2;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const bool col = p < G.nxh && 2 * p != G.nx;
+  const int s0 = A.sid[f0];
+  int s1 = s0;
+  for (int f = f0; f < f1; ++f)
+    if (A.sid[f] != s0) s1 = A.sid[f];
+  C v0[TQ], v1[TQ], md[TQ];
+  float fc[TQ], fsn[TQ];
+  const double kx = 2.0 * M_PI * (double)p / G.lx;
+  const double bx = A.pre ? (4.0 + 2.0 * cos(2.0 * M_PI * (double)p / (double)A.gx)) / 6.0 : 1.0;
+  const double z = surf ? 0.0 : A.z[l];
+  const double kys = 2.0 * M_PI / G.ly;
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) {
+    const int q = tid + 256 * t;
+    const int qs = q >= half ? q - ny : q;
+    const bool ok = col && q < ny && qs > -half;
+    const cd a = ok ? A.srcs[s0][(size_t)q * G.nxh + p] : mk(0.0, 0.0);
+    const cd b = ok ? A.srcs[s1][(size_t)q * G.nxh + p] : mk(0.0, 0.0);
+    v0[t] = mk((float)a.x, (float)a.y);
+    v1[t] = mk((float)b.x, (float)b.y);
+    const C w = q < ny ? tw[(qs + N) % N] : mk(1.f, 0.f);
+    md[t] = mk(w.x, -w.y);
+  }
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) {
+    const int q = tid + 256 * t;
+    const int qs = q >= half ? q - ny : q;
+    const double ky = kys * (double)qs;
+    double c = 1.0, sn = 1.0;
+    if (!surf) vfactors(sqrt(kx * kx + ky * ky), z, G.depth, c, sn);
+    const double by = A.pre ? (4.0 + 2.0 * cos(2.0 * M_PI * (double)qs / (double)A.gy)) / 6.0 : 1.0;
+    const double pre = 1.0 / (bx * by);
+    fc[t] = (float)(c * pre);
+    fsn[t] = (float)(sn * pre);
+  }
+  const float kxf = (float)kx, kysf = (float)kys;
+  for (int f = f0; f < f1; ++f) {
+    if (A.alias[f] >= 0) continue;  // formed by the x pass from its alias
+    const EvField F = A.f[f];
+    const bool first = A.sid[f] == s0;
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) {
+      const int q = tid + 256 * t;
+      if (q >= ny) continue;
+      const int qs = q >= half ? q - ny : q;
+      C w = mk(0.f, 0.f);
+      if (col && qs > -half) {
+        const float fac = F.vf == 1 ? fsn[t] : fc[t];
+        const float ky = kysf * (float)qs;
+        C m;
+        switch (F.mult) {
+          case 0: m = mk(fac, 0.f); break;
+          case 1: m = mk(0.f, kxf * fac); break;
+          case 2: m = mk(0.f, ky * fac); break;
+          default: m = mk(sqrtf(kxf * kxf + ky * ky) * fac, 0.f); break;
+        }
+        w = cmul(first ? v0[t] : v1[t], m);
+      }
+#pragma unroll
+      for (int r = 0; r < RS; ++r) {
+        buf[r * WL + sk(q)] = w;
+        w = cmul(w, md[t]);
+      }
+    }
+    __syncthreads();
+    const int job = surf ? A.nvol * A.nl + (f - A.nvol) : f * A.nl + l;
+    C* dst = reinterpret_cast<C*>(A.inter) + (size_t)job * A.wy * G.nxh;
+    if (wave < RS) {
+      C* b = buf + wave * WL;
+      wave_fft<float, MAXE>(b, pny, +1, lane, RS);
+      const int r0 = ((wave - A.iy0) % RS + RS) % RS;
+      for (int rr = r0 + RS * lane; rr < A.wy; rr += RS * 64) {
+        int y = A.iy0 + rr;
+        if (y >= N) y -= N * (y / N);
+        dst[(size_t)rr * G.nxh + p] = b[sk((y - wave) / RS)];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Complex length-gx sequence whose inverse transform is a + i b at the nodes,
 // from two rows of half spectra (x modes p < nx/2), padding or folding.
 template <typename R>
@@ -1165,6 +1265,29 @@ void eval_t(swense_hos* h, const swense_grid_desc* gd, const double* zdev, unsig
         }
 #undef L_YRN
 #undef L_YR
+      ydone = true;
+    } else if (ny >= 16 && ny <= 512 && ny % 2 == 0 && rs >= 2 && rs <= 4 && rs * ny == py.n && !grp_len_ok(py.n)) {
+      // residue form with a runtime plan of the mode count (refinements of
+      // 2-4 times a 2/3/5-smooth count whose refined length has no
+      // compile-time transform); its twiddles are read from the refined
+      // length's table, so no other table is needed
+      FftPlan sub{};
+      sub.n = ny;
+      sub.tw = py.tw;
+      const WPlan pny = make_wplan(sub);
+      const size_t lds = (size_t)rs * wbuf_len(ny) * csz;
+      const int nly = (A.nvol > 0 ? A.nl : 0) + (A.nsurf > 0 ? 1 : 0);
+      dim3 grid((unsigned)(h->G.nxh * nly));
+      const cpx<float>* twy = reinterpret_cast<const cpx<float>*>(py.tw);
+#define L_RR(RS, TQ)   sw_launch(h, SWENSE_K_YINV_EVAL, &k_yinv_eval_rr<RS, TQ, 8>, grid, dim3(256), lds, h->st, A, h->G, twy, pny)
+#define L_RRN(RS)                if (ny <= 256) L_RR(RS, 1);   else L_RR(RS, 2);
+      if (nly > 0) switch (rs) {
+          case 2: L_RRN(2); break;
+          case 3: L_RRN(3); break;
+          default: L_RRN(4); break;
+        }
+#undef L_RRN
+#undef L_RR
       ydone = true;
     } else if (h->G.ny > 1 && grp_len_ok(py.n) && py.n >= h->G.ny && tq <= 4) {
     // one workgroup per (column, layer): the layer's fields share the FP64 factors

@@ -69,9 +69,10 @@ __device__ __forceinline__ void dft_any(cpx<R>* v, int sign) {
   else dft16(v, sign);
 }
 
+// ts: twiddle stride (the table holds the twiddles of a length ts n)
 template <typename R, int RAD, int MAXE>
 __device__ __forceinline__ void wave_pass(cpx<R>* buf, int n, int Ns, const cpx<R>* __restrict__ tw, int sign,
-                                          int lane) {
+                                          int lane, int ts = 1) {
   constexpr int MAXB = (MAXE + RAD - 1) / RAD;
   const int nb = n / RAD;
   const int twstep = n / (Ns * RAD);
@@ -94,7 +95,7 @@ __device__ __forceinline__ void wave_pass(cpx<R>* buf, int n, int Ns, const cpx<
       if (k > 0) {
 #pragma unroll
         for (int r = 1; r < RAD; ++r) {
-          cpx<R> w = tw[k * r * twstep];
+          cpx<R> w = tw[k * r * twstep * ts];
           if (sign > 0) w.y = -w.y;
           v[m][r] = cmul(v[m][r], w);
         }
@@ -143,18 +144,19 @@ inline int wave_maxe(int n) {
   return 64;
 }
 
+// ts: twiddle stride, for a plan whose table is that of a length ts n
 template <typename R, int MAXE>
-__device__ void wave_fft(cpx<R>* buf, const WPlan& plan, int sign, int lane) {
+__device__ void wave_fft(cpx<R>* buf, const WPlan& plan, int sign, int lane, int ts = 1) {
   const cpx<R>* tw = reinterpret_cast<const cpx<R>*>(plan.tw);
   int Ns = 1;
   for (int p = 0; p < plan.nrad; ++p) {
     switch (plan.rad[p]) {
-      case 16: wave_pass<R, 16, MAXE>(buf, plan.n, Ns, tw, sign, lane); break;
-      case 8: wave_pass<R, 8, MAXE>(buf, plan.n, Ns, tw, sign, lane); break;
-      case 4: wave_pass<R, 4, MAXE>(buf, plan.n, Ns, tw, sign, lane); break;
-      case 2: wave_pass<R, 2, MAXE>(buf, plan.n, Ns, tw, sign, lane); break;
-      case 3: wave_pass<R, 3, MAXE>(buf, plan.n, Ns, tw, sign, lane); break;
-      default: wave_pass<R, 5, MAXE>(buf, plan.n, Ns, tw, sign, lane); break;
+      case 16: wave_pass<R, 16, MAXE>(buf, plan.n, Ns, tw, sign, lane, ts); break;
+      case 8: wave_pass<R, 8, MAXE>(buf, plan.n, Ns, tw, sign, lane, ts); break;
+      case 4: wave_pass<R, 4, MAXE>(buf, plan.n, Ns, tw, sign, lane, ts); break;
+      case 2: wave_pass<R, 2, MAXE>(buf, plan.n, Ns, tw, sign, lane, ts); break;
+      case 3: wave_pass<R, 3, MAXE>(buf, plan.n, Ns, tw, sign, lane, ts); break;
+      default: wave_pass<R, 5, MAXE>(buf, plan.n, Ns, tw, sign, lane, ts); break;
     }
     Ns *= plan.rad[p];
   }

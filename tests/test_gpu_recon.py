@@ -127,13 +127,17 @@ def test_interp_parity(gpu_lib, dim, nx, ny, gx, gy, win):
     h.close()
 
 
-@pytest.mark.parametrize("nx,ny,gx,gy", [(256, 256, 512, 768), (512, 256, 1536, 1024), (1024, 256, 2048, 512)])
+@pytest.mark.parametrize("nx,ny,gx,gy", [(256, 256, 512, 768), (512, 256, 1536, 1024), (1024, 256, 2048, 512),
+                                         # 2/3/5-smooth mode counts whose refined lengths have no
+                                         # compile-time transform: runtime-plan residue y pass
+                                         (192, 150, 384, 600), (160, 360, 320, 1080), (128, 480, 256, 960)])
 def test_interp_residue_forms(gpu_lib, nx, ny, gx, gy):
-    """Refinements of 2, 3 and 4 times the mode count at 256 to 1024 modes:
-    the evaluation's residue-form transforms (one wavefront per output
-    residue of the refined grid) in both directions, with 6 layers (below
-    the skeleton threshold, so the plane x pass runs): all 11 fields at 4000
-    points of a window against the oracle."""
+    """Refinements of 2, 3 and 4 times the mode count: the evaluation's
+    residue-form transforms (one wavefront per output residue of the refined
+    grid; compile-time lengths at 256 to 1024 modes, runtime plans for the
+    2/3/5-smooth counts), with 6 layers (below the skeleton threshold, so
+    the plane x pass runs): all 11 fields at 4000 points of a window against
+    the oracle."""
     from paper_2005_12716_amd import lib
     h, g, (er, pr, A, At, eth) = _state(lib, 3, nx, ny, -1.0, steps=2)
     zl = np.linspace(-1.0, 0.2, 6)
