@@ -737,12 +737,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NX >= 
     const C w = tw[pp % N];
     md[t] = mk(w.x, -w.y);
   }
+  // the pair's two rows, read one pair ahead: the next pair's loads are in
+  // flight while the current pair is transformed and stored
+  C la[PT], lb[PT];
+  auto load_pair = [&](int pi) {
+    const int ja = 2 * pi;
+    float kk;
+    const C* ra = src_row(ja, kk);
+    const C* rb = ja + 1 < njobs ? src_row(ja + 1, kk) : nullptr;
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int pp = tid + 256 * t;
+      la[t] = pp < hx && pp < NX / 2 ? ra[pp] : mk(0.f, 0.f);
+      lb[t] = rb && pp < hx && pp < NX / 2 ? rb[pp] : mk(0.f, 0.f);
+    }
+  };
+  if (blockIdx.y * ppb < pe) load_pair(blockIdx.y * ppb);
   for (int pi = blockIdx.y * ppb; pi < pe; ++pi) {
     const int ja = 2 * pi;
     const bool hasb = ja + 1 < njobs;
     float ka, kb = 0.f;
-    const C* ra = src_row(ja, ka);
-    const C* rb = hasb ? src_row(ja + 1, kb) : nullptr;
+    (void)src_row(ja, ka);
+    if (hasb) (void)src_row(ja + 1, kb);
     // slot p (0 <= p < hx): a + i b; slot nx - p: conj(a) + i conj(b); the
     // Nyquist slot nx/2 stays zero
 #pragma unroll
@@ -751,8 +767,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NX >= 
       if (pp < NX / 2) {
         C va = mk(0.f, 0.f), vb = mk(0.f, 0.f);
         if (pp < hx) {
-          va = ra[pp];
-          if (rb) vb = rb[pp];
+          va = la[t];
+          vb = lb[t];
           if (ka != 0.f) va = mk(-ka * (float)pp * va.y, ka * (float)pp * va.x);
           if (kb != 0.f) vb = mk(-kb * (float)pp * vb.y, kb * (float)pp * vb.x);
         }
@@ -772,6 +788,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NX >= 
       }
     }
     __syncthreads();
+    if (pi + 1 < pe) load_pair(pi + 1);
     if (wave < RS) {
       C* b = buf + wave * WL;
       wave_fft_static<float, NX, RS, false>(b, tw, +1, lane);
