@@ -984,7 +984,7 @@ struct Rows3 {
     const int hx = G.nx / 2;
     const int dxa = A.in[ia].dx, dxb = ib >= 0 ? A.in[ib].dx : 0;
     if constexpr (RES) {
-      constexpr int WL = Q + Q / 16 + 1;
+      constexpr int WL = b3_stride<Q>();
 #pragma unroll
       for (int k = 0; k < KP; ++k) {
         const int p = (int)threadIdx.x + NT * k;
@@ -1034,7 +1034,7 @@ struct Rows3 {
 template <typename R, int Q, int NT, bool HT, bool RES>
 __device__ __forceinline__ void rows3_inv(cpx<R>* buf, const cpx<R>* __restrict__ tw) {
   if constexpr (RES) {
-    constexpr int WL = Q + Q / 16 + 1;
+    constexpr int WL = b3_stride<Q>();
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
     __syncthreads();
     if (wave < 3) wave_fft_static<R, Q, 3, HT>(buf + wave * WL, tw, +1, lane);
@@ -1052,7 +1052,7 @@ __device__ __forceinline__ int rows3_pt(int x) { return RES ? b3_in<Q>(x) : b3_o
 template <typename R, int Q, int NT, bool HT = true, bool RES = false>
 __device__ __forceinline__ void rows3_out(cpx<R>* buf, const cpx<R>* tw, const XArgs& A, const Geom& G, int y) {
   constexpr int Px = 3 * Q;
-  constexpr int WL = Q + Q / 16 + 1;
+  constexpr int WL = b3_stride<Q>();
   const int hx = G.nx / 2;
   const R sc = (R)(0.5 / (double)Px);
   cpx<R>* d0 = reinterpret_cast<cpx<R>*>(A.out0);

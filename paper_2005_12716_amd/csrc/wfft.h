@@ -382,16 +382,25 @@ __device__ __forceinline__ void block4_fft(cpx<R>* buf, const cpx<R>* __restrict
 // Input element n sits at b3_in<Q>(n), output element k at b3_out<Q>(k); the
 // three sub-buffers take b3_len<Q>() elements.  Each k' is combined in place
 // by one thread (it reads and writes the same three slots).
+// Sub-buffer stride: the skewed length Q + Q/16 + 1 rounded up to 11 mod 32
+// (8-byte elements), so that the consecutive elements n of b3_in, which
+// cycle through the three sub-buffers, fall into distinct banks for 16 as
+// for 32 lanes of 8-byte accesses per cycle (offsets 11 r + n/3 are distinct
+// mod 16 for n < 16 and mod 32 for n < 32).
 template <int Q>
-__host__ __device__ constexpr int b3_len() { return 3 * (Q + Q / 16 + 1); }
+__host__ __device__ constexpr int b3_stride() {
+  return (Q + Q / 16 + 1) + ((11 - (Q + Q / 16 + 1) % 32) + 32) % 32;
+}
 template <int Q>
-__device__ __forceinline__ int b3_in(int n) { return (n % 3) * (Q + Q / 16 + 1) + sk(n / 3); }
+__host__ __device__ constexpr int b3_len() { return 3 * b3_stride<Q>(); }
 template <int Q>
-__device__ __forceinline__ int b3_out(int k) { return (k / Q) * (Q + Q / 16 + 1) + sk(k % Q); }
+__device__ __forceinline__ int b3_in(int n) { return (n % 3) * b3_stride<Q>() + sk(n / 3); }
+template <int Q>
+__device__ __forceinline__ int b3_out(int k) { return (k / Q) * b3_stride<Q>() + sk(k % Q); }
 
 template <typename R, int Q>
 __device__ __forceinline__ void b3_combine(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int kq) {
-  constexpr int WL = Q + Q / 16 + 1;
+  constexpr int WL = b3_stride<Q>();
   cpx<R> a[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) a[r] = buf[r * WL + sk(kq)];
@@ -410,7 +419,7 @@ __device__ __forceinline__ void b3_combine(cpx<R>* buf, const cpx<R>* __restrict
 template <typename R, int Q>
 __device__ __forceinline__ void wave_fft3(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign, int lane) {
   static_assert(Q >= 64 && Q <= 1024 && (Q & (Q - 1)) == 0, "N = 3Q with Q a power of two in [64, 1024]");
-  constexpr int WL = Q + Q / 16 + 1;
+  constexpr int WL = b3_stride<Q>();
 #pragma unroll
   for (int r = 0; r < 3; ++r) wave_fft_static<R, Q, 3>(buf + r * WL, tw, sign, lane);
 #pragma unroll
@@ -425,7 +434,7 @@ template <typename R, int Q, int NT = 256, bool HT = false>
 __device__ __forceinline__ void block3_fft(cpx<R>* buf, const cpx<R>* __restrict__ tw, int sign) {
   static_assert(Q >= 64 && Q <= 1024 && (Q & (Q - 1)) == 0, "N = 3Q with Q a power of two in [64, 1024]");
   static_assert(NT % 64 == 0 && NT >= 192, "three wavefronts at least");
-  constexpr int WL = Q + Q / 16 + 1;
+  constexpr int WL = b3_stride<Q>();
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
   __syncthreads();
   if (wave < 3) wave_fft_static<R, Q, 3, HT>(buf + wave * WL, tw, sign, lane);
