@@ -1127,7 +1127,9 @@ float* zq_of(swense_fno* f) {
 }
 float* h_of(swense_fno* f) { return zq_of(f) + (size_t)f->d.max_batch * f->d.hidden * f->d.n * f->d.n; }
 
-void forward_impl(swense_fno* f, const float* x, float* y, int B) {
+// keep: store the pre-activations a backward pass needs (an inference call
+// skips those writes and leaves no forward for a backward to follow)
+void forward_impl(swense_fno* f, const float* x, float* y, int B, bool keep = true) {
   const auto& d = f->d;
   const int C = d.channels, H = d.hidden;
   float* tS = f->tmp + (size_t)d.max_batch * std::max(H, C) * d.n * d.n;
@@ -1138,11 +1140,11 @@ void forward_impl(swense_fno* f, const float* x, float* y, int B) {
     spec_fwd(f, v, U, B, 1.f / ((float)d.n * d.n), 0);
     mix(f, U, f->wb + f->oR[l - 1], f->Y, B);
     spec_inv(f, f->Y, tS, B, 1.f, 0.f, 1);
-    conv1x1(f, f->wb + f->oW[l - 1], C, C, v, v_of(f, l), B, f->w + f->ob[l - 1], tS, z_of(f, l), 1);
+    conv1x1(f, f->wb + f->oW[l - 1], C, C, v, v_of(f, l), B, f->w + f->ob[l - 1], tS, keep ? z_of(f, l) : nullptr, 1);
   }
-  conv1x1(f, f->wb + f->oQ1, H, C, v_of(f, d.layers), h_of(f), B, f->w + f->oc1, nullptr, zq_of(f), 1);
+  conv1x1(f, f->wb + f->oQ1, H, C, v_of(f, d.layers), h_of(f), B, f->w + f->oc1, nullptr, keep ? zq_of(f) : nullptr, 1);
   conv1x1(f, f->wb + f->oQ2, 2, H, h_of(f), y, B, f->w + f->oc2);
-  f->last_batch = B;
+  f->last_batch = keep ? B : 0;
 }
 
 void bias_grad(swense_fno* f, const float* g, float* gb, int B, int chans) {
@@ -1242,6 +1244,17 @@ int guarded_f(swense_fno* f, F&& fn) {
 
 hipStream_t fno_stream(const swense_fno* f) { return f->st; }
 swense_fno_desc fno_desc_of(const swense_fno* f) { return f->d; }
+
+// The network's output only, for callers inside the library that never
+// take a gradient (the surrogate's calls).
+__attribute__((visibility("hidden"))) int fno_forward_infer(swense_fno* f, const float* x, float* y, int batch) {
+  if (!f || !x || !y) return SWENSE_EINVAL;
+  return guarded_f(f, [&] {
+    SW_REQUIRE(batch >= 1 && batch <= f->d.max_batch, "batch outside [1, max_batch]");
+    forward_impl(f, x, y, batch, false);
+    return (int)SWENSE_OK;
+  });
+}
 
 extern "C" {
 

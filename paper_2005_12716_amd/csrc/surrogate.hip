@@ -31,6 +31,9 @@ struct swense_surrogate {
   bool spent = false;      // drift bound reached: HOS alone until the next reset
 };
 
+// network output without the pre-activations a backward pass would need
+__attribute__((visibility("hidden"))) int fno_forward_infer(swense_fno* f, const float* x, float* y, int batch);
+
 namespace {
 
 __device__ __forceinline__ double wavenumber(const Geom& G, int p, int q) {
@@ -212,7 +215,7 @@ void network_call(swense_surrogate* s, swense_surrogate_stats* st, bool force_au
     features_of(s, s->backup[0], s->backup[1], s->x);
     base_into_state(s, s->backup[0], s->backup[1]);
     if (s->in_channels == 4) features_of(s, h->xn[0], h->xn[1], s->x + 2 * np);
-    const int rc = swense_fno_forward(s->f, s->x, s->y, 1);
+    const int rc = fno_forward_infer(s->f, s->x, s->y, 1);
     if (rc != SWENSE_OK) throw SwenseError{rc, "network forward failed"};
     hipLaunchKernelGGL(k_residual_in, dim3(nblk(np)), dim3(256), 0, h->st, s->y, h->phys, h->phys + np, np,
                        s->d.rho * s->d.sigma_eta, s->d.rho * s->d.sigma_phi);

@@ -42,9 +42,12 @@ def default_scales(stride: int, base_substeps: int = 0) -> dict:
     linear dispersion (phis ~ g/omega eta, omega_p = 1), for phis; residual
     scale rho in proportion to the base's one-call error at s = 10 (about
     4e-2 linear, 7e-3 with one integrating-factor RK4 substep, 2e-4 with
-    two): 0.05, 0.005, 0.0002."""
+    two): 0.05, 0.005, 0.0002; for the RK4 bases scaled by (s / 10)^5, the
+    order of a fourth-order step's error over one call."""
     sig = 0.02 * LAM / 4.0
     rho = {0: 0.05, 1: 0.005}.get(base_substeps, 0.0002)
+    if base_substeps > 0:
+        rho *= (stride / 10.0) ** 5
     return {"stride_s": stride, "sigma_eta": sig, "sigma_phi": sig, "rho": rho, "base_substeps": base_substeps}
 
 
