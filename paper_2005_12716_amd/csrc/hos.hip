@@ -581,6 +581,124 @@ __global__ void __launch_bounds__(256) k_yfwd_r(YFwdArgs A, Geom G, WPlan plan) 
   }
 }
 
+// The residue forms with a runtime plan of the mode count, for padded
+// lengths N = RS ny whose ny is 2/3/5-smooth (up to 64 MAXE points) and
+// whose N has no compile-time transform: wavefront r runs the ny-point
+// transform with the plan `pny`, whose twiddles are every RS-th entry of the
+// N-point table that also gives the modulations.  Same jobs, symbols and
+// epilogues as k_yinv_r / k_yfwd_r.
+template <int RS, int TQ, int MAXE>
+__global__ void __launch_bounds__(256) k_yinv_rr(YInvArgs args, Geom G, WPlan plan, WPlan pny, int nrows, int row0) {
+  static_assert(RS >= 2 && RS <= 4, "residues");
+  using C = cpx<float>;
+  extern __shared__ unsigned char smem[];
+  C* buf = reinterpret_cast<C*>(smem);
+  const C* tw = reinterpret_cast<const C*>(plan.tw);
+  const int ny = G.ny, N = RS * ny, WL = wbuf_len(ny);
+  const int p = xcd_tile(blockIdx.x, gridDim.x);
+  const YInvJob& jb = args.job[blockIdx.y];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int half = ny / 2;
+  const bool col = p < G.nxh && 2 * p != G.nx;
+  cd v[TQ];
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) {
+    const int q = tid + 256 * t;
+    const int qs = q >= half ? q - ny : q;
+    v[t] = mk(0.0, 0.0);
+    if (col && q < ny && qs > -half) v[t] = jb.src[(size_t)q * G.nxh + p];
+  }
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) {
+    const int q = tid + 256 * t;
+    if (q >= ny) continue;
+    const int qs = q >= half ? q - ny : q;
+    C w = mk(0.f, 0.f);
+    if (col && qs > -half) {
+      const cd x = cmul(v[t], symbol_of(G, jb, p, qs));
+      w = mk((float)x.x, (float)x.y);
+    }
+    const C tm = tw[(qs + N) % N];
+    const C md = mk(tm.x, -tm.y);  // e^{2 pi i qs / N}
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+      buf[r * WL + sk(q)] = w;
+      w = cmul(w, md);
+    }
+  }
+  __syncthreads();
+  if (wave >= RS || p >= G.nxh) return;
+  C* b = buf + wave * WL;
+  wave_fft<float, MAXE>(b, pny, +1, lane, RS);
+  C* dst = reinterpret_cast<C*>(jb.dst);
+  const int r0 = ((wave - row0) % RS + RS) % RS;
+  for (int rr = r0 + RS * lane; rr < nrows; rr += RS * 64) {
+    int y = row0 + rr;
+    if (y >= N) y -= N * (y / N);
+    dst[(size_t)rr * G.nxh + p] = b[sk((y - wave) / RS)];
+  }
+}
+
+template <int RS, int TQ, int MAXE>
+__global__ void __launch_bounds__(256) k_yfwd_rr(YFwdArgs A, Geom G, WPlan plan, WPlan pny) {
+  static_assert(RS >= 2 && RS <= 4, "residues");
+  constexpr int T = RS * TQ;  // padded points per thread, at most
+  using C = cpx<float>;
+  extern __shared__ unsigned char smem[];
+  C* buf = reinterpret_cast<C*>(smem);
+  const C* tw = reinterpret_cast<const C*>(plan.tw);
+  const int ny = G.ny, N = RS * ny, WL = wbuf_len(ny);
+  const int p = xcd_tile(blockIdx.x, gridDim.x);
+  const YFwdJob& jb = A.job[blockIdx.y];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const bool colp = p < G.nxh;
+  const C* src = reinterpret_cast<const C*>(jb.src);
+  C colv[T];
+  EpiOps o[TQ];
+  if (colp) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int y = tid + 256 * t;
+      if (y < N) colv[t] = src[(size_t)y * G.nxh + p];
+    }
+#pragma unroll
+    for (int k = 0; k < TQ; ++k) {
+      const int q = tid + 256 * k;
+      if (q < ny) o[k] = yfwd_epi_load(jb, A.rk, (size_t)q * G.nxh + p);
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int y = tid + 256 * t;
+      if (y < N) buf[(y % RS) * WL + sk(y / RS)] = colv[t];
+    }
+  }
+  __syncthreads();
+  if (wave < RS) wave_fft<float, MAXE>(buf + wave * WL, pny, -1, lane, RS);
+  __syncthreads();
+  if (!colp) return;
+  const double inv = 1.0 / (double)N;
+#pragma unroll
+  for (int k = 0; k < TQ; ++k) {
+    const int q = tid + 256 * k;
+    if (q >= ny) continue;
+    const int qs = signed_q(q, ny);
+    cd v = mk(0.0, 0.0);
+    if (2 * p != G.nx && !(ny > 1 && 2 * q == ny)) {
+      const C w1 = tw[(qs + N) % N];  // e^{-2 pi i qs / N}
+      C acc = buf[sk(q)], w = w1;
+#pragma unroll
+      for (int r = 1; r < RS; ++r) {
+        acc = acc + cmul(buf[r * WL + sk(q)], w);
+        w = cmul(w, w1);
+      }
+      v = mk((double)acc.x * inv, (double)acc.y * inv);
+    }
+    yfwd_epi_store(jb, A.rk, G, p, q, qs, v, o[k]);
+  }
+}
+
 // Fused x pass, wavefront version: block = physical row y, four wavefronts.
 // Field pairs are spread over the wavefronts (each transforms its pair in
 // its own LDS buffer and leaves the two real rows in LDS); after one block
@@ -1492,6 +1610,28 @@ void yinv_t(swense_hos* h, const YInvArgs& a, const FftPlan& plan, int nrows, in
 #undef L_YIR
       return;
     }
+    if (ny >= 16 && ny <= 512 && ny % 2 == 0 && rs >= 2 && rs <= 4 && rs * ny == plan.n && !grp_len_ok(plan.n)) {
+      // residue form with a runtime plan of the mode count (twiddles from the padded table)
+      const WPlan wp = make_wplan(plan);
+      FftPlan sub{};
+      sub.n = ny;
+      sub.tw = plan.tw;
+      const WPlan pny = make_wplan(sub);
+      const size_t lds = (size_t)rs * wbuf_len(ny) * sizeof(cpx<R>);
+      dim3 grid(h->G.nxh, a.njobs);
+#define L_YIRR(RS, TQ) sw_launch(h, SWENSE_K_YINV, &k_yinv_rr<RS, TQ, 8>, grid, dim3(256), lds, st, a, h->G, wp, pny, nrows, row0)
+#define L_YIRRN(RS)              \
+  if (ny <= 256) L_YIRR(RS, 1); \
+  else L_YIRR(RS, 2);
+      switch (rs) {
+        case 2: L_YIRRN(2); break;
+        case 3: L_YIRRN(3); break;
+        default: L_YIRRN(4); break;
+      }
+#undef L_YIRRN
+#undef L_YIRR
+      return;
+    }
   }
   if (grp_len_ok(plan.n) && h->G.ny > 1 && plan.n >= h->G.ny) {
     const WPlan wp = make_wplan(plan);
@@ -1559,6 +1699,28 @@ void yfwd_t(swense_hos* h, const YFwdArgs& a, const FftPlan& plan, hipStream_t s
       }
 #undef L_YFRN
 #undef L_YFR
+      return;
+    }
+    if (ny >= 16 && ny <= 512 && ny % 2 == 0 && rs >= 2 && rs <= 4 && rs * ny == plan.n && !grp_len_ok(plan.n)) {
+      // residue form with a runtime plan of the mode count (twiddles from the padded table)
+      const WPlan wp = make_wplan(plan);
+      FftPlan sub{};
+      sub.n = ny;
+      sub.tw = plan.tw;
+      const WPlan pny = make_wplan(sub);
+      const size_t lds = (size_t)rs * wbuf_len(ny) * sizeof(cpx<R>);
+      dim3 grid(h->G.nxh, a.njobs);
+#define L_YFRR(RS, TQ) sw_launch(h, SWENSE_K_YFWD, &k_yfwd_rr<RS, TQ, 8>, grid, dim3(256), lds, st, a, h->G, wp, pny)
+#define L_YFRRN(RS)              \
+  if (ny <= 256) L_YFRR(RS, 1); \
+  else L_YFRR(RS, 2);
+      switch (rs) {
+        case 2: L_YFRRN(2); break;
+        case 3: L_YFRRN(3); break;
+        default: L_YFRRN(4); break;
+      }
+#undef L_YFRRN
+#undef L_YFRR
       return;
     }
   }

@@ -108,6 +108,30 @@ def test_rhs_parity_runtime_rows(gpu_lib, dim, nx, ny, depth, M, dealias, precis
     test_rhs_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision)
 
 
+# Padded y lengths of 2 and 3 times a 2/3/5-smooth mode count that have no
+# compile-time transform: the residue-form y passes with runtime plans of the
+# mode count (one wavefront per residue).
+YRR_CASES = [
+    # dim, nx, ny, depth, M, dealias   -> padded Py = rs ny
+    (3, 32, 150, -1.0, 3, 1),  # 300 = 2 x 150
+    (3, 24, 160, 2.0, 3, 1),   # 320 = 2 x 160, finite depth
+    (3, 16, 120, -1.0, 5, 1),  # 360 = 3 x 120
+    (3, 16, 90, 1.5, 5, 1),    # 270 = 3 x 90, finite depth
+    (3, 32, 16, -1.0, 3, 1),   # 32 = 2 x 16
+]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("dim,nx,ny,depth,M,dealias", YRR_CASES)
+def test_rhs_parity_runtime_residue_y(gpu_lib, dim, nx, ny, depth, M, dealias, precision):
+    test_rhs_parity(gpu_lib, dim, nx, ny, depth, M, dealias, precision)
+
+
+@pytest.mark.parametrize("dim,nx,ny,depth,M,dealias", YRR_CASES[:2])
+def test_steps_parity_runtime_residue_y(gpu_lib, dim, nx, ny, depth, M, dealias):
+    test_steps_parity(gpu_lib, dim, nx, ny, depth, M, dealias, 0)
+
+
 @pytest.mark.parametrize("dim,nx,ny,depth,M,dealias,precisions", X3_CASES)
 def test_rhs_parity_three_way_x_transforms(gpu_lib, dim, nx, ny, depth, M, dealias, precisions):
     for precision in precisions:
