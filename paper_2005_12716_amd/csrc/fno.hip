@@ -551,10 +551,6 @@ __global__ void __launch_bounds__(256) k_fno_ix(const cf* __restrict__ xi, float
   }
 }
 
-// Spectral weight gradient: gR[s][i][o] = sum_b conj(U[b][s][i]) gY[b][s][o]
-// with both factors rounded to BF16.  A handful of samples per mode makes
-// this an outer-product sum bound by the store of gR, so it runs on plain
-// FP32 FMAs, one block per mode, the factors staged in LDS.
 // Spectral mixing at small batch, Y[b][s][o] = sum_i U[b][s][i] R[s][i][o]
 // for b < B <= BB: a weight-bandwidth-bound product (each mode's C x C
 // complex BF16 block is read once and used B times), so it runs on the vector
@@ -626,6 +622,121 @@ __global__ void __launch_bounds__(256) k_mix_small(const cf* __restrict__ U, con
     }
 }
 
+// One Fourier layer's output row, fused: for sample b, grid row y and half h
+// of the output channels, the inverse x transforms of the row's retained
+// modes for those channels (the spectral branch, channel pairs as one
+// complex sequence, k_fno_ix's arithmetic) land in LDS while the layer
+// input's row values the 1x1 convolution needs are read into registers as
+// BF16; the convolution runs on 16x16x32 BF16 MFMA with k_gemm_bf16's
+// operands and K order, and the epilogue adds the bias and the spectral
+// branch, keeps the pre-activation (zout, when non-null) and applies GELU.
+// Results equal the unfused kernels' bit for bit; the spectral branch never
+// goes through HBM.  512 threads: wavefront w transforms channel pairs
+// 16 h + w and 16 h + w + 8 and computes x tiles 2w, 2w + 1 (16 points
+// each) of the half's 32 output channels.
+constexpr int kRowC = 64;
+template <int N>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_fno_row(const cf* __restrict__ xi, const float* __restrict__ vin,
+                                                 const unsigned short* __restrict__ W, const float* __restrict__ bias,
+                                                 float* __restrict__ vout, float* __restrict__ zout, FnoDims d,
+                                                 WPlan plan) {
+  static_assert(N == 256, "one row of 256 points, 16 x tiles over 8 wavefronts");
+  constexpr int C = kRowC, TP = N + 16, HC = C / 2;
+  extern __shared__ unsigned char smem[];
+  float* ts = reinterpret_cast<float*>(smem);                  // [half's channel][x], pitch TP
+  cf* fb = reinterpret_cast<cf*>(ts + (size_t)HC * TP);        // per-wavefront transform buffers
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int h = blockIdx.x & 1, row = blockIdx.x >> 1;
+  const int b = row / N, y = row - b * N;
+  const size_t plane = (size_t)N * N;
+  const int kq = 8 * (lane >> 4);
+  cf* buf = fb + (size_t)wave * wbuf_len(N);
+#pragma unroll 1
+  for (int cp = HC / 2 * h + wave; cp < HC / 2 * (h + 1); cp += 8) {
+    const cf* ra = xi + (((size_t)b * C + 2 * cp) * N + y) * d.P;
+    const cf* rb = xi + (((size_t)b * C + 2 * cp + 1) * N + y) * d.P;
+    for (int s2 = lane; s2 < N; s2 += 64) {
+      cf z = mk(0.f, 0.f);
+      int p = -1;
+      bool cj = false;
+      if (s2 < d.P) p = s2;
+      else if (s2 > N - d.P) { p = N - s2; cj = true; }
+      if (p >= 0) {
+        cf va = ra[p], vb = rb[p];
+        if (cj) { va = conjg(va); vb = conjg(vb); }
+        if (p == 0) { va.y = 0.f; vb.y = 0.f; }
+        z = mk(va.x - vb.y, va.y + vb.x);
+      }
+      buf[sk(s2)] = z;
+    }
+    wave_sync();
+    wave_fft_any<float, 8, N, true>(buf, plan, +1, lane);
+    const int c0 = 2 * cp - HC * h;
+    for (int x = lane; x < N; x += 64) {
+      const cf z = buf[sk(x)];
+      ts[c0 * TP + x] = 0.f + 1.f * z.x;
+      ts[(c0 + 1) * TP + x] = 0.f + 1.f * z.y;
+    }
+    wave_sync();
+  }
+  // the convolution's B operands (input channels k0 + kq .. + 7 at this
+  // lane's x of each tile), read once the transforms are done (held
+  // across them they would cost the registers of a second workgroup per CU)
+  float vr[2][2][8];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int x = 16 * (2 * wave + j) + (lane & 15);
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) vr[j][kc][u] = vin[((size_t)b * C + 32 * kc + kq + u) * plane + (size_t)y * N + x];
+  }
+  __syncthreads();
+  v4f acc[2][2];
+#pragma unroll
+  for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[ot][j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kc = 0; kc < 2; ++kc) {
+    v8bf af[2], bfr[2];
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot)
+      af[ot] = __builtin_bit_cast(
+          v8bf, *reinterpret_cast<const v8s*>(W + (size_t)(HC * h + 16 * ot + (lane & 15)) * C + 32 * kc + kq));
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      v8s t;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = (short)f2bf(vr[j][kc][u]);
+      bfr[j] = __builtin_bit_cast(v8bf, t);
+    }
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[ot][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ot], bfr[j], acc[ot][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ol = 16 * ot + 4 * (lane >> 4) + r, o = HC * h + ol;
+        const int x = 16 * (2 * wave + j) + (lane & 15);
+        float v = 1.f * acc[ot][j][r];
+        v += bias[o];
+        v += ts[ol * TP + x];
+        const size_t ci = ((size_t)b * C + o) * plane + (size_t)y * N + x;
+        if (zout) zout[ci] = v;
+        vout[ci] = gelu_f(v);
+      }
+}
+
+// Spectral weight gradient: gR[s][i][o] = sum_b conj(U[b][s][i]) gY[b][s][o]
+// with both factors rounded to BF16.  A handful of samples per mode makes
+// this an outer-product sum bound by the store of gR, so it runs on plain
+// FP32 FMAs, one block per mode, the factors staged in LDS.
 __global__ void __launch_bounds__(256) k_mix_dw(const cf* __restrict__ U, const cf* __restrict__ gY,
                                                 float* __restrict__ gR, int B, int S, int C) {
   extern __shared__ unsigned char smem[];
@@ -746,6 +857,7 @@ struct swense_fno {
   size_t npart = 0;
   float* sums = nullptr;
   int last_batch = 0;
+  bool fuse_rows = false;  // layers through k_fno_row (64 channels, 256-point rows, aligned weights)
   float* trace = nullptr;  // caller's buffer for the backward's intermediate gradients (checking)
   void* mem = nullptr;
 };
@@ -1127,6 +1239,24 @@ float* zq_of(swense_fno* f) {
 }
 float* h_of(swense_fno* f) { return zq_of(f) + (size_t)f->d.max_batch * f->d.hidden * f->d.n * f->d.n; }
 
+// dynamic LDS of k_fno_row<256>: the spectral branch's row for half the
+// channels, eight transform buffers
+constexpr size_t kRowLds = (size_t)(kRowC / 2) * (256 + 16) * 4 + 8ull * (256 + 16 + 1) * sizeof(cf);
+
+// One layer's spectral inverse and 1x1 convolution fused per row (k_fno_row)
+// when its shapes fit: 64 channels, 256 points per row, 16-byte aligned
+// weights.  Returns false when the unfused kernels must run.
+bool layer_row(swense_fno* f, const unsigned short* W, const float* in, float* out, int B, const float* bias,
+               float* zout) {
+  const auto& d = f->d;
+  if (d.channels != kRowC || d.n != 256 || !aligned(W, 16) || !aligned(f->xi, 8)) return false;
+  const FnoDims dd{256, d.channels, d.p_modes, d.q_modes, B};
+  hipLaunchKernelGGL(k_fno_row<256>, dim3((unsigned)(B * 256 * 2)), dim3(512), kRowLds, f->st, f->xi, in, W, bias, out, zout,
+                     dd, f->plan);
+  SW_HIP(hipGetLastError());
+  return true;
+}
+
 // keep: store the pre-activations a backward pass needs (an inference call
 // skips those writes and leaves no forward for a backward to follow)
 void forward_impl(swense_fno* f, const float* x, float* y, int B, bool keep = true) {
@@ -1139,6 +1269,17 @@ void forward_impl(swense_fno* f, const float* x, float* y, int B, bool keep = tr
     cf* U = f->U + (size_t)(l - 1) * d.max_batch * (2 * d.q_modes + 1) * d.p_modes * C;
     spec_fwd(f, v, U, B, 1.f / ((float)d.n * d.n), 0);
     mix(f, U, f->wb + f->oR[l - 1], f->Y, B);
+    if (f->fuse_rows) {
+      // the y inverse into xi, then the fused x inverse + 1x1 convolution per row
+      const FnoDims dd{d.n, C, d.p_modes, d.q_modes, B};
+      const size_t lds = 4ull * wbuf_len(d.n) * sizeof(cf);
+      hipLaunchKernelGGL(k_fno_iy<256>, dim3((B * C * d.p_modes + 3) / 4), dim3(256), lds, f->st, f->Y, f->xi, dd,
+                         f->plan, 1);
+      SW_HIP(hipGetLastError());
+      if (layer_row(f, f->wb + f->oW[l - 1], v, v_of(f, l), B, f->w + f->ob[l - 1], keep ? z_of(f, l) : nullptr))
+        continue;
+      throw SwenseError{SWENSE_EHIP, "fused layer rows unavailable"};
+    }
     spec_inv(f, f->Y, tS, B, 1.f, 0.f, 1);
     conv1x1(f, f->wb + f->oW[l - 1], C, C, v, v_of(f, l), B, f->w + f->ob[l - 1], tS, keep ? z_of(f, l) : nullptr, 1);
   }
@@ -1273,6 +1414,11 @@ int swense_fno_create(const swense_fno_desc* d, const float* params, void* strea
     SW_REQUIRE(f->nparam == count_params(*d), "internal layout mismatch");
     f->plan = make_wplan(f->tw.get(d->n, false));
     allocate_fno(f);
+    f->fuse_rows = d->channels == kRowC && d->n == 256 && aligned(f->xi, 8);
+    for (int l = 0; l < d->layers; ++l) f->fuse_rows = f->fuse_rows && aligned(f->wb + f->oW[l], 16);
+    if (f->fuse_rows)
+      SW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fno_row<256>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowLds));
     SW_HIP(hipMemcpy(f->w, params, f->nparam * 4, hipMemcpyHostToDevice));
     hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((f->nparam + 255) / 256)), dim3(256), 0, f->st, f->w, f->wb,
                        (long long)f->nparam);
