@@ -638,8 +638,8 @@ constexpr int kRowC = 64;
 template <int N>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_fno_row(const cf* __restrict__ xi, const float* __restrict__ vin,
                                                  const unsigned short* __restrict__ W, const float* __restrict__ bias,
-                                                 float* __restrict__ vout, float* __restrict__ zout, FnoDims d,
-                                                 WPlan plan) {
+                                                 float* __restrict__ vout, float* __restrict__ zout,
+                                                 cf* __restrict__ xn, FnoDims d, WPlan plan) {
   static_assert(N == 256, "one row of 256 points, 16 x tiles over 8 wavefronts");
   constexpr int C = kRowC, TP = N + 16, HC = C / 2;
   extern __shared__ unsigned char smem[];
@@ -729,8 +729,29 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
         v += ts[ol * TP + x];
         const size_t ci = ((size_t)b * C + o) * plane + (size_t)y * N + x;
         if (zout) zout[ci] = v;
-        vout[ci] = gelu_f(v);
+        const float g = gelu_f(v);
+        vout[ci] = g;
+        if (xn) ts[ol * TP + x] = g;  // this lane's own slot, read just above
       }
+  if (!xn) return;
+  // the next layer's forward x transforms of the half's rows (k_fno_fx's
+  // arithmetic): channel pairs as one complex sequence, kept modes unpacked
+  __syncthreads();
+#pragma unroll 1
+  for (int lp = wave; lp < HC / 2; lp += 8) {
+    for (int x = lane; x < N; x += 64) buf[sk(x)] = mk(ts[(2 * lp) * TP + x], ts[(2 * lp + 1) * TP + x]);
+    wave_sync();
+    wave_fft_any<float, 8, N, true>(buf, plan, -1, lane);
+    const float sc = 0.5f;
+    const int c = HC * h + 2 * lp;
+    for (int p = lane; p < d.P; p += 64) {
+      const cf zp = buf[sk(p)], zm = conjg(buf[sk((N - p) % N)]);
+      const cf s2 = zp + zm, t = zp - zm;
+      xn[(((size_t)b * C + c) * N + y) * d.P + p] = cscale(s2, sc);
+      xn[(((size_t)b * C + c + 1) * N + y) * d.P + p] = mk(t.y * sc, -t.x * sc);
+    }
+    wave_sync();
+  }
 }
 
 // Spectral weight gradient: gR[s][i][o] = sum_b conj(U[b][s][i]) gY[b][s][o]
@@ -849,6 +870,7 @@ struct swense_fno {
   float* act = nullptr;  // v_0 .. v_L, z_1 .. z_L, zq, h  (each [B][C or H][n][n])
   float* tmp = nullptr;  // scratch [B][H][n][n] x 2
   cf* xi = nullptr;      // [B][C][n][P]
+  cf* xi2 = nullptr;     // the same, the fused rows' forward modes of the next layer
   cf* U = nullptr;       // per layer [B][S][C]
   cf* Y = nullptr;       // [B][S][C]
   float* part = nullptr;     // split-K partials
@@ -1199,9 +1221,11 @@ void allocate_fno(swense_fno* f) {
   const size_t npart2 = (size_t)kReduceGroups * maxmn;
   const size_t nrow = 64 * std::max(C, H);
   f->npart = npart;
-  size_t bytes = f->nparam * (4 + 2 + 4 + 4 + 4) + nact * 4 + ntmp * 4 + nxi * 8 + nU * 8 + nY * 8 + npart * 4 +
-                 npart2 * 4 + nrow * 4 + 3 * 256 +
-                 2 * B * 2 * 4 + 16 * 256;
+  // the fused layer rows write the next layer's forward x modes beside the
+  // current inverse ones
+  const size_t nxi2 = (C == kRowC && d.n == 256) ? nxi : 0;
+  size_t bytes = f->nparam * (4 + 2 + 4 + 4 + 4) + nact * 4 + ntmp * 4 + (nxi + nxi2) * 8 + nU * 8 + nY * 8 +
+                 npart * 4 + npart2 * 4 + nrow * 4 + 3 * 256 + 2 * B * 2 * 4 + 17 * 256;
   SW_HIP(hipMalloc(&f->mem, bytes));
   SW_HIP(hipMemset(f->mem, 0, bytes));
   char* p = reinterpret_cast<char*>(f->mem);
@@ -1218,6 +1242,7 @@ void allocate_fno(swense_fno* f) {
   f->act = reinterpret_cast<float*>(take(nact * 4));
   f->tmp = reinterpret_cast<float*>(take(ntmp * 4));
   f->xi = reinterpret_cast<cf*>(take(nxi * 8));
+  f->xi2 = nxi2 ? reinterpret_cast<cf*>(take(nxi2 * 8)) : nullptr;
   f->U = reinterpret_cast<cf*>(take(nU * 8));
   f->Y = reinterpret_cast<cf*>(take(nY * 8));
   f->part = reinterpret_cast<float*>(take(npart * 4));
@@ -1247,12 +1272,12 @@ constexpr size_t kRowLds = (size_t)(kRowC / 2) * (256 + 16) * 4 + 8ull * (256 + 
 // when its shapes fit: 64 channels, 256 points per row, 16-byte aligned
 // weights.  Returns false when the unfused kernels must run.
 bool layer_row(swense_fno* f, const unsigned short* W, const float* in, float* out, int B, const float* bias,
-               float* zout) {
+               float* zout, cf* xn) {
   const auto& d = f->d;
   if (d.channels != kRowC || d.n != 256 || !aligned(W, 16) || !aligned(f->xi, 8)) return false;
   const FnoDims dd{256, d.channels, d.p_modes, d.q_modes, B};
   hipLaunchKernelGGL(k_fno_row<256>, dim3((unsigned)(B * 256 * 2)), dim3(512), kRowLds, f->st, f->xi, in, W, bias, out, zout,
-                     dd, f->plan);
+                     xn, dd, f->plan);
   SW_HIP(hipGetLastError());
   return true;
 }
@@ -1267,7 +1292,16 @@ void forward_impl(swense_fno* f, const float* x, float* y, int B, bool keep = tr
   for (int l = 1; l <= d.layers; ++l) {
     const float* v = v_of(f, l - 1);
     cf* U = f->U + (size_t)(l - 1) * d.max_batch * (2 * d.q_modes + 1) * d.p_modes * C;
-    spec_fwd(f, v, U, B, 1.f / ((float)d.n * d.n), 0);
+    if (f->fuse_rows && l > 1) {
+      // the x modes of this layer's input came with the previous layer's rows
+      const FnoDims dd{d.n, C, d.p_modes, d.q_modes, B};
+      const size_t lds = 4ull * wbuf_len(d.n) * sizeof(cf);
+      hipLaunchKernelGGL(k_fno_fy<256>, dim3((B * C * d.p_modes + 3) / 4), dim3(256), lds, f->st, f->xi2, U, dd,
+                         f->plan, 1.f / ((float)d.n * d.n), 0);
+      SW_HIP(hipGetLastError());
+    } else {
+      spec_fwd(f, v, U, B, 1.f / ((float)d.n * d.n), 0);
+    }
     mix(f, U, f->wb + f->oR[l - 1], f->Y, B);
     if (f->fuse_rows) {
       // the y inverse into xi, then the fused x inverse + 1x1 convolution per row
@@ -1276,7 +1310,8 @@ void forward_impl(swense_fno* f, const float* x, float* y, int B, bool keep = tr
       hipLaunchKernelGGL(k_fno_iy<256>, dim3((B * C * d.p_modes + 3) / 4), dim3(256), lds, f->st, f->Y, f->xi, dd,
                          f->plan, 1);
       SW_HIP(hipGetLastError());
-      if (layer_row(f, f->wb + f->oW[l - 1], v, v_of(f, l), B, f->w + f->ob[l - 1], keep ? z_of(f, l) : nullptr))
+      if (layer_row(f, f->wb + f->oW[l - 1], v, v_of(f, l), B, f->w + f->ob[l - 1], keep ? z_of(f, l) : nullptr,
+                    l < d.layers ? f->xi2 : nullptr))
         continue;
       throw SwenseError{SWENSE_EHIP, "fused layer rows unavailable"};
     }
@@ -1414,7 +1449,7 @@ int swense_fno_create(const swense_fno_desc* d, const float* params, void* strea
     SW_REQUIRE(f->nparam == count_params(*d), "internal layout mismatch");
     f->plan = make_wplan(f->tw.get(d->n, false));
     allocate_fno(f);
-    f->fuse_rows = d->channels == kRowC && d->n == 256 && aligned(f->xi, 8);
+    f->fuse_rows = d->channels == kRowC && d->n == 256 && aligned(f->xi, 8) && f->xi2 != nullptr;
     for (int l = 0; l < d->layers; ++l) f->fuse_rows = f->fuse_rows && aligned(f->wb + f->oW[l], 16);
     if (f->fuse_rows)
       SW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fno_row<256>),
