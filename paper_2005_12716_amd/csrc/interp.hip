@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(256) k_gather_col(GatherArgs A, const Col* __r
 // Points: one thread each, 4 x 4 horizontal taps (4 x 1 in 2D) of 4 layers
 // per volume field, 16 (4) taps per surface field.
 template <int THREE>
-__global__ void __launch_bounds__(kTileThreads) k_gather_tile(GatherArgs A, TileDev T, PtDev pd) {
+__global__ void __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(5))) k_gather_tile(GatherArgs A, TileDev T, PtDev pd) {
   extern __shared__ float lds[];
   const int it = xcd_tile(blockIdx.x, gridDim.x);
   if (it >= T.nitems) return;  // uniform over the workgroup
@@ -696,7 +696,9 @@ long long tile_stride(int fv, int tl, int fs) {
 // lines its staging reads plus a fixed 16 KB for its launch slot, so that
 // sparse clouds take large tiles and dense ones small tiles with less halo.  Sized
 // for the full field set (8 volume and 2 surface fields in 3D, 6 and 2 in
-// 2D); one block at most 53 KB, so that three workgroups share a CU.
+// 2D); one block at most 31 KB, so that five workgroups share a CU (the
+// kernel is held to five wavefronts per SIMD: measured on the 20M-point hex
+// cloud, 1.77 ms with three 53 KB workgroups per CU, 1.34 ms with five).
 void choose_tile(swense_cells* c, const std::vector<int>& ixs, const std::vector<int>& iys,
                  const std::vector<char>& okh, const std::vector<int>& l0, bool three) {
   const int nl = c->gd.nl, wx = c->gd.wx, wy = three ? c->gd.wy : 1;
@@ -718,7 +720,7 @@ void choose_tile(swense_cells* c, const std::vector<int>& ixs, const std::vector
       const long long stride = tile_stride(fv, tl, fs);
       const long long nodes = (long long)(T + 3) * (three ? T + 3 : 1);
       const long long lds = nodes * (stride + 1) * 4;
-      if (lds > 53 * 1024) continue;
+      if (lds > 31 * 1024) continue;
       // bytes the staging moves through the caches: each node's band is one
       // run of fv tl floats (whole 128-byte lines), its surface floats one more line
       const double staged = (double)nodes * (std::ceil((fv * tl * 4.0 + 124.0) / 128.0) + 1.0) * 128.0;
