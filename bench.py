@@ -131,14 +131,19 @@ def batched_setup(lib, torch, pts_scale=1.0, fields=None, streams=None, padding=
     return hoses, cells, outs, npts, mask, nf
 
 
-def run_batched(lib, torch, steps):
+def run_batched(lib, torch, steps, fixed=False):
+    """fixed: product-grid policy 2 for every realisation and the graph's
+    default branch count (no timed choices: a short run for counter passes)."""
     import tempfile
     t0 = time.time()
-    hoses, cells, outs, npts, mask, nf = batched_setup(lib, torch, padding="tune")
+    hoses, cells, outs, npts, mask, nf = batched_setup(lib, torch, padding=2 if fixed else "tune")
     setup_s = time.time() - t0
     b = lib.Batch(hoses, cells, [mask] * len(hoses), outs, nsteps=1)
-    with tempfile.TemporaryDirectory() as td:
-        k, tune_ms = b.autotune(os.path.join(td, "tune.json"))
+    if fixed:
+        k, tune_ms = None, None
+    else:
+        with tempfile.TemporaryDirectory() as td:
+            k, tune_ms = b.autotune(os.path.join(td, "tune.json"))
     b.run()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -719,6 +724,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline only (no other configurations)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-fixed", action="store_true",
+                    help="batched leg with product-grid policy 2 everywhere and no branch autotuning (counter passes)")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-trajectories", type=int, default=100)
     ap.add_argument("--surrogate-iters", type=int, default=1000)
@@ -746,7 +753,7 @@ def main():
         torch.cuda.set_device(0)
         run = {"cylinder": lambda: run_cylinder(lib, torch, max(20, args.steps), args.warmup),
                "regular_wave_2d": lambda: run_regular_2d(lib, torch, args.steps),
-               "batched": lambda: run_batched(lib, torch, max(2, args.steps // 4)),
+               "batched": lambda: run_batched(lib, torch, max(2, args.steps // 4), args.batched_fixed),
                "surrogate": lambda: run_surrogate(lib, torch, max(5, args.steps), args.surrogate_trajectories,
                                                   args.surrogate_iters)}[args.only]
         print(json.dumps({args.only: run()}))
