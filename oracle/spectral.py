@@ -29,6 +29,17 @@ def next_5smooth_even(n: int) -> int:
         v += 2
 
 
+def next_2k_or_3x2k(n: int) -> int:
+    """Smallest 2^a or 3 2^a (a >= 1) at or above n."""
+    best = None
+    for b in (2, 6):
+        c = b
+        while c < n:
+            c *= 2
+        best = c if best is None else min(best, c)
+    return best
+
+
 @dataclass
 class Grid:
     """Mode grid, depth and padding of one realisation."""
@@ -56,11 +67,16 @@ class Grid:
 
     def padded(self) -> tuple[int, int]:
         """Product grid: the (M+1)/2 rule, Px >= (M+1) Nx / 2, so products of
-        up to M band-limited factors alias nothing into the kept band."""
+        up to M band-limited factors alias nothing into the kept band.  The
+        length at or above the rule is a choice (dealias = 1: the next even
+        2/3/5-smooth length; 2: the next 2^a or 3 2^a); products with more
+        factors than the rule covers alias by amounts that depend on it, so a
+        comparison takes the length of the computation it checks."""
         if not self.dealias:
             return self.nx, self.ny
-        px = next_5smooth_even(-(-(self.order_m + 1) * self.nx // 2))
-        py = 1 if self.ny == 1 else next_5smooth_even(-(-(self.order_m + 1) * self.ny // 2))
+        nxt = next_2k_or_3x2k if self.dealias == 2 else next_5smooth_even
+        px = nxt(-(-(self.order_m + 1) * self.nx // 2))
+        py = 1 if self.ny == 1 else nxt(-(-(self.order_m + 1) * self.ny // 2))
         return px, py
 
     # wavenumbers on the half spectrum -------------------------------------------------

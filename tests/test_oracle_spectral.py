@@ -41,6 +41,37 @@ def test_splitmix64_published_vector():
     assert u == (0xE220A8397B1DCDAF >> 11) * 2.0 ** -53
 
 
+@pytest.mark.parametrize("nx,ny,M,dealias,expect", [
+    # (M+1) n / 2 -> policy 1 (next even 2/3/5-smooth) or 2 (next 2^a or 3 2^a)
+    (150, 480, 3, 1, (300, 960)), (150, 480, 3, 2, (384, 1024)),
+    (500, 160, 3, 2, (1024, 384)), (40, 10, 5, 2, (128, 32)),
+    (24, 20, 4, 2, (64, 64)), (1024, 1, 5, 2, (3072, 1)), (25, 25, 4, 1, (64, 64)), (25, 25, 4, 2, (64, 64)),
+])
+def test_product_grid_lengths(nx, ny, M, dealias, expect):
+    g = Grid(nx=nx, ny=ny, lx=1.0, ly=1.0, depth=-1.0, order_m=M, dealias=dealias)
+    assert g.padded() == expect
+
+
+@pytest.mark.parametrize("dealias", [1, 2])
+def test_products_of_m_factors_alias_nothing_into_the_kept_band(dealias):
+    """The rule's defining property on both policies: the kept modes of a
+    product of M band-limited fields formed on the product grid equal those
+    of the exact product (a direct sum on a grid fine enough for all of its
+    modes)."""
+    g = Grid(nx=10, ny=6, lx=3.0, ly=2.0, depth=-1.0, order_m=3, dealias=dealias)
+    fs = [_rand_spec(g, 10 + i) for i in range(g.order_m)]
+    prod = np.ones(g.padded()[::-1])
+    for f in fs:
+        prod = prod * g.to_phys(f)
+    got = g.to_spec(prod)
+    # exact: the same product sampled on a grid of at least (M N) points per axis
+    big = Grid(nx=10, ny=6, lx=3.0, ly=2.0, depth=-1.0, order_m=7, dealias=1)
+    pe = np.ones(big.padded()[::-1])
+    for f in fs:
+        pe = pe * big.to_phys(f)
+    assert np.allclose(got, big.to_spec(pe), atol=1e-12, rtol=0)
+
+
 @pytest.mark.parametrize("nx,ny", [(8, 1), (12, 1), (8, 6), (10, 4)])
 def test_to_phys_equals_direct_sum(nx, ny):
     g = Grid(nx=nx, ny=ny, lx=3.0, ly=2.0, depth=1.0, order_m=3)
