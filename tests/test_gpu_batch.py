@@ -58,7 +58,7 @@ def test_batch_matches_individual_runs(gpu_lib):
         rc = ref.bind(gd, torch.tensor(pts, device="cuda"))
         o_r, _ = rc.interp(mask)
         assert torch.equal(out, o_r)
-        g = Grid(nx=d.nx, ny=d.ny, lx=d.lx, ly=d.ly, depth=-1.0, order_m=3)
+        g = Grid(nx=d.nx, ny=d.ny, lx=d.lx, ly=d.ly, depth=-1.0, order_m=3, dealias=d.dealias)
         er, pr = hos.run(g, eh, ph, d.dt, 6)
         assert np.linalg.norm(e_b - er) / np.linalg.norm(er) < 1e-6
         rc.close()
@@ -99,13 +99,15 @@ def test_batch_autotune_and_cache(gpu_lib, tmp_path):
 def test_batched_configuration_recipe_sampled(gpu_lib):
     """The 64-realisation batched recipe (mode grids over the even 5-smooth
     sizes in [128, 512], Hs/lambda_p in [0.01, 0.03], n = 4 windows, 32
-    layers) with the point counts scaled down: one graph launch of one step
-    each, sampled against the oracle (states of 6 realisations, fields of the
-    2 smallest at 300 points each)."""
+    layers) with the point counts scaled down and the product-grid policy of
+    each size chosen by the padding tuner, as the bench runs it: one graph
+    launch of one step each, sampled against the oracle on each
+    realisation's own product grid (states of 6 realisations, fields of the 2
+    smallest and the 2 largest at 300 points each)."""
     import bench
     from oracle import reconstruct as rc
     from paper_2005_12716_amd import lib
-    hoses, cells, outs, npts, mask, nf = bench.batched_setup(lib, torch, pts_scale=0.01)
+    hoses, cells, outs, npts, mask, nf = bench.batched_setup(lib, torch, pts_scale=0.01, padding="tune")
     assert len(hoses) == 64
     inits = [h.state() for h in hoses]
     b = lib.Batch(hoses, cells, [mask] * 64, outs, nsteps=1)
@@ -116,14 +118,14 @@ def test_batched_configuration_recipe_sampled(gpu_lib):
     for i in check:
         h = hoses[i]
         d = h.desc
-        g = Grid(nx=d.nx, ny=d.ny, lx=d.lx, ly=d.ly, depth=-1.0, order_m=3)
+        g = Grid(nx=d.nx, ny=d.ny, lx=d.lx, ly=d.ly, depth=-1.0, order_m=3, dealias=d.dealias)
         er, pr = hos.run(g, inits[i][0], inits[i][1], d.dt, 1)
         e, p, _ = h.state()
         assert np.linalg.norm(e - er) / np.linalg.norm(er) < 1e-6
-    for i in check[:2]:
+    for i in check[:2] + check[-2:]:
         h, c, out = hoses[i], cells[i], outs[i].cpu().numpy()
         d = h.desc
-        g = Grid(nx=d.nx, ny=d.ny, lx=d.lx, ly=d.ly, depth=-1.0, order_m=3)
+        g = Grid(nx=d.nx, ny=d.ny, lx=d.lx, ly=d.ly, depth=-1.0, order_m=3, dealias=d.dealias)
         e, p, _ = h.state()
         A = hos.mean_level_modes(g, e, p)
         At, eth = hos.mean_level_modes_t(g, e, p)

@@ -139,9 +139,7 @@ def test_rhs_parity_three_way_x_transforms(gpu_lib, dim, nx, ny, depth, M, deali
 
 
 # Product grids of policy 2 (the smallest 2^k or 3 2^k at or above the
-# (M+1)/2 rule) against the oracle on its own 5-smooth grid: any product
-# length at or above the rule aliases nothing into the kept band, so the
-# kept modes agree to rounding.
+# (M+1)/2 rule) against the oracle on the same product grid.
 P2_CASES = [
     # dim, nx, ny, depth, M, dealias   -> padded (policy 1 -> policy 2)
     (3, 40, 10, -1.0, 5, 2),   # 120 x 30 -> 128 x 32
