@@ -516,7 +516,8 @@ __global__ void __launch_bounds__(256) k_fno_iy(const cf* __restrict__ Y, cf* __
 // (two channels per complex transform); beta: out = beta out + that.
 template <int N>
 __global__ void __launch_bounds__(256) k_fno_ix(const cf* __restrict__ xi, float* __restrict__ out, FnoDims d,
-                                                WPlan plan, float scale, float beta) {
+                                                WPlan plan, float scale, float beta, const float* __restrict__ zact,
+                                                float* __restrict__ gout) {
   extern __shared__ unsigned char smem[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ncp = d.C / 2;
@@ -544,6 +545,22 @@ __global__ void __launch_bounds__(256) k_fno_ix(const cf* __restrict__ xi, float
   wave_fft_any<float, N / 64 < 8 ? 8 : N / 64, N, true>(buf, plan, +1, lane);
   float* oa = out + (((size_t)b * d.C + 2 * cp) * N + row) * N;
   float* ob = oa + (size_t)N * N;
+  if (zact) {
+    // the backward's next step fused: gout = out * gelu'(zact), out not stored
+    const size_t o0 = (((size_t)b * d.C + 2 * cp) * N + row) * N;
+    const float* za = zact + o0;
+    const float* zb = za + (size_t)N * N;
+    float* ga = gout + o0;
+    float* gb = ga + (size_t)N * N;
+    for (int x = lane; x < N; x += 64) {
+      const cf z = buf[sk(x)];
+      const float va = (beta != 0.f ? beta * oa[x] : 0.f) + scale * z.x;
+      const float vb = (beta != 0.f ? beta * ob[x] : 0.f) + scale * z.y;
+      ga[x] = va * gelu_g(za[x]);
+      gb[x] = vb * gelu_g(zb[x]);
+    }
+    return;
+  }
   for (int x = lane; x < N; x += 64) {
     const cf z = buf[sk(x)];
     oa[x] = (beta != 0.f ? beta * oa[x] : 0.f) + scale * z.x;
@@ -1075,14 +1092,16 @@ void spec_fwd_n(swense_fno* f, const float* v, cf* U, int B, float scale, int cp
 }
 
 template <int N>
-void spec_inv_n(swense_fno* f, const cf* Y, float* out, int B, float scale, float beta, int hmode) {
+void spec_inv_n(swense_fno* f, const cf* Y, float* out, int B, float scale, float beta, int hmode,
+                const float* zact, float* gout) {
   const FnoDims dd{N, f->d.channels, f->d.p_modes, f->d.q_modes, B};
   const size_t lds = 4ull * wbuf_len(N) * sizeof(cf);
   const int jy = B * f->d.channels * f->d.p_modes;
   hipLaunchKernelGGL(k_fno_iy<N>, dim3((jy + 3) / 4), dim3(256), lds, f->st, Y, f->xi, dd, f->plan, hmode);
   SW_HIP(hipGetLastError());
   const int jx = B * (f->d.channels / 2) * N;
-  hipLaunchKernelGGL(k_fno_ix<N>, dim3((jx + 3) / 4), dim3(256), lds, f->st, f->xi, out, dd, f->plan, scale, beta);
+  hipLaunchKernelGGL(k_fno_ix<N>, dim3((jx + 3) / 4), dim3(256), lds, f->st, f->xi, out, dd, f->plan, scale, beta,
+                     zact, gout);
   SW_HIP(hipGetLastError());
 }
 
@@ -1098,13 +1117,16 @@ void spec_fwd(swense_fno* f, const float* v, cf* U, int B, float scale, int cp_f
 
 // out = beta out + scale * inverse transform of Y; hmode as k_fno_iy (the
 // Hermitian projection applied on the way in, Y itself untouched)
-void spec_inv(swense_fno* f, const cf* Y, float* out, int B, float scale, float beta, int hmode) {
+// zact, gout (both or neither): instead of storing out, store out * gelu'(zact)
+// into gout (the backward's step through the previous layer's activation)
+void spec_inv(swense_fno* f, const cf* Y, float* out, int B, float scale, float beta, int hmode,
+              const float* zact = nullptr, float* gout = nullptr) {
   switch (f->d.n) {
-    case 64: spec_inv_n<64>(f, Y, out, B, scale, beta, hmode); break;
-    case 128: spec_inv_n<128>(f, Y, out, B, scale, beta, hmode); break;
-    case 256: spec_inv_n<256>(f, Y, out, B, scale, beta, hmode); break;
-    case 512: spec_inv_n<512>(f, Y, out, B, scale, beta, hmode); break;
-    default: spec_inv_n<1024>(f, Y, out, B, scale, beta, hmode); break;
+    case 64: spec_inv_n<64>(f, Y, out, B, scale, beta, hmode, zact, gout); break;
+    case 128: spec_inv_n<128>(f, Y, out, B, scale, beta, hmode, zact, gout); break;
+    case 256: spec_inv_n<256>(f, Y, out, B, scale, beta, hmode, zact, gout); break;
+    case 512: spec_inv_n<512>(f, Y, out, B, scale, beta, hmode, zact, gout); break;
+    default: spec_inv_n<1024>(f, Y, out, B, scale, beta, hmode, zact, gout); break;
   }
 }
 
@@ -1366,7 +1388,8 @@ void backward_impl(swense_fno* f, const float* x, const float* gy, float* gx, in
   cf* gY = f->Y;
   cf* gU = f->Y + (size_t)d.max_batch * S * C;
   for (int l = d.layers; l >= 1; --l) {
-    gelu_back(f, gv, z_of(f, l), gz, (long long)B * C * plane);
+    // below the top layer, gz came with the previous iteration's inverse x pass
+    if (l == d.layers) gelu_back(f, gv, z_of(f, l), gz, (long long)B * C * plane);
     trace(gz, (size_t)l - 1, cplane);
     const float* u = v_of(f, l - 1);
     conv1x1_dw(f, gz, u, C, C, B, f->g + f->oW[l - 1]);
@@ -1379,7 +1402,10 @@ void backward_impl(swense_fno* f, const float* x, const float* gy, float* gx, in
     mix_dx(f, gY, f->wb + f->oR[l - 1], gU, B);
     // gv = W^T gz + (1/n^2) Re sum P(gU / c_p) e^{ik.x}
     conv1x1_dx(f, f->wb + f->oW[l - 1], C, C, gz, gv, B, 0.f);
-    spec_inv(f, gU, gv, B, 1.f / ((float)plane), 1.f, 2);
+    if (l > 1)  // gz of layer l - 1 = gv * gelu'(z_{l-1}), gz's uses above done
+      spec_inv(f, gU, gv, B, 1.f / ((float)plane), 1.f, 2, z_of(f, l - 1), gz);
+    else
+      spec_inv(f, gU, gv, B, 1.f / ((float)plane), 1.f, 2);
   }
   trace(gv, (size_t)d.layers, cplane);
   conv1x1_dw(f, gv, x, C, d.in_channels, B, f->g + f->oW0);
