@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NY >= 
   C* buf = reinterpret_cast<C*>(smem);
   // one-dimensional grid over (column, layer slot), grouped by columns
   int p, ly;
-  grouped_tile<32>(blockIdx.x, G.nxh, A.nvol > 0 ? A.nl + (A.nsurf > 0 ? 1 : 0) : 1, p, ly);
+  grouped_tile<16>(blockIdx.x, G.nxh, A.nvol > 0 ? A.nl + (A.nsurf > 0 ? 1 : 0) : 1, p, ly);
   const int l = A.nvol > 0 ? ly : A.nl;
   const bool surf = l == A.nl;
   const int f0 = surf ? A.nvol : 0, f1 = surf ? A.nvol + A.nsurf : A.nvol;
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(256) k_yinv_eval_rr(EvArgs A, Geom G, const cp
   C* buf = reinterpret_cast<C*>(smem);
   const int ny = G.ny, N = RS * ny, WL = wbuf_len(ny);
   int p, ly;
-  grouped_tile<32>(blockIdx.x, G.nxh, A.nvol > 0 ? A.nl + (A.nsurf > 0 ? 1 : 0) : 1, p, ly);
+  grouped_tile<16>(blockIdx.x, G.nxh, A.nvol > 0 ? A.nl + (A.nsurf > 0 ? 1 : 0) : 1, p, ly);
   const int l = A.nvol > 0 ? ly : A.nl;
   const bool surf = l == A.nl;
   const int f0 = surf ? A.nvol : 0, f1 = surf ? A.nvol + A.nsurf : A.nvol;
